@@ -1,0 +1,446 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test compares the oracle with a closed form, a limit, an invariance or an
+independent construction (numerical Hessians, adaptive quadrature, the
+whole-system model) so that a dropped term, a wrong sign, a wrong index or a
+transposed operand anywhere in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import lmbd as L
+from workloads import SPECIES_TABLE, SPECIES_INDEX, frequency_grid, Structure
+from workloads import configs as C
+from tests import closed_forms as cf
+
+GRID12 = frequency_grid(12)
+GRID200 = frequency_grid(200)
+
+C_IDX = SPECIES_INDEX["C"]
+
+
+def _open(pos, species=None, nu=None):
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    sp = np.full(n, C_IDX, dtype=np.int32) if species is None else np.asarray(species, np.int32)
+    nu = np.full(n, 0.85) if nu is None else np.asarray(nu, np.float64)
+    return Structure(pos, sp, nu, None, np.zeros(3, bool))
+
+
+def _params(r_scs, r_nbr, grid=GRID12, **kw):
+    return oracle.make_params(dict(r_scs=r_scs, r_nbr=r_nbr, r_mbd1=r_nbr, r_mbd2=r_nbr),
+                              grid[0], grid[1], **kw)
+
+
+def _rand_cluster(n, seed, box=7.0, dmin=1.6, hcno=True):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    from workloads.structures import rsa_cube_open, hcno_species
+    pos = rsa_cube_open(n, box, dmin, rng)
+    sp = hcno_species(n, rng) if hcno else np.full(n, C_IDX, np.int32)
+    nu = rng.uniform(0.6, 1.0, n)
+    return Structure(pos, sp, nu, None, np.zeros(3, bool))
+
+
+def _free(st):
+    tab = SPECIES_TABLE[st.species]
+    a = tab[:, 0] * st.nu
+    w = 4.0 * tab[:, 1] / (3.0 * tab[:, 0] ** 2)
+    R = tab[:, 2] * st.nu ** (1.0 / 3.0)
+    return a, w, R
+
+
+# SCS switched off: K1 = {k}, K2 empty (2 r_scs below every distance), so the
+# polarisabilities stay at their TS values; all MBD pairs inside r_nbr - r_b.
+NO_SCS = 0.6
+
+
+# --------------------------------------------------------------------------- P1
+
+def test_quadrature_reproduces_casimir_polder():
+    """(3/pi) int abar_i abar_j dw on the 12-point grid equals the London formula."""
+    om, wt = GRID12
+    worst = 0.0
+    for i in range(4):
+        for j in range(4):
+            for nui, nuj in ((1.0, 1.0), (0.6, 0.9)):
+                fi = oracle.free_atom_terms(SPECIES_TABLE, np.array([i, j]), np.array([nui, nuj]), om)
+                num = 3.0 / math.pi * np.sum(wt * fi["abar"][0] * fi["abar"][1])
+                a0 = SPECIES_TABLE[[i, j], 0] * [nui, nuj]
+                w0 = 4 * SPECIES_TABLE[[i, j], 1] / (3 * SPECIES_TABLE[[i, j], 0] ** 2)
+                ref = cf.c6_casimir_polder(a0[0], w0[0], a0[1], w0[1])
+                worst = max(worst, abs(num / ref - 1.0))
+                if i == j and nui == nuj:
+                    # the free-atom C6 comes back, scaled by nu^2
+                    assert abs(ref / (SPECIES_TABLE[i, 1] * nui ** 2) - 1) < 1e-13
+    assert worst < 5e-8
+    om2, wt2 = GRID200
+    fi = oracle.free_atom_terms(SPECIES_TABLE, np.array([0, 3]), np.array([0.7, 0.9]), om2)
+    num = 3.0 / math.pi * np.sum(wt2 * fi["abar"][0] * fi["abar"][1])
+    a0 = SPECIES_TABLE[[0, 3], 0] * [0.7, 0.9]
+    w0 = 4 * SPECIES_TABLE[[0, 3], 1] / (3 * SPECIES_TABLE[[0, 3], 0] ** 2)
+    assert abs(num / cf.c6_casimir_polder(a0[0], w0[0], a0[1], w0[1]) - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- pair tensors
+
+def test_dipole_tensor_is_hessian_of_coulomb():
+    import torch
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rv = rng.normal(size=3) * 3
+        T = L._dipole_T(torch.as_tensor(rv)[None]).numpy()[0]
+        H = cf.numerical_hessian(cf.coulomb, rv, h=1e-2 * np.linalg.norm(rv))
+        assert np.allclose(T, H, rtol=1e-8, atol=1e-8 * np.abs(H).max())
+
+
+def test_short_range_tensor_is_screened_erf_hessian():
+    """T_SR = (1 - f) d/dr_i d/dr_j [erf(r/sigma)/r] with the f_SR cutoff equal to 1."""
+    import torch
+    rng = np.random.default_rng(4)
+    for _ in range(6):
+        rv = rng.normal(size=3)
+        rv *= rng.uniform(1.0, 7.0) / np.linalg.norm(rv)
+        sig = rng.uniform(1.0, 3.0)
+        S = rng.uniform(4.0, 7.0)
+        got = L._t_sr(torch.as_tensor(rv)[None], torch.tensor([[sig]], dtype=torch.float64),
+                      torch.tensor([S], dtype=torch.float64),
+                      100.0, 1.0, 6.0).numpy()[0, 0]
+        ref = cf.sr_tensor_fd(rv, sig, S)
+        assert np.allclose(got, ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
+
+
+def test_cutoff_polynomial_is_c1_smooth():
+    import torch
+    r = torch.linspace(3.0, 6.0, 3001, dtype=torch.float64)
+    f = L._cutoff_poly(r, 5.0, 0.5).numpy()
+    assert f[0] == 1.0 and f[-1] == 0.0
+    assert np.all(np.diff(f) <= 1e-15)
+    assert np.max(np.abs(np.diff(f))) < 4e-3   # no jump; slope bounded by 1.5 / r_b
+
+
+# --------------------------------------------------------------- SCS (P6, P7, P8)
+
+def _sigma(a):
+    return (math.sqrt(2.0 / math.pi) * a / 3.0) ** (1.0 / 3.0)
+
+
+def _solve_scs_fd(centers_bohr, abar, R, fixed=None, beta=0.83, finner=None, rc=None):
+    """Independent small SCS solve with tensors from numerical Hessians.
+
+    centers: coupled atoms (n, 3) bohr; abar/R: their TS values; fixed: list of
+    (pos, abar_j, R_j) uncoupled atoms entering the right-hand side, with the
+    optional inner-buffer weight finner(r).  Pairs at or beyond rc (bohr) do not
+    couple; the constructions keep every coupled pair clear of the cutoff buffer.
+    """
+    n = len(centers_bohr)
+    B = np.zeros((3 * n, 3 * n))
+    couples = lambda rv: rc is None or np.linalg.norm(rv) < rc
+    for i in range(n):
+        B[3 * i:3 * i + 3, 3 * i:3 * i + 3] = np.eye(3) / abar[i]
+        for j in range(n):
+            if i != j and couples(centers_bohr[i] - centers_bohr[j]):
+                rv = centers_bohr[i] - centers_bohr[j]
+                sig = math.hypot(_sigma(abar[i]), _sigma(abar[j]))
+                B[3 * i:3 * i + 3, 3 * j:3 * j + 3] = cf.sr_tensor_fd(rv, sig, beta * (R[i] + R[j]))
+    d = np.tile(np.eye(3), (n, 1))
+    for (pj, aj, Rj) in (fixed or []):
+        for i in range(n):
+            rv = centers_bohr[i] - pj
+            r = np.linalg.norm(rv)
+            if not couples(rv):
+                continue
+            sig = math.hypot(_sigma(abar[i]), _sigma(aj))
+            w = 1.0 if finner is None else finner(r)
+            d[3 * i:3 * i + 3] -= w * cf.sr_tensor_fd(rv, sig, beta * (R[i] + Rj)) * aj
+    X = np.linalg.solve(B, d)
+    return np.array([np.trace(X[3 * i:3 * i + 3]) / 3.0 for i in range(n)])
+
+
+def test_scs_dimer_matches_independent_solve():
+    st = _open([[0, 0, 0], [1.2, 1.0, 0.4]], species=[C_IDX, SPECIES_INDEX["O"]], nu=[0.8, 0.95])
+    prm = _params(5.0, 5.0)
+    got = oracle.scs_central(st, prm, SPECIES_TABLE)
+    a0, w0, R = _free(st)
+    omegas = np.concatenate([[0.0], prm.omega])
+    x = st.pos / cf.BOHR
+    for q, w in enumerate(omegas):
+        ab = a0 / (1.0 + (w / w0) ** 2)
+        ref = _solve_scs_fd(x, ab, R)
+        assert np.allclose(got[:, q], ref, rtol=1e-7)
+    # screening raises the polarisability along a bonded pair at this distance
+    assert np.all(got[:, 0] != a0)
+
+
+def test_scs_isolated_atom_keeps_ts_polarisability():
+    st = _open([[0, 0, 0], [20.0, 0, 0]], nu=[0.7, 0.9])
+    prm = _params(5.0, 5.0)
+    got = oracle.scs_central(st, prm, SPECIES_TABLE)
+    fa = oracle.free_atom_terms(SPECIES_TABLE, st.species, st.nu, np.concatenate([[0.0], prm.omega]))
+    assert np.allclose(got, fa["abar"], rtol=1e-15, atol=0)
+
+
+def test_scs_uncoupled_shell_and_inner_buffer():
+    """K2 atoms enter only the right-hand side, with TS polarisability and f_inner."""
+    # k at the origin, i inside r_scs, j in the shell [r_scs, 2 r_scs) of k but 1.49 A from i
+    st = _open([[0, 0, 0], [2.0, 0, 0], [3.4, 0.5, 0.0]], nu=[0.9, 0.8, 0.7],
+               species=[C_IDX, C_IDX, SPECIES_INDEX["N"]])
+    prm = _params(3.0, 3.0)
+    got = oracle.scs_central(st, prm, SPECIES_TABLE)
+    a0, w0, R = _free(st)
+    x = st.pos / cf.BOHR
+    rin = 2.0 / cf.BOHR
+    rc = 3.0 / cf.BOHR
+    finner = lambda r: 3 * (r / rin) ** 2 - 2 * (r / rin) ** 3 if r < rin else 1.0
+    for q, w in enumerate(np.concatenate([[0.0], prm.omega])):
+        ab = a0 / (1.0 + (w / w0) ** 2)
+        # frame of atom 0: K1 = {0, 1}, K2 = {2}
+        ref0 = _solve_scs_fd(x[:2], ab[:2], R[:2], fixed=[(x[2], ab[2], R[2])], finner=finner, rc=rc)[0]
+        # frame of atom 1: all three inside r_scs, no shell
+        ref1 = _solve_scs_fd(x, ab, R, rc=rc)[1]
+        assert abs(got[0, q] / ref0 - 1) < 1e-7
+        assert abs(got[1, q] / ref1 - 1) < 1e-7
+
+
+def test_full_cutoff_local_scs_is_whole_system_scs():
+    st = _rand_cluster(16, 11)
+    prm = _params(16.0, 16.0)  # covers the cluster diameter plus the buffer
+    got = oracle.scs_central(st, prm, SPECIES_TABLE)
+    ref = oracle.full_scs(st.pos, st.species, st.nu, SPECIES_TABLE, np.concatenate([[0.0], prm.omega]))
+    assert np.allclose(got, ref, rtol=1e-12)
+
+
+# ------------------------------------------------------------ MBD (P2, P3, P4)
+
+def test_second_order_is_damped_pairwise_c6():
+    st = _rand_cluster(8, 21, box=6.0, dmin=1.5)
+    prm = _params(NO_SCS, 30.0, grid=GRID200, n_max=2)
+    e = oracle.lmbd_energies(st, prm, SPECIES_TABLE)
+    a, w, R = _free(st)
+    x = st.pos / cf.BOHR
+    ref = np.zeros(st.n)
+    for i in range(st.n):
+        for j in range(st.n):
+            if i != j:
+                r = np.linalg.norm(x[i] - x[j])
+                f = cf.fermi(r, 0.83 * (R[i] + R[j]) / cf.BOHR * cf.BOHR)
+                f = cf.fermi(r, 0.83 * (R[i] + R[j]))
+                ref[i] += -0.5 * cf.c6_casimir_polder(a[i], w[i], a[j], w[j]) * f * f / r ** 6
+    assert np.allclose(e, ref * cf.HARTREE, rtol=1e-11, atol=0)
+
+
+def test_third_order_is_axilrod_teller_muto():
+    pos = np.array([[0.0, 0.0, 0.0], [3.1, 0.0, 0.0], [1.2, 2.6, 0.7]])
+    st = _open(pos, species=[C_IDX, SPECIES_INDEX["N"], SPECIES_INDEX["H"]], nu=[0.9, 0.75, 0.8])
+    e2 = oracle.lmbd_energies(st, _params(NO_SCS, 30.0, grid=GRID200, n_max=2), SPECIES_TABLE).sum()
+    e3 = oracle.lmbd_energies(st, _params(NO_SCS, 30.0, grid=GRID200, n_max=3), SPECIES_TABLE).sum()
+    a, w, R = _free(st)
+    x = pos / cf.BOHR
+    f = 1.0
+    for i, j in ((0, 1), (1, 2), (2, 0)):
+        f *= cf.fermi(np.linalg.norm(x[i] - x[j]), 0.83 * (R[i] + R[j]))
+    ref = cf.c9_atm(a[0], w[0], a[1], w[1], a[2], w[2]) * f * cf.atm_geometry_factor(*x)
+    assert abs((e3 - e2) / (ref * cf.HARTREE) - 1.0) < 1e-10
+
+
+def _dimer_couplings(st):
+    a, w, R = _free(st)
+    r = np.linalg.norm(st.pos[1] - st.pos[0]) / cf.BOHR
+    f = cf.fermi(r, 0.83 * (R[0] + R[1]))
+    return a, w, [2.0 * f / r ** 3, -f / r ** 3, -f / r ** 3]
+
+
+def test_coupled_oscillator_dimer_log_limit():
+    st = _open([[0, 0, 0], [2.3, 1.1, -0.6]], species=[C_IDX, SPECIES_INDEX["O"]], nu=[0.8, 0.9])
+    e = oracle.lmbd_energies(st, _params(NO_SCS, 30.0, grid=GRID200, n_max=None), SPECIES_TABLE)
+    a, w, t = _dimer_couplings(st)
+    ref = cf.qho_dimer_energy(a[0], w[0], a[1], w[1], t) * cf.HARTREE
+    assert abs(e.sum() / ref - 1) < 1e-10
+    assert abs(e[0] - e[1]) < 1e-12 * abs(ref)
+
+
+def test_dimer_truncated_series_matches_adaptive_quadrature():
+    st = _open([[0, 0, 0], [1.9, 0.0, 0.9]], species=[C_IDX, C_IDX], nu=[0.7, 1.0])
+    e = oracle.lmbd_energies(st, _params(NO_SCS, 30.0, grid=GRID200, n_max=6), SPECIES_TABLE)
+    a, w, t = _dimer_couplings(st)
+    ref = cf.dimer_series_energy(a[0], w[0], a[1], w[1], t, 6) * cf.HARTREE
+    assert abs(e.sum() / ref - 1) < 1e-10
+
+
+def test_series_converges_to_block_logarithm():
+    st = _rand_cluster(10, 31, box=7.0, dmin=2.0)
+    e_log = oracle.lmbd_energies(st, _params(4.0, 6.0, n_max=None), SPECIES_TABLE)
+    e_40 = oracle.lmbd_energies(st, _params(4.0, 6.0, n_max=40), SPECIES_TABLE)
+    e_2 = oracle.lmbd_energies(st, _params(4.0, 6.0, n_max=2), SPECIES_TABLE)
+    assert np.allclose(e_40, e_log, rtol=1e-9, atol=1e-13)
+    assert not np.allclose(e_2, e_log, rtol=1e-4)
+
+
+# ------------------------------------------------------------------ limits (P5)
+
+def test_full_cutoff_lmbd_is_full_mbd_series_and_log():
+    s, _ = C.config_small_open()
+    sub = Structure(s.pos[:24], s.species[:24], s.nu[:24], None, np.zeros(3, bool))
+    big = 22.0
+    for n_max in (6, None):
+        prm = _params(big, big, n_max=n_max)
+        e = oracle.lmbd_energies(sub, prm, SPECIES_TABLE)
+        E, shares = oracle.full_mbd(sub.pos, sub.species, sub.nu, SPECIES_TABLE, prm.omega, prm.weight,
+                                    n_max=n_max)
+        assert abs(e.sum() / E - 1) < 1e-12
+        assert np.allclose(e, shares, rtol=1e-10, atol=1e-14)
+
+
+def test_blend_uses_local_and_central_polarisabilities():
+    """Three atoms in a row: the middle atom's polarisability in the first atom's
+    frame is the f_SCS blend of the two-atom-plus-shell solve and its own three-atom
+    solve (Sec. III.B, the range-separated combination)."""
+    pos = np.array([[0.0, 0, 0], [2.4, 0, 0], [4.8, 0.3, 0]])
+    st = _open(pos, nu=[0.8, 0.9, 0.7])
+    rs = 3.0
+    grid = frequency_grid(40)
+    prm = _params(rs, 10.0, grid=grid, n_max=2)
+    e = oracle.lmbd_energies(st, prm, SPECIES_TABLE)
+    a0, w0, R = _free(st)
+    x = pos / cf.BOHR
+    omegas = np.concatenate([[0.0], grid[0]])
+    rin = 2.0 / cf.BOHR
+    finner = lambda r: 3 * (r / rin) ** 2 - 2 * (r / rin) ** 3 if r < rin else 1.0
+    alpha = np.zeros((len(omegas), 3))
+    for q, w in enumerate(omegas):
+        ab = a0 / (1.0 + (w / w0) ** 2)
+        rc = rs / cf.BOHR
+        loc0 = _solve_scs_fd(x[:2], ab[:2], R[:2], fixed=[(x[2], ab[2], R[2])], finner=finner, rc=rc)
+        cen1 = _solve_scs_fd(x, ab, R, rc=rc)[1]
+        cen2 = _solve_scs_fd(x[1:], ab[1:], R[1:], fixed=[(x[0], ab[0], R[0])], finner=finner,
+                             rc=rc)[1]
+        fs = 3 * (2.4 / rs) ** 2 - 2 * (2.4 / rs) ** 3
+        alpha[q] = [loc0[0], (1 - fs) * loc0[1] + fs * cen1, cen2]
+    atom0 = st.species[0]
+    r0 = SPECIES_TABLE[st.species, 2]
+    Rt = r0 * (alpha[0] / SPECIES_TABLE[st.species, 0]) ** (1.0 / 3.0)
+    ref = 0.0
+    for j in (1, 2):
+        rv = x[0] - x[j]
+        r = np.linalg.norm(rv)
+        f = cf.fermi(r, 0.83 * (Rt[0] + Rt[j]))
+        T = cf.numerical_hessian(cf.coulomb, rv, h=1e-2 * r) * f
+        tr = np.trace(T @ T)
+        ref += -0.5 * np.sum(grid[1] * alpha[1:, 0] * alpha[1:, j]) * tr / (2 * math.pi)
+    assert abs(e[0] / (ref * cf.HARTREE) - 1) < 2e-7
+
+
+# ---------------------------------------------------------- invariances (P9, P12)
+
+def test_rotation_translation_permutation_invariance():
+    st = _rand_cluster(14, 41)
+    prm = _params(3.5, 4.5)
+    e0, f0 = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    perm = rng.permutation(st.n)
+    st2 = Structure(st.pos[perm] @ Q.T + np.array([1.3, -7.2, 0.4]), st.species[perm], st.nu[perm],
+                    None, np.zeros(3, bool))
+    e1, f1 = oracle.lmbd_energy_forces(st2, prm, SPECIES_TABLE)
+    assert np.allclose(e1, e0[perm], rtol=1e-10, atol=1e-14)
+    assert np.allclose(f1, f0[perm] @ Q.T, rtol=1e-8, atol=1e-11)
+
+
+def test_lattice_shift_and_supercell_invariance():
+    st = C.carbon_box(24, 7, g_cm3=1.2, dmin=1.4)
+    prm = _params(3.5, 3.5)
+    e0 = oracle.lmbd_energies(st, prm, SPECIES_TABLE)
+    shifted = st.copy()
+    shifted.pos[3] += st.cell[1] - 2 * st.cell[2]
+    e1 = oracle.lmbd_energies(shifted, prm, SPECIES_TABLE)
+    assert np.allclose(e1, e0, rtol=1e-11, atol=1e-15)
+    reps = [st.pos + np.array([a, b, c]) @ st.cell for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    sup = Structure(np.concatenate(reps), np.tile(st.species, 8), np.tile(st.nu, 8), 2 * st.cell,
+                    np.ones(3, bool))
+    e2 = oracle.lmbd_energies(sup, prm, SPECIES_TABLE, atoms=list(range(st.n)))
+    assert np.allclose(e2[:st.n], e0, rtol=1e-11, atol=1e-15)
+
+
+def test_size_consistency_of_distant_fragments():
+    a = _rand_cluster(6, 51, box=4.0)
+    b = _rand_cluster(5, 52, box=4.0)
+    prm = _params(3.0, 4.0)
+    far = np.array([30.0, 0, 0])
+    ab = Structure(np.concatenate([a.pos, b.pos + far]), np.concatenate([a.species, b.species]),
+                   np.concatenate([a.nu, b.nu]), None, np.zeros(3, bool))
+    e = oracle.lmbd_energies(ab, prm, SPECIES_TABLE)
+    ea = oracle.lmbd_energies(a, prm, SPECIES_TABLE)
+    eb = oracle.lmbd_energies(b, prm, SPECIES_TABLE)
+    assert np.allclose(e, np.concatenate([ea, eb]), rtol=1e-12, atol=1e-16)
+
+
+# ----------------------------------------------------------------- forces (P10)
+
+def _lists_equal(st, prm, pos2):
+    r_big = max(2 * prm.r_scs, prm.r_nbr)
+    s2 = st.copy()
+    s2.pos = pos2
+    for k in range(st.n):
+        b1, s1, d1 = oracle.neighbourhood(st.pos, st.cell, st.pbc, k, r_big)
+        b2, sh2, d2 = oracle.neighbourhood(pos2, st.cell, st.pbc, k, r_big)
+        if len(b1) != len(b2):
+            return False
+        for rc in (prm.r_scs, prm.r_nbr):
+            if np.sum(d1 < rc) != np.sum(d2 < rc):
+                return False
+    return True
+
+
+def _fd_check(st, prm, comps, h=1e-4, tol=2e-6):
+    e, f = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    assert np.allclose(f.sum(0), 0.0, atol=1e-10 * max(1.0, np.abs(f).max()))
+    checked = 0
+    for (a, g) in comps:
+        pp, pm = st.pos.copy(), st.pos.copy()
+        pp[a, g] += h
+        pm[a, g] -= h
+        if not (_lists_equal(st, prm, pp) and _lists_equal(st, prm, pm)):
+            continue  # a neighbour set changes inside the stencil: skip this draw
+        sp_, sm_ = st.copy(), st.copy()
+        sp_.pos, sm_.pos = pp, pm
+        ep = oracle.lmbd_energies(sp_, prm, SPECIES_TABLE).sum()
+        em = oracle.lmbd_energies(sm_, prm, SPECIES_TABLE).sum()
+        fd = -(ep - em) / (2 * h)
+        assert abs(fd - f[a, g]) < tol * max(1.0, abs(f[a, g])) + 1e-8, (a, g, fd, f[a, g])
+        checked += 1
+    assert checked >= len(comps) // 2
+
+
+def test_forces_finite_difference_open_cluster():
+    st = _rand_cluster(12, 61, box=5.5, dmin=1.4)
+    prm = _params(3.0, 4.0)
+    _fd_check(st, prm, [(0, 0), (3, 1), (7, 2), (11, 0)])
+
+
+@pytest.mark.slow
+def test_forces_finite_difference_periodic_box():
+    st = C.hcno_box(20, 9, g_cm3=1.0)
+    prm = _params(3.2, 3.5)
+    _fd_check(st, prm, [(1, 0), (5, 2), (13, 1)])
+
+
+# ------------------------------------------------------------------ neighbours
+
+def test_neighbourhood_matches_brute_force_images():
+    st = C.carbon_box(10, 3, g_cm3=1.0, dmin=1.2)   # L ~ 5.8 A, so many images are in reach
+    rmax = 7.3
+    for k in (0, 4, 9):
+        base, sh, d = oracle.neighbourhood(st.pos, st.cell, st.pbc, k, rmax)
+        ref = set()
+        for a in range(-4, 5):
+            for b in range(-4, 5):
+                for c in range(-4, 5):
+                    for j in range(st.n):
+                        v = st.pos[j] + np.array([a, b, c]) @ st.cell - st.pos[k]
+                        if np.linalg.norm(v) < rmax:
+                            ref.add((j, a, b, c))
+        got = {(int(j), *map(int, s)) for j, s in zip(base, sh)}
+        assert got == ref
+        assert base[0] == k and np.all(sh[0] == 0) and np.all(np.diff(d[1:]) >= 0)
