@@ -1,0 +1,173 @@
+/*
+ * lmbd.h -- C ABI of the atom-wise linear many-body dispersion (lMBD) library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for every atom k of one or more structures, the
+ * atom-wise MBD energy of Muhli, Ala-Nissila & Caro (2024), "Atom-wise
+ * formulation of the many-body dispersion problem for linear-scaling van der
+ * Waals corrections":
+ *
+ *   E_k = (1/2pi) sum_q w_q sum_{n=2}^{n_max} c_n Tr[ G~_K(w_q)^n ]_kk     (Sec. III.A,
+ *         symmetrised local energy), G~_K = sqrt(A_K) T_LR,K sqrt(A_K),
+ *
+ * where A_K holds the blended SCS polarisabilities of the neighbourhood of k
+ * (Sec. III.B, local polarisability system B~_K alpha~_K = d_K and the
+ * central/local combination), and the exact forces
+ *
+ *   F_a = -d( sum_k w_k E_k ) / d R_a       (Hirshfeld ratios held fixed),
+ *
+ * from hand-written adjoint kernels.  Units: positions and lengths in Angstrom,
+ * frequencies in hartree, free-atom data in atomic units (bohr^3, Ha bohr^6,
+ * bohr), energies in eV, forces in eV/Angstrom.  Internally everything is in
+ * Hartree atomic units (CODATA 2018 bohr and hartree).
+ *
+ * Plain C99; no C++ or torch types cross this boundary.  Every array is owned
+ * by the caller; the library keeps no caller pointer after a call returns.
+ */
+#ifndef LMBD_H
+#define LMBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMBD_ABI_VERSION 1
+
+typedef enum lmbd_status {
+    LMBD_OK = 0,
+    LMBD_E_INVALID_ARG = 1,    /* bad pointer, size, NaN/Inf input, inconsistent cutoffs */
+    LMBD_E_OOM = 2,            /* device allocation failed */
+    LMBD_E_OOM_ADMISSION = 3,  /* request larger than the memory budget of the context */
+    LMBD_E_DEVICE = 4,         /* a HIP runtime call failed; see lmbd_last_error */
+    LMBD_E_SCS_BREAKDOWN = 5,  /* a local SCS matrix B~_K is not positive definite */
+    LMBD_E_UNSUPPORTED = 6     /* a size limit of the kernels is exceeded */
+} lmbd_status;
+
+/* precision of the hot path */
+enum { LMBD_FP64 = 0, LMBD_MIXED = 1 };
+/* where the caller's arrays live */
+enum { LMBD_HOST = 0, LMBD_DEVICE = 1 };
+
+/* Free-atom reference data of one species (Sec. II.B: the TS polarisability,
+ * its characteristic frequency omega = 4 C6 / (3 alpha0^2), and vdW radius). */
+typedef struct lmbd_species {
+    double alpha0;   /* static free-atom polarisability, bohr^3 (> 0) */
+    double c6;       /* free-atom C6 coefficient, Ha bohr^6 (> 0) */
+    double r0;       /* free-atom vdW radius, bohr (> 0) */
+} lmbd_species;
+
+/* Method parameters, shared by every structure of a call.
+ *  beta, damp_d : Fermi damping f(r,S) = 1/(1+exp(-d (r/S - 1))), S = beta (R_i + R_j)
+ *                 (Sec. II.B; defaults 0.83 and 6)
+ *  r_buf        : width of the smooth cutoff buffers f_SR and f_LR (Sec. III.A/III.B), A
+ *  r_inner      : inner buffer f_inner for shell atoms near K1 atoms (Sec. III.B), A
+ *  n_max        : highest body order of the series (>= 2)
+ *  c_n          : host array of n_max+1 series coefficients, or NULL for c_n = -1/n
+ *                 (the logarithm series; c_0 and c_1 are ignored)
+ *  n_freq, omega, weight : host arrays; imaginary-frequency nodes (Ha) and weights of
+ *                 int_0^inf d omega; the library applies the 1/(2 pi) itself
+ *  precision    : LMBD_FP64 or LMBD_MIXED
+ * Cutoffs are per structure (lmbd_structure). */
+typedef struct lmbd_params {
+    double beta;
+    double damp_d;
+    double r_buf;
+    double r_inner;
+    int32_t n_max;
+    const double* c_n;
+    int32_t n_freq;
+    const double* omega;
+    const double* weight;
+    int32_t precision;
+} lmbd_params;
+
+/* One structure of a batch.  Pointers are host or device pointers according to
+ * the `mem` argument of the call.
+ *  n_atoms     : number of atoms (>= 1)
+ *  pos         : [n_atoms][3] Cartesian positions, A
+ *  species     : [n_atoms] index into the species table
+ *  v_ratio     : [n_atoms] Hirshfeld-volume ratios nu (> 0)
+ *  cell        : HOST array [3][3], rows = lattice vectors (A), or NULL for an open
+ *                structure; used only along directions with pbc[d] != 0
+ *  pbc         : periodicity per lattice direction
+ *  r_scs       : SCS cutoff: K1 = B(r_scs), K2 = B(2 r_scs) \ B(r_scs) (Sec. III.B)
+ *  r_nbr       : radius of the energy neighbourhood K = B(r_nbr) (Sec. III.A)
+ *  r_mbd1/2    : f_LR cutoffs for pairs touching / not touching the central atom
+ *  e_weight    : [n_atoms] adjoint seeds w_k of the forces, or NULL for w_k = 1
+ *  e_atom      : [n_atoms] output per-atom energies E_k (eV), or NULL
+ *  forces      : [n_atoms][3] output forces (eV/A), or NULL for energies only
+ *  alpha_scs0  : [n_atoms] output central static SCS polarisabilities (bohr^3), or NULL */
+typedef struct lmbd_structure {
+    int64_t n_atoms;
+    const double* pos;
+    const int32_t* species;
+    const double* v_ratio;
+    const double* cell;
+    int32_t pbc[3];
+    double r_scs;
+    double r_nbr;
+    double r_mbd1;
+    double r_mbd2;
+    const double* e_weight;
+    double* e_atom;
+    double* forces;
+    double* alpha_scs0;
+} lmbd_structure;
+
+typedef struct lmbd_context lmbd_context;
+
+/* ABI version of the loaded library (LMBD_ABI_VERSION of its build). */
+int32_t lmbd_abi_version(void);
+
+/* Create a context on HIP device `device`.  The context owns its device
+ * workspaces and caches them between calls; it is not thread-safe.
+ * Returns LMBD_E_INVALID_ARG for a NULL `out` or a bad device index. */
+lmbd_status lmbd_create(int32_t device, lmbd_context** out);
+
+/* Release the context and every device buffer it owns.  NULL is ignored. */
+void lmbd_destroy(lmbd_context* ctx);
+
+/* Cap the device memory (bytes) that one call may use; 0 = no cap.  A call whose
+ * footprint exceeds the cap fails with LMBD_E_OOM_ADMISSION before touching the
+ * device. */
+lmbd_status lmbd_set_memory_budget(lmbd_context* ctx, size_t bytes);
+
+/* Energies (and forces) of a batch of structures in one set of kernel launches.
+ *
+ * species_table: HOST array of n_species entries.  structs: HOST array of
+ * n_structs descriptors.  mem = LMBD_DEVICE: every array of the descriptors is a
+ * device pointer on the context's device and the work is ordered on
+ * `hip_stream` (a hipStream_t, NULL = default stream); the call returns after
+ * enqueueing the work that follows its single host synchronisation (the
+ * neighbour-count read-back) and outputs are valid once the stream is
+ * synchronised.  mem = LMBD_HOST: host arrays; the call is synchronous.
+ * Results of a structure do not depend on the other structures of the batch. */
+lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params,
+                               int32_t n_species, const lmbd_species* species_table,
+                               int32_t n_structs, const lmbd_structure* structs,
+                               int32_t mem, void* hip_stream);
+
+/* Single-structure convenience form of lmbd_compute_batch. */
+lmbd_status lmbd_compute(lmbd_context* ctx, const lmbd_params* params,
+                         int32_t n_species, const lmbd_species* species_table,
+                         const lmbd_structure* structure, int32_t mem, void* hip_stream);
+
+/* Device bytes a call on these structures would need (host-side neighbour
+ * counting; positions are HOST arrays here whatever `mem` a later call uses). */
+lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs,
+                                    const lmbd_structure* structs, size_t* bytes);
+
+/* Static description of a status code. */
+const char* lmbd_status_string(lmbd_status status);
+
+/* Detail of the last error of a context (empty string if none). */
+const char* lmbd_last_error(const lmbd_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMBD_H */

@@ -1,0 +1,88 @@
+"""ctypes view of the C ABI in include/lmbd.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblmbd.so")
+
+LMBD_FP64, LMBD_MIXED = 0, 1
+LMBD_HOST, LMBD_DEVICE = 0, 1
+
+STATUS = {
+    0: "LMBD_OK", 1: "LMBD_E_INVALID_ARG", 2: "LMBD_E_OOM", 3: "LMBD_E_OOM_ADMISSION",
+    4: "LMBD_E_DEVICE", 5: "LMBD_E_SCS_BREAKDOWN", 6: "LMBD_E_UNSUPPORTED",
+}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class Species(ctypes.Structure):
+    _fields_ = [("alpha0", ctypes.c_double), ("c6", ctypes.c_double), ("r0", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("beta", ctypes.c_double), ("damp_d", ctypes.c_double), ("r_buf", ctypes.c_double),
+        ("r_inner", ctypes.c_double), ("n_max", ctypes.c_int32), ("c_n", _dp),
+        ("n_freq", ctypes.c_int32), ("omega", _dp), ("weight", _dp), ("precision", ctypes.c_int32),
+    ]
+
+
+class StructureDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int64), ("pos", ctypes.c_void_p), ("species", ctypes.c_void_p),
+        ("v_ratio", ctypes.c_void_p), ("cell", _dp), ("pbc", ctypes.c_int32 * 3),
+        ("r_scs", ctypes.c_double), ("r_nbr", ctypes.c_double), ("r_mbd1", ctypes.c_double),
+        ("r_mbd2", ctypes.c_double), ("e_weight", ctypes.c_void_p), ("e_atom", ctypes.c_void_p),
+        ("forces", ctypes.c_void_p), ("alpha_scs0", ctypes.c_void_p),
+    ]
+
+
+class LmbdError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"{self.code}: {detail}" if detail else self.code)
+
+
+_lib = None
+
+
+def lib():
+    """Load liblmbd.so; fails loudly if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_06409_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.lmbd_abi_version.restype = ctypes.c_int32
+    L.lmbd_status_string.restype = ctypes.c_char_p
+    L.lmbd_status_string.argtypes = [ctypes.c_int]
+    L.lmbd_last_error.restype = ctypes.c_char_p
+    L.lmbd_last_error.argtypes = [ctypes.c_void_p]
+    L.lmbd_create.restype = ctypes.c_int
+    L.lmbd_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+    L.lmbd_destroy.restype = None
+    L.lmbd_destroy.argtypes = [ctypes.c_void_p]
+    L.lmbd_set_memory_budget.restype = ctypes.c_int
+    L.lmbd_set_memory_budget.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    L.lmbd_compute_batch.restype = ctypes.c_int
+    L.lmbd_compute_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
+                                     ctypes.POINTER(Species), ctypes.c_int32,
+                                     ctypes.POINTER(StructureDesc), ctypes.c_int32, ctypes.c_void_p]
+    L.lmbd_compute.restype = ctypes.c_int
+    L.lmbd_compute.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
+                               ctypes.POINTER(Species), ctypes.POINTER(StructureDesc), ctypes.c_int32,
+                               ctypes.c_void_p]
+    L.lmbd_estimate_footprint.restype = ctypes.c_int
+    L.lmbd_estimate_footprint.argtypes = [ctypes.POINTER(Params), ctypes.c_int32,
+                                          ctypes.POINTER(StructureDesc), ctypes.POINTER(ctypes.c_size_t)]
+    _lib = L
+    return L
+
+
+EXPORTED = ["lmbd_abi_version", "lmbd_create", "lmbd_destroy", "lmbd_set_memory_budget",
+            "lmbd_compute_batch", "lmbd_compute", "lmbd_estimate_footprint", "lmbd_status_string",
+            "lmbd_last_error"]

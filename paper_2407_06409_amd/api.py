@@ -1,0 +1,224 @@
+"""Python face of the lMBD library: marshals arguments to the C ABI.
+
+Every step of the method runs in the HIP kernels of ``liblmbd.so``; torch is
+used only for device memory and the current stream.
+"""
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+
+@dataclass
+class MethodParams:
+    """Parameters shared by every structure of a call (lengths in Angstrom, Ha)."""
+    omega: Sequence[float]
+    weight: Sequence[float]
+    beta: float = 0.83
+    damp_d: float = 6.0
+    r_buf: float = 0.5
+    r_inner: float = 2.0
+    n_max: int = 6
+    c_n: Optional[Sequence[float]] = None
+    precision: str = "fp64"
+
+    def to_c(self):
+        om = np.ascontiguousarray(self.omega, dtype=np.float64)
+        wt = np.ascontiguousarray(self.weight, dtype=np.float64)
+        keep = [om, wt]
+        cn = None
+        if self.c_n is not None:
+            cn = np.ascontiguousarray(self.c_n, dtype=np.float64)
+            keep.append(cn)
+        p = C.Params(self.beta, self.damp_d, self.r_buf, self.r_inner, int(self.n_max),
+                     cn.ctypes.data_as(C._dp) if cn is not None else None, int(om.shape[0]),
+                     om.ctypes.data_as(C._dp), wt.ctypes.data_as(C._dp),
+                     C.LMBD_MIXED if self.precision == "mixed" else C.LMBD_FP64)
+        return p, keep
+
+
+def species_array(table):
+    t = np.asarray(table, dtype=np.float64).reshape(-1, 3)
+    arr = (C.Species * t.shape[0])()
+    for i, (a, c6, r0) in enumerate(t):
+        arr[i] = C.Species(a, c6, r0)
+    return arr, t.shape[0]
+
+
+class Context:
+    """Owns one library context (device workspaces) on one GPU."""
+
+    def __init__(self, device: int = 0, memory_budget: int = 0):
+        self.lib = C.lib()
+        h = ctypes.c_void_p()
+        st = self.lib.lmbd_create(int(device), ctypes.byref(h))
+        if st != 0:
+            raise C.LmbdError(st, f"lmbd_create(device={device})")
+        self.handle = h
+        self.device = device
+        if memory_budget:
+            self.set_memory_budget(memory_budget)
+
+    def set_memory_budget(self, nbytes: int):
+        st = self.lib.lmbd_set_memory_budget(self.handle, ctypes.c_size_t(int(nbytes)))
+        if st != 0:
+            raise C.LmbdError(st)
+
+    def last_error(self) -> str:
+        return (self.lib.lmbd_last_error(self.handle) or b"").decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lmbd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return ctypes.c_void_p(x.data_ptr())
+    return ctypes.c_void_p(x.ctypes.data)
+
+
+def compute_batch(structures, params: MethodParams, species_table, *, forces=True, ctx: Context = None,
+                  stream=None, want_alpha=False):
+    """Energies and forces of several structures in one set of launches.
+
+    ``structures``: list of dicts with keys pos (N,3), species (N,), v_ratio (N,),
+    cell (3,3) or None, pbc (3,), cutoffs {r_scs, r_nbr, r_mbd1, r_mbd2} and
+    optionally e_weight (N,).  Arrays are either all CUDA tensors (float64/int32,
+    results are CUDA tensors, work on the current or given stream) or all host
+    numpy arrays (results are numpy arrays).
+    Returns a list of dicts {energies, forces?, alpha_scs0?}.
+    """
+    device_mode = isinstance(structures[0]["pos"], torch.Tensor) and structures[0]["pos"].is_cuda
+    if ctx is None:
+        dev = structures[0]["pos"].device.index if device_mode else 0
+        ctx = default_context(dev or 0)
+    p, keep = params.to_c()
+    sp, n_sp = species_array(species_table)
+    descs = (C.StructureDesc * len(structures))()
+    outs = []
+    for i, s in enumerate(structures):
+        if device_mode:
+            pos = s["pos"].contiguous()
+            spc = s["species"].to(torch.int32).contiguous()
+            nu = s["v_ratio"].contiguous()
+            w = s.get("e_weight")
+            w = None if w is None else w.contiguous()
+            e = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
+            f = torch.empty_like(pos) if forces else None
+            a = torch.empty_like(e) if want_alpha else None
+        else:
+            pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
+            spc = np.ascontiguousarray(s["species"], dtype=np.int32)
+            nu = np.ascontiguousarray(s["v_ratio"], dtype=np.float64)
+            w = s.get("e_weight")
+            w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+            e = np.empty(pos.shape[0])
+            f = np.empty_like(pos) if forces else None
+            a = np.empty_like(e) if want_alpha else None
+        cell = s.get("cell")
+        cell_np = None if cell is None else np.ascontiguousarray(
+            cell.detach().cpu().numpy() if isinstance(cell, torch.Tensor) else cell, dtype=np.float64)
+        pbc = s.get("pbc", (0, 0, 0))
+        pbc = [int(bool(x)) for x in (pbc.tolist() if hasattr(pbc, "tolist") else pbc)]
+        cut = s["cutoffs"]
+        keep.extend([pos, spc, nu, w, e, f, a, cell_np])
+        descs[i] = C.StructureDesc(
+            int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
+            cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
+            (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
+            float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a))
+        outs.append({"energies": e, "forces": f, "alpha_scs0": a})
+    if device_mode:
+        if stream is None:
+            stream = torch.cuda.current_stream(structures[0]["pos"].device)
+        hs = ctypes.c_void_p(stream.cuda_stream)
+        mem = C.LMBD_DEVICE
+    else:
+        hs = None
+        mem = C.LMBD_HOST
+    st = ctx.lib.lmbd_compute_batch(ctx.handle, ctypes.byref(p), n_sp, sp, len(structures), descs, mem, hs)
+    if st != 0:
+        raise C.LmbdError(st, ctx.last_error())
+    return outs
+
+
+def compute(pos, species, v_ratio, *, cutoffs, params: MethodParams, species_table, cell=None,
+            pbc=None, e_weight=None, forces=True, ctx: Context = None, stream=None, want_alpha=False):
+    """Per-atom energies (eV) and forces (eV/A) of one structure."""
+    if pbc is None:
+        pbc = (1, 1, 1) if cell is not None else (0, 0, 0)
+    s = dict(pos=pos, species=species, v_ratio=v_ratio, cell=cell, pbc=pbc, cutoffs=cutoffs,
+             e_weight=e_weight)
+    return compute_batch([s], params, species_table, forces=forces, ctx=ctx, stream=stream,
+                         want_alpha=want_alpha)[0]
+
+
+def estimate_footprint(structures, params: MethodParams, forces=True) -> int:
+    """Device bytes that one call on these (host-array) structures would use."""
+    p, keep = params.to_c()
+    descs = (C.StructureDesc * len(structures))()
+    for i, s in enumerate(structures):
+        pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
+        cell = s.get("cell")
+        cell_np = None if cell is None else np.ascontiguousarray(cell, dtype=np.float64)
+        keep.extend([pos, cell_np])
+        pbc = [int(bool(x)) for x in s.get("pbc", (0, 0, 0))]
+        cut = s["cutoffs"]
+        dummy = ctypes.c_void_p(1)
+        descs[i] = C.StructureDesc(
+            int(pos.shape[0]), _ptr(pos), dummy, dummy,
+            cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
+            (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
+            float(cut["r_mbd1"]), float(cut["r_mbd2"]), None, None, dummy if forces else None, None)
+    out = ctypes.c_size_t(0)
+    st = C.lib().lmbd_estimate_footprint(ctypes.byref(p), len(structures), descs, ctypes.byref(out))
+    if st != 0:
+        raise C.LmbdError(st)
+    return int(out.value)
+
+
+class LMBDEnergy(torch.autograd.Function):
+    """Per-atom lMBD energies as a differentiable function of positions.
+
+    backward() runs the library once more with the incoming gradient as the
+    adjoint seeds w_k and returns -forces = d(sum_k w_k E_k)/dR.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, species, v_ratio, cell, cutoffs, params, species_table):
+        out = compute(pos.detach(), species, v_ratio, cutoffs=cutoffs, params=params,
+                      species_table=species_table, cell=cell, forces=False)
+        ctx.save_for_backward(pos, species, v_ratio)
+        ctx.extra = (cell, cutoffs, params, species_table)
+        return out["energies"]
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        pos, species, v_ratio = ctx.saved_tensors
+        cell, cutoffs, params, species_table = ctx.extra
+        out = compute(pos.detach(), species, v_ratio, cutoffs=cutoffs, params=params,
+                      species_table=species_table, cell=cell, e_weight=grad_e.contiguous(), forces=True)
+        return -out["forces"], None, None, None, None, None, None

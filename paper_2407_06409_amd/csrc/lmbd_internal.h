@@ -1,0 +1,219 @@
+// Internal definitions shared by the lMBD HIP kernels and the host driver.
+// Not part of the public ABI (see include/lmbd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lmbd {
+
+// CODATA 2018
+constexpr double kBohr = 0.529177210903;      // Angstrom per bohr
+constexpr double kHartree = 27.211386245988;  // eV per hartree
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoOverSqrtPi = 1.12837916709551257390;  // 2/sqrt(pi)
+constexpr double kSqrt2OverPi = 0.79788456080286535588;    // sqrt(2/pi)
+
+// Kernel size limits (checked on the host before any launch).
+constexpr int kMaxFreq = 33;       // omega = 0 plus up to 32 quadrature nodes
+constexpr int kMaxNmax = 12;       // highest body order
+constexpr int kMaxN1 = 160;        // atoms in K1 (r < r_scs), central atom included
+constexpr int kMaxNK = 160;        // atoms in K (r < r_nbr), central atom included
+constexpr int kMaxSites = 4096;    // sites in the largest ball, central atom included
+
+// One site of a neighbourhood: an atom or one of its periodic images, stored
+// relative to the central atom.  32 bytes.
+struct Site {
+    double x, y, z;   // position relative to the central atom, bohr
+    int32_t base;     // batch-global index of the atom it is an image of
+    int32_t shift;    // lattice shift packed as 3 x 8 bits, each biased by 128
+};
+
+__host__ __device__ inline int32_t pack_shift(int a, int b, int c) {
+    return ((a + 128) << 16) | ((b + 128) << 8) | (c + 128);
+}
+__host__ __device__ inline void unpack_shift(int32_t s, int& a, int& b, int& c) {
+    a = ((s >> 16) & 255) - 128;
+    b = ((s >> 8) & 255) - 128;
+    c = (s & 255) - 128;
+}
+
+// Per-structure data on the device.
+struct StructInfo {
+    double cell[9];      // rows = lattice vectors, bohr (open: diagonal grid box)
+    double inv[9];       // inverse of cell: frac = pos @ inv
+    double origin[3];    // open structures: lower corner of the bounding box, bohr
+    int periodic;        // 1 = periodic in all three directions, 0 = open
+    int ncell[3];        // cell-list grid
+    int reach[3];        // cells to visit on each side
+    int cell_offset;     // first batch-global cell index
+    int atom_offset;     // first batch-global atom index
+    int n_atoms;
+    double r_scs, r_nbr, r_mbd1, r_mbd2, r_big;  // bohr
+};
+
+// Per-atom neighbourhood counts (central atom included in every count).
+struct Counts {
+    int32_t n_all;   // sites with r < r_big = max(2 r_scs, r_nbr)
+    int32_t n1;      // r < r_scs       (K1 of the SCS)
+    int32_t nK;      // r < r_nbr       (K of the energy)
+    int32_t n12;     // r < 2 r_scs     (K1 plus the uncoupled shell K2)
+};
+
+// ---------------------------------------------------------------------------
+// Pair functions (device).  r in bohr.
+// ---------------------------------------------------------------------------
+
+// Fermi damping f(r, S) = 1 / (1 + exp(-d (r / S - 1))) and its partial
+// derivatives: df/dr = d f (1 - f) / S, df/dS = -d r f (1 - f) / S^2.
+__device__ inline double fermi(double r, double S, double d, double& dfdr, double& dfdS) {
+    const double f = 1.0 / (1.0 + exp(-d * (r / S - 1.0)));
+    const double g = d * f * (1.0 - f) / S;
+    dfdr = g;
+    dfdS = -g * r / S;
+    return f;
+}
+
+// Smooth cutoff: 1 below rc - rb, 1 - 3x^2 + 2x^3 with x = (r - rc + rb)/rb in
+// the buffer, 0 from rc on; returns value and d/dr.
+__device__ inline double cutoff_poly(double r, double rc, double rb, double& dcdr) {
+    if (r < rc - rb) { dcdr = 0.0; return 1.0; }
+    if (r >= rc) { dcdr = 0.0; return 0.0; }
+    const double x = (r - rc + rb) / rb;
+    dcdr = (-6.0 * x + 6.0 * x * x) / rb;
+    return 1.0 - 3.0 * x * x + 2.0 * x * x * x;
+}
+
+// Radial decomposition of a symmetric pair tensor M(r_vec) = A(r) rhat rhat^T + B(r) I.
+// Its gradient contracted with a symmetric 3x3 matrix C is
+//   sum_ab C_ab dM_ab/dr_g = (A' - 2A/r)(rhat.C.rhat) rhat_g + (2A/r)(C rhat)_g + B' tr(C) rhat_g,
+// using d rhat_a / dr_g = (delta_ag - rhat_a rhat_g) / r.
+__device__ inline void radial_tensor_grad(const double rh[3], double r, double A, double dA,
+                                          double dB, const double C[9], double g[3]) {
+    const double Cr0 = C[0] * rh[0] + C[1] * rh[1] + C[2] * rh[2];
+    const double Cr1 = C[3] * rh[0] + C[4] * rh[1] + C[5] * rh[2];
+    const double Cr2 = C[6] * rh[0] + C[7] * rh[1] + C[8] * rh[2];
+    const double rCr = rh[0] * Cr0 + rh[1] * Cr1 + rh[2] * Cr2;
+    const double tr = C[0] + C[4] + C[8];
+    const double a = (dA - 2.0 * A / r) * rCr + dB * tr;
+    const double b = 2.0 * A / r;
+    g[0] = a * rh[0] + b * Cr0;
+    g[1] = a * rh[1] + b * Cr1;
+    g[2] = a * rh[2] + b * Cr2;
+}
+
+// Coefficients of the short-range core H = -T g + h = -(Hessian of erf(r/s)/r)
+// written as A rhat rhat^T + B I:
+//   A = -(3 g - 2 c u^3 e) / r^3,  B = g / r^3,  c = 2/sqrt(pi), u = r/s, e = exp(-u^2)
+// with g = erf(u) - c u e (Sec. II.B, T_SR with the g and h functions).
+__device__ inline void sr_core(double r, double s, double& A, double& B, double& dA, double& dB) {
+    const double u = r / s;
+    const double e = exp(-u * u);
+    const double g = erf(u) - kTwoOverSqrtPi * u * e;
+    const double u3e = u * u * u * e;
+    const double r3 = r * r * r;
+    const double P = 3.0 * g - 2.0 * kTwoOverSqrtPi * u3e;       // A = -P / r^3
+    // dP/dr = 2 c u^5 e / r * 2  (from g' = 2 c u^3 e / r and (u^3 e)' = (3 - 2u^2) u^3 e / r)
+    const double dP = 4.0 * kTwoOverSqrtPi * u3e * u * u / r;
+    A = -P / r3;
+    dA = -dP / r3 + 3.0 * P / (r3 * r);
+    B = g / r3;
+    dB = 2.0 * kTwoOverSqrtPi * u3e / r3 / r - 3.0 * g / (r3 * r);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks and host launchers
+// ---------------------------------------------------------------------------
+struct NbrArgs {
+    int n;
+    const double* pos_b;
+    const int32_t* atom_struct;
+    const StructInfo* sinfo;
+    const int32_t* cell_id;
+    const int32_t* wrap;
+    const int32_t* cell_start;
+    const int32_t* cell_end;
+    const int32_t* sorted_atoms;
+};
+
+struct ScsArgs {
+    int n, nw;
+    const Counts* counts;
+    const int64_t* site_off;
+    const Site* sites;
+    const double* abar;      // [n][nw]
+    const double* sigma;     // [n][nw]
+    const double* Rv;        // [n]
+    const int32_t* atom_struct;
+    const StructInfo* sinfo;
+    double beta, damp_d, r_buf, r_inner;   // bohr
+    double* fac;             // factor slots: per atom nw * ld * N, column-major lower
+    const int64_t* fac_off;
+    const int32_t* fac_ld;
+    double* xsol;            // per atom nw * N * 3 (row-major)
+    const int64_t* x_off;
+    double* alpha_loc;       // per atom n1 * nw
+    const int64_t* aloc_off;
+    int* err;
+    int* err_atom;
+    // adjoint only
+    const double* abar_loc;  // per atom n1 * nw: adjoint of the local polarisabilities
+    const double* abar_cen;  // [n][nw]: adjoint of the central polarisabilities
+    double* cf;              // force contributions [nw][total_sites][3] (slice base)
+    int64_t cf_slice;        // stride between frequency slices
+};
+
+struct MbdArgs {
+    int n, nw, nq, n_max, ncol, mmax;
+    const Counts* counts;
+    const int64_t* site_off;
+    const Site* sites;
+    const double* alpha_loc;   // per atom n1 * nw
+    const int64_t* aloc_off;
+    const double* a0v;
+    const double* r0v;
+    const int32_t* atom_struct;
+    const StructInfo* sinfo;
+    double beta, damp_d, r_buf;
+    double coef[kMaxNmax + 1];
+    double wq[kMaxFreq];       // quadrature weight * Hartree / (2 pi): eV per unit integrand
+    const double* e_weight;    // [n] or null
+    double* e_atom;            // [n]
+    double* work;              // per atom T (N3^2), U (mmax N3 ncol), Z (n_max N3 ncol)
+    const int64_t* work_off;
+    int forces;
+    double* abar_loc;          // per atom n1 * nw (aloc_off)
+    double* ca;                // [total_sites][nw]
+    double* cf0;               // [total_sites][3]
+};
+
+hipError_t launch_prep(hipStream_t st, int n, const double* pos_A, const int32_t* species,
+                       const double* nu, const int32_t* atom_struct, const StructInfo* sinfo,
+                       const double* sp_table, int n_species, const double* omegas, int nw,
+                       double* pos_b, double* abar, double* sigma, double* Rv, double* a0v,
+                       double* r0v, int32_t* cell_id, int32_t* wrap, int* err);
+hipError_t sort_cells(hipStream_t st, int n, int n_cells, const int32_t* cell_id,
+                      const int32_t* iota, int32_t* sorted_cell, int32_t* sorted_atoms,
+                      void* temp, size_t* temp_bytes, int32_t* cell_start, int32_t* cell_end);
+hipError_t launch_nbr_count(hipStream_t st, const NbrArgs& a, Counts* counts);
+hipError_t launch_nbr_fill(hipStream_t st, const NbrArgs& a, const Counts* counts,
+                           const int64_t* site_off, Site* sites);
+hipError_t launch_rev_map(hipStream_t st, int n, const Counts* counts, const int64_t* site_off,
+                          const Site* sites, const int64_t* hash_off, const int32_t* hash_cap,
+                          int32_t* table, size_t table_len, int32_t* rev, int* err);
+size_t scs_lds_bytes(int n1max);
+hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max);
+hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max);
+size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max);
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax);
+hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
+                                 const int64_t* site_off, const Site* sites, const int32_t* rev,
+                                 const double* ca, double* abar_cen);
+hipError_t launch_gather_forces(hipStream_t st, int n, int nslices, int64_t slice_stride,
+                                const Counts* counts, const int64_t* site_off, const Site* sites,
+                                const int32_t* rev, const double* cf, double* forces);
+hipError_t launch_central_static(hipStream_t st, int n, int nw, const double* alpha_loc,
+                                 const int64_t* aloc_off, double* out);
+
+}  // namespace lmbd
