@@ -1,0 +1,179 @@
+"""Throughput of the lMBD hot path (energy + exact forces) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+                    [--workload plain|mixed] [--no-cpu-baseline]
+
+A step is one complete evaluation (neighbour lists, local SCS at every
+frequency, local MBD energies, all adjoints, forces) of the whole workload,
+with inputs resident in device memory.  The default workload is 1,728 C atoms
+in a periodic box at 2.0 g/cm^3 with a 6 A cutoff, 12 quadrature nodes and
+n_max = 6, in FP64.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atoms/s lMBD energy+forces, FP64 plain vs mixed/served at <=1e-5 eV/atom; p99"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def neighbour_counts(st, rc):
+    """Atoms within rc of every atom, itself included (input analysis only)."""
+    from scipy.spatial import cKDTree
+    if st.cell is not None:
+        L = float(st.cell[0, 0])
+        tree = cKDTree(np.mod(st.pos, L), boxsize=L)
+        pts = np.mod(st.pos, L)
+    else:
+        tree = cKDTree(st.pos)
+        pts = st.pos
+    return np.array([len(x) for x in tree.query_ball_point(pts, rc - 1e-12)])
+
+
+def scs_forward_flops(n1, nw):
+    """Algorithmic FLOPs of the SCS forward stage: per (atom, frequency) a
+    symmetric factorisation (N^3/3) and two triangular solves with 3 right-hand
+    sides (6 N^2), N = 3 n1."""
+    N = 3.0 * n1.astype(np.float64)
+    return float(np.sum(nw * (N ** 3 / 3.0 + 6.0 * N ** 2)))
+
+
+def mbd_flops(nK, nq, n_max, forces):
+    """Algorithmic FLOPs of the MBD stage: Krylov products (N3^2 x 3 n_q each) and,
+    with forces, the Tbar product (N3^2 x 3 n_q n_max)."""
+    N3 = 3.0 * nK.astype(np.float64)
+    ncol = 3 * nq
+    prods = (n_max - 2) if forces else (math.ceil(n_max / 2) - 1)
+    f = np.sum(prods * 2.0 * N3 ** 2 * ncol)
+    if forces:
+        f += np.sum(2.0 * N3 ** 2 * ncol * n_max)
+    return float(f)
+
+
+def cpu_baseline(st, cut, grid):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload.
+
+    Sample: the energy+forces pass of two central atoms; the oracle reports the
+    time and atom count of each of its three passes, from which the cost of one
+    atom of the complete job (one central SCS, one MBD+SCS reverse pass, one SCS
+    reverse pass) is extrapolated.
+    """
+    import torch
+    import oracle
+    from workloads import SPECIES_TABLE, DEFAULT_PARAMS
+    prm = oracle.make_params(cut, grid[0], grid[1], n_max=DEFAULT_PARAMS["n_max"], beta=DEFAULT_PARAMS["beta"],
+                             damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
+                             r_inner=DEFAULT_PARAMS["r_inner"])
+    sample = [0, st.n // 2]
+    tm = {}
+    t0 = time.perf_counter()
+    oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE, atoms=sample, timings=tm)
+    wall = time.perf_counter() - t0
+    per_atom = (tm["central_s"] / tm["central_atoms"] + tm["pass_b_s"] / tm["pass_b_atoms"]
+                + tm["pass_c_s"] / max(1, tm["pass_c_atoms"]))
+    return {"value": 1.0 / per_atom, "unit": "atoms/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": (f"energy+forces of {len(sample)} central atoms of the same 1,728-atom box "
+                       f"({tm['central_atoms']} central SCS solves, {tm['pass_c_atoms']} SCS reverse passes, "
+                       f"{wall:.1f} s); per-atom cost of the full job extrapolated from the three pass timings"),
+            "wall_s": wall}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "documented but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from workloads import SPECIES_TABLE, DEFAULT_PARAMS, frequency_grid
+    from workloads import configs as C
+    import paper_2407_06409_amd as P
+
+    if args.workload == "plain":
+        st, cut = C.config_plain_pbc()
+    else:
+        st, cut = C.config_mixed_pbc()
+    grid = frequency_grid(DEFAULT_PARAMS["n_freq"])
+    mp = P.MethodParams(omega=grid[0], weight=grid[1], beta=DEFAULT_PARAMS["beta"], damp_d=DEFAULT_PARAMS["damp_d"],
+                        r_buf=DEFAULT_PARAMS["r_buf"], r_inner=DEFAULT_PARAMS["r_inner"],
+                        n_max=DEFAULT_PARAMS["n_max"], precision=args.precision)
+    dev = torch.device("cuda:0")
+    pos = torch.as_tensor(st.pos, dtype=torch.float64, device=dev)
+    sp = torch.as_tensor(st.species, dtype=torch.int32, device=dev)
+    nu = torch.as_tensor(st.nu, dtype=torch.float64, device=dev)
+    ctx = P.Context(0)
+    ctx.set_profiling(True)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        return P.compute(pos, sp, nu, cutoffs=cut, params=mp, species_table=SPECIES_TABLE, cell=st.cell,
+                         forces=True, ctx=ctx, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, stages = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        out = step()
+        lat.append(time.perf_counter() - ts)
+        stages.append(ctx.stage_times())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = st.n * args.steps / elapsed
+    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+
+    nq, nw, n_max = len(grid[0]), len(grid[0]) + 1, DEFAULT_PARAMS["n_max"]
+    n1 = neighbour_counts(st, cut["r_scs"])
+    nK = neighbour_counts(st, cut["r_nbr"])
+    kernels = {
+        "scs_forward": (scs_forward_flops(n1, nw), stage_ms["scs_forward"]),
+        "mbd": (mbd_flops(nK, nq, n_max, True), stage_ms["mbd"]),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    flops, ms = kernels[dom]
+    peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    achieved = flops / (ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"lMBD energy+forces, {st.n} C atoms periodic 2.0 g/cm3, cutoff "
+                               f"{cut['r_scs']} A, {nq} GL nodes, n_max {n_max}, {args.precision}",
+                   "n_atoms": st.n, "cutoff_A": cut["r_scs"], "n_freq": nq, "n_max": n_max,
+                   "precision": args.precision},
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "stages_ms": stage_ms, "roofline": roofline,
+        "mean_n1": float(n1.mean()), "energy_eV": float(out["energies"].sum().item()),
+    }
+    if not args.no_cpu_baseline and args.workload == "plain":
+        line["cpu_baseline"] = cpu_baseline(st, cut, grid)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

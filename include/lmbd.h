@@ -139,12 +139,14 @@ lmbd_status lmbd_set_memory_budget(lmbd_context* ctx, size_t bytes);
  *
  * species_table: HOST array of n_species entries.  structs: HOST array of
  * n_structs descriptors.  mem = LMBD_DEVICE: every array of the descriptors is a
- * device pointer on the context's device and the work is ordered on
- * `hip_stream` (a hipStream_t, NULL = default stream); the call returns after
- * enqueueing the work that follows its single host synchronisation (the
- * neighbour-count read-back) and outputs are valid once the stream is
- * synchronised.  mem = LMBD_HOST: host arrays; the call is synchronous.
- * Results of a structure do not depend on the other structures of the batch. */
+ * device pointer on the context's device; mem = LMBD_HOST: host arrays.  All
+ * work is ordered on `hip_stream` (a hipStream_t, NULL = default stream) and
+ * the call returns when the outputs are written (it synchronises the stream,
+ * once after the neighbour counts and once at the end), so that a breakdown or
+ * a bad input is reported by its status.  Concurrent calls on different
+ * streams need one context each (one host thread per context); their kernels
+ * overlap on the device.  Results of a structure are bitwise independent of the
+ * other structures of the batch.  On error the outputs are unspecified. */
 lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params,
                                int32_t n_species, const lmbd_species* species_table,
                                int32_t n_structs, const lmbd_structure* structs,
@@ -159,6 +161,19 @@ lmbd_status lmbd_compute(lmbd_context* ctx, const lmbd_params* params,
  * counting; positions are HOST arrays here whatever `mem` a later call uses). */
 lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs,
                                     const lmbd_structure* structs, size_t* bytes);
+
+/* Stage timers.  With profiling on, the library records a HIP event on the
+ * call's stream before and after each stage of the hot path and, once the call
+ * has completed, keeps the elapsed milliseconds of the last call per stage.
+ * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map,
+ * 2 local SCS forward, 3 local MBD energy (+adjoint), 4 central-polarisability
+ * gather, 5 local SCS adjoint, 6 force gather. */
+#define LMBD_N_STAGES 7
+lmbd_status lmbd_set_profiling(lmbd_context* ctx, int32_t enable);
+/* ms: caller array of LMBD_N_STAGES doubles; stages not run in the last call read 0. */
+lmbd_status lmbd_stage_times(const lmbd_context* ctx, double* ms);
+/* Name of stage i (0 <= i < LMBD_N_STAGES), or NULL. */
+const char* lmbd_stage_name(int32_t i);
 
 /* Static description of a status code. */
 const char* lmbd_status_string(lmbd_status status);

@@ -420,7 +420,7 @@ def lmbd_energies(structure, prm, species_table, atoms=None, central=None):
     return e
 
 
-def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None):
+def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, timings=None):
     """Per-atom energies (eV) and exact forces -d(sum_k w_k E_k)/dR (eV/A).
 
     Reverse mode in two passes, mirroring the two stages: pass B differentiates
@@ -428,7 +428,11 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None):
     gradients of the central polarisabilities it used; pass C pushes those
     through each atom's own SCS solve.  ``atoms`` restricts the sum over k
     (for timing a bounded sample); the forces are then those of that partial sum.
+    If ``timings`` is a dict, the wall time and the number of atoms of the
+    central pass (A), pass B and pass C are stored in it.
     """
+    import time
+    t0 = time.perf_counter()
     st, fa, images = _prepare(structure, prm, species_table)
     N = structure.n
     nw = 1 + len(prm.omega)
@@ -442,7 +446,9 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None):
         return frames[k]
 
     needed = sorted({int(b) for k in ks for b in frame(k).base[:frame(k).nK]})
+    t1 = time.perf_counter()
     central = scs_central(structure, prm, species_table, needed)
+    t2 = time.perf_counter()
     cell_t = _cell_tensor(st)
     pos_t = torch.tensor(st["pos"], dtype=_DT, requires_grad=True)
     abar_c = np.zeros((N, nw))
@@ -456,11 +462,18 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None):
         e[k] = float(ek.detach())
         (w[k] * ek).backward()
         np.add.at(abar_c, fr.base[:fr.nK], acen.grad.numpy())
+    t3 = time.perf_counter()
+    n_c = 0
     for a in range(N):  # pass C
         if not np.any(abar_c[a] != 0.0):
             continue
+        n_c += 1
         fr = frame(a)
         p = fr.positions(pos_t, cell_t)
         aloc = _scs_solve(fr, p, fa, prm)
         (aloc[:, 0] * torch.as_tensor(abar_c[a], dtype=_DT)).sum().backward()
+    t4 = time.perf_counter()
+    if timings is not None:
+        timings.update(prepare_s=t1 - t0, central_s=t2 - t1, central_atoms=len(needed), pass_b_s=t3 - t2,
+                       pass_b_atoms=len(ks), pass_c_s=t4 - t3, pass_c_atoms=n_c)
     return e, -pos_t.grad.numpy().copy()

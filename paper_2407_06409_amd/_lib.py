@@ -79,10 +79,17 @@ def lib():
     L.lmbd_estimate_footprint.restype = ctypes.c_int
     L.lmbd_estimate_footprint.argtypes = [ctypes.POINTER(Params), ctypes.c_int32,
                                           ctypes.POINTER(StructureDesc), ctypes.POINTER(ctypes.c_size_t)]
+    L.lmbd_set_profiling.restype = ctypes.c_int
+    L.lmbd_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.lmbd_stage_times.restype = ctypes.c_int
+    L.lmbd_stage_times.argtypes = [ctypes.c_void_p, _dp]
+    L.lmbd_stage_name.restype = ctypes.c_char_p
+    L.lmbd_stage_name.argtypes = [ctypes.c_int32]
     _lib = L
     return L
 
 
 EXPORTED = ["lmbd_abi_version", "lmbd_create", "lmbd_destroy", "lmbd_set_memory_budget",
             "lmbd_compute_batch", "lmbd_compute", "lmbd_estimate_footprint", "lmbd_status_string",
-            "lmbd_last_error"]
+            "lmbd_last_error", "lmbd_set_profiling", "lmbd_stage_times", "lmbd_stage_name"]
+N_STAGES = 7

@@ -68,6 +68,19 @@ class Context:
         if st != 0:
             raise C.LmbdError(st)
 
+    def set_profiling(self, on: bool = True):
+        st = self.lib.lmbd_set_profiling(self.handle, 1 if on else 0)
+        if st != 0:
+            raise C.LmbdError(st, self.last_error())
+
+    def stage_times(self) -> dict:
+        """Milliseconds per stage of the last call (HIP events on the call's stream)."""
+        arr = (ctypes.c_double * C.N_STAGES)()
+        st = self.lib.lmbd_stage_times(self.handle, arr)
+        if st != 0:
+            raise C.LmbdError(st)
+        return {self.lib.lmbd_stage_name(i).decode(): arr[i] for i in range(C.N_STAGES)}
+
     def last_error(self) -> str:
         return (self.lib.lmbd_last_error(self.handle) or b"").decode()
 

@@ -55,6 +55,10 @@ struct lmbd_context {
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
     DBuf e_out, f_out, a_out;
+    bool profiling = false;
+    hipEvent_t ev[2 * LMBD_N_STAGES] = {};
+    bool ev_used[LMBD_N_STAGES] = {};
+    double stage_ms[LMBD_N_STAGES] = {};
 };
 
 namespace {
@@ -309,6 +313,8 @@ void lmbd_destroy(lmbd_context* ctx) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    for (hipEvent_t& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     DBuf* all[] = {&ctx->in_pos, &ctx->in_sp, &ctx->in_nu, &ctx->in_w, &ctx->atom_struct, &ctx->sinfo,
                    &ctx->sp_table, &ctx->omegas, &ctx->pos_b, &ctx->abar, &ctx->sigma, &ctx->Rv,
                    &ctx->a0v, &ctx->r0v, &ctx->cell_id, &ctx->wrap, &ctx->iota, &ctx->sorted_cell,
@@ -320,6 +326,27 @@ void lmbd_destroy(lmbd_context* ctx) {
     for (DBuf* b : all) release(*b);
     (void)hipSetDevice(prev);
     delete ctx;
+}
+
+static const char* kStageNames[LMBD_N_STAGES] = {"prep_sort_count", "nbr_fill_revmap", "scs_forward",
+                                                  "mbd",  "gather_central", "scs_adjoint", "gather_forces"};
+
+const char* lmbd_stage_name(int32_t i) { return (i >= 0 && i < LMBD_N_STAGES) ? kStageNames[i] : nullptr; }
+
+lmbd_status lmbd_set_profiling(lmbd_context* ctx, int32_t enable) {
+    if (!ctx) return LMBD_E_INVALID_ARG;
+    if (enable && !ctx->ev[0]) {
+        HIP_TRY(hipSetDevice(ctx->device));
+        for (hipEvent_t& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    ctx->profiling = enable != 0;
+    return LMBD_OK;
+}
+
+lmbd_status lmbd_stage_times(const lmbd_context* ctx, double* ms) {
+    if (!ctx || !ms) return LMBD_E_INVALID_ARG;
+    for (int i = 0; i < LMBD_N_STAGES; ++i) ms[i] = ctx->stage_ms[i];
+    return LMBD_OK;
 }
 
 lmbd_status lmbd_set_memory_budget(lmbd_context* ctx, size_t bytes) {
@@ -413,6 +440,15 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     const int nq = params->n_freq, nw = nq + 1, ncol = 3 * nq, n_max = params->n_max;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < LMBD_N_STAGES; ++i) {
+        ctx->ev_used[i] = false;
+        ctx->stage_ms[i] = 0.0;
+    }
+    auto mark = [&](int stage, int which) -> hipError_t {
+        if (!ctx->profiling) return hipSuccess;
+        if (which == 1) ctx->ev_used[stage] = true;
+        return hipEventRecord(ctx->ev[2 * stage + which], stream);
+    };
     const hipMemcpyKind h2d = mem == LMBD_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind d2o = mem == LMBD_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
 
@@ -499,6 +535,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(hipMemcpyAsync(ctx->flags.p, flags_init, sizeof(flags_init), hipMemcpyHostToDevice, stream));
     int* err = as<int>(ctx->flags);
     int* err_atom = err + 1;
+    HIP_TRY(mark(0, 0));
     HIP_TRY(launch_prep(stream, N, as<double>(ctx->in_pos), as<int32_t>(ctx->in_sp), as<double>(ctx->in_nu),
                         as<int32_t>(ctx->atom_struct), as<StructInfo>(ctx->sinfo), as<double>(ctx->sp_table),
                         n_species, as<double>(ctx->omegas), nw, as<double>(ctx->pos_b), as<double>(ctx->abar),
@@ -523,6 +560,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     na.cell_end = as<int32_t>(ctx->cell_end);
     na.sorted_atoms = as<int32_t>(ctx->sorted_atoms);
     HIP_TRY(launch_nbr_count(stream, na, as<Counts>(ctx->counts)));
+    HIP_TRY(mark(0, 1));
     std::vector<Counts> cnt(N);
     int flags[4];
     HIP_TRY(hipMemcpyAsync(cnt.data(), ctx->counts.p, sizeof(Counts) * N, hipMemcpyDeviceToHost, stream));
@@ -577,10 +615,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(ensure(ctx->a_out, sizeof(double) * N));
 
     // --- neighbour lists and the reverse-slot map
+    HIP_TRY(mark(1, 0));
     HIP_TRY(launch_nbr_fill(stream, na, as<Counts>(ctx->counts), as<int64_t>(ctx->site_off), as<Site>(ctx->sites)));
     HIP_TRY(launch_rev_map(stream, N, as<Counts>(ctx->counts), as<int64_t>(ctx->site_off), as<Site>(ctx->sites),
                            as<int64_t>(ctx->hash_off), as<int32_t>(ctx->hash_cap), as<int32_t>(ctx->table),
                            (size_t)P.table_len, as<int32_t>(ctx->rev), err));
+    HIP_TRY(mark(1, 1));
 
     // --- local SCS at omega = 0 and every node
     ScsArgs sa;
@@ -608,7 +648,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.aloc_off = as<int64_t>(ctx->aloc_off);
     sa.err = err;
     sa.err_atom = err_atom;
+    HIP_TRY(mark(2, 0));
     HIP_TRY(launch_scs_forward(stream, sa, P.n1max));
+    HIP_TRY(mark(2, 1));
 
     // --- local MBD energy (+ adjoint)
     MbdArgs ma;
@@ -641,18 +683,26 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.abar_loc = as<double>(ctx->abar_loc);
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
+    HIP_TRY(mark(3, 0));
     HIP_TRY(launch_mbd(stream, ma, P.nkmax));
+    HIP_TRY(mark(3, 1));
 
     if (forces) {
+        HIP_TRY(mark(4, 0));
         HIP_TRY(launch_gather_central(stream, N, nw, sa.counts, sa.site_off, sa.sites, as<int32_t>(ctx->rev),
                                       as<double>(ctx->ca), as<double>(ctx->abar_cen)));
+        HIP_TRY(mark(4, 1));
         sa.abar_loc = as<double>(ctx->abar_loc);
         sa.abar_cen = as<double>(ctx->abar_cen);
         sa.cf_slice = TS * 3;
         sa.cf = as<double>(ctx->cf) + sa.cf_slice;  // slices 1..nw
+        HIP_TRY(mark(5, 0));
         HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max));
+        HIP_TRY(mark(5, 1));
+        HIP_TRY(mark(6, 0));
         HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,
                                      as<int32_t>(ctx->rev), as<double>(ctx->cf), as<double>(ctx->f_out)));
+        HIP_TRY(mark(6, 1));
     }
     HIP_TRY(launch_central_static(stream, N, nw, sa.alpha_loc, sa.aloc_off, as<double>(ctx->a_out)));
 
@@ -672,6 +722,13 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     }
     HIP_TRY(hipMemcpyAsync(flags, ctx->flags.p, sizeof(flags), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    if (ctx->profiling)
+        for (int i = 0; i < LMBD_N_STAGES; ++i)
+            if (ctx->ev_used[i]) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+                ctx->stage_ms[i] = ms;
+            }
     if (flags[0] & 2) return fail(ctx, LMBD_E_DEVICE, "reverse neighbour slot not found");
     if (flags[0] & 4)
         return fail(ctx, LMBD_E_SCS_BREAKDOWN,
