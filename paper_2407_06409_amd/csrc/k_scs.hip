@@ -22,10 +22,10 @@ struct SrPair {
     double A, B, dA, dB;
 };
 
-__device__ inline SrPair sr_pair(double r, double s_ij, double S, double damp_d, double rc,
+__device__ inline SrPair sr_pair(double r, double ir, double s_ij, double S, double damp_d, double rc,
                                  double rb, double wmul, double dwmul) {
     double A, B, dA, dB;
-    sr_core(r, s_ij, A, B, dA, dB);
+    sr_core(r, ir, s_ij, A, B, dA, dB);
     double dfdr, dfdS, dcut;
     const double f = fermi(r, S, damp_d, dfdr, dfdS);
     const double fc = cutoff_poly(r, rc, rb, dcut);
@@ -43,24 +43,65 @@ __device__ inline void tri_decode(int t, int& i, int& j) {
 }
 
 // ---------------------------------------------------------------------------
-// Blocked Cholesky of the N x N lower triangle of A (column-major, leading
-// dimension ld) by one workgroup.  P is an LDS panel of at least N*NB doubles,
-// D an LDS 16x16 block.  Returns false in `ok` on a non-positive pivot.
+// Left-looking blocked Cholesky of the N x N lower triangle of A (column-major,
+// leading dimension ld) by one workgroup, 16-column panels:
+//   A[c0:N, c0:c0+16] -= L[c0:N, 0:c0] L[c0:c0+16, 0:c0]^T     (MFMA f64 16x16x4)
+//   L_pp = chol(A_pp)                                          (one wavefront, shuffles)
+//   L[c0+16:N, c0:c0+16] = A[c0+16:N, c0:c0+16] L_pp^{-T}       (one row per thread)
+// The update reads the finished columns with coalesced 128-byte row segments
+// and writes each panel element once.  D is a 16x16 LDS block.
+// MFMA f64 16x16x4 lane layout (gfx950): A[i][k] <- lane i + 16k, B[k][j] <- lane
+// j + 16k, D[i][j] -> lane j + 16 (i % 4), register i / 4.
 // ---------------------------------------------------------------------------
-__device__ void chol_factor(double* __restrict__ A, int N, int ld, double* P, double* D, bool& ok) {
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ void chol_factor(double* __restrict__ A, int N, int ld, double* D, bool& ok) {
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (N + NB - 1) / NB;
     bool good = true;
-    for (int j0 = 0; j0 < N; j0 += NB) {
-        const int jb = min(NB, N - j0);
-        // (a) diagonal block: wave 0, lane l holds row l of the block
+    for (int p = 0; p < nt; ++p) {
+        const int c0 = p * NB;
+        const int jb = min(NB, N - c0);
+        // (1) panel update with MFMA, one 16x16 row tile per wavefront at a time
+        if (c0 > 0) {
+            for (int r = p + wave; r < nt; r += nwave) {
+                const int R0 = r * NB;
+                d4_t acc;
+                const int col = c0 + li;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = R0 + lk + 4 * q;
+                    acc[q] = (row < N && col < N) ? A[(size_t)col * ld + row] : 0.0;
+                }
+                const int arow = R0 + li;
+                const bool arow_ok = arow < N;
+                const bool bcol_ok = col < N;
+#pragma unroll 4
+                for (int k0 = 0; k0 < c0; k0 += 4) {
+                    const size_t kc = (size_t)(k0 + lk) * ld;
+                    const double a = arow_ok ? -A[kc + arow] : 0.0;
+                    const double b = bcol_ok ? A[kc + col] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = R0 + lk + 4 * q;
+                    if (row < N && col < N && row >= col) A[(size_t)col * ld + row] = acc[q];
+                }
+            }
+            __syncthreads();
+        }
+        // (2) diagonal block: wavefront 0, lane l holds row l of the block
         if (tid < 64) {
             const int l = tid;
             double row[NB];
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 const bool valid = (l < jb) && (c <= l);
-                row[c] = valid ? A[(size_t)(j0 + c) * ld + j0 + l] : (l == c ? 1.0 : 0.0);
+                row[c] = valid ? A[(size_t)(c0 + c) * ld + c0 + l] : (l == c ? 1.0 : 0.0);
             }
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
@@ -83,16 +124,15 @@ __device__ void chol_factor(double* __restrict__ A, int N, int ld, double* P, do
             if (l < jb) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
-                    if (c <= l) A[(size_t)(j0 + c) * ld + j0 + l] = row[c];
+                    if (c <= l) A[(size_t)(c0 + c) * ld + c0 + l] = row[c];
             }
         }
         __syncthreads();
-        // (b) panel below the block: X L_bb^T = A_panel, row by row
-        const int r0 = j0 + jb;
-        for (int i = r0 + tid; i < N; i += nthr) {
+        // (3) rows below the block: X L_pp^T = A_panel, one row per thread
+        for (int i = c0 + jb + tid; i < N; i += nthr) {
             double x[NB];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = (c < jb) ? A[(size_t)(j0 + c) * ld + i] : 0.0;
+            for (int c = 0; c < NB; ++c) x[c] = (c < jb) ? A[(size_t)(c0 + c) * ld + i] : 0.0;
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 if (c < jb) {
@@ -103,45 +143,8 @@ __device__ void chol_factor(double* __restrict__ A, int N, int ld, double* P, do
                 }
             }
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c < jb) A[(size_t)(j0 + c) * ld + i] = x[c];
-                P[(size_t)(i - r0) * NB + c] = x[c];
-            }
-        }
-        __syncthreads();
-        // (c) trailing update A22 -= P P^T on 4x4 tiles of the lower triangle
-        const int m = N - r0;
-        if (m > 0) {
-            const int nt = (m + 3) / 4;
-            const int ntiles = nt * (nt + 1) / 2;
-            for (int t = tid; t < ntiles; t += nthr) {
-                int ti, tj;
-                tri_decode(t, ti, tj);
-                const int i0 = ti * 4, c0 = tj * 4;
-                double acc[4][4] = {};
-                for (int c = 0; c < jb; ++c) {
-                    double a[4], b[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        a[r] = (i0 + r < m) ? P[(size_t)(i0 + r) * NB + c] : 0.0;
-                        b[r] = (c0 + r < m) ? P[(size_t)(c0 + r) * NB + c] : 0.0;
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) acc[r][q] += a[r] * b[q];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int j = c0 + q;
-                    if (j >= m) continue;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = i0 + r;
-                        if (i < m && i >= j) A[(size_t)(r0 + j) * ld + r0 + i] -= acc[r][q];
-                    }
-                }
-            }
+            for (int c = 0; c < NB; ++c)
+                if (c < jb) A[(size_t)(c0 + c) * ld + i] = x[c];
         }
         __syncthreads();
     }
@@ -149,28 +152,44 @@ __device__ void chol_factor(double* __restrict__ A, int N, int ld, double* P, do
 }
 
 // Solve L L^T Y = Y in place for 3 right-hand sides (Y: LDS, row-major N x 3).
+// Each 16x16 diagonal block is solved by one wavefront with shuffles (lane
+// r + 16 c holds row r, right-hand side c); the coupling to the other rows is
+// one row per thread.
 __device__ void chol_solve3(const double* __restrict__ A, int N, int ld, double* Y) {
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    const int nt = (N + NB - 1) / NB;
     // forward: L y = b
-    for (int j0 = 0; j0 < N; j0 += NB) {
-        const int jb = min(NB, N - j0);
-        if (tid < 3) {
-            const int c = tid;
-            for (int r = 0; r < jb; ++r) {
-                double y = Y[(j0 + r) * 3 + c];
-                for (int q = 0; q < r; ++q) y -= A[(size_t)(j0 + q) * ld + j0 + r] * Y[(j0 + q) * 3 + c];
-                Y[(j0 + r) * 3 + c] = y / A[(size_t)(j0 + r) * ld + j0 + r];
+    for (int p = 0; p < nt; ++p) {
+        const int c0 = p * NB;
+        const int jb = min(NB, N - c0);
+        if (tid < 64) {
+            const int r = tid & 15, c = tid >> 4;
+            const bool act = (c < 3) && (r < jb);
+            double Lrow[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) Lrow[q] = (act && q <= r) ? A[(size_t)(c0 + q) * ld + c0 + r] : 0.0;
+            double y = act ? Y[(c0 + r) * 3 + c] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const double diag = __shfl(Lrow[j], (tid & 48) + j, 64);
+                const double xj = __shfl(y, (tid & 48) + j, 64) / diag;
+                if (r == j) y = xj;
+                else if (r > j) y -= Lrow[j] * xj;
             }
+            if (act) Y[(c0 + r) * 3 + c] = y;
         }
         __syncthreads();
-        for (int i = j0 + jb + tid; i < N; i += nthr) {
+        for (int i = c0 + jb + tid; i < N; i += nthr) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int q = 0; q < jb; ++q) {
-                const double l = A[(size_t)(j0 + q) * ld + i];
-                s0 += l * Y[(j0 + q) * 3 + 0];
-                s1 += l * Y[(j0 + q) * 3 + 1];
-                s2 += l * Y[(j0 + q) * 3 + 2];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q < jb) {
+                    const double l = A[(size_t)(c0 + q) * ld + i];
+                    s0 += l * Y[(c0 + q) * 3 + 0];
+                    s1 += l * Y[(c0 + q) * 3 + 1];
+                    s2 += l * Y[(c0 + q) * 3 + 2];
+                }
             }
             Y[i * 3 + 0] -= s0;
             Y[i * 3 + 1] -= s1;
@@ -179,26 +198,38 @@ __device__ void chol_solve3(const double* __restrict__ A, int N, int ld, double*
         __syncthreads();
     }
     // backward: L^T x = y
-    const int nblk = (N + NB - 1) / NB;
-    for (int b = nblk - 1; b >= 0; --b) {
-        const int j0 = b * NB;
-        const int jb = min(NB, N - j0);
-        if (tid < 3) {
-            const int c = tid;
-            for (int r = jb - 1; r >= 0; --r) {
-                double x = Y[(j0 + r) * 3 + c];
-                for (int q = r + 1; q < jb; ++q) x -= A[(size_t)(j0 + r) * ld + j0 + q] * Y[(j0 + q) * 3 + c];
-                Y[(j0 + r) * 3 + c] = x / A[(size_t)(j0 + r) * ld + j0 + r];
+    for (int p = nt - 1; p >= 0; --p) {
+        const int c0 = p * NB;
+        const int jb = min(NB, N - c0);
+        if (tid < 64) {
+            const int r = tid & 15, c = tid >> 4;
+            const bool act = (c < 3) && (r < jb);
+            double Lcol[NB];  // column r of the block: L[c0 + q][c0 + r]
+#pragma unroll
+            for (int q = 0; q < NB; ++q) Lcol[q] = (act && q >= r && q < jb) ? A[(size_t)(c0 + r) * ld + c0 + q] : 0.0;
+            double y = act ? Y[(c0 + r) * 3 + c] : 0.0;
+#pragma unroll
+            for (int j = NB - 1; j >= 0; --j) {
+                const double diag = __shfl(Lcol[j], (tid & 48) + j, 64);
+                const double xj = __shfl(y, (tid & 48) + j, 64) / diag;
+                if (j < jb) {
+                    if (r == j) y = xj;
+                    else if (r < j) y -= Lcol[j] * xj;
+                }
             }
+            if (act) Y[(c0 + r) * 3 + c] = y;
         }
         __syncthreads();
-        for (int i = tid; i < j0; i += nthr) {
+        for (int i = tid; i < c0; i += nthr) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int q = 0; q < jb; ++q) {
-                const double l = A[(size_t)i * ld + j0 + q];
-                s0 += l * Y[(j0 + q) * 3 + 0];
-                s1 += l * Y[(j0 + q) * 3 + 1];
-                s2 += l * Y[(j0 + q) * 3 + 2];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q < jb) {
+                    const double l = A[(size_t)i * ld + c0 + q];
+                    s0 += l * Y[(c0 + q) * 3 + 0];
+                    s1 += l * Y[(c0 + q) * 3 + 1];
+                    s2 += l * Y[(c0 + q) * 3 + 2];
+                }
             }
             Y[i * 3 + 0] -= s0;
             Y[i * 3 + 1] -= s1;
@@ -208,11 +239,18 @@ __device__ void chol_solve3(const double* __restrict__ A, int N, int ld, double*
     }
 }
 
-// LDS layout shared by the forward and adjoint kernels
+// LDS layout shared by the forward and adjoint kernels: K1 sites, shell (K2)
+// sites, right-hand sides / solutions, the 16x16 diagonal block and a reduction
+// scratch area.
 struct ScsLds {
-    double *px, *py, *pz, *ab, *sg, *R, *Y, *D, *P, *X;
+    double *px, *py, *pz, *ab, *sg, *R;        // K1 sites
+    double *qx, *qy, *qz, *qab, *qsg, *qR;     // shell sites
+    double *Y, *X, *D, *red;
 };
-__device__ inline ScsLds scs_lds(double* base, int n1max) {
+constexpr int kParts = 4;   // partner-range splits of the per-site pair loops (adjoint)
+constexpr int kPartsD = 2;  // partner-range splits of the right-hand-side assembly
+
+__device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     const int N = 3 * n1max;
     ScsLds L;
     L.px = base;
@@ -221,39 +259,66 @@ __device__ inline ScsLds scs_lds(double* base, int n1max) {
     L.ab = L.pz + n1max;
     L.sg = L.ab + n1max;
     L.R = L.sg + n1max;
-    L.Y = L.R + n1max;
-    L.D = L.Y + 3 * N;
-    L.P = L.D + NB * NB;
-    L.X = L.P + (size_t)N * NB;
+    L.qx = L.R + n1max;
+    L.qy = L.qx + n2max;
+    L.qz = L.qy + n2max;
+    L.qab = L.qz + n2max;
+    L.qsg = L.qab + n2max;
+    L.qR = L.qsg + n2max;
+    L.Y = L.qR + n2max;
+    L.X = L.Y + 3 * N;
+    L.D = L.X + 3 * N;
+    L.red = L.D + NB * NB;   // max(kParts * 3, kPartsD * 9) * n1max
     return L;
 }
 
-__device__ inline void load_k1(const ScsArgs& a, int k, int w, int n1, const ScsLds& L) {
+size_t scs_lds_bytes(int n1max, int n2max) {
+    const size_t N = 3 * (size_t)n1max;
+    const size_t red = (kParts * 3 > kPartsD * 9 ? kParts * 3 : kPartsD * 9) * (size_t)n1max;
+    return sizeof(double) * (6 * (size_t)n1max + 6 * (size_t)n2max + 6 * N + NB * NB + red);
+}
+
+__device__ inline void load_sites(const ScsArgs& a, int k, int w, int n1, int n12, const ScsLds& L) {
     const Site* S = a.sites + a.site_off[k];
-    for (int s = threadIdx.x; s < n1; s += blockDim.x) {
+    for (int s = threadIdx.x; s < n12; s += blockDim.x) {
         const Site st = S[s];
-        L.px[s] = st.x;
-        L.py[s] = st.y;
-        L.pz[s] = st.z;
-        L.ab[s] = a.abar[(size_t)st.base * a.nw + w];
-        L.sg[s] = a.sigma[(size_t)st.base * a.nw + w];
-        L.R[s] = a.Rv[st.base];
+        const double ab = a.abar[(size_t)st.base * a.nw + w];
+        const double sg = a.sigma[(size_t)st.base * a.nw + w];
+        const double R = a.Rv[st.base];
+        if (s < n1) {
+            L.px[s] = st.x; L.py[s] = st.y; L.pz[s] = st.z;
+            L.ab[s] = ab; L.sg[s] = sg; L.R[s] = R;
+        } else {
+            const int q = s - n1;
+            L.qx[q] = st.x; L.qy[q] = st.y; L.qz[q] = st.z;
+            L.qab[q] = ab; L.qsg[q] = sg; L.qR[q] = R;
+        }
     }
 }
 
-__global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max) {
+__device__ inline void inner_buffer(double r, double rin, double& fin, double& dfin) {
+    fin = 1.0;
+    dfin = 0.0;
+    if (r < rin) {
+        const double x = r / rin;
+        fin = 3.0 * x * x - 2.0 * x * x * x;
+        dfin = (6.0 * x - 6.0 * x * x) / rin;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
     const int w = blockIdx.y;
     const Counts cnt = a.counts[k];
-    const int n1 = cnt.n1, n12 = cnt.n12;
+    const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1;
     const int N = 3 * n1;
     const int ld = a.fac_ld[k];
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rc = SI.r_scs;
-    ScsLds L = scs_lds(lds, n1max);
+    ScsLds L = scs_lds(lds, n1max, n2max);
     double* A = a.fac + a.fac_off[k] + (size_t)w * ld * N;
-    load_k1(a, k, w, n1, L);
+    load_sites(a, k, w, n1, n12, L);
     __syncthreads();
 
     // B~ (lower triangle, block by block)
@@ -269,47 +334,49 @@ __global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max) {
         }
         const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
         const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+        const double ir = 1.0 / r;
+        const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
         const double s_ij = sqrt(L.sg[i] * L.sg[i] + L.sg[j] * L.sg[j]);
-        const SrPair t = sr_pair(r, s_ij, a.beta * (L.R[i] + L.R[j]), a.damp_d, rc, a.r_buf, 1.0, 0.0);
+        const SrPair t = sr_pair(r, ir, s_ij, a.beta * (L.R[i] + L.R[j]), a.damp_d, rc, a.r_buf, 1.0, 0.0);
         for (int q = 0; q < 3; ++q)
             for (int c = 0; c < 3; ++c)
                 A[(size_t)(3 * j + c) * ld + 3 * i + q] = t.A * rh[q] * rh[c] + (q == c ? t.B : 0.0);
     }
-    // d: identity minus the uncoupled shell K2 with TS polarisabilities and f_inner
-    const Site* S = a.sites + a.site_off[k];
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        double d[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
-        for (int jj = n1; jj < n12; ++jj) {
-            const Site sj = S[jj];
-            const double v[3] = {L.px[i] - sj.x, L.py[i] - sj.y, L.pz[i] - sj.z};
-            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-            if (!(r2 < rc * rc)) continue;
-            const double r = sqrt(r2);
-            const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
-            const double abj = a.abar[(size_t)sj.base * a.nw + w];
-            const double sgj = a.sigma[(size_t)sj.base * a.nw + w];
-            const double s_ij = sqrt(L.sg[i] * L.sg[i] + sgj * sgj);
-            double fin = 1.0, dfin = 0.0;
-            if (r < a.r_inner) {
-                const double x = r / a.r_inner;
-                fin = 3.0 * x * x - 2.0 * x * x * x;
-                dfin = (6.0 * x - 6.0 * x * x) / a.r_inner;
-            }
-            const SrPair t = sr_pair(r, s_ij, a.beta * (L.R[i] + a.Rv[sj.base]), a.damp_d, rc, a.r_buf,
-                                     fin, dfin);
-            for (int q = 0; q < 3; ++q)
-                for (int c = 0; c < 3; ++c)
-                    d[3 * q + c] -= abj * (t.A * rh[q] * rh[c] + (q == c ? t.B : 0.0));
+    // d: the shell K2 (TS polarisabilities, f_inner), over the compact list of
+    // coupled (K1 site, shell site) pairs; each site's segment is split over
+    // kPartsD threads and recombined in a fixed order.
+    const int32_t* seg_i = a.pl_seg + a.site_off[k] + 2 * (int64_t)k;
+    const int32_t* li = a.pl_i + a.pl_off[k];
+    for (int t = threadIdx.x; t < n1 * kPartsD; t += blockDim.x) {
+        const int i = t % n1, part = t / n1;
+        double d[9] = {};
+        for (int e = seg_i[i] + part; e < seg_i[i + 1]; e += kPartsD) {
+            const int q = li[e] & 0xFFFF;
+            const double v[3] = {L.px[i] - L.qx[q], L.py[i] - L.qy[q], L.pz[i] - L.qz[q]};
+            const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double ir = 1.0 / r;
+            const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
+            const double s_ij = sqrt(L.sg[i] * L.sg[i] + L.qsg[q] * L.qsg[q]);
+            double fin, dfin;
+            inner_buffer(r, a.r_inner, fin, dfin);
+            const SrPair tp = sr_pair(r, ir, s_ij, a.beta * (L.R[i] + L.qR[q]), a.damp_d, rc, a.r_buf, fin, dfin);
+            for (int e2 = 0; e2 < 3; ++e2)
+                for (int c = 0; c < 3; ++c) d[3 * e2 + c] -= L.qab[q] * (tp.A * rh[e2] * rh[c] + (e2 == c ? tp.B : 0.0));
         }
-        for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) L.Y[(3 * i + q) * 3 + c] = d[3 * q + c];
+        for (int e = 0; e < 9; ++e) L.red[(size_t)(part * n1 + i) * 9 + e] = d[e];
     }
-    __threadfence_block();
+    __syncthreads();
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        for (int e = 0; e < 9; ++e) {
+            double v = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
+            for (int part = 0; part < kPartsD; ++part) v += L.red[(size_t)(part * n1 + i) * 9 + e];
+            L.Y[(3 * i + e / 3) * 3 + e % 3] = v;
+        }
+    }
     __syncthreads();
 
     bool ok = true;
-    chol_factor(A, N, ld, L.P, L.D, ok);
+    chol_factor(A, N, ld, L.D, ok);
     if (!ok && threadIdx.x == 0) {
         atomicOr(a.err, 4);
         atomicMin(a.err_atom, k);
@@ -327,22 +394,23 @@ __global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max) {
 // Tr X_i / 3): lambda = B~^{-1} Xbar with Xbar_i = xbar_i I / 3, then
 //   dE = -<lambda X^T, dB~> + <lambda, dd>.
 // Per site, the gradient sums over its partners (each pair is evaluated from
-// both ends, so the order of summation is fixed).
+// both ends; partner ranges are split over kParts threads and recombined in a
+// fixed order), so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max) {
+__global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
     const int w = blockIdx.y;
     const Counts cnt = a.counts[k];
-    const int n1 = cnt.n1, n12 = cnt.n12, nall = cnt.n_all;
+    const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1, nall = cnt.n_all;
     const int N = 3 * n1;
     const int ld = a.fac_ld[k];
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rc = SI.r_scs;
-    ScsLds L = scs_lds(lds, n1max);
+    ScsLds L = scs_lds(lds, n1max, n2max);
     const double* A = a.fac + a.fac_off[k] + (size_t)w * ld * N;
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
-    load_k1(a, k, w, n1, L);
+    load_sites(a, k, w, n1, n12, L);
     const double* abl = a.abar_loc + a.aloc_off[k];
     for (int s = threadIdx.x; s < n1; s += blockDim.x) {
         double xb = abl[(size_t)s * a.nw + w];
@@ -354,105 +422,116 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max) {
     __syncthreads();
     chol_solve3(A, N, ld, L.Y);  // Y = lambda
 
-    const Site* S = a.sites + a.site_off[k];
     double* out = a.cf + (size_t)w * a.cf_slice + a.site_off[k] * 3;
     const double fconv = -1.0 / kBohr;  // force = -dE/dx, per Angstrom
     // K1 sites: couplings inside B~ and to the shell through d
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+    for (int t = threadIdx.x; t < n1 * kParts; t += blockDim.x) {
+        const int i = t % n1, part = t / n1;
         double g[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < n1; ++j) {
+        double Yi[9], Xi[9];
+        for (int e = 0; e < 9; ++e) {
+            Yi[e] = L.Y[(3 * i + e / 3) * 3 + e % 3];
+            Xi[e] = L.X[(3 * i + e / 3) * 3 + e % 3];
+        }
+        for (int j = part; j < n1; j += kParts) {
             if (j == i) continue;
             const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-            const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-            if (!(r < rc)) continue;
-            const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            if (!(r2 < rc * rc)) continue;
+            const double r = sqrt(r2);
+            const double ir = 1.0 / r;
+            const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
             const double s_ij = sqrt(L.sg[i] * L.sg[i] + L.sg[j] * L.sg[j]);
-            const SrPair t = sr_pair(r, s_ij, a.beta * (L.R[i] + L.R[j]), a.damp_d, rc, a.r_buf, 1.0, 0.0);
-            double C[9];
+            const SrPair tp = sr_pair(r, ir, s_ij, a.beta * (L.R[i] + L.R[j]), a.damp_d, rc, a.r_buf, 1.0, 0.0);
+            double Yj[9], Xj[9];
+            for (int e = 0; e < 9; ++e) {
+                Yj[e] = L.Y[(3 * j + e / 3) * 3 + e % 3];
+                Xj[e] = L.X[(3 * j + e / 3) * 3 + e % 3];
+            }
+            double Cs[9];
             for (int q = 0; q < 3; ++q)
                 for (int c = 0; c < 3; ++c) {
                     double s1 = 0.0, s2 = 0.0;
                     for (int m = 0; m < 3; ++m) {
-                        s1 += L.Y[(3 * i + q) * 3 + m] * L.X[(3 * j + c) * 3 + m];
-                        s2 += L.X[(3 * i + q) * 3 + m] * L.Y[(3 * j + c) * 3 + m];
+                        s1 += Yi[3 * q + m] * Xj[3 * c + m] + Yi[3 * c + m] * Xj[3 * q + m];
+                        s2 += Xi[3 * q + m] * Yj[3 * c + m] + Xi[3 * c + m] * Yj[3 * q + m];
                     }
-                    C[3 * q + c] = -(s1 + s2);
+                    Cs[3 * q + c] = -0.5 * (s1 + s2);
                 }
-            double Cs[9];
-            for (int q = 0; q < 3; ++q)
-                for (int c = 0; c < 3; ++c) Cs[3 * q + c] = 0.5 * (C[3 * q + c] + C[3 * c + q]);
             double gp[3];
-            radial_tensor_grad(rh, r, t.A, t.dA, t.dB, Cs, gp);
+            radial_tensor_grad(rh, r, tp.A, tp.dA, tp.dB, Cs, gp);
             g[0] += gp[0];
             g[1] += gp[1];
             g[2] += gp[2];
         }
         double lam[9];
         for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c)
-                lam[3 * q + c] = 0.5 * (L.Y[(3 * i + q) * 3 + c] + L.Y[(3 * i + c) * 3 + q]);
-        for (int jj = n1; jj < n12; ++jj) {
-            const Site sj = S[jj];
-            const double v[3] = {L.px[i] - sj.x, L.py[i] - sj.y, L.pz[i] - sj.z};
-            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-            if (!(r2 < rc * rc)) continue;
-            const double r = sqrt(r2);
-            const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
-            const double abj = a.abar[(size_t)sj.base * a.nw + w];
-            const double sgj = a.sigma[(size_t)sj.base * a.nw + w];
-            const double s_ij = sqrt(L.sg[i] * L.sg[i] + sgj * sgj);
-            double fin = 1.0, dfin = 0.0;
-            if (r < a.r_inner) {
-                const double x = r / a.r_inner;
-                fin = 3.0 * x * x - 2.0 * x * x * x;
-                dfin = (6.0 * x - 6.0 * x * x) / a.r_inner;
-            }
-            const SrPair t = sr_pair(r, s_ij, a.beta * (L.R[i] + a.Rv[sj.base]), a.damp_d, rc, a.r_buf,
-                                     fin, dfin);
+            for (int c = 0; c < 3; ++c) lam[3 * q + c] = 0.5 * (Yi[3 * q + c] + Yi[3 * c + q]);
+        const int32_t* seg_i = a.pl_seg + a.site_off[k] + 2 * (int64_t)k;
+        const int32_t* li = a.pl_i + a.pl_off[k];
+        for (int e = seg_i[i] + part; e < seg_i[i + 1]; e += kParts) {
+            const int q = li[e] & 0xFFFF;
+            const double v[3] = {L.px[i] - L.qx[q], L.py[i] - L.qy[q], L.pz[i] - L.qz[q]};
+            const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double ir = 1.0 / r;
+            const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
+            const double s_ij = sqrt(L.sg[i] * L.sg[i] + L.qsg[q] * L.qsg[q]);
+            double fin, dfin;
+            inner_buffer(r, a.r_inner, fin, dfin);
+            const SrPair tp = sr_pair(r, ir, s_ij, a.beta * (L.R[i] + L.qR[q]), a.damp_d, rc, a.r_buf, fin, dfin);
             double gp[3];
-            radial_tensor_grad(rh, r, t.A, t.dA, t.dB, lam, gp);
-            g[0] -= abj * gp[0];
-            g[1] -= abj * gp[1];
-            g[2] -= abj * gp[2];
+            radial_tensor_grad(rh, r, tp.A, tp.dA, tp.dB, lam, gp);
+            g[0] -= L.qab[q] * gp[0];
+            g[1] -= L.qab[q] * gp[1];
+            g[2] -= L.qab[q] * gp[2];
         }
-        out[3 * i + 0] = fconv * g[0];
-        out[3 * i + 1] = fconv * g[1];
-        out[3 * i + 2] = fconv * g[2];
+        L.red[(size_t)(part * n1 + i) * 3 + 0] = g[0];
+        L.red[(size_t)(part * n1 + i) * 3 + 1] = g[1];
+        L.red[(size_t)(part * n1 + i) * 3 + 2] = g[2];
     }
-    // shell sites K2: their coupling to K1 through d
-    for (int jj = n1 + threadIdx.x; jj < n12; jj += blockDim.x) {
-        const Site sj = S[jj];
-        const double abj = a.abar[(size_t)sj.base * a.nw + w];
-        const double sgj = a.sigma[(size_t)sj.base * a.nw + w];
-        const double Rj = a.Rv[sj.base];
-        double g[3] = {0.0, 0.0, 0.0};
-        for (int i = 0; i < n1; ++i) {
-            const double v[3] = {L.px[i] - sj.x, L.py[i] - sj.y, L.pz[i] - sj.z};
-            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-            if (!(r2 < rc * rc)) continue;
-            const double r = sqrt(r2);
-            const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
-            const double s_ij = sqrt(L.sg[i] * L.sg[i] + sgj * sgj);
-            double fin = 1.0, dfin = 0.0;
-            if (r < a.r_inner) {
-                const double x = r / a.r_inner;
-                fin = 3.0 * x * x - 2.0 * x * x * x;
-                dfin = (6.0 * x - 6.0 * x * x) / a.r_inner;
-            }
-            const SrPair t = sr_pair(r, s_ij, a.beta * (L.R[i] + Rj), a.damp_d, rc, a.r_buf, fin, dfin);
-            double lam[9];
-            for (int q = 0; q < 3; ++q)
-                for (int c = 0; c < 3; ++c)
-                    lam[3 * q + c] = 0.5 * (L.Y[(3 * i + q) * 3 + c] + L.Y[(3 * i + c) * 3 + q]);
-            double gp[3];
-            radial_tensor_grad(rh, r, t.A, t.dA, t.dB, lam, gp);
-            g[0] += abj * gp[0];
-            g[1] += abj * gp[1];
-            g[2] += abj * gp[2];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+        for (int part = 0; part < kParts; ++part) {
+            g0 += L.red[(size_t)(part * n1 + i) * 3 + 0];
+            g1 += L.red[(size_t)(part * n1 + i) * 3 + 1];
+            g2 += L.red[(size_t)(part * n1 + i) * 3 + 2];
         }
-        out[3 * jj + 0] = fconv * g[0];
-        out[3 * jj + 1] = fconv * g[1];
-        out[3 * jj + 2] = fconv * g[2];
+        out[3 * i + 0] = fconv * g0;
+        out[3 * i + 1] = fconv * g1;
+        out[3 * i + 2] = fconv * g2;
+    }
+    // shell sites K2: their coupling to K1 through d (one thread per shell site,
+    // over its segment of the shell-major list)
+    {
+        const int32_t* seg_q = a.pl_seg + a.site_off[k] + 2 * (int64_t)k + (n1 + 1);
+        const int32_t* lq = a.pl_q + a.pl_off[k];
+        for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+            double g[3] = {0.0, 0.0, 0.0};
+            for (int e = seg_q[q]; e < seg_q[q + 1]; ++e) {
+                const int i = lq[e] & 0xFFFF;
+                const double v[3] = {L.px[i] - L.qx[q], L.py[i] - L.qy[q], L.pz[i] - L.qz[q]};
+                const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                const double ir = 1.0 / r;
+                const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
+                const double s_ij = sqrt(L.sg[i] * L.sg[i] + L.qsg[q] * L.qsg[q]);
+                double fin, dfin;
+                inner_buffer(r, a.r_inner, fin, dfin);
+                const SrPair tp = sr_pair(r, ir, s_ij, a.beta * (L.R[i] + L.qR[q]), a.damp_d, rc, a.r_buf, fin, dfin);
+                double lam[9];
+                for (int e2 = 0; e2 < 3; ++e2)
+                    for (int c = 0; c < 3; ++c)
+                        lam[3 * e2 + c] = 0.5 * (L.Y[(3 * i + e2) * 3 + c] + L.Y[(3 * i + c) * 3 + e2]);
+                double gp[3];
+                radial_tensor_grad(rh, r, tp.A, tp.dA, tp.dB, lam, gp);
+                g[0] += L.qab[q] * gp[0];
+                g[1] += L.qab[q] * gp[1];
+                g[2] += L.qab[q] * gp[2];
+            }
+            out[3 * (n1 + q) + 0] = fconv * g[0];
+            out[3 * (n1 + q) + 1] = fconv * g[1];
+            out[3 * (n1 + q) + 2] = fconv * g[2];
+        }
     }
     for (int s = n12 + threadIdx.x; s < nall; s += blockDim.x) {
         out[3 * s + 0] = 0.0;
@@ -461,18 +540,94 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max) {
     }
 }
 
-size_t scs_lds_bytes(int n1max) {
-    const size_t N = 3 * (size_t)n1max;
-    return sizeof(double) * (6 * (size_t)n1max + 3 * N + NB * NB + N * NB + 3 * N);
+// ---------------------------------------------------------------------------
+// K1 x K2 coupling lists of one atom (frequency independent).  A shell site q
+// couples to a K1 site i when r_iq < r_scs (beyond, f_SR vanishes).  The lists
+// are written in i-major and shell-major order with CSR offsets; both orders
+// are deterministic (one thread per major index, minors in increasing order).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2max) {
+    extern __shared__ double lds[];
+    const int k = blockIdx.x;
+    const Counts cnt = a.counts[k];
+    const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1;
+    const StructInfo& SI = a.sinfo[a.atom_struct[k]];
+    const double rc2 = SI.r_scs * SI.r_scs;
+    double* px = lds;
+    double* py = px + n1max;
+    double* pz = py + n1max;
+    double* qx = pz + n1max;
+    double* qy = qx + n2max;
+    double* qz = qy + n2max;
+    int32_t* cnt_i = reinterpret_cast<int32_t*>(qz + n2max);   // n1max + 1
+    int32_t* cnt_q = cnt_i + (n1max + 1);                        // n2max + 1
+    const Site* S = a.sites + a.site_off[k];
+    for (int s = threadIdx.x; s < n12; s += blockDim.x) {
+        if (s < n1) { px[s] = S[s].x; py[s] = S[s].y; pz[s] = S[s].z; }
+        else { qx[s - n1] = S[s].x; qy[s - n1] = S[s].y; qz[s - n1] = S[s].z; }
+    }
+    __syncthreads();
+    auto coupled = [&](int i, int q) {
+        const double dx = px[i] - qx[q], dy = py[i] - qy[q], dz = pz[i] - qz[q];
+        return dx * dx + dy * dy + dz * dz < rc2;
+    };
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        int c = 0;
+        for (int q = 0; q < n2; ++q) c += coupled(i, q);
+        cnt_i[i] = c;
+    }
+    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+        int c = 0;
+        for (int i = 0; i < n1; ++i) c += coupled(i, q);
+        cnt_q[q] = c;
+    }
+    __syncthreads();
+    int32_t* seg = const_cast<int32_t*>(a.pl_seg) + a.site_off[k] + 2 * (int64_t)k;
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < n1; ++i) { const int c = cnt_i[i]; cnt_i[i] = acc; seg[i] = acc; acc += c; }
+        seg[n1] = acc;
+        cnt_i[n1] = acc;
+    }
+    if (threadIdx.x == 64) {
+        int acc = 0;
+        for (int q = 0; q < n2; ++q) { const int c = cnt_q[q]; cnt_q[q] = acc; seg[n1 + 1 + q] = acc; acc += c; }
+        seg[n1 + 1 + n2] = acc;
+        cnt_q[n2] = acc;
+    }
+    __syncthreads();
+    int32_t* li = const_cast<int32_t*>(a.pl_i) + a.pl_off[k];
+    int32_t* lq = const_cast<int32_t*>(a.pl_q) + a.pl_off[k];
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        int pos = cnt_i[i];
+        for (int q = 0; q < n2; ++q)
+            if (coupled(i, q)) li[pos++] = (i << 16) | q;
+    }
+    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+        int pos = cnt_q[q];
+        for (int i = 0; i < n1; ++i)
+            if (coupled(i, q)) lq[pos++] = (q << 16) | i;
+    }
 }
 
-hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max) {
-    hipLaunchKernelGGL(k_scs_forward, dim3(a.n, a.nw), dim3(256), scs_lds_bytes(n1max), st, a, n1max);
+size_t pairlist_lds_bytes(int n1max, int n2max) {
+    return sizeof(double) * 3 * ((size_t)n1max + n2max) + sizeof(int32_t) * ((size_t)n1max + n2max + 2);
+}
+
+hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max) {
+    hipLaunchKernelGGL(k_pairlist, dim3(a.n), dim3(256), pairlist_lds_bytes(n1max, n2max), st, a, n1max, n2max);
     return hipGetLastError();
 }
 
-hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max) {
-    hipLaunchKernelGGL(k_scs_adjoint, dim3(a.n, a.nw), dim3(256), scs_lds_bytes(n1max), st, a, n1max);
+hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n2max) {
+    hipLaunchKernelGGL(k_scs_forward, dim3(a.n, a.nw), dim3(256), scs_lds_bytes(n1max, n2max), st, a, n1max,
+                       n2max);
+    return hipGetLastError();
+}
+
+hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max) {
+    hipLaunchKernelGGL(k_scs_adjoint, dim3(a.n, a.nw), dim3(256), scs_lds_bytes(n1max, n2max), st, a, n1max,
+                       n2max);
     return hipGetLastError();
 }
 

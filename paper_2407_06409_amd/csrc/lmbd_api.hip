@@ -36,8 +36,9 @@ struct Plan {
     int64_t total_sites = 0;
     int64_t table_len = 0;
     int64_t fac_len = 0, x_len = 0, aloc_len = 0, work_len = 0;
-    int n1max = 0, nkmax = 0, nallmax = 0;
-    std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off;
+    int n1max = 0, nkmax = 0, nallmax = 0, n2max = 0;
+    std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off;
+    int64_t pl_len = 0;
     std::vector<int32_t> hash_cap, fac_ld;
     size_t bytes = 0;
 };
@@ -54,6 +55,7 @@ struct lmbd_context {
     DBuf site_off, sites, hash_off, hash_cap, table, rev;
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
+    DBuf pl_i, pl_q, pl_off, pl_seg;
     DBuf e_out, f_out, a_out;
     bool profiling = false;
     hipEvent_t ev[2 * LMBD_N_STAGES] = {};
@@ -225,11 +227,12 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.x_off.resize(n + 1);
     P.aloc_off.resize(n + 1);
     P.work_off.resize(n + 1);
+    P.pl_off.resize(n + 1);
     P.hash_cap.resize(n);
     P.fac_ld.resize(n);
     const int mmax = forces ? std::max(1, n_max - 1) : std::max(1, (n_max + 1) / 2);
-    int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0;
-    P.n1max = P.nkmax = P.nallmax = 0;
+    int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0, po = 0;
+    P.n1max = P.nkmax = P.nallmax = P.n2max = 0;
     for (int64_t k = 0; k < n; ++k) {
         const Counts& c = cnt[k];
         P.site_off[k] = so;
@@ -238,6 +241,8 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         P.x_off[k] = xo;
         P.aloc_off[k] = ao;
         P.work_off[k] = wo;
+        P.pl_off[k] = po;
+        po += (int64_t)c.n1 * (c.n12 - c.n1);
         const int64_t N1 = 3 * (int64_t)c.n1, N3 = 3 * (int64_t)c.nK;
         P.hash_cap[k] = (int32_t)next_pow2(2 * (int64_t)c.n_all);
         P.fac_ld[k] = (int32_t)N1;
@@ -250,6 +255,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         P.n1max = std::max(P.n1max, c.n1);
         P.nkmax = std::max(P.nkmax, c.nK);
         P.nallmax = std::max(P.nallmax, c.n_all);
+        P.n2max = std::max(P.n2max, c.n12 - c.n1);
     }
     P.site_off[n] = so;
     P.total_sites = so;
@@ -258,6 +264,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.x_len = xo;
     P.aloc_len = ao;
     P.work_len = wo;
+    P.pl_len = po;
     const size_t d = sizeof(double);
     size_t b = 0;
     b += (size_t)so * sizeof(Site) + (size_t)so * 4 /*rev*/ + (size_t)ho * 4 /*hash*/;
@@ -265,6 +272,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     b += (size_t)n * nw * d /*abar_cen*/;
     if (forces) b += (size_t)so * nw * d /*ca*/ + (size_t)(1 + nw) * so * 3 * d /*cf*/;
     b += (size_t)n * (8 * d + 64);  // per-atom tables and offsets
+    b += (size_t)po * 8 + (size_t)(so + 2 * n) * 4;  // coupling lists
     P.bytes = b;
 }
 
@@ -322,7 +330,8 @@ void lmbd_destroy(lmbd_context* ctx) {
                    &ctx->flags, &ctx->site_off, &ctx->sites, &ctx->hash_off, &ctx->hash_cap, &ctx->table,
                    &ctx->rev, &ctx->fac_off, &ctx->fac_ld, &ctx->x_off, &ctx->aloc_off, &ctx->work_off,
                    &ctx->fac, &ctx->xsol, &ctx->alpha_loc, &ctx->abar_loc, &ctx->abar_cen, &ctx->work,
-                   &ctx->ca, &ctx->cf, &ctx->e_out, &ctx->f_out, &ctx->a_out};
+                   &ctx->ca, &ctx->cf, &ctx->e_out, &ctx->f_out, &ctx->a_out, &ctx->pl_i, &ctx->pl_q,
+                   &ctx->pl_off, &ctx->pl_seg};
     for (DBuf* b : all) release(*b);
     (void)hipSetDevice(prev);
     delete ctx;
@@ -577,7 +586,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
                         ", sites " + std::to_string(P.nallmax) + ")");
     int lds_limit = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    if (scs_lds_bytes(P.n1max) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit)
+    if (scs_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit)
         return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood needs more LDS than the device offers (" +
                                                  std::to_string(lds_limit) + " bytes)");
     if (ctx->budget && P.bytes > ctx->budget)
@@ -588,6 +597,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     std::vector<int64_t> xo(P.x_off.begin(), P.x_off.end() - 1);
     std::vector<int64_t> ao(P.aloc_off.begin(), P.aloc_off.end() - 1);
     std::vector<int64_t> wo(P.work_off.begin(), P.work_off.end() - 1);
+    std::vector<int64_t> plo(P.pl_off.begin(), P.pl_off.end() - 1);
+    if ((st = upload(ctx, ctx->pl_off, plo, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->site_off, so, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->hash_off, ho, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->hash_cap, P.hash_cap, stream)) != LMBD_OK) return st;
@@ -613,6 +624,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         HIP_TRY(ensure(ctx->f_out, sizeof(double) * 3 * N));
     }
     HIP_TRY(ensure(ctx->a_out, sizeof(double) * N));
+    HIP_TRY(ensure(ctx->pl_i, sizeof(int32_t) * P.pl_len));
+    HIP_TRY(ensure(ctx->pl_q, sizeof(int32_t) * P.pl_len));
+    HIP_TRY(ensure(ctx->pl_seg, sizeof(int32_t) * (TS + 2 * (int64_t)N)));
 
     // --- neighbour lists and the reverse-slot map
     HIP_TRY(mark(1, 0));
@@ -620,7 +634,6 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_rev_map(stream, N, as<Counts>(ctx->counts), as<int64_t>(ctx->site_off), as<Site>(ctx->sites),
                            as<int64_t>(ctx->hash_off), as<int32_t>(ctx->hash_cap), as<int32_t>(ctx->table),
                            (size_t)P.table_len, as<int32_t>(ctx->rev), err));
-    HIP_TRY(mark(1, 1));
 
     // --- local SCS at omega = 0 and every node
     ScsArgs sa;
@@ -648,8 +661,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.aloc_off = as<int64_t>(ctx->aloc_off);
     sa.err = err;
     sa.err_atom = err_atom;
+    sa.pl_i = as<int32_t>(ctx->pl_i);
+    sa.pl_q = as<int32_t>(ctx->pl_q);
+    sa.pl_off = as<int64_t>(ctx->pl_off);
+    sa.pl_seg = as<int32_t>(ctx->pl_seg);
+    HIP_TRY(launch_pairlist(stream, sa, P.n1max, P.n2max));
+    HIP_TRY(mark(1, 1));
     HIP_TRY(mark(2, 0));
-    HIP_TRY(launch_scs_forward(stream, sa, P.n1max));
+    HIP_TRY(launch_scs_forward(stream, sa, P.n1max, P.n2max));
     HIP_TRY(mark(2, 1));
 
     // --- local MBD energy (+ adjoint)
@@ -697,7 +716,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         sa.cf_slice = TS * 3;
         sa.cf = as<double>(ctx->cf) + sa.cf_slice;  // slices 1..nw
         HIP_TRY(mark(5, 0));
-        HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max));
+        HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max, P.n2max));
         HIP_TRY(mark(5, 1));
         HIP_TRY(mark(6, 0));
         HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,

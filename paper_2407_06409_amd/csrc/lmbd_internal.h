@@ -68,10 +68,11 @@ struct Counts {
 // Fermi damping f(r, S) = 1 / (1 + exp(-d (r / S - 1))) and its partial
 // derivatives: df/dr = d f (1 - f) / S, df/dS = -d r f (1 - f) / S^2.
 __device__ inline double fermi(double r, double S, double d, double& dfdr, double& dfdS) {
-    const double f = 1.0 / (1.0 + exp(-d * (r / S - 1.0)));
-    const double g = d * f * (1.0 - f) / S;
+    const double iS = 1.0 / S;
+    const double f = 1.0 / (1.0 + exp(-d * (r * iS - 1.0)));
+    const double g = d * f * (1.0 - f) * iS;
     dfdr = g;
-    dfdS = -g * r / S;
+    dfdS = -g * r * iS;
     return f;
 }
 
@@ -80,8 +81,9 @@ __device__ inline double fermi(double r, double S, double d, double& dfdr, doubl
 __device__ inline double cutoff_poly(double r, double rc, double rb, double& dcdr) {
     if (r < rc - rb) { dcdr = 0.0; return 1.0; }
     if (r >= rc) { dcdr = 0.0; return 0.0; }
-    const double x = (r - rc + rb) / rb;
-    dcdr = (-6.0 * x + 6.0 * x * x) / rb;
+    const double irb = 1.0 / rb;
+    const double x = (r - rc + rb) * irb;
+    dcdr = (-6.0 * x + 6.0 * x * x) * irb;
     return 1.0 - 3.0 * x * x + 2.0 * x * x * x;
 }
 
@@ -107,19 +109,20 @@ __device__ inline void radial_tensor_grad(const double rh[3], double r, double A
 // written as A rhat rhat^T + B I:
 //   A = -(3 g - 2 c u^3 e) / r^3,  B = g / r^3,  c = 2/sqrt(pi), u = r/s, e = exp(-u^2)
 // with g = erf(u) - c u e (Sec. II.B, T_SR with the g and h functions).
-__device__ inline void sr_core(double r, double s, double& A, double& B, double& dA, double& dB) {
+__device__ inline void sr_core(double r, double ir, double s, double& A, double& B, double& dA, double& dB) {
     const double u = r / s;
     const double e = exp(-u * u);
     const double g = erf(u) - kTwoOverSqrtPi * u * e;
     const double u3e = u * u * u * e;
-    const double r3 = r * r * r;
+    const double ir3 = ir * ir * ir;
+    const double ir4 = ir3 * ir;
     const double P = 3.0 * g - 2.0 * kTwoOverSqrtPi * u3e;       // A = -P / r^3
-    // dP/dr = 2 c u^5 e / r * 2  (from g' = 2 c u^3 e / r and (u^3 e)' = (3 - 2u^2) u^3 e / r)
-    const double dP = 4.0 * kTwoOverSqrtPi * u3e * u * u / r;
-    A = -P / r3;
-    dA = -dP / r3 + 3.0 * P / (r3 * r);
-    B = g / r3;
-    dB = 2.0 * kTwoOverSqrtPi * u3e / r3 / r - 3.0 * g / (r3 * r);
+    // dP/dr = 4 c u^5 e / r  (from g' = 2 c u^3 e / r and (u^3 e)' = (3 - 2u^2) u^3 e / r)
+    const double dP = 4.0 * kTwoOverSqrtPi * u3e * u * u * ir;
+    A = -P * ir3;
+    dA = -dP * ir3 + 3.0 * P * ir4;
+    B = g * ir3;
+    dB = 2.0 * kTwoOverSqrtPi * u3e * ir4 - 3.0 * g * ir4;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,6 +158,12 @@ struct ScsArgs {
     const int64_t* x_off;
     double* alpha_loc;       // per atom n1 * nw
     const int64_t* aloc_off;
+    // K1 x K2 coupling lists (frequency independent): per atom, entries packed as
+    // (major << 16) | minor in i-major and shell-major order, CSR offsets of both
+    const int32_t* pl_i;
+    const int32_t* pl_q;
+    const int64_t* pl_off;   // per atom: first entry of both lists
+    const int32_t* pl_seg;   // per atom at site_off[k] + 2k: n1 + 1 i-offsets then n2 + 1 q-offsets
     int* err;
     int* err_atom;
     // adjoint only
@@ -202,9 +211,10 @@ hipError_t launch_nbr_fill(hipStream_t st, const NbrArgs& a, const Counts* count
 hipError_t launch_rev_map(hipStream_t st, int n, const Counts* counts, const int64_t* site_off,
                           const Site* sites, const int64_t* hash_off, const int32_t* hash_cap,
                           int32_t* table, size_t table_len, int32_t* rev, int* err);
-size_t scs_lds_bytes(int n1max);
-hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max);
-hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max);
+size_t scs_lds_bytes(int n1max, int n2max);
+hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
+hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
+hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
 size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max);
 hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
