@@ -1,0 +1,73 @@
+"""Write the stored oracle values used by the full-size GPU parity tests.
+
+Every number in the files written here comes from the CPU oracle (``oracle/``)
+on the seeded workloads of ``workloads/``; nothing is taken from the GPU path.
+
+    python tests/golden/make_golden.py            # all fixtures
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from workloads import SPECIES_TABLE, DEFAULT_PARAMS, frequency_grid  # noqa: E402
+from workloads import configs as C  # noqa: E402
+
+
+def params(cut):
+    g = frequency_grid(DEFAULT_PARAMS["n_freq"])
+    return oracle.make_params(cut, g[0], g[1], n_max=DEFAULT_PARAMS["n_max"], beta=DEFAULT_PARAMS["beta"],
+                              damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
+                              r_inner=DEFAULT_PARAMS["r_inner"])
+
+
+def sample(n, m, seed):
+    return sorted(int(x) for x in np.random.Generator(np.random.PCG64(seed)).choice(n, m, replace=False))
+
+
+def energies_fixture(name, st, cut, atoms):
+    t = time.time()
+    e = oracle.lmbd_energies(st, params(cut), SPECIES_TABLE, atoms=atoms)
+    print(f"{name}: energies of {len(atoms)} atoms in {time.time() - t:.1f} s", flush=True)
+    return {"atoms": atoms, "energies_eV": [float(e[a]) for a in atoms]}
+
+
+def forces_fixture(name, st, cut, atoms):
+    """Forces of the partial sum sum_{k in atoms} E_k (weights 1 on the sample, 0 elsewhere)."""
+    t = time.time()
+    w = np.zeros(st.n)
+    w[atoms] = 1.0
+    e, f = oracle.lmbd_energy_forces(st, params(cut), SPECIES_TABLE, weights=w, atoms=atoms)
+    nz = np.nonzero(np.any(f != 0.0, axis=1))[0]
+    print(f"{name}: forces of the {len(atoms)}-atom partial sum in {time.time() - t:.1f} s "
+          f"({len(nz)} atoms with nonzero force)", flush=True)
+    return {"weighted_atoms": atoms, "force_atoms": [int(a) for a in nz],
+            "forces_eV_per_A": [[float(x) for x in f[a]] for a in nz]}
+
+
+def main():
+    out = {"source": "CPU FP64 oracle (oracle/lmbd.py) on the seeded workloads; written by "
+                     "tests/golden/make_golden.py",
+           "params": DEFAULT_PARAMS}
+    st, cut = C.config_plain_pbc()
+    out["C1728_pbc"] = {"cutoffs": cut,
+                        "energies": energies_fixture("C1728", st, cut, sample(st.n, 12, 7)),
+                        "forces": forces_fixture("C1728", st, cut, sample(st.n, 3, 8))}
+    st, cut = C.config_diff_hcno()
+    out["HCNO4096_pbc"] = {"cutoffs": cut, "energies": energies_fixture("HCNO4096", st, cut, sample(st.n, 8, 9))}
+    st, cut = C.config_mixed_pbc()
+    out["C13824_pbc"] = {"cutoffs": cut, "energies": energies_fixture("C13824", st, cut, sample(st.n, 6, 10))}
+    with open(os.path.join(HERE, "oracle_fullsize.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", os.path.join(HERE, "oracle_fullsize.json"))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,113 @@
+"""Full-size workloads on the GPU against stored oracle values and finite differences.
+
+The stored values (tests/golden/oracle_fullsize.json) are written by
+tests/golden/make_golden.py, which calls only the CPU oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from tests.gpu_common import gpu_run
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_fullsize.json")
+
+
+def golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def test_c1728_energies_and_partial_forces_match_oracle():
+    g = golden()["C1728_pbc"]
+    st, cut = C.config_plain_pbc()
+    print(f"case C1728 n={st.n}", flush=True)
+    full = gpu_run(st, cut, forces=True)
+    atoms = g["energies"]["atoms"]
+    de = np.abs(full["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+    print(f"  max |dE| on {len(atoms)} sampled atoms: {de:.3e} eV", flush=True)
+    assert de < 1e-8
+    f = full["forces"]
+    assert np.abs(f.sum(0)).max() < 1e-10
+    w = np.zeros(st.n)
+    w[g["forces"]["weighted_atoms"]] = 1.0
+    part = gpu_run(st, cut, forces=True, weights=w)
+    ref = np.zeros((st.n, 3))
+    ref[g["forces"]["force_atoms"]] = np.array(g["forces"]["forces_eV_per_A"])
+    df = np.abs(part["forces"] - ref).max()
+    print(f"  max |dF| of the weighted partial sum over all atoms: {df:.3e} eV/A "
+          f"(max |F| {np.abs(ref).max():.3e})", flush=True)
+    assert df < 1e-8
+
+
+def test_hcno4096_energies_match_oracle():
+    g = golden()["HCNO4096_pbc"]
+    st, cut = C.config_diff_hcno()
+    print(f"case HCNO4096 n={st.n}", flush=True)
+    out = gpu_run(st, cut, forces=False)
+    atoms = g["energies"]["atoms"]
+    de = np.abs(out["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+    print(f"  max |dE| {de:.3e} eV", flush=True)
+    assert de < 1e-8
+
+
+def test_c13824_energies_match_oracle_fp64():
+    g = golden()["C13824_pbc"]
+    st, cut = C.config_mixed_pbc()
+    print(f"case C13824 n={st.n}", flush=True)
+    out = gpu_run(st, cut, forces=False)
+    atoms = g["energies"]["atoms"]
+    de = np.abs(out["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+    print(f"  max |dE| {de:.3e} eV", flush=True)
+    assert de < 1e-8
+
+
+def _crosses(st, a, g, h, radii):
+    """True if moving atom a by +-h along g changes any neighbour-set membership."""
+    L = st.cell[0, 0]
+    for sgn in (-1.0, 1.0):
+        p = st.pos[a].copy()
+        p[g] += sgn * h
+        d0 = st.pos - st.pos[a]
+        d0 -= L * np.round(d0 / L)
+        d1 = st.pos - p
+        d1 -= L * np.round(d1 / L)
+        r0 = np.linalg.norm(d0, axis=1)
+        r1 = np.linalg.norm(d1, axis=1)
+        for rc in radii:
+            if np.any((r0 < rc) != (r1 < rc)):
+                return True
+    return False
+
+
+def test_hcno4096_adjoint_forces_match_central_differences():
+    """F = -dE/dR of the GPU adjoint vs central differences of the GPU energy (h = 1e-4 A)
+    on 32 seeded (atom, component) draws; draws whose stencil changes a neighbour set
+    (the method's hard membership switches) are skipped and replaced."""
+    st, cut = C.config_diff_hcno()
+    print(f"case HCNO4096 FD n={st.n}", flush=True)
+    full = gpu_run(st, cut, forces=True)
+    rng = np.random.Generator(np.random.PCG64(4242))
+    radii = [cut["r_scs"], 2 * cut["r_scs"], cut["r_nbr"]]
+    h = 1e-4
+    checked, worst = 0, 0.0
+    while checked < 32:
+        a = int(rng.integers(st.n))
+        g = int(rng.integers(3))
+        if _crosses(st, a, g, h, radii):
+            continue
+        sp, sm = st.copy(), st.copy()
+        sp.pos[a, g] += h
+        sm.pos[a, g] -= h
+        ep = gpu_run(sp, cut, forces=False)["energies"].sum()
+        em = gpu_run(sm, cut, forces=False)["energies"].sum()
+        fd = -(ep - em) / (2 * h)
+        err = abs(fd - full["forces"][a, g])
+        worst = max(worst, err)
+        assert err < 1e-7 + 1e-6 * abs(fd), (a, g, fd, full["forces"][a, g])
+        checked += 1
+    print(f"  32 FD components, max |F_adj - F_fd| = {worst:.3e} eV/A", flush=True)
