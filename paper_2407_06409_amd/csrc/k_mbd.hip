@@ -25,7 +25,7 @@ namespace lmbd {
 
 // LDS layout
 struct MbdLds {
-    double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu, *tA, *tB;
+    double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu;
 };
 __device__ inline MbdLds mbd_lds(double* b, int nk, int nw, int nq, int n_max) {
     MbdLds L;
@@ -42,81 +42,112 @@ __device__ inline MbdLds mbd_lds(double* b, int nk, int nw, int nq, int n_max) {
     L.rb = L.g + 12 * (size_t)nk;     // [4 parts][nk]
     L.fg = L.rb + 4 * (size_t)nk;     // [nk][3]
     L.mu = L.fg + 3 * (size_t)nk;
-    L.tA = L.mu + (size_t)(n_max + 1) * nq;
-    L.tB = L.tA + 16 * 65;
     return L;
 }
 
 size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max) {
     const size_t nk = nkmax;
     return sizeof(double) * (3 * nk + nk * nw + nk * nq + 3 * nk + nk * nw + 12 * nk + 4 * nk +
-                             3 * nk + (size_t)(n_max + 1) * nq + 2 * 16 * 65);
+                             3 * nk + (size_t)(n_max + 1) * nq);
 }
 
-// Workgroup GEMM: out(m, n) = sum_k A(m, k) B(k, n), 64x64 tiles, 4x4 per thread,
-// k staged through LDS in chunks of 16.  Loaders return 0 outside the range.
-template <typename LA, typename LB, typename ST>
-__device__ void wg_gemm(int M, int N, int K, LA la, LB lb, ST st, double* tA, double* tB) {
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    for (int m0 = 0; m0 < M; m0 += 64)
-        for (int n0 = 0; n0 < N; n0 += 64) {
-            double acc[4][4] = {};
-            for (int k0 = 0; k0 < K; k0 += 16) {
-                for (int e = tid; e < 16 * 64; e += 256) {
-                    const int kk = e >> 6, mm = e & 63;
-                    tA[kk * 65 + mm] = (m0 + mm < M && k0 + kk < K) ? la(m0 + mm, k0 + kk) : 0.0;
-                    tB[kk * 65 + mm] = (n0 + mm < N && k0 + kk < K) ? lb(k0 + kk, n0 + mm) : 0.0;
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// MFMA 16x16x4 in the workspace type (lane layouts as measured on gfx950: A[i][k]
+// <- lane i + 16k, B[k][j] <- lane j + 16k; D[i][j] in lane j + 16 (i % 4), register
+// i / 4 for f64 and lane j + 16 (i / 4), register i % 4 for f32).
+template <typename W> struct MfmaW;
+template <> struct MfmaW<double> {
+    typedef d4_t acc;
+    static __device__ inline acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int acc_row(int g, int q) { return g + 4 * q; }
+};
+template <> struct MfmaW<float> {
+    typedef f4_t acc;
+    static __device__ inline acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int acc_row(int g, int q) { return 4 * g + q; }
+};
+
+// Workgroup GEMM on the matrix cores: out(m, n) = sum_k A(m, k) B(k, n).  Each
+// wavefront takes a 16-row strip times up to four 16-column tiles (sharing the A
+// operand) and runs the k loop in steps of 4 with one MFMA per column tile.
+// Loaders are called only inside the bounds; padding is zero.
+template <typename W, typename LA, typename LB, typename ST>
+__device__ void mfma_gemm(int M, int N, int K, LA la, LB lb, ST st) {
+    typedef MfmaW<W> Mf;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int mt = (M + 15) / 16;
+    const int nt = (N + 15) / 16;
+    const int ng = (nt + 3) / 4;
+    for (int t = wave; t < mt * ng; t += nwave) {
+        const int m0 = (t / ng) * 16;
+        const int tc0 = (t % ng) * 4;
+        const int ntc = min(4, nt - tc0);
+        typename Mf::acc acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[c][q] = W(0);
+        const int am = m0 + li;
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int kk = k0 + lk;
+            const W a = (am < M && kk < K) ? la(am, kk) : W(0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c < ntc) {
+                    const int bn = (tc0 + c) * 16 + li;
+                    const W b = (bn < N && kk < K) ? lb(kk, bn) : W(0);
+                    acc[c] = Mf::mma(a, b, acc[c]);
                 }
-                __syncthreads();
-#pragma unroll 4
-                for (int kk = 0; kk < 16; ++kk) {
-                    double a[4], b[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        a[i] = tA[kk * 65 + ty + 16 * i];
-                        b[i] = tB[kk * 65 + tx + 16 * i];
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-                }
-                __syncthreads();
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int m = m0 + ty + 16 * i, nn = n0 + tx + 16 * j;
-                    if (m < M && nn < N) st(m, nn, acc[i][j]);
-                }
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c < ntc) {
+                const int n = (tc0 + c) * 16 + li;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m0 + Mf::acc_row(lk, q);
+                    if (m < M && n < N) st(m, n, acc[c][q]);
+                }
+            }
+        }
+    }
     __syncthreads();
 }
 
 // T_LR pair coefficients: T_LR = A rhat rhat^T + B I with radial derivatives,
 // and dT_LR/dS~ = fLR (df/dS~) T.
+template <typename P>
 struct LrPair {
-    double A, B, dA, dB, dfS, fLR;
+    P A, B, dA, dB, dfS, fLR;
 };
-__device__ inline LrPair lr_pair(double r, double S, double damp_d, double rcut, double rb) {
-    double dfdr, dfdS, dcut;
-    const double f = fermi(r, S, damp_d, dfdr, dfdS);
-    const double fc = cutoff_poly(r, rcut, rb, dcut);
-    const double w = fc * f;
-    const double dw = dcut * f + fc * dfdr;
-    const double r3 = r * r * r;
-    LrPair p;
-    p.A = 3.0 * w / r3;
-    p.B = -w / r3;
-    p.dA = 3.0 * dw / r3 - 9.0 * w / (r3 * r);
-    p.dB = -dw / r3 + 3.0 * w / (r3 * r);
+template <typename P>
+__device__ inline LrPair<P> lr_pair(P r, P S, P damp_d, P rcut, P rb) {
+    P dfdr, dfdS, dcut;
+    const P f = fermi<P>(r, S, damp_d, dfdr, dfdS);
+    const P fc = cutoff_poly<P>(r, rcut, rb, dcut);
+    const P w = fc * f;
+    const P dw = dcut * f + fc * dfdr;
+    const P ir = P(1) / r;
+    const P ir3 = ir * ir * ir;
+    LrPair<P> p;
+    p.A = P(3) * w * ir3;
+    p.B = -w * ir3;
+    p.dA = P(3) * dw * ir3 - P(9) * w * ir3 * ir;
+    p.dB = -dw * ir3 + P(3) * w * ir3 * ir;
     p.dfS = dfdS;
     p.fLR = fc;
     return p;
 }
 
+template <typename W>
 __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
@@ -130,9 +161,9 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     MbdLds L = mbd_lds(lds, nkmax, nw, nq, n_max);
     const Site* S = a.sites + a.site_off[k];
     const double* aloc = a.alpha_loc + a.aloc_off[k];
-    double* T = a.work + a.work_off[k];
-    double* U = T + (size_t)N3 * N3;                         // u_1 .. u_mmax
-    double* Z = U + (size_t)a.mmax * N3 * ncol;              // Z_0 .. Z_{n_max-1}
+    W* T = static_cast<W*>(a.work) + a.work_off[k];
+    W* U = T + (size_t)N3 * N3;                              // u_1 .. u_mmax
+    W* Z = U + (size_t)a.mmax * N3 * ncol;                   // Z_0 .. Z_{n_max-1}
     auto Uat = [&](int m) { return U + (size_t)(m - 1) * N3 * ncol; };
 
     // --- blend (Sec. III.B, central/local combination) and SCS radii
@@ -172,34 +203,35 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
             const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
             const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
             if (r < rcut) {
-                const LrPair t = lr_pair(r, a.beta * (L.Rt[i] + L.Rt[j]), a.damp_d, rcut, a.r_buf);
+                const LrPair<W> t = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
+                                               W(a.r_buf));
                 const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
                 for (int q = 0; q < 3; ++q)
-                    for (int c = 0; c < 3; ++c) blk[3 * q + c] = t.A * rh[q] * rh[c] + (q == c ? t.B : 0.0);
+                    for (int c = 0; c < 3; ++c)
+                        blk[3 * q + c] = double(t.A) * rh[q] * rh[c] + (q == c ? double(t.B) : 0.0);
             }
         }
         for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) T[(size_t)(3 * i + q) * N3 + 3 * j + c] = blk[3 * q + c];
+            for (int c = 0; c < 3; ++c) T[(size_t)(3 * i + q) * N3 + 3 * j + c] = W(blk[3 * q + c]);
     }
     __syncthreads();
 
     // --- u_1 = D T D e_k
-    double* U1 = Uat(1);
+    W* U1 = Uat(1);
     for (int e = tid; e < N3 * ncol; e += blockDim.x) {
         const int row = e / ncol, col = e % ncol;
         const int q = col / 3, c = col % 3;
-        U1[e] = L.sqa[(size_t)(row / 3) * nq + q] * T[(size_t)row * N3 + c] * L.sqa[q];
+        U1[e] = W(L.sqa[(size_t)(row / 3) * nq + q] * double(T[(size_t)row * N3 + c]) * L.sqa[q]);
     }
     __syncthreads();
-    // --- u_{m+1} = D T (D u_m)
+    // --- u_{m+1} = D T (D u_m)  (T symmetric: its column k is read as row k, coalesced)
     for (int m = 1; m < a.mmax; ++m) {
-        const double* Um = Uat(m);
-        double* Un = Uat(m + 1);
-        wg_gemm(
-            N3, ncol, N3, [&](int r, int l) { return T[(size_t)r * N3 + l]; },
-            [&](int l, int col) { return L.sqa[(size_t)(l / 3) * nq + col / 3] * Um[(size_t)l * ncol + col]; },
-            [&](int r, int col, double v) { Un[(size_t)r * ncol + col] = L.sqa[(size_t)(r / 3) * nq + col / 3] * v; },
-            L.tA, L.tB);
+        const W* Um = Uat(m);
+        W* Un = Uat(m + 1);
+        mfma_gemm<W>(
+            N3, ncol, N3, [&](int r, int l) { return T[(size_t)l * N3 + r]; },
+            [&](int l, int col) { return W(L.sqa[(size_t)(l / 3) * nq + col / 3]) * Um[(size_t)l * ncol + col]; },
+            [&](int r, int col, W v) { Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v; });
     }
 
     // --- moments mu_n(q) = <u_a, u_b>, a + b = n
@@ -207,11 +239,12 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     for (int t = tid; t < nmom; t += blockDim.x) {
         const int n = 2 + t / nq, q = t % nq;
         const int ia = n / 2, ib = n - ia;
-        const double* ua = Uat(ia);
-        const double* ub = Uat(ib);
+        const W* ua = Uat(ia);
+        const W* ub = Uat(ib);
         double s = 0.0;
         for (int row = 0; row < N3; ++row)
-            for (int c = 0; c < 3; ++c) s += ua[(size_t)row * ncol + 3 * q + c] * ub[(size_t)row * ncol + 3 * q + c];
+            for (int c = 0; c < 3; ++c)
+                s += double(ua[(size_t)row * ncol + 3 * q + c]) * double(ub[(size_t)row * ncol + 3 * q + c]);
         L.mu[n * nq + q] = s;
     }
     __syncthreads();
@@ -237,11 +270,11 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
             for (int n = 2; n <= n_max; ++n) {
                 double sn = (i == 0) ? L.mu[n * nq + q] : 0.0;
                 for (int aa = 1; aa < n; ++aa) {
-                    const double* ua = Uat(aa);
-                    const double* ub = Uat(n - aa);
+                    const W* ua = Uat(aa);
+                    const W* ub = Uat(n - aa);
                     for (int r = 3 * i; r < 3 * i + 3; ++r)
                         for (int c = 0; c < 3; ++c)
-                            sn += ua[(size_t)r * ncol + 3 * q + c] * ub[(size_t)r * ncol + 3 * q + c];
+                            sn += double(ua[(size_t)r * ncol + 3 * q + c]) * double(ub[(size_t)r * ncol + 3 * q + c]);
                 }
                 s += a.coef[n] * sn;
             }
@@ -254,28 +287,28 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
         const int aa = e / (N3 * ncol);
         const int rem = e % (N3 * ncol);
         const int row = rem / ncol, col = rem % ncol;
-        double s = (row == col % 3) ? a.coef[aa + 1] : 0.0;   // b = 0 term, c_1 = 0 anyway
-        if (aa + 1 < 2) s = 0.0;
-        for (int b = 1; b <= n_max - 1 - aa; ++b) s += a.coef[aa + b + 1] * Uat(b)[(size_t)row * ncol + col];
-        Z[e] = s;
+        double s = (aa >= 1 && row == col % 3) ? a.coef[aa + 1] : 0.0;   // b = 0 term (u_0 = e_k)
+        for (int b = 1; b <= n_max - 1 - aa; ++b) s += a.coef[aa + b + 1] * double(Uat(b)[(size_t)row * ncol + col]);
+        Z[e] = W(s);
     }
     __syncthreads();
     // --- Tbar = sum_a (D u_a)(W D Z_a)^T  (overwrites T)
     const int KK = n_max * ncol;
-    wg_gemm(
+    mfma_gemm<W>(
         N3, N3, KK,
         [&](int r, int kk) {
             const int aa = kk / ncol, col = kk % ncol;
-            double u;
-            if (aa == 0) u = (r == col % 3) ? 1.0 : 0.0;
+            W u;
+            if (aa == 0) u = (r == col % 3) ? W(1) : W(0);
             else u = Uat(aa)[(size_t)r * ncol + col];
-            return L.sqa[(size_t)(r / 3) * nq + col / 3] * u;
+            return W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * u;
         },
         [&](int kk, int s) {
             const int aa = kk / ncol, col = kk % ncol;
-            return wk * a.wq[col / 3] * L.sqa[(size_t)(s / 3) * nq + col / 3] * Z[(size_t)aa * N3 * ncol + (size_t)s * ncol + col];
+            return W(wk * a.wq[col / 3] * L.sqa[(size_t)(s / 3) * nq + col / 3]) *
+                   Z[(size_t)aa * N3 * ncol + (size_t)s * ncol + col];
         },
-        [&](int r, int s, double v) { T[(size_t)r * N3 + s] = v; }, L.tA, L.tB);
+        [&](int r, int s, W v) { T[(size_t)r * N3 + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
@@ -290,13 +323,15 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
             const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
             if (!(r < rcut)) continue;
             const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
-            const LrPair lp = lr_pair(r, a.beta * (L.Rt[i] + L.Rt[j]), a.damp_d, rcut, a.r_buf);
+            const LrPair<W> lp = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
+                                            W(a.r_buf));
             double C[9];
             for (int q = 0; q < 3; ++q)
                 for (int c = 0; c < 3; ++c)
-                    C[3 * q + c] = T[(size_t)(3 * i + q) * N3 + 3 * j + c] + T[(size_t)(3 * i + c) * N3 + 3 * j + q];
+                    C[3 * q + c] = double(T[(size_t)(3 * i + q) * N3 + 3 * j + c]) +
+                                   double(T[(size_t)(3 * i + c) * N3 + 3 * j + q]);
             double gp[3];
-            radial_tensor_grad(rh, r, lp.A, lp.dA, lp.dB, C, gp);
+            radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
             g[0] += gp[0];
             g[1] += gp[1];
             g[2] += gp[2];
@@ -305,7 +340,7 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
             for (int q = 0; q < 3; ++q)
                 for (int c = 0; c < 3; ++c) rCr += rh[q] * C[3 * q + c] * rh[c];
             const double ct = (3.0 * rCr - (C[0] + C[4] + C[8])) / (r * r * r);
-            Rb += a.beta * lp.fLR * lp.dfS * ct;
+            Rb += a.beta * double(lp.fLR) * double(lp.dfS) * ct;
         }
         L.g[(size_t)(part * nK + i) * 3 + 0] = g[0];
         L.g[(size_t)(part * nK + i) * 3 + 1] = g[1];
@@ -384,9 +419,12 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     for (int e = tid; e < (nall - nK) * nw; e += blockDim.x) cap[(size_t)nK * nw + e] = 0.0;
 }
 
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax) {
-    hipLaunchKernelGGL(k_mbd, dim3(a.n), dim3(256), mbd_lds_bytes(nkmax, a.nw, a.nq, a.n_max), st, a,
-                       nkmax);
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed) {
+    const size_t lds = mbd_lds_bytes(nkmax, a.nw, a.nq, a.n_max);
+    if (mixed)
+        hipLaunchKernelGGL(k_mbd<float>, dim3(a.n), dim3(256), lds, st, a, nkmax);
+    else
+        hipLaunchKernelGGL(k_mbd<double>, dim3(a.n), dim3(256), lds, st, a, nkmax);
     return hipGetLastError();
 }
 

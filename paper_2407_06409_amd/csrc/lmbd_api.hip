@@ -218,7 +218,7 @@ int64_t next_pow2(int64_t x) {
     return p;
 }
 
-void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, Plan& P) {
+void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, bool mixed, Plan& P) {
     const int64_t n = (int64_t)cnt.size();
     P.n_atoms = n;
     P.site_off.resize(n + 1);
@@ -268,7 +268,8 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     const size_t d = sizeof(double);
     size_t b = 0;
     b += (size_t)so * sizeof(Site) + (size_t)so * 4 /*rev*/ + (size_t)ho * 4 /*hash*/;
-    b += (size_t)(fo + xo + 2 * ao + wo) * d;
+    const size_t wsz = mixed ? sizeof(float) : sizeof(double);
+    b += (size_t)(fo + wo) * wsz + (size_t)(xo + 2 * ao) * d;
     b += (size_t)n * nw * d /*abar_cen*/;
     if (forces) b += (size_t)so * nw * d /*ca*/ + (size_t)(1 + nw) * so * 3 * d /*cf*/;
     b += (size_t)n * (8 * d + 64);  // per-atom tables and offsets
@@ -416,7 +417,8 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
         forces = forces || structs[s].forces != nullptr;
     }
     Plan P;
-    build_plan(cnt, params->n_freq + 1, 3 * params->n_freq, params->n_max, forces, P);
+    build_plan(cnt, params->n_freq + 1, 3 * params->n_freq, params->n_max, forces,
+               params->precision == LMBD_MIXED, P);
     *bytes = P.bytes;
     return LMBD_OK;
 }
@@ -428,7 +430,6 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ctx->err.clear();
     lmbd_status st = check_params(ctx, params);
     if (st != LMBD_OK) return st;
-    if (params->precision != LMBD_FP64) return fail(ctx, LMBD_E_UNSUPPORTED, "mixed precision not built");
     if (!species_table || n_species < 1) return fail(ctx, LMBD_E_INVALID_ARG, "empty species table");
     for (int i = 0; i < n_species; ++i)
         if (!finite_pos(species_table[i].alpha0) || !finite_pos(species_table[i].c6) ||
@@ -447,6 +448,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if (N64 > INT32_MAX / 8) return fail(ctx, LMBD_E_UNSUPPORTED, "too many atoms in one call");
     const int N = (int)N64;
     const int nq = params->n_freq, nw = nq + 1, ncol = 3 * nq, n_max = params->n_max;
+    const bool mixed = params->precision == LMBD_MIXED;
+    const size_t wsz = mixed ? sizeof(float) : sizeof(double);  // matrix and workspace element size
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     for (int i = 0; i < LMBD_N_STAGES; ++i) {
@@ -579,14 +582,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
 
     // --- memory plan
     Plan P;
-    build_plan(cnt, nw, ncol, n_max, forces, P);
+    build_plan(cnt, nw, ncol, n_max, forces, mixed, P);
     if (P.n1max > kMaxN1 || P.nkmax > kMaxNK || P.nallmax > kMaxSites)
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
                         ", sites " + std::to_string(P.nallmax) + ")");
     int lds_limit = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    if (scs_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit)
+    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit)
         return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood needs more LDS than the device offers (" +
                                                  std::to_string(lds_limit) + " bytes)");
     if (ctx->budget && P.bytes > ctx->budget)
@@ -611,12 +614,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(ensure(ctx->sites, sizeof(Site) * TS));
     HIP_TRY(ensure(ctx->table, sizeof(int32_t) * P.table_len));
     HIP_TRY(ensure(ctx->rev, sizeof(int32_t) * TS));
-    HIP_TRY(ensure(ctx->fac, sizeof(double) * P.fac_len));
+    HIP_TRY(ensure(ctx->fac, wsz * P.fac_len));
     HIP_TRY(ensure(ctx->xsol, sizeof(double) * P.x_len));
     HIP_TRY(ensure(ctx->alpha_loc, sizeof(double) * P.aloc_len));
     HIP_TRY(ensure(ctx->abar_loc, sizeof(double) * P.aloc_len));
     HIP_TRY(ensure(ctx->abar_cen, sizeof(double) * (size_t)N * nw));
-    HIP_TRY(ensure(ctx->work, sizeof(double) * P.work_len));
+    HIP_TRY(ensure(ctx->work, wsz * P.work_len));
     HIP_TRY(ensure(ctx->e_out, sizeof(double) * N));
     if (forces) {
         HIP_TRY(ensure(ctx->ca, sizeof(double) * TS * nw));
@@ -652,7 +655,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.damp_d = params->damp_d;
     sa.r_buf = params->r_buf / kBohr;
     sa.r_inner = params->r_inner / kBohr;
-    sa.fac = as<double>(ctx->fac);
+    sa.fac = ctx->fac.p;
+    sa.n_refine = 2;
     sa.fac_off = as<int64_t>(ctx->fac_off);
     sa.fac_ld = as<int32_t>(ctx->fac_ld);
     sa.xsol = as<double>(ctx->xsol);
@@ -668,7 +672,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_pairlist(stream, sa, P.n1max, P.n2max));
     HIP_TRY(mark(1, 1));
     HIP_TRY(mark(2, 0));
-    HIP_TRY(launch_scs_forward(stream, sa, P.n1max, P.n2max));
+    HIP_TRY(launch_scs_forward(stream, sa, P.n1max, P.n2max, mixed));
     HIP_TRY(mark(2, 1));
 
     // --- local MBD energy (+ adjoint)
@@ -696,14 +700,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     for (int q = 0; q < nq; ++q) ma.wq[q] = params->weight[q] * kHartree / (2.0 * kPi);
     ma.e_weight = as<double>(ctx->in_w);
     ma.e_atom = as<double>(ctx->e_out);
-    ma.work = as<double>(ctx->work);
+    ma.work = ctx->work.p;
     ma.work_off = as<int64_t>(ctx->work_off);
     ma.forces = forces ? 1 : 0;
     ma.abar_loc = as<double>(ctx->abar_loc);
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
     HIP_TRY(mark(3, 0));
-    HIP_TRY(launch_mbd(stream, ma, P.nkmax));
+    HIP_TRY(launch_mbd(stream, ma, P.nkmax, mixed));
     HIP_TRY(mark(3, 1));
 
     if (forces) {
@@ -716,7 +720,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         sa.cf_slice = TS * 3;
         sa.cf = as<double>(ctx->cf) + sa.cf_slice;  // slices 1..nw
         HIP_TRY(mark(5, 0));
-        HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max, P.n2max));
+        HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max, P.n2max, mixed));
         HIP_TRY(mark(5, 1));
         HIP_TRY(mark(6, 0));
         HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,

@@ -62,15 +62,23 @@ struct Counts {
 };
 
 // ---------------------------------------------------------------------------
-// Pair functions (device).  r in bohr.
+// Pair functions (device), templated on the arithmetic type P (double, or float
+// for the mixed-precision path).  r in bohr.
 // ---------------------------------------------------------------------------
+__device__ inline double m_exp(double x) { return exp(x); }
+__device__ inline float m_exp(float x) { return expf(x); }
+__device__ inline double m_erf(double x) { return erf(x); }
+__device__ inline float m_erf(float x) { return erff(x); }
+__device__ inline double m_sqrt(double x) { return sqrt(x); }
+__device__ inline float m_sqrt(float x) { return sqrtf(x); }
 
 // Fermi damping f(r, S) = 1 / (1 + exp(-d (r / S - 1))) and its partial
 // derivatives: df/dr = d f (1 - f) / S, df/dS = -d r f (1 - f) / S^2.
-__device__ inline double fermi(double r, double S, double d, double& dfdr, double& dfdS) {
-    const double iS = 1.0 / S;
-    const double f = 1.0 / (1.0 + exp(-d * (r * iS - 1.0)));
-    const double g = d * f * (1.0 - f) * iS;
+template <typename P>
+__device__ inline P fermi(P r, P S, P d, P& dfdr, P& dfdS) {
+    const P iS = P(1) / S;
+    const P f = P(1) / (P(1) + m_exp(-d * (r * iS - P(1))));
+    const P g = d * f * (P(1) - f) * iS;
     dfdr = g;
     dfdS = -g * r * iS;
     return f;
@@ -78,13 +86,14 @@ __device__ inline double fermi(double r, double S, double d, double& dfdr, doubl
 
 // Smooth cutoff: 1 below rc - rb, 1 - 3x^2 + 2x^3 with x = (r - rc + rb)/rb in
 // the buffer, 0 from rc on; returns value and d/dr.
-__device__ inline double cutoff_poly(double r, double rc, double rb, double& dcdr) {
-    if (r < rc - rb) { dcdr = 0.0; return 1.0; }
-    if (r >= rc) { dcdr = 0.0; return 0.0; }
-    const double irb = 1.0 / rb;
-    const double x = (r - rc + rb) * irb;
-    dcdr = (-6.0 * x + 6.0 * x * x) * irb;
-    return 1.0 - 3.0 * x * x + 2.0 * x * x * x;
+template <typename P>
+__device__ inline P cutoff_poly(P r, P rc, P rb, P& dcdr) {
+    if (r < rc - rb) { dcdr = P(0); return P(1); }
+    if (r >= rc) { dcdr = P(0); return P(0); }
+    const P irb = P(1) / rb;
+    const P x = (r - rc + rb) * irb;
+    dcdr = (P(-6) * x + P(6) * x * x) * irb;
+    return P(1) - P(3) * x * x + P(2) * x * x * x;
 }
 
 // Radial decomposition of a symmetric pair tensor M(r_vec) = A(r) rhat rhat^T + B(r) I.
@@ -109,20 +118,22 @@ __device__ inline void radial_tensor_grad(const double rh[3], double r, double A
 // written as A rhat rhat^T + B I:
 //   A = -(3 g - 2 c u^3 e) / r^3,  B = g / r^3,  c = 2/sqrt(pi), u = r/s, e = exp(-u^2)
 // with g = erf(u) - c u e (Sec. II.B, T_SR with the g and h functions).
-__device__ inline void sr_core(double r, double ir, double s, double& A, double& B, double& dA, double& dB) {
-    const double u = r / s;
-    const double e = exp(-u * u);
-    const double g = erf(u) - kTwoOverSqrtPi * u * e;
-    const double u3e = u * u * u * e;
-    const double ir3 = ir * ir * ir;
-    const double ir4 = ir3 * ir;
-    const double P = 3.0 * g - 2.0 * kTwoOverSqrtPi * u3e;       // A = -P / r^3
-    // dP/dr = 4 c u^5 e / r  (from g' = 2 c u^3 e / r and (u^3 e)' = (3 - 2u^2) u^3 e / r)
-    const double dP = 4.0 * kTwoOverSqrtPi * u3e * u * u * ir;
-    A = -P * ir3;
-    dA = -dP * ir3 + 3.0 * P * ir4;
+template <typename P>
+__device__ inline void sr_core(P r, P ir, P s, P& A, P& B, P& dA, P& dB) {
+    const P c = P(kTwoOverSqrtPi);
+    const P u = r / s;
+    const P e = m_exp(-u * u);
+    const P g = m_erf(u) - c * u * e;
+    const P u3e = u * u * u * e;
+    const P ir3 = ir * ir * ir;
+    const P ir4 = ir3 * ir;
+    const P Pc = P(3) * g - P(2) * c * u3e;       // A = -Pc / r^3
+    // dPc/dr = 4 c u^5 e / r  (from g' = 2 c u^3 e / r and (u^3 e)' = (3 - 2u^2) u^3 e / r)
+    const P dP = P(4) * c * u3e * u * u * ir;
+    A = -Pc * ir3;
+    dA = -dP * ir3 + P(3) * Pc * ir4;
     B = g * ir3;
-    dB = 2.0 * kTwoOverSqrtPi * u3e * ir4 - 3.0 * g * ir4;
+    dB = P(2) * c * u3e * ir4 - P(3) * g * ir4;
 }
 
 // ---------------------------------------------------------------------------
@@ -142,6 +153,7 @@ struct NbrArgs {
 
 struct ScsArgs {
     int n, nw;
+    int n_refine;            // refinement steps of the FP32 solve (mixed precision)
     const Counts* counts;
     const int64_t* site_off;
     const Site* sites;
@@ -151,7 +163,7 @@ struct ScsArgs {
     const int32_t* atom_struct;
     const StructInfo* sinfo;
     double beta, damp_d, r_buf, r_inner;   // bohr
-    double* fac;             // factor slots: per atom nw * ld * N, column-major lower
+    void* fac;               // factor slots (double or float): per atom nw * ld * N, column-major lower
     const int64_t* fac_off;
     const int32_t* fac_ld;
     double* xsol;            // per atom nw * N * 3 (row-major)
@@ -189,7 +201,7 @@ struct MbdArgs {
     double wq[kMaxFreq];       // quadrature weight * Hartree / (2 pi): eV per unit integrand
     const double* e_weight;    // [n] or null
     double* e_atom;            // [n]
-    double* work;              // per atom T (N3^2), U (mmax N3 ncol), Z (n_max N3 ncol)
+    void* work;                // per atom T (N3^2), U (mmax N3 ncol), Z (n_max N3 ncol): double or float
     const int64_t* work_off;
     int forces;
     double* abar_loc;          // per atom n1 * nw (aloc_off)
@@ -211,12 +223,12 @@ hipError_t launch_nbr_fill(hipStream_t st, const NbrArgs& a, const Counts* count
 hipError_t launch_rev_map(hipStream_t st, int n, const Counts* counts, const int64_t* site_off,
                           const Site* sites, const int64_t* hash_off, const int32_t* hash_cap,
                           int32_t* table, size_t table_len, int32_t* rev, int* err);
-size_t scs_lds_bytes(int n1max, int n2max);
-hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
+size_t scs_lds_bytes(int n1max, int n2max, bool mixed);
+hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
-hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
+hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
 size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max);
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax);
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,
                                  const double* ca, double* abar_cen);
