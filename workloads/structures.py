@@ -4,6 +4,7 @@ Positions are drawn uniformly and a candidate is rejected when it lies closer
 than ``dmin`` to an accepted atom (minimum image for periodic boxes).  All
 generators take a numpy ``Generator`` so that every workload is reproducible.
 """
+import math
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -39,66 +40,55 @@ def number_density(g_cm3: float, fractions: dict) -> float:
     return g_cm3 / (mean_mass * AMU_G) * 1e-24
 
 
-class _Grid:
-    """Bucket grid used only to speed up the RSA overlap test."""
-
-    def __init__(self, lo, hi, cell_size, periodic):
-        self.lo = np.asarray(lo, dtype=np.float64)
-        self.span = np.asarray(hi, dtype=np.float64) - self.lo
-        self.nc = np.maximum(1, np.floor(self.span / cell_size).astype(int))
-        self.h = self.span / self.nc
-        self.periodic = periodic
-        self.buckets = {}
-
-    def key(self, p):
-        c = np.floor((p - self.lo) / self.h).astype(int)
-        if self.periodic:
-            c %= self.nc
-        else:
-            c = np.clip(c, 0, self.nc - 1)
-        return tuple(c)
-
-    def near(self, p):
-        c = np.array(self.key(p))
-        out = []
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    q = c + (dx, dy, dz)
-                    if self.periodic:
-                        q %= self.nc
-                    elif np.any(q < 0) or np.any(q >= self.nc):
-                        continue
-                    out.extend(self.buckets.get(tuple(q), ()))
-        return out
-
-    def add(self, idx, p):
-        self.buckets.setdefault(self.key(p), []).append(idx)
-
-
 def _rsa(n, sampler, dmin, lo, hi, periodic, rng, max_tries=200000):
-    box = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
-    grid = _Grid(lo, hi, dmin, periodic)
-    pos = np.empty((n, 3), dtype=np.float64)
-    count = 0
-    tries = 0
+    """Accept candidates from ``sampler`` that keep ``dmin`` to every accepted atom.
+
+    The overlap test looks only at the 27 buckets (edge >= dmin) around the
+    candidate; it is plain Python on floats, which is much faster than numpy on
+    three-element arrays and takes the same decisions.
+    """
+    lo = [float(x) for x in lo]
+    box = [float(hi[d]) - lo[d] for d in range(3)]
+    nc = [max(1, int(math.floor(box[d] / dmin))) for d in range(3)]
+    h = [box[d] / nc[d] for d in range(3)]
+    offsets = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    buckets = {}
+    acc = []
     d2min = dmin * dmin
-    while count < n:
+    tries = 0
+    while len(acc) < n:
         tries += 1
         if tries > max_tries + 50 * n:
             raise RuntimeError("RSA failed to place all atoms; density too high for dmin")
-        p = sampler(rng)
-        cand = grid.near(p)
-        if cand:
-            d = pos[cand] - p
+        p = sampler(rng).tolist()
+        key = []
+        for d in range(3):
+            c = math.floor((p[d] - lo[d]) / h[d])
+            key.append(c % nc[d] if periodic else min(max(c, 0), nc[d] - 1))
+        clash = False
+        for off in offsets:
+            q = [key[0] + off[0], key[1] + off[1], key[2] + off[2]]
             if periodic:
-                d -= box * np.round(d / box)
-            if np.min(np.einsum("ij,ij->i", d, d)) < d2min:
+                q = (q[0] % nc[0], q[1] % nc[1], q[2] % nc[2])
+            elif min(q) < 0 or q[0] >= nc[0] or q[1] >= nc[1] or q[2] >= nc[2]:
                 continue
-        pos[count] = p
-        grid.add(count, p)
-        count += 1
-    return pos
+            for j in buckets.get(tuple(q), ()):
+                x = acc[j]
+                dx, dy, dz = x[0] - p[0], x[1] - p[1], x[2] - p[2]
+                if periodic:
+                    dx -= box[0] * round(dx / box[0])
+                    dy -= box[1] * round(dy / box[1])
+                    dz -= box[2] * round(dz / box[2])
+                if dx * dx + dy * dy + dz * dz < d2min:
+                    clash = True
+                    break
+            if clash:
+                break
+        if clash:
+            continue
+        buckets.setdefault(tuple(key), []).append(len(acc))
+        acc.append(p)
+    return np.array(acc, dtype=np.float64).reshape(n, 3)
 
 
 def rsa_box(n, length, dmin, rng):
