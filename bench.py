@@ -1,13 +1,17 @@
 """Throughput of the lMBD hot path (energy + exact forces) on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
-                    [--workload plain|mixed] [--no-cpu-baseline]
+                    [--workload plain|mixed] [--no-cpu-baseline] [--no-serve] [--serve-sweep]
 
 A step is one complete evaluation (neighbour lists, local SCS at every
 frequency, local MBD energies, all adjoints, forces) of the whole workload,
 with inputs resident in device memory.  The default workload is 1,728 C atoms
 in a periodic box at 2.0 g/cm^3 with a 6 A cutoff, 12 quadrature nodes and
-n_max = 6, in FP64.  Prints one JSON line.
+n_max = 6, in FP64; the same workload is also timed in mixed precision.  The
+serving section replays 256 H/C/N/O requests (50-5,000 atoms) arriving as a
+Poisson stream through the continuous-batching server in mixed precision,
+and through a one-request-at-a-time FP64 server, and reports atoms/s with
+p50/p99 latency.  Prints one JSON line.
 """
 import argparse
 import json
@@ -88,6 +92,91 @@ def cpu_baseline(st, cut, grid):
             "wall_s": wall}
 
 
+def _replay(srv, reqs, arrivals):
+    """Submit each request at its arrival time (s from now); latency runs from the
+    arrival to the outputs being written on the host."""
+    first_batch = srv.stats()["batches"]
+    t0 = time.perf_counter()
+    tickets, intake = [], []
+    for r, ta in zip(reqs, arrivals):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ts = time.perf_counter()
+        tickets.append(srv.submit(r))
+        intake.append(time.perf_counter() - ts)   # host-side footprint analysis before queueing
+    infos = [srv.wait(t) for t in tickets]
+    bad = [i["detail"] for i in infos if i["status"] != "LMBD_OK"]
+    if bad:
+        raise RuntimeError(f"served requests failed: {bad[:3]}")
+    lat = np.array([i["t_end"] - i["t_submit"] + d for i, d in zip(infos, intake)])
+    t_first = min(i["t_submit"] - d for i, d in zip(infos, intake))
+    span = max(i["t_end"] for i in infos) - t_first
+    atoms = sum(len(r["pos"]) for r in reqs)
+    stats = srv.stats()
+    for t in tickets:
+        srv.release(t)
+    return {"atoms_per_s": atoms / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "span_s": span,
+            "batches": int(stats["batches"] - first_batch),
+            "mean_requests_per_batch": float(np.mean([i["batch_requests"] for i in infos])),
+            "max_concurrent_batches": int(stats["max_concurrent"]), "pool_peak_GB": stats["pool_peak"] / 1e9}
+
+
+def serve_bench(sweep=False):
+    """Serving workload: mixed-precision continuous batching vs one-at-a-time FP64."""
+    import paper_2407_06409_amd as P
+    from workloads import SPECIES_TABLE, DEFAULT_PARAMS, frequency_grid
+    from workloads import configs as C
+    grid = frequency_grid(DEFAULT_PARAMS["n_freq"])
+    items = C.serving_requests()
+    reqs = [dict(pos=it["structure"].pos, species=it["structure"].species, v_ratio=it["structure"].nu,
+                 cell=it["structure"].cell, pbc=tuple(int(x) for x in it["structure"].pbc), cutoffs=it["cutoffs"])
+            for it in items]
+    unit_gaps = np.array([it["arrival"] for it in items])
+    mean_atoms = float(np.mean([len(r["pos"]) for r in reqs]))
+
+    def mp(precision):
+        return P.MethodParams(omega=grid[0], weight=grid[1], beta=DEFAULT_PARAMS["beta"],
+                              damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
+                              r_inner=DEFAULT_PARAMS["r_inner"], n_max=DEFAULT_PARAMS["n_max"], precision=precision)
+
+    served_cfg = dict(n_slots=SERVE_SLOTS, memory_budget=SERVE_POOL, max_batch_atoms=SERVE_BATCH_ATOMS)
+    with P.Server(mp("mixed"), SPECIES_TABLE, **served_cfg) as srv:
+        t = srv.submit(reqs[0])  # first-use costs (code objects, pool pages) outside the timed runs
+        srv.wait(t)
+        srv.release(t)
+        cap = _replay(srv, reqs, np.zeros(len(reqs)))
+        rate = 0.8 * cap["atoms_per_s"] / mean_atoms
+        served = _replay(srv, reqs, unit_gaps / rate)
+        sweep_out = {}
+        if sweep:
+            for m in (0.5, 1.0, 1.2):
+                sweep_out[str(m)] = _replay(srv, reqs, unit_gaps / (m / 0.8 * rate))
+    with P.Server(mp("fp64"), SPECIES_TABLE, n_slots=1, max_batch_requests=1, memory_budget=SERVE_POOL) as srv:
+        t = srv.submit(reqs[0])
+        srv.wait(t)
+        srv.release(t)
+        single_cap = _replay(srv, reqs, np.zeros(len(reqs)))
+        single = _replay(srv, reqs, unit_gaps / rate)
+    out = {"workload": f"{len(reqs)} H/C/N/O requests, 50-5,000 atoms log-uniform (mean {mean_atoms:.0f}), half open "
+                       "spheres and half periodic cubes at 1.0 g/cm3, cutoff U[5,6] A, energy+forces, Poisson "
+                       "arrivals at 0.8 x the measured mixed capacity",
+           "rate_req_per_s": rate, "capacity_mixed_served_atoms_per_s": cap["atoms_per_s"],
+           "capacity_fp64_one_at_a_time_atoms_per_s": single_cap["atoms_per_s"],
+           "server": {"n_slots": SERVE_SLOTS, "pool_GB": SERVE_POOL / 1e9, "max_batch_atoms": SERVE_BATCH_ATOMS},
+           "mixed_served": served, "fp64_one_at_a_time": single,
+           "capacity_ratio": cap["atoms_per_s"] / single_cap["atoms_per_s"]}
+    if sweep:
+        out["rate_sweep_mixed_served"] = sweep_out
+    return out
+
+
+SERVE_SLOTS = 3
+SERVE_POOL = 96 << 30
+SERVE_BATCH_ATOMS = 8192
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +185,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--workload", default="plain", choices=["plain", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
+    ap.add_argument("--serve-sweep", action="store_true", help="also replay at 0.5/1.0/1.2 x the rate")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing of the workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -178,6 +270,29 @@ def main():
         "stages_ms": stage_ms, "roofline": roofline,
         "mean_n1": float(n1.mean()), "energy_eV": float(out["energies"].sum().item()),
     }
+    if not args.no_mixed and args.precision == "fp64":
+        mp_mixed = P.MethodParams(omega=grid[0], weight=grid[1], beta=DEFAULT_PARAMS["beta"],
+                                  damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
+                                  r_inner=DEFAULT_PARAMS["r_inner"], n_max=DEFAULT_PARAMS["n_max"], precision="mixed")
+
+        def step_mixed():
+            return P.compute(pos, sp, nu, cutoffs=cut, params=mp_mixed, species_table=SPECIES_TABLE,
+                             cell=st.cell, forces=True, ctx=ctx, stream=stream)
+
+        for _ in range(args.warmup):
+            om = step_mixed()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            om = step_mixed()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        line["mixed"] = {"value": st.n * args.steps / el, "unit": "atoms/s", "ms_per_step": el / args.steps * 1e3,
+                         "dtype": "f32 matrices/GEMMs on MFMA, f64 refinement and accumulation",
+                         "max_abs_dE_vs_fp64_eV_per_atom": float((om["energies"] - out["energies"]).abs().max()),
+                         "max_abs_dF_vs_fp64_eV_per_A": float((om["forces"] - out["forces"]).abs().max())}
+    if not args.no_serve:
+        line["served"] = serve_bench(args.serve_sweep)
     if not args.no_cpu_baseline and args.workload == "plain":
         line["cpu_baseline"] = cpu_baseline(st, cut, grid)
     print(json.dumps(line), flush=True)

@@ -43,7 +43,8 @@ typedef enum lmbd_status {
     LMBD_E_OOM_ADMISSION = 3,  /* request larger than the memory budget of the context */
     LMBD_E_DEVICE = 4,         /* a HIP runtime call failed; see lmbd_last_error */
     LMBD_E_SCS_BREAKDOWN = 5,  /* a local SCS matrix B~_K is not positive definite */
-    LMBD_E_UNSUPPORTED = 6     /* a size limit of the kernels is exceeded */
+    LMBD_E_UNSUPPORTED = 6,    /* a size limit of the kernels is exceeded */
+    LMBD_E_CANCELLED = 7       /* a queued request was dropped when its server was destroyed */
 } lmbd_status;
 
 /* precision of the hot path */
@@ -131,8 +132,8 @@ lmbd_status lmbd_create(int32_t device, lmbd_context** out);
 void lmbd_destroy(lmbd_context* ctx);
 
 /* Cap the device memory (bytes) that one call may use; 0 = no cap.  A call whose
- * footprint exceeds the cap fails with LMBD_E_OOM_ADMISSION before touching the
- * device. */
+ * footprint exceeds the cap fails with LMBD_E_OOM_ADMISSION after the neighbour
+ * counts and before any workspace that depends on them is allocated. */
 lmbd_status lmbd_set_memory_budget(lmbd_context* ctx, size_t bytes);
 
 /* Energies (and forces) of a batch of structures in one set of kernel launches.
@@ -157,8 +158,11 @@ lmbd_status lmbd_compute(lmbd_context* ctx, const lmbd_params* params,
                          int32_t n_species, const lmbd_species* species_table,
                          const lmbd_structure* structure, int32_t mem, void* hip_stream);
 
-/* Device bytes a call on these structures would need (host-side neighbour
- * counting; positions are HOST arrays here whatever `mem` a later call uses). */
+/* Device bytes a call on these structures would need: the exact size of the
+ * workspace lmbd_compute_batch lays out, from host-side neighbour counts that
+ * equal the device's (every array of the descriptors is a HOST array here,
+ * whatever `mem` a later call uses).  Exact for species tables of up to 64
+ * entries.  Needs the HIP runtime, not a launch. */
 lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs,
                                     const lmbd_structure* structs, size_t* bytes);
 
@@ -180,6 +184,74 @@ const char* lmbd_status_string(lmbd_status status);
 
 /* Detail of the last error of a context (empty string if none). */
 const char* lmbd_last_error(const lmbd_context* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent structures on one device.
+ *
+ * A server owns one device memory pool of `memory_budget` bytes and `n_slots`
+ * slots; each slot is a host thread with its own lmbd context and HIP stream.
+ * Submitted structures wait in a FIFO queue.  A free slot takes the longest
+ * prefix of the queue whose exact device footprint (lmbd_estimate_footprint of
+ * the batch) fits in one free block of the pool and in the batch caps, carves
+ * its whole workspace from that block, and evaluates the prefix as one batch.
+ * Requests that arrive while others run are admitted as soon as a slot and
+ * pool memory are free, so batches of different slots overlap on the device.
+ * Every result is bitwise the one the structure gets when evaluated alone.
+ * --------------------------------------------------------------------------- */
+typedef struct lmbd_server lmbd_server;
+
+typedef struct lmbd_server_config {
+    int32_t device;              /* HIP device index */
+    int32_t n_slots;             /* batches in flight at once (1..16) */
+    size_t memory_budget;        /* bytes of the device pool; 0 = 80 % of the free device memory */
+    int64_t max_batch_atoms;     /* atoms per batch (0 = no cap); a larger request runs alone */
+    int32_t max_batch_requests;  /* requests per batch (0 = no cap) */
+} lmbd_server_config;
+
+typedef struct lmbd_request_info {
+    int32_t done;                /* 1 once the outputs are written (or the request failed) */
+    lmbd_status status;          /* result of the request, valid when done */
+    double t_submit;             /* seconds since server creation: submission, */
+    double t_start;              /*   start of the batch that ran it, */
+    double t_end;                /*   outputs written */
+    size_t footprint;            /* exact device bytes of the request evaluated alone */
+    uint64_t batch;              /* serial number of that batch (from 1) */
+    int32_t batch_requests;      /* requests in that batch */
+    int32_t slot;                /* slot that ran it */
+    char detail[160];            /* error detail when status != LMBD_OK */
+} lmbd_request_info;
+
+typedef struct lmbd_server_stats {
+    uint64_t submitted, completed, batches;
+    int32_t max_concurrent;      /* most batches ever in flight together */
+    size_t pool_bytes, pool_peak;
+} lmbd_server_stats;
+
+/* Create a server.  params (with its arrays) and the species table are copied;
+ * every request of the server uses them.  The pool is allocated here. */
+lmbd_status lmbd_server_create(const lmbd_server_config* config, const lmbd_params* params, int32_t n_species,
+                               const lmbd_species* species_table, lmbd_server** out);
+
+/* Drop queued requests (status LMBD_E_CANCELLED), wait for running batches,
+ * release the pool, the slots and every request record.  NULL is ignored. */
+void lmbd_server_destroy(lmbd_server* server);
+
+/* Queue one structure.  Its arrays are HOST arrays owned by the caller, who
+ * keeps them alive and leaves them untouched until the request is done.
+ * Returns LMBD_E_OOM_ADMISSION (the structure alone needs more than the pool)
+ * or LMBD_E_INVALID_ARG without issuing a ticket. */
+lmbd_status lmbd_submit(lmbd_server* server, const lmbd_structure* request, uint64_t* ticket);
+
+/* State of a request without blocking (info->done tells whether it finished). */
+lmbd_status lmbd_poll(lmbd_server* server, uint64_t ticket, lmbd_request_info* info);
+
+/* Block until the request is done; then as lmbd_poll. */
+lmbd_status lmbd_wait(lmbd_server* server, uint64_t ticket, lmbd_request_info* info);
+
+/* Forget a finished request (LMBD_E_INVALID_ARG while it is queued or running). */
+lmbd_status lmbd_release(lmbd_server* server, uint64_t ticket);
+
+lmbd_status lmbd_server_get_stats(lmbd_server* server, lmbd_server_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ LMBD_HOST, LMBD_DEVICE = 0, 1
 
 STATUS = {
     0: "LMBD_OK", 1: "LMBD_E_INVALID_ARG", 2: "LMBD_E_OOM", 3: "LMBD_E_OOM_ADMISSION",
-    4: "LMBD_E_DEVICE", 5: "LMBD_E_SCS_BREAKDOWN", 6: "LMBD_E_UNSUPPORTED",
+    4: "LMBD_E_DEVICE", 5: "LMBD_E_SCS_BREAKDOWN", 6: "LMBD_E_UNSUPPORTED", 7: "LMBD_E_CANCELLED",
 }
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -37,6 +37,24 @@ class StructureDesc(ctypes.Structure):
         ("r_mbd2", ctypes.c_double), ("e_weight", ctypes.c_void_p), ("e_atom", ctypes.c_void_p),
         ("forces", ctypes.c_void_p), ("alpha_scs0", ctypes.c_void_p),
     ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("memory_budget", ctypes.c_size_t),
+                ("max_batch_atoms", ctypes.c_int64), ("max_batch_requests", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("footprint", ctypes.c_size_t),
+                ("batch", ctypes.c_uint64), ("batch_requests", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("detail", ctypes.c_char * 160)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("max_concurrent", ctypes.c_int32), ("pool_bytes", ctypes.c_size_t),
+                ("pool_peak", ctypes.c_size_t)]
 
 
 class LmbdError(RuntimeError):
@@ -85,11 +103,28 @@ def lib():
     L.lmbd_stage_times.argtypes = [ctypes.c_void_p, _dp]
     L.lmbd_stage_name.restype = ctypes.c_char_p
     L.lmbd_stage_name.argtypes = [ctypes.c_int32]
+    L.lmbd_server_create.restype = ctypes.c_int
+    L.lmbd_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(Params), ctypes.c_int32,
+                                     ctypes.POINTER(Species), ctypes.POINTER(ctypes.c_void_p)]
+    L.lmbd_server_destroy.restype = None
+    L.lmbd_server_destroy.argtypes = [ctypes.c_void_p]
+    L.lmbd_submit.restype = ctypes.c_int
+    L.lmbd_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(StructureDesc), ctypes.POINTER(ctypes.c_uint64)]
+    for name in ("lmbd_poll", "lmbd_wait"):
+        fn = getattr(L, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(RequestInfo)]
+    L.lmbd_release.restype = ctypes.c_int
+    L.lmbd_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    L.lmbd_server_get_stats.restype = ctypes.c_int
+    L.lmbd_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServerStats)]
     _lib = L
     return L
 
 
 EXPORTED = ["lmbd_abi_version", "lmbd_create", "lmbd_destroy", "lmbd_set_memory_budget",
             "lmbd_compute_batch", "lmbd_compute", "lmbd_estimate_footprint", "lmbd_status_string",
-            "lmbd_last_error", "lmbd_set_profiling", "lmbd_stage_times", "lmbd_stage_name"]
+            "lmbd_last_error", "lmbd_set_profiling", "lmbd_stage_times", "lmbd_stage_name",
+            "lmbd_server_create", "lmbd_server_destroy", "lmbd_submit", "lmbd_poll", "lmbd_wait",
+            "lmbd_release", "lmbd_server_get_stats"]
 N_STAGES = 7

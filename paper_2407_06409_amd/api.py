@@ -189,28 +189,136 @@ def compute(pos, species, v_ratio, *, cutoffs, params: MethodParams, species_tab
                          want_alpha=want_alpha)[0]
 
 
+def _host_desc(s, forces, keep):
+    """StructureDesc of a structure dict with host (numpy) arrays; outputs allocated here."""
+    pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
+    spc = np.ascontiguousarray(s["species"], dtype=np.int32)
+    nu = np.ascontiguousarray(s["v_ratio"], dtype=np.float64)
+    w = s.get("e_weight")
+    w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    cell = s.get("cell")
+    cell_np = None if cell is None else np.ascontiguousarray(cell, dtype=np.float64)
+    pbc = s.get("pbc")
+    if pbc is None:
+        pbc = (1, 1, 1) if cell is not None else (0, 0, 0)
+    pbc = [int(bool(x)) for x in (pbc.tolist() if hasattr(pbc, "tolist") else pbc)]
+    e = np.empty(pos.shape[0])
+    f = np.empty_like(pos) if forces else None
+    a = np.empty(pos.shape[0])
+    keep.extend([pos, spc, nu, w, cell_np, e, f, a])
+    cut = s["cutoffs"]
+    d = C.StructureDesc(
+        int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
+        cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
+        (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
+        float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a))
+    return d, {"energies": e, "forces": f, "alpha_scs0": a}
+
+
 def estimate_footprint(structures, params: MethodParams, forces=True) -> int:
-    """Device bytes that one call on these (host-array) structures would use."""
+    """Exact device bytes of one call on these (host-array) structures."""
     p, keep = params.to_c()
     descs = (C.StructureDesc * len(structures))()
     for i, s in enumerate(structures):
-        pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
-        cell = s.get("cell")
-        cell_np = None if cell is None else np.ascontiguousarray(cell, dtype=np.float64)
-        keep.extend([pos, cell_np])
-        pbc = [int(bool(x)) for x in s.get("pbc", (0, 0, 0))]
-        cut = s["cutoffs"]
-        dummy = ctypes.c_void_p(1)
-        descs[i] = C.StructureDesc(
-            int(pos.shape[0]), _ptr(pos), dummy, dummy,
-            cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
-            (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
-            float(cut["r_mbd1"]), float(cut["r_mbd2"]), None, None, dummy if forces else None, None)
+        descs[i], _ = _host_desc(s, forces, keep)
     out = ctypes.c_size_t(0)
     st = C.lib().lmbd_estimate_footprint(ctypes.byref(p), len(structures), descs, ctypes.byref(out))
     if st != 0:
         raise C.LmbdError(st)
     return int(out.value)
+
+
+def _info_dict(info):
+    return {"done": bool(info.done), "status": C.STATUS.get(info.status, str(info.status)),
+            "t_submit": info.t_submit, "t_start": info.t_start, "t_end": info.t_end,
+            "footprint": int(info.footprint), "batch": int(info.batch),
+            "batch_requests": int(info.batch_requests), "slot": int(info.slot),
+            "detail": info.detail.decode(errors="replace")}
+
+
+class Server:
+    """Continuous-batching server (one device pool, ``n_slots`` concurrent batches).
+
+    ``submit`` queues one structure (host arrays, copied here and kept alive
+    until the request is released) and returns a ticket; ``wait``/``poll``
+    return the outputs with the request's timing (seconds since the server was
+    created) and the batch that ran it.
+    """
+
+    def __init__(self, params: MethodParams, species_table, *, device=0, n_slots=2, memory_budget=0,
+                 max_batch_atoms=0, max_batch_requests=0):
+        self.lib = C.lib()
+        p, self._keep = params.to_c()
+        sp, n_sp = species_array(species_table)
+        cfg = C.ServerConfig(int(device), int(n_slots), ctypes.c_size_t(int(memory_budget)),
+                             int(max_batch_atoms), int(max_batch_requests))
+        h = ctypes.c_void_p()
+        st = self.lib.lmbd_server_create(ctypes.byref(cfg), ctypes.byref(p), n_sp, sp, ctypes.byref(h))
+        if st != 0:
+            raise C.LmbdError(st, "lmbd_server_create")
+        self.handle = h
+        self._live = {}
+
+    def submit(self, structure: dict, forces=True) -> int:
+        keep = []
+        desc, outs = _host_desc(structure, forces, keep)
+        t = ctypes.c_uint64(0)
+        st = self.lib.lmbd_submit(self.handle, ctypes.byref(desc), ctypes.byref(t))
+        if st != 0:
+            raise C.LmbdError(st, "lmbd_submit")
+        self._live[t.value] = (keep, outs)
+        return int(t.value)
+
+    def _result(self, ticket, info):
+        d = _info_dict(info)
+        if info.done:
+            d.update(self._live[ticket][1])
+        return d
+
+    def poll(self, ticket: int) -> dict:
+        info = C.RequestInfo()
+        st = self.lib.lmbd_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(info))
+        if st != 0:
+            raise C.LmbdError(st, "lmbd_poll")
+        return self._result(ticket, info)
+
+    def wait(self, ticket: int) -> dict:
+        info = C.RequestInfo()
+        st = self.lib.lmbd_wait(self.handle, ctypes.c_uint64(ticket), ctypes.byref(info))
+        if st != 0:
+            raise C.LmbdError(st, "lmbd_wait")
+        return self._result(ticket, info)
+
+    def release(self, ticket: int):
+        st = self.lib.lmbd_release(self.handle, ctypes.c_uint64(ticket))
+        if st != 0:
+            raise C.LmbdError(st, "lmbd_release")
+        self._live.pop(ticket, None)
+
+    def stats(self) -> dict:
+        s = C.ServerStats()
+        st = self.lib.lmbd_server_get_stats(self.handle, ctypes.byref(s))
+        if st != 0:
+            raise C.LmbdError(st)
+        return {k: getattr(s, k) for k, _ in C.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lmbd_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class LMBDEnergy(torch.autograd.Function):

@@ -9,11 +9,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["lmbd_api.hip", "k_nbr.hip", "k_scs.hip", "k_mbd.hip", "k_gather.hip"]
+SOURCES = ["lmbd_api.hip", "lmbd_serve.hip", "k_nbr.hip", "k_scs.hip", "k_mbd.hip", "k_gather.hip"]
 LIB = os.path.join(HERE, "liblmbd.so")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "--offload-arch=gfx950",
     # keep hand-written float code away from the packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -12,6 +12,7 @@
 // single-GPU form of the exchange of central polarisabilities between the two
 // stages of the paper's flowchart (Sec. III.A).
 #include "lmbd.h"
+#include "lmbd_host.h"
 #include "lmbd_internal.h"
 
 #include <algorithm>
@@ -29,6 +30,7 @@ namespace {
 struct DBuf {
     void* p = nullptr;
     size_t cap = 0;
+    bool owned = false;  // false: a slice of a caller-provided workspace
 };
 
 struct Plan {
@@ -40,7 +42,6 @@ struct Plan {
     std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off;
     int64_t pl_len = 0;
     std::vector<int32_t> hash_cap, fac_ld;
-    size_t bytes = 0;
 };
 
 }  // namespace
@@ -57,33 +58,64 @@ struct lmbd_context {
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
     DBuf pl_i, pl_q, pl_off, pl_seg;
     DBuf e_out, f_out, a_out;
+    // caller-provided workspace: every buffer of a call is carved from it in a
+    // fixed order (nothing is allocated while it is set)
+    char* arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
     bool profiling = false;
     hipEvent_t ev[2 * LMBD_N_STAGES] = {};
     bool ev_used[LMBD_N_STAGES] = {};
     double stage_ms[LMBD_N_STAGES] = {};
 };
 
+#define ALL_BUFFERS(c)                                                                                     \
+    &c->in_pos, &c->in_sp, &c->in_nu, &c->in_w, &c->atom_struct, &c->sinfo, &c->sp_table, &c->omegas, &c->pos_b,  \
+        &c->abar, &c->sigma, &c->Rv, &c->a0v, &c->r0v, &c->cell_id, &c->wrap, &c->iota, &c->sorted_cell,           \
+        &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
+        &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
+        &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg
+
 namespace {
 
-hipError_t ensure(DBuf& b, size_t bytes) {
+constexpr size_t kAlign = 256;
+
+size_t aligned(size_t bytes) {
     if (bytes == 0) bytes = 8;
-    if (bytes <= b.cap) return hipSuccess;
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
-        if (e != hipSuccess) return e;
-    }
-    const size_t nb = bytes + bytes / 8 + 256;
-    hipError_t e = hipMalloc(&b.p, nb);
-    if (e == hipSuccess) b.cap = nb;
-    return e;
+    return (bytes + kAlign - 1) / kAlign * kAlign;
 }
 
 void release(DBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && b.owned) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
+    b.owned = false;
+}
+
+// Make b hold at least `bytes`: a slice of the context's workspace when one is
+// set, else an owned allocation that grows and is cached between calls.
+hipError_t ensure(lmbd_context* ctx, DBuf& b, size_t bytes) {
+    if (ctx->arena) {
+        const size_t need = aligned(bytes);
+        if (ctx->arena_used + need > ctx->arena_size) return hipErrorOutOfMemory;
+        release(b);
+        b.p = ctx->arena + ctx->arena_used;
+        b.cap = need;
+        ctx->arena_used += need;
+        return hipSuccess;
+    }
+    if (bytes == 0) bytes = 8;
+    if (b.owned && bytes <= b.cap) return hipSuccess;
+    release(b);
+    const size_t nb = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&b.p, nb);
+    if (e == hipSuccess) {
+        b.cap = nb;
+        b.owned = true;
+    } else {
+        b.p = nullptr;
+    }
+    return e;
 }
 
 template <typename T>
@@ -218,7 +250,7 @@ int64_t next_pow2(int64_t x) {
     return p;
 }
 
-void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, bool mixed, Plan& P) {
+void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, Plan& P) {
     const int64_t n = (int64_t)cnt.size();
     P.n_atoms = n;
     P.site_off.resize(n + 1);
@@ -265,24 +297,78 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.aloc_len = ao;
     P.work_len = wo;
     P.pl_len = po;
-    const size_t d = sizeof(double);
-    size_t b = 0;
-    b += (size_t)so * sizeof(Site) + (size_t)so * 4 /*rev*/ + (size_t)ho * 4 /*hash*/;
-    const size_t wsz = mixed ? sizeof(float) : sizeof(double);
-    b += (size_t)(fo + wo) * wsz + (size_t)(xo + 2 * ao) * d;
-    b += (size_t)n * nw * d /*abar_cen*/;
-    if (forces) b += (size_t)so * nw * d /*ca*/ + (size_t)(1 + nw) * so * 3 * d /*cf*/;
-    b += (size_t)n * (8 * d + 64);  // per-atom tables and offsets
-    b += (size_t)po * 8 + (size_t)(so + 2 * n) * 4;  // coupling lists
-    P.bytes = b;
 }
 
 template <typename T>
 lmbd_status upload(lmbd_context* ctx, DBuf& b, const std::vector<T>& v, hipStream_t st) {
-    HIP_TRY(ensure(b, sizeof(T) * v.size()));
+    if (sizeof(T) * v.size() > b.cap) return fail(ctx, LMBD_E_DEVICE, "workspace layout mismatch");
     HIP_TRY(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
     return LMBD_OK;
 }
+
+// Sizes that fix the buffers needed before the neighbour counts are known.
+struct PreDims {
+    int64_t N = 0;
+    int n_structs = 0, n_cells = 0, nw = 0, n_species = 0;
+    size_t sort_temp = 0;
+};
+
+// Every workspace buffer of a call, in the order it is laid out.  `get(buf,
+// bytes)` allocates (or, for a footprint estimate, only counts) one buffer.
+template <class F>
+hipError_t layout_pre(lmbd_context* c, const PreDims& d, F&& get) {
+    const size_t N = (size_t)d.N, D = sizeof(double), I = sizeof(int32_t), nw = (size_t)d.nw;
+    const std::pair<DBuf*, size_t> L[] = {
+        {&c->in_pos, 3 * N * D}, {&c->in_sp, N * I}, {&c->in_nu, N * D}, {&c->in_w, N * D},
+        {&c->atom_struct, N * I}, {&c->sinfo, (size_t)d.n_structs * sizeof(StructInfo)},
+        {&c->omegas, nw * D}, {&c->sp_table, 3 * (size_t)std::max(d.n_species, 64) * D}, {&c->iota, N * I},
+        {&c->pos_b, 3 * N * D}, {&c->abar, N * nw * D}, {&c->sigma, N * nw * D}, {&c->Rv, N * D},
+        {&c->a0v, N * D}, {&c->r0v, N * D}, {&c->cell_id, N * I}, {&c->wrap, 3 * N * I},
+        {&c->sorted_cell, N * I}, {&c->sorted_atoms, N * I}, {&c->cell_start, (size_t)d.n_cells * I},
+        {&c->cell_end, (size_t)d.n_cells * I}, {&c->counts, N * sizeof(Counts)}, {&c->flags, 4 * sizeof(int)},
+        {&c->sort_temp, d.sort_temp}};
+    for (const auto& e : L) {
+        const hipError_t r = get(*e.first, e.second);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
+template <class F>
+hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size_t wsz, F&& get) {
+    const size_t N = (size_t)P.n_atoms, D = sizeof(double), I = sizeof(int32_t), L8 = sizeof(int64_t);
+    const size_t TS = (size_t)P.total_sites;
+    const std::pair<DBuf*, size_t> L[] = {
+        {&c->pl_off, N * L8}, {&c->site_off, N * L8}, {&c->hash_off, N * L8}, {&c->hash_cap, N * I},
+        {&c->fac_off, N * L8}, {&c->fac_ld, N * I}, {&c->x_off, N * L8}, {&c->aloc_off, N * L8},
+        {&c->work_off, N * L8}, {&c->sites, TS * sizeof(Site)}, {&c->table, (size_t)P.table_len * I},
+        {&c->rev, TS * I}, {&c->fac, (size_t)P.fac_len * wsz}, {&c->xsol, (size_t)P.x_len * D},
+        {&c->alpha_loc, (size_t)P.aloc_len * D}, {&c->abar_loc, (size_t)P.aloc_len * D},
+        {&c->abar_cen, N * nw * D}, {&c->work, (size_t)P.work_len * wsz}, {&c->e_out, N * D},
+        {&c->a_out, N * D}, {&c->pl_i, (size_t)P.pl_len * I}, {&c->pl_q, (size_t)P.pl_len * I},
+        {&c->pl_seg, (TS + 2 * N) * I}};
+    for (const auto& e : L) {
+        const hipError_t r = get(*e.first, e.second);
+        if (r != hipSuccess) return r;
+    }
+    if (forces) {
+        const std::pair<DBuf*, size_t> F2[] = {
+            {&c->ca, TS * nw * D}, {&c->cf, (size_t)(1 + nw) * TS * 3 * D}, {&c->f_out, 3 * N * D}};
+        for (const auto& e : F2) {
+            const hipError_t r = get(*e.first, e.second);
+            if (r != hipSuccess) return r;
+        }
+    }
+    return hipSuccess;
+}
+
+struct Measure {
+    size_t total = 0;
+    hipError_t operator()(DBuf&, size_t bytes) {
+        total += aligned(bytes);
+        return hipSuccess;
+    }
+};
 
 }  // namespace
 
@@ -299,6 +385,7 @@ const char* lmbd_status_string(lmbd_status s) {
         case LMBD_E_DEVICE: return "HIP runtime error";
         case LMBD_E_SCS_BREAKDOWN: return "local SCS matrix is not positive definite";
         case LMBD_E_UNSUPPORTED: return "unsupported size or option";
+        case LMBD_E_CANCELLED: return "request cancelled";
     }
     return "unknown status";
 }
@@ -324,15 +411,7 @@ void lmbd_destroy(lmbd_context* ctx) {
     (void)hipDeviceSynchronize();
     for (hipEvent_t& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
-    DBuf* all[] = {&ctx->in_pos, &ctx->in_sp, &ctx->in_nu, &ctx->in_w, &ctx->atom_struct, &ctx->sinfo,
-                   &ctx->sp_table, &ctx->omegas, &ctx->pos_b, &ctx->abar, &ctx->sigma, &ctx->Rv,
-                   &ctx->a0v, &ctx->r0v, &ctx->cell_id, &ctx->wrap, &ctx->iota, &ctx->sorted_cell,
-                   &ctx->sorted_atoms, &ctx->cell_start, &ctx->cell_end, &ctx->sort_temp, &ctx->counts,
-                   &ctx->flags, &ctx->site_off, &ctx->sites, &ctx->hash_off, &ctx->hash_cap, &ctx->table,
-                   &ctx->rev, &ctx->fac_off, &ctx->fac_ld, &ctx->x_off, &ctx->aloc_off, &ctx->work_off,
-                   &ctx->fac, &ctx->xsol, &ctx->alpha_loc, &ctx->abar_loc, &ctx->abar_cen, &ctx->work,
-                   &ctx->ca, &ctx->cf, &ctx->e_out, &ctx->f_out, &ctx->a_out, &ctx->pl_i, &ctx->pl_q,
-                   &ctx->pl_off, &ctx->pl_seg};
+    DBuf* all[] = {ALL_BUFFERS(ctx)};
     for (DBuf* b : all) release(*b);
     (void)hipSetDevice(prev);
     delete ctx;
@@ -365,62 +444,185 @@ lmbd_status lmbd_set_memory_budget(lmbd_context* ctx, size_t bytes) {
     return LMBD_OK;
 }
 
-// Host-side neighbour counting for the footprint estimate (same radii and the
-// same cell geometry as the device, plain loops).
-static lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<Counts>& out) {
-    StructInfo si;
-    lmbd_status st = make_struct_info(ctx, s, s.pos, 0, 0, si);
+}  // extern "C"
+
+// Host-side neighbour counts for footprint estimates: the cell list of the
+// device (same grid, same traversal) and the same pair vectors, evaluated with
+// the same operations, so the counts equal the device's.
+namespace {
+
+void h_lattice_vec(const double* c, int t0, int t1, int t2, double out[3]) {
+    out[0] = std::fma((double)t2, c[6], std::fma((double)t1, c[3], (double)t0 * c[0]));
+    out[1] = std::fma((double)t2, c[7], std::fma((double)t1, c[4], (double)t0 * c[1]));
+    out[2] = std::fma((double)t2, c[8], std::fma((double)t1, c[5], (double)t0 * c[2]));
+}
+
+void h_canonical_rel(const double* pos, const double* cell, int kc, int j, int t0, int t1, int t2, double v[3]) {
+    const bool pos_dir = j > kc || (j == kc && (t0 > 0 || (t0 == 0 && (t1 > 0 || (t1 == 0 && t2 > 0)))));
+    double T[3];
+    if (pos_dir) {
+        h_lattice_vec(cell, t0, t1, t2, T);
+        for (int d = 0; d < 3; ++d) v[d] = (pos[3 * j + d] + T[d]) - pos[3 * kc + d];
+    } else {
+        h_lattice_vec(cell, -t0, -t1, -t2, T);
+        for (int d = 0; d < 3; ++d) v[d] = -((pos[3 * kc + d] + T[d]) - pos[3 * j + d]);
+    }
+}
+
+lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<Counts>& out, int& n_cells) {
+    StructInfo S;
+    lmbd_status st = make_struct_info(ctx, s, s.pos, 0, 0, S);
     if (st != LMBD_OK) return st;
     const int n = (int)s.n_atoms;
+    const int nc = S.ncell[0] * S.ncell[1] * S.ncell[2];
+    n_cells = nc;
     std::vector<double> p(3 * (size_t)n);
-    for (int i = 0; i < 3 * n; ++i) p[i] = s.pos[i] / kBohr;
-    int range[3];
-    for (int d = 0; d < 3; ++d) range[d] = si.periodic ? si.reach[d] + 1 : 0;
-    const double r1 = si.r_scs * si.r_scs, rK = si.r_nbr * si.r_nbr, r2 = 4 * si.r_scs * si.r_scs,
-                 rb = si.r_big * si.r_big;
+    std::vector<int> cell(n), wrap(3 * (size_t)n);
+    for (int g = 0; g < n; ++g) {
+        for (int d = 0; d < 3; ++d) p[3 * g + d] = s.pos[3 * g + d] / kBohr;
+        int c[3];
+        for (int d = 0; d < 3; ++d) {
+            if (S.periodic) {
+                const double f = p[3 * g] * S.inv[d] + p[3 * g + 1] * S.inv[3 + d] + p[3 * g + 2] * S.inv[6 + d];
+                const double fl = std::floor(f);
+                wrap[3 * g + d] = (int)fl;
+                c[d] = std::min(std::max((int)((f - fl) * S.ncell[d]), 0), S.ncell[d] - 1);
+            } else {
+                const double h = S.cell[4 * d] / S.ncell[d];
+                c[d] = std::min(std::max((int)((p[3 * g + d] - S.origin[d]) / h), 0), S.ncell[d] - 1);
+                wrap[3 * g + d] = 0;
+            }
+        }
+        cell[g] = (c[0] * S.ncell[1] + c[1]) * S.ncell[2] + c[2];
+    }
+    std::vector<int> start(nc + 1, 0), order(n);
+    for (int g = 0; g < n; ++g) start[cell[g] + 1]++;
+    for (int c = 0; c < nc; ++c) start[c + 1] += start[c];
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int g = 0; g < n; ++g) order[fill[cell[g]]++] = g;
+    }
+    const double r1 = S.r_scs * S.r_scs, rK = S.r_nbr * S.r_nbr, r2 = 4.0 * S.r_scs * S.r_scs,
+                 rb = S.r_big * S.r_big;
     for (int k = 0; k < n; ++k) {
         Counts c{1, 1, 1, 1};
-        for (int a = -range[0]; a <= range[0]; ++a)
-            for (int b = -range[1]; b <= range[1]; ++b)
-                for (int e = -range[2]; e <= range[2]; ++e)
-                    for (int j = 0; j < n; ++j) {
-                        if (j == k && a == 0 && b == 0 && e == 0) continue;
+        const int ck[3] = {cell[k] / (S.ncell[1] * S.ncell[2]), (cell[k] / S.ncell[2]) % S.ncell[1],
+                           cell[k] % S.ncell[2]};
+        for (int dx = -S.reach[0]; dx <= S.reach[0]; ++dx)
+            for (int dy = -S.reach[1]; dy <= S.reach[1]; ++dy)
+                for (int dz = -S.reach[2]; dz <= S.reach[2]; ++dz) {
+                    int cc[3] = {ck[0] + dx, ck[1] + dy, ck[2] + dz};
+                    int sh[3] = {0, 0, 0};
+                    bool inside = true;
+                    for (int d = 0; d < 3; ++d) {
+                        if (S.periodic) {
+                            const int m = S.ncell[d];
+                            const int q = (cc[d] >= 0) ? cc[d] / m : -((-cc[d] + m - 1) / m);
+                            sh[d] = q;
+                            cc[d] -= q * m;
+                        } else if (cc[d] < 0 || cc[d] >= S.ncell[d]) {
+                            inside = false;
+                        }
+                    }
+                    if (!inside) continue;
+                    const int gc = (cc[0] * S.ncell[1] + cc[1]) * S.ncell[2] + cc[2];
+                    for (int i = start[gc]; i < start[gc + 1]; ++i) {
+                        const int j = order[i];
+                        const int t0 = sh[0] - wrap[3 * j] + wrap[3 * k];
+                        const int t1 = sh[1] - wrap[3 * j + 1] + wrap[3 * k + 1];
+                        const int t2 = sh[2] - wrap[3 * j + 2] + wrap[3 * k + 2];
+                        if (j == k && t0 == 0 && t1 == 0 && t2 == 0) continue;
                         double v[3];
-                        for (int d = 0; d < 3; ++d)
-                            v[d] = p[3 * j + d] - p[3 * k + d] +
-                                   (si.periodic ? a * si.cell[d] + b * si.cell[3 + d] + e * si.cell[6 + d] : 0.0);
-                        const double d2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-                        if (d2 >= rb) continue;
+                        h_canonical_rel(p.data(), S.cell, k, j, t0, t1, t2, v);
+                        const double d2 = std::fma(v[2], v[2], std::fma(v[1], v[1], v[0] * v[0]));
+                        if (!(d2 < rb)) continue;
                         c.n_all++;
                         c.n1 += d2 < r1;
                         c.nK += d2 < rK;
                         c.n12 += d2 < r2;
                     }
+                }
         out.push_back(c);
     }
     return LMBD_OK;
 }
 
-lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs,
-                                    const lmbd_structure* structs, size_t* bytes) {
+}  // namespace
+
+namespace lmbd {
+
+lmbd_status analyse_structure(const lmbd_params* params, const lmbd_structure& s, StructCounts& out) {
     lmbd_context* ctx = nullptr;
-    if (!bytes || !structs || n_structs < 1) return LMBD_E_INVALID_ARG;
-    lmbd_status st = check_params(ctx, params);
+    lmbd_status st = check_struct(ctx, params, s);
     if (st != LMBD_OK) return st;
+    for (int64_t i = 0; i < s.n_atoms; ++i) {
+        if (!finite_pos(s.v_ratio[i]) || s.species[i] < 0) return LMBD_E_INVALID_ARG;
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(s.pos[3 * i + d])) return LMBD_E_INVALID_ARG;
+    }
+    out.cnt.clear();
+    out.cnt.reserve((size_t)s.n_atoms);
+    out.forces = s.forces != nullptr;
+    return host_counts(ctx, s, out.cnt, out.n_cells);
+}
+
+lmbd_status layout_bytes(const lmbd_params* params, int n_species, const std::vector<const StructCounts*>& parts,
+                         size_t* bytes) {
     std::vector<Counts> cnt;
     bool forces = false;
-    for (int s = 0; s < n_structs; ++s) {
-        st = check_struct(ctx, params, structs[s]);
-        if (st != LMBD_OK) return st;
-        st = host_counts(ctx, structs[s], cnt);
-        if (st != LMBD_OK) return st;
-        forces = forces || structs[s].forces != nullptr;
+    int n_cells = 0;
+    for (const StructCounts* p : parts) {
+        cnt.insert(cnt.end(), p->cnt.begin(), p->cnt.end());
+        n_cells += p->n_cells;
+        forces = forces || p->forces;
     }
+    if (cnt.empty() || cnt.size() > (size_t)(INT32_MAX / 8)) return LMBD_E_UNSUPPORTED;
+    const int nw = params->n_freq + 1;
+    PreDims pd;
+    pd.N = (int64_t)cnt.size();
+    pd.n_structs = (int)parts.size();
+    pd.n_cells = n_cells;
+    pd.nw = nw;
+    pd.n_species = n_species;
+    if (sort_cells(nullptr, (int)pd.N, n_cells, nullptr, nullptr, nullptr, nullptr, nullptr, &pd.sort_temp,
+                   nullptr, nullptr) != hipSuccess)
+        return LMBD_E_DEVICE;
+    lmbd_context layout;  // only its buffer descriptors are named; nothing is allocated
+    Measure m;
+    (void)layout_pre(&layout, pd, m);
     Plan P;
-    build_plan(cnt, params->n_freq + 1, 3 * params->n_freq, params->n_max, forces,
-               params->precision == LMBD_MIXED, P);
-    *bytes = P.bytes;
+    build_plan(cnt, nw, 3 * params->n_freq, params->n_max, forces, P);
+    (void)layout_post(&layout, P, nw, forces, params->precision == LMBD_MIXED ? sizeof(float) : sizeof(double), m);
+    *bytes = m.total;
     return LMBD_OK;
+}
+
+void set_workspace(lmbd_context* ctx, void* base, size_t bytes) {
+    DBuf* all[] = {ALL_BUFFERS(ctx)};
+    for (DBuf* b : all) release(*b);
+    ctx->arena = static_cast<char*>(base);
+    ctx->arena_size = base ? bytes : 0;
+    ctx->arena_used = 0;
+}
+
+}  // namespace lmbd
+
+extern "C" {
+
+lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs, const lmbd_structure* structs,
+                                    size_t* bytes) {
+    if (!bytes || !structs || n_structs < 1) return LMBD_E_INVALID_ARG;
+    lmbd_status st = check_params(nullptr, params);
+    if (st != LMBD_OK) return st;
+    std::vector<StructCounts> sc(n_structs);
+    std::vector<const StructCounts*> parts;
+    int max_sp = 0;
+    for (int s = 0; s < n_structs; ++s) {
+        if ((st = analyse_structure(params, structs[s], sc[s])) != LMBD_OK) return st;
+        for (int64_t i = 0; i < structs[s].n_atoms; ++i) max_sp = std::max(max_sp, structs[s].species[i]);
+        parts.push_back(&sc[s]);
+    }
+    return layout_bytes(params, std::max(64, max_sp + 1), parts, bytes);
 }
 
 lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int32_t n_species,
@@ -464,17 +666,54 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     const hipMemcpyKind h2d = mem == LMBD_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind d2o = mem == LMBD_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
 
-    // --- inputs into contiguous batch arrays
-    HIP_TRY(ensure(ctx->in_pos, sizeof(double) * 3 * N));
-    HIP_TRY(ensure(ctx->in_sp, sizeof(int32_t) * N));
-    HIP_TRY(ensure(ctx->in_nu, sizeof(double) * N));
-    HIP_TRY(ensure(ctx->in_w, sizeof(double) * N));
-    std::vector<int32_t> atom_struct(N);
-    std::vector<double> pos_host;
-    std::vector<double> ones;
+    // --- workspace of the stages before the memory plan
+    int n_cells = 0;
     std::vector<StructInfo> sinfo(n_structs);
-    int off = 0, coff = 0;
-    for (int s = 0; s < n_structs; ++s) {
+    std::vector<std::vector<double>> pos_host(n_structs);
+    for (int s = 0, off = 0, coff = 0; s < n_structs; ++s) {
+        const lmbd_structure& S = structs[s];
+        const int n = (int)S.n_atoms;
+        const double* ph = S.pos;
+        if (mem == LMBD_DEVICE && !(S.pbc[0] && S.pbc[1] && S.pbc[2])) {
+            pos_host[s].resize(3 * (size_t)n);
+            HIP_TRY(hipMemcpyAsync(pos_host[s].data(), S.pos, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            ph = pos_host[s].data();
+        }
+        if (mem == LMBD_HOST) {
+            for (int i = 0; i < n; ++i) {
+                if (S.species[i] < 0 || S.species[i] >= n_species)
+                    return fail(ctx, LMBD_E_INVALID_ARG, "species index out of range");
+                if (!finite_pos(S.v_ratio[i])) return fail(ctx, LMBD_E_INVALID_ARG, "non-positive volume ratio");
+                for (int d = 0; d < 3; ++d)
+                    if (!std::isfinite(S.pos[3 * i + d])) return fail(ctx, LMBD_E_INVALID_ARG, "non-finite position");
+            }
+        }
+        st = make_struct_info(ctx, S, ph, off, coff, sinfo[s]);
+        if (st != LMBD_OK) return st;
+        off += n;
+        coff += sinfo[s].ncell[0] * sinfo[s].ncell[1] * sinfo[s].ncell[2];
+        n_cells = coff;
+    }
+    PreDims pd;
+    pd.N = N;
+    pd.n_structs = n_structs;
+    pd.n_cells = n_cells;
+    pd.nw = nw;
+    pd.n_species = n_species;
+    HIP_TRY(sort_cells(stream, N, n_cells, nullptr, nullptr, nullptr, nullptr, nullptr, &pd.sort_temp, nullptr,
+                       nullptr));
+    Measure pre_bytes;
+    (void)layout_pre(ctx, pd, pre_bytes);
+    if (ctx->budget && pre_bytes.total > ctx->budget)
+        return fail(ctx, LMBD_E_OOM_ADMISSION, "footprint over the memory budget");
+    if (ctx->arena && pre_bytes.total > ctx->arena_size)
+        return fail(ctx, LMBD_E_OOM_ADMISSION, "footprint over the workspace size");
+    ctx->arena_used = 0;
+    HIP_TRY(layout_pre(ctx, pd, [&](DBuf& b, size_t n) { return ensure(ctx, b, n); }));
+    std::vector<int32_t> atom_struct(N);
+    std::vector<double> ones;
+    for (int s = 0, off = 0; s < n_structs; ++s) {
         const lmbd_structure& S = structs[s];
         const int n = (int)S.n_atoms;
         HIP_TRY(hipMemcpyAsync(as<double>(ctx->in_pos) + 3 * (size_t)off, S.pos, sizeof(double) * 3 * n, h2d, stream));
@@ -488,29 +727,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
                                    hipMemcpyHostToDevice, stream));
             HIP_TRY(hipStreamSynchronize(stream));
         }
-        const double* ph = S.pos;
-        if (mem == LMBD_DEVICE && !(S.pbc[0] && S.pbc[1] && S.pbc[2])) {
-            pos_host.resize(3 * (size_t)n);
-            HIP_TRY(hipMemcpyAsync(pos_host.data(), S.pos, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            ph = pos_host.data();
-        }
-        if (mem == LMBD_HOST) {
-            for (int i = 0; i < n; ++i) {
-                if (S.species[i] < 0 || S.species[i] >= n_species)
-                    return fail(ctx, LMBD_E_INVALID_ARG, "species index out of range");
-                if (!finite_pos(S.v_ratio[i])) return fail(ctx, LMBD_E_INVALID_ARG, "non-positive volume ratio");
-                for (int d = 0; d < 3; ++d)
-                    if (!std::isfinite(S.pos[3 * i + d])) return fail(ctx, LMBD_E_INVALID_ARG, "non-finite position");
-            }
-        }
-        st = make_struct_info(ctx, S, ph, off, coff, sinfo[s]);
-        if (st != LMBD_OK) return st;
         for (int i = 0; i < n; ++i) atom_struct[off + i] = s;
         off += n;
-        coff += sinfo[s].ncell[0] * sinfo[s].ncell[1] * sinfo[s].ncell[2];
     }
-    const int n_cells = coff;
     std::vector<double> omegas(nw);
     omegas[0] = 0.0;
     for (int q = 0; q < nq; ++q) omegas[q + 1] = params->omega[q];
@@ -529,20 +748,6 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if ((st = upload(ctx, ctx->iota, iota, stream)) != LMBD_OK) return st;
 
     // --- per-atom tables and cell list
-    HIP_TRY(ensure(ctx->pos_b, sizeof(double) * 3 * N));
-    HIP_TRY(ensure(ctx->abar, sizeof(double) * (size_t)N * nw));
-    HIP_TRY(ensure(ctx->sigma, sizeof(double) * (size_t)N * nw));
-    HIP_TRY(ensure(ctx->Rv, sizeof(double) * N));
-    HIP_TRY(ensure(ctx->a0v, sizeof(double) * N));
-    HIP_TRY(ensure(ctx->r0v, sizeof(double) * N));
-    HIP_TRY(ensure(ctx->cell_id, sizeof(int32_t) * N));
-    HIP_TRY(ensure(ctx->wrap, sizeof(int32_t) * 3 * N));
-    HIP_TRY(ensure(ctx->sorted_cell, sizeof(int32_t) * N));
-    HIP_TRY(ensure(ctx->sorted_atoms, sizeof(int32_t) * N));
-    HIP_TRY(ensure(ctx->cell_start, sizeof(int32_t) * n_cells));
-    HIP_TRY(ensure(ctx->cell_end, sizeof(int32_t) * n_cells));
-    HIP_TRY(ensure(ctx->counts, sizeof(Counts) * N));
-    HIP_TRY(ensure(ctx->flags, sizeof(int) * 4));
     int flags_init[4] = {0, INT_MAX, 0, 0};
     HIP_TRY(hipMemcpyAsync(ctx->flags.p, flags_init, sizeof(flags_init), hipMemcpyHostToDevice, stream));
     int* err = as<int>(ctx->flags);
@@ -553,11 +758,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
                         n_species, as<double>(ctx->omegas), nw, as<double>(ctx->pos_b), as<double>(ctx->abar),
                         as<double>(ctx->sigma), as<double>(ctx->Rv), as<double>(ctx->a0v), as<double>(ctx->r0v),
                         as<int32_t>(ctx->cell_id), as<int32_t>(ctx->wrap), err));
-    size_t temp_bytes = 0;
-    HIP_TRY(sort_cells(stream, N, n_cells, nullptr, nullptr, nullptr, nullptr, nullptr, &temp_bytes, nullptr,
-                       nullptr));
-    HIP_TRY(ensure(ctx->sort_temp, temp_bytes));
-    temp_bytes = ctx->sort_temp.cap;
+    size_t temp_bytes = ctx->sort_temp.cap;
     HIP_TRY(sort_cells(stream, N, n_cells, as<int32_t>(ctx->cell_id), as<int32_t>(ctx->iota),
                        as<int32_t>(ctx->sorted_cell), as<int32_t>(ctx->sorted_atoms), ctx->sort_temp.p,
                        &temp_bytes, as<int32_t>(ctx->cell_start), as<int32_t>(ctx->cell_end)));
@@ -582,7 +783,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
 
     // --- memory plan
     Plan P;
-    build_plan(cnt, nw, ncol, n_max, forces, mixed, P);
+    build_plan(cnt, nw, ncol, n_max, forces, P);
     if (P.n1max > kMaxN1 || P.nkmax > kMaxNK || P.nallmax > kMaxSites)
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
@@ -592,8 +793,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit)
         return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood needs more LDS than the device offers (" +
                                                  std::to_string(lds_limit) + " bytes)");
-    if (ctx->budget && P.bytes > ctx->budget)
-        return fail(ctx, LMBD_E_OOM_ADMISSION, "footprint " + std::to_string(P.bytes) + " bytes over budget");
+    Measure post_bytes;
+    (void)layout_post(ctx, P, nw, forces, wsz, post_bytes);
+    if (ctx->budget && pre_bytes.total + post_bytes.total > ctx->budget)
+        return fail(ctx, LMBD_E_OOM_ADMISSION,
+                    "footprint " + std::to_string(pre_bytes.total + post_bytes.total) + " bytes over the memory budget");
+    if (ctx->arena && ctx->arena_used + post_bytes.total > ctx->arena_size)
+        return fail(ctx, LMBD_E_OOM_ADMISSION, "footprint over the workspace size");
+    HIP_TRY(layout_post(ctx, P, nw, forces, wsz, [&](DBuf& b, size_t n) { return ensure(ctx, b, n); }));
     std::vector<int64_t> so(P.site_off.begin(), P.site_off.end() - 1);
     std::vector<int64_t> ho(P.hash_off.begin(), P.hash_off.end() - 1);
     std::vector<int64_t> fo(P.fac_off.begin(), P.fac_off.end() - 1);
@@ -611,25 +818,6 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if ((st = upload(ctx, ctx->aloc_off, ao, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->work_off, wo, stream)) != LMBD_OK) return st;
     const int64_t TS = P.total_sites;
-    HIP_TRY(ensure(ctx->sites, sizeof(Site) * TS));
-    HIP_TRY(ensure(ctx->table, sizeof(int32_t) * P.table_len));
-    HIP_TRY(ensure(ctx->rev, sizeof(int32_t) * TS));
-    HIP_TRY(ensure(ctx->fac, wsz * P.fac_len));
-    HIP_TRY(ensure(ctx->xsol, sizeof(double) * P.x_len));
-    HIP_TRY(ensure(ctx->alpha_loc, sizeof(double) * P.aloc_len));
-    HIP_TRY(ensure(ctx->abar_loc, sizeof(double) * P.aloc_len));
-    HIP_TRY(ensure(ctx->abar_cen, sizeof(double) * (size_t)N * nw));
-    HIP_TRY(ensure(ctx->work, wsz * P.work_len));
-    HIP_TRY(ensure(ctx->e_out, sizeof(double) * N));
-    if (forces) {
-        HIP_TRY(ensure(ctx->ca, sizeof(double) * TS * nw));
-        HIP_TRY(ensure(ctx->cf, sizeof(double) * (size_t)(1 + nw) * TS * 3));
-        HIP_TRY(ensure(ctx->f_out, sizeof(double) * 3 * N));
-    }
-    HIP_TRY(ensure(ctx->a_out, sizeof(double) * N));
-    HIP_TRY(ensure(ctx->pl_i, sizeof(int32_t) * P.pl_len));
-    HIP_TRY(ensure(ctx->pl_q, sizeof(int32_t) * P.pl_len));
-    HIP_TRY(ensure(ctx->pl_seg, sizeof(int32_t) * (TS + 2 * (int64_t)N)));
 
     // --- neighbour lists and the reverse-slot map
     HIP_TRY(mark(1, 0));
@@ -730,8 +918,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_central_static(stream, N, nw, sa.alpha_loc, sa.aloc_off, as<double>(ctx->a_out)));
 
     // --- outputs
-    off = 0;
-    for (int s = 0; s < n_structs; ++s) {
+    for (int s = 0, off = 0; s < n_structs; ++s) {
         const lmbd_structure& S = structs[s];
         const int n = (int)S.n_atoms;
         if (S.e_atom)

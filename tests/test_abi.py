@@ -1,0 +1,68 @@
+"""The C ABI without a GPU: the built library loads, exports every function that
+include/lmbd.h declares, the binding declares the same set, and the calls that
+need no device behave as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lmbd.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(lmbd_\w+)\s*\(", text))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2407_06409_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("liblmbd.so not built")
+    return _lib.lib()
+
+
+def test_header_declares_the_expected_api():
+    names = header_functions()
+    for must in ("lmbd_create", "lmbd_destroy", "lmbd_compute", "lmbd_compute_batch", "lmbd_estimate_footprint",
+                 "lmbd_submit", "lmbd_poll", "lmbd_wait", "lmbd_server_create", "lmbd_server_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_function(lib):
+    from paper_2407_06409_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\sT\s+(lmbd_\w+)$", out.stdout, flags=re.M))
+    declared = header_functions()
+    assert declared <= exported, declared - exported
+    assert set(_lib.EXPORTED) == declared
+
+
+def test_calls_that_need_no_device(lib):
+    assert lib.lmbd_abi_version() == 1
+    assert lib.lmbd_status_string(0) == b"ok"
+    assert lib.lmbd_status_string(3) == b"request exceeds the memory budget"
+    assert lib.lmbd_status_string(7) == b"request cancelled"
+    assert lib.lmbd_stage_name(2) == b"scs_forward"
+    assert lib.lmbd_stage_name(7) is None
+    assert lib.lmbd_last_error(None) == b""
+    lib.lmbd_destroy(None)
+    lib.lmbd_server_destroy(None)
+    # NULL handles and out-pointers are argument errors, not crashes
+    assert lib.lmbd_create(0, None) == 1
+    assert lib.lmbd_compute_batch(None, None, 0, None, 0, None, 0, None) == 1
+    assert lib.lmbd_set_memory_budget(None, 0) == 1
+    assert lib.lmbd_submit(None, None, None) == 1
+    assert lib.lmbd_poll(None, 0, None) == 1
+    assert lib.lmbd_release(None, 0) == 1
+    assert lib.lmbd_estimate_footprint(None, 0, None, None) == 1
+
+
+def test_bad_device_index_is_an_argument_error(lib):
+    h = ctypes.c_void_p()
+    assert lib.lmbd_create(-1, ctypes.byref(h)) == 1
+    assert lib.lmbd_create(1 << 20, ctypes.byref(h)) == 1
