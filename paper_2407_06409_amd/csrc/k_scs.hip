@@ -21,10 +21,10 @@ namespace lmbd {
 
 constexpr int NB = 16;      // block size of the factorisation
 constexpr int kParts = 4;   // partner-range splits of the per-site pair loops (adjoint)
-constexpr int kPartsD = 2;  // partner-range splits of the right-hand-side assembly
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+
 
 // MFMA 16x16x4 in the matrix type.  Lane layouts measured on gfx950: A[i][k] <- lane
 // i + 16k and B[k][j] <- lane j + 16k for both types; the accumulator holds D[i][j] in
@@ -83,18 +83,44 @@ __device__ inline void inner_buffer(double r, double rin, double& fin, double& d
 }
 
 // ---------------------------------------------------------------------------
-// Left-looking blocked Cholesky of the N x N lower triangle of A (column-major,
-// leading dimension ld) by one workgroup, 16-column panels:
-//   A[c0:N, c0:c0+16] -= L[c0:N, 0:c0] L[c0:c0+16, 0:c0]^T     (MFMA 16x16x4)
-//   L_pp = chol(A_pp)                                          (one wavefront, shuffles)
-//   L[c0+16:N, c0:c0+16] = A[c0+16:N, c0:c0+16] L_pp^{-T}       (one row per thread)
-// The update reads the finished columns with coalesced row segments and writes
-// each panel element once; the strict upper triangle is never touched.  D is a
-// 16x16 LDS block.
+// Storage: the N x N matrix is row-major, lower triangle (A[row * ld + col],
+// col <= row), ld a multiple of 4 so that a 16-column row segment is four
+// aligned 4-vectors.  After the factorisation the strict upper part of each
+// 16x16 diagonal block holds the strict lower part of that block's inverse
+// Z = L_bb^{-1}, transposed (Z[r][q], r > q, at (q, r)); the diagonal of Z is
+// 1 / L[r][r].
+//
+// Left-looking blocked Cholesky by one workgroup, 16-column panels p:
+//  (1) update  A[c0:N, c0:c0+16] -= L[c0:N, 0:c0] L[c0:c0+16, 0:c0]^T  on MFMA
+//      16x16x4, one (row tile, k-split) unit per wavefront, 16 k at a time
+//      from two aligned 4-vector loads per lane.  When the panel has fewer row
+//      tiles than there are wavefronts the k range is split and the partial
+//      tiles go to LDS; otherwise each unit adds into the matrix in place;
+//  (2) diagonal block: wavefront 0 factorises it with lane shuffles (lane l
+//      holds row l), keeps L_pp and 1/L_ii in LDS;
+//  (3) rows below: one row per thread solves x L_pp^T = a by substitution.
+// Then every wavefront inverts some of the diagonal blocks.  LDS use is a few
+// kilobytes, independent of N, so several factorisations share a compute unit
+// and hide each other's memory latency.
 // ---------------------------------------------------------------------------
+constexpr int kSlotLd = 17;   // row stride of a 16x16 tile in LDS (padding against bank conflicts)
+
+template <typename R> struct Vec4T;
+template <> struct Vec4T<double> { typedef d4_t type; };
+template <> struct Vec4T<float> { typedef f4_t type; };
+
 template <typename R>
-__device__ void chol_factor(R* __restrict__ A, int N, int ld, R* D, bool& ok) {
+__device__ inline typename Vec4T<R>::type load4(const R* p) {
+    return *reinterpret_cast<const typename Vec4T<R>::type*>(p);
+}
+
+constexpr int kMaxSplitSlots = 4;  // partial tiles of a split-K panel update (one per wavefront)
+
+template <typename R>
+__device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ slots, R* __restrict__ Ld,
+                            R* __restrict__ rinv, bool& ok) {
     typedef Mfma<R> M;
+    typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
@@ -104,43 +130,67 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* D, bool& ok) {
     for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        // (1) panel update, one 16x16 row tile per wavefront at a time
-        if (c0 > 0) {
-            for (int r = p + wave; r < nt; r += nwave) {
-                const int R0 = r * NB;
-                typename M::acc acc;
+        const int m = nt - p;
+        const int S = (p > 0 && m < nwave) ? min(nwave / m, p) : 1;
+        const int U = p > 0 ? m * S : 0;
+        // (1) update of the panel, one (tile, split) unit per wavefront; a unit
+        // that covers the whole k range adds into the matrix in place, split
+        // units leave partial tiles in LDS
+        for (int u = wave; u < U; u += nwave) {
+            const int t = u % m, s = u / m;
+            const int arow = c0 + NB * t + li, brow = c0 + li;
+            const bool aok = arow < N, bok = brow < N;
+            const R* pa = A + (size_t)(aok ? arow : 0) * ld + 4 * lk;
+            const R* pb = A + (size_t)(bok ? brow : 0) * ld + 4 * lk;
+            typename M::acc acc0, acc1;
+            for (int q = 0; q < 4; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
+            const V4 zero = {R(0), R(0), R(0), R(0)};
+            int ch = s;
+            for (; ch + S < p; ch += 2 * S) {
+                const V4 a0 = aok ? load4(pa + NB * ch) : zero;
+                const V4 b0 = bok ? load4(pb + NB * ch) : zero;
+                const V4 a1 = aok ? load4(pa + NB * (ch + S)) : zero;
+                const V4 b1 = bok ? load4(pb + NB * (ch + S)) : zero;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], b1[e], acc1);
+            }
+            if (ch < p) {
+                const V4 a0 = aok ? load4(pa + NB * ch) : zero;
+                const V4 b0 = bok ? load4(pb + NB * ch) : zero;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
+            }
+            if (S == 1) {
                 const int col = c0 + li;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row = R0 + M::acc_row(lk, q);
-                    acc[q] = (row < N && col < N && row >= col) ? A[(size_t)col * ld + row] : R(0);
+                    const int row = c0 + NB * t + M::acc_row(lk, q);
+                    if (row < N && col < N && (t > 0 || row >= col)) A[(size_t)row * ld + col] += acc0[q] + acc1[q];
                 }
-                const int arow = R0 + li;
-                const bool arow_ok = arow < N;
-                const bool bcol_ok = col < N;
-#pragma unroll 4
-                for (int k0 = 0; k0 < c0; k0 += 4) {
-                    const size_t kc = (size_t)(k0 + lk) * ld;
-                    const R a = arow_ok ? -A[kc + arow] : R(0);
-                    const R b = bcol_ok ? A[kc + col] : R(0);
-                    acc = M::mma(a, b, acc);
-                }
+            } else {
+                R* sl = slots + (size_t)u * NB * kSlotLd;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = R0 + M::acc_row(lk, q);
-                    if (row < N && col < N && row >= col) A[(size_t)col * ld + row] = acc[q];
-                }
+                for (int q = 0; q < 4; ++q) sl[M::acc_row(lk, q) * kSlotLd + li] = acc0[q] + acc1[q];
             }
-            __syncthreads();
         }
-        // (2) diagonal block: wavefront 0, lane l holds row l of the block
+    __syncthreads();
+        // (2) diagonal block: wavefront 0, lane l holds row l
         if (tid < 64) {
             const int l = tid;
             R row[NB];
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 const bool valid = (l < jb) && (c <= l);
-                row[c] = valid ? A[(size_t)(c0 + c) * ld + c0 + l] : (l == c ? R(1) : R(0));
+                row[c] = valid ? A[(size_t)(c0 + l) * ld + c0 + c] : (l == c ? R(1) : R(0));
+            }
+            for (int s = 0; s < S && S > 1; ++s) {
+                const R* sl = slots + (size_t)(s * m) * NB * kSlotLd + (l & 15) * kSlotLd;
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (l < jb && c <= l) row[c] += sl[c];
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
@@ -155,79 +205,117 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* D, bool& ok) {
                     const R lsc = __shfl(row[c], s, 64);
                     if (l >= s) row[s] -= row[c] * lsc;
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (l < NB) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) D[l * NB + c] = (c <= l) ? row[c] : R(0);
+                for (int c = 0; c < NB; ++c) Ld[l * kSlotLd + c] = (c <= l) ? row[c] : R(0);
+                rinv[l] = R(1) / row[l];
             }
             if (l < jb) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
-                    if (c <= l) A[(size_t)(c0 + c) * ld + c0 + l] = row[c];
+                    if (c <= l) A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
             }
         }
         __syncthreads();
-        // (3) rows below the block: X L_pp^T = A_panel, one row per thread
+        // (3) rows below the block: x L_pp^T = a, one row per thread
         for (int i = c0 + jb + tid; i < N; i += nthr) {
+            const int t = (i - c0) / NB, lr = (i - c0) % NB;
+            R* ar = A + (size_t)i * ld + c0;
             R x[NB];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = (c < jb) ? A[(size_t)(c0 + c) * ld + i] : R(0);
+            for (int v = 0; v < 4; ++v) {
+                const V4 q4 = load4(ar + 4 * v);
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c < jb) {
-                    R s = x[c];
+                for (int e = 0; e < 4; ++e) x[4 * v + e] = q4[e];
+            }
+            for (int s = 0; s < S && S > 1; ++s) {
+                const R* sl = slots + (size_t)(t + s * m) * NB * kSlotLd + lr * kSlotLd;
 #pragma unroll
-                    for (int q = 0; q < c; ++q) s -= x[q] * D[c * NB + q];
-                    x[c] = s / D[c * NB + c];
-                }
+                for (int c = 0; c < NB; ++c) x[c] += sl[c];
             }
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < jb) A[(size_t)(c0 + c) * ld + i] = x[c];
+            for (int c = 0; c < NB; ++c) {  // column sweep; the barriers keep the LDS reads of L_pp
+                const R xc = (c < jb) ? x[c] * rinv[c] : R(0);  // next to their use
+                x[c] = xc;
+#pragma unroll
+                for (int q = c + 1; q < NB; ++q) x[q] -= xc * Ld[q * kSlotLd + c];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                V4 q4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) q4[e] = x[4 * v + e];
+                *reinterpret_cast<V4*>(ar + 4 * v) = q4;
+            }
         }
         __syncthreads();
     }
+    // inverses of the diagonal blocks: lane j < jb computes column j of Z = L_bb^{-1}
+    // by forward substitution and stores Z[q][j] (q > j) at (c0 + j, c0 + q)
+    for (int b = wave; b < nt; b += nwave) {
+        const int c0 = b * NB;
+        const int jb = min(NB, N - c0);
+        const int j = li;
+        if (lk == 0 && j < jb) {
+            R z[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q < j || q >= jb) {
+                    z[q] = R(0);
+                    continue;
+                }
+                const R* lrow = A + (size_t)(c0 + q) * ld + c0;
+                R v = (q == j) ? R(1) : R(0);
+#pragma unroll
+                for (int r = 0; r < q; ++r) v -= lrow[r] * z[r];
+                z[q] = v / lrow[q];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            R* urow = A + (size_t)(c0 + j) * ld + c0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q > j && q < jb) urow[q] = z[q];
+        }
+    }
+    __syncthreads();
     ok = good;
 }
 
-// Solve L L^T Y = Y in place for 3 right-hand sides (Y: LDS, row-major N x 3).
-// Each 16x16 diagonal block is solved by one wavefront with shuffles (lane
-// r + 16 c holds row r, right-hand side c); the coupling to the other rows is
-// one row per thread.
+// Solve L L^T Y = Y in place for 3 right-hand sides (Y in LDS, row-major N x 3),
+// with the stored inverses of the diagonal blocks.  Per block: the 48 block
+// values are products with Z (threads r + 16 c of wavefront 0), then every
+// other row takes the block's contribution, one row per thread.
 template <typename R>
 __device__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y) {
+    typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int nt = (N + NB - 1) / NB;
+    const int r = tid & 15, c = tid >> 4;
     for (int p = 0; p < nt; ++p) {  // forward: L y = b
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        if (tid < 64) {
-            const int r = tid & 15, c = tid >> 4;
-            const bool act = (c < 3) && (r < jb);
-            R Lrow[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) Lrow[q] = (act && q <= r) ? A[(size_t)(c0 + q) * ld + c0 + r] : R(0);
-            R y = act ? Y[(c0 + r) * 3 + c] : R(0);
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const R diag = __shfl(Lrow[j], (tid & 48) + j, 64);
-                const R xj = __shfl(y, (tid & 48) + j, 64) / diag;
-                if (r == j) y = xj;
-                else if (r > j) y -= Lrow[j] * xj;
-            }
-            if (act) Y[(c0 + r) * 3 + c] = y;
+        if (tid < 48 && r < jb) {
+            R v = Y[(c0 + r) * 3 + c] / A[(size_t)(c0 + r) * ld + c0 + r];
+            for (int q = 0; q < r; ++q) v += A[(size_t)(c0 + q) * ld + c0 + r] * Y[(c0 + q) * 3 + c];
+            Y[(c0 + r) * 3 + c] = v;  // one wavefront: all reads of the block precede this write
         }
         __syncthreads();
         for (int i = c0 + jb + tid; i < N; i += nthr) {
+            const R* lr = A + (size_t)i * ld + c0;  // jb = 16 whenever rows follow the block
             R s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (q < jb) {
-                    const R l = A[(size_t)(c0 + q) * ld + i];
-                    s0 += l * Y[(c0 + q) * 3 + 0];
-                    s1 += l * Y[(c0 + q) * 3 + 1];
-                    s2 += l * Y[(c0 + q) * 3 + 2];
+            for (int v = 0; v < 4; ++v) {
+                const V4 l4 = load4(lr + 4 * v);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int q = 4 * v + e;
+                    s0 += l4[e] * Y[(c0 + q) * 3 + 0];
+                    s1 += l4[e] * Y[(c0 + q) * 3 + 1];
+                    s2 += l4[e] * Y[(c0 + q) * 3 + 2];
                 }
             }
             Y[i * 3 + 0] -= s0;
@@ -239,35 +327,20 @@ __device__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y) {
     for (int p = nt - 1; p >= 0; --p) {  // backward: L^T x = y
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        if (tid < 64) {
-            const int r = tid & 15, c = tid >> 4;
-            const bool act = (c < 3) && (r < jb);
-            R Lcol[NB];  // column r of the block: L[c0 + q][c0 + r]
-#pragma unroll
-            for (int q = 0; q < NB; ++q) Lcol[q] = (act && q >= r && q < jb) ? A[(size_t)(c0 + r) * ld + c0 + q] : R(0);
-            R y = act ? Y[(c0 + r) * 3 + c] : R(0);
-#pragma unroll
-            for (int j = NB - 1; j >= 0; --j) {
-                const R diag = __shfl(Lcol[j], (tid & 48) + j, 64);
-                const R xj = __shfl(y, (tid & 48) + j, 64) / diag;
-                if (j < jb) {
-                    if (r == j) y = xj;
-                    else if (r < j) y -= Lcol[j] * xj;
-                }
-            }
-            if (act) Y[(c0 + r) * 3 + c] = y;
+        if (tid < 48 && r < jb) {
+            const R* zrow = A + (size_t)(c0 + r) * ld + c0;
+            R v = Y[(c0 + r) * 3 + c] / zrow[r];
+            for (int q = r + 1; q < jb; ++q) v += zrow[q] * Y[(c0 + q) * 3 + c];
+            Y[(c0 + r) * 3 + c] = v;
         }
         __syncthreads();
         for (int i = tid; i < c0; i += nthr) {
             R s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (q < jb) {
-                    const R l = A[(size_t)i * ld + c0 + q];
-                    s0 += l * Y[(c0 + q) * 3 + 0];
-                    s1 += l * Y[(c0 + q) * 3 + 1];
-                    s2 += l * Y[(c0 + q) * 3 + 2];
-                }
+            for (int q = 0; q < jb; ++q) {  // rows past N hold no solution values
+                const R l = A[(size_t)(c0 + q) * ld + i];
+                s0 += l * Y[(c0 + q) * 3 + 0];
+                s1 += l * Y[(c0 + q) * 3 + 1];
+                s2 += l * Y[(c0 + q) * 3 + 2];
             }
             Y[i * 3 + 0] -= s0;
             Y[i * 3 + 1] -= s1;
@@ -278,29 +351,19 @@ __device__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS layout.  K1 sites, then a union region (shell sites and the per-site
-// reduction area during the right-hand-side assembly; FP32 pair coefficients
-// of B~ afterwards, mixed path only), right-hand sides / solutions (FP64), the
-// solve buffer in the matrix type, and the 16x16 diagonal block.
+// LDS layout of the pair kernels.  K1 sites, right-hand sides / solutions
+// (FP64), the solve buffer in the matrix type, shell sites and a per-site
+// reduction area.
 // ---------------------------------------------------------------------------
 struct ScsLds {
     double *px, *py, *pz, *ab, *sg, *R;        // K1 sites
-    double *qx, *qy, *qz, *qab, *qsg, *qR;     // shell sites (union region)
-    double* red;                               // reduction area (union region)
-    float* coef;                               // pair coefficients (A, B) of B~ (union region)
+    double *qx, *qy, *qz, *qab, *qsg, *qR;     // shell sites
+    double* red;                               // reduction area
     double *Y, *X;
     void* Yr;                                  // solve buffer (matrix type)
-    void* D;                                   // 16x16 block (matrix type)
 };
 
-__device__ __host__ inline size_t scs_union_doubles(int n1max, int n2max, bool mixed) {
-    const size_t red = (kParts * 3 > kPartsD * 9 ? kParts * 3 : kPartsD * 9) * (size_t)n1max;
-    const size_t a = 6 * (size_t)n2max + red;
-    const size_t coef = mixed ? ((size_t)n1max * (n1max + 1) / 2) : 0;  // 2 floats = 1 double each
-    return a > coef ? a : coef;
-}
-
-__device__ inline ScsLds scs_lds(double* base, int n1max, int n2max, bool mixed) {
+__device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     const int N = 3 * n1max;
     ScsLds L;
     L.px = base;
@@ -309,25 +372,42 @@ __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max, bool mixed)
     L.ab = L.pz + n1max;
     L.sg = L.ab + n1max;
     L.R = L.sg + n1max;
-    double* u = L.R + n1max;
-    L.qx = u;
+    L.Y = L.R + n1max;
+    L.X = L.Y + 3 * N;
+    L.Yr = L.X + 3 * N;
+    L.qx = L.X + 6 * N;   // Yr takes at most 3N doubles
     L.qy = L.qx + n2max;
     L.qz = L.qy + n2max;
     L.qab = L.qz + n2max;
     L.qsg = L.qab + n2max;
     L.qR = L.qsg + n2max;
     L.red = L.qR + n2max;
-    L.coef = reinterpret_cast<float*>(u);
-    L.Y = u + scs_union_doubles(n1max, n2max, mixed);
-    L.X = L.Y + 3 * N;
-    L.Yr = L.X + 3 * N;
-    L.D = L.X + 6 * N;   // Yr takes at most 3N doubles
     return L;
 }
 
-size_t scs_lds_bytes(int n1max, int n2max, bool mixed) {
+size_t scs_lds_bytes(int n1max, int n2max, bool) {
     const size_t N = 3 * (size_t)n1max;
-    return sizeof(double) * (6 * (size_t)n1max + scs_union_doubles(n1max, n2max, mixed) + 9 * N + NB * NB);
+    return sizeof(double) * (6 * (size_t)n1max + 9 * N + 6 * (size_t)n2max + (size_t)kParts * 3 * n1max);
+}
+
+// sites only (assembly): K1 sites then shell sites
+size_t scs_assemble_lds_bytes(int n1max, int n2max) { return sizeof(double) * 6 * ((size_t)n1max + n2max); }
+
+__device__ inline ScsLds scs_assemble_lds(double* base, int n1max, int n2max) {
+    ScsLds L = {};
+    L.px = base;
+    L.py = L.px + n1max;
+    L.pz = L.py + n1max;
+    L.ab = L.pz + n1max;
+    L.sg = L.ab + n1max;
+    L.R = L.sg + n1max;
+    L.qx = L.R + n1max;
+    L.qy = L.qx + n2max;
+    L.qz = L.qy + n2max;
+    L.qab = L.qz + n2max;
+    L.qsg = L.qab + n2max;
+    L.qR = L.qsg + n2max;
+    return L;
 }
 
 __device__ inline void load_sites(const ScsArgs& a, int k, int w, int n1, int n12, const ScsLds& L) {
@@ -376,8 +456,10 @@ __device__ inline SrPair<P> k2_pair(const ScsArgs& a, const ScsLds& L, int i, in
                       P(fin), P(dfin));
 }
 
+// Assembly of d (into the solution slot) and of the lower triangle of B~ (into
+// the factor slot), one workgroup per (atom, frequency).
 template <typename R>
-__global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max, int n2max) {
+__global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     constexpr bool mixed = sizeof(R) == 4;
     const int k = blockIdx.x;
@@ -386,24 +468,22 @@ __global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max, int n
     const int n1 = cnt.n1, n12 = cnt.n12;
     const int N = 3 * n1;
     const int ld = a.fac_ld[k];
-    const StructInfo& SI = a.sinfo[a.atom_struct[k]];
-    const double rc = SI.r_scs;
-    ScsLds L = scs_lds(lds, n1max, n2max, mixed);
+    const double rc = a.sinfo[a.atom_struct[k]].r_scs;
+    ScsLds L = scs_assemble_lds(lds, n1max, n2max);
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
-    R* Yr = static_cast<R*>(L.Yr);
-    R* D = static_cast<R*>(L.D);
+    double* D = a.xsol + a.x_off[k] + (size_t)w * N * 3;
+    const int npairs = n1 * (n1 + 1) / 2;
+    float* coef = mixed ? a.coef + a.coef_off[k] + (size_t)w * 2 * npairs : nullptr;
     load_sites(a, k, w, n1, n12, L);
     __syncthreads();
 
-    // d: the shell K2 (TS polarisabilities, f_inner), over the compact list of
-    // coupled (K1 site, shell site) pairs; each site's segment is split over
-    // kPartsD threads and recombined in a fixed order.
+    // d: the shell K2 (TS polarisabilities, f_inner), one K1 site per thread over
+    // its segment of the compact list of coupled (K1 site, shell site) pairs
     const int32_t* seg_i = a.pl_seg + a.site_off[k] + 2 * (int64_t)k;
     const int32_t* li = a.pl_i + a.pl_off[k];
-    for (int t = threadIdx.x; t < n1 * kPartsD; t += blockDim.x) {
-        const int i = t % n1, part = t / n1;
-        double d[9] = {};
-        for (int e = seg_i[i] + part; e < seg_i[i + 1]; e += kPartsD) {
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        double d[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+        for (int e = seg_i[i]; e < seg_i[i + 1]; ++e) {
             const int q = li[e] & 0xFFFF;
             double rh[3], r;
             const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
@@ -411,95 +491,150 @@ __global__ void __launch_bounds__(256) k_scs_forward(ScsArgs a, int n1max, int n
             for (int e2 = 0; e2 < 3; ++e2)
                 for (int c = 0; c < 3; ++c) d[3 * e2 + c] -= ab * (A_ * rh[e2] * rh[c] + (e2 == c ? B_ : 0.0));
         }
-        for (int e = 0; e < 9; ++e) L.red[(size_t)(part * n1 + i) * 9 + e] = d[e];
+        for (int e = 0; e < 9; ++e) D[(3 * i + e / 3) * 3 + e % 3] = d[e];
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        for (int e = 0; e < 9; ++e) {
-            double v = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
-            for (int part = 0; part < kPartsD; ++part) v += L.red[(size_t)(part * n1 + i) * 9 + e];
-            L.Y[(3 * i + e / 3) * 3 + e % 3] = v;
-        }
-    }
-    __syncthreads();  // the union region is free from here on
 
-    // B~ (lower triangle, block by block); the mixed path keeps the FP32 pair
-    // coefficients in LDS for the refinement residual
-    const int npairs = n1 * (n1 + 1) / 2;
+    // B~ (row-major lower triangle), one atom pair per thread: the three rows of
+    // atom i are written in contiguous 3-element runs; the mixed path also keeps
+    // the FP32 pair coefficients for the refinement residual
     for (int p = threadIdx.x; p < npairs; p += blockDim.x) {
         int i, j;
         tri_decode(p, i, j);
         if (i == j) {
             const R inv = R(1.0 / L.ab[i]);
             for (int q = 0; q < 3; ++q)
-                for (int r = q; r < 3; ++r) A[(size_t)(3 * i + q) * ld + 3 * i + r] = (q == r) ? inv : R(0);
-            if (mixed) { L.coef[2 * p] = 0.f; L.coef[2 * p + 1] = 0.f; }
+                for (int c = 0; c <= q; ++c) A[(size_t)(3 * i + q) * ld + 3 * i + c] = (q == c) ? inv : R(0);
+            if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
             continue;
         }
         double rh[3], r;
         const SrPair<R> t = k1_pair<R>(a, L, i, j, rc, rh, r);
         if (mixed) {
-            L.coef[2 * p] = (float)t.A;
-            L.coef[2 * p + 1] = (float)t.B;
+            coef[2 * p] = (float)t.A;
+            coef[2 * p + 1] = (float)t.B;
         }
         for (int q = 0; q < 3; ++q)
             for (int c = 0; c < 3; ++c)
-                A[(size_t)(3 * j + c) * ld + 3 * i + q] = R(double(t.A) * rh[q] * rh[c] + (q == c ? double(t.B) : 0.0));
+                A[(size_t)(3 * i + q) * ld + 3 * j + c] = R(double(t.A) * rh[q] * rh[c] + (q == c ? double(t.B) : 0.0));
     }
-    __syncthreads();
+}
 
+// Factorisation of B~ in place, one workgroup per (atom, frequency); LDS is a
+// fixed few kilobytes, so several factorisations share a compute unit.
+template <typename R>
+__global__ void __launch_bounds__(256) k_scs_factor(ScsArgs a) {
+    __shared__ R slots[kMaxSplitSlots * NB * kSlotLd];
+    __shared__ R Ld[NB * kSlotLd];
+    __shared__ R rinv[NB];
+    const int k = blockIdx.x;
+    const int w = blockIdx.y;
+    const int N = 3 * a.counts[k].n1;
+    const int ld = a.fac_ld[k];
+    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
     bool ok = true;
-    chol_factor<R>(A, N, ld, D, ok);
+    chol_factor<R>(A, N, ld, slots, Ld, rinv, ok);
     if (!ok && threadIdx.x == 0) {
         atomicOr(a.err, 4);
         atomicMin(a.err_atom, k);
     }
+}
+
+// Solve B~ X = d.  FP64: two triangular solves.  Mixed: X = 0, then repeat
+// { residual r = d - B~ X in FP64 with B~ rebuilt from its FP32 pair
+// coefficients; FP32 solve of r; X += correction }.  Writes X over d and the
+// local isotropic polarisabilities Tr(X_i) / 3.
+template <typename R>
+__global__ void __launch_bounds__(256) k_scs_solve(ScsArgs a, int n1max) {
+    extern __shared__ double lds[];
+    constexpr bool mixed = sizeof(R) == 4;
+    constexpr int kRes = 2;  // partner-range splits of the residual
+    const int k = blockIdx.x;
+    const int w = blockIdx.y;
+    const int n1 = a.counts[k].n1;
+    const int N = 3 * n1;
+    const int Nmax = 3 * n1max;
+    const int ld = a.fac_ld[k];
+    const R* A = static_cast<const R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
+    double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
+    double* Y = lds;
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = Xg[e];
+    __syncthreads();
     if (!mixed) {
-        chol_solve3<double>(reinterpret_cast<const double*>(A), N, ld, L.Y);
+        chol_solve3<double>(reinterpret_cast<const double*>(A), N, ld, Y);
     } else {
-        // X = 0; repeat: residual r = d - B~ X in FP64 with B~ rebuilt from its
-        // FP32 pair coefficients, FP32 solve of r, X += correction
-        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.X[e] = 0.0;
+        double* X = Y + 3 * Nmax;
+        R* Yr = reinterpret_cast<R*>(X + 3 * Nmax);
+        double* px = X + 6 * Nmax;  // Yr takes at most 3 Nmax doubles
+        double* py = px + n1max;
+        double* pz = py + n1max;
+        double* ab = pz + n1max;
+        double* red = ab + n1max;   // kRes * n1max * 9
+        const Site* S = a.sites + a.site_off[k];
+        for (int s = threadIdx.x; s < n1; s += blockDim.x) {
+            px[s] = S[s].x;
+            py[s] = S[s].y;
+            pz[s] = S[s].z;
+            ab[s] = a.abar[(size_t)S[s].base * a.nw + w];
+        }
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] = 0.0;
+        const int npairs = n1 * (n1 + 1) / 2;
+        const float* coef = a.coef + a.coef_off[k] + (size_t)w * 2 * npairs;
         __syncthreads();
         for (int it = 0; it <= a.n_refine; ++it) {
-            for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-                double res[9];
-                for (int e = 0; e < 9; ++e) res[e] = L.Y[(3 * i + e / 3) * 3 + e % 3];
-                if (it > 0) {
-                    for (int e = 0; e < 9; ++e) res[e] -= L.X[(3 * i + e / 3) * 3 + e % 3] / L.ab[i];
-                    for (int j = 0; j < n1; ++j) {
+            if (it == 0) {
+                for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Yr[e] = R(Y[e]);
+            } else {
+                // partial products of the off-diagonal blocks, partner range split in kRes parts
+                for (int t = threadIdx.x; t < n1 * kRes; t += blockDim.x) {
+                    const int i = t % n1, part = t / n1;
+                    double acc[9] = {};
+                    for (int j = part; j < n1; j += kRes) {
                         if (j == i) continue;
                         const int pj = i > j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
-                        const double cA = L.coef[2 * pj], cB = L.coef[2 * pj + 1];
+                        const double cA = coef[2 * pj], cB = coef[2 * pj + 1];
                         if (cA == 0.0 && cB == 0.0) continue;
-                        const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+                        const double v[3] = {px[i] - px[j], py[i] - py[j], pz[i] - pz[j]};
                         const double ir = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                         const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
                         for (int c = 0; c < 3; ++c) {
-                            const double x0 = L.X[(3 * j + 0) * 3 + c], x1 = L.X[(3 * j + 1) * 3 + c],
-                                         x2 = L.X[(3 * j + 2) * 3 + c];
+                            const double x0 = X[(3 * j + 0) * 3 + c], x1 = X[(3 * j + 1) * 3 + c],
+                                         x2 = X[(3 * j + 2) * 3 + c];
                             const double rx = rh[0] * x0 + rh[1] * x1 + rh[2] * x2;
-                            res[0 * 3 + c] -= cA * rh[0] * rx + cB * x0;
-                            res[1 * 3 + c] -= cA * rh[1] * rx + cB * x1;
-                            res[2 * 3 + c] -= cA * rh[2] * rx + cB * x2;
+                            acc[0 * 3 + c] += cA * rh[0] * rx + cB * x0;
+                            acc[1 * 3 + c] += cA * rh[1] * rx + cB * x1;
+                            acc[2 * 3 + c] += cA * rh[2] * rx + cB * x2;
                         }
                     }
+                    for (int e = 0; e < 9; ++e) red[(size_t)(part * n1 + i) * 9 + e] = acc[e];
                 }
-                for (int e = 0; e < 9; ++e) Yr[(3 * i + e / 3) * 3 + e % 3] = R(res[e]);
+                __syncthreads();
+                for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+                    for (int e = 0; e < 9; ++e) {
+                        const int idx = (3 * i + e / 3) * 3 + e % 3;
+                        double r = Y[idx] - X[idx] / ab[i];
+                        for (int part = 0; part < kRes; ++part) r -= red[(size_t)(part * n1 + i) * 9 + e];
+                        Yr[idx] = R(r);
+                    }
+                }
             }
             __syncthreads();
             chol_solve3<R>(A, N, ld, Yr);
-            for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.X[e] += double(Yr[e]);
+            for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] += double(Yr[e]);
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.Y[e] = L.X[e];
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = X[e];
         __syncthreads();
     }
-    double* X = a.xsol + a.x_off[k] + (size_t)w * N * 3;
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] = L.Y[e];
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Xg[e] = Y[e];
     double* al = a.alpha_loc + a.aloc_off[k];
     for (int s = threadIdx.x; s < n1; s += blockDim.x)
-        al[(size_t)s * a.nw + w] = (L.Y[(3 * s) * 3 + 0] + L.Y[(3 * s + 1) * 3 + 1] + L.Y[(3 * s + 2) * 3 + 2]) / 3.0;
+        al[(size_t)s * a.nw + w] = (Y[(3 * s) * 3 + 0] + Y[(3 * s + 1) * 3 + 1] + Y[(3 * s + 2) * 3 + 2]) / 3.0;
+}
+
+size_t scs_solve_lds_bytes(int n1max, bool mixed) {
+    const size_t N = 3 * (size_t)n1max;
+    if (!mixed) return sizeof(double) * 3 * N;
+    return sizeof(double) * (9 * N + 4 * (size_t)n1max + 2 * 9 * (size_t)n1max);
 }
 
 // ---------------------------------------------------------------------------
@@ -524,7 +659,7 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
     const int ld = a.fac_ld[k];
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rc = SI.r_scs;
-    ScsLds L = scs_lds(lds, n1max, n2max, mixed);
+    ScsLds L = scs_lds(lds, n1max, n2max);
     const R* A = static_cast<const R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
     R* Yr = static_cast<R*>(L.Yr);
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
@@ -722,11 +857,17 @@ hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2ma
 }
 
 hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
-    const size_t lds = scs_lds_bytes(n1max, n2max, mixed);
-    if (mixed)
-        hipLaunchKernelGGL(k_scs_forward<float>, dim3(a.n, a.nw), dim3(256), lds, st, a, n1max, n2max);
-    else
-        hipLaunchKernelGGL(k_scs_forward<double>, dim3(a.n, a.nw), dim3(256), lds, st, a, n1max, n2max);
+    const dim3 grid(a.n, a.nw);
+    const size_t la = scs_assemble_lds_bytes(n1max, n2max), ls = scs_solve_lds_bytes(n1max, mixed);
+    if (mixed) {
+        hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(256), la, st, a, n1max, n2max);
+        hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(256), ls, st, a, n1max);
+    } else {
+        hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(256), la, st, a, n1max, n2max);
+        hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(256), ls, st, a, n1max);
+    }
     return hipGetLastError();
 }
 

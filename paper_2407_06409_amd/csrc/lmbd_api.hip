@@ -37,9 +37,9 @@ struct Plan {
     int64_t n_atoms = 0;
     int64_t total_sites = 0;
     int64_t table_len = 0;
-    int64_t fac_len = 0, x_len = 0, aloc_len = 0, work_len = 0;
+    int64_t fac_len = 0, x_len = 0, aloc_len = 0, work_len = 0, coef_len = 0;
     int n1max = 0, nkmax = 0, nallmax = 0, n2max = 0;
-    std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off;
+    std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off, coef_off;
     int64_t pl_len = 0;
     std::vector<int32_t> hash_cap, fac_ld;
 };
@@ -56,7 +56,7 @@ struct lmbd_context {
     DBuf site_off, sites, hash_off, hash_cap, table, rev;
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
-    DBuf pl_i, pl_q, pl_off, pl_seg;
+    DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off;
     DBuf e_out, f_out, a_out;
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
@@ -74,7 +74,7 @@ struct lmbd_context {
         &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
-        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off
 
 namespace {
 
@@ -250,7 +250,7 @@ int64_t next_pow2(int64_t x) {
     return p;
 }
 
-void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, Plan& P) {
+void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, bool mixed, Plan& P) {
     const int64_t n = (int64_t)cnt.size();
     P.n_atoms = n;
     P.site_off.resize(n + 1);
@@ -260,10 +260,11 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.aloc_off.resize(n + 1);
     P.work_off.resize(n + 1);
     P.pl_off.resize(n + 1);
+    P.coef_off.resize(n + 1);
     P.hash_cap.resize(n);
     P.fac_ld.resize(n);
     const int mmax = forces ? std::max(1, n_max - 1) : std::max(1, (n_max + 1) / 2);
-    int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0, po = 0;
+    int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0, po = 0, co = 0;
     P.n1max = P.nkmax = P.nallmax = P.n2max = 0;
     for (int64_t k = 0; k < n; ++k) {
         const Counts& c = cnt[k];
@@ -274,13 +275,15 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         P.aloc_off[k] = ao;
         P.work_off[k] = wo;
         P.pl_off[k] = po;
+        P.coef_off[k] = co;
         po += (int64_t)c.n1 * (c.n12 - c.n1);
+        if (mixed) co += (int64_t)nw * c.n1 * (c.n1 + 1);
         const int64_t N1 = 3 * (int64_t)c.n1, N3 = 3 * (int64_t)c.nK;
         P.hash_cap[k] = (int32_t)next_pow2(2 * (int64_t)c.n_all);
-        P.fac_ld[k] = (int32_t)N1;
+        P.fac_ld[k] = (int32_t)((N1 + 3) / 4 * 4);
         so += c.n_all;
         ho += P.hash_cap[k];
-        fo += (int64_t)nw * N1 * N1;
+        fo += (int64_t)nw * N1 * P.fac_ld[k];
         xo += (int64_t)nw * N1 * 3;
         ao += (int64_t)c.n1 * nw;
         wo += N3 * N3 + (int64_t)mmax * N3 * ncol + (forces ? (int64_t)n_max * N3 * ncol : 0);
@@ -297,6 +300,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.aloc_len = ao;
     P.work_len = wo;
     P.pl_len = po;
+    P.coef_len = co;
 }
 
 template <typename T>
@@ -346,7 +350,7 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
         {&c->alpha_loc, (size_t)P.aloc_len * D}, {&c->abar_loc, (size_t)P.aloc_len * D},
         {&c->abar_cen, N * nw * D}, {&c->work, (size_t)P.work_len * wsz}, {&c->e_out, N * D},
         {&c->a_out, N * D}, {&c->pl_i, (size_t)P.pl_len * I}, {&c->pl_q, (size_t)P.pl_len * I},
-        {&c->pl_seg, (TS + 2 * N) * I}};
+        {&c->pl_seg, (TS + 2 * N) * I}, {&c->coef_off, N * L8}, {&c->coef, (size_t)P.coef_len * sizeof(float)}};
     for (const auto& e : L) {
         const hipError_t r = get(*e.first, e.second);
         if (r != hipSuccess) return r;
@@ -591,7 +595,7 @@ lmbd_status layout_bytes(const lmbd_params* params, int n_species, const std::ve
     Measure m;
     (void)layout_pre(&layout, pd, m);
     Plan P;
-    build_plan(cnt, nw, 3 * params->n_freq, params->n_max, forces, P);
+    build_plan(cnt, nw, 3 * params->n_freq, params->n_max, forces, params->precision == LMBD_MIXED, P);
     (void)layout_post(&layout, P, nw, forces, params->precision == LMBD_MIXED ? sizeof(float) : sizeof(double), m);
     *bytes = m.total;
     return LMBD_OK;
@@ -783,7 +787,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
 
     // --- memory plan
     Plan P;
-    build_plan(cnt, nw, ncol, n_max, forces, P);
+    build_plan(cnt, nw, ncol, n_max, forces, mixed, P);
     if (P.n1max > kMaxN1 || P.nkmax > kMaxNK || P.nallmax > kMaxSites)
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
@@ -808,7 +812,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     std::vector<int64_t> ao(P.aloc_off.begin(), P.aloc_off.end() - 1);
     std::vector<int64_t> wo(P.work_off.begin(), P.work_off.end() - 1);
     std::vector<int64_t> plo(P.pl_off.begin(), P.pl_off.end() - 1);
+    std::vector<int64_t> coo(P.coef_off.begin(), P.coef_off.end() - 1);
     if ((st = upload(ctx, ctx->pl_off, plo, stream)) != LMBD_OK) return st;
+    if ((st = upload(ctx, ctx->coef_off, coo, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->site_off, so, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->hash_off, ho, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->hash_cap, P.hash_cap, stream)) != LMBD_OK) return st;
@@ -847,6 +853,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.n_refine = 2;
     sa.fac_off = as<int64_t>(ctx->fac_off);
     sa.fac_ld = as<int32_t>(ctx->fac_ld);
+    sa.coef = mixed ? as<float>(ctx->coef) : nullptr;
+    sa.coef_off = as<int64_t>(ctx->coef_off);
     sa.xsol = as<double>(ctx->xsol);
     sa.x_off = as<int64_t>(ctx->x_off);
     sa.alpha_loc = as<double>(ctx->alpha_loc);

@@ -163,9 +163,12 @@ struct ScsArgs {
     const int32_t* atom_struct;
     const StructInfo* sinfo;
     double beta, damp_d, r_buf, r_inner;   // bohr
-    void* fac;               // factor slots (double or float): per atom nw * ld * N, column-major lower
+    void* fac;               // factor slots (double or float): per atom nw * N * ld, row-major lower,
+                             // inverses of the 16x16 diagonal blocks in their strict upper parts
     const int64_t* fac_off;
-    const int32_t* fac_ld;
+    const int32_t* fac_ld;   // ld >= N, a multiple of 4
+    float* coef;             // mixed path: FP32 pair coefficients (A, B) of B~, per atom nw * n1 (n1 + 1) / 2 pairs
+    const int64_t* coef_off; // per atom, in floats
     double* xsol;            // per atom nw * N * 3 (row-major)
     const int64_t* x_off;
     double* alpha_loc;       // per atom n1 * nw
