@@ -73,12 +73,14 @@ template <> struct MfmaW<float> {
     static __device__ inline int acc_row(int g, int q) { return 4 * g + q; }
 };
 
-// Workgroup GEMM on the matrix cores: out(m, n) = sum_k A(m, k) B(k, n).  Each
-// wavefront takes a 16-row strip times up to four 16-column tiles (sharing the A
-// operand) and runs the k loop in steps of 4 with one MFMA per column tile.
-// Loaders are called only inside the bounds; padding is zero.
-template <typename W, typename LA, typename LB, typename ST>
-__device__ void mfma_gemm(int M, int N, int K, LA la, LB lb, ST st) {
+// Workgroup GEMM on the matrix cores: out(m, n) = sum_k AT[k][m] B[k][n], both
+// operands K-major (lda, ldb), so the 16 lanes of an MFMA operand read 16
+// consecutive elements.  Each wavefront takes a 16-row strip times up to four
+// 16-column tiles (sharing the A operand); the k loop advances 16 at a time with
+// the next 16 in flight.  Out-of-range rows, columns and k are zero.
+template <typename W, typename ST>
+__device__ __forceinline__ void mfma_gemm(int M, int N, int K, const W* __restrict__ AT, int lda,
+                                          const W* __restrict__ B, int ldb, ST st) {
     typedef MfmaW<W> Mf;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -88,33 +90,53 @@ __device__ void mfma_gemm(int M, int N, int K, LA la, LB lb, ST st) {
     for (int t = wave; t < mt * ng; t += nwave) {
         const int m0 = (t / ng) * 16;
         const int tc0 = (t % ng) * 4;
-        const int ntc = min(4, nt - tc0);
         typename Mf::acc acc[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[c][q] = W(0);
         const int am = m0 + li;
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            const int kk = k0 + lk;
-            const W a = (am < M && kk < K) ? la(am, kk) : W(0);
+        int bn[4];
+        bool bok[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c < ntc) {
-                    const int bn = (tc0 + c) * 16 + li;
-                    const W b = (bn < N && kk < K) ? lb(kk, bn) : W(0);
-                    acc[c] = Mf::mma(a, b, acc[c]);
-                }
+        for (int c = 0; c < 4; ++c) {
+            bn[c] = (tc0 + c) * 16 + li;
+            bok[c] = bn[c] < N && tc0 + c < nt;
+        }
+        const bool aok = am < M;
+        // one 16-k chunk: four MFMA k-steps, lane k index lk + 4 s
+        W a[4], b[4][4], na[4], nb[4][4];
+        auto load = [&](int k0, W* xa, W (*xb)[4]) {
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int kk = k0 + lk + 4 * s2;
+                const bool kok = kk < K;
+                xa[s2] = (aok && kok) ? AT[(size_t)kk * lda + am] : W(0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xb[c][s2] = (bok[c] && kok) ? B[(size_t)kk * ldb + bn[c]] : W(0);
+            }
+        };
+        load(0, a, b);
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            load(k0 + 16, na, nb);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = Mf::mma(a[s2], b[c][s2], acc[c]);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                a[s2] = na[s2];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) b[c][s2] = nb[c][s2];
             }
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            if (c < ntc) {
-                const int n = (tc0 + c) * 16 + li;
+            if (bok[c]) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int m = m0 + Mf::acc_row(lk, q);
-                    if (m < M && n < N) st(m, n, acc[c][q]);
+                    if (m < M) st(m, bn[c], acc[c][q]);
                 }
             }
         }
@@ -163,7 +185,9 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     const double* aloc = a.alpha_loc + a.aloc_off[k];
     W* T = static_cast<W*>(a.work) + a.work_off[k];
     W* U = T + (size_t)N3 * N3;                              // u_1 .. u_mmax
-    W* Z = U + (size_t)a.mmax * N3 * ncol;                   // Z_0 .. Z_{n_max-1}
+    W* V = U + (size_t)a.mmax * N3 * ncol;                   // D u_m, the next product's operand
+    W* PT = V + (size_t)N3 * ncol;                           // (D u_a)^T, a = 0 .. n_max-1 (K-major)
+    W* QT = PT + (size_t)a.n_max * ncol * N3;                // (W D Z_a)^T
     auto Uat = [&](int m) { return U + (size_t)(m - 1) * N3 * ncol; };
 
     // --- blend (Sec. III.B, central/local combination) and SCS radii
@@ -216,22 +240,28 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
 
-    // --- u_1 = D T D e_k
+    // --- u_1 = D T D e_k, V = D u_1
     W* U1 = Uat(1);
     for (int e = tid; e < N3 * ncol; e += blockDim.x) {
         const int row = e / ncol, col = e % ncol;
         const int q = col / 3, c = col % 3;
-        U1[e] = W(L.sqa[(size_t)(row / 3) * nq + q] * double(T[(size_t)row * N3 + c]) * L.sqa[q]);
+        const double sq = L.sqa[(size_t)(row / 3) * nq + q];
+        const double u = sq * double(T[(size_t)row * N3 + c]) * L.sqa[q];
+        U1[e] = W(u);
+        V[e] = W(sq * u);
     }
     __syncthreads();
-    // --- u_{m+1} = D T (D u_m)  (T symmetric: its column k is read as row k, coalesced)
+    // --- u_{m+1} = D (T V), V = D u_{m+1}  (T symmetric, so it is its own K-major operand)
     for (int m = 1; m < a.mmax; ++m) {
-        const W* Um = Uat(m);
         W* Un = Uat(m + 1);
-        mfma_gemm<W>(
-            N3, ncol, N3, [&](int r, int l) { return T[(size_t)l * N3 + r]; },
-            [&](int l, int col) { return W(L.sqa[(size_t)(l / 3) * nq + col / 3]) * Um[(size_t)l * ncol + col]; },
-            [&](int r, int col, W v) { Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v; });
+        mfma_gemm<W>(N3, ncol, N3, T, N3, V, ncol, [&](int r, int col, W v) {
+            Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v;
+        });
+        for (int e = tid; e < N3 * ncol; e += blockDim.x) {
+            const int row = e / ncol, col = e % ncol;
+            V[e] = W(L.sqa[(size_t)(row / 3) * nq + col / 3]) * Un[e];
+        }
+        __syncthreads();
     }
 
     // --- moments mu_n(q) = <u_a, u_b>, a + b = n
@@ -282,33 +312,23 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
         }
         L.ab[t] = v;
     }
-    // --- Z_a = sum_b c_{a+b+1} u_b (u_0 = e_k)
-    for (int e = tid; e < n_max * N3 * ncol; e += blockDim.x) {
-        const int aa = e / (N3 * ncol);
-        const int rem = e % (N3 * ncol);
-        const int row = rem / ncol, col = rem % ncol;
-        double s = (aa >= 1 && row == col % 3) ? a.coef[aa + 1] : 0.0;   // b = 0 term (u_0 = e_k)
-        for (int b = 1; b <= n_max - 1 - aa; ++b) s += a.coef[aa + b + 1] * double(Uat(b)[(size_t)row * ncol + col]);
-        Z[e] = W(s);
+    // --- K-major operands of Tbar = sum_a (D u_a)(W D Z_a)^T, Z_a = sum_b c_{a+b+1} u_b
+    // (u_0 = e_k): PT[a ncol + col][r] = sqrt(alpha~_r) u_a[r][col] and
+    // QT[a ncol + col][s] = w_k W_q sqrt(alpha~_s) Z_a[s][col]
+    const int KK = n_max * ncol;
+    for (int e = tid; e < KK * N3; e += blockDim.x) {
+        const int kk = e / N3, r = e % N3;
+        const int aa = kk / ncol, col = kk % ncol, q = col / 3;
+        const double sq = L.sqa[(size_t)(r / 3) * nq + q];
+        const double u = (aa == 0) ? ((r == col % 3) ? 1.0 : 0.0) : double(Uat(aa)[(size_t)r * ncol + col]);
+        double z = (aa >= 1 && r == col % 3) ? a.coef[aa + 1] : 0.0;   // b = 0 term (u_0 = e_k)
+        for (int b = 1; b <= n_max - 1 - aa; ++b) z += a.coef[aa + b + 1] * double(Uat(b)[(size_t)r * ncol + col]);
+        PT[e] = W(sq * u);
+        QT[e] = W(wk * a.wq[q] * sq * z);
     }
     __syncthreads();
-    // --- Tbar = sum_a (D u_a)(W D Z_a)^T  (overwrites T)
-    const int KK = n_max * ncol;
-    mfma_gemm<W>(
-        N3, N3, KK,
-        [&](int r, int kk) {
-            const int aa = kk / ncol, col = kk % ncol;
-            W u;
-            if (aa == 0) u = (r == col % 3) ? W(1) : W(0);
-            else u = Uat(aa)[(size_t)r * ncol + col];
-            return W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * u;
-        },
-        [&](int kk, int s) {
-            const int aa = kk / ncol, col = kk % ncol;
-            return W(wk * a.wq[col / 3] * L.sqa[(size_t)(s / 3) * nq + col / 3]) *
-                   Z[(size_t)aa * N3 * ncol + (size_t)s * ncol + col];
-        },
-        [&](int r, int s, W v) { T[(size_t)r * N3 + s] = v; });
+    // --- Tbar (overwrites T)
+    mfma_gemm<W>(N3, N3, KK, PT, N3, QT, N3, [&](int r, int s, W v) { T[(size_t)r * N3 + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));

@@ -96,14 +96,26 @@ __device__ inline void inner_buffer(double r, double rin, double& fin, double& d
 //      from two aligned 4-vector loads per lane.  When the panel has fewer row
 //      tiles than there are wavefronts the k range is split and the partial
 //      tiles go to LDS; otherwise each unit adds into the matrix in place;
-//  (2) diagonal block: wavefront 0 factorises it with lane shuffles (lane l
-//      holds row l), keeps L_pp and 1/L_ii in LDS;
+//  (2) diagonal block: wavefront 0 factorises it (lane l holds row l, values
+//      of other rows are broadcast with lane reads), keeps L_pp and 1/L_ii in
+//      LDS, and inverts it into the block's strict upper part;
 //  (3) rows below: one row per thread solves x L_pp^T = a by substitution.
-// Then every wavefront inverts some of the diagonal blocks.  LDS use is a few
+// LDS use is a few
 // kilobytes, independent of N, so several factorisations share a compute unit
 // and hide each other's memory latency.
 // ---------------------------------------------------------------------------
 constexpr int kSlotLd = 17;   // row stride of a 16x16 tile in LDS (padding against bank conflicts)
+
+// value of x in lane `lane` (a wavefront-uniform constant) for every lane
+__device__ __forceinline__ double bcast(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float bcast(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
 
 template <typename R> struct Vec4T;
 template <> struct Vec4T<double> { typedef d4_t type; };
@@ -117,7 +129,7 @@ __device__ inline typename Vec4T<R>::type load4(const R* p) {
 constexpr int kMaxSplitSlots = 4;  // partial tiles of a split-K panel update (one per wavefront)
 
 template <typename R>
-__device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ slots, R* __restrict__ Ld,
+__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ slots, R* __restrict__ Ld,
                             R* __restrict__ rinv, bool& ok) {
     typedef Mfma<R> M;
     typedef typename Vec4T<R>::type V4;
@@ -145,22 +157,19 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ sl
             typename M::acc acc0, acc1;
             for (int q = 0; q < 4; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
             const V4 zero = {R(0), R(0), R(0), R(0)};
-            int ch = s;
-            for (; ch + S < p; ch += 2 * S) {
-                const V4 a0 = aok ? load4(pa + NB * ch) : zero;
-                const V4 b0 = bok ? load4(pb + NB * ch) : zero;
-                const V4 a1 = aok ? load4(pa + NB * (ch + S)) : zero;
-                const V4 b1 = bok ? load4(pb + NB * (ch + S)) : zero;
+            // chunks s, s + S, ... < p, two per step, the next step's loads in
+            // flight while the current one is on the matrix cores
+            auto ld_a = [&](int c) { return (aok && c < p) ? load4(pa + NB * c) : zero; };
+            auto ld_b = [&](int c) { return (bok && c < p) ? load4(pb + NB * c) : zero; };
+            V4 a0 = ld_a(s), b0 = ld_b(s), a1 = ld_a(s + S), b1 = ld_b(s + S);
+            for (int ch = s; ch < p; ch += 2 * S) {
+                const V4 na0 = ld_a(ch + 2 * S), nb0 = ld_b(ch + 2 * S);
+                const V4 na1 = ld_a(ch + 3 * S), nb1 = ld_b(ch + 3 * S);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], b1[e], acc1);
-            }
-            if (ch < p) {
-                const V4 a0 = aok ? load4(pa + NB * ch) : zero;
-                const V4 b0 = bok ? load4(pb + NB * ch) : zero;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
+                a0 = na0; b0 = nb0; a1 = na1; b1 = nb1;
             }
             if (S == 1) {
                 const int col = c0 + li;
@@ -194,7 +203,7 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ sl
             }
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                const R dcc = __shfl(row[c], c, 64);
+                const R dcc = bcast(row[c], c);
                 if (c < jb && !(dcc > R(0))) good = false;
                 const R sq = m_sqrt(dcc);
                 const R inv = R(1) / sq;
@@ -202,7 +211,7 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ sl
                 else if (l > c) row[c] *= inv;
 #pragma unroll
                 for (int s = c + 1; s < NB; ++s) {
-                    const R lsc = __shfl(row[c], s, 64);
+                    const R lsc = bcast(row[c], s);  // L[s][c]
                     if (l >= s) row[s] -= row[c] * lsc;
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -210,12 +219,29 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ sl
             if (l < NB) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c) Ld[l * kSlotLd + c] = (c <= l) ? row[c] : R(0);
-                rinv[l] = R(1) / row[l];
+                rinv[l] = R(1) / Ld[l * kSlotLd + l];
             }
             if (l < jb) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
                     if (c <= l) A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
+            }
+            // Z = L_pp^{-1}, lane j < 16 holds column j (forward substitution with
+            // the rows of L broadcast from their lanes); Z[q][j] (q > j) is stored
+            // at (c0 + j, c0 + q)
+            R z[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                R v = (q == l) ? R(1) : R(0);
+#pragma unroll
+                for (int r = 0; r < q; ++r) v -= bcast(row[r], q) * z[r];
+                z[q] = v / bcast(row[q], q);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (l < jb) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (q > l && q < jb) A[(size_t)(c0 + l) * ld + c0 + q] = z[q];
             }
         }
         __syncthreads();
@@ -253,33 +279,6 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ sl
         }
         __syncthreads();
     }
-    // inverses of the diagonal blocks: lane j < jb computes column j of Z = L_bb^{-1}
-    // by forward substitution and stores Z[q][j] (q > j) at (c0 + j, c0 + q)
-    for (int b = wave; b < nt; b += nwave) {
-        const int c0 = b * NB;
-        const int jb = min(NB, N - c0);
-        const int j = li;
-        if (lk == 0 && j < jb) {
-            R z[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (q < j || q >= jb) {
-                    z[q] = R(0);
-                    continue;
-                }
-                const R* lrow = A + (size_t)(c0 + q) * ld + c0;
-                R v = (q == j) ? R(1) : R(0);
-#pragma unroll
-                for (int r = 0; r < q; ++r) v -= lrow[r] * z[r];
-                z[q] = v / lrow[q];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            R* urow = A + (size_t)(c0 + j) * ld + c0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q > j && q < jb) urow[q] = z[q];
-        }
-    }
     __syncthreads();
     ok = good;
 }
@@ -287,66 +286,118 @@ __device__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ sl
 // Solve L L^T Y = Y in place for 3 right-hand sides (Y in LDS, row-major N x 3),
 // with the stored inverses of the diagonal blocks.  Per block: the 48 block
 // values are products with Z (threads r + 16 c of wavefront 0), then every
-// other row takes the block's contribution, one row per thread.
+// other row takes the block's contribution, one row per thread.  Each thread's
+// first row is loaded one block ahead (best with blockDim >= N).
 template <typename R>
-__device__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y) {
+__device__ __forceinline__ void solve_row_update(const R* __restrict__ lrow, int c0, int jb, int i, R* Y) {
+    R s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (q < jb) {  // rows past N hold no solution values
+            s0 += lrow[q] * Y[(c0 + q) * 3 + 0];
+            s1 += lrow[q] * Y[(c0 + q) * 3 + 1];
+            s2 += lrow[q] * Y[(c0 + q) * 3 + 2];
+        }
+    }
+    Y[i * 3 + 0] -= s0;
+    Y[i * 3 + 1] -= s1;
+    Y[i * 3 + 2] -= s2;
+}
+
+template <typename R, bool kOneRow>
+__device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y) {
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int nt = (N + NB - 1) / NB;
     const int r = tid & 15, c = tid >> 4;
-    for (int p = 0; p < nt; ++p) {  // forward: L y = b
+    const bool blk = tid < 48;   // threads of the block step (wavefront 0)
+    const V4 zero = {R(0), R(0), R(0), R(0)};
+    // forward: L y = b.  With one row per thread (blockDim >= N) the row's
+    // segment of the next block is loaded a block ahead.
+    R cur[NB], nxt[NB];
+    if (kOneRow) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const V4 t4 = (tid >= NB && tid < N) ? load4(A + (size_t)tid * ld + 4 * v) : zero;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cur[4 * v + e] = t4[e];
+        }
+    }
+    for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        if (tid < 48 && r < jb) {
+        if (kOneRow) {
+            const bool pre = tid >= c0 + 2 * NB && tid < N;   // row tid follows block p + 1
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const V4 t4 = pre ? load4(A + (size_t)tid * ld + c0 + NB + 4 * v) : zero;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
+            }
+        }
+        if (blk && r < jb) {
             R v = Y[(c0 + r) * 3 + c] / A[(size_t)(c0 + r) * ld + c0 + r];
             for (int q = 0; q < r; ++q) v += A[(size_t)(c0 + q) * ld + c0 + r] * Y[(c0 + q) * 3 + c];
             Y[(c0 + r) * 3 + c] = v;  // one wavefront: all reads of the block precede this write
         }
         __syncthreads();
-        for (int i = c0 + jb + tid; i < N; i += nthr) {
-            const R* lr = A + (size_t)i * ld + c0;  // jb = 16 whenever rows follow the block
-            R s0 = 0, s1 = 0, s2 = 0;
+        if (kOneRow) {
+            if (tid >= c0 + NB && tid < N) solve_row_update(cur, c0, NB, tid, Y);  // jb = 16 when rows follow
+        } else {
+            for (int i = c0 + NB + tid; i < N; i += nthr) {
+                R l[NB];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const V4 l4 = load4(lr + 4 * v);
+                for (int v = 0; v < 4; ++v) {
+                    const V4 t4 = load4(A + (size_t)i * ld + c0 + 4 * v);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int q = 4 * v + e;
-                    s0 += l4[e] * Y[(c0 + q) * 3 + 0];
-                    s1 += l4[e] * Y[(c0 + q) * 3 + 1];
-                    s2 += l4[e] * Y[(c0 + q) * 3 + 2];
+                    for (int e = 0; e < 4; ++e) l[4 * v + e] = t4[e];
                 }
+                solve_row_update(l, c0, NB, i, Y);
             }
-            Y[i * 3 + 0] -= s0;
-            Y[i * 3 + 1] -= s1;
-            Y[i * 3 + 2] -= s2;
         }
         __syncthreads();
+        if (kOneRow) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
+        }
     }
-    for (int p = nt - 1; p >= 0; --p) {  // backward: L^T x = y
+    // backward: L^T x = y; with one row per thread, column tid's segment of the
+    // previous block is loaded a block ahead
+    if (kOneRow) {
+        const int c0 = (nt - 1) * NB, jb = N - c0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) cur[q] = (tid < c0 && q < jb) ? A[(size_t)(c0 + q) * ld + tid] : R(0);
+    }
+    for (int p = nt - 1; p >= 0; --p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        if (tid < 48 && r < jb) {
+        if (kOneRow) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) nxt[q] = (p > 0 && tid < c0 - NB) ? A[(size_t)(c0 - NB + q) * ld + tid] : R(0);
+        }
+        if (blk && r < jb) {
             const R* zrow = A + (size_t)(c0 + r) * ld + c0;
             R v = Y[(c0 + r) * 3 + c] / zrow[r];
             for (int q = r + 1; q < jb; ++q) v += zrow[q] * Y[(c0 + q) * 3 + c];
             Y[(c0 + r) * 3 + c] = v;
         }
         __syncthreads();
-        for (int i = tid; i < c0; i += nthr) {
-            R s0 = 0, s1 = 0, s2 = 0;
-            for (int q = 0; q < jb; ++q) {  // rows past N hold no solution values
-                const R l = A[(size_t)(c0 + q) * ld + i];
-                s0 += l * Y[(c0 + q) * 3 + 0];
-                s1 += l * Y[(c0 + q) * 3 + 1];
-                s2 += l * Y[(c0 + q) * 3 + 2];
+        if (kOneRow) {
+            if (tid < c0) solve_row_update(cur, c0, jb, tid, Y);
+        } else {
+            for (int i = tid; i < c0; i += nthr) {
+                R l[NB];
+#pragma unroll
+                for (int q = 0; q < NB; ++q) l[q] = (q < jb) ? A[(size_t)(c0 + q) * ld + i] : R(0);
+                solve_row_update(l, c0, jb, i, Y);
             }
-            Y[i * 3 + 0] -= s0;
-            Y[i * 3 + 1] -= s1;
-            Y[i * 3 + 2] -= s2;
         }
         __syncthreads();
+        if (kOneRow) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
+        }
     }
 }
 
@@ -544,7 +595,7 @@ __global__ void __launch_bounds__(256) k_scs_factor(ScsArgs a) {
 // coefficients; FP32 solve of r; X += correction }.  Writes X over d and the
 // local isotropic polarisabilities Tr(X_i) / 3.
 template <typename R>
-__global__ void __launch_bounds__(256) k_scs_solve(ScsArgs a, int n1max) {
+__global__ void __launch_bounds__(sizeof(R) == 8 ? 512 : 256) k_scs_solve(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
     constexpr bool mixed = sizeof(R) == 4;
     constexpr int kRes = 2;  // partner-range splits of the residual
@@ -560,7 +611,7 @@ __global__ void __launch_bounds__(256) k_scs_solve(ScsArgs a, int n1max) {
     for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = Xg[e];
     __syncthreads();
     if (!mixed) {
-        chol_solve3<double>(reinterpret_cast<const double*>(A), N, ld, Y);
+        chol_solve3<double, true>(reinterpret_cast<const double*>(A), N, ld, Y);
     } else {
         double* X = Y + 3 * Nmax;
         R* Yr = reinterpret_cast<R*>(X + 3 * Nmax);
@@ -618,7 +669,7 @@ __global__ void __launch_bounds__(256) k_scs_solve(ScsArgs a, int n1max) {
                 }
             }
             __syncthreads();
-            chol_solve3<R>(A, N, ld, Yr);
+            chol_solve3<R, false>(A, N, ld, Yr);
             for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] += double(Yr[e]);
             __syncthreads();
         }
@@ -673,7 +724,7 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
     }
     for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.X[e] = Xg[e];
     __syncthreads();
-    chol_solve3<R>(A, N, ld, Yr);  // lambda
+    chol_solve3<R, false>(A, N, ld, Yr);  // lambda
     for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.Y[e] = double(Yr[e]);
     __syncthreads();
 
@@ -866,7 +917,7 @@ hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n
     } else {
         hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(256), la, st, a, n1max, n2max);
         hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), 0, st, a);
-        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(256), ls, st, a, n1max);
+        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max);
     }
     return hipGetLastError();
 }

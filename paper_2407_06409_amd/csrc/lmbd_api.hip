@@ -286,7 +286,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         fo += (int64_t)nw * N1 * P.fac_ld[k];
         xo += (int64_t)nw * N1 * 3;
         ao += (int64_t)c.n1 * nw;
-        wo += N3 * N3 + (int64_t)mmax * N3 * ncol + (forces ? (int64_t)n_max * N3 * ncol : 0);
+        wo += N3 * N3 + (int64_t)(mmax + 1) * N3 * ncol + (forces ? 2 * (int64_t)n_max * N3 * ncol : 0);
         P.n1max = std::max(P.n1max, c.n1);
         P.nkmax = std::max(P.nkmax, c.nK);
         P.nallmax = std::max(P.nallmax, c.n_all);
@@ -850,7 +850,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.r_buf = params->r_buf / kBohr;
     sa.r_inner = params->r_inner / kBohr;
     sa.fac = ctx->fac.p;
-    sa.n_refine = 2;
+    sa.n_refine = 1;
     sa.fac_off = as<int64_t>(ctx->fac_off);
     sa.fac_ld = as<int32_t>(ctx->fac_ld);
     sa.coef = mixed ? as<float>(ctx->coef) : nullptr;

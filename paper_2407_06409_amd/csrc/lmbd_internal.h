@@ -204,7 +204,8 @@ struct MbdArgs {
     double wq[kMaxFreq];       // quadrature weight * Hartree / (2 pi): eV per unit integrand
     const double* e_weight;    // [n] or null
     double* e_atom;            // [n]
-    void* work;                // per atom T (N3^2), U (mmax N3 ncol), Z (n_max N3 ncol): double or float
+    void* work;                // per atom T (N3^2), U (mmax N3 ncol), V (N3 ncol), with forces P^T and
+                               // Q^T (n_max ncol x N3 each): double or float
     const int64_t* work_off;
     int forces;
     double* abar_loc;          // per atom n1 * nw (aloc_off)
