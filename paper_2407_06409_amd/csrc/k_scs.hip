@@ -283,11 +283,12 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     ok = good;
 }
 
-// Solve L L^T Y = Y in place for 3 right-hand sides (Y in LDS, row-major N x 3),
-// with the stored inverses of the diagonal blocks.  Per block: the 48 block
-// values are products with Z (threads r + 16 c of wavefront 0), then every
-// other row takes the block's contribution, one row per thread.  Each thread's
-// first row is loaded one block ahead (best with blockDim >= N).
+// Solve L L^T Y = Y in place for 3 right-hand sides (Y in LDS, row-major N x 3,
+// blockDim >= N), with the stored inverses of the diagonal blocks.  Per block:
+// the 48 block values are products with Z (threads r + 16 c of wavefront 0,
+// Z staged in LDS by wavefront 1 a block ahead), then every other row takes the
+// block's contribution, one row per thread, its segment loaded a block ahead.
+// Apart from the first block, no step waits on device memory.
 template <typename R>
 __device__ __forceinline__ void solve_row_update(const R* __restrict__ lrow, int c0, int jb, int i, R* Y) {
     R s0 = 0, s1 = 0, s2 = 0;
@@ -304,100 +305,112 @@ __device__ __forceinline__ void solve_row_update(const R* __restrict__ lrow, int
     Y[i * 3 + 2] -= s2;
 }
 
-template <typename R, bool kOneRow>
-__device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y) {
+template <typename R>
+__device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y, R* zbuf) {
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int nt = (N + NB - 1) / NB;
     const int r = tid & 15, c = tid >> 4;
     const bool blk = tid < 48;   // threads of the block step (wavefront 0)
     const V4 zero = {R(0), R(0), R(0), R(0)};
-    // forward: L y = b.  With one row per thread (blockDim >= N) the row's
-    // segment of the next block is loaded a block ahead.
-    R cur[NB], nxt[NB];
-    if (kOneRow) {
+    constexpr int kZ = NB * NB / 64;   // staged block entries per lane of wavefront 1
+    // block-step operators, staged by wavefront 1 into LDS one block ahead:
+    // forward Z[r][q] (q <= r), backward Z^T[r][q] = Z[q][r] (q >= r); Z[r][r] = 1 / L[r][r]
+    auto zload = [&](int p, bool fwd, R* zr) {
+        const int c0 = p * NB;
+        const int jb = (p >= 0 && p < nt) ? min(NB, N - c0) : 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const V4 t4 = (tid >= NB && tid < N) ? load4(A + (size_t)tid * ld + 4 * v) : zero;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) cur[4 * v + e] = t4[e];
+        for (int t = 0; t < kZ; ++t) {
+            const int e = lane + 64 * t, rr = e / NB, q = e % NB;
+            R v = R(0);
+            if (wave == 1 && rr < jb && q < jb) {
+                if (q == rr) v = A[(size_t)(c0 + rr) * ld + c0 + rr];
+                else if (fwd && q < rr) v = A[(size_t)(c0 + q) * ld + c0 + rr];
+                else if (!fwd && q > rr) v = A[(size_t)(c0 + rr) * ld + c0 + q];
+            }
+            zr[t] = v;
         }
+    };
+    auto zstore = [&](R* zb, const R* zr) {
+        if (wave == 1) {
+#pragma unroll
+            for (int t = 0; t < kZ; ++t) {
+                const int e = lane + 64 * t, rr = e / NB, q = e % NB;
+                zb[rr * kSlotLd + q] = (q == rr && zr[t] != R(0)) ? R(1) / zr[t] : zr[t];
+            }
+        }
+    };
+    R zr[kZ];
+    // forward: L y = b, one row per thread (blockDim >= N); the row's segment of
+    // the next block is loaded a block ahead
+    R cur[NB], nxt[NB];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const V4 t4 = (tid >= NB && tid < N) ? load4(A + (size_t)tid * ld + 4 * v) : zero;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cur[4 * v + e] = t4[e];
     }
+    zload(0, true, zr);
+    zstore(zbuf, zr);
+    zload(1, true, zr);
+    __syncthreads();
     for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        if (kOneRow) {
-            const bool pre = tid >= c0 + 2 * NB && tid < N;   // row tid follows block p + 1
+        R* zb = zbuf + (p & 1) * NB * kSlotLd;
+        zstore(zbuf + ((p + 1) & 1) * NB * kSlotLd, zr);   // block p + 1 (loaded during block p - 1)
+        zload(p + 2, true, zr);
+        const bool pre = tid >= c0 + 2 * NB && tid < N;      // row tid follows block p + 1
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const V4 t4 = pre ? load4(A + (size_t)tid * ld + c0 + NB + 4 * v) : zero;
+        for (int v = 0; v < 4; ++v) {
+            const V4 t4 = pre ? load4(A + (size_t)tid * ld + c0 + NB + 4 * v) : zero;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
-            }
+            for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
         }
         if (blk && r < jb) {
-            R v = Y[(c0 + r) * 3 + c] / A[(size_t)(c0 + r) * ld + c0 + r];
-            for (int q = 0; q < r; ++q) v += A[(size_t)(c0 + q) * ld + c0 + r] * Y[(c0 + q) * 3 + c];
+            R v = 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < jb) v += zb[r * kSlotLd + q] * Y[(c0 + q) * 3 + c];  // rows past N hold no values
             Y[(c0 + r) * 3 + c] = v;  // one wavefront: all reads of the block precede this write
         }
         __syncthreads();
-        if (kOneRow) {
-            if (tid >= c0 + NB && tid < N) solve_row_update(cur, c0, NB, tid, Y);  // jb = 16 when rows follow
-        } else {
-            for (int i = c0 + NB + tid; i < N; i += nthr) {
-                R l[NB];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const V4 t4 = load4(A + (size_t)i * ld + c0 + 4 * v);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) l[4 * v + e] = t4[e];
-                }
-                solve_row_update(l, c0, NB, i, Y);
-            }
-        }
+        if (tid >= c0 + NB && tid < N) solve_row_update(cur, c0, NB, tid, Y);  // jb = 16 when rows follow
         __syncthreads();
-        if (kOneRow) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
-        }
+        for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
     }
-    // backward: L^T x = y; with one row per thread, column tid's segment of the
-    // previous block is loaded a block ahead
-    if (kOneRow) {
+    // backward: L^T x = y; column tid's segment of the previous block is loaded a block ahead
+    {
         const int c0 = (nt - 1) * NB, jb = N - c0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) cur[q] = (tid < c0 && q < jb) ? A[(size_t)(c0 + q) * ld + tid] : R(0);
     }
+    zload(nt - 1, false, zr);
+    zstore(zbuf + ((nt - 1) & 1) * NB * kSlotLd, zr);
+    zload(nt - 2, false, zr);
+    __syncthreads();
     for (int p = nt - 1; p >= 0; --p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        if (kOneRow) {
+        R* zb = zbuf + (p & 1) * NB * kSlotLd;
+        zstore(zbuf + ((p + 1) & 1) * NB * kSlotLd, zr);   // block p - 1
+        zload(p - 2, false, zr);
 #pragma unroll
-            for (int q = 0; q < NB; ++q) nxt[q] = (p > 0 && tid < c0 - NB) ? A[(size_t)(c0 - NB + q) * ld + tid] : R(0);
-        }
+        for (int q = 0; q < NB; ++q) nxt[q] = (p > 0 && tid < c0 - NB) ? A[(size_t)(c0 - NB + q) * ld + tid] : R(0);
         if (blk && r < jb) {
-            const R* zrow = A + (size_t)(c0 + r) * ld + c0;
-            R v = Y[(c0 + r) * 3 + c] / zrow[r];
-            for (int q = r + 1; q < jb; ++q) v += zrow[q] * Y[(c0 + q) * 3 + c];
+            R v = 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < jb) v += zb[r * kSlotLd + q] * Y[(c0 + q) * 3 + c];  // rows past N hold no values
             Y[(c0 + r) * 3 + c] = v;
         }
         __syncthreads();
-        if (kOneRow) {
-            if (tid < c0) solve_row_update(cur, c0, jb, tid, Y);
-        } else {
-            for (int i = tid; i < c0; i += nthr) {
-                R l[NB];
-#pragma unroll
-                for (int q = 0; q < NB; ++q) l[q] = (q < jb) ? A[(size_t)(c0 + q) * ld + i] : R(0);
-                solve_row_update(l, c0, jb, i, Y);
-            }
-        }
+        if (tid < c0) solve_row_update(cur, c0, jb, tid, Y);
         __syncthreads();
-        if (kOneRow) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
-        }
+        for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
     }
 }
 
@@ -522,7 +535,7 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
     const double rc = a.sinfo[a.atom_struct[k]].r_scs;
     ScsLds L = scs_assemble_lds(lds, n1max, n2max);
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
-    double* D = a.xsol + a.x_off[k] + (size_t)w * N * 3;
+    double* D = (mixed ? a.dvec : a.xsol) + a.x_off[k] + (size_t)w * N * 3;
     const int npairs = n1 * (n1 + 1) / 2;
     float* coef = mixed ? a.coef + a.coef_off[k] + (size_t)w * 2 * npairs : nullptr;
     load_sites(a, k, w, n1, n12, L);
@@ -590,103 +603,119 @@ __global__ void __launch_bounds__(256) k_scs_factor(ScsArgs a) {
     }
 }
 
-// Solve B~ X = d.  FP64: two triangular solves.  Mixed: X = 0, then repeat
-// { residual r = d - B~ X in FP64 with B~ rebuilt from its FP32 pair
-// coefficients; FP32 solve of r; X += correction }.  Writes X over d and the
-// local isotropic polarisabilities Tr(X_i) / 3.
+// Triangular solves with the stored factor, one workgroup of >= N threads per
+// (atom, frequency).  Right-hand side and result by mode:
+//   kSolveD      : d (solution slot) -> X (solution slot) and Tr(X_i)/3      [FP64]
+//   kSolveFirst  : d (dvec) -> X                                             [mixed]
+//   kSolveCorr   : residual -> X += correction, then Tr(X_i)/3               [mixed]
+//   kSolveLambda : Xbar_i = xbar_i I / 3 from the polarisability adjoints -> lambda
+enum { kSolveD = 0, kSolveFirst = 1, kSolveCorr = 2, kSolveLambda = 3 };
+
 template <typename R>
-__global__ void __launch_bounds__(sizeof(R) == 8 ? 512 : 256) k_scs_solve(ScsArgs a, int n1max) {
+__global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mode) {
     extern __shared__ double lds[];
-    constexpr bool mixed = sizeof(R) == 4;
-    constexpr int kRes = 2;  // partner-range splits of the residual
     const int k = blockIdx.x;
     const int w = blockIdx.y;
     const int n1 = a.counts[k].n1;
     const int N = 3 * n1;
-    const int Nmax = 3 * n1max;
     const int ld = a.fac_ld[k];
     const R* A = static_cast<const R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
-    double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
-    double* Y = lds;
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = Xg[e];
-    __syncthreads();
-    if (!mixed) {
-        chol_solve3<double, true>(reinterpret_cast<const double*>(A), N, ld, Y);
+    const size_t xo = a.x_off[k] + (size_t)w * N * 3;
+    R* Y = reinterpret_cast<R*>(lds);
+    R* zbuf = Y + 9 * n1max;
+    if (mode == kSolveLambda) {
+        const double* abl = a.abar_loc + a.aloc_off[k];
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
+            const int s = e / 9, q = (e / 3) % 3, c = e % 3;
+            double xb = abl[(size_t)s * a.nw + w];
+            if (s == 0) xb += a.abar_cen[(size_t)k * a.nw + w];
+            Y[e] = (q == c) ? R(xb / 3.0) : R(0);
+        }
     } else {
-        double* X = Y + 3 * Nmax;
-        R* Yr = reinterpret_cast<R*>(X + 3 * Nmax);
-        double* px = X + 6 * Nmax;  // Yr takes at most 3 Nmax doubles
-        double* py = px + n1max;
-        double* pz = py + n1max;
-        double* ab = pz + n1max;
-        double* red = ab + n1max;   // kRes * n1max * 9
-        const Site* S = a.sites + a.site_off[k];
-        for (int s = threadIdx.x; s < n1; s += blockDim.x) {
-            px[s] = S[s].x;
-            py[s] = S[s].y;
-            pz[s] = S[s].z;
-            ab[s] = a.abar[(size_t)S[s].base * a.nw + w];
-        }
-        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] = 0.0;
-        const int npairs = n1 * (n1 + 1) / 2;
-        const float* coef = a.coef + a.coef_off[k] + (size_t)w * 2 * npairs;
-        __syncthreads();
-        for (int it = 0; it <= a.n_refine; ++it) {
-            if (it == 0) {
-                for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Yr[e] = R(Y[e]);
-            } else {
-                // partial products of the off-diagonal blocks, partner range split in kRes parts
-                for (int t = threadIdx.x; t < n1 * kRes; t += blockDim.x) {
-                    const int i = t % n1, part = t / n1;
-                    double acc[9] = {};
-                    for (int j = part; j < n1; j += kRes) {
-                        if (j == i) continue;
-                        const int pj = i > j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
-                        const double cA = coef[2 * pj], cB = coef[2 * pj + 1];
-                        if (cA == 0.0 && cB == 0.0) continue;
-                        const double v[3] = {px[i] - px[j], py[i] - py[j], pz[i] - pz[j]};
-                        const double ir = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                        const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
-                        for (int c = 0; c < 3; ++c) {
-                            const double x0 = X[(3 * j + 0) * 3 + c], x1 = X[(3 * j + 1) * 3 + c],
-                                         x2 = X[(3 * j + 2) * 3 + c];
-                            const double rx = rh[0] * x0 + rh[1] * x1 + rh[2] * x2;
-                            acc[0 * 3 + c] += cA * rh[0] * rx + cB * x0;
-                            acc[1 * 3 + c] += cA * rh[1] * rx + cB * x1;
-                            acc[2 * 3 + c] += cA * rh[2] * rx + cB * x2;
-                        }
-                    }
-                    for (int e = 0; e < 9; ++e) red[(size_t)(part * n1 + i) * 9 + e] = acc[e];
-                }
-                __syncthreads();
-                for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-                    for (int e = 0; e < 9; ++e) {
-                        const int idx = (3 * i + e / 3) * 3 + e % 3;
-                        double r = Y[idx] - X[idx] / ab[i];
-                        for (int part = 0; part < kRes; ++part) r -= red[(size_t)(part * n1 + i) * 9 + e];
-                        Yr[idx] = R(r);
-                    }
-                }
-            }
-            __syncthreads();
-            chol_solve3<R, false>(A, N, ld, Yr);
-            for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] += double(Yr[e]);
-            __syncthreads();
-        }
-        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = X[e];
-        __syncthreads();
+        const double* src = mode == kSolveD ? a.xsol : (mode == kSolveFirst ? a.dvec : a.resid);
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = R(src[xo + e]);
     }
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Xg[e] = Y[e];
+    __syncthreads();
+    chol_solve3<R>(A, N, ld, Y, zbuf);
+    if (mode == kSolveLambda) {
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) a.lam[xo + e] = double(Y[e]);
+        return;
+    }
+    double* X = a.xsol + xo;
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] = (mode == kSolveCorr ? X[e] : 0.0) + double(Y[e]);
+    if (mode == kSolveFirst) return;
+    __syncthreads();
     double* al = a.alpha_loc + a.aloc_off[k];
     for (int s = threadIdx.x; s < n1; s += blockDim.x)
-        al[(size_t)s * a.nw + w] = (Y[(3 * s) * 3 + 0] + Y[(3 * s + 1) * 3 + 1] + Y[(3 * s + 2) * 3 + 2]) / 3.0;
+        al[(size_t)s * a.nw + w] = (X[(3 * s) * 3 + 0] + X[(3 * s + 1) * 3 + 1] + X[(3 * s + 2) * 3 + 2]) / 3.0;
 }
 
 size_t scs_solve_lds_bytes(int n1max, bool mixed) {
-    const size_t N = 3 * (size_t)n1max;
-    if (!mixed) return sizeof(double) * 3 * N;
-    return sizeof(double) * (9 * N + 4 * (size_t)n1max + 2 * 9 * (size_t)n1max);
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return r * (9 * (size_t)n1max + 2 * NB * kSlotLd);
 }
+
+// Refinement residual of the mixed path: resid = d - B~ X in FP64, with B~
+// rebuilt from its FP32 pair coefficients; partner ranges split over kRes
+// threads and recombined in a fixed order.
+__global__ void __launch_bounds__(256) k_scs_residual(ScsArgs a, int n1max) {
+    extern __shared__ double lds[];
+    constexpr int kRes = 2;
+    const int k = blockIdx.x;
+    const int w = blockIdx.y;
+    const int n1 = a.counts[k].n1;
+    const int N = 3 * n1;
+    const size_t xo = a.x_off[k] + (size_t)w * N * 3;
+    double* X = lds;
+    double* px = X + 9 * n1max;
+    double* py = px + n1max;
+    double* pz = py + n1max;
+    double* ab = pz + n1max;
+    double* red = ab + n1max;   // kRes * n1max * 9
+    const Site* S = a.sites + a.site_off[k];
+    for (int s = threadIdx.x; s < n1; s += blockDim.x) {
+        px[s] = S[s].x;
+        py[s] = S[s].y;
+        pz[s] = S[s].z;
+        ab[s] = a.abar[(size_t)S[s].base * a.nw + w];
+    }
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) X[e] = a.xsol[xo + e];
+    const int npairs = n1 * (n1 + 1) / 2;
+    const float* coef = a.coef + a.coef_off[k] + (size_t)w * 2 * npairs;
+    __syncthreads();
+    for (int t = threadIdx.x; t < n1 * kRes; t += blockDim.x) {
+        const int i = t % n1, part = t / n1;
+        double acc[9] = {};
+        for (int j = part; j < n1; j += kRes) {
+            if (j == i) continue;
+            const int pj = i > j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+            const double cA = coef[2 * pj], cB = coef[2 * pj + 1];
+            if (cA == 0.0 && cB == 0.0) continue;
+            const double v[3] = {px[i] - px[j], py[i] - py[j], pz[i] - pz[j]};
+            const double ir = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
+            for (int c = 0; c < 3; ++c) {
+                const double x0 = X[(3 * j + 0) * 3 + c], x1 = X[(3 * j + 1) * 3 + c], x2 = X[(3 * j + 2) * 3 + c];
+                const double rx = rh[0] * x0 + rh[1] * x1 + rh[2] * x2;
+                acc[0 * 3 + c] += cA * rh[0] * rx + cB * x0;
+                acc[1 * 3 + c] += cA * rh[1] * rx + cB * x1;
+                acc[2 * 3 + c] += cA * rh[2] * rx + cB * x2;
+            }
+        }
+        for (int e = 0; e < 9; ++e) red[(size_t)(part * n1 + i) * 9 + e] = acc[e];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        for (int e = 0; e < 9; ++e) {
+            const int idx = (3 * i + e / 3) * 3 + e % 3;
+            double r = a.dvec[xo + idx] - X[idx] / ab[i];
+            for (int part = 0; part < kRes; ++part) r -= red[(size_t)(part * n1 + i) * 9 + e];
+            a.resid[xo + idx] = r;
+        }
+    }
+}
+
+size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)n1max + 4 * (size_t)n1max + 2 * 9 * (size_t)n1max); }
 
 // ---------------------------------------------------------------------------
 // Adjoint.  With X = B~^{-1} d and seeds xbar_i (adjoint of alpha~_iso_i =
@@ -711,21 +740,13 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rc = SI.r_scs;
     ScsLds L = scs_lds(lds, n1max, n2max);
-    const R* A = static_cast<const R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
-    R* Yr = static_cast<R*>(L.Yr);
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
+    const double* Lg = a.lam + a.x_off[k] + (size_t)w * N * 3;
     load_sites(a, k, w, n1, n12, L);
-    const double* abl = a.abar_loc + a.aloc_off[k];
-    for (int s = threadIdx.x; s < n1; s += blockDim.x) {
-        double xb = abl[(size_t)s * a.nw + w];
-        if (s == 0) xb += a.abar_cen[(size_t)k * a.nw + w];
-        for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) Yr[(3 * s + q) * 3 + c] = (q == c) ? R(xb / 3.0) : R(0);
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
+        L.X[e] = Xg[e];
+        L.Y[e] = Lg[e];
     }
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.X[e] = Xg[e];
-    __syncthreads();
-    chol_solve3<R, false>(A, N, ld, Yr);  // lambda
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) L.Y[e] = double(Yr[e]);
     __syncthreads();
 
     double* out = a.cf + (size_t)w * a.cf_slice + a.site_off[k] * 3;
@@ -913,21 +934,29 @@ hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n
     if (mixed) {
         hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(256), la, st, a, n1max, n2max);
         hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), 0, st, a);
-        hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(256), ls, st, a, n1max);
+        hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveFirst);
+        for (int it = 0; it < a.n_refine; ++it) {
+            hipLaunchKernelGGL(k_scs_residual, grid, dim3(256), scs_residual_lds_bytes(n1max), st, a, n1max);
+            hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveCorr);
+        }
     } else {
         hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(256), la, st, a, n1max, n2max);
         hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), 0, st, a);
-        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max);
+        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max, (int)kSolveD);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
-    const size_t lds = scs_lds_bytes(n1max, n2max, mixed);
-    if (mixed)
-        hipLaunchKernelGGL(k_scs_adjoint<float>, dim3(a.n, a.nw), dim3(256), lds, st, a, n1max, n2max);
-    else
-        hipLaunchKernelGGL(k_scs_adjoint<double>, dim3(a.n, a.nw), dim3(256), lds, st, a, n1max, n2max);
+    const dim3 grid(a.n, a.nw);
+    const size_t lds = scs_lds_bytes(n1max, n2max, mixed), ls = scs_solve_lds_bytes(n1max, mixed);
+    if (mixed) {
+        hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveLambda);
+        hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(256), lds, st, a, n1max, n2max);
+    } else {
+        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max, (int)kSolveLambda);
+        hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(256), lds, st, a, n1max, n2max);
+    }
     return hipGetLastError();
 }
 

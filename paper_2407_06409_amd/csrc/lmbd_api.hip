@@ -56,7 +56,7 @@ struct lmbd_context {
     DBuf site_off, sites, hash_off, hash_cap, table, rev;
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
-    DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off;
+    DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam;
     DBuf e_out, f_out, a_out;
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
@@ -74,7 +74,7 @@ struct lmbd_context {
         &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
-        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam
 
 namespace {
 
@@ -340,6 +340,7 @@ hipError_t layout_pre(lmbd_context* c, const PreDims& d, F&& get) {
 
 template <class F>
 hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size_t wsz, F&& get) {
+    const bool mixed = wsz == sizeof(float);
     const size_t N = (size_t)P.n_atoms, D = sizeof(double), I = sizeof(int32_t), L8 = sizeof(int64_t);
     const size_t TS = (size_t)P.total_sites;
     const std::pair<DBuf*, size_t> L[] = {
@@ -355,9 +356,17 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
         const hipError_t r = get(*e.first, e.second);
         if (r != hipSuccess) return r;
     }
+    if (mixed) {
+        const std::pair<DBuf*, size_t> M2[] = {{&c->dvec, (size_t)P.x_len * D}, {&c->resid, (size_t)P.x_len * D}};
+        for (const auto& e : M2) {
+            const hipError_t r = get(*e.first, e.second);
+            if (r != hipSuccess) return r;
+        }
+    }
     if (forces) {
         const std::pair<DBuf*, size_t> F2[] = {
-            {&c->ca, TS * nw * D}, {&c->cf, (size_t)(1 + nw) * TS * 3 * D}, {&c->f_out, 3 * N * D}};
+            {&c->ca, TS * nw * D}, {&c->cf, (size_t)(1 + nw) * TS * 3 * D}, {&c->f_out, 3 * N * D},
+            {&c->lam, (size_t)P.x_len * D}};
         for (const auto& e : F2) {
             const hipError_t r = get(*e.first, e.second);
             if (r != hipSuccess) return r;
@@ -856,6 +865,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.coef = mixed ? as<float>(ctx->coef) : nullptr;
     sa.coef_off = as<int64_t>(ctx->coef_off);
     sa.xsol = as<double>(ctx->xsol);
+    sa.dvec = mixed ? as<double>(ctx->dvec) : nullptr;
+    sa.resid = mixed ? as<double>(ctx->resid) : nullptr;
+    sa.lam = forces ? as<double>(ctx->lam) : nullptr;
     sa.x_off = as<int64_t>(ctx->x_off);
     sa.alpha_loc = as<double>(ctx->alpha_loc);
     sa.aloc_off = as<int64_t>(ctx->aloc_off);

@@ -169,7 +169,10 @@ struct ScsArgs {
     const int32_t* fac_ld;   // ld >= N, a multiple of 4
     float* coef;             // mixed path: FP32 pair coefficients (A, B) of B~, per atom nw * n1 (n1 + 1) / 2 pairs
     const int64_t* coef_off; // per atom, in floats
-    double* xsol;            // per atom nw * N * 3 (row-major)
+    double* xsol;            // per atom nw * N * 3 (row-major): d, then the solution X
+    double* dvec;            // mixed path: d (same layout)
+    double* resid;           // mixed path: refinement residual (same layout)
+    double* lam;             // forces: adjoint solution lambda (same layout)
     const int64_t* x_off;
     double* alpha_loc;       // per atom n1 * nw
     const int64_t* aloc_off;
