@@ -44,12 +44,48 @@ def neighbour_counts(st, rc):
     return np.array([len(x) for x in tree.query_ball_point(pts, rc - 1e-12)])
 
 
-def scs_forward_flops(n1, nw):
-    """Algorithmic FLOPs of the SCS forward stage: per (atom, frequency) a
-    symmetric factorisation (N^3/3) and two triangular solves with 3 right-hand
-    sides (6 N^2), N = 3 n1."""
+def scs_factor_flops(n1, nw):
+    """Algorithmic FLOPs of the SCS factorisation: N^3/3 per (atom, frequency), N = 3 n1."""
     N = 3.0 * n1.astype(np.float64)
-    return float(np.sum(nw * (N ** 3 / 3.0 + 6.0 * N ** 2)))
+    return float(np.sum(nw * N ** 3 / 3.0))
+
+
+def scs_solve_flops(n1, nw, n_solves):
+    """Two triangular solves with 3 right-hand sides: 6 N^2 per solve and (atom, frequency)."""
+    N = 3.0 * n1.astype(np.float64)
+    return float(np.sum(nw * n_solves * 6.0 * N ** 2))
+
+
+def source_digest(paths):
+    """SHA-256 over kernel sources (ties a stored counter reading to the code it was taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+FACTOR_SOURCES = ["paper_2407_06409_amd/csrc/k_scs.hip", "paper_2407_06409_amd/csrc/lmbd_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scs_factor_C1728_fp64_traffic.md")
+
+
+def stored_traffic():
+    """HBM bytes per launch of the factorisation kernel from the committed counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != source_digest(FACTOR_SOURCES):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def mbd_flops(nK, nq, n_max, forces):
@@ -177,7 +213,53 @@ SERVE_POOL = 96 << 30
 SERVE_BATCH_ATOMS = 8192
 
 
+def summarize(kind, d, workload):
+    """Markdown summary of rocprofv3 output (kernel stats, or FETCH/WRITE counters)."""
+    import csv
+    import glob
+
+    def one(pattern):
+        f = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+        if not f:
+            sys.exit(f"no {pattern} under {d}")
+        return list(csv.DictReader(open(f[0])))
+
+    if kind == "stats":
+        rows = one("*kernel_stats.csv")
+        out = [f"| kernel | calls | avg ms | share |", "|---|---|---|---|"]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            out.append(f"| `{r['Name'][:72]}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                       f"{float(r['Percentage']):.1f}% |")
+        return "\n".join(out)
+    # counters: kind = "pmc:<fetch dir>:<write dir>"
+    _, dfetch, dwrite = kind.split(":")
+    res = {}
+    for counter, dd in (("FETCH_SIZE", dfetch), ("WRITE_SIZE", dwrite)):
+        d = dd
+        rows = [r for r in one("*counter_collection.csv") if r["Counter_Name"] == counter]
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ref = max(copy) if copy else float("nan")
+        fac = [float(r["Counter_Value"]) for r in rows if "k_scs_factor" in r["Kernel_Name"]]
+        res[counter] = (ref, fac[0] if fac else float("nan"))
+    copy_kib = 1024.0 * 1024.0   # the 1 GiB calibration copy (bench.py --calibrate-copy 1024)
+    f_fetch = copy_kib / res["FETCH_SIZE"][0]
+    f_write = copy_kib / res["WRITE_SIZE"][0]
+    hbm = (res["FETCH_SIZE"][1] * f_fetch + res["WRITE_SIZE"][1] * f_write) * 1024.0
+    lines = [f"| counter | 1 GiB copy reads (KiB) | calibration factor | k_scs_factor<double> (KiB) | calibrated GB |",
+             "|---|---|---|---|---|",
+             f"| FETCH_SIZE | {res['FETCH_SIZE'][0]:.0f} | {f_fetch:.4f} | {res['FETCH_SIZE'][1]:.4g} | "
+             f"{res['FETCH_SIZE'][1] * f_fetch * 1024 / 1e9:.2f} |",
+             f"| WRITE_SIZE | {res['WRITE_SIZE'][0]:.0f} | {f_write:.4f} | {res['WRITE_SIZE'][1]:.4g} | "
+             f"{res['WRITE_SIZE'][1] * f_write * 1024 / 1e9:.2f} |",
+             "", f"- hbm_bytes_per_launch: `{hbm:.6g}`",
+             f"- source_digest: `{source_digest(FACTOR_SOURCES)}`"]
+    return "\n".join(lines)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize":
+        print(summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ".", ""))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -245,17 +327,24 @@ def main():
     nq, nw, n_max = len(grid[0]), len(grid[0]) + 1, DEFAULT_PARAMS["n_max"]
     n1 = neighbour_counts(st, cut["r_scs"])
     nK = neighbour_counts(st, cut["r_nbr"])
-    kernels = {
-        "scs_forward": (scs_forward_flops(n1, nw), stage_ms["scs_forward"]),
-        "mbd": (mbd_flops(nK, nq, n_max, True), stage_ms["mbd"]),
+    n_solves = 1 if args.precision == "fp64" else 2
+    flops = {
+        "scs_factor": scs_factor_flops(n1, nw),
+        "scs_solve": scs_solve_flops(n1, nw, n_solves),
+        "mbd": mbd_flops(nK, nq, n_max, True),
+        "scs_lambda": scs_solve_flops(n1, nw, 1),
     }
-    dom = max(kernels, key=lambda k: kernels[k][1])
-    flops, ms = kernels[dom]
     peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
-    achieved = flops / (ms * 1e-3) / 1e12
+    stage_tflops = {k: flops[k] / (stage_ms[k] * 1e-3) / 1e12 for k in flops if stage_ms.get(k, 0) > 0}
+    dom = max(flops, key=lambda k: stage_ms.get(k, 0.0))   # the longest kernel with a dense-algebra count
+    ms = stage_ms[dom]
+    achieved = flops[dom] / (ms * 1e-3) / 1e12
+    traffic = stored_traffic() if (dom == "scs_factor" and args.precision == "fp64" and args.workload == "plain") else None
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms}
+                "frac": achieved / peak, "traffic": traffic,
+                "algorithmic_flops_per_launch": flops[dom], "avg_launch_ms": ms,
+                "traffic_unit": "bytes of HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "stage_tflops": stage_tflops}
 
     line = {
         "metric": METRIC, "value": value, "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LMBD_ABI_VERSION 1
+#define LMBD_ABI_VERSION 2
 
 typedef enum lmbd_status {
     LMBD_OK = 0,
@@ -169,10 +169,12 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
 /* Stage timers.  With profiling on, the library records a HIP event on the
  * call's stream before and after each stage of the hot path and, once the call
  * has completed, keeps the elapsed milliseconds of the last call per stage.
- * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map,
- * 2 local SCS forward, 3 local MBD energy (+adjoint), 4 central-polarisability
- * gather, 5 local SCS adjoint, 6 force gather. */
-#define LMBD_N_STAGES 7
+ * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map+
+ * coupling lists, 2 local SCS assembly, 3 local SCS factorisation, 4 local SCS
+ * solves (with the refinement of the mixed path), 5 local MBD energy
+ * (+adjoint), 6 central-polarisability gather, 7 adjoint SCS solves, 8 SCS
+ * pair gradients, 9 force gather. */
+#define LMBD_N_STAGES 10
 lmbd_status lmbd_set_profiling(lmbd_context* ctx, int32_t enable);
 /* ms: caller array of LMBD_N_STAGES doubles; stages not run in the last call read 0. */
 lmbd_status lmbd_stage_times(const lmbd_context* ctx, double* ms);

@@ -127,4 +127,4 @@ EXPORTED = ["lmbd_abi_version", "lmbd_create", "lmbd_destroy", "lmbd_set_memory_
             "lmbd_last_error", "lmbd_set_profiling", "lmbd_stage_times", "lmbd_stage_name",
             "lmbd_server_create", "lmbd_server_destroy", "lmbd_submit", "lmbd_poll", "lmbd_wait",
             "lmbd_release", "lmbd_server_get_stats"]
-N_STAGES = 7
+N_STAGES = 10

@@ -928,35 +928,49 @@ hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2ma
     return hipGetLastError();
 }
 
-hipError_t launch_scs_forward(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
+hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
-    const size_t la = scs_assemble_lds_bytes(n1max, n2max), ls = scs_solve_lds_bytes(n1max, mixed);
+    const size_t la = scs_assemble_lds_bytes(n1max, n2max);
+    if (mixed) hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(256), la, st, a, n1max, n2max);
+    else hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(256), la, st, a, n1max, n2max);
+    return hipGetLastError();
+}
+
+hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, bool mixed) {
+    const dim3 grid(a.n, a.nw);
+    if (mixed) hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
+    const dim3 grid(a.n, a.nw);
+    const size_t ls = scs_solve_lds_bytes(n1max, mixed);
     if (mixed) {
-        hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(256), la, st, a, n1max, n2max);
-        hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), 0, st, a);
         hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveFirst);
         for (int it = 0; it < a.n_refine; ++it) {
             hipLaunchKernelGGL(k_scs_residual, grid, dim3(256), scs_residual_lds_bytes(n1max), st, a, n1max);
             hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveCorr);
         }
     } else {
-        hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(256), la, st, a, n1max, n2max);
-        hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), 0, st, a);
         hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max, (int)kSolveD);
     }
     return hipGetLastError();
 }
 
+hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
+    const dim3 grid(a.n, a.nw);
+    const size_t ls = scs_solve_lds_bytes(n1max, mixed);
+    if (mixed) hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveLambda);
+    else hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max, (int)kSolveLambda);
+    return hipGetLastError();
+}
+
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
-    const size_t lds = scs_lds_bytes(n1max, n2max, mixed), ls = scs_solve_lds_bytes(n1max, mixed);
-    if (mixed) {
-        hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveLambda);
-        hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(256), lds, st, a, n1max, n2max);
-    } else {
-        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max, (int)kSolveLambda);
-        hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(256), lds, st, a, n1max, n2max);
-    }
+    const size_t lds = scs_lds_bytes(n1max, n2max, mixed);
+    if (mixed) hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(256), lds, st, a, n1max, n2max);
+    else hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(256), lds, st, a, n1max, n2max);
     return hipGetLastError();
 }
 

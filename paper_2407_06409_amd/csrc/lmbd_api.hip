@@ -430,8 +430,10 @@ void lmbd_destroy(lmbd_context* ctx) {
     delete ctx;
 }
 
-static const char* kStageNames[LMBD_N_STAGES] = {"prep_sort_count", "nbr_fill_revmap", "scs_forward",
-                                                  "mbd",  "gather_central", "scs_adjoint", "gather_forces"};
+static const char* kStageNames[LMBD_N_STAGES] = {"prep_sort_count", "nbr_fill_revmap", "scs_assemble",
+                                                  "scs_factor",      "scs_solve",       "mbd",
+                                                  "gather_central",  "scs_lambda",      "scs_adjoint",
+                                                  "gather_forces"};
 
 const char* lmbd_stage_name(int32_t i) { return (i >= 0 && i < LMBD_N_STAGES) ? kStageNames[i] : nullptr; }
 
@@ -880,8 +882,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_pairlist(stream, sa, P.n1max, P.n2max));
     HIP_TRY(mark(1, 1));
     HIP_TRY(mark(2, 0));
-    HIP_TRY(launch_scs_forward(stream, sa, P.n1max, P.n2max, mixed));
+    HIP_TRY(launch_scs_assemble(stream, sa, P.n1max, P.n2max, mixed));
     HIP_TRY(mark(2, 1));
+    HIP_TRY(mark(3, 0));
+    HIP_TRY(launch_scs_factor(stream, sa, mixed));
+    HIP_TRY(mark(3, 1));
+    HIP_TRY(mark(4, 0));
+    HIP_TRY(launch_scs_solve(stream, sa, P.n1max, mixed));
+    HIP_TRY(mark(4, 1));
 
     // --- local MBD energy (+ adjoint)
     MbdArgs ma;
@@ -914,26 +922,29 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.abar_loc = as<double>(ctx->abar_loc);
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
-    HIP_TRY(mark(3, 0));
+    HIP_TRY(mark(5, 0));
     HIP_TRY(launch_mbd(stream, ma, P.nkmax, mixed));
-    HIP_TRY(mark(3, 1));
+    HIP_TRY(mark(5, 1));
 
     if (forces) {
-        HIP_TRY(mark(4, 0));
+        HIP_TRY(mark(6, 0));
         HIP_TRY(launch_gather_central(stream, N, nw, sa.counts, sa.site_off, sa.sites, as<int32_t>(ctx->rev),
                                       as<double>(ctx->ca), as<double>(ctx->abar_cen)));
-        HIP_TRY(mark(4, 1));
+        HIP_TRY(mark(6, 1));
         sa.abar_loc = as<double>(ctx->abar_loc);
         sa.abar_cen = as<double>(ctx->abar_cen);
         sa.cf_slice = TS * 3;
         sa.cf = as<double>(ctx->cf) + sa.cf_slice;  // slices 1..nw
-        HIP_TRY(mark(5, 0));
+        HIP_TRY(mark(7, 0));
+        HIP_TRY(launch_scs_lambda(stream, sa, P.n1max, mixed));
+        HIP_TRY(mark(7, 1));
+        HIP_TRY(mark(8, 0));
         HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max, P.n2max, mixed));
-        HIP_TRY(mark(5, 1));
-        HIP_TRY(mark(6, 0));
+        HIP_TRY(mark(8, 1));
+        HIP_TRY(mark(9, 0));
         HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,
                                      as<int32_t>(ctx->rev), as<double>(ctx->cf), as<double>(ctx->f_out)));
-        HIP_TRY(mark(6, 1));
+        HIP_TRY(mark(9, 1));
     }
     HIP_TRY(launch_central_static(stream, N, nw, sa.alpha_loc, sa.aloc_off, as<double>(ctx->a_out)));
 
