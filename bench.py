@@ -103,7 +103,7 @@ def mbd_flops(nK, nq, n_max, forces):
 def cpu_baseline(st, cut, grid):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload.
 
-    Sample: the energy+forces pass of two central atoms; the oracle reports the
+    Sample: the energy+forces pass of six central atoms; the oracle reports the
     time and atom count of each of its three passes, from which the cost of one
     atom of the complete job (one central SCS, one MBD+SCS reverse pass, one SCS
     reverse pass) is extrapolated.
@@ -114,7 +114,7 @@ def cpu_baseline(st, cut, grid):
     prm = oracle.make_params(cut, grid[0], grid[1], n_max=DEFAULT_PARAMS["n_max"], beta=DEFAULT_PARAMS["beta"],
                              damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
                              r_inner=DEFAULT_PARAMS["r_inner"])
-    sample = [0, st.n // 2]
+    sample = [0, st.n // 6, st.n // 3, st.n // 2, 2 * st.n // 3, 5 * st.n // 6]
     tm = {}
     t0 = time.perf_counter()
     oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE, atoms=sample, timings=tm)
