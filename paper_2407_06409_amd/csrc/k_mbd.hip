@@ -23,6 +23,8 @@
 namespace lmbd {
 
 
+__host__ __device__ inline size_t al4(size_t x) { return (x + 3) / 4 * 4; }
+
 // LDS layout
 struct MbdLds {
     double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu;
@@ -144,6 +146,77 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const W* __restri
     __syncthreads();
 }
 
+// Workgroup GEMM out(m, n) = sum_k A[m][k] B[n][k] with both operands k-contiguous
+// (row-major, lda/ldb multiples of 4, K a multiple of 4).  Lane (i, g) of an MFMA
+// operand reads the 4-vector k = 16 c + 4 g .. + 3 and feeds element e to k-step e,
+// the same permutation of k for both operands; 16 k per chunk, the next chunk in
+// flight.  Each wavefront takes a 16-row strip times up to four 16-column tiles.
+template <typename W, typename ST>
+__device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __restrict__ A, int lda,
+                                             const W* __restrict__ B, int ldb, ST st) {
+    typedef MfmaW<W> Mf;
+    typedef W V4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int mt = (M + 15) / 16;
+    const int nt = (N + 15) / 16;
+    const int ng = (nt + 3) / 4;
+    const int nch = (K + 15) / 16;
+    const V4 zero = {W(0), W(0), W(0), W(0)};
+    for (int t = wave; t < mt * ng; t += nwave) {
+        const int m0 = (t / ng) * 16;
+        const int tc0 = (t % ng) * 4;
+        typename Mf::acc acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[c][q] = W(0);
+        const int am = m0 + li;
+        const bool aok = am < M;
+        const W* pa = A + (size_t)(aok ? am : 0) * lda + 4 * lk;
+        const W* pb[4];
+        bool bok[4];
+        int bn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            bn[c] = (tc0 + c) * 16 + li;
+            bok[c] = bn[c] < N && tc0 + c < nt;
+            pb[c] = B + (size_t)(bok[c] ? bn[c] : 0) * ldb + 4 * lk;
+        }
+        auto kin = [&](int ch) { return ch < nch && 16 * ch + 4 * lk < K; };
+        V4 a = (aok && kin(0)) ? *reinterpret_cast<const V4*>(pa) : zero;
+        V4 b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = (bok[c] && kin(0)) ? *reinterpret_cast<const V4*>(pb[c]) : zero;
+        for (int ch = 0; ch < nch; ++ch) {
+            const bool kn = kin(ch + 1);
+            const V4 na = (aok && kn) ? *reinterpret_cast<const V4*>(pa + 16 * (ch + 1)) : zero;
+            V4 nb[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                nb[c] = (bok[c] && kn) ? *reinterpret_cast<const V4*>(pb[c] + 16 * (ch + 1)) : zero;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = Mf::mma(a[e], b[c][e], acc[c]);
+            a = na;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = nb[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (bok[c]) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = m0 + Mf::acc_row(lk, q);
+                    if (m < M) st(m, bn[c], acc[c][q]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // T_LR pair coefficients: T_LR = A rhat rhat^T + B I with radial derivatives,
 // and dT_LR/dS~ = fLR (df/dS~) T.
 template <typename P>
@@ -184,10 +257,12 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     const Site* S = a.sites + a.site_off[k];
     const double* aloc = a.alpha_loc + a.aloc_off[k];
     W* T = static_cast<W*>(a.work) + a.work_off[k];
-    W* U = T + (size_t)N3 * N3;                              // u_1 .. u_mmax
-    W* V = U + (size_t)a.mmax * N3 * ncol;                   // D u_m, the next product's operand
-    W* PT = V + (size_t)N3 * ncol;                           // (D u_a)^T, a = 0 .. n_max-1 (K-major)
-    W* QT = PT + (size_t)a.n_max * ncol * N3;                // (W D Z_a)^T
+    // sub-arrays start on multiples of 4 elements (aligned 4-vector loads)
+    const int KK = n_max * ncol, KKp = (KK + 3) / 4 * 4;
+    W* U = T + al4((size_t)N3 * N3);                         // u_1 .. u_mmax
+    W* V = U + al4((size_t)a.mmax * N3 * ncol);              // D u_m, the next product's operand
+    W* Pm = V + al4((size_t)N3 * ncol);                      // D u_a side by side, a = 0 .. n_max-1
+    W* Qm = Pm + (size_t)N3 * KKp;                           // W D Z_a side by side
     auto Uat = [&](int m) { return U + (size_t)(m - 1) * N3 * ncol; };
 
     // --- blend (Sec. III.B, central/local combination) and SCS radii
@@ -312,23 +387,27 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
         }
         L.ab[t] = v;
     }
-    // --- K-major operands of Tbar = sum_a (D u_a)(W D Z_a)^T, Z_a = sum_b c_{a+b+1} u_b
-    // (u_0 = e_k): PT[a ncol + col][r] = sqrt(alpha~_r) u_a[r][col] and
-    // QT[a ncol + col][s] = w_k W_q sqrt(alpha~_s) Z_a[s][col]
-    const int KK = n_max * ncol;
-    for (int e = tid; e < KK * N3; e += blockDim.x) {
-        const int kk = e / N3, r = e % N3;
+    // --- operands of Tbar = sum_a (D u_a)(W D Z_a)^T, Z_a = sum_b c_{a+b+1} u_b (u_0 = e_k),
+    // k-contiguous: P[r][a ncol + col] = sqrt(alpha~_r) u_a[r][col] and
+    // Q[s][a ncol + col] = w_k W_q sqrt(alpha~_s) Z_a[s][col]
+    for (int e = tid; e < N3 * KKp; e += blockDim.x) {
+        const int r = e / KKp, kk = e % KKp;
+        if (kk >= KK) {
+            Pm[e] = W(0);
+            Qm[e] = W(0);
+            continue;
+        }
         const int aa = kk / ncol, col = kk % ncol, q = col / 3;
         const double sq = L.sqa[(size_t)(r / 3) * nq + q];
         const double u = (aa == 0) ? ((r == col % 3) ? 1.0 : 0.0) : double(Uat(aa)[(size_t)r * ncol + col]);
         double z = (aa >= 1 && r == col % 3) ? a.coef[aa + 1] : 0.0;   // b = 0 term (u_0 = e_k)
         for (int b = 1; b <= n_max - 1 - aa; ++b) z += a.coef[aa + b + 1] * double(Uat(b)[(size_t)r * ncol + col]);
-        PT[e] = W(sq * u);
-        QT[e] = W(wk * a.wq[q] * sq * z);
+        Pm[e] = W(sq * u);
+        Qm[e] = W(wk * a.wq[q] * sq * z);
     }
     __syncthreads();
     // --- Tbar (overwrites T)
-    mfma_gemm<W>(N3, N3, KK, PT, N3, QT, N3, [&](int r, int s, W v) { T[(size_t)r * N3 + s] = v; });
+    mfma_gemm_nt<W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3 + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));

@@ -117,6 +117,16 @@ __device__ __forceinline__ float bcast(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// 1/sqrt(x): the hardware estimate and one Newton step (error a few ulp)
+__device__ __forceinline__ double rsqrt_refined(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ float rsqrt_refined(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+
 template <typename R> struct Vec4T;
 template <> struct Vec4T<double> { typedef d4_t type; };
 template <> struct Vec4T<float> { typedef f4_t type; };
@@ -157,19 +167,32 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             typename M::acc acc0, acc1;
             for (int q = 0; q < 4; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
             const V4 zero = {R(0), R(0), R(0), R(0)};
-            // chunks s, s + S, ... < p, two per step, the next step's loads in
-            // flight while the current one is on the matrix cores
+            // chunks s, s + S, ... < p on a ring of four: each chunk's registers are
+            // refilled with the chunk four ahead right after use, so four loads
+            // stay in flight (chunks past p load as zero)
             auto ld_a = [&](int c) { return (aok && c < p) ? load4(pa + NB * c) : zero; };
             auto ld_b = [&](int c) { return (bok && c < p) ? load4(pb + NB * c) : zero; };
             V4 a0 = ld_a(s), b0 = ld_b(s), a1 = ld_a(s + S), b1 = ld_b(s + S);
-            for (int ch = s; ch < p; ch += 2 * S) {
-                const V4 na0 = ld_a(ch + 2 * S), nb0 = ld_b(ch + 2 * S);
-                const V4 na1 = ld_a(ch + 3 * S), nb1 = ld_b(ch + 3 * S);
+            V4 a2 = ld_a(s + 2 * S), b2 = ld_b(s + 2 * S), a3 = ld_a(s + 3 * S), b3 = ld_b(s + 3 * S);
+            for (int ch = s; ch < p; ch += 4 * S) {  // (ch + k S < p) is uniform: no idle products
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
+                a0 = ld_a(ch + 4 * S); b0 = ld_b(ch + 4 * S);
+                if (ch + S < p) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], b1[e], acc1);
-                a0 = na0; b0 = nb0; a1 = na1; b1 = nb1;
+                    for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], b1[e], acc1);
+                }
+                a1 = ld_a(ch + 5 * S); b1 = ld_b(ch + 5 * S);
+                if (ch + 2 * S < p) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc0 = M::mma(-a2[e], b2[e], acc0);
+                }
+                a2 = ld_a(ch + 6 * S); b2 = ld_b(ch + 6 * S);
+                if (ch + 3 * S < p) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc1 = M::mma(-a3[e], b3[e], acc1);
+                }
+                a3 = ld_a(ch + 7 * S); b3 = ld_b(ch + 7 * S);
             }
             if (S == 1) {
                 const int col = c0 + li;
@@ -189,10 +212,19 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         if (tid < 64) {
             const int l = tid;
             R row[NB];
+            if (jb == NB && l < NB) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const bool valid = (l < jb) && (c <= l);
-                row[c] = valid ? A[(size_t)(c0 + l) * ld + c0 + c] : (l == c ? R(1) : R(0));
+                for (int v = 0; v < 4; ++v) {
+                    const V4 q4 = load4(A + (size_t)(c0 + l) * ld + c0 + 4 * v);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) row[4 * v + e] = (4 * v + e <= l) ? q4[e] : R(0);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    const bool valid = (l < jb) && (c <= l);
+                    row[c] = valid ? A[(size_t)(c0 + l) * ld + c0 + c] : (l == c ? R(1) : R(0));
+                }
             }
             for (int s = 0; s < S && S > 1; ++s) {
                 const R* sl = slots + (size_t)(s * m) * NB * kSlotLd + (l & 15) * kSlotLd;
@@ -201,13 +233,14 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                     if (l < jb && c <= l) row[c] += sl[c];
                 __builtin_amdgcn_sched_barrier(0);
             }
+            R invv[NB];   // 1 / L[c][c], the same in every lane
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 const R dcc = bcast(row[c], c);
                 if (c < jb && !(dcc > R(0))) good = false;
-                const R sq = m_sqrt(dcc);
-                const R inv = R(1) / sq;
-                if (l == c) row[c] = sq;
+                const R inv = rsqrt_refined(dcc);
+                invv[c] = inv;
+                if (l == c) row[c] = dcc * inv;
                 else if (l > c) row[c] *= inv;
 #pragma unroll
                 for (int s = c + 1; s < NB; ++s) {
@@ -219,7 +252,10 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             if (l < NB) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c) Ld[l * kSlotLd + c] = (c <= l) ? row[c] : R(0);
-                rinv[l] = R(1) / Ld[l * kSlotLd + l];
+            }
+            if (l == 0) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) rinv[c] = invv[c];
             }
             if (l < jb) {
 #pragma unroll
@@ -235,7 +271,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 R v = (q == l) ? R(1) : R(0);
 #pragma unroll
                 for (int r = 0; r < q; ++r) v -= bcast(row[r], q) * z[r];
-                z[q] = v / bcast(row[q], q);
+                z[q] = v * invv[q];
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (l < jb) {
@@ -586,7 +622,7 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
 // Factorisation of B~ in place, one workgroup per (atom, frequency); LDS is a
 // fixed few kilobytes, so several factorisations share a compute unit.
 template <typename R>
-__global__ void __launch_bounds__(256) k_scs_factor(ScsArgs a) {
+__global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a) {
     __shared__ R slots[kMaxSplitSlots * NB * kSlotLd];
     __shared__ R Ld[NB * kSlotLd];
     __shared__ R rinv[NB];

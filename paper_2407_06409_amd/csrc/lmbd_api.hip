@@ -286,7 +286,9 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         fo += (int64_t)nw * N1 * P.fac_ld[k];
         xo += (int64_t)nw * N1 * 3;
         ao += (int64_t)c.n1 * nw;
-        wo += N3 * N3 + (int64_t)(mmax + 1) * N3 * ncol + (forces ? 2 * (int64_t)n_max * N3 * ncol : 0);
+        auto al4 = [](int64_t x) { return (x + 3) / 4 * 4; };  // as the MBD kernel lays out its workspace
+        wo += al4(N3 * N3) + al4((int64_t)mmax * N3 * ncol) + al4(N3 * ncol) +
+              (forces ? 2 * N3 * al4((int64_t)n_max * ncol) : 0);
         P.n1max = std::max(P.n1max, c.n1);
         P.nkmax = std::max(P.nkmax, c.nK);
         P.nallmax = std::max(P.nallmax, c.n_all);
