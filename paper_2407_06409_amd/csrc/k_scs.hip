@@ -137,6 +137,7 @@ __device__ inline typename Vec4T<R>::type load4(const R* p) {
 }
 
 constexpr int kMaxSplitSlots = 4;  // partial tiles of a split-K panel update (one per wavefront)
+constexpr int kPLd = 2 * NB + 1;    // row stride of a partial tile pair (two panels) in LDS
 
 template <typename R>
 __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ slots, R* __restrict__ Ld,
@@ -149,65 +150,101 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     const int li = lane & 15, lk = lane >> 4;
     const int nt = (N + NB - 1) / NB;
     bool good = true;
+    const V4 zero = {R(0), R(0), R(0), R(0)};
+    int Se = 1, me = 0;   // split and tile count of the last even panel's update
     for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
         const int m = nt - p;
-        const int S = (p > 0 && m < nwave) ? min(nwave / m, p) : 1;
-        const int U = p > 0 ? m * S : 0;
-        // (1) update of the panel, one (tile, split) unit per wavefront; a unit
-        // that covers the whole k range adds into the matrix in place, split
-        // units leave partial tiles in LDS
-        for (int u = wave; u < U; u += nwave) {
-            const int t = u % m, s = u / m;
-            const int arow = c0 + NB * t + li, brow = c0 + li;
-            const bool aok = arow < N, bok = brow < N;
-            const R* pa = A + (size_t)(aok ? arow : 0) * ld + 4 * lk;
-            const R* pb = A + (size_t)(bok ? brow : 0) * ld + 4 * lk;
-            typename M::acc acc0, acc1;
-            for (int q = 0; q < 4; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
-            const V4 zero = {R(0), R(0), R(0), R(0)};
-            // chunks s, s + S, ... < p on a ring of four: each chunk's registers are
-            // refilled with the chunk four ahead right after use, so four loads
-            // stay in flight (chunks past p load as zero)
-            auto ld_a = [&](int c) { return (aok && c < p) ? load4(pa + NB * c) : zero; };
-            auto ld_b = [&](int c) { return (bok && c < p) ? load4(pb + NB * c) : zero; };
-            V4 a0 = ld_a(s), b0 = ld_b(s), a1 = ld_a(s + S), b1 = ld_b(s + S);
-            V4 a2 = ld_a(s + 2 * S), b2 = ld_b(s + 2 * S), a3 = ld_a(s + 3 * S), b3 = ld_b(s + 3 * S);
-            for (int ch = s; ch < p; ch += 4 * S) {  // (ch + k S < p) is uniform: no idle products
+        const bool even = (p % 2) == 0;
+        int S = 1;
+        if (even) {
+            // (1e) update of panels p and p + 1 from chunks 0 .. p-1, one (row tile,
+            // k-split) unit per wavefront: each loaded chunk of L serves both
+            // panels' tiles (the tile of panel p + 1 in row tile 0 is above the
+            // diagonal and skipped).  A unit covering the whole k range adds into
+            // the matrix in place; split units leave partial tiles in LDS.
+            S = (p > 0 && m < nwave) ? min(nwave / m, p) : 1;
+            const int U = p > 0 ? m * S : 0;
+            const bool next = p + 1 < nt;
+            for (int u = wave; u < U; u += nwave) {
+                const int t = u % m, s = u / m;
+                const bool two = next && t > 0;
+                const int arow = c0 + NB * t + li, brow0 = c0 + li, brow1 = c0 + NB + li;
+                const bool aok = arow < N, bok0 = brow0 < N, bok1 = two && brow1 < N;
+                const R* pa = A + (size_t)(aok ? arow : 0) * ld + 4 * lk;
+                const R* pb0 = A + (size_t)(bok0 ? brow0 : 0) * ld + 4 * lk;
+                const R* pb1 = A + (size_t)(bok1 ? brow1 : 0) * ld + 4 * lk;
+                typename M::acc acc0, acc1;
+                for (int q = 0; q < 4; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
+                auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < p) ? load4(base + NB * c) : zero; };
+                // ring of two chunks: each chunk's registers are refilled with the
+                // chunk two ahead right after use
+                V4 a0 = ld4(pa, aok, s), b0 = ld4(pb0, bok0, s), c0v = ld4(pb1, bok1, s);
+                V4 a1 = ld4(pa, aok, s + S), b1 = ld4(pb0, bok0, s + S), c1v = ld4(pb1, bok1, s + S);
+                for (int ch = s; ch < p; ch += 2 * S) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
+                    if (two) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc1 = M::mma(-a0[e], c0v[e], acc1);
+                    }
+                    a0 = ld4(pa, aok, ch + 2 * S); b0 = ld4(pb0, bok0, ch + 2 * S); c0v = ld4(pb1, bok1, ch + 2 * S);
+                    if (ch + S < p) {   // uniform
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc0 = M::mma(-a1[e], b1[e], acc0);
+                        if (two) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], c1v[e], acc1);
+                        }
+                    }
+                    a1 = ld4(pa, aok, ch + 3 * S); b1 = ld4(pb0, bok0, ch + 3 * S); c1v = ld4(pb1, bok1, ch + 3 * S);
+                }
+                if (S == 1) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = c0 + NB * t + M::acc_row(lk, q);
+                        if (row >= N) continue;
+                        const int col0 = c0 + li, col1 = c0 + NB + li;
+                        if (col0 < N && (t > 0 || row >= col0)) A[(size_t)row * ld + col0] += acc0[q];
+                        if (two && col1 < N && (t > 1 || row >= col1)) A[(size_t)row * ld + col1] += acc1[q];
+                    }
+                } else {
+                    R* sl = slots + (size_t)u * NB * kPLd;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        sl[M::acc_row(lk, q) * kPLd + li] = acc0[q];
+                        sl[M::acc_row(lk, q) * kPLd + NB + li] = two ? acc1[q] : R(0);
+                    }
+                }
+            }
+            Se = S;
+            me = m;
+        } else {
+            // (1o) update of an odd panel from the chunk of the even panel just
+            // finished (its other chunks came with the even panel's update)
+            for (int t = wave; t < m; t += nwave) {
+                const int arow = c0 + NB * t + li, brow = c0 + li;
+                const bool aok = arow < N, bok = brow < N;
+                const V4 a0 = aok ? load4(A + (size_t)arow * ld + NB * (p - 1) + 4 * lk) : zero;
+                const V4 b0 = bok ? load4(A + (size_t)brow * ld + NB * (p - 1) + 4 * lk) : zero;
+                typename M::acc acc0;
+                for (int q = 0; q < 4; ++q) acc0[q] = R(0);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
-                a0 = ld_a(ch + 4 * S); b0 = ld_b(ch + 4 * S);
-                if (ch + S < p) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], b1[e], acc1);
-                }
-                a1 = ld_a(ch + 5 * S); b1 = ld_b(ch + 5 * S);
-                if (ch + 2 * S < p) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc0 = M::mma(-a2[e], b2[e], acc0);
-                }
-                a2 = ld_a(ch + 6 * S); b2 = ld_b(ch + 6 * S);
-                if (ch + 3 * S < p) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc1 = M::mma(-a3[e], b3[e], acc1);
-                }
-                a3 = ld_a(ch + 7 * S); b3 = ld_b(ch + 7 * S);
-            }
-            if (S == 1) {
                 const int col = c0 + li;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = c0 + NB * t + M::acc_row(lk, q);
-                    if (row < N && col < N && (t > 0 || row >= col)) A[(size_t)row * ld + col] += acc0[q] + acc1[q];
+                    if (row < N && col < N && (t > 0 || row >= col)) A[(size_t)row * ld + col] += acc0[q];
                 }
-            } else {
-                R* sl = slots + (size_t)u * NB * kSlotLd;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) sl[M::acc_row(lk, q) * kSlotLd + li] = acc0[q] + acc1[q];
             }
         }
-    __syncthreads();
+        // partial tiles of this panel left by a split even update: tile t of this
+        // panel is slot (t + toff) + s me, columns coff .. coff + 15
+        const int PS = even ? S : Se;
+        const int toff = even ? 0 : 1, coff = even ? 0 : NB;
+        __syncthreads();
         // (2) diagonal block: wavefront 0, lane l holds row l
         if (tid < 64) {
             const int l = tid;
@@ -226,8 +263,8 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                     row[c] = valid ? A[(size_t)(c0 + l) * ld + c0 + c] : (l == c ? R(1) : R(0));
                 }
             }
-            for (int s = 0; s < S && S > 1; ++s) {
-                const R* sl = slots + (size_t)(s * m) * NB * kSlotLd + (l & 15) * kSlotLd;
+            for (int s = 0; s < PS && PS > 1; ++s) {
+                const R* sl = slots + (size_t)(toff + s * me) * NB * kPLd + (l & 15) * kPLd + coff;
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
                     if (l < jb && c <= l) row[c] += sl[c];
@@ -292,8 +329,8 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
 #pragma unroll
                 for (int e = 0; e < 4; ++e) x[4 * v + e] = q4[e];
             }
-            for (int s = 0; s < S && S > 1; ++s) {
-                const R* sl = slots + (size_t)(t + s * m) * NB * kSlotLd + lr * kSlotLd;
+            for (int s = 0; s < PS && PS > 1; ++s) {
+                const R* sl = slots + (size_t)(t + toff + s * me) * NB * kPLd + lr * kPLd + coff;
 #pragma unroll
                 for (int c = 0; c < NB; ++c) x[c] += sl[c];
             }
@@ -623,7 +660,7 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
 // fixed few kilobytes, so several factorisations share a compute unit.
 template <typename R>
 __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a) {
-    __shared__ R slots[kMaxSplitSlots * NB * kSlotLd];
+    __shared__ R slots[kMaxSplitSlots * NB * kPLd];
     __shared__ R Ld[NB * kSlotLd];
     __shared__ R rinv[NB];
     const int k = blockIdx.x;

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace lmbd;
@@ -521,7 +522,7 @@ lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<
     }
     const double r1 = S.r_scs * S.r_scs, rK = S.r_nbr * S.r_nbr, r2 = 4.0 * S.r_scs * S.r_scs,
                  rb = S.r_big * S.r_big;
-    for (int k = 0; k < n; ++k) {
+    auto count_one = [&](int k) {
         Counts c{1, 1, 1, 1};
         const int ck[3] = {cell[k] / (S.ncell[1] * S.ncell[2]), (cell[k] / S.ncell[2]) % S.ncell[1],
                            cell[k] % S.ncell[2]};
@@ -559,8 +560,19 @@ lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<
                         c.n12 += d2 < r2;
                     }
                 }
-        out.push_back(c);
-    }
+        return c;
+    };
+    // atoms are independent: split them over host threads (each writes its own entries)
+    const size_t base = out.size();
+    out.resize(base + (size_t)n);
+    const int nthreads = (int)std::max<unsigned>(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
+    const int nt = n >= 512 ? nthreads : 1;
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            for (int k = t; k < n; k += nt) out[base + k] = count_one(k);
+        });
+    for (std::thread& th : pool) th.join();
     return LMBD_OK;
 }
 
