@@ -93,16 +93,22 @@ __device__ inline void inner_buffer(double r, double rin, double& fin, double& d
 // Left-looking blocked Cholesky by one workgroup, 16-column panels p:
 //  (1) update  A[c0:N, c0:c0+16] -= L[c0:N, 0:c0] L[c0:c0+16, 0:c0]^T  on MFMA
 //      16x16x4, one (row tile, k-split) unit per wavefront, 16 k at a time
-//      from two aligned 4-vector loads per lane.  When the panel has fewer row
-//      tiles than there are wavefronts the k range is split and the partial
-//      tiles go to LDS; otherwise each unit adds into the matrix in place;
-//  (2) diagonal block: wavefront 0 factorises it (lane l holds row l, values
-//      of other rows are broadcast with lane reads), keeps L_pp and 1/L_ii in
-//      LDS, and inverts it into the block's strict upper part;
-//  (3) rows below: one row per thread solves x L_pp^T = a by substitution.
-// LDS use is a few
-// kilobytes, independent of N, so several factorisations share a compute unit
-// and hide each other's memory latency.
+//      from two aligned 4-vector loads per lane.  The updated tiles go to a
+//      panel buffer in LDS (never back to the matrix); when the panel has
+//      fewer row tiles than there are wavefronts the k range is split and the
+//      partial tiles sit side by side in that buffer.  An even panel whose
+//      update is not split also applies the same loaded chunks to the next
+//      panel's columns (in place in the matrix), so the odd panel after it
+//      only needs the one chunk just finished;
+//  (2) diagonal block: wavefront 0 factorises it from the panel buffer (lane
+//      l holds row l, values of other rows are broadcast with lane reads),
+//      keeps L_pp and 1/L_ii in LDS, and inverts it into the block's strict
+//      upper part;
+//  (3) rows below: one row per thread reads its row from the panel buffer,
+//      solves x L_pp^T = a by substitution and writes the finished row.
+// LDS use is one 16-row tile per 16 rows of the neighbourhood (about 2 KB per
+// tile in FP64), so several factorisations share a compute unit and hide
+// each other's memory latency.
 // ---------------------------------------------------------------------------
 constexpr int kSlotLd = 17;   // row stride of a 16x16 tile in LDS (padding against bank conflicts)
 
@@ -136,12 +142,10 @@ __device__ inline typename Vec4T<R>::type load4(const R* p) {
     return *reinterpret_cast<const typename Vec4T<R>::type*>(p);
 }
 
-constexpr int kMaxSplitSlots = 4;  // partial tiles of a split-K panel update (one per wavefront)
-constexpr int kPLd = 2 * NB + 1;    // row stride of a partial tile pair (two panels) in LDS
 
 template <typename R>
-__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ slots, R* __restrict__ Ld,
-                            R* __restrict__ rinv, bool& ok) {
+__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ pan, R* __restrict__ Ld,
+                                            R* __restrict__ rinv, bool& ok) {
     typedef Mfma<R> M;
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
@@ -149,40 +153,47 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nt = (N + NB - 1) / NB;
-    bool good = true;
     const V4 zero = {R(0), R(0), R(0), R(0)};
-    int Se = 1, me = 0;   // split and tile count of the last even panel's update
+    bool good = true;
+    bool paired_prev = false;   // the previous (even) panel already applied chunks < p-1 to this panel
     for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
         const int m = nt - p;
-        const bool even = (p % 2) == 0;
-        int S = 1;
-        if (even) {
-            // (1e) update of panels p and p + 1 from chunks 0 .. p-1, one (row tile,
-            // k-split) unit per wavefront: each loaded chunk of L serves both
-            // panels' tiles (the tile of panel p + 1 in row tile 0 is above the
-            // diagonal and skipped).  A unit covering the whole k range adds into
-            // the matrix in place; split units leave partial tiles in LDS.
-            S = (p > 0 && m < nwave) ? min(nwave / m, p) : 1;
-            const int U = p > 0 ? m * S : 0;
-            const bool next = p + 1 < nt;
-            for (int u = wave; u < U; u += nwave) {
-                const int t = u % m, s = u / m;
-                const bool two = next && t > 0;
+        const bool only_last = paired_prev;          // then only chunk p-1 is left
+        const int k_lo = only_last ? p - 1 : 0;
+        const int nk = p - k_lo;                     // chunks of this panel's update
+        const int S = (!only_last && p > 0 && m < nwave) ? min(nwave / m, nk) : 1;
+        // an even panel with an unsplit update also applies its chunks to the
+        // next panel's columns (in place), so that panel only needs the last chunk
+        const bool pair = (p % 2 == 0) && p > 0 && S == 1 && !only_last && p + 1 < nt;
+        const int U = m * S;
+        // (1) update: one (row tile, k-split) unit per wavefront; the unit with
+        // s = 0 starts from the matrix, the others from zero; results (partial
+        // tiles for s > 0) go to the panel buffer in LDS, tile u = t + s m
+        for (int u = wave; u < U; u += nwave) {
+            const int t = u % m, s = u / m;
+            const bool two = pair && t > 0;
+            typename M::acc acc0, acc1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li;
+                acc0[q] = (s == 0 && row < N && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
+                acc1[q] = R(0);
+            }
+            if (nk > 0) {
                 const int arow = c0 + NB * t + li, brow0 = c0 + li, brow1 = c0 + NB + li;
                 const bool aok = arow < N, bok0 = brow0 < N, bok1 = two && brow1 < N;
                 const R* pa = A + (size_t)(aok ? arow : 0) * ld + 4 * lk;
                 const R* pb0 = A + (size_t)(bok0 ? brow0 : 0) * ld + 4 * lk;
                 const R* pb1 = A + (size_t)(bok1 ? brow1 : 0) * ld + 4 * lk;
-                typename M::acc acc0, acc1;
-                for (int q = 0; q < 4; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
                 auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < p) ? load4(base + NB * c) : zero; };
                 // ring of two chunks: each chunk's registers are refilled with the
                 // chunk two ahead right after use
-                V4 a0 = ld4(pa, aok, s), b0 = ld4(pb0, bok0, s), c0v = ld4(pb1, bok1, s);
-                V4 a1 = ld4(pa, aok, s + S), b1 = ld4(pb0, bok0, s + S), c1v = ld4(pb1, bok1, s + S);
-                for (int ch = s; ch < p; ch += 2 * S) {
+                const int c1 = k_lo + s;
+                V4 a0 = ld4(pa, aok, c1), b0 = ld4(pb0, bok0, c1), c0v = ld4(pb1, bok1, c1);
+                V4 a1 = ld4(pa, aok, c1 + S), b1 = ld4(pb0, bok0, c1 + S), c1v = ld4(pb1, bok1, c1 + S);
+                for (int ch = c1; ch < p; ch += 2 * S) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
                     if (two) {
@@ -200,75 +211,34 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                     }
                     a1 = ld4(pa, aok, ch + 3 * S); b1 = ld4(pb0, bok0, ch + 3 * S); c1v = ld4(pb1, bok1, ch + 3 * S);
                 }
-                if (S == 1) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = c0 + NB * t + M::acc_row(lk, q);
-                        if (row >= N) continue;
-                        const int col0 = c0 + li, col1 = c0 + NB + li;
-                        if (col0 < N && (t > 0 || row >= col0)) A[(size_t)row * ld + col0] += acc0[q];
-                        if (two && col1 < N && (t > 1 || row >= col1)) A[(size_t)row * ld + col1] += acc1[q];
-                    }
-                } else {
-                    R* sl = slots + (size_t)u * NB * kPLd;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        sl[M::acc_row(lk, q) * kPLd + li] = acc0[q];
-                        sl[M::acc_row(lk, q) * kPLd + NB + li] = two ? acc1[q] : R(0);
-                    }
-                }
             }
-            Se = S;
-            me = m;
-        } else {
-            // (1o) update of an odd panel from the chunk of the even panel just
-            // finished (its other chunks came with the even panel's update)
-            for (int t = wave; t < m; t += nwave) {
-                const int arow = c0 + NB * t + li, brow = c0 + li;
-                const bool aok = arow < N, bok = brow < N;
-                const V4 a0 = aok ? load4(A + (size_t)arow * ld + NB * (p - 1) + 4 * lk) : zero;
-                const V4 b0 = bok ? load4(A + (size_t)brow * ld + NB * (p - 1) + 4 * lk) : zero;
-                typename M::acc acc0;
-                for (int q = 0; q < 4; ++q) acc0[q] = R(0);
+            R* tl = pan + (size_t)u * NB * kSlotLd;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
-                const int col = c0 + li;
+            for (int q = 0; q < 4; ++q) tl[M::acc_row(lk, q) * kSlotLd + li] = acc0[q];
+            if (two) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row = c0 + NB * t + M::acc_row(lk, q);
-                    if (row < N && col < N && (t > 0 || row >= col)) A[(size_t)row * ld + col] += acc0[q];
+                    const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + NB + li;
+                    if (row < N && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] += acc1[q];
                 }
             }
         }
-        // partial tiles of this panel left by a split even update: tile t of this
-        // panel is slot (t + toff) + s me, columns coff .. coff + 15
-        const int PS = even ? S : Se;
-        const int toff = even ? 0 : 1, coff = even ? 0 : NB;
+        paired_prev = pair;
         __syncthreads();
         // (2) diagonal block: wavefront 0, lane l holds row l
         if (tid < 64) {
             const int l = tid;
             R row[NB];
-            if (jb == NB && l < NB) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const V4 q4 = load4(A + (size_t)(c0 + l) * ld + c0 + 4 * v);
+            for (int c = 0; c < NB; ++c) row[c] = (l < jb && c <= l) ? R(0) : (l == c ? R(1) : R(0));
+            if (l < jb) {
+                for (int s = 0; s < S; ++s) {
+                    const R* tl = pan + (size_t)(s * m) * NB * kSlotLd + l * kSlotLd;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) row[4 * v + e] = (4 * v + e <= l) ? q4[e] : R(0);
+                    for (int c = 0; c < NB; ++c)
+                        if (c <= l) row[c] += tl[c];
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-            } else {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    const bool valid = (l < jb) && (c <= l);
-                    row[c] = valid ? A[(size_t)(c0 + l) * ld + c0 + c] : (l == c ? R(1) : R(0));
-                }
-            }
-            for (int s = 0; s < PS && PS > 1; ++s) {
-                const R* sl = slots + (size_t)(toff + s * me) * NB * kPLd + (l & 15) * kPLd + coff;
-#pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (l < jb && c <= l) row[c] += sl[c];
-                __builtin_amdgcn_sched_barrier(0);
             }
             R invv[NB];   // 1 / L[c][c], the same in every lane
 #pragma unroll
@@ -318,22 +288,21 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             }
         }
         __syncthreads();
-        // (3) rows below the block: x L_pp^T = a, one row per thread
+        // (3) rows below the block: x L_pp^T = a, one row per thread, a from the
+        // panel buffer; the finished rows go to the matrix
+#pragma unroll 1
         for (int i = c0 + jb + tid; i < N; i += nthr) {
             const int t = (i - c0) / NB, lr = (i - c0) % NB;
-            R* ar = A + (size_t)i * ld + c0;
             R x[NB];
+            const R* tl0 = pan + (size_t)t * NB * kSlotLd + lr * kSlotLd;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const V4 q4 = load4(ar + 4 * v);
+            for (int c = 0; c < NB; ++c) x[c] = tl0[c];
+            for (int s = 1; s < S; ++s) {
+                const R* tl = pan + (size_t)(t + s * m) * NB * kSlotLd + lr * kSlotLd;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) x[4 * v + e] = q4[e];
+                for (int c = 0; c < NB; ++c) x[c] += tl[c];
             }
-            for (int s = 0; s < PS && PS > 1; ++s) {
-                const R* sl = slots + (size_t)(t + toff + s * me) * NB * kPLd + lr * kPLd + coff;
-#pragma unroll
-                for (int c = 0; c < NB; ++c) x[c] += sl[c];
-            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < NB; ++c) {  // column sweep; the barriers keep the LDS reads of L_pp
                 const R xc = (c < jb) ? x[c] * rinv[c] : R(0);  // next to their use
@@ -342,6 +311,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 for (int q = c + 1; q < NB; ++q) x[q] -= xc * Ld[q * kSlotLd + c];
                 __builtin_amdgcn_sched_barrier(0);
             }
+            R* ar = A + (size_t)i * ld + c0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 V4 q4;
@@ -352,16 +322,15 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         }
         __syncthreads();
     }
-    __syncthreads();
     ok = good;
 }
 
-// Solve L L^T Y = Y in place for 3 right-hand sides (Y in LDS, row-major N x 3,
-// blockDim >= N), with the stored inverses of the diagonal blocks.  Per block:
-// the 48 block values are products with Z (threads r + 16 c of wavefront 0,
-// Z staged in LDS by wavefront 1 a block ahead), then every other row takes the
-// block's contribution, one row per thread, its segment loaded a block ahead.
-// Apart from the first block, no step waits on device memory.
+// panel buffer tiles of the factorisation for neighbourhoods of up to n1max atoms
+__host__ __device__ inline int factor_tiles(int n1max) {
+    const int nt = (3 * n1max + NB - 1) / NB;
+    return nt > 4 ? nt : 4;
+}
+
 template <typename R>
 __device__ __forceinline__ void solve_row_update(const R* __restrict__ lrow, int c0, int jb, int i, R* Y) {
     R s0 = 0, s1 = 0, s2 = 0;
@@ -611,6 +580,7 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
     double* D = (mixed ? a.dvec : a.xsol) + a.x_off[k] + (size_t)w * N * 3;
     const int npairs = n1 * (n1 + 1) / 2;
     float* coef = mixed ? a.coef + a.coef_off[k] + (size_t)w * 2 * npairs : nullptr;
+    R* pd = a.pd1 ? static_cast<R*>(a.pd1) + a.pd1_off[k] + (size_t)w * 3 * npairs : nullptr;
     load_sites(a, k, w, n1, n12, L);
     __syncthreads();
 
@@ -650,30 +620,50 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
             coef[2 * p] = (float)t.A;
             coef[2 * p + 1] = (float)t.B;
         }
+        if (pd) {
+            pd[3 * p] = t.A;
+            pd[3 * p + 1] = t.dA;
+            pd[3 * p + 2] = t.dB;
+        }
         for (int q = 0; q < 3; ++q)
             for (int c = 0; c < 3; ++c)
                 A[(size_t)(3 * i + q) * ld + 3 * j + c] = R(double(t.A) * rh[q] * rh[c] + (q == c ? double(t.B) : 0.0));
     }
 }
 
-// Factorisation of B~ in place, one workgroup per (atom, frequency); LDS is a
-// fixed few kilobytes, so several factorisations share a compute unit.
+// Factorisation of B~ in place, one workgroup per (atom, frequency).  The
+// panel buffer is dynamic LDS; L_pp and 1/L_ii are separate static arrays so
+// that the compiler sees they cannot alias it (with one carved buffer it
+// spilled the diagonal step's registers).
 template <typename R>
-__global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a) {
-    __shared__ R slots[kMaxSplitSlots * NB * kPLd];
+__global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
+    extern __shared__ double lds[];
     __shared__ R Ld[NB * kSlotLd];
     __shared__ R rinv[NB];
+    R* pan = reinterpret_cast<R*>(lds);
     const int k = blockIdx.x;
     const int w = blockIdx.y;
     const int N = 3 * a.counts[k].n1;
     const int ld = a.fac_ld[k];
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
     bool ok = true;
-    chol_factor<R>(A, N, ld, slots, Ld, rinv, ok);
+    chol_factor<R>(A, N, ld, pan, Ld, rinv, ok);
     if (!ok && threadIdx.x == 0) {
         atomicOr(a.err, 4);
         atomicMin(a.err_atom, k);
     }
+}
+
+// dynamic LDS of the factorisation (the panel buffer)
+static size_t factor_panel_bytes(int n1max, bool mixed) {
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return r * (size_t)factor_tiles(n1max) * NB * kSlotLd;
+}
+
+// all LDS of the factorisation: panel buffer, L_pp and 1/L_ii
+size_t scs_factor_lds_bytes(int n1max, bool mixed) {
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return factor_panel_bytes(n1max, mixed) + r * (NB * kSlotLd + NB);
 }
 
 // Triangular solves with the stored factor, one workgroup of >= N threads per
@@ -815,6 +805,7 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
     ScsLds L = scs_lds(lds, n1max, n2max);
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
     const double* Lg = a.lam + a.x_off[k] + (size_t)w * N * 3;
+    const R* pd = static_cast<const R*>(a.pd1) + a.pd1_off[k] + (size_t)w * 3 * (n1 * (n1 + 1) / 2);
     load_sites(a, k, w, n1, n12, L);
     for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
         L.X[e] = Xg[e];
@@ -838,9 +829,12 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
         for (int j = part; j < n1; j += kParts) {
             if (j == i) continue;
             const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-            if (!(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc)) continue;
-            double rh[3], r;
-            const SrPair<R> tp = k1_pair<R>(a, L, i, j, rc, rh, r);
+            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            if (!(r2 < rc * rc)) continue;
+            const double r = sqrt(r2), ir = 1.0 / r;
+            const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
+            const R* t3 = pd + 3 * (size_t)(i > j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i);  // from the assembly
+            const SrPair<R> tp = {t3[0], R(0), t3[1], t3[2]};
             double Yj[9], Xj[9];
             for (int e = 0; e < 9; ++e) {
                 Yj[e] = L.Y[(3 * j + e / 3) * 3 + e % 3];
@@ -1009,10 +1003,11 @@ hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int 
     return hipGetLastError();
 }
 
-hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, bool mixed) {
+hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
     const dim3 grid(a.n, a.nw);
-    if (mixed) hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), 0, st, a);
+    const size_t lf = factor_panel_bytes(n1max, mixed);
+    if (mixed) hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), lf, st, a, n1max);
+    else hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), lf, st, a, n1max);
     return hipGetLastError();
 }
 

@@ -169,6 +169,8 @@ struct ScsArgs {
     const int32_t* fac_ld;   // ld >= N, a multiple of 4
     float* coef;             // mixed path: FP32 pair coefficients (A, B) of B~, per atom nw * n1 (n1 + 1) / 2 pairs
     const int64_t* coef_off; // per atom, in floats
+    void* pd1;               // forces: (A, dA/dr, dB/dr) of every K1 pair tensor in the matrix type, per atom
+    const int64_t* pd1_off;  //   nw * n1 (n1 + 1) / 2 triples in the pair order of the assembly; offsets in elements
     double* xsol;            // per atom nw * N * 3 (row-major): d, then the solution X
     double* dvec;            // mixed path: d (same layout)
     double* resid;           // mixed path: refinement residual (same layout)
@@ -232,7 +234,8 @@ hipError_t launch_rev_map(hipStream_t st, int n, const Counts* counts, const int
                           int32_t* table, size_t table_len, int32_t* rev, int* err);
 size_t scs_lds_bytes(int n1max, int n2max, bool mixed);
 hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
-hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, bool mixed);
+hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
+size_t scs_factor_lds_bytes(int n1max, bool mixed);
 hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
