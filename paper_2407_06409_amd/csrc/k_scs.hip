@@ -100,12 +100,16 @@ __device__ inline void inner_buffer(double r, double rin, double& fin, double& d
 //      update is not split also applies the same loaded chunks to the next
 //      panel's columns (in place in the matrix), so the odd panel after it
 //      only needs the one chunk just finished;
-//  (2) diagonal block: wavefront 0 factorises it from the panel buffer (lane
-//      l holds row l, values of other rows are broadcast with lane reads),
-//      keeps L_pp and 1/L_ii in LDS, and inverts it into the block's strict
-//      upper part;
-//  (3) rows below: one row per thread reads its row from the panel buffer,
-//      solves x L_pp^T = a by substitution and writes the finished row.
+//  (2) diagonal block: one wavefront factorises it from the panel buffer
+//      (lane l holds row l, values of other rows are broadcast with lane
+//      reads) and inverts it, Z = L_pp^{-1}, into the block's strict upper
+//      part and into LDS.  When the update is not split, this wavefront
+//      updates only the diagonal tile and starts at once, while the others
+//      update the tiles below; which wavefront it is rotates over the
+//      workgroups, so that the diagonal steps of the workgroups sharing a
+//      compute unit spread over its SIMDs;
+//  (3) rows below: X = A Z^T on MFMA, one 16-row tile per wavefront, read
+//      from the panel buffer and written to the matrix.
 // LDS use is one 16-row tile per 16 rows of the neighbourhood (about 2 KB per
 // tile in FP64), so several factorisations share a compute unit and hide
 // each other's memory latency.
@@ -144,8 +148,8 @@ __device__ inline typename Vec4T<R>::type load4(const R* p) {
 
 
 template <typename R>
-__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ pan, R* __restrict__ Ld,
-                                            R* __restrict__ rinv, bool& ok) {
+__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ pan, R* __restrict__ Zs,
+                                            int dw, bool& ok) {
     typedef Mfma<R> M;
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
@@ -168,10 +172,24 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         // next panel's columns (in place), so that panel only needs the last chunk
         const bool pair = (p % 2 == 0) && p > 0 && S == 1 && !only_last && p + 1 < nt;
         const int U = m * S;
+        // with an unsplit update the diagonal wave updates tile 0 alone and
+        // factorises it at once, while the other waves update the tiles below
+        const bool early = (S == 1) && nwave > 1;
+        int u0, ustep;
+        if (!early) {
+            u0 = (wave - dw + nwave) % nwave;
+            ustep = nwave;
+        } else if (wave == dw) {
+            u0 = 0;
+            ustep = U;
+        } else {
+            u0 = 1 + (wave - dw - 1 + nwave) % nwave;
+            ustep = nwave - 1;
+        }
         // (1) update: one (row tile, k-split) unit per wavefront; the unit with
         // s = 0 starts from the matrix, the others from zero; results (partial
         // tiles for s > 0) go to the panel buffer in LDS, tile u = t + s m
-        for (int u = wave; u < U; u += nwave) {
+        for (int u = u0; u < U; u += ustep) {
             const int t = u % m, s = u / m;
             const bool two = pair && t > 0;
             typename M::acc acc0, acc1;
@@ -224,10 +242,12 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             }
         }
         paired_prev = pair;
-        __syncthreads();
-        // (2) diagonal block: wavefront 0, lane l holds row l
-        if (tid < 64) {
-            const int l = tid;
+        if (!early) __syncthreads();
+        // (2) diagonal block: the diagonal wave, lane l holds row l (in the early
+        // case it reads back the tile it has just written itself)
+        if (wave == dw) {
+            const int l = lane;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             R row[NB];
 #pragma unroll
             for (int c = 0; c < NB; ++c) row[c] = (l < jb && c <= l) ? R(0) : (l == c ? R(1) : R(0));
@@ -256,14 +276,6 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (l < NB) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) Ld[l * kSlotLd + c] = (c <= l) ? row[c] : R(0);
-            }
-            if (l == 0) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) rinv[c] = invv[c];
-            }
             if (l < jb) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
@@ -271,7 +283,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             }
             // Z = L_pp^{-1}, lane j < 16 holds column j (forward substitution with
             // the rows of L broadcast from their lanes); Z[q][j] (q > j) is stored
-            // at (c0 + j, c0 + q)
+            // at (c0 + j, c0 + q), and all of Z row-major in LDS
             R z[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
@@ -281,6 +293,10 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 z[q] = v * invv[q];
                 __builtin_amdgcn_sched_barrier(0);
             }
+            if (l < NB) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) Zs[q * kSlotLd + l] = z[q];
+            }
             if (l < jb) {
 #pragma unroll
                 for (int q = 0; q < NB; ++q)
@@ -288,36 +304,23 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             }
         }
         __syncthreads();
-        // (3) rows below the block: x L_pp^T = a, one row per thread, a from the
-        // panel buffer; the finished rows go to the matrix
-#pragma unroll 1
-        for (int i = c0 + jb + tid; i < N; i += nthr) {
-            const int t = (i - c0) / NB, lr = (i - c0) % NB;
-            R x[NB];
-            const R* tl0 = pan + (size_t)t * NB * kSlotLd + lr * kSlotLd;
+        // (3) rows below the block: X = A Z^T on MFMA, one 16-row tile per
+        // wavefront, A summed over the k-split parts in the panel buffer
+        for (int t = 1 + (wave - dw + nwave) % nwave; t < m; t += nwave) {
+            typename M::acc x;
 #pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = tl0[c];
-            for (int s = 1; s < S; ++s) {
-                const R* tl = pan + (size_t)(t + s * m) * NB * kSlotLd + lr * kSlotLd;
+            for (int q = 0; q < 4; ++q) x[q] = R(0);
 #pragma unroll
-                for (int c = 0; c < NB; ++c) x[c] += tl[c];
+            for (int e = 0; e < 4; ++e) {
+                const int kk = 4 * lk + e;
+                R av = pan[(size_t)t * NB * kSlotLd + li * kSlotLd + kk];
+                for (int s = 1; s < S; ++s) av += pan[(size_t)(t + s * m) * NB * kSlotLd + li * kSlotLd + kk];
+                x = M::mma(av, Zs[li * kSlotLd + kk], x);
             }
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {  // column sweep; the barriers keep the LDS reads of L_pp
-                const R xc = (c < jb) ? x[c] * rinv[c] : R(0);  // next to their use
-                x[c] = xc;
-#pragma unroll
-                for (int q = c + 1; q < NB; ++q) x[q] -= xc * Ld[q * kSlotLd + c];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            R* ar = A + (size_t)i * ld + c0;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                V4 q4;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) q4[e] = x[4 * v + e];
-                *reinterpret_cast<V4*>(ar + 4 * v) = q4;
+            for (int q = 0; q < 4; ++q) {
+                const int row = c0 + NB * t + M::acc_row(lk, q);
+                if (row < N) A[(size_t)row * ld + c0 + li] = x[q];
             }
         }
         __syncthreads();
@@ -580,7 +583,6 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
     double* D = (mixed ? a.dvec : a.xsol) + a.x_off[k] + (size_t)w * N * 3;
     const int npairs = n1 * (n1 + 1) / 2;
     float* coef = mixed ? a.coef + a.coef_off[k] + (size_t)w * 2 * npairs : nullptr;
-    R* pd = a.pd1 ? static_cast<R*>(a.pd1) + a.pd1_off[k] + (size_t)w * 3 * npairs : nullptr;
     load_sites(a, k, w, n1, n12, L);
     __syncthreads();
 
@@ -620,11 +622,6 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
             coef[2 * p] = (float)t.A;
             coef[2 * p + 1] = (float)t.B;
         }
-        if (pd) {
-            pd[3 * p] = t.A;
-            pd[3 * p + 1] = t.dA;
-            pd[3 * p + 2] = t.dB;
-        }
         for (int q = 0; q < 3; ++q)
             for (int c = 0; c < 3; ++c)
                 A[(size_t)(3 * i + q) * ld + 3 * j + c] = R(double(t.A) * rh[q] * rh[c] + (q == c ? double(t.B) : 0.0));
@@ -632,23 +629,24 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
 }
 
 // Factorisation of B~ in place, one workgroup per (atom, frequency).  The
-// panel buffer is dynamic LDS; L_pp and 1/L_ii are separate static arrays so
-// that the compiler sees they cannot alias it (with one carved buffer it
+// panel buffer is dynamic LDS; Z is a separate static array so that the
+// compiler sees it cannot alias the panel buffer (with one carved buffer it
 // spilled the diagonal step's registers).
 template <typename R>
 __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
-    __shared__ R Ld[NB * kSlotLd];
-    __shared__ R rinv[NB];
+    __shared__ R Zs[NB * kSlotLd];
     R* pan = reinterpret_cast<R*>(lds);
     const int k = blockIdx.x;
     const int w = blockIdx.y;
     const int N = 3 * a.counts[k].n1;
     const int ld = a.fac_ld[k];
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
+    // the wave that factorises the diagonal blocks rotates over the workgroups
+    const int dw = (k + w) % (blockDim.x >> 6);
     bool ok = true;
-    chol_factor<R>(A, N, ld, pan, Ld, rinv, ok);
-    if (!ok && threadIdx.x == 0) {
+    chol_factor<R>(A, N, ld, pan, Zs, dw, ok);
+    if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
         atomicOr(a.err, 4);
         atomicMin(a.err_atom, k);
     }
@@ -660,10 +658,10 @@ static size_t factor_panel_bytes(int n1max, bool mixed) {
     return r * (size_t)factor_tiles(n1max) * NB * kSlotLd;
 }
 
-// all LDS of the factorisation: panel buffer, L_pp and 1/L_ii
+// all LDS of the factorisation: panel buffer and Z = L_pp^{-1}
 size_t scs_factor_lds_bytes(int n1max, bool mixed) {
     const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return factor_panel_bytes(n1max, mixed) + r * (NB * kSlotLd + NB);
+    return factor_panel_bytes(n1max, mixed) + r * NB * kSlotLd;
 }
 
 // Triangular solves with the stored factor, one workgroup of >= N threads per
@@ -805,7 +803,6 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
     ScsLds L = scs_lds(lds, n1max, n2max);
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
     const double* Lg = a.lam + a.x_off[k] + (size_t)w * N * 3;
-    const R* pd = static_cast<const R*>(a.pd1) + a.pd1_off[k] + (size_t)w * 3 * (n1 * (n1 + 1) / 2);
     load_sites(a, k, w, n1, n12, L);
     for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
         L.X[e] = Xg[e];
@@ -829,12 +826,9 @@ __global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n
         for (int j = part; j < n1; j += kParts) {
             if (j == i) continue;
             const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-            const double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-            if (!(r2 < rc * rc)) continue;
-            const double r = sqrt(r2), ir = 1.0 / r;
-            const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
-            const R* t3 = pd + 3 * (size_t)(i > j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i);  // from the assembly
-            const SrPair<R> tp = {t3[0], R(0), t3[1], t3[2]};
+            if (!(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc)) continue;
+            double rh[3], r;
+            const SrPair<R> tp = k1_pair<R>(a, L, i, j, rc, rh, r);
             double Yj[9], Xj[9];
             for (int e = 0; e < 9; ++e) {
                 Yj[e] = L.Y[(3 * j + e / 3) * 3 + e % 3];

@@ -38,9 +38,9 @@ struct Plan {
     int64_t n_atoms = 0;
     int64_t total_sites = 0;
     int64_t table_len = 0;
-    int64_t fac_len = 0, x_len = 0, aloc_len = 0, work_len = 0, coef_len = 0, pd1_len = 0;
+    int64_t fac_len = 0, x_len = 0, aloc_len = 0, work_len = 0, coef_len = 0;
     int n1max = 0, nkmax = 0, nallmax = 0, n2max = 0;
-    std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off, coef_off, pd1_off;
+    std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off, coef_off;
     int64_t pl_len = 0;
     std::vector<int32_t> hash_cap, fac_ld;
 };
@@ -57,7 +57,7 @@ struct lmbd_context {
     DBuf site_off, sites, hash_off, hash_cap, table, rev;
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
-    DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam, pd1, pd1_off;
+    DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam;
     DBuf e_out, f_out, a_out;
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
@@ -75,7 +75,7 @@ struct lmbd_context {
         &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
-        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, &c->pd1, &c->pd1_off
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam
 
 namespace {
 
@@ -262,11 +262,10 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.work_off.resize(n + 1);
     P.pl_off.resize(n + 1);
     P.coef_off.resize(n + 1);
-    P.pd1_off.resize(n + 1);
     P.hash_cap.resize(n);
     P.fac_ld.resize(n);
     const int mmax = forces ? std::max(1, n_max - 1) : std::max(1, (n_max + 1) / 2);
-    int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0, po = 0, co = 0, d1 = 0;
+    int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0, po = 0, co = 0;
     P.n1max = P.nkmax = P.nallmax = P.n2max = 0;
     for (int64_t k = 0; k < n; ++k) {
         const Counts& c = cnt[k];
@@ -278,8 +277,6 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         P.work_off[k] = wo;
         P.pl_off[k] = po;
         P.coef_off[k] = co;
-        P.pd1_off[k] = d1;
-        if (forces) d1 += (int64_t)nw * 3 * ((int64_t)c.n1 * (c.n1 + 1) / 2);
         po += (int64_t)c.n1 * (c.n12 - c.n1);
         if (mixed) co += (int64_t)nw * c.n1 * (c.n1 + 1);
         const int64_t N1 = 3 * (int64_t)c.n1, N3 = 3 * (int64_t)c.nK;
@@ -307,7 +304,6 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.work_len = wo;
     P.pl_len = po;
     P.coef_len = co;
-    P.pd1_len = d1;
 }
 
 template <typename T>
@@ -373,7 +369,7 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
     if (forces) {
         const std::pair<DBuf*, size_t> F2[] = {
             {&c->ca, TS * nw * D}, {&c->cf, (size_t)(1 + nw) * TS * 3 * D}, {&c->f_out, 3 * N * D},
-            {&c->lam, (size_t)P.x_len * D}, {&c->pd1, (size_t)P.pd1_len * wsz}, {&c->pd1_off, N * L8}};
+            {&c->lam, (size_t)P.x_len * D}};
         for (const auto& e : F2) {
             const hipError_t r = get(*e.first, e.second);
             if (r != hipSuccess) return r;
@@ -843,10 +839,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     std::vector<int64_t> wo(P.work_off.begin(), P.work_off.end() - 1);
     std::vector<int64_t> plo(P.pl_off.begin(), P.pl_off.end() - 1);
     std::vector<int64_t> coo(P.coef_off.begin(), P.coef_off.end() - 1);
-    std::vector<int64_t> pdo(P.pd1_off.begin(), P.pd1_off.end() - 1);
     if ((st = upload(ctx, ctx->pl_off, plo, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->coef_off, coo, stream)) != LMBD_OK) return st;
-    if (forces && (st = upload(ctx, ctx->pd1_off, pdo, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->site_off, so, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->hash_off, ho, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->hash_cap, P.hash_cap, stream)) != LMBD_OK) return st;
@@ -887,8 +881,6 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.fac_ld = as<int32_t>(ctx->fac_ld);
     sa.coef = mixed ? as<float>(ctx->coef) : nullptr;
     sa.coef_off = as<int64_t>(ctx->coef_off);
-    sa.pd1 = forces ? ctx->pd1.p : nullptr;
-    sa.pd1_off = forces ? as<int64_t>(ctx->pd1_off) : nullptr;
     sa.xsol = as<double>(ctx->xsol);
     sa.dvec = mixed ? as<double>(ctx->dvec) : nullptr;
     sa.resid = mixed ? as<double>(ctx->resid) : nullptr;

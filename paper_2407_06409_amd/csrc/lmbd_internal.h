@@ -169,8 +169,6 @@ struct ScsArgs {
     const int32_t* fac_ld;   // ld >= N, a multiple of 4
     float* coef;             // mixed path: FP32 pair coefficients (A, B) of B~, per atom nw * n1 (n1 + 1) / 2 pairs
     const int64_t* coef_off; // per atom, in floats
-    void* pd1;               // forces: (A, dA/dr, dB/dr) of every K1 pair tensor in the matrix type, per atom
-    const int64_t* pd1_off;  //   nw * n1 (n1 + 1) / 2 triples in the pair order of the assembly; offsets in elements
     double* xsol;            // per atom nw * N * 3 (row-major): d, then the solution X
     double* dvec;            // mixed path: d (same layout)
     double* resid;           // mixed path: refinement residual (same layout)
