@@ -20,7 +20,6 @@
 namespace lmbd {
 
 constexpr int NB = 16;      // block size of the factorisation
-constexpr int kParts = 4;   // partner-range splits of the per-site pair loops (adjoint)
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -467,10 +466,14 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
 struct ScsLds {
     double *px, *py, *pz, *ab, *sg, *R;        // K1 sites
     double *qx, *qy, *qz, *qab, *qsg, *qR;     // shell sites
-    double* red;                               // reduction area
-    double *Y, *X;
-    void* Yr;                                  // solve buffer (matrix type)
+    double *Y, *X;                             // adjoint: lambda and X, 3N x 3 each
+    double* H;                                 // adjoint: pair terms of one chunk, 3 per thread
+    double *gk, *gq;                           // adjoint: per-site sums (K1, shell), 3 each
+    int32_t* key;                              // adjoint: reduction key of each thread's pair
 };
+
+constexpr int kAdjThreads = 256;   // threads of the adjoint kernel = pairs per chunk
+static_assert(kAdjThreads >= kMaxN1, "the adjoint gives every K1 site a thread of its own");
 
 __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     const int N = 3 * n1max;
@@ -481,22 +484,30 @@ __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     L.ab = L.pz + n1max;
     L.sg = L.ab + n1max;
     L.R = L.sg + n1max;
-    L.Y = L.R + n1max;
-    L.X = L.Y + 3 * N;
-    L.Yr = L.X + 3 * N;
-    L.qx = L.X + 6 * N;   // Yr takes at most 3N doubles
+    L.qx = L.R + n1max;
     L.qy = L.qx + n2max;
     L.qz = L.qy + n2max;
     L.qab = L.qz + n2max;
     L.qsg = L.qab + n2max;
     L.qR = L.qsg + n2max;
-    L.red = L.qR + n2max;
+    L.Y = L.qR + n2max;
+    L.X = L.Y + 3 * N;
+    L.H = L.X + 3 * N;
+    L.gk = L.H + 3 * kAdjThreads;
+    L.gq = L.gk + 3 * n1max;
+    L.key = reinterpret_cast<int32_t*>(L.gq + 3 * n2max);
     return L;
 }
 
 size_t scs_lds_bytes(int n1max, int n2max, bool) {
     const size_t N = 3 * (size_t)n1max;
-    return sizeof(double) * (6 * (size_t)n1max + 9 * N + 6 * (size_t)n2max + (size_t)kParts * 3 * n1max);
+    return sizeof(double) * (9 * (size_t)n1max + 6 * N + 9 * (size_t)n2max + 3 * kAdjThreads) +
+           sizeof(int32_t) * kAdjThreads;
+}
+
+// CSR offsets of the pair lists of atom k (i, q, a, b; see ScsArgs)
+__device__ inline int32_t* pair_segs(const ScsArgs& a, int k) {
+    return const_cast<int32_t*>(a.pl_seg) + 3 * (a.site_off[k] + 2 * (int64_t)k);
 }
 
 // sites only (assembly): K1 sites then shell sites
@@ -588,12 +599,13 @@ __global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int 
 
     // d: the shell K2 (TS polarisabilities, f_inner), one K1 site per thread over
     // its segment of the compact list of coupled (K1 site, shell site) pairs
-    const int32_t* seg_i = a.pl_seg + a.site_off[k] + 2 * (int64_t)k;
+    const int32_t* seg_i = pair_segs(a, k);
     const int32_t* li = a.pl_i + a.pl_off[k];
+    const int32_t* lq = a.pl_q + a.pl_off[k];
     for (int i = threadIdx.x; i < n1; i += blockDim.x) {
         double d[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
         for (int e = seg_i[i]; e < seg_i[i + 1]; ++e) {
-            const int q = li[e] & 0xFFFF;
+            const int q = lq[li[e]] >> 16;
             double rh[3], r;
             const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
             const double A_ = tp.A, B_ = tp.B, ab = L.qab[q];
@@ -782,140 +794,254 @@ size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)
 // Adjoint.  With X = B~^{-1} d and seeds xbar_i (adjoint of alpha~_iso_i =
 // Tr X_i / 3): lambda = B~^{-1} Xbar with Xbar_i = xbar_i I / 3, then
 //   dE = -<lambda X^T, dB~> + <lambda, dd>.
-// Per site, the gradient sums over its partners (each pair is evaluated from
-// both ends; partner ranges are split over kParts threads and recombined in a
-// fixed order), so the result does not depend on scheduling.  The mixed path
+// Each coupled pair is evaluated once: the gradient of its term with respect
+// to the first site is h, with respect to the second -h.  The pairs are taken
+// in chunks of one per thread; h goes to LDS, the first sites' sums are formed
+// over the runs of equal first site in the chunk (by the run's first thread),
+// and each K1 site's thread walks its index list over the other side.  Sums
+// are thus formed in a fixed order, independent of scheduling.  The mixed path
 // solves for lambda in FP32 and evaluates the pair-tensor derivatives in FP32;
 // contractions and sums are FP64.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(256) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
+__global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
-    constexpr bool mixed = sizeof(R) == 4;
     const int k = blockIdx.x;
     const int w = blockIdx.y;
+    const int t = threadIdx.x;
     const Counts cnt = a.counts[k];
     const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1, nall = cnt.n_all;
     const int N = 3 * n1;
-    const int ld = a.fac_ld[k];
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rc = SI.r_scs;
     ScsLds L = scs_lds(lds, n1max, n2max);
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
     const double* Lg = a.lam + a.x_off[k] + (size_t)w * N * 3;
     load_sites(a, k, w, n1, n12, L);
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
+    for (int e = t; e < 3 * N; e += kAdjThreads) {
         L.X[e] = Xg[e];
         L.Y[e] = Lg[e];
+    }
+    for (int e = t; e < 3 * n1; e += kAdjThreads) L.gk[e] = 0.0;
+    for (int e = t; e < 3 * n2; e += kAdjThreads) L.gq[e] = 0.0;
+    const int32_t* seg = pair_segs(a, k);
+    const int32_t* seg_i = seg;
+    const int32_t* seg_q = seg + (n1 + 1);
+    const int32_t* seg_a = seg + (n12 + 2);
+    const int32_t* seg_b = seg + (n12 + n1 + 3);
+    const int32_t* li = a.pl_i + a.pl_off[k];
+    const int32_t* lq = a.pl_q + a.pl_off[k];
+    const int32_t* la = li + (int64_t)n1 * n2;
+    const int32_t* lb = lq + (int64_t)n1 * n2;
+    __syncthreads();
+
+    constexpr int kWaves = kAdjThreads / 64;
+    __shared__ double carry[3 * kWaves];
+    __shared__ int carry_key[kWaves];
+    const int lane = t & 63, wave = t >> 6;
+    // the chunk's runs of equal key: each run's sum goes to acc[3 key].  Sums
+    // within a wavefront by segmented suffix sums over the lanes; the part of
+    // a run that continues from the previous wavefront is left in carry[] and
+    // added by thread 0 (in wavefront order) after the next barrier
+    auto run_sums = [&](int key, double h0, double h1, double h2, double* acc) {
+        for (int d = 1; d < 64; d <<= 1) {
+            const int kd = __shfl_down(key, d);
+            const double u0 = __shfl_down(h0, d), u1 = __shfl_down(h1, d), u2 = __shfl_down(h2, d);
+            if (lane + d < 64 && kd == key) {
+                h0 += u0;
+                h1 += u1;
+                h2 += u2;
+            }
+        }
+        const int kprev = t > 0 ? L.key[t - 1] : -2;
+        const bool cont = lane == 0 && wave > 0 && key >= 0 && kprev == key;
+        if (lane == 0 && wave > 0) carry_key[wave] = cont ? key : -1;
+        if (cont) {
+            carry[3 * wave + 0] = h0;
+            carry[3 * wave + 1] = h1;
+            carry[3 * wave + 2] = h2;
+        } else if (key >= 0 && (lane == 0 || kprev != key)) {
+            acc[3 * key + 0] += h0;
+            acc[3 * key + 1] += h1;
+            acc[3 * key + 2] += h2;
+        }
+    };
+    auto add_carries = [&](double* acc) {
+        if (t != 0) return;
+        for (int v = 1; v < kWaves; ++v) {
+            const int key = carry_key[v];
+            if (key < 0) continue;
+            acc[3 * key + 0] += carry[3 * v + 0];
+            acc[3 * key + 1] += carry[3 * v + 1];
+            acc[3 * key + 2] += carry[3 * v + 2];
+        }
+    };
+    // K1 site t's index list over the other side: the next entries are loaded
+    // before the chunk's pair is evaluated, and the terms of the pairs in this
+    // chunk are subtracted from g after the barrier
+    constexpr int kAhead = 8;
+    int ahead[kAhead];
+    auto prefetch = [&](const int32_t* lst, int p, int pe) {
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) ahead[j] = p + j < pe ? lst[p + j] : 0x7fffffff;
+    };
+    auto consume = [&](const int32_t* lst, int& p, int pe, int e1, double* g) {
+        bool more = true;
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) {
+            more = more && ahead[j] < e1;
+            if (more) {
+                const int u = ahead[j] - (e1 - kAdjThreads);
+                g[0] -= L.H[3 * u + 0];
+                g[1] -= L.H[3 * u + 1];
+                g[2] -= L.H[3 * u + 2];
+                ++p;
+            }
+        }
+        if (more) {
+            for (; p < pe && lst[p] < e1; ++p) {
+                const int u = lst[p] - (e1 - kAdjThreads);
+                g[0] -= L.H[3 * u + 0];
+                g[1] -= L.H[3 * u + 1];
+                g[2] -= L.H[3 * u + 2];
+            }
+        }
+    };
+
+    double gb[3] = {0.0, 0.0, 0.0};   // K1 site t as the second site of K1 x K1 pairs
+    double gi[3] = {0.0, 0.0, 0.0};   // K1 site t against the shell
+    // K1 x K1 pairs a < b: h = gradient of the pair's term with respect to r_a
+    {
+        const int P = seg_a[n1];
+        int p = t < n1 ? seg_b[t] : 0;
+        const int pe = t < n1 ? seg_b[t + 1] : 0;
+        for (int e0 = 0; e0 < P; e0 += kAdjThreads) {
+            prefetch(lb, p, pe);
+            const int e = e0 + t;
+            int key = -1;
+            double h[3] = {0.0, 0.0, 0.0};
+            if (e < P) {
+                const int32_t ent = la[e];
+                const int i = ent >> 16, j = ent & 0xFFFF;
+                key = i;
+                double rh[3], r;
+                const SrPair<R> tp = k1_pair<R>(a, L, i, j, rc, rh, r);
+                const double* Xi = L.X + 9 * i;
+                const double* Yi = L.Y + 9 * i;
+                const double* Xj = L.X + 9 * j;
+                const double* Yj = L.Y + 9 * j;
+                double Cs[9];
+                for (int q = 0; q < 3; ++q)
+                    for (int c = q; c < 3; ++c) {
+                        double s1 = 0.0, s2 = 0.0;
+                        for (int m = 0; m < 3; ++m) {
+                            s1 += Yi[3 * q + m] * Xj[3 * c + m] + Yi[3 * c + m] * Xj[3 * q + m];
+                            s2 += Xi[3 * q + m] * Yj[3 * c + m] + Xi[3 * c + m] * Yj[3 * q + m];
+                        }
+                        Cs[3 * q + c] = -0.5 * (s1 + s2);
+                        Cs[3 * c + q] = Cs[3 * q + c];
+                    }
+                radial_tensor_grad(rh, r, double(tp.A), double(tp.dA), double(tp.dB), Cs, h);
+            }
+            L.key[t] = key;
+            L.H[3 * t + 0] = h[0];
+            L.H[3 * t + 1] = h[1];
+            L.H[3 * t + 2] = h[2];
+            __syncthreads();
+            run_sums(key, h[0], h[1], h[2], L.gk);
+            if (t < n1) consume(lb, p, pe, e0 + kAdjThreads, gb);
+            __syncthreads();
+            add_carries(L.gk);
+        }
+    }
+    // K1 x shell pairs, shell-major: h = qab_q * (gradient of the lambda_i : dd_i
+    // term with respect to r_i); the shell site gains h, the K1 site loses it
+    {
+        const int P = seg_q[n2];
+        int p = t < n1 ? seg_i[t] : 0;
+        const int pe = t < n1 ? seg_i[t + 1] : 0;
+        for (int e0 = 0; e0 < P; e0 += kAdjThreads) {
+            prefetch(li, p, pe);
+            const int e = e0 + t;
+            int key = -1;
+            double h[3] = {0.0, 0.0, 0.0};
+            if (e < P) {
+                const int32_t ent = lq[e];
+                const int q = ent >> 16, i = ent & 0xFFFF;
+                key = q;
+                double rh[3], r;
+                const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
+                const double* Yi = L.Y + 9 * i;
+                double lam[9];
+                for (int e2 = 0; e2 < 3; ++e2)
+                    for (int c = 0; c < 3; ++c) lam[3 * e2 + c] = 0.5 * (Yi[3 * e2 + c] + Yi[3 * c + e2]);
+                double gp[3];
+                radial_tensor_grad(rh, r, double(tp.A), double(tp.dA), double(tp.dB), lam, gp);
+                const double ab = L.qab[q];
+                h[0] = ab * gp[0];
+                h[1] = ab * gp[1];
+                h[2] = ab * gp[2];
+            }
+            L.key[t] = key;
+            L.H[3 * t + 0] = h[0];
+            L.H[3 * t + 1] = h[1];
+            L.H[3 * t + 2] = h[2];
+            __syncthreads();
+            run_sums(key, h[0], h[1], h[2], L.gq);
+            if (t < n1) consume(li, p, pe, e0 + kAdjThreads, gi);
+            __syncthreads();
+            add_carries(L.gq);
+        }
     }
     __syncthreads();
 
     double* out = a.cf + (size_t)w * a.cf_slice + a.site_off[k] * 3;
     const double fconv = -1.0 / kBohr;  // force = -dE/dx, per Angstrom
-    const int32_t* seg_i = a.pl_seg + a.site_off[k] + 2 * (int64_t)k;
-    const int32_t* li = a.pl_i + a.pl_off[k];
-    // K1 sites: couplings inside B~ and to the shell through d
-    for (int t = threadIdx.x; t < n1 * kParts; t += blockDim.x) {
-        const int i = t % n1, part = t / n1;
-        double g[3] = {0.0, 0.0, 0.0};
-        double Yi[9], Xi[9];
-        for (int e = 0; e < 9; ++e) {
-            Yi[e] = L.Y[(3 * i + e / 3) * 3 + e % 3];
-            Xi[e] = L.X[(3 * i + e / 3) * 3 + e % 3];
-        }
-        for (int j = part; j < n1; j += kParts) {
-            if (j == i) continue;
-            const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-            if (!(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] < rc * rc)) continue;
-            double rh[3], r;
-            const SrPair<R> tp = k1_pair<R>(a, L, i, j, rc, rh, r);
-            double Yj[9], Xj[9];
-            for (int e = 0; e < 9; ++e) {
-                Yj[e] = L.Y[(3 * j + e / 3) * 3 + e % 3];
-                Xj[e] = L.X[(3 * j + e / 3) * 3 + e % 3];
-            }
-            double Cs[9];
-            for (int q = 0; q < 3; ++q)
-                for (int c = 0; c < 3; ++c) {
-                    double s1 = 0.0, s2 = 0.0;
-                    for (int m = 0; m < 3; ++m) {
-                        s1 += Yi[3 * q + m] * Xj[3 * c + m] + Yi[3 * c + m] * Xj[3 * q + m];
-                        s2 += Xi[3 * q + m] * Yj[3 * c + m] + Xi[3 * c + m] * Yj[3 * q + m];
-                    }
-                    Cs[3 * q + c] = -0.5 * (s1 + s2);
-                }
-            double gp[3];
-            radial_tensor_grad(rh, r, double(tp.A), double(tp.dA), double(tp.dB), Cs, gp);
-            g[0] += gp[0];
-            g[1] += gp[1];
-            g[2] += gp[2];
-        }
-        double lam[9];
-        for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) lam[3 * q + c] = 0.5 * (Yi[3 * q + c] + Yi[3 * c + q]);
-        for (int e = seg_i[i] + part; e < seg_i[i + 1]; e += kParts) {
-            const int q = li[e] & 0xFFFF;
-            double rh[3], r;
-            const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
-            double gp[3];
-            radial_tensor_grad(rh, r, double(tp.A), double(tp.dA), double(tp.dB), lam, gp);
-            g[0] -= L.qab[q] * gp[0];
-            g[1] -= L.qab[q] * gp[1];
-            g[2] -= L.qab[q] * gp[2];
-        }
-        L.red[(size_t)(part * n1 + i) * 3 + 0] = g[0];
-        L.red[(size_t)(part * n1 + i) * 3 + 1] = g[1];
-        L.red[(size_t)(part * n1 + i) * 3 + 2] = g[2];
+    if (t < n1) {
+        for (int c = 0; c < 3; ++c) out[3 * t + c] = fconv * ((L.gk[3 * t + c] + gb[c]) + gi[c]);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-        for (int part = 0; part < kParts; ++part) {
-            g0 += L.red[(size_t)(part * n1 + i) * 3 + 0];
-            g1 += L.red[(size_t)(part * n1 + i) * 3 + 1];
-            g2 += L.red[(size_t)(part * n1 + i) * 3 + 2];
-        }
-        out[3 * i + 0] = fconv * g0;
-        out[3 * i + 1] = fconv * g1;
-        out[3 * i + 2] = fconv * g2;
-    }
-    // shell sites K2: their coupling to K1 through d (one thread per shell site,
-    // over its segment of the shell-major list)
-    const int32_t* seg_q = seg_i + (n1 + 1);
-    const int32_t* lq = a.pl_q + a.pl_off[k];
-    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
-        double g[3] = {0.0, 0.0, 0.0};
-        for (int e = seg_q[q]; e < seg_q[q + 1]; ++e) {
-            const int i = lq[e] & 0xFFFF;
-            double rh[3], r;
-            const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
-            double lam[9];
-            for (int e2 = 0; e2 < 3; ++e2)
-                for (int c = 0; c < 3; ++c)
-                    lam[3 * e2 + c] = 0.5 * (L.Y[(3 * i + e2) * 3 + c] + L.Y[(3 * i + c) * 3 + e2]);
-            double gp[3];
-            radial_tensor_grad(rh, r, double(tp.A), double(tp.dA), double(tp.dB), lam, gp);
-            g[0] += L.qab[q] * gp[0];
-            g[1] += L.qab[q] * gp[1];
-            g[2] += L.qab[q] * gp[2];
-        }
-        out[3 * (n1 + q) + 0] = fconv * g[0];
-        out[3 * (n1 + q) + 1] = fconv * g[1];
-        out[3 * (n1 + q) + 2] = fconv * g[2];
-    }
-    for (int s = n12 + threadIdx.x; s < nall; s += blockDim.x) {
-        out[3 * s + 0] = 0.0;
-        out[3 * s + 1] = 0.0;
-        out[3 * s + 2] = 0.0;
-    }
+    for (int q = t; q < n2; q += kAdjThreads)
+        for (int c = 0; c < 3; ++c) out[3 * (n1 + q) + c] = fconv * L.gq[3 * q + c];
+    for (int s = n12 + t; s < nall; s += kAdjThreads)
+        for (int c = 0; c < 3; ++c) out[3 * s + c] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
-// K1 x K2 coupling lists of one atom (frequency independent).  A shell site q
-// couples to a K1 site i when r_iq < r_scs (beyond, f_SR vanishes).  The lists
-// are written in i-major and shell-major order with CSR offsets; both orders
-// are deterministic (one thread per major index, minors in increasing order).
+// Pair lists of one atom (frequency independent).  A shell site q couples to a
+// K1 site i when r_iq < r_scs, two K1 sites a < b when r_ab < r_scs (beyond,
+// f_SR vanishes).  Each coupling appears once; the second list of each kind
+// holds, per minor site, the indices of its pairs in the first list, so that a
+// pass over one list can also reduce over the other side without atomics.
+// The shell-major and a-major lists take their major sites in a scrambled
+// order (a fixed stride coprime with the count), so that a site's pairs on the
+// other side spread evenly over any run of the list instead of clustering in
+// the part where spatially close sites sit.  All orders are deterministic (one
+// thread per major index, minors ascending).
 // ---------------------------------------------------------------------------
+__device__ inline int gcd_int(int x, int y) {
+    while (y) { const int r = x % y; x = y; y = r; }
+    return x;
+}
+
+// stride of the scrambled order of n items: about 0.618 n, coprime with n
+__device__ inline int scramble_stride(int n) {
+    if (n <= 2) return 1;
+    int s = (int)(0.6180339887 * n);
+    if (s < 1) s = 1;
+    while (gcd_int(s, n) != 1) ++s;
+    return s;
+}
+
+// index of the entry with minor index `minor` in a sorted segment [lo, hi)
+__device__ inline int find_minor(const int32_t* list, int lo, int hi, int minor) {
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((list[mid] & 0xFFFF) <= minor) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
@@ -929,8 +1055,12 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
     double* qx = pz + n1max;
     double* qy = qx + n2max;
     double* qz = qy + n2max;
-    int32_t* cnt_i = reinterpret_cast<int32_t*>(qz + n2max);   // n1max + 1
+    int32_t* cnt_i = reinterpret_cast<int32_t*>(qz + n2max);   // n1max + 1 (counts, then offsets)
     int32_t* cnt_q = cnt_i + (n1max + 1);                        // n2max + 1
+    int32_t* cnt_a = cnt_q + (n2max + 1);                        // n1max + 1
+    int32_t* cnt_b = cnt_a + (n1max + 1);                        // n1max + 1
+    int32_t* num_q = cnt_b + (n1max + 1);                        // n2max (counts kept)
+    int32_t* num_a = num_q + n2max;                              // n1max
     const Site* S = a.sites + a.site_off[k];
     for (int s = threadIdx.x; s < n12; s += blockDim.x) {
         if (s < n1) { px[s] = S[s].x; py[s] = S[s].y; pz[s] = S[s].z; }
@@ -941,47 +1071,92 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
         const double dx = px[i] - qx[q], dy = py[i] - qy[q], dz = pz[i] - qz[q];
         return dx * dx + dy * dy + dz * dz < rc2;
     };
+    auto near = [&](int i, int j) {
+        const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
+        return dx * dx + dy * dy + dz * dz < rc2;
+    };
+    const int sq = scramble_stride(n2), sa = scramble_stride(n1);
     for (int i = threadIdx.x; i < n1; i += blockDim.x) {
         int c = 0;
         for (int q = 0; q < n2; ++q) c += coupled(i, q);
         cnt_i[i] = c;
+        int ca = 0, cb = 0;
+        for (int j = 0; j < n1; ++j) {
+            if (j == i || !near(i, j)) continue;
+            if (j > i) ++ca;
+            else ++cb;
+        }
+        cnt_a[i] = ca;
+        num_a[i] = ca;
+        cnt_b[i] = cb;
     }
     for (int q = threadIdx.x; q < n2; q += blockDim.x) {
         int c = 0;
         for (int i = 0; i < n1; ++i) c += coupled(i, q);
         cnt_q[q] = c;
+        num_q[q] = c;
     }
     __syncthreads();
-    int32_t* seg = const_cast<int32_t*>(a.pl_seg) + a.site_off[k] + 2 * (int64_t)k;
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < n1; ++i) { const int c = cnt_i[i]; cnt_i[i] = acc; seg[i] = acc; acc += c; }
-        seg[n1] = acc;
-        cnt_i[n1] = acc;
-    }
-    if (threadIdx.x == 64) {
-        int acc = 0;
-        for (int q = 0; q < n2; ++q) { const int c = cnt_q[q]; cnt_q[q] = acc; seg[n1 + 1 + q] = acc; acc += c; }
-        seg[n1 + 1 + n2] = acc;
-        cnt_q[n2] = acc;
+    int32_t* seg = pair_segs(a, k);
+    // exclusive prefix sums, one thread per list, into LDS and the segment
+    // table (i, q, a, b); q and a in their scrambled order, with the total last
+    {
+        int32_t* c = nullptr;
+        int len = 0, at = 0, stride = 1;
+        switch (threadIdx.x) {
+            case 0: c = cnt_i; len = n1; at = 0; break;
+            case 64: c = cnt_q; len = n2; at = n1 + 1; stride = sq; break;
+            case 128: c = cnt_a; len = n1; at = n12 + 2; stride = sa; break;
+            case 192: c = cnt_b; len = n1; at = n12 + n1 + 3; break;
+            default: break;
+        }
+        if (c) {
+            int acc = 0;
+            for (int x = 0; x < len; ++x) {
+                const int y = (int)(((int64_t)x * stride) % (len > 0 ? len : 1));
+                const int v = c[y];
+                c[y] = acc;
+                seg[at + y] = acc;
+                acc += v;
+            }
+            c[len] = acc;
+            seg[at + len] = acc;
+        }
     }
     __syncthreads();
-    int32_t* lio = const_cast<int32_t*>(a.pl_i) + a.pl_off[k];
-    int32_t* lqo = const_cast<int32_t*>(a.pl_q) + a.pl_off[k];
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        int pos = cnt_i[i];
-        for (int q = 0; q < n2; ++q)
-            if (coupled(i, q)) lio[pos++] = (i << 16) | q;
-    }
+    int32_t* li = const_cast<int32_t*>(a.pl_i) + a.pl_off[k];
+    int32_t* lq = const_cast<int32_t*>(a.pl_q) + a.pl_off[k];
+    int32_t* la = li + (int64_t)n1 * n2;
+    int32_t* lb = lq + (int64_t)n1 * n2;
     for (int q = threadIdx.x; q < n2; q += blockDim.x) {
         int pos = cnt_q[q];
         for (int i = 0; i < n1; ++i)
-            if (coupled(i, q)) lqo[pos++] = (q << 16) | i;
+            if (coupled(i, q)) lq[pos++] = (q << 16) | i;
+    }
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        int pos = cnt_a[i];
+        for (int j = i + 1; j < n1; ++j)
+            if (near(i, j)) la[pos++] = (i << 16) | j;
+    }
+    __syncthreads();
+    // index lists, each in ascending index order (majors of the other list in
+    // their scrambled order)
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        int pos = cnt_i[i];
+        for (int x = 0; x < n2; ++x) {
+            const int q = (int)(((int64_t)x * sq) % n2);
+            if (coupled(i, q)) li[pos++] = find_minor(lq, cnt_q[q], cnt_q[q] + num_q[q], i);
+        }
+        pos = cnt_b[i];
+        for (int x = 0; x < n1; ++x) {
+            const int j = (int)(((int64_t)x * sa) % n1);
+            if (j < i && near(j, i)) lb[pos++] = find_minor(la, cnt_a[j], cnt_a[j] + num_a[j], i);
+        }
     }
 }
 
 size_t pairlist_lds_bytes(int n1max, int n2max) {
-    return sizeof(double) * 3 * ((size_t)n1max + n2max) + sizeof(int32_t) * ((size_t)n1max + n2max + 2);
+    return sizeof(double) * 3 * ((size_t)n1max + n2max) + sizeof(int32_t) * (4 * (size_t)n1max + 2 * (size_t)n2max + 4);
 }
 
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max) {
@@ -1031,8 +1206,8 @@ hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool m
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
     const size_t lds = scs_lds_bytes(n1max, n2max, mixed);
-    if (mixed) hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(256), lds, st, a, n1max, n2max);
-    else hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(256), lds, st, a, n1max, n2max);
+    if (mixed) hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(kAdjThreads), lds, st, a, n1max, n2max);
+    else hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(kAdjThreads), lds, st, a, n1max, n2max);
     return hipGetLastError();
 }
 

@@ -277,7 +277,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         P.work_off[k] = wo;
         P.pl_off[k] = po;
         P.coef_off[k] = co;
-        po += (int64_t)c.n1 * (c.n12 - c.n1);
+        po += (int64_t)c.n1 * (c.n12 - c.n1) + (int64_t)c.n1 * (c.n1 - 1) / 2;
         if (mixed) co += (int64_t)nw * c.n1 * (c.n1 + 1);
         const int64_t N1 = 3 * (int64_t)c.n1, N3 = 3 * (int64_t)c.nK;
         P.hash_cap[k] = (int32_t)next_pow2(2 * (int64_t)c.n_all);
@@ -354,7 +354,7 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
         {&c->alpha_loc, (size_t)P.aloc_len * D}, {&c->abar_loc, (size_t)P.aloc_len * D},
         {&c->abar_cen, N * nw * D}, {&c->work, (size_t)P.work_len * wsz}, {&c->e_out, N * D},
         {&c->a_out, N * D}, {&c->pl_i, (size_t)P.pl_len * I}, {&c->pl_q, (size_t)P.pl_len * I},
-        {&c->pl_seg, (TS + 2 * N) * I}, {&c->coef_off, N * L8}, {&c->coef, (size_t)P.coef_len * sizeof(float)}};
+        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef_off, N * L8}, {&c->coef, (size_t)P.coef_len * sizeof(float)}};
     for (const auto& e : L) {
         const hipError_t r = get(*e.first, e.second);
         if (r != hipSuccess) return r;

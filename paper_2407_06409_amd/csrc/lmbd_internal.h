@@ -176,12 +176,20 @@ struct ScsArgs {
     const int64_t* x_off;
     double* alpha_loc;       // per atom n1 * nw
     const int64_t* aloc_off;
-    // K1 x K2 coupling lists (frequency independent): per atom, entries packed as
-    // (major << 16) | minor in i-major and shell-major order, CSR offsets of both
+    // pair lists of one atom (frequency independent), per atom a block of
+    // n1 n2 + n1 (n1 - 1) / 2 entries in each of pl_i and pl_q:
+    //   K1 x K2 (r_iq < r_scs): pl_q[0 ..) shell-major, entries (q << 16) | i;
+    //                           pl_i[0 ..) i-major, entries = index into the shell-major list
+    //   K1 x K1 (a < b, r_ab < r_scs), from n1 n2 on:
+    //                           pl_i a-major, entries (a << 16) | b;
+    //                           pl_q b-major, entries = index into the a-major list
+    // each list is ordered by major site (shell-major and a-major lists in a
+    // scrambled order of the majors), then minor index; index lists ascend
     const int32_t* pl_i;
     const int32_t* pl_q;
-    const int64_t* pl_off;   // per atom: first entry of both lists
-    const int32_t* pl_seg;   // per atom at site_off[k] + 2k: n1 + 1 i-offsets then n2 + 1 q-offsets
+    const int64_t* pl_off;   // per atom: first entry of the block
+    const int32_t* pl_seg;   // per atom at 3 (site_off[k] + 2k): segment starts per major site, then
+                             //   the total: i (n1 + 1), q (n2 + 1), a (n1 + 1), b (n1 + 1)
     int* err;
     int* err_atom;
     // adjoint only
