@@ -148,7 +148,7 @@ __device__ inline typename Vec4T<R>::type load4(const R* p) {
 
 template <typename R>
 __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ pan, R* __restrict__ Zs,
-                                            int dw, bool& ok) {
+                                            int* counter, int dw, bool& ok) {
     typedef Mfma<R> M;
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
@@ -159,6 +159,8 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     const V4 zero = {R(0), R(0), R(0), R(0)};
     bool good = true;
     bool paired_prev = false;   // the previous (even) panel already applied chunks < p-1 to this panel
+    if (tid == 0) counter[0] = 0;
+    __syncthreads();
     for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
@@ -174,21 +176,12 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         // with an unsplit update the diagonal wave updates tile 0 alone and
         // factorises it at once, while the other waves update the tiles below
         const bool early = (S == 1) && nwave > 1;
-        int u0, ustep;
-        if (!early) {
-            u0 = (wave - dw + nwave) % nwave;
-            ustep = nwave;
-        } else if (wave == dw) {
-            u0 = 0;
-            ustep = U;
-        } else {
-            u0 = 1 + (wave - dw - 1 + nwave) % nwave;
-            ustep = nwave - 1;
-        }
-        // (1) update: one (row tile, k-split) unit per wavefront; the unit with
-        // s = 0 starts from the matrix, the others from zero; results (partial
-        // tiles for s > 0) go to the panel buffer in LDS, tile u = t + s m
-        for (int u = u0; u < U; u += ustep) {
+        // (1) update: one (row tile, k-split) unit at a time per wavefront, units
+        // taken from a counter in LDS; the unit with s = 0 starts from the
+        // matrix, the others from zero; results (partial tiles for s > 0) go to
+        // the panel buffer, tile u = t + s m.  A unit's result does not depend
+        // on which wavefront computes it.
+        auto unit = [&](int u) {
             const int t = u % m, s = u / m;
             const bool two = pair && t > 0;
             typename M::acc acc0, acc1;
@@ -239,12 +232,10 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                     if (row < N && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] += acc1[q];
                 }
             }
-        }
-        paired_prev = pair;
-        if (!early) __syncthreads();
+        };
         // (2) diagonal block: the diagonal wave, lane l holds row l (in the early
         // case it reads back the tile it has just written itself)
-        if (wave == dw) {
+        auto diag = [&]() {
             const int l = lane;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             R row[NB];
@@ -301,7 +292,26 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 for (int q = 0; q < NB; ++q)
                     if (q > l && q < jb) A[(size_t)(c0 + l) * ld + c0 + q] = z[q];
             }
+        };
+        int* ctr = counter + (p & 1);
+        if (early && wave == dw) {
+            unit(0);
+            diag();
         }
+        for (;;) {
+            int g = 0;
+            if (lane == 0) g = atomicAdd(ctr, 1);
+            g = __shfl(g, 0);
+            const int u = early ? g + 1 : g;
+            if (u >= U) break;
+            unit(u);
+        }
+        paired_prev = pair;
+        if (!early) {
+            __syncthreads();
+            if (wave == dw) diag();
+        }
+        if (tid == 0) counter[(p + 1) & 1] = 0;   // for the next panel (its last use was two barriers ago)
         __syncthreads();
         // (3) rows below the block: X = A Z^T on MFMA, one 16-row tile per
         // wavefront, A summed over the k-split parts in the panel buffer
@@ -459,6 +469,57 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
 }
 
 // ---------------------------------------------------------------------------
+// Sums over runs of equal key in a chunk of kChunk values (one per thread,
+// keys ascending through the chunk, -1 for no value): each run's sum is added
+// to acc[NV key ..].  Within a wavefront by segmented suffix sums over the
+// lanes (after the steps with distance d, lane l holds the sum over
+// [l, l + 2d) of its run), written by the run's first lane; the part of a run
+// that continues from the previous wavefront goes to carry[] and is added by
+// thread 0, in wavefront order, in add_carries() after the next barrier.  The
+// order of every addition is fixed, so the sums do not depend on scheduling.
+// keys[] holds the chunk's keys (written before the barrier that precedes).
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 256;              // threads of the chunked pair kernels = values per chunk
+constexpr int kChunkWaves = kChunk / 64;
+
+template <int NV>
+__device__ __forceinline__ void run_sums(int key, double (&h)[NV], const int32_t* keys, double* acc, double* carry,
+                                         int* carry_key) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int kd = __shfl_down(key, d);
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = __shfl_down(h[v], d);
+        if (lane + d < 64 && kd == key) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) h[v] += u[v];
+        }
+    }
+    const int kprev = t > 0 ? keys[t - 1] : -2;
+    const bool cont = lane == 0 && wave > 0 && key >= 0 && kprev == key;
+    if (lane == 0 && wave > 0) carry_key[wave] = cont ? key : -1;
+    if (cont) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) carry[NV * wave + v] = h[v];
+    } else if (key >= 0 && (lane == 0 || kprev != key)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[NV * key + v] += h[v];
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void add_carries(double* acc, const double* carry, const int* carry_key) {
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < kChunkWaves; ++w) {
+        const int key = carry_key[w];
+        if (key < 0) continue;
+        for (int v = 0; v < NV; ++v) acc[NV * key + v] += carry[NV * w + v];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS layout of the pair kernels.  K1 sites, right-hand sides / solutions
 // (FP64), the solve buffer in the matrix type, shell sites and a per-site
 // reduction area.
@@ -472,8 +533,7 @@ struct ScsLds {
     int32_t* key;                              // adjoint: reduction key of each thread's pair
 };
 
-constexpr int kAdjThreads = 256;   // threads of the adjoint kernel = pairs per chunk
-static_assert(kAdjThreads >= kMaxN1, "the adjoint gives every K1 site a thread of its own");
+static_assert(kChunk >= kMaxN1, "the adjoint gives every K1 site a thread of its own");
 
 __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     const int N = 3 * n1max;
@@ -493,7 +553,7 @@ __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     L.Y = L.qR + n2max;
     L.X = L.Y + 3 * N;
     L.H = L.X + 3 * N;
-    L.gk = L.H + 3 * kAdjThreads;
+    L.gk = L.H + 3 * kChunk;
     L.gq = L.gk + 3 * n1max;
     L.key = reinterpret_cast<int32_t*>(L.gq + 3 * n2max);
     return L;
@@ -501,8 +561,8 @@ __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
 
 size_t scs_lds_bytes(int n1max, int n2max, bool) {
     const size_t N = 3 * (size_t)n1max;
-    return sizeof(double) * (9 * (size_t)n1max + 6 * N + 9 * (size_t)n2max + 3 * kAdjThreads) +
-           sizeof(int32_t) * kAdjThreads;
+    return sizeof(double) * (9 * (size_t)n1max + 6 * N + 9 * (size_t)n2max + 3 * kChunk) +
+           sizeof(int32_t) * kChunk;
 }
 
 // CSR offsets of the pair lists of atom k (i, q, a, b; see ScsArgs)
@@ -511,9 +571,23 @@ __device__ inline int32_t* pair_segs(const ScsArgs& a, int k) {
 }
 
 // sites only (assembly): K1 sites then shell sites
-size_t scs_assemble_lds_bytes(int n1max, int n2max) { return sizeof(double) * 6 * ((size_t)n1max + n2max); }
+// assembly of d: K1 sites, shell sites, the d sums (6 per K1 site) and the
+// chunk's keys; assembly of B~: K1 sites, one chunk of pair values and slots,
+// word counts and a bit per K1 pair (coupled)
+__host__ __device__ inline int assemble_mask_words(int n1max) { return (n1max * (n1max + 1) / 2 + 31) / 32; }
 
-__device__ inline ScsLds scs_assemble_lds(double* base, int n1max, int n2max) {
+static size_t dvec_lds_bytes(int n1max, int n2max) {
+    return sizeof(double) * (12 * (size_t)n1max + 6 * (size_t)n2max) + sizeof(int32_t) * kChunk;
+}
+static size_t matrix_lds_bytes(int n1max) {
+    return sizeof(double) * (6 * (size_t)n1max + 2 * kChunk) +
+           sizeof(int32_t) * (2 * kChunk + (size_t)assemble_mask_words(n1max));
+}
+size_t scs_assemble_lds_bytes(int n1max, int n2max) {
+    return std::max(dvec_lds_bytes(n1max, n2max), matrix_lds_bytes(n1max));
+}
+
+__device__ inline ScsLds scs_assemble_lds(double* base, int n1max, int n2max, bool matrix) {
     ScsLds L = {};
     L.px = base;
     L.py = L.px + n1max;
@@ -527,6 +601,8 @@ __device__ inline ScsLds scs_assemble_lds(double* base, int n1max, int n2max) {
     L.qab = L.qz + n2max;
     L.qsg = L.qab + n2max;
     L.qR = L.qsg + n2max;
+    L.gk = L.qR + n2max;          // d: sums; B~: pair values
+    L.key = reinterpret_cast<int32_t*>(L.gk + (matrix ? 2 * kChunk : 6 * n1max));
     return L;
 }
 
@@ -576,67 +652,161 @@ __device__ inline SrPair<P> k2_pair(const ScsArgs& a, const ScsLds& L, int i, in
                       P(fin), P(dfin));
 }
 
-// Assembly of d (into the solution slot) and of the lower triangle of B~ (into
-// the factor slot), one workgroup per (atom, frequency).
+// Assembly of d (into the solution slot), one workgroup per (atom, frequency):
+// d_i = I - sum_q alpha_q T_SR(i, q) over the coupled shell sites, one pair
+// per thread from the i-major list; the 6 components of each symmetric 3x3
+// term are summed over the runs of each K1 site.
 template <typename R>
-__global__ void __launch_bounds__(256) k_scs_assemble(ScsArgs a, int n1max, int n2max) {
+__global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n2max) {
+    extern __shared__ double lds[];
+    __shared__ double carry[6 * kChunkWaves];
+    __shared__ int carry_key[kChunkWaves];
+    constexpr bool mixed = sizeof(R) == 4;
+    const int k = blockIdx.x;
+    const int w = blockIdx.y;
+    const int t = threadIdx.x;
+    const Counts cnt = a.counts[k];
+    const int n1 = cnt.n1, n12 = cnt.n12;
+    const int N = 3 * n1;
+    const double rc = a.sinfo[a.atom_struct[k]].r_scs;
+    ScsLds L = scs_assemble_lds(lds, n1max, n2max, false);
+    double* D = (mixed ? a.dvec : a.xsol) + a.x_off[k] + (size_t)w * N * 3;
+    const int32_t* seg_i = pair_segs(a, k);
+    const int32_t* li = a.pl_i + a.pl_off[k];
+    const int32_t* lq = a.pl_q + a.pl_off[k];
+    load_sites(a, k, w, n1, n12, L);
+    for (int e = t; e < 6 * n1; e += kChunk) L.gk[e] = 0.0;
+    __syncthreads();
+    const int P12 = seg_i[n1];
+    for (int e0 = 0; e0 < P12; e0 += kChunk) {
+        const int e = e0 + t;
+        int key = -1;
+        double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (e < P12) {
+            const int32_t ent = lq[li[e]];
+            const int q = ent >> 16, i = ent & 0xFFFF;
+            key = i;
+            double rh[3], r;
+            const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
+            const double A_ = tp.A, B_ = tp.B, ab = L.qab[q];
+            h[0] = ab * (A_ * rh[0] * rh[0] + B_);
+            h[1] = ab * (A_ * rh[0] * rh[1]);
+            h[2] = ab * (A_ * rh[0] * rh[2]);
+            h[3] = ab * (A_ * rh[1] * rh[1] + B_);
+            h[4] = ab * (A_ * rh[1] * rh[2]);
+            h[5] = ab * (A_ * rh[2] * rh[2] + B_);
+        }
+        L.key[t] = key;
+        __syncthreads();
+        run_sums<6>(key, h, L.key, L.gk, carry, carry_key);
+        __syncthreads();
+        add_carries<6>(L.gk, carry, carry_key);
+    }
+    __syncthreads();
+    for (int i = t; i < n1; i += kChunk) {
+        const double* g = L.gk + 6 * i;
+        const double d[9] = {1.0 - g[0], -g[1], -g[2], -g[1], 1.0 - g[3], -g[4], -g[2], -g[4], 1.0 - g[5]};
+        for (int e = 0; e < 9; ++e) D[(3 * i + e / 3) * 3 + e % 3] = d[e];
+    }
+}
+
+// Assembly of the lower triangle of B~ (into the factor slot), one workgroup
+// per (atom, frequency), pairs in triangle order in chunks of kChunk: the
+// coupled pairs of a chunk (from the a-major list) are evaluated compactly,
+// one per thread, into LDS; then each pair of the chunk is written by its own
+// thread (rows of atom i in contiguous 3-element runs), zero blocks for
+// uncoupled pairs.  The mixed path also keeps the FP32 pair coefficients for
+// the refinement residual.
+template <typename R>
+__global__ void __launch_bounds__(kChunk) k_scs_assemble(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
     constexpr bool mixed = sizeof(R) == 4;
     const int k = blockIdx.x;
     const int w = blockIdx.y;
+    const int t = threadIdx.x;
     const Counts cnt = a.counts[k];
-    const int n1 = cnt.n1, n12 = cnt.n12;
+    const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1;
     const int N = 3 * n1;
     const int ld = a.fac_ld[k];
     const double rc = a.sinfo[a.atom_struct[k]].r_scs;
-    ScsLds L = scs_assemble_lds(lds, n1max, n2max);
+    ScsLds L = scs_assemble_lds(lds, n1max, 0, true);
+    double* vA = L.gk;                                      // kChunk
+    double* vB = L.gk + kChunk;                             // kChunk
+    int32_t* slot = L.key;                                  // kChunk
+    int32_t* wcnt = L.key + kChunk;                         // kChunk / 32
+    uint32_t* mask = reinterpret_cast<uint32_t*>(L.key + 2 * kChunk);
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
-    double* D = (mixed ? a.dvec : a.xsol) + a.x_off[k] + (size_t)w * N * 3;
     const int npairs = n1 * (n1 + 1) / 2;
     float* coef = mixed ? a.coef + a.coef_off[k] + (size_t)w * 2 * npairs : nullptr;
-    load_sites(a, k, w, n1, n12, L);
+    const int32_t* seg_a = pair_segs(a, k) + (n12 + 2);
+    const int32_t* la = a.pl_i + a.pl_off[k] + (int64_t)n1 * n2;
+    load_sites(a, k, w, n1, n1, L);
+    for (int e = t; e < assemble_mask_words(n1); e += kChunk) mask[e] = 0u;
     __syncthreads();
-
-    // d: the shell K2 (TS polarisabilities, f_inner), one K1 site per thread over
-    // its segment of the compact list of coupled (K1 site, shell site) pairs
-    const int32_t* seg_i = pair_segs(a, k);
-    const int32_t* li = a.pl_i + a.pl_off[k];
-    const int32_t* lq = a.pl_q + a.pl_off[k];
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        double d[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
-        for (int e = seg_i[i]; e < seg_i[i + 1]; ++e) {
-            const int q = lq[li[e]] >> 16;
-            double rh[3], r;
-            const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
-            const double A_ = tp.A, B_ = tp.B, ab = L.qab[q];
-            for (int e2 = 0; e2 < 3; ++e2)
-                for (int c = 0; c < 3; ++c) d[3 * e2 + c] -= ab * (A_ * rh[e2] * rh[c] + (e2 == c ? B_ : 0.0));
-        }
-        for (int e = 0; e < 9; ++e) D[(3 * i + e / 3) * 3 + e % 3] = d[e];
+    const int P11 = seg_a[n1];
+    for (int e = t; e < P11; e += kChunk) {   // coupled K1 pairs (a < b) -> bit of lower-triangle pair (b, a)
+        const int32_t ent = la[e];
+        const int i = ent & 0xFFFF, j = ent >> 16;
+        const int p = i * (i + 1) / 2 + j;
+        atomicOr(&mask[p >> 5], 1u << (p & 31));
     }
-
-    // B~ (row-major lower triangle), one atom pair per thread: the three rows of
-    // atom i are written in contiguous 3-element runs; the mixed path also keeps
-    // the FP32 pair coefficients for the refinement residual
-    for (int p = threadIdx.x; p < npairs; p += blockDim.x) {
-        int i, j;
-        tri_decode(p, i, j);
-        if (i == j) {
-            const R inv = R(1.0 / L.ab[i]);
-            for (int q = 0; q < 3; ++q)
-                for (int c = 0; c <= q; ++c) A[(size_t)(3 * i + q) * ld + 3 * i + c] = (q == c) ? inv : R(0);
-            if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
-            continue;
+    __syncthreads();
+    for (int p0 = 0; p0 < npairs; p0 += kChunk) {
+        const int w0 = p0 >> 5;
+        if (t < kChunk / 32) wcnt[t] = (p0 + 32 * t < npairs) ? __popc(mask[w0 + t]) : 0;
+        __syncthreads();
+        int total = 0;
+        for (int x = 0; x < kChunk / 32; ++x) total += wcnt[x];
+        const int p = p0 + t;
+        int rank = -1;
+        if (p < npairs) {
+            const int wd = p >> 5;
+            const uint32_t m = mask[wd];
+            if ((m >> (p & 31)) & 1u) {
+                int r = __popc(m & ((1u << (p & 31)) - 1u));
+                for (int x = w0; x < wd; ++x) r += wcnt[x - w0];
+                rank = r;
+                slot[r] = p;
+            }
         }
-        double rh[3], r;
-        const SrPair<R> t = k1_pair<R>(a, L, i, j, rc, rh, r);
-        if (mixed) {
-            coef[2 * p] = (float)t.A;
-            coef[2 * p + 1] = (float)t.B;
+        __syncthreads();
+        if (t < total) {
+            const int pp = slot[t];
+            int i, j;
+            tri_decode(pp, i, j);
+            double rh[3], rr;
+            const SrPair<R> tp = k1_pair<R>(a, L, i, j, rc, rh, rr);
+            vA[t] = double(tp.A);
+            vB[t] = double(tp.B);
+            if (mixed) {
+                coef[2 * pp] = (float)tp.A;
+                coef[2 * pp + 1] = (float)tp.B;
+            }
         }
-        for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c)
-                A[(size_t)(3 * i + q) * ld + 3 * j + c] = R(double(t.A) * rh[q] * rh[c] + (q == c ? double(t.B) : 0.0));
+        __syncthreads();
+        if (p < npairs) {
+            int i, j;
+            tri_decode(p, i, j);
+            R* blk = A + (size_t)(3 * i) * ld + 3 * j;
+            if (i == j) {
+                const R inv = R(1.0 / L.ab[i]);
+                for (int q = 0; q < 3; ++q)
+                    for (int c = 0; c <= q; ++c) blk[(size_t)q * ld + c] = (q == c) ? inv : R(0);
+                if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
+            } else if (rank < 0) {
+                for (int q = 0; q < 3; ++q)
+                    for (int c = 0; c < 3; ++c) blk[(size_t)q * ld + c] = R(0);
+                if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
+            } else {
+                const double Av = vA[rank], Bv = vB[rank];
+                const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+                const double ir = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
+                for (int q = 0; q < 3; ++q)
+                    for (int c = 0; c < 3; ++c) blk[(size_t)q * ld + c] = R(Av * rh[q] * rh[c] + (q == c ? Bv : 0.0));
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -648,6 +818,7 @@ template <typename R>
 __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
     __shared__ R Zs[NB * kSlotLd];
+    __shared__ int counter[2];
     R* pan = reinterpret_cast<R*>(lds);
     const int k = blockIdx.x;
     const int w = blockIdx.y;
@@ -657,7 +828,7 @@ __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     // the wave that factorises the diagonal blocks rotates over the workgroups
     const int dw = (k + w) % (blockDim.x >> 6);
     bool ok = true;
-    chol_factor<R>(A, N, ld, pan, Zs, dw, ok);
+    chol_factor<R>(A, N, ld, pan, Zs, counter, dw, ok);
     if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
         atomicOr(a.err, 4);
         atomicMin(a.err_atom, k);
@@ -804,7 +975,7 @@ size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)
 // contractions and sums are FP64.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
+__global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
     const int w = blockIdx.y;
@@ -818,12 +989,12 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
     const double* Lg = a.lam + a.x_off[k] + (size_t)w * N * 3;
     load_sites(a, k, w, n1, n12, L);
-    for (int e = t; e < 3 * N; e += kAdjThreads) {
+    for (int e = t; e < 3 * N; e += kChunk) {
         L.X[e] = Xg[e];
         L.Y[e] = Lg[e];
     }
-    for (int e = t; e < 3 * n1; e += kAdjThreads) L.gk[e] = 0.0;
-    for (int e = t; e < 3 * n2; e += kAdjThreads) L.gq[e] = 0.0;
+    for (int e = t; e < 3 * n1; e += kChunk) L.gk[e] = 0.0;
+    for (int e = t; e < 3 * n2; e += kChunk) L.gq[e] = 0.0;
     const int32_t* seg = pair_segs(a, k);
     const int32_t* seg_i = seg;
     const int32_t* seg_q = seg + (n1 + 1);
@@ -835,47 +1006,8 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
     const int32_t* lb = lq + (int64_t)n1 * n2;
     __syncthreads();
 
-    constexpr int kWaves = kAdjThreads / 64;
-    __shared__ double carry[3 * kWaves];
-    __shared__ int carry_key[kWaves];
-    const int lane = t & 63, wave = t >> 6;
-    // the chunk's runs of equal key: each run's sum goes to acc[3 key].  Sums
-    // within a wavefront by segmented suffix sums over the lanes; the part of
-    // a run that continues from the previous wavefront is left in carry[] and
-    // added by thread 0 (in wavefront order) after the next barrier
-    auto run_sums = [&](int key, double h0, double h1, double h2, double* acc) {
-        for (int d = 1; d < 64; d <<= 1) {
-            const int kd = __shfl_down(key, d);
-            const double u0 = __shfl_down(h0, d), u1 = __shfl_down(h1, d), u2 = __shfl_down(h2, d);
-            if (lane + d < 64 && kd == key) {
-                h0 += u0;
-                h1 += u1;
-                h2 += u2;
-            }
-        }
-        const int kprev = t > 0 ? L.key[t - 1] : -2;
-        const bool cont = lane == 0 && wave > 0 && key >= 0 && kprev == key;
-        if (lane == 0 && wave > 0) carry_key[wave] = cont ? key : -1;
-        if (cont) {
-            carry[3 * wave + 0] = h0;
-            carry[3 * wave + 1] = h1;
-            carry[3 * wave + 2] = h2;
-        } else if (key >= 0 && (lane == 0 || kprev != key)) {
-            acc[3 * key + 0] += h0;
-            acc[3 * key + 1] += h1;
-            acc[3 * key + 2] += h2;
-        }
-    };
-    auto add_carries = [&](double* acc) {
-        if (t != 0) return;
-        for (int v = 1; v < kWaves; ++v) {
-            const int key = carry_key[v];
-            if (key < 0) continue;
-            acc[3 * key + 0] += carry[3 * v + 0];
-            acc[3 * key + 1] += carry[3 * v + 1];
-            acc[3 * key + 2] += carry[3 * v + 2];
-        }
-    };
+    __shared__ double carry[3 * kChunkWaves];
+    __shared__ int carry_key[kChunkWaves];
     // K1 site t's index list over the other side: the next entries are loaded
     // before the chunk's pair is evaluated, and the terms of the pairs in this
     // chunk are subtracted from g after the barrier
@@ -891,7 +1023,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
         for (int j = 0; j < kAhead; ++j) {
             more = more && ahead[j] < e1;
             if (more) {
-                const int u = ahead[j] - (e1 - kAdjThreads);
+                const int u = ahead[j] - (e1 - kChunk);
                 g[0] -= L.H[3 * u + 0];
                 g[1] -= L.H[3 * u + 1];
                 g[2] -= L.H[3 * u + 2];
@@ -900,7 +1032,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
         }
         if (more) {
             for (; p < pe && lst[p] < e1; ++p) {
-                const int u = lst[p] - (e1 - kAdjThreads);
+                const int u = lst[p] - (e1 - kChunk);
                 g[0] -= L.H[3 * u + 0];
                 g[1] -= L.H[3 * u + 1];
                 g[2] -= L.H[3 * u + 2];
@@ -915,7 +1047,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
         const int P = seg_a[n1];
         int p = t < n1 ? seg_b[t] : 0;
         const int pe = t < n1 ? seg_b[t + 1] : 0;
-        for (int e0 = 0; e0 < P; e0 += kAdjThreads) {
+        for (int e0 = 0; e0 < P; e0 += kChunk) {
             prefetch(lb, p, pe);
             const int e = e0 + t;
             int key = -1;
@@ -948,10 +1080,10 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
             L.H[3 * t + 1] = h[1];
             L.H[3 * t + 2] = h[2];
             __syncthreads();
-            run_sums(key, h[0], h[1], h[2], L.gk);
-            if (t < n1) consume(lb, p, pe, e0 + kAdjThreads, gb);
+            run_sums<3>(key, h, L.key, L.gk, carry, carry_key);
+            if (t < n1) consume(lb, p, pe, e0 + kChunk, gb);
             __syncthreads();
-            add_carries(L.gk);
+            add_carries<3>(L.gk, carry, carry_key);
         }
     }
     // K1 x shell pairs, shell-major: h = qab_q * (gradient of the lambda_i : dd_i
@@ -960,7 +1092,7 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
         const int P = seg_q[n2];
         int p = t < n1 ? seg_i[t] : 0;
         const int pe = t < n1 ? seg_i[t + 1] : 0;
-        for (int e0 = 0; e0 < P; e0 += kAdjThreads) {
+        for (int e0 = 0; e0 < P; e0 += kChunk) {
             prefetch(li, p, pe);
             const int e = e0 + t;
             int key = -1;
@@ -987,10 +1119,10 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
             L.H[3 * t + 1] = h[1];
             L.H[3 * t + 2] = h[2];
             __syncthreads();
-            run_sums(key, h[0], h[1], h[2], L.gq);
-            if (t < n1) consume(li, p, pe, e0 + kAdjThreads, gi);
+            run_sums<3>(key, h, L.key, L.gq, carry, carry_key);
+            if (t < n1) consume(li, p, pe, e0 + kChunk, gi);
             __syncthreads();
-            add_carries(L.gq);
+            add_carries<3>(L.gq, carry, carry_key);
         }
     }
     __syncthreads();
@@ -1000,9 +1132,9 @@ __global__ void __launch_bounds__(kAdjThreads) k_scs_adjoint(ScsArgs a, int n1ma
     if (t < n1) {
         for (int c = 0; c < 3; ++c) out[3 * t + c] = fconv * ((L.gk[3 * t + c] + gb[c]) + gi[c]);
     }
-    for (int q = t; q < n2; q += kAdjThreads)
+    for (int q = t; q < n2; q += kChunk)
         for (int c = 0; c < 3; ++c) out[3 * (n1 + q) + c] = fconv * L.gq[3 * q + c];
-    for (int s = n12 + t; s < nall; s += kAdjThreads)
+    for (int s = n12 + t; s < nall; s += kChunk)
         for (int c = 0; c < 3; ++c) out[3 * s + c] = 0.0;
 }
 
@@ -1166,9 +1298,14 @@ hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2ma
 
 hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
-    const size_t la = scs_assemble_lds_bytes(n1max, n2max);
-    if (mixed) hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(256), la, st, a, n1max, n2max);
-    else hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(256), la, st, a, n1max, n2max);
+    const size_t ld = dvec_lds_bytes(n1max, n2max), lm = matrix_lds_bytes(n1max);
+    if (mixed) {
+        hipLaunchKernelGGL(k_scs_dvec<float>, grid, dim3(kChunk), ld, st, a, n1max, n2max);
+        hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(kChunk), lm, st, a, n1max);
+    } else {
+        hipLaunchKernelGGL(k_scs_dvec<double>, grid, dim3(kChunk), ld, st, a, n1max, n2max);
+        hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(kChunk), lm, st, a, n1max);
+    }
     return hipGetLastError();
 }
 
@@ -1206,8 +1343,8 @@ hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool m
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
     const size_t lds = scs_lds_bytes(n1max, n2max, mixed);
-    if (mixed) hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(kAdjThreads), lds, st, a, n1max, n2max);
-    else hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(kAdjThreads), lds, st, a, n1max, n2max);
+    if (mixed) hipLaunchKernelGGL(k_scs_adjoint<float>, grid, dim3(kChunk), lds, st, a, n1max, n2max);
+    else hipLaunchKernelGGL(k_scs_adjoint<double>, grid, dim3(kChunk), lds, st, a, n1max, n2max);
     return hipGetLastError();
 }
 
