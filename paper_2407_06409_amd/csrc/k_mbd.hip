@@ -339,18 +339,24 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
         __syncthreads();
     }
 
-    // --- moments mu_n(q) = <u_a, u_b>, a + b = n
+    // --- moments mu_n(q) = <u_a, u_b>, a + b = n; four lanes per moment over
+    // rows r = part (mod 4), combined by lane exchanges in a fixed order
     const int nmom = (n_max - 1) * nq;
-    for (int t = tid; t < nmom; t += blockDim.x) {
-        const int n = 2 + t / nq, q = t % nq;
-        const int ia = n / 2, ib = n - ia;
-        const W* ua = Uat(ia);
-        const W* ub = Uat(ib);
+    for (int base = 0; base < 4 * nmom; base += blockDim.x) {
+        const int t = (base + tid) >> 2, part = (base + tid) & 3;
         double s = 0.0;
-        for (int row = 0; row < N3; ++row)
-            for (int c = 0; c < 3; ++c)
-                s += double(ua[(size_t)row * ncol + 3 * q + c]) * double(ub[(size_t)row * ncol + 3 * q + c]);
-        L.mu[n * nq + q] = s;
+        if (t < nmom) {
+            const int n = 2 + t / nq, q = t % nq;
+            const int ia = n / 2, ib = n - ia;
+            const W* ua = Uat(ia);
+            const W* ub = Uat(ib);
+            for (int row = part; row < N3; row += 4)
+                for (int c = 0; c < 3; ++c)
+                    s += double(ua[(size_t)row * ncol + 3 * q + c]) * double(ub[(size_t)row * ncol + 3 * q + c]);
+        }
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        if (t < nmom && part == 0) L.mu[(2 + t / nq) * nq + t % nq] = s;
     }
     __syncthreads();
     const double wk = a.e_weight ? a.e_weight[k] : 1.0;
@@ -390,20 +396,33 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     // --- operands of Tbar = sum_a (D u_a)(W D Z_a)^T, Z_a = sum_b c_{a+b+1} u_b (u_0 = e_k),
     // k-contiguous: P[r][a ncol + col] = sqrt(alpha~_r) u_a[r][col] and
     // Q[s][a ncol + col] = w_k W_q sqrt(alpha~_s) Z_a[s][col]
-    for (int e = tid; e < N3 * KKp; e += blockDim.x) {
-        const int r = e / KKp, kk = e % KKp;
-        if (kk >= KK) {
-            Pm[e] = W(0);
-            Qm[e] = W(0);
-            continue;
-        }
-        const int aa = kk / ncol, col = kk % ncol, q = col / 3;
+    // one (row, column) of the Krylov blocks per thread: u_0 .. u_{n_max-1} read
+    // once, all n_max column blocks of P and Q written
+    for (int e = tid; e < N3 * ncol; e += blockDim.x) {
+        const int r = e / ncol, col = e % ncol, q = col / 3;
         const double sq = L.sqa[(size_t)(r / 3) * nq + q];
-        const double u = (aa == 0) ? ((r == col % 3) ? 1.0 : 0.0) : double(Uat(aa)[(size_t)r * ncol + col]);
-        double z = (aa >= 1 && r == col % 3) ? a.coef[aa + 1] : 0.0;   // b = 0 term (u_0 = e_k)
-        for (int b = 1; b <= n_max - 1 - aa; ++b) z += a.coef[aa + b + 1] * double(Uat(b)[(size_t)r * ncol + col]);
-        Pm[e] = W(sq * u);
-        Qm[e] = W(wk * a.wq[q] * sq * z);
+        const double scale = wk * a.wq[q] * sq;
+        double u[kMaxNmax];
+        u[0] = (r == col % 3) ? 1.0 : 0.0;
+#pragma unroll
+        for (int b = 1; b < kMaxNmax; ++b) u[b] = (b < n_max) ? double(Uat(b)[(size_t)r * ncol + col]) : 0.0;
+        W* pr = Pm + (size_t)r * KKp + col;
+        W* qr = Qm + (size_t)r * KKp + col;
+#pragma unroll
+        for (int aa = 0; aa < kMaxNmax; ++aa) {
+            if (aa >= n_max) break;
+            double z = 0.0;
+#pragma unroll
+            for (int b = 0; b < kMaxNmax; ++b)
+                if ((b > 0 || aa >= 1) && b <= n_max - 1 - aa) z += a.coef[min(aa + b + 1, kMaxNmax)] * u[b];
+            pr[(size_t)aa * ncol] = W(sq * u[aa]);
+            qr[(size_t)aa * ncol] = W(scale * z);
+        }
+    }
+    for (int e = tid; e < N3 * (KKp - KK); e += blockDim.x) {   // padding columns
+        const int r = e / (KKp - KK), kk = KK + e % (KKp - KK);
+        Pm[(size_t)r * KKp + kk] = W(0);
+        Qm[(size_t)r * KKp + kk] = W(0);
     }
     __syncthreads();
     // --- Tbar (overwrites T)

@@ -1164,69 +1164,109 @@ __device__ inline int scramble_stride(int n) {
     return s;
 }
 
-// index of the entry with minor index `minor` in a sorted segment [lo, hi)
-__device__ inline int find_minor(const int32_t* list, int lo, int hi, int minor) {
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((list[mid] & 0xFFFF) <= minor) lo = mid;
-        else hi = mid;
-    }
-    return lo;
+// LDS of the pair-list kernel: positions, then coupling bit rows: per K1 site
+// over the shell in scrambled order (wq words) and over K1 (a > i natural,
+// a < i scrambled; wa words each), per shell site over K1 (wa words), then
+// counts and offsets
+struct PairlistLds {
+    double *px, *py, *pz, *qx, *qy, *qz;
+    uint32_t *bq, *na, *nb, *cq;
+    int32_t *cnt_i, *cnt_q, *cnt_a, *cnt_b;
+    int wq, wa;
+};
+
+__host__ __device__ inline size_t pairlist_lds_words(int n1max, int n2max) {
+    const size_t wq = (n2max + 31) / 32, wa = (n1max + 31) / 32;
+    return (size_t)n1max * wq + 2 * (size_t)n1max * wa + (size_t)n2max * wa + 3 * ((size_t)n1max + 1) +
+           ((size_t)n2max + 1);
+}
+
+__device__ inline PairlistLds pairlist_lds(double* base, int n1max, int n2max) {
+    PairlistLds L;
+    L.px = base;
+    L.py = L.px + n1max;
+    L.pz = L.py + n1max;
+    L.qx = L.pz + n1max;
+    L.qy = L.qx + n2max;
+    L.qz = L.qy + n2max;
+    L.wq = (n2max + 31) / 32;
+    L.wa = (n1max + 31) / 32;
+    L.bq = reinterpret_cast<uint32_t*>(L.qz + n2max);
+    L.na = L.bq + (size_t)n1max * L.wq;
+    L.nb = L.na + (size_t)n1max * L.wa;
+    L.cq = L.nb + (size_t)n1max * L.wa;
+    L.cnt_i = reinterpret_cast<int32_t*>(L.cq + (size_t)n2max * L.wa);
+    L.cnt_q = L.cnt_i + (n1max + 1);
+    L.cnt_a = L.cnt_q + (n2max + 1);
+    L.cnt_b = L.cnt_a + (n1max + 1);
+    return L;
+}
+
+// number of set bits of a bit row below position x
+__device__ inline int bits_below(const uint32_t* row, int x) {
+    int c = 0;
+    for (int w = 0; w < (x >> 5); ++w) c += __popc(row[w]);
+    if (x & 31) c += __popc(row[x >> 5] & ((1u << (x & 31)) - 1u));
+    return c;
 }
 
 __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     const Counts cnt = a.counts[k];
     const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1;
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rc2 = SI.r_scs * SI.r_scs;
-    double* px = lds;
-    double* py = px + n1max;
-    double* pz = py + n1max;
-    double* qx = pz + n1max;
-    double* qy = qx + n2max;
-    double* qz = qy + n2max;
-    int32_t* cnt_i = reinterpret_cast<int32_t*>(qz + n2max);   // n1max + 1 (counts, then offsets)
-    int32_t* cnt_q = cnt_i + (n1max + 1);                        // n2max + 1
-    int32_t* cnt_a = cnt_q + (n2max + 1);                        // n1max + 1
-    int32_t* cnt_b = cnt_a + (n1max + 1);                        // n1max + 1
-    int32_t* num_q = cnt_b + (n1max + 1);                        // n2max (counts kept)
-    int32_t* num_a = num_q + n2max;                              // n1max
+    PairlistLds L = pairlist_lds(lds, n1max, n2max);
+    const int wq = L.wq, wa = L.wa;
     const Site* S = a.sites + a.site_off[k];
-    for (int s = threadIdx.x; s < n12; s += blockDim.x) {
-        if (s < n1) { px[s] = S[s].x; py[s] = S[s].y; pz[s] = S[s].z; }
-        else { qx[s - n1] = S[s].x; qy[s - n1] = S[s].y; qz[s - n1] = S[s].z; }
+    for (int s = t; s < n12; s += nt) {
+        if (s < n1) { L.px[s] = S[s].x; L.py[s] = S[s].y; L.pz[s] = S[s].z; }
+        else { L.qx[s - n1] = S[s].x; L.qy[s - n1] = S[s].y; L.qz[s - n1] = S[s].z; }
+    }
+    const int nwords = n1max * wq + 2 * n1max * wa + n2max * wa;
+    for (int e = t; e < nwords; e += nt) L.bq[e] = 0u;
+    __syncthreads();
+    const int sq = scramble_stride(n2), sa = scramble_stride(n1);
+    // every coupling tested once: K1 x shell (i, x = scrambled shell position)
+    for (int e = t; e < n1 * n2; e += nt) {
+        const int i = e / n2, x = e % n2;
+        const int q = (int)(((int64_t)x * sq) % n2);
+        const double dx = L.px[i] - L.qx[q], dy = L.py[i] - L.qy[q], dz = L.pz[i] - L.qz[q];
+        if (dx * dx + dy * dy + dz * dz < rc2) {
+            atomicOr(&L.bq[(size_t)i * wq + (x >> 5)], 1u << (x & 31));
+            atomicOr(&L.cq[(size_t)q * wa + (i >> 5)], 1u << (i & 31));
+        }
+    }
+    // K1 x K1 (i, x = scrambled K1 position of j): j > i in natural order for
+    // i's a-major entries, j < i in scrambled order for i's b-side list
+    for (int e = t; e < n1 * n1; e += nt) {
+        const int i = e / n1, x = e % n1;
+        const int j = (int)(((int64_t)x * sa) % n1);
+        if (j == i) continue;
+        const double dx = L.px[i] - L.px[j], dy = L.py[i] - L.py[j], dz = L.pz[i] - L.pz[j];
+        if (dx * dx + dy * dy + dz * dz < rc2) {
+            if (j > i) atomicOr(&L.na[(size_t)i * wa + (j >> 5)], 1u << (j & 31));
+            else atomicOr(&L.nb[(size_t)i * wa + (x >> 5)], 1u << (x & 31));
+        }
     }
     __syncthreads();
-    auto coupled = [&](int i, int q) {
-        const double dx = px[i] - qx[q], dy = py[i] - qy[q], dz = pz[i] - qz[q];
-        return dx * dx + dy * dy + dz * dz < rc2;
-    };
-    auto near = [&](int i, int j) {
-        const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
-        return dx * dx + dy * dy + dz * dz < rc2;
-    };
-    const int sq = scramble_stride(n2), sa = scramble_stride(n1);
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        int c = 0;
-        for (int q = 0; q < n2; ++q) c += coupled(i, q);
-        cnt_i[i] = c;
-        int ca = 0, cb = 0;
-        for (int j = 0; j < n1; ++j) {
-            if (j == i || !near(i, j)) continue;
-            if (j > i) ++ca;
-            else ++cb;
+    for (int i = t; i < n1; i += nt) {
+        int ci = 0, ca = 0, cb = 0;
+        for (int w = 0; w < wq; ++w) ci += __popc(L.bq[(size_t)i * wq + w]);
+        for (int w = 0; w < wa; ++w) {
+            ca += __popc(L.na[(size_t)i * wa + w]);
+            cb += __popc(L.nb[(size_t)i * wa + w]);
         }
-        cnt_a[i] = ca;
-        num_a[i] = ca;
-        cnt_b[i] = cb;
+        L.cnt_i[i] = ci;
+        L.cnt_a[i] = ca;
+        L.cnt_b[i] = cb;
     }
-    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+    for (int q = t; q < n2; q += nt) {
         int c = 0;
-        for (int i = 0; i < n1; ++i) c += coupled(i, q);
-        cnt_q[q] = c;
-        num_q[q] = c;
+        for (int w = 0; w < wa; ++w) c += __popc(L.cq[(size_t)q * wa + w]);
+        L.cnt_q[q] = c;
     }
     __syncthreads();
     int32_t* seg = pair_segs(a, k);
@@ -1235,17 +1275,17 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
     {
         int32_t* c = nullptr;
         int len = 0, at = 0, stride = 1;
-        switch (threadIdx.x) {
-            case 0: c = cnt_i; len = n1; at = 0; break;
-            case 64: c = cnt_q; len = n2; at = n1 + 1; stride = sq; break;
-            case 128: c = cnt_a; len = n1; at = n12 + 2; stride = sa; break;
-            case 192: c = cnt_b; len = n1; at = n12 + n1 + 3; break;
+        switch (t) {
+            case 0: c = L.cnt_i; len = n1; at = 0; break;
+            case 64: c = L.cnt_q; len = n2; at = n1 + 1; stride = sq; break;
+            case 128: c = L.cnt_a; len = n1; at = n12 + 2; stride = sa; break;
+            case 192: c = L.cnt_b; len = n1; at = n12 + n1 + 3; break;
             default: break;
         }
         if (c) {
             int acc = 0;
             for (int x = 0; x < len; ++x) {
-                const int y = (int)(((int64_t)x * stride) % (len > 0 ? len : 1));
+                const int y = (int)(((int64_t)x * stride) % len);
                 const int v = c[y];
                 c[y] = acc;
                 seg[at + y] = acc;
@@ -1260,35 +1300,40 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
     int32_t* lq = const_cast<int32_t*>(a.pl_q) + a.pl_off[k];
     int32_t* la = li + (int64_t)n1 * n2;
     int32_t* lb = lq + (int64_t)n1 * n2;
-    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
-        int pos = cnt_q[q];
-        for (int i = 0; i < n1; ++i)
-            if (coupled(i, q)) lq[pos++] = (q << 16) | i;
+    // shell-major entries (q << 16) | i, i ascending
+    for (int q = t; q < n2; q += nt) {
+        int pos = L.cnt_q[q];
+        for (int w = 0; w < wa; ++w)
+            for (uint32_t m = L.cq[(size_t)q * wa + w]; m; m &= m - 1) lq[pos++] = (q << 16) | (32 * w + __ffs(m) - 1);
     }
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        int pos = cnt_a[i];
-        for (int j = i + 1; j < n1; ++j)
-            if (near(i, j)) la[pos++] = (i << 16) | j;
-    }
-    __syncthreads();
-    // index lists, each in ascending index order (majors of the other list in
-    // their scrambled order)
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        int pos = cnt_i[i];
-        for (int x = 0; x < n2; ++x) {
-            const int q = (int)(((int64_t)x * sq) % n2);
-            if (coupled(i, q)) li[pos++] = find_minor(lq, cnt_q[q], cnt_q[q] + num_q[q], i);
-        }
-        pos = cnt_b[i];
-        for (int x = 0; x < n1; ++x) {
-            const int j = (int)(((int64_t)x * sa) % n1);
-            if (j < i && near(j, i)) lb[pos++] = find_minor(la, cnt_a[j], cnt_a[j] + num_a[j], i);
-        }
+    for (int i = t; i < n1; i += nt) {
+        // a-major entries (i << 16) | j, j > i ascending
+        int pos = L.cnt_a[i];
+        for (int w = 0; w < wa; ++w)
+            for (uint32_t m = L.na[(size_t)i * wa + w]; m; m &= m - 1) la[pos++] = (i << 16) | (32 * w + __ffs(m) - 1);
+        // i-major index list: shell partners in scrambled order, each the index
+        // of (q, i) in the shell-major list
+        pos = L.cnt_i[i];
+        for (int w = 0; w < wq; ++w)
+            for (uint32_t m = L.bq[(size_t)i * wq + w]; m; m &= m - 1) {
+                const int x = 32 * w + __ffs(m) - 1;
+                const int q = (int)(((int64_t)x * sq) % n2);
+                li[pos++] = L.cnt_q[q] + bits_below(L.cq + (size_t)q * wa, i);
+            }
+        // b-side index list: K1 partners j < i in scrambled order, each the
+        // index of (j, i) in the a-major list
+        pos = L.cnt_b[i];
+        for (int w = 0; w < wa; ++w)
+            for (uint32_t m = L.nb[(size_t)i * wa + w]; m; m &= m - 1) {
+                const int x = 32 * w + __ffs(m) - 1;
+                const int j = (int)(((int64_t)x * sa) % n1);
+                lb[pos++] = L.cnt_a[j] + bits_below(L.na + (size_t)j * wa, i);
+            }
     }
 }
 
 size_t pairlist_lds_bytes(int n1max, int n2max) {
-    return sizeof(double) * 3 * ((size_t)n1max + n2max) + sizeof(int32_t) * (4 * (size_t)n1max + 2 * (size_t)n2max + 4);
+    return sizeof(double) * 3 * ((size_t)n1max + n2max) + sizeof(uint32_t) * pairlist_lds_words(n1max, n2max);
 }
 
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max) {

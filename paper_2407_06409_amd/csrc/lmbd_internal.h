@@ -240,6 +240,7 @@ hipError_t launch_rev_map(hipStream_t st, int n, const Counts* counts, const int
                           int32_t* table, size_t table_len, int32_t* rev, int* err);
 size_t scs_lds_bytes(int n1max, int n2max, bool mixed);
 size_t scs_assemble_lds_bytes(int n1max, int n2max);
+size_t pairlist_lds_bytes(int n1max, int n2max);
 hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
 hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 size_t scs_factor_lds_bytes(int n1max, bool mixed);
