@@ -198,7 +198,8 @@ __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __res
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = Mf::mma(a[e], b[c][e], acc[c]);
+                for (int c = 0; c < 4; ++c)
+                    acc[c] = Mf::mma(a[e], b[c][e], acc[c]);
             a = na;
 #pragma unroll
             for (int c = 0; c < 4; ++c) b[c] = nb[c];
@@ -243,7 +244,7 @@ __device__ inline LrPair<P> lr_pair(P r, P S, P damp_d, P rcut, P rb) {
 }
 
 template <typename W>
-__global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
+__global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     extern __shared__ double lds[];
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
@@ -259,9 +260,10 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     W* T = static_cast<W*>(a.work) + a.work_off[k];
     // sub-arrays start on multiples of 4 elements (aligned 4-vector loads)
     const int KK = n_max * ncol, KKp = (KK + 3) / 4 * 4;
-    W* U = T + al4((size_t)N3 * N3);                         // u_1 .. u_mmax
-    W* V = U + al4((size_t)a.mmax * N3 * ncol);              // D u_m, the next product's operand
-    W* Pm = V + al4((size_t)N3 * ncol);                      // D u_a side by side, a = 0 .. n_max-1
+    const int N3p = (int)al4(N3);                            // row stride of T and of V^T (zero padded)
+    W* U = T + al4((size_t)N3 * N3p);                        // u_1 .. u_mmax
+    W* V = U + al4((size_t)a.mmax * N3 * ncol);              // (D u_m)^T, the next product's operand, ncol x N3p
+    W* Pm = V + al4((size_t)ncol * N3p);                     // D u_a side by side, a = 0 .. n_max-1
     W* Qm = Pm + (size_t)N3 * KKp;                           // W D Z_a side by side
     auto Uat = [&](int m) { return U + (size_t)(m - 1) * N3 * ncol; };
 
@@ -311,8 +313,10 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
             }
         }
         for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) T[(size_t)(3 * i + q) * N3 + 3 * j + c] = W(blk[3 * q + c]);
+            for (int c = 0; c < 3; ++c) T[(size_t)(3 * i + q) * N3p + 3 * j + c] = W(blk[3 * q + c]);
     }
+    for (int e = tid; e < N3 * (N3p - N3); e += blockDim.x) T[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
+    for (int e = tid; e < ncol * (N3p - N3); e += blockDim.x) V[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
     __syncthreads();
 
     // --- u_1 = D T D e_k, V = D u_1
@@ -321,20 +325,20 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
         const int row = e / ncol, col = e % ncol;
         const int q = col / 3, c = col % 3;
         const double sq = L.sqa[(size_t)(row / 3) * nq + q];
-        const double u = sq * double(T[(size_t)row * N3 + c]) * L.sqa[q];
+        const double u = sq * double(T[(size_t)row * N3p + c]) * L.sqa[q];
         U1[e] = W(u);
-        V[e] = W(sq * u);
+        V[(size_t)col * N3p + row] = W(sq * u);
     }
     __syncthreads();
     // --- u_{m+1} = D (T V), V = D u_{m+1}  (T symmetric, so it is its own K-major operand)
     for (int m = 1; m < a.mmax; ++m) {
         W* Un = Uat(m + 1);
-        mfma_gemm<W>(N3, ncol, N3, T, N3, V, ncol, [&](int r, int col, W v) {
+        mfma_gemm_nt<W>(N3, ncol, N3, T, N3p, V, N3p, [&](int r, int col, W v) {
             Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v;
         });
         for (int e = tid; e < N3 * ncol; e += blockDim.x) {
             const int row = e / ncol, col = e % ncol;
-            V[e] = W(L.sqa[(size_t)(row / 3) * nq + col / 3]) * Un[e];
+            V[(size_t)col * N3p + row] = W(L.sqa[(size_t)(row / 3) * nq + col / 3]) * Un[e];
         }
         __syncthreads();
     }
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
     // --- Tbar (overwrites T)
-    mfma_gemm_nt<W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3 + s] = v; });
+    mfma_gemm_nt<W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
@@ -446,8 +450,8 @@ __global__ void __launch_bounds__(256) k_mbd(MbdArgs a, int nkmax) {
             double C[9];
             for (int q = 0; q < 3; ++q)
                 for (int c = 0; c < 3; ++c)
-                    C[3 * q + c] = double(T[(size_t)(3 * i + q) * N3 + 3 * j + c]) +
-                                   double(T[(size_t)(3 * i + c) * N3 + 3 * j + q]);
+                    C[3 * q + c] = double(T[(size_t)(3 * i + q) * N3p + 3 * j + c]) +
+                                   double(T[(size_t)(3 * i + c) * N3p + 3 * j + q]);
             double gp[3];
             radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
             g[0] += gp[0];

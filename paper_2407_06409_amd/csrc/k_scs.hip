@@ -114,6 +114,10 @@ __device__ inline void inner_buffer(double r, double rin, double& fin, double& d
 // each other's memory latency.
 // ---------------------------------------------------------------------------
 constexpr int kSlotLd = 17;   // row stride of a 16x16 tile in LDS (padding against bank conflicts)
+#ifndef LMBD_FACTOR_RING
+#define LMBD_FACTOR_RING 2
+#endif
+constexpr int kRing = LMBD_FACTOR_RING;   // chunks of the panel update in flight per wavefront
 
 // value of x in lane `lane` (a wavefront-uniform constant) for every lane
 __device__ __forceinline__ double bcast(double x, int lane) {
@@ -198,28 +202,32 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 const R* pb0 = A + (size_t)(bok0 ? brow0 : 0) * ld + 4 * lk;
                 const R* pb1 = A + (size_t)(bok1 ? brow1 : 0) * ld + 4 * lk;
                 auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < p) ? load4(base + NB * c) : zero; };
-                // ring of two chunks: each chunk's registers are refilled with the
-                // chunk two ahead right after use
+                // ring of kRing chunks: each chunk's registers are refilled with the
+                // chunk kRing ahead right after use
                 const int c1 = k_lo + s;
-                V4 a0 = ld4(pa, aok, c1), b0 = ld4(pb0, bok0, c1), c0v = ld4(pb1, bok1, c1);
-                V4 a1 = ld4(pa, aok, c1 + S), b1 = ld4(pb0, bok0, c1 + S), c1v = ld4(pb1, bok1, c1 + S);
-                for (int ch = c1; ch < p; ch += 2 * S) {
+                V4 ra[kRing], rb[kRing], rc[kRing];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) acc0 = M::mma(-a0[e], b0[e], acc0);
-                    if (two) {
+                for (int j = 0; j < kRing; ++j) {
+                    ra[j] = ld4(pa, aok, c1 + j * S);
+                    rb[j] = ld4(pb0, bok0, c1 + j * S);
+                    rc[j] = ld4(pb1, bok1, c1 + j * S);
+                }
+                for (int ch = c1; ch < p; ch += kRing * S) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) acc1 = M::mma(-a0[e], c0v[e], acc1);
-                    }
-                    a0 = ld4(pa, aok, ch + 2 * S); b0 = ld4(pb0, bok0, ch + 2 * S); c0v = ld4(pb1, bok1, ch + 2 * S);
-                    if (ch + S < p) {   // uniform
+                    for (int j = 0; j < kRing; ++j) {
+                        if (ch + j * S < p) {   // uniform
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) acc0 = M::mma(-a1[e], b1[e], acc0);
-                        if (two) {
+                            for (int e = 0; e < 4; ++e) acc0 = M::mma(-ra[j][e], rb[j][e], acc0);
+                            if (two) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) acc1 = M::mma(-a1[e], c1v[e], acc1);
+                                for (int e = 0; e < 4; ++e) acc1 = M::mma(-ra[j][e], rc[j][e], acc1);
+                            }
                         }
+                        const int cn = ch + (j + kRing) * S;
+                        ra[j] = ld4(pa, aok, cn);
+                        rb[j] = ld4(pb0, bok0, cn);
+                        rc[j] = ld4(pb1, bok1, cn);
                     }
-                    a1 = ld4(pa, aok, ch + 3 * S); b1 = ld4(pb0, bok0, ch + 3 * S); c1v = ld4(pb1, bok1, ch + 3 * S);
                 }
             }
             R* tl = pan + (size_t)u * NB * kSlotLd;
