@@ -159,7 +159,9 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     const int nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int nt = (N + NB - 1) / NB;
+    const int nt = (N + NB - 1) / NB;           // panels (columns of B~)
+    const int Nr = N + 3;                        // rows: B~, then d^T
+    const int ntr = (Nr + NB - 1) / NB;          // row tiles
     const V4 zero = {R(0), R(0), R(0), R(0)};
     bool good = true;
     bool paired_prev = false;   // the previous (even) panel already applied chunks < p-1 to this panel
@@ -168,7 +170,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     for (int p = 0; p < nt; ++p) {
         const int c0 = p * NB;
         const int jb = min(NB, N - c0);
-        const int m = nt - p;
+        const int m = ntr - p;                       // row tiles from this panel down
         const bool only_last = paired_prev;          // then only chunk p-1 is left
         const int k_lo = only_last ? p - 1 : 0;
         const int nk = p - k_lo;                     // chunks of this panel's update
@@ -192,12 +194,12 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li;
-                acc0[q] = (s == 0 && row < N && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
+                acc0[q] = (s == 0 && row < Nr && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
                 acc1[q] = R(0);
             }
             if (nk > 0) {
                 const int arow = c0 + NB * t + li, brow0 = c0 + li, brow1 = c0 + NB + li;
-                const bool aok = arow < N, bok0 = brow0 < N, bok1 = two && brow1 < N;
+                const bool aok = arow < Nr, bok0 = brow0 < N, bok1 = two && brow1 < N;
                 const R* pa = A + (size_t)(aok ? arow : 0) * ld + 4 * lk;
                 const R* pb0 = A + (size_t)(bok0 ? brow0 : 0) * ld + 4 * lk;
                 const R* pb1 = A + (size_t)(bok1 ? brow1 : 0) * ld + 4 * lk;
@@ -237,7 +239,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + NB + li;
-                    if (row < N && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] += acc1[q];
+                    if (row < Nr && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] += acc1[q];
                 }
             }
         };
@@ -321,9 +323,12 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         }
         if (tid == 0) counter[(p + 1) & 1] = 0;   // for the next panel (its last use was two barriers ago)
         __syncthreads();
-        // (3) rows below the block: X = A Z^T on MFMA, one 16-row tile per
-        // wavefront, A summed over the k-split parts in the panel buffer
-        for (int t = 1 + (wave - dw + nwave) % nwave; t < m; t += nwave) {
+        // (3) rows below the block (the rows of d^T among them): X = A Z^T on
+        // MFMA, one 16-row tile per wavefront, A summed over the k-split parts in
+        // the panel buffer; in a last, partial panel the rows of d^T share the
+        // diagonal tile
+        const int t0 = jb < NB ? 0 : 1;
+        for (int t = t0 + (wave - dw + nwave) % nwave; t < m; t += nwave) {
             typename M::acc x;
 #pragma unroll
             for (int q = 0; q < 4; ++q) x[q] = R(0);
@@ -337,7 +342,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = c0 + NB * t + M::acc_row(lk, q);
-                if (row < N) A[(size_t)row * ld + c0 + li] = x[q];
+                if (row >= c0 + jb && row < Nr && c0 + li < N) A[(size_t)row * ld + c0 + li] = x[q];
             }
         }
         __syncthreads();
@@ -347,7 +352,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
 
 // panel buffer tiles of the factorisation for neighbourhoods of up to n1max atoms
 __host__ __device__ inline int factor_tiles(int n1max) {
-    const int nt = (3 * n1max + NB - 1) / NB;
+    const int nt = (3 * n1max + 3 + NB - 1) / NB;
     return nt > 4 ? nt : 4;
 }
 
@@ -368,7 +373,7 @@ __device__ __forceinline__ void solve_row_update(const R* __restrict__ lrow, int
 }
 
 template <typename R>
-__device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y, R* zbuf) {
+__device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y, R* zbuf, bool fwd) {
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -404,44 +409,46 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
         }
     };
     R zr[kZ];
-    // forward: L y = b, one row per thread (blockDim >= N); the row's segment of
-    // the next block is loaded a block ahead
     R cur[NB], nxt[NB];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const V4 t4 = (tid >= NB && tid < N) ? load4(A + (size_t)tid * ld + 4 * v) : zero;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) cur[4 * v + e] = t4[e];
-    }
-    zload(0, true, zr);
-    zstore(zbuf, zr);
-    zload(1, true, zr);
-    __syncthreads();
-    for (int p = 0; p < nt; ++p) {
-        const int c0 = p * NB;
-        const int jb = min(NB, N - c0);
-        R* zb = zbuf + (p & 1) * NB * kSlotLd;
-        zstore(zbuf + ((p + 1) & 1) * NB * kSlotLd, zr);   // block p + 1 (loaded during block p - 1)
-        zload(p + 2, true, zr);
-        const bool pre = tid >= c0 + 2 * NB && tid < N;      // row tid follows block p + 1
+    if (fwd) {
+        // forward: L y = b, one row per thread (blockDim >= N); the row's segment of
+        // the next block is loaded a block ahead
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const V4 t4 = pre ? load4(A + (size_t)tid * ld + c0 + NB + 4 * v) : zero;
+            const V4 t4 = (tid >= NB && tid < N) ? load4(A + (size_t)tid * ld + 4 * v) : zero;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
+            for (int e = 0; e < 4; ++e) cur[4 * v + e] = t4[e];
         }
-        if (blk && r < jb) {
-            R v = 0;
+        zload(0, true, zr);
+        zstore(zbuf, zr);
+        zload(1, true, zr);
+        __syncthreads();
+        for (int p = 0; p < nt; ++p) {
+            const int c0 = p * NB;
+            const int jb = min(NB, N - c0);
+            R* zb = zbuf + (p & 1) * NB * kSlotLd;
+            zstore(zbuf + ((p + 1) & 1) * NB * kSlotLd, zr);   // block p + 1 (loaded during block p - 1)
+            zload(p + 2, true, zr);
+            const bool pre = tid >= c0 + 2 * NB && tid < N;      // row tid follows block p + 1
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q < jb) v += zb[r * kSlotLd + q] * Y[(c0 + q) * 3 + c];  // rows past N hold no values
-            Y[(c0 + r) * 3 + c] = v;  // one wavefront: all reads of the block precede this write
+            for (int v = 0; v < 4; ++v) {
+                const V4 t4 = pre ? load4(A + (size_t)tid * ld + c0 + NB + 4 * v) : zero;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
+            }
+            if (blk && r < jb) {
+                R v = 0;
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (q < jb) v += zb[r * kSlotLd + q] * Y[(c0 + q) * 3 + c];  // rows past N hold no values
+                Y[(c0 + r) * 3 + c] = v;  // one wavefront: all reads of the block precede this write
+            }
+            __syncthreads();
+            if (tid >= c0 + NB && tid < N) solve_row_update(cur, c0, NB, tid, Y);  // jb = 16 when rows follow
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
         }
-        __syncthreads();
-        if (tid >= c0 + NB && tid < N) solve_row_update(cur, c0, NB, tid, Y);  // jb = 16 when rows follow
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
     }
     // backward: L^T x = y; column tid's segment of the previous block is loaded a block ahead
     {
@@ -676,6 +683,7 @@ __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n
     const Counts cnt = a.counts[k];
     const int n1 = cnt.n1, n12 = cnt.n12;
     const int N = 3 * n1;
+    const int ld = a.fac_ld[k];
     const double rc = a.sinfo[a.atom_struct[k]].r_scs;
     ScsLds L = scs_assemble_lds(lds, n1max, n2max, false);
     double* D = (mixed ? a.dvec : a.xsol) + a.x_off[k] + (size_t)w * N * 3;
@@ -711,10 +719,15 @@ __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n
         add_carries<6>(L.gk, carry, carry_key);
     }
     __syncthreads();
+    // d (N x 3) to its slot, and d^T as the three rows appended to B~, so that the
+    // factorisation carries out the forward substitution
+    R* Dt = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3) + (size_t)N * ld;
     for (int i = t; i < n1; i += kChunk) {
         const double* g = L.gk + 6 * i;
         const double d[9] = {1.0 - g[0], -g[1], -g[2], -g[1], 1.0 - g[3], -g[4], -g[2], -g[4], 1.0 - g[5]};
         for (int e = 0; e < 9; ++e) D[(3 * i + e / 3) * 3 + e % 3] = d[e];
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c) Dt[(size_t)c * ld + 3 * i + q] = R(d[3 * q + c]);
     }
 }
 
@@ -743,7 +756,7 @@ __global__ void __launch_bounds__(kChunk) k_scs_assemble(ScsArgs a, int n1max) {
     int32_t* slot = L.key;                                  // kChunk
     int32_t* wcnt = L.key + kChunk;                         // kChunk / 32
     uint32_t* mask = reinterpret_cast<uint32_t*>(L.key + 2 * kChunk);
-    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
+    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
     const int npairs = n1 * (n1 + 1) / 2;
     float* coef = mixed ? a.coef + a.coef_off[k] + (size_t)w * 2 * npairs : nullptr;
     const int32_t* seg_a = pair_segs(a, k) + (n12 + 2);
@@ -832,7 +845,7 @@ __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     const int w = blockIdx.y;
     const int N = 3 * a.counts[k].n1;
     const int ld = a.fac_ld[k];
-    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
+    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
     // the wave that factorises the diagonal blocks rotates over the workgroups
     const int dw = (k + w) % (blockDim.x >> 6);
     bool ok = true;
@@ -857,8 +870,9 @@ size_t scs_factor_lds_bytes(int n1max, bool mixed) {
 
 // Triangular solves with the stored factor, one workgroup of >= N threads per
 // (atom, frequency).  Right-hand side and result by mode:
-//   kSolveD      : d (solution slot) -> X (solution slot) and Tr(X_i)/3      [FP64]
-//   kSolveFirst  : d (dvec) -> X                                             [mixed]
+//   kSolveD      : y = L^{-1} d (left by the factorisation) -> X (solution
+//                  slot) and Tr(X_i)/3                                       [FP64]
+//   kSolveFirst  : y = L^{-1} d -> X                                         [mixed]
 //   kSolveCorr   : residual -> X += correction, then Tr(X_i)/3               [mixed]
 //   kSolveLambda : Xbar_i = xbar_i I / 3 from the polarisability adjoints -> lambda
 enum { kSolveD = 0, kSolveFirst = 1, kSolveCorr = 2, kSolveLambda = 3 };
@@ -871,7 +885,7 @@ __global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mod
     const int n1 = a.counts[k].n1;
     const int N = 3 * n1;
     const int ld = a.fac_ld[k];
-    const R* A = static_cast<const R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * N;
+    const R* A = static_cast<const R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
     const size_t xo = a.x_off[k] + (size_t)w * N * 3;
     R* Y = reinterpret_cast<R*>(lds);
     R* zbuf = Y + 9 * n1max;
@@ -883,12 +897,14 @@ __global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mod
             if (s == 0) xb += a.abar_cen[(size_t)k * a.nw + w];
             Y[e] = (q == c) ? R(xb / 3.0) : R(0);
         }
+    } else if (mode == kSolveCorr) {
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = R(a.resid[xo + e]);
     } else {
-        const double* src = mode == kSolveD ? a.xsol : (mode == kSolveFirst ? a.dvec : a.resid);
-        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = R(src[xo + e]);
+        // the factorisation left y = L^{-1} d in the rows appended to B~
+        for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = A[(size_t)(N + e % 3) * ld + e / 3];
     }
     __syncthreads();
-    chol_solve3<R>(A, N, ld, Y, zbuf);
+    chol_solve3<R>(A, N, ld, Y, zbuf, mode == kSolveCorr || mode == kSolveLambda);
     if (mode == kSolveLambda) {
         for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) a.lam[xo + e] = double(Y[e]);
         return;

@@ -284,7 +284,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         P.fac_ld[k] = (int32_t)((N1 + 3) / 4 * 4);
         so += c.n_all;
         ho += P.hash_cap[k];
-        fo += (int64_t)nw * N1 * P.fac_ld[k];
+        fo += (int64_t)nw * (N1 + 3) * P.fac_ld[k];   // B~ and, appended, the three rows of d^T
         xo += (int64_t)nw * N1 * 3;
         ao += (int64_t)c.n1 * nw;
         auto al4 = [](int64_t x) { return (x + 3) / 4 * 4; };  // as the MBD kernel lays out its workspace

@@ -166,7 +166,7 @@ struct ScsArgs {
     void* fac;               // factor slots (double or float): per atom nw * N * ld, row-major lower,
                              // inverses of the 16x16 diagonal blocks in their strict upper parts
     const int64_t* fac_off;
-    const int32_t* fac_ld;   // ld >= N, a multiple of 4
+    const int32_t* fac_ld;   // ld >= N, a multiple of 4; per (atom, frequency) N + 3 rows: B~, then d^T
     float* coef;             // mixed path: FP32 pair coefficients (A, B) of B~, per atom nw * n1 (n1 + 1) / 2 pairs
     const int64_t* coef_off; // per atom, in floats
     double* xsol;            // per atom nw * N * 3 (row-major): d, then the solution X
