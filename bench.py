@@ -50,10 +50,10 @@ def scs_factor_flops(n1, nw):
     return float(np.sum(nw * N ** 3 / 3.0))
 
 
-def scs_solve_flops(n1, nw, n_solves):
-    """Two triangular solves with 3 right-hand sides: 6 N^2 per solve and (atom, frequency)."""
+def scs_solve_flops(n1, nw, n_tri):
+    """Triangular solves with 3 right-hand sides: 3 N^2 per triangular solve and (atom, frequency)."""
     N = 3.0 * n1.astype(np.float64)
-    return float(np.sum(nw * n_solves * 6.0 * N ** 2))
+    return float(np.sum(nw * n_tri * 3.0 * N ** 2))
 
 
 def source_digest(paths):
@@ -327,12 +327,14 @@ def main():
     nq, nw, n_max = len(grid[0]), len(grid[0]) + 1, DEFAULT_PARAMS["n_max"]
     n1 = neighbour_counts(st, cut["r_scs"])
     nK = neighbour_counts(st, cut["r_nbr"])
-    n_solves = 1 if args.precision == "fp64" else 2
+    # the forward substitution of X = B~^-1 d is carried by the factorisation:
+    # FP64 solves backward only; mixed adds the forward+backward correction solve
+    n_tri = 1 if args.precision == "fp64" else 3
     flops = {
         "scs_factor": scs_factor_flops(n1, nw),
-        "scs_solve": scs_solve_flops(n1, nw, n_solves),
+        "scs_solve": scs_solve_flops(n1, nw, n_tri),
         "mbd": mbd_flops(nK, nq, n_max, True),
-        "scs_lambda": scs_solve_flops(n1, nw, 1),
+        "scs_lambda": scs_solve_flops(n1, nw, 2),
     }
     peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
     stage_tflops = {k: flops[k] / (stage_ms[k] * 1e-3) / 1e12 for k in flops if stage_ms.get(k, 0) > 0}
