@@ -18,6 +18,8 @@
 // then contracted pair by pair with dT_LR/dr and dT_LR/dS~, and pushed
 // through the blend (local part to this atom's SCS, central part scattered to
 // the neighbours' own SCS through a per-site contribution buffer).
+#include <type_traits>
+
 #include "lmbd_internal.h"
 
 namespace lmbd {
@@ -75,78 +77,7 @@ template <> struct MfmaW<float> {
     static __device__ inline int acc_row(int g, int q) { return 4 * g + q; }
 };
 
-// Workgroup GEMM on the matrix cores: out(m, n) = sum_k AT[k][m] B[k][n], both
-// operands K-major (lda, ldb), so the 16 lanes of an MFMA operand read 16
-// consecutive elements.  Each wavefront takes a 16-row strip times up to four
-// 16-column tiles (sharing the A operand); the k loop advances 16 at a time with
-// the next 16 in flight.  Out-of-range rows, columns and k are zero.
-template <typename W, typename ST>
-__device__ __forceinline__ void mfma_gemm(int M, int N, int K, const W* __restrict__ AT, int lda,
-                                          const W* __restrict__ B, int ldb, ST st) {
-    typedef MfmaW<W> Mf;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int mt = (M + 15) / 16;
-    const int nt = (N + 15) / 16;
-    const int ng = (nt + 3) / 4;
-    for (int t = wave; t < mt * ng; t += nwave) {
-        const int m0 = (t / ng) * 16;
-        const int tc0 = (t % ng) * 4;
-        typename Mf::acc acc[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[c][q] = W(0);
-        const int am = m0 + li;
-        int bn[4];
-        bool bok[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            bn[c] = (tc0 + c) * 16 + li;
-            bok[c] = bn[c] < N && tc0 + c < nt;
-        }
-        const bool aok = am < M;
-        // one 16-k chunk: four MFMA k-steps, lane k index lk + 4 s
-        W a[4], b[4][4], na[4], nb[4][4];
-        auto load = [&](int k0, W* xa, W (*xb)[4]) {
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) {
-                const int kk = k0 + lk + 4 * s2;
-                const bool kok = kk < K;
-                xa[s2] = (aok && kok) ? AT[(size_t)kk * lda + am] : W(0);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) xb[c][s2] = (bok[c] && kok) ? B[(size_t)kk * ldb + bn[c]] : W(0);
-            }
-        };
-        load(0, a, b);
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            load(k0 + 16, na, nb);
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = Mf::mma(a[s2], b[c][s2], acc[c]);
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) {
-                a[s2] = na[s2];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) b[c][s2] = nb[c][s2];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (bok[c]) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int m = m0 + Mf::acc_row(lk, q);
-                    if (m < M) st(m, bn[c], acc[c][q]);
-                }
-            }
-        }
-    }
-    __syncthreads();
-}
-
-// Workgroup GEMM out(m, n) = sum_k A[m][k] B[n][k] with both operands k-contiguous
+// Workgroup GEMM on the matrix cores: out(m, n) = sum_k A[m][k] B[n][k] with both operands k-contiguous
 // (row-major, lda/ldb multiples of 4, K a multiple of 4).  Lane (i, g) of an MFMA
 // operand reads the 4-vector k = 16 c + 4 g .. + 3 and feeds element e to k-step e,
 // the same permutation of k for both operands; 16 k per chunk, the next chunk in
@@ -163,49 +94,48 @@ __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __res
     const int ng = (nt + 3) / 4;
     const int nch = (K + 15) / 16;
     const V4 zero = {W(0), W(0), W(0), W(0)};
-    for (int t = wave; t < mt * ng; t += nwave) {
-        const int m0 = (t / ng) * 16;
-        const int tc0 = (t % ng) * 4;
-        typename Mf::acc acc[4];
+    auto kin = [&](int ch) { return ch < nch && 16 * ch + 4 * lk < K; };
+    // one 16-row strip times NV column tiles (NV = the tiles of the group inside N)
+    auto item = [&](int m0, int tc0, auto nvc) {
+        constexpr int NV = decltype(nvc)::value;
+        typename Mf::acc acc[NV];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NV; ++c)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[c][q] = W(0);
         const int am = m0 + li;
         const bool aok = am < M;
         const W* pa = A + (size_t)(aok ? am : 0) * lda + 4 * lk;
-        const W* pb[4];
-        bool bok[4];
-        int bn[4];
+        const W* pb[NV];
+        bool bok[NV];
+        int bn[NV];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NV; ++c) {
             bn[c] = (tc0 + c) * 16 + li;
-            bok[c] = bn[c] < N && tc0 + c < nt;
+            bok[c] = bn[c] < N;
             pb[c] = B + (size_t)(bok[c] ? bn[c] : 0) * ldb + 4 * lk;
         }
-        auto kin = [&](int ch) { return ch < nch && 16 * ch + 4 * lk < K; };
         V4 a = (aok && kin(0)) ? *reinterpret_cast<const V4*>(pa) : zero;
-        V4 b[4];
+        V4 b[NV];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = (bok[c] && kin(0)) ? *reinterpret_cast<const V4*>(pb[c]) : zero;
+        for (int c = 0; c < NV; ++c) b[c] = (bok[c] && kin(0)) ? *reinterpret_cast<const V4*>(pb[c]) : zero;
         for (int ch = 0; ch < nch; ++ch) {
             const bool kn = kin(ch + 1);
             const V4 na = (aok && kn) ? *reinterpret_cast<const V4*>(pa + 16 * (ch + 1)) : zero;
-            V4 nb[4];
+            V4 nb[NV];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < NV; ++c)
                 nb[c] = (bok[c] && kn) ? *reinterpret_cast<const V4*>(pb[c] + 16 * (ch + 1)) : zero;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[c] = Mf::mma(a[e], b[c][e], acc[c]);
+                for (int c = 0; c < NV; ++c) acc[c] = Mf::mma(a[e], b[c][e], acc[c]);
             a = na;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = nb[c];
+            for (int c = 0; c < NV; ++c) b[c] = nb[c];
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NV; ++c) {
             if (bok[c]) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -213,6 +143,16 @@ __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __res
                     if (m < M) st(m, bn[c], acc[c][q]);
                 }
             }
+        }
+    };
+    for (int t = wave; t < mt * ng; t += nwave) {
+        const int m0 = (t / ng) * 16;
+        const int tc0 = (t % ng) * 4;
+        switch (min(4, nt - tc0)) {   // uniform over the wavefront
+            case 1: item(m0, tc0, std::integral_constant<int, 1>()); break;
+            case 2: item(m0, tc0, std::integral_constant<int, 2>()); break;
+            case 3: item(m0, tc0, std::integral_constant<int, 3>()); break;
+            default: item(m0, tc0, std::integral_constant<int, 4>()); break;
         }
     }
     __syncthreads();

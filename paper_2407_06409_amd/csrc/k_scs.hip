@@ -694,12 +694,15 @@ __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n
     for (int e = t; e < 6 * n1; e += kChunk) L.gk[e] = 0.0;
     __syncthreads();
     const int P12 = seg_i[n1];
+    // list entries are loaded a chunk ahead (two dependent global reads)
+    int32_t ent_next = t < P12 ? lq[li[t]] : 0;
     for (int e0 = 0; e0 < P12; e0 += kChunk) {
         const int e = e0 + t;
+        const int32_t ent = ent_next;
+        if (e + kChunk < P12) ent_next = lq[li[e + kChunk]];
         int key = -1;
         double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (e < P12) {
-            const int32_t ent = lq[li[e]];
             const int q = ent >> 16, i = ent & 0xFFFF;
             key = i;
             double rh[3], r;
@@ -1071,13 +1074,15 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
         const int P = seg_a[n1];
         int p = t < n1 ? seg_b[t] : 0;
         const int pe = t < n1 ? seg_b[t + 1] : 0;
+        int32_t ent_next = t < P ? la[t] : 0;   // list entries a chunk ahead
         for (int e0 = 0; e0 < P; e0 += kChunk) {
             prefetch(lb, p, pe);
             const int e = e0 + t;
+            const int32_t ent = ent_next;
+            if (e + kChunk < P) ent_next = la[e + kChunk];
             int key = -1;
             double h[3] = {0.0, 0.0, 0.0};
             if (e < P) {
-                const int32_t ent = la[e];
                 const int i = ent >> 16, j = ent & 0xFFFF;
                 key = i;
                 double rh[3], r;
@@ -1116,13 +1121,15 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
         const int P = seg_q[n2];
         int p = t < n1 ? seg_i[t] : 0;
         const int pe = t < n1 ? seg_i[t + 1] : 0;
+        int32_t ent_next = t < P ? lq[t] : 0;   // list entries a chunk ahead
         for (int e0 = 0; e0 < P; e0 += kChunk) {
             prefetch(li, p, pe);
             const int e = e0 + t;
+            const int32_t ent = ent_next;
+            if (e + kChunk < P) ent_next = lq[e + kChunk];
             int key = -1;
             double h[3] = {0.0, 0.0, 0.0};
             if (e < P) {
-                const int32_t ent = lq[e];
                 const int q = ent >> 16, i = ent & 0xFFFF;
                 key = q;
                 double rh[3], r;
