@@ -190,11 +190,16 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         auto unit = [&](int u) {
             const int t = u % m, s = u / m;
             const bool two = pair && t > 0;
+            // the matrix values this unit adds to are read first and added after
+            // the products, so their latency hides behind the chunk loop
             typename M::acc acc0, acc1;
+            R init0[4], init1[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li;
-                acc0[q] = (s == 0 && row < Nr && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
+                const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li, col1 = c0 + NB + li;
+                init0[q] = (s == 0 && row < Nr && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
+                init1[q] = (two && row < Nr && col1 < N && (t > 1 || row >= col1)) ? A[(size_t)row * ld + col1] : R(0);
+                acc0[q] = R(0);
                 acc1[q] = R(0);
             }
             if (nk > 0) {
@@ -234,12 +239,12 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             }
             R* tl = pan + (size_t)u * NB * kSlotLd;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) tl[M::acc_row(lk, q) * kSlotLd + li] = acc0[q];
+            for (int q = 0; q < 4; ++q) tl[M::acc_row(lk, q) * kSlotLd + li] = init0[q] + acc0[q];
             if (two) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + NB + li;
-                    if (row < Nr && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] += acc1[q];
+                    if (row < Nr && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] = init1[q] + acc1[q];
                 }
             }
         };
