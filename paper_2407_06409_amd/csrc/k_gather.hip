@@ -69,6 +69,17 @@ __global__ void __launch_bounds__(256) k_gather_forces(int n, int nslices, int64
     }
 }
 
+// cf[0][x] = sum over slices sl = 0 .. nslices-1 of cf[sl][x] (in slice order), so
+// that the force gather reads one slice
+__global__ void __launch_bounds__(256) k_slice_sum(int64_t len, int nslices, int64_t slice_stride,
+                                                   double* __restrict__ cf) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= len) return;
+    double s = cf[x];
+    for (int sl = 1; sl < nslices; ++sl) s += cf[sl * slice_stride + x];
+    cf[x] = s;
+}
+
 // central static SCS polarisability alpha~_I,k(0): row 0, frequency 0 of each local solve
 __global__ void k_central_static(int n, int nw, const double* __restrict__ alpha_loc,
                                  const int64_t* __restrict__ aloc_off, double* __restrict__ out) {
@@ -86,8 +97,11 @@ hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* co
 
 hipError_t launch_gather_forces(hipStream_t st, int n, int nslices, int64_t slice_stride,
                                 const Counts* counts, const int64_t* site_off, const Site* sites,
-                                const int32_t* rev, const double* cf, double* forces) {
-    hipLaunchKernelGGL(k_gather_forces, dim3((n + 3) / 4), dim3(256), 0, st, n, nslices, slice_stride,
+                                const int32_t* rev, double* cf, double* forces) {
+    // slices first summed in place into slice 0 (coalesced), then one gathered read per site
+    hipLaunchKernelGGL(k_slice_sum, dim3((unsigned)((slice_stride + 255) / 256)), dim3(256), 0, st, slice_stride,
+                       nslices, slice_stride, cf);
+    hipLaunchKernelGGL(k_gather_forces, dim3((n + 3) / 4), dim3(256), 0, st, n, 1, slice_stride,
                        counts, site_off, sites, rev, cf, forces);
     return hipGetLastError();
 }

@@ -1336,37 +1336,46 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
     int32_t* lq = const_cast<int32_t*>(a.pl_q) + a.pl_off[k];
     int32_t* la = li + (int64_t)n1 * n2;
     int32_t* lb = lq + (int64_t)n1 * n2;
-    // shell-major entries (q << 16) | i, i ascending
-    for (int q = t; q < n2; q += nt) {
-        int pos = L.cnt_q[q];
-        for (int w = 0; w < wa; ++w)
-            for (uint32_t m = L.cq[(size_t)q * wa + w]; m; m &= m - 1) lq[pos++] = (q << 16) | (32 * w + __ffs(m) - 1);
+    // list entries, one (major site, 32-bit word of its bit row) per thread: the
+    // word's first position is the row's offset plus the set bits before it
+    for (int it = t; it < n2 * wa; it += nt) {   // shell-major entries (q << 16) | i, i ascending
+        const int q = it / wa, w = it % wa;
+        const uint32_t* row = L.cq + (size_t)q * wa;
+        int pos = L.cnt_q[q] + bits_below(row, 32 * w);
+        for (uint32_t m = row[w]; m; m &= m - 1) lq[pos++] = (q << 16) | (32 * w + __ffs(m) - 1);
     }
-    for (int i = t; i < n1; i += nt) {
-        // a-major entries (i << 16) | j, j > i ascending
-        int pos = L.cnt_a[i];
-        for (int w = 0; w < wa; ++w)
-            for (uint32_t m = L.na[(size_t)i * wa + w]; m; m &= m - 1) la[pos++] = (i << 16) | (32 * w + __ffs(m) - 1);
-        // i-major index list: shell partners in scrambled order, each the index
-        // of (q, i) in the shell-major list
-        pos = L.cnt_i[i];
-        for (int w = 0; w < wq; ++w)
-            for (uint32_t m = L.bq[(size_t)i * wq + w]; m; m &= m - 1) {
-                const int x = 32 * w + __ffs(m) - 1;
-                const int q = (int)(((int64_t)x * sq) % n2);
-                li[pos++] = L.cnt_q[q] + bits_below(L.cq + (size_t)q * wa, i);
-            }
-        // b-side index list: K1 partners j < i in scrambled order, each the
-        // index of (j, i) in the a-major list
-        pos = L.cnt_b[i];
-        for (int w = 0; w < wa; ++w)
-            for (uint32_t m = L.nb[(size_t)i * wa + w]; m; m &= m - 1) {
-                const int x = 32 * w + __ffs(m) - 1;
-                const int j = (int)(((int64_t)x * sa) % n1);
-                lb[pos++] = L.cnt_a[j] + bits_below(L.na + (size_t)j * wa, i);
-            }
+    for (int it = t; it < n1 * wa; it += nt) {   // a-major entries (i << 16) | j, j > i ascending
+        const int i = it / wa, w = it % wa;
+        const uint32_t* row = L.na + (size_t)i * wa;
+        int pos = L.cnt_a[i] + bits_below(row, 32 * w);
+        for (uint32_t m = row[w]; m; m &= m - 1) la[pos++] = (i << 16) | (32 * w + __ffs(m) - 1);
+    }
+    // i-major index list: shell partners in scrambled order, each the index of
+    // (q, i) in the shell-major list
+    for (int it = t; it < n1 * wq; it += nt) {
+        const int i = it / wq, w = it % wq;
+        const uint32_t* row = L.bq + (size_t)i * wq;
+        int pos = L.cnt_i[i] + bits_below(row, 32 * w);
+        for (uint32_t m = row[w]; m; m &= m - 1) {
+            const int x = 32 * w + __ffs(m) - 1;
+            const int q = (int)(((int64_t)x * sq) % n2);
+            li[pos++] = L.cnt_q[q] + bits_below(L.cq + (size_t)q * wa, i);
+        }
+    }
+    // b-side index list: K1 partners j < i in scrambled order, each the index of
+    // (j, i) in the a-major list
+    for (int it = t; it < n1 * wa; it += nt) {
+        const int i = it / wa, w = it % wa;
+        const uint32_t* row = L.nb + (size_t)i * wa;
+        int pos = L.cnt_b[i] + bits_below(row, 32 * w);
+        for (uint32_t m = row[w]; m; m &= m - 1) {
+            const int x = 32 * w + __ffs(m) - 1;
+            const int j = (int)(((int64_t)x * sa) % n1);
+            lb[pos++] = L.cnt_a[j] + bits_below(L.na + (size_t)j * wa, i);
+        }
     }
 }
+
 
 size_t pairlist_lds_bytes(int n1max, int n2max) {
     return sizeof(double) * 3 * ((size_t)n1max + n2max) + sizeof(uint32_t) * pairlist_lds_words(n1max, n2max);

@@ -255,7 +255,7 @@ hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* co
                                  const double* ca, double* abar_cen);
 hipError_t launch_gather_forces(hipStream_t st, int n, int nslices, int64_t slice_stride,
                                 const Counts* counts, const int64_t* site_off, const Site* sites,
-                                const int32_t* rev, const double* cf, double* forces);
+                                const int32_t* rev, double* cf, double* forces);
 hipError_t launch_central_static(hipStream_t st, int n, int nw, const double* alpha_loc,
                                  const int64_t* aloc_off, double* out);
 
