@@ -591,14 +591,11 @@ __device__ inline int32_t* pair_segs(const ScsArgs& a, int k) {
 }
 
 // sites only (assembly): K1 sites then shell sites
-// assembly of d: K1 sites, shell sites, the d sums (6 per K1 site) and the
-// chunk's keys; assembly of B~: K1 sites, one chunk of pair values and slots,
-// word counts and a bit per K1 pair (coupled)
+// assembly of d: K1 sites and shell sites; assembly of B~: K1 sites, one
+// chunk of pair values and slots, word counts and a bit per K1 pair (coupled)
 __host__ __device__ inline int assemble_mask_words(int n1max) { return (n1max * (n1max + 1) / 2 + 31) / 32; }
 
-static size_t dvec_lds_bytes(int n1max, int n2max) {
-    return sizeof(double) * (12 * (size_t)n1max + 6 * (size_t)n2max) + sizeof(int32_t) * kChunk;
-}
+static size_t dvec_lds_bytes(int n1max, int n2max) { return sizeof(double) * 6 * ((size_t)n1max + n2max); }
 static size_t matrix_lds_bytes(int n1max) {
     return sizeof(double) * (6 * (size_t)n1max + 2 * kChunk) +
            sizeof(int32_t) * (2 * kChunk + (size_t)assemble_mask_words(n1max));
@@ -673,14 +670,15 @@ __device__ inline SrPair<P> k2_pair(const ScsArgs& a, const ScsLds& L, int i, in
 }
 
 // Assembly of d (into the solution slot), one workgroup per (atom, frequency):
-// d_i = I - sum_q alpha_q T_SR(i, q) over the coupled shell sites, one pair
-// per thread from the i-major list; the 6 components of each symmetric 3x3
-// term are summed over the runs of each K1 site.
+// d_i = I - sum_q alpha_q T_SR(i, q) over the coupled shell sites.  Sixteen
+// lanes per K1 site take its pairs of the i-major list in turn (lane l the
+// pairs l, l + 16, ...), and a fixed exchange tree over the sixteen lanes sums
+// the 6 components of the symmetric 3x3 terms: no barriers, a fixed order.
+constexpr int kSiteLanes = 16;
+
 template <typename R>
 __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
-    __shared__ double carry[6 * kChunkWaves];
-    __shared__ int carry_key[kChunkWaves];
     constexpr bool mixed = sizeof(R) == 4;
     const int k = blockIdx.x;
     const int w = blockIdx.y;
@@ -696,46 +694,35 @@ __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n
     const int32_t* li = a.pl_i + a.pl_off[k];
     const int32_t* lq = a.pl_q + a.pl_off[k];
     load_sites(a, k, w, n1, n12, L);
-    for (int e = t; e < 6 * n1; e += kChunk) L.gk[e] = 0.0;
-    __syncthreads();
-    const int P12 = seg_i[n1];
-    // list entries are loaded a chunk ahead (two dependent global reads)
-    int32_t ent_next = t < P12 ? lq[li[t]] : 0;
-    for (int e0 = 0; e0 < P12; e0 += kChunk) {
-        const int e = e0 + t;
-        const int32_t ent = ent_next;
-        if (e + kChunk < P12) ent_next = lq[li[e + kChunk]];
-        int key = -1;
-        double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (e < P12) {
-            const int q = ent >> 16, i = ent & 0xFFFF;
-            key = i;
-            double rh[3], r;
-            const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
-            const double A_ = tp.A, B_ = tp.B, ab = L.qab[q];
-            h[0] = ab * (A_ * rh[0] * rh[0] + B_);
-            h[1] = ab * (A_ * rh[0] * rh[1]);
-            h[2] = ab * (A_ * rh[0] * rh[2]);
-            h[3] = ab * (A_ * rh[1] * rh[1] + B_);
-            h[4] = ab * (A_ * rh[1] * rh[2]);
-            h[5] = ab * (A_ * rh[2] * rh[2] + B_);
-        }
-        L.key[t] = key;
-        __syncthreads();
-        run_sums<6>(key, h, L.key, L.gk, carry, carry_key);
-        __syncthreads();
-        add_carries<6>(L.gk, carry, carry_key);
-    }
     __syncthreads();
     // d (N x 3) to its slot, and d^T as the three rows appended to B~, so that the
     // factorisation carries out the forward substitution
     R* Dt = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3) + (size_t)N * ld;
-    for (int i = t; i < n1; i += kChunk) {
-        const double* g = L.gk + 6 * i;
-        const double d[9] = {1.0 - g[0], -g[1], -g[2], -g[1], 1.0 - g[3], -g[4], -g[2], -g[4], 1.0 - g[5]};
-        for (int e = 0; e < 9; ++e) D[(3 * i + e / 3) * 3 + e % 3] = d[e];
-        for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) Dt[(size_t)c * ld + 3 * i + q] = R(d[3 * q + c]);
+    const int g = t / kSiteLanes, gl = t % kSiteLanes;
+    for (int i = g; i < n1; i += kChunk / kSiteLanes) {
+        double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int e = seg_i[i] + gl; e < seg_i[i + 1]; e += kSiteLanes) {
+            const int q = lq[li[e]] >> 16;
+            double rh[3], r;
+            const SrPair<R> tp = k2_pair<R>(a, L, i, q, rc, rh, r);
+            const double A_ = tp.A, B_ = tp.B, ab = L.qab[q];
+            h[0] += ab * (A_ * rh[0] * rh[0] + B_);
+            h[1] += ab * (A_ * rh[0] * rh[1]);
+            h[2] += ab * (A_ * rh[0] * rh[2]);
+            h[3] += ab * (A_ * rh[1] * rh[1] + B_);
+            h[4] += ab * (A_ * rh[1] * rh[2]);
+            h[5] += ab * (A_ * rh[2] * rh[2] + B_);
+        }
+#pragma unroll
+        for (int m = 1; m < kSiteLanes; m <<= 1)
+#pragma unroll
+            for (int v = 0; v < 6; ++v) h[v] += __shfl_xor(h[v], m);
+        if (gl == 0) {
+            const double d[9] = {1.0 - h[0], -h[1], -h[2], -h[1], 1.0 - h[3], -h[4], -h[2], -h[4], 1.0 - h[5]};
+            for (int e = 0; e < 9; ++e) D[(3 * i + e / 3) * 3 + e % 3] = d[e];
+            for (int q = 0; q < 3; ++q)
+                for (int c = 0; c < 3; ++c) Dt[(size_t)c * ld + 3 * i + q] = R(d[3 * q + c]);
+        }
     }
 }
 
