@@ -491,39 +491,58 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
 // ---------------------------------------------------------------------------
 // Sums over runs of equal key in a chunk of kChunk values (one per thread,
 // keys ascending through the chunk, -1 for no value): each run's sum is added
-// to acc[NV key ..].  Within a wavefront by segmented suffix sums over the
-// lanes (after the steps with distance d, lane l holds the sum over
-// [l, l + 2d) of its run), written by the run's first lane; the part of a run
-// that continues from the previous wavefront goes to carry[] and is added by
-// thread 0, in wavefront order, in add_carries() after the next barrier.  The
-// order of every addition is fixed, so the sums do not depend on scheduling.
-// keys[] holds the chunk's keys (written before the barrier that precedes).
+// to acc[NV key ..].  Within a wavefront by segmented prefix sums over the lanes
+// with DPP moves (row shifts by 1, 2, 4, 8 inside rows of 16 lanes, then the
+// last lane of a row broadcast to the rows after it; a lane adds what it
+// receives when the sending lane has its key), so the run's last lane holds
+// the run's sum and adds it; the part of a run that continues into the next
+// wavefront goes to carry[] instead and is added by thread 0, in wavefront
+// order, in add_carries() after the next barrier.  The order of every addition
+// is fixed, so the sums do not depend on scheduling.  keys[] holds the chunk's
+// keys (written before the barrier that precedes).
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 256;              // threads of the chunked pair kernels = values per chunk
 constexpr int kChunkWaves = kChunk / 64;
+
+template <int CTRL, int RMASK>
+__device__ __forceinline__ int dpp_int(int old, int src) {
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, RMASK, 0xF, false);
+}
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_dbl(double src) {   // lanes without a source read 0
+    const long long b = __double_as_longlong(src);
+    const int lo = dpp_int<CTRL, RMASK>(0, (int)b), hi = dpp_int<CTRL, RMASK>(0, (int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int RMASK, int NV>
+__device__ __forceinline__ void seg_step(int key, double (&h)[NV]) {
+    const int kd = dpp_int<CTRL, RMASK>(-2, key);
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = dpp_dbl<CTRL, RMASK>(h[v]);
+    if (kd == key) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) h[v] += u[v];
+    }
+}
 
 template <int NV>
 __device__ __forceinline__ void run_sums(int key, double (&h)[NV], const int32_t* keys, double* acc, double* carry,
                                          int* carry_key) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int kd = __shfl_down(key, d);
-        double u[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = __shfl_down(h[v], d);
-        if (lane + d < 64 && kd == key) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) h[v] += u[v];
-        }
-    }
-    const int kprev = t > 0 ? keys[t - 1] : -2;
-    const bool cont = lane == 0 && wave > 0 && key >= 0 && kprev == key;
-    if (lane == 0 && wave > 0) carry_key[wave] = cont ? key : -1;
+    seg_step<0x111, 0xF>(key, h);   // row_shr:1
+    seg_step<0x112, 0xF>(key, h);   // row_shr:2
+    seg_step<0x114, 0xF>(key, h);   // row_shr:4
+    seg_step<0x118, 0xF>(key, h);   // row_shr:8
+    seg_step<0x142, 0xA>(key, h);   // row_bcast:15 to rows 1 and 3
+    seg_step<0x143, 0xC>(key, h);   // row_bcast:31 to rows 2 and 3
+    const int knext = t + 1 < kChunk ? keys[t + 1] : -2;
+    const bool cont = lane == 63 && wave + 1 < kChunkWaves && key >= 0 && knext == key;
+    if (lane == 63) carry_key[wave] = cont ? key : -1;
     if (cont) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) carry[NV * wave + v] = h[v];
-    } else if (key >= 0 && (lane == 0 || kprev != key)) {
+    } else if (key >= 0 && (lane == 63 || knext != key)) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[NV * key + v] += h[v];
     }
@@ -532,7 +551,7 @@ __device__ __forceinline__ void run_sums(int key, double (&h)[NV], const int32_t
 template <int NV>
 __device__ __forceinline__ void add_carries(double* acc, const double* carry, const int* carry_key) {
     if (threadIdx.x != 0) return;
-    for (int w = 1; w < kChunkWaves; ++w) {
+    for (int w = 0; w + 1 < kChunkWaves; ++w) {
         const int key = carry_key[w];
         if (key < 0) continue;
         for (int v = 0; v < NV; ++v) acc[NV * key + v] += carry[NV * w + v];
