@@ -1046,14 +1046,18 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
 
     __shared__ double carry[3 * kChunkWaves];
     __shared__ int carry_key[kChunkWaves];
-    // K1 site t's index list over the other side: the next entries are loaded
-    // before the chunk's pair is evaluated, and the terms of the pairs in this
-    // chunk are subtracted from g after the barrier
+    // K1 site's index list over the other side, walked by ws threads (entries
+    // part, part + ws, ...; two per site when n1 <= kChunk / 2): the next
+    // entries are loaded before the chunk's pair is evaluated, and the terms of
+    // the pairs in this chunk are subtracted from g after the barrier
+    const int ws = 2 * n1 <= kChunk ? 2 : 1;
+    const int site = t / ws, part = t % ws;
+    const bool walker = site < n1;
     constexpr int kAhead = 8;
     int ahead[kAhead];
     auto prefetch = [&](const int32_t* lst, int p, int pe) {
 #pragma unroll
-        for (int j = 0; j < kAhead; ++j) ahead[j] = p + j < pe ? lst[p + j] : 0x7fffffff;
+        for (int j = 0; j < kAhead; ++j) ahead[j] = p + j * ws < pe ? lst[p + j * ws] : 0x7fffffff;
     };
     auto consume = [&](const int32_t* lst, int& p, int pe, int e1, double* g) {
         bool more = true;
@@ -1065,11 +1069,11 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
                 g[0] -= L.H[3 * u + 0];
                 g[1] -= L.H[3 * u + 1];
                 g[2] -= L.H[3 * u + 2];
-                ++p;
+                p += ws;
             }
         }
         if (more) {
-            for (; p < pe && lst[p] < e1; ++p) {
+            for (; p < pe && lst[p] < e1; p += ws) {
                 const int u = lst[p] - (e1 - kChunk);
                 g[0] -= L.H[3 * u + 0];
                 g[1] -= L.H[3 * u + 1];
@@ -1078,13 +1082,13 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
         }
     };
 
-    double gb[3] = {0.0, 0.0, 0.0};   // K1 site t as the second site of K1 x K1 pairs
-    double gi[3] = {0.0, 0.0, 0.0};   // K1 site t against the shell
+    double gb[3] = {0.0, 0.0, 0.0};   // the walked K1 site as the second site of K1 x K1 pairs
+    double gi[3] = {0.0, 0.0, 0.0};   // the walked K1 site against the shell
     // K1 x K1 pairs a < b: h = gradient of the pair's term with respect to r_a
     {
         const int P = seg_a[n1];
-        int p = t < n1 ? seg_b[t] : 0;
-        const int pe = t < n1 ? seg_b[t + 1] : 0;
+        int p = walker ? seg_b[site] + part : 0;
+        const int pe = walker ? seg_b[site + 1] : 0;
         int32_t ent_next = t < P ? la[t] : 0;   // list entries a chunk ahead
         for (int e0 = 0; e0 < P; e0 += kChunk) {
             prefetch(lb, p, pe);
@@ -1121,7 +1125,7 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
             L.H[3 * t + 2] = h[2];
             __syncthreads();
             run_sums<3>(key, h, L.key, L.gk, carry, carry_key);
-            if (t < n1) consume(lb, p, pe, e0 + kChunk, gb);
+            if (walker) consume(lb, p, pe, e0 + kChunk, gb);
             __syncthreads();
             add_carries<3>(L.gk, carry, carry_key);
         }
@@ -1130,8 +1134,8 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
     // term with respect to r_i); the shell site gains h, the K1 site loses it
     {
         const int P = seg_q[n2];
-        int p = t < n1 ? seg_i[t] : 0;
-        const int pe = t < n1 ? seg_i[t + 1] : 0;
+        int p = walker ? seg_i[site] + part : 0;
+        const int pe = walker ? seg_i[site + 1] : 0;
         int32_t ent_next = t < P ? lq[t] : 0;   // list entries a chunk ahead
         for (int e0 = 0; e0 < P; e0 += kChunk) {
             prefetch(li, p, pe);
@@ -1162,7 +1166,7 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
             L.H[3 * t + 2] = h[2];
             __syncthreads();
             run_sums<3>(key, h, L.key, L.gq, carry, carry_key);
-            if (t < n1) consume(li, p, pe, e0 + kChunk, gi);
+            if (walker) consume(li, p, pe, e0 + kChunk, gi);
             __syncthreads();
             add_carries<3>(L.gq, carry, carry_key);
         }
@@ -1171,8 +1175,14 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
 
     double* out = a.cf + (size_t)w * a.cf_slice + a.site_off[k] * 3;
     const double fconv = -1.0 / kBohr;  // force = -dE/dx, per Angstrom
-    if (t < n1) {
-        for (int c = 0; c < 3; ++c) out[3 * t + c] = fconv * ((L.gk[3 * t + c] + gb[c]) + gi[c]);
+    if (ws == 2) {   // the two walkers of a site are adjacent lanes
+        for (int c = 0; c < 3; ++c) {
+            gb[c] += __shfl_xor(gb[c], 1);
+            gi[c] += __shfl_xor(gi[c], 1);
+        }
+    }
+    if (walker && part == 0) {
+        for (int c = 0; c < 3; ++c) out[3 * site + c] = fconv * ((L.gk[3 * site + c] + gb[c]) + gi[c]);
     }
     for (int q = t; q < n2; q += kChunk)
         for (int c = 0; c < 3; ++c) out[3 * (n1 + q) + c] = fconv * L.gq[3 * q + c];
