@@ -15,6 +15,8 @@
 // plain FP64 path.  R = float is the mixed path: pair tensors, the matrix and
 // its factor in FP32 (MFMA f32), the forward solve refined in FP64 against the
 // matrix rebuilt from its FP32 pair coefficients, solutions and all sums in FP64.
+#include <type_traits>
+
 #include "lmbd_internal.h"
 
 namespace lmbd {
@@ -187,35 +189,47 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         // matrix, the others from zero; results (partial tiles for s > 0) go to
         // the panel buffer, tile u = t + s m.  A unit's result does not depend
         // on which wavefront computes it.
-        auto unit = [&](int u) {
-            const int t = u % m, s = u / m;
-            const bool two = pair && t > 0;
-            // the matrix values this unit adds to are read first and added after
-            // the products, so their latency hides behind the chunk loop
-            typename M::acc acc0, acc1;
-            R init0[4], init1[4];
+        // NT row tiles t0, t0 + 1, .. (k-split part s) as one unit: the panel
+        // rows (b) loaded once per chunk serve all its tiles
+        auto unit_tiles = [&](int t0, int s, auto ntc) {
+            constexpr int NT = decltype(ntc)::value;
+            typename M::acc acc0[NT], acc1[NT];   // start from the matrix values
+            bool tv[NT], two[NT];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li, col1 = c0 + NB + li;
-                init0[q] = (s == 0 && row < Nr && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
-                init1[q] = (two && row < Nr && col1 < N && (t > 1 || row >= col1)) ? A[(size_t)row * ld + col1] : R(0);
-                acc0[q] = R(0);
-                acc1[q] = R(0);
+            for (int x = 0; x < NT; ++x) {
+                const int t = t0 + x;
+                tv[x] = t < m;
+                two[x] = pair && t > 0 && tv[x];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li, col1 = c0 + NB + li;
+                    acc0[x][q] = (tv[x] && s == 0 && row < Nr && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
+                    acc1[x][q] = (two[x] && row < Nr && col1 < N && (t > 1 || row >= col1)) ? A[(size_t)row * ld + col1] : R(0);
+                }
             }
+            const bool anytwo = pair && t0 + NT - 1 > 0;   // uniform
             if (nk > 0) {
-                const int arow = c0 + NB * t + li, brow0 = c0 + li, brow1 = c0 + NB + li;
-                const bool aok = arow < Nr, bok0 = brow0 < N, bok1 = two && brow1 < N;
-                const R* pa = A + (size_t)(aok ? arow : 0) * ld + 4 * lk;
+                const int brow0 = c0 + li, brow1 = c0 + NB + li;
+                const bool bok0 = brow0 < N, bok1 = anytwo && brow1 < N;
+                const R* pa[NT];
+                bool aok[NT];
+#pragma unroll
+                for (int x = 0; x < NT; ++x) {
+                    const int arow = c0 + NB * (t0 + x) + li;
+                    aok[x] = tv[x] && arow < Nr;
+                    pa[x] = A + (size_t)(aok[x] ? arow : 0) * ld + 4 * lk;
+                }
                 const R* pb0 = A + (size_t)(bok0 ? brow0 : 0) * ld + 4 * lk;
                 const R* pb1 = A + (size_t)(bok1 ? brow1 : 0) * ld + 4 * lk;
                 auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < p) ? load4(base + NB * c) : zero; };
                 // ring of kRing chunks: each chunk's registers are refilled with the
                 // chunk kRing ahead right after use
                 const int c1 = k_lo + s;
-                V4 ra[kRing], rb[kRing], rc[kRing];
+                V4 ra[kRing][NT], rb[kRing], rc[kRing];
 #pragma unroll
                 for (int j = 0; j < kRing; ++j) {
-                    ra[j] = ld4(pa, aok, c1 + j * S);
+#pragma unroll
+                    for (int x = 0; x < NT; ++x) ra[j][x] = ld4(pa[x], aok[x], c1 + j * S);
                     rb[j] = ld4(pb0, bok0, c1 + j * S);
                     rc[j] = ld4(pb1, bok1, c1 + j * S);
                 }
@@ -224,33 +238,47 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                     for (int j = 0; j < kRing; ++j) {
                         if (ch + j * S < p) {   // uniform
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) acc0 = M::mma(-ra[j][e], rb[j][e], acc0);
-                            if (two) {
+                            for (int x = 0; x < NT; ++x) {
 #pragma unroll
-                                for (int e = 0; e < 4; ++e) acc1 = M::mma(-ra[j][e], rc[j][e], acc1);
+                                for (int e = 0; e < 4; ++e) acc0[x] = M::mma(-ra[j][x][e], rb[j][e], acc0[x]);
+                            }
+                            if (anytwo) {
+#pragma unroll
+                                for (int x = 0; x < NT; ++x) {
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e) acc1[x] = M::mma(-ra[j][x][e], rc[j][e], acc1[x]);
+                                }
                             }
                         }
                         const int cn = ch + (j + kRing) * S;
-                        ra[j] = ld4(pa, aok, cn);
+#pragma unroll
+                        for (int x = 0; x < NT; ++x) ra[j][x] = ld4(pa[x], aok[x], cn);
                         rb[j] = ld4(pb0, bok0, cn);
                         rc[j] = ld4(pb1, bok1, cn);
                     }
                 }
             }
-            R* tl = pan + (size_t)u * NB * kSlotLd;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) tl[M::acc_row(lk, q) * kSlotLd + li] = init0[q] + acc0[q];
-            if (two) {
+            for (int x = 0; x < NT; ++x) {
+                if (!tv[x]) continue;
+                const int t = t0 + x;
+                R* tl = pan + (size_t)(t + s * m) * NB * kSlotLd;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + NB + li;
-                    if (row < Nr && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] = init1[q] + acc1[q];
+                for (int q = 0; q < 4; ++q) tl[M::acc_row(lk, q) * kSlotLd + li] = acc0[x][q];
+                if (two[x]) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + NB + li;
+                        if (row < Nr && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] = acc1[x][q];
+                    }
                 }
             }
         };
+        auto unit = [&](int u) { unit_tiles(u % m, u / m, std::integral_constant<int, 1>()); };
         // (2) diagonal block: the diagonal wave, lane l holds row l (in the early
         // case it reads back the tile it has just written itself)
         auto diag = [&]() {
+          {
             const int l = lane;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             R row[NB];
@@ -281,21 +309,41 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            // L to the matrix, and to the diagonal tile of the panel buffer (its rows
+            // < jb are not needed any more) with 1/L_ii in the padding column
+            R* Lt = pan;
             if (l < jb) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
-                    if (c <= l) A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
+                    if (c <= l) {
+                        A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
+                        Lt[l * kSlotLd + c] = row[c];
+                    }
             }
+            if (l == 0) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) Lt[c * kSlotLd + NB] = invv[c];
+            }
+          }
+          {
             // Z = L_pp^{-1}, lane j < 16 holds column j (forward substitution with
-            // the rows of L broadcast from their lanes); Z[q][j] (q > j) is stored
-            // at (c0 + j, c0 + q), and all of Z row-major in LDS
+            // the rows of L read back as LDS broadcasts); Z[q][j] (q > j) is stored
+            // at (c0 + j, c0 + q), and all of Z row-major in LDS.  (l is made
+            // opaque so that the per-lane constants are not hoisted out of the
+            // panel loop, where they would only take registers.)
+            int l = lane;
+            asm volatile("" : "+v"(l));
+            const R* Lt = pan;
             R z[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 R v = (q == l) ? R(1) : R(0);
+                if (q < jb) {
 #pragma unroll
-                for (int r = 0; r < q; ++r) v -= bcast(row[r], q) * z[r];
-                z[q] = v * invv[q];
+                    for (int r = 0; r < q; ++r) v -= Lt[q * kSlotLd + r] * z[r];
+                    v *= Lt[q * kSlotLd + NB];
+                }
+                z[q] = v;
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (l < NB) {
@@ -307,6 +355,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 for (int q = 0; q < NB; ++q)
                     if (q > l && q < jb) A[(size_t)(c0 + l) * ld + c0 + q] = z[q];
             }
+          }
         };
         int* ctr = counter + (p & 1);
         if (early && wave == dw) {
@@ -317,9 +366,13 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             int g = 0;
             if (lane == 0) g = atomicAdd(ctr, 1);
             g = __shfl(g, 0);
-            const int u = early ? g + 1 : g;
-            if (u >= U) break;
-            unit(u);
+            if (early) {   // tiles 1 + 2g and 2 + 2g
+                if (1 + 2 * g >= m) break;
+                unit_tiles(1 + 2 * g, 0, std::integral_constant<int, 2>());
+            } else {
+                if (g >= U) break;
+                unit(g);
+            }
         }
         paired_prev = pair;
         if (!early) {
