@@ -82,30 +82,37 @@ template <> struct MfmaW<float> {
 // operand reads the 4-vector k = 16 c + 4 g .. + 3 and feeds element e to k-step e,
 // the same permutation of k for both operands; 16 k per chunk, the next chunk in
 // flight.  Each wavefront takes a 16-row strip times up to four 16-column tiles.
-template <typename W, typename ST>
+template <int MR, int NVMAX, typename W, typename ST>
 __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __restrict__ A, int lda,
                                              const W* __restrict__ B, int ldb, ST st) {
     typedef MfmaW<W> Mf;
     typedef W V4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int mt = (M + 15) / 16;
+    const int mt = (M + 16 * MR - 1) / (16 * MR);   // items of MR 16-row strips
     const int nt = (N + 15) / 16;
-    const int ng = (nt + 3) / 4;
+    const int ng = (nt + NVMAX - 1) / NVMAX;
     const int nch = (K + 15) / 16;
     const V4 zero = {W(0), W(0), W(0), W(0)};
     auto kin = [&](int ch) { return ch < nch && 16 * ch + 4 * lk < K; };
-    // one 16-row strip times NV column tiles (NV = the tiles of the group inside N)
+    // MR 16-row strips times NV column tiles (NV = the tiles of the group inside N)
     auto item = [&](int m0, int tc0, auto nvc) {
         constexpr int NV = decltype(nvc)::value;
-        typename Mf::acc acc[NV];
+        typename Mf::acc acc[MR][NV];
 #pragma unroll
-        for (int c = 0; c < NV; ++c)
+        for (int x = 0; x < MR; ++x)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[c][q] = W(0);
-        const int am = m0 + li;
-        const bool aok = am < M;
-        const W* pa = A + (size_t)(aok ? am : 0) * lda + 4 * lk;
+            for (int c = 0; c < NV; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[x][c][q] = W(0);
+        const W* pa[MR];
+        bool aok[MR];
+#pragma unroll
+        for (int x = 0; x < MR; ++x) {
+            const int am = m0 + 16 * x + li;
+            aok[x] = am < M;
+            pa[x] = A + (size_t)(aok[x] ? am : 0) * lda + 4 * lk;
+        }
         const W* pb[NV];
         bool bok[NV];
         int bn[NV];
@@ -115,45 +122,52 @@ __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __res
             bok[c] = bn[c] < N;
             pb[c] = B + (size_t)(bok[c] ? bn[c] : 0) * ldb + 4 * lk;
         }
-        V4 a = (aok && kin(0)) ? *reinterpret_cast<const V4*>(pa) : zero;
-        V4 b[NV];
+        V4 a[MR], b[NV];
+#pragma unroll
+        for (int x = 0; x < MR; ++x) a[x] = (aok[x] && kin(0)) ? *reinterpret_cast<const V4*>(pa[x]) : zero;
 #pragma unroll
         for (int c = 0; c < NV; ++c) b[c] = (bok[c] && kin(0)) ? *reinterpret_cast<const V4*>(pb[c]) : zero;
         for (int ch = 0; ch < nch; ++ch) {
             const bool kn = kin(ch + 1);
-            const V4 na = (aok && kn) ? *reinterpret_cast<const V4*>(pa + 16 * (ch + 1)) : zero;
-            V4 nb[NV];
+            V4 na[MR], nb[NV];
+#pragma unroll
+            for (int x = 0; x < MR; ++x)
+                na[x] = (aok[x] && kn) ? *reinterpret_cast<const V4*>(pa[x] + 16 * (ch + 1)) : zero;
 #pragma unroll
             for (int c = 0; c < NV; ++c)
                 nb[c] = (bok[c] && kn) ? *reinterpret_cast<const V4*>(pb[c] + 16 * (ch + 1)) : zero;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
-                for (int c = 0; c < NV; ++c) acc[c] = Mf::mma(a[e], b[c][e], acc[c]);
-            a = na;
+                for (int x = 0; x < MR; ++x)
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) acc[x][c] = Mf::mma(a[x][e], b[c][e], acc[x][c]);
+#pragma unroll
+            for (int x = 0; x < MR; ++x) a[x] = na[x];
 #pragma unroll
             for (int c = 0; c < NV; ++c) b[c] = nb[c];
         }
 #pragma unroll
-        for (int c = 0; c < NV; ++c) {
-            if (bok[c]) {
+        for (int x = 0; x < MR; ++x)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int m = m0 + Mf::acc_row(lk, q);
-                    if (m < M) st(m, bn[c], acc[c][q]);
+            for (int c = 0; c < NV; ++c) {
+                if (bok[c]) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int m = m0 + 16 * x + Mf::acc_row(lk, q);
+                        if (m < M) st(m, bn[c], acc[x][c][q]);
+                    }
                 }
             }
-        }
     };
     for (int t = wave; t < mt * ng; t += nwave) {
-        const int m0 = (t / ng) * 16;
-        const int tc0 = (t % ng) * 4;
-        switch (min(4, nt - tc0)) {   // uniform over the wavefront
-            case 1: item(m0, tc0, std::integral_constant<int, 1>()); break;
-            case 2: item(m0, tc0, std::integral_constant<int, 2>()); break;
-            case 3: item(m0, tc0, std::integral_constant<int, 3>()); break;
-            default: item(m0, tc0, std::integral_constant<int, 4>()); break;
-        }
+        const int m0 = (t / ng) * 16 * MR;
+        const int tc0 = (t % ng) * NVMAX;
+        const int nv = min(NVMAX, nt - tc0);   // uniform over the wavefront
+        if (nv >= 4) item(m0, tc0, std::integral_constant<int, NVMAX >= 4 ? 4 : 1>());
+        else if (nv == 3) item(m0, tc0, std::integral_constant<int, NVMAX >= 3 ? 3 : 1>());
+        else if (nv == 2) item(m0, tc0, std::integral_constant<int, NVMAX >= 2 ? 2 : 1>());
+        else item(m0, tc0, std::integral_constant<int, 1>());
     }
     __syncthreads();
 }
@@ -273,7 +287,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     // --- u_{m+1} = D (T V), V = D u_{m+1}  (T symmetric, so it is its own K-major operand)
     for (int m = 1; m < a.mmax; ++m) {
         W* Un = Uat(m + 1);
-        mfma_gemm_nt<W>(N3, ncol, N3, T, N3p, V, N3p, [&](int r, int col, W v) {
+        mfma_gemm_nt<1, 4, W>(N3, ncol, N3, T, N3p, V, N3p, [&](int r, int col, W v) {
             Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v;
         });
         for (int e = tid; e < N3 * ncol; e += blockDim.x) {
@@ -370,7 +384,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
     // --- Tbar (overwrites T)
-    mfma_gemm_nt<W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+    mfma_gemm_nt<2, 2, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
