@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
     // --- Tbar (overwrites T)
-    mfma_gemm_nt<2, 2, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+    mfma_gemm_nt<2, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
