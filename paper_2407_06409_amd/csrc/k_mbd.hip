@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     // --- u_{m+1} = D (T V), V = D u_{m+1}  (T symmetric, so it is its own K-major operand)
     for (int m = 1; m < a.mmax; ++m) {
         W* Un = Uat(m + 1);
-        mfma_gemm_nt<2, 3, W>(N3, ncol, N3, T, N3p, V, N3p, [&](int r, int col, W v) {
+        mfma_gemm_nt<3, 3, W>(N3, ncol, N3, T, N3p, V, N3p, [&](int r, int col, W v) {
             Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v;
         });
         for (int e = tid; e < N3 * ncol; e += blockDim.x) {
@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
     // --- Tbar (overwrites T)
-    mfma_gemm_nt<2, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+    mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
