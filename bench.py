@@ -90,13 +90,14 @@ def stored_traffic():
 
 def mbd_flops(nK, nq, n_max, forces):
     """Algorithmic FLOPs of the MBD stage: Krylov products (N3^2 x 3 n_q each) and,
-    with forces, the Tbar product (N3^2 x 3 n_q n_max)."""
+    with forces, the Tbar product (N3^2 x 3 n_q n_max), of which only the lower
+    triangle N3 (N3 + 1) / 2 is needed since Tbar is symmetric."""
     N3 = 3.0 * nK.astype(np.float64)
     ncol = 3 * nq
     prods = (n_max - 2) if forces else (math.ceil(n_max / 2) - 1)
     f = np.sum(prods * 2.0 * N3 ** 2 * ncol)
     if forces:
-        f += np.sum(2.0 * N3 ** 2 * ncol * n_max)
+        f += np.sum(N3 * (N3 + 1.0) * ncol * n_max)
     return float(f)
 
 

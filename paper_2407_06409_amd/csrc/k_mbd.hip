@@ -81,10 +81,13 @@ template <> struct MfmaW<float> {
 // (row-major, lda/ldb multiples of 4, K a multiple of 4).  Lane (i, g) of an MFMA
 // operand reads the 4-vector k = 16 c + 4 g .. + 3 and feeds element e to k-step e,
 // the same permutation of k for both operands; 16 k per chunk, the next chunk in
-// flight.  Each wavefront takes a 16-row strip times up to four 16-column tiles.
+// flight.  Each wavefront takes MR 16-row strips times up to NVMAX 16-column tiles.
+// With `lower` set, only items holding entries on or below the diagonal are
+// computed (for a product known to be symmetric; the rest of the output is left
+// as it was).
 template <int MR, int NVMAX, typename W, typename ST>
 __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __restrict__ A, int lda,
-                                             const W* __restrict__ B, int ldb, ST st) {
+                                             const W* __restrict__ B, int ldb, bool lower, ST st) {
     typedef MfmaW<W> Mf;
     typedef W V4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -163,6 +166,7 @@ __device__ __forceinline__ void mfma_gemm_nt(int M, int N, int K, const W* __res
     for (int t = wave; t < mt * ng; t += nwave) {
         const int m0 = (t / ng) * 16 * MR;
         const int tc0 = (t % ng) * NVMAX;
+        if (lower && 16 * tc0 > m0 + 16 * MR - 1) continue;   // wholly above the diagonal
         const int nv = min(NVMAX, nt - tc0);   // uniform over the wavefront
         if (nv >= 4) item(m0, tc0, std::integral_constant<int, NVMAX >= 4 ? 4 : 1>());
         else if (nv == 3) item(m0, tc0, std::integral_constant<int, NVMAX >= 3 ? 3 : 1>());
@@ -249,9 +253,13 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
 
-    // --- T_LR (row-major, symmetric, zero diagonal blocks)
-    for (int p = tid; p < nK * nK; p += blockDim.x) {
-        const int i = p / nK, j = p % nK;
+    // --- T_LR (row-major, symmetric, zero diagonal blocks).  Each unordered pair
+    // j <= i once: its 3x3 block is symmetric and the same for (i, j) and (j, i).
+    for (int p = tid; p < nK * (nK + 1) / 2; p += blockDim.x) {
+        int i = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= p) ++i;
+        while (i * (i + 1) / 2 > p) --i;
+        const int j = p - i * (i + 1) / 2;
         double blk[9] = {};
         if (i != j) {
             const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
@@ -267,7 +275,10 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
             }
         }
         for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) T[(size_t)(3 * i + q) * N3p + 3 * j + c] = W(blk[3 * q + c]);
+            for (int c = 0; c < 3; ++c) {
+                T[(size_t)(3 * i + q) * N3p + 3 * j + c] = W(blk[3 * q + c]);
+                T[(size_t)(3 * j + q) * N3p + 3 * i + c] = W(blk[3 * q + c]);
+            }
     }
     for (int e = tid; e < N3 * (N3p - N3); e += blockDim.x) T[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
     for (int e = tid; e < ncol * (N3p - N3); e += blockDim.x) V[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
@@ -287,7 +298,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     // --- u_{m+1} = D (T V), V = D u_{m+1}  (T symmetric, so it is its own K-major operand)
     for (int m = 1; m < a.mmax; ++m) {
         W* Un = Uat(m + 1);
-        mfma_gemm_nt<3, 3, W>(N3, ncol, N3, T, N3p, V, N3p, [&](int r, int col, W v) {
+        mfma_gemm_nt<3, 3, W>(N3, ncol, N3, T, N3p, V, N3p, false, [&](int r, int col, W v) {
             Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v;
         });
         for (int e = tid; e < N3 * ncol; e += blockDim.x) {
@@ -383,8 +394,10 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
         Qm[(size_t)r * KKp + kk] = W(0);
     }
     __syncthreads();
-    // --- Tbar (overwrites T)
-    mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+    // --- Tbar (overwrites T).  Tbar is symmetric (the terms a, b and b, a of
+    // Gbar are transposes of each other), so only blocks on or below the
+    // diagonal are formed and read.
+    mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
@@ -401,11 +414,13 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
             const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
             const LrPair<W> lp = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
                                             W(a.r_buf));
+            // C = Tbar_ij + Tbar_ji = Tbar_IJ + Tbar_IJ^T with I > J
+            const int I = max(i, j), J = min(i, j);
             double C[9];
             for (int q = 0; q < 3; ++q)
                 for (int c = 0; c < 3; ++c)
-                    C[3 * q + c] = double(T[(size_t)(3 * i + q) * N3p + 3 * j + c]) +
-                                   double(T[(size_t)(3 * i + c) * N3p + 3 * j + q]);
+                    C[3 * q + c] = double(T[(size_t)(3 * I + q) * N3p + 3 * J + c]) +
+                                   double(T[(size_t)(3 * I + c) * N3p + 3 * J + q]);
             double gp[3];
             radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
             g[0] += gp[0];
