@@ -106,6 +106,17 @@ hipError_t launch_gather_forces(hipStream_t st, int n, int nslices, int64_t slic
     return hipGetLastError();
 }
 
+__global__ void k_fill(int n, double v, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+hipError_t launch_fill(hipStream_t st, int n, double v, double* out) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, v, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_central_static(hipStream_t st, int n, int nw, const double* alpha_loc,
                                  const int64_t* aloc_off, double* out) {
     hipLaunchKernelGGL(k_central_static, dim3((n + 255) / 256), dim3(256), 0, st, n, nw, alpha_loc,

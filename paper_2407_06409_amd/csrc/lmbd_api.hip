@@ -741,7 +741,6 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ctx->arena_used = 0;
     HIP_TRY(layout_pre(ctx, pd, [&](DBuf& b, size_t n) { return ensure(ctx, b, n); }));
     std::vector<int32_t> atom_struct(N);
-    std::vector<double> ones;
     for (int s = 0, off = 0; s < n_structs; ++s) {
         const lmbd_structure& S = structs[s];
         const int n = (int)S.n_atoms;
@@ -751,10 +750,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         if (S.e_weight) {
             HIP_TRY(hipMemcpyAsync(as<double>(ctx->in_w) + off, S.e_weight, sizeof(double) * n, h2d, stream));
         } else {
-            ones.assign(n, 1.0);
-            HIP_TRY(hipMemcpyAsync(as<double>(ctx->in_w) + off, ones.data(), sizeof(double) * n,
-                                   hipMemcpyHostToDevice, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
+            HIP_TRY(launch_fill(stream, n, 1.0, as<double>(ctx->in_w) + off));   // no weights: 1 per atom
         }
         for (int i = 0; i < n; ++i) atom_struct[off + i] = s;
         off += n;

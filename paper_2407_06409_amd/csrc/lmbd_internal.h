@@ -253,6 +253,8 @@ hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,
                                  const double* ca, double* abar_cen);
+// out[0 .. n) = v
+hipError_t launch_fill(hipStream_t st, int n, double v, double* out);
 hipError_t launch_gather_forces(hipStream_t st, int n, int nslices, int64_t slice_stride,
                                 const Counts* counts, const int64_t* site_off, const Site* sites,
                                 const int32_t* rev, double* cf, double* forces);
