@@ -204,7 +204,7 @@ __device__ inline LrPair<P> lr_pair(P r, P S, P damp_d, P rcut, P rb) {
 template <typename W>
 __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     extern __shared__ double lds[];
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int tid = threadIdx.x;
     const Counts cnt = a.counts[k];
     const int nK = cnt.nK, n1 = cnt.n1, nall = cnt.n_all;

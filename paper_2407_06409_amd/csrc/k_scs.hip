@@ -752,7 +752,7 @@ template <typename R>
 __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     constexpr bool mixed = sizeof(R) == 4;
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     const int t = threadIdx.x;
     const Counts cnt = a.counts[k];
@@ -809,7 +809,7 @@ template <typename R>
 __global__ void __launch_bounds__(kChunk) k_scs_assemble(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
     constexpr bool mixed = sizeof(R) == 4;
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     const int t = threadIdx.x;
     const Counts cnt = a.counts[k];
@@ -908,7 +908,7 @@ __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     __shared__ R Zs[NB * kSlotLd];
     __shared__ int counter[2];
     R* pan = reinterpret_cast<R*>(lds);
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     const int N = 3 * a.counts[k].n1;
     const int ld = a.fac_ld[k];
@@ -947,7 +947,7 @@ enum { kSolveD = 0, kSolveFirst = 1, kSolveCorr = 2, kSolveLambda = 3 };
 template <typename R>
 __global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mode) {
     extern __shared__ double lds[];
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     const int n1 = a.counts[k].n1;
     const int N = 3 * n1;
@@ -996,7 +996,7 @@ size_t scs_solve_lds_bytes(int n1max, bool mixed) {
 __global__ void __launch_bounds__(256) k_scs_residual(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
     constexpr int kRes = 2;
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     const int n1 = a.counts[k].n1;
     const int N = 3 * n1;
@@ -1068,7 +1068,7 @@ size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)
 template <typename R>
 __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     const int t = threadIdx.x;
     const Counts cnt = a.counts[k];
@@ -1317,7 +1317,7 @@ __device__ inline int bits_below(const uint32_t* row, int x) {
 
 __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
-    const int k = blockIdx.x;
+    const int k = a.order[blockIdx.x];
     const int t = threadIdx.x, nt = blockDim.x;
     const Counts cnt = a.counts[k];
     const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1;

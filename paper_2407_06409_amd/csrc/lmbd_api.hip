@@ -43,6 +43,7 @@ struct Plan {
     std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off, coef_off;
     int64_t pl_len = 0;
     std::vector<int32_t> hash_cap, fac_ld;
+    std::vector<int32_t> order;   // dispatch order of the per-atom workgroups: largest neighbourhoods first
 };
 
 }  // namespace
@@ -58,7 +59,7 @@ struct lmbd_context {
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
     DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam;
-    DBuf e_out, f_out, a_out;
+    DBuf e_out, f_out, a_out, order;
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
     char* arena = nullptr;
@@ -75,7 +76,8 @@ struct lmbd_context {
         &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
-        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
+        &c->order
 
 namespace {
 
@@ -304,6 +306,14 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.work_len = wo;
     P.pl_len = po;
     P.coef_len = co;
+    // the work of an atom's workgroups grows with its neighbourhood: taking the
+    // largest first leaves the shortest ones for the end of each launch
+    P.order.resize(n);
+    for (int64_t k = 0; k < n; ++k) P.order[k] = (int32_t)k;
+    std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t x, int32_t y) {
+        if (cnt[x].n1 != cnt[y].n1) return cnt[x].n1 > cnt[y].n1;
+        return cnt[x].nK > cnt[y].nK;
+    });
 }
 
 template <typename T>
@@ -354,7 +364,8 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
         {&c->alpha_loc, (size_t)P.aloc_len * D}, {&c->abar_loc, (size_t)P.aloc_len * D},
         {&c->abar_cen, N * nw * D}, {&c->work, (size_t)P.work_len * wsz}, {&c->e_out, N * D},
         {&c->a_out, N * D}, {&c->pl_i, (size_t)P.pl_len * I}, {&c->pl_q, (size_t)P.pl_len * I},
-        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef_off, N * L8}, {&c->coef, (size_t)P.coef_len * sizeof(float)}};
+        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef_off, N * L8}, {&c->coef, (size_t)P.coef_len * sizeof(float)},
+        {&c->order, N * I}};
     for (const auto& e : L) {
         const hipError_t r = get(*e.first, e.second);
         if (r != hipSuccess) return r;
@@ -846,6 +857,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if ((st = upload(ctx, ctx->x_off, xo, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->aloc_off, ao, stream)) != LMBD_OK) return st;
     if ((st = upload(ctx, ctx->work_off, wo, stream)) != LMBD_OK) return st;
+    if ((st = upload(ctx, ctx->order, P.order, stream)) != LMBD_OK) return st;
     const int64_t TS = P.total_sites;
 
     // --- neighbour lists and the reverse-slot map
@@ -861,6 +873,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     sa.n = N;
     sa.nw = nw;
     sa.counts = as<Counts>(ctx->counts);
+    sa.order = as<int32_t>(ctx->order);
     sa.site_off = as<int64_t>(ctx->site_off);
     sa.sites = as<Site>(ctx->sites);
     sa.abar = as<double>(ctx->abar);
@@ -913,6 +926,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.ncol = ncol;
     ma.mmax = forces ? std::max(1, n_max - 1) : std::max(1, (n_max + 1) / 2);
     ma.counts = sa.counts;
+    ma.order = sa.order;
     ma.site_off = sa.site_off;
     ma.sites = sa.sites;
     ma.alpha_loc = sa.alpha_loc;

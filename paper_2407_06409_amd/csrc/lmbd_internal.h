@@ -155,6 +155,7 @@ struct ScsArgs {
     int n, nw;
     int n_refine;            // refinement steps of the FP32 solve (mixed precision)
     const Counts* counts;
+    const int32_t* order;    // per-atom launches: workgroup x takes atom order[x] (largest neighbourhoods first)
     const int64_t* site_off;
     const Site* sites;
     const double* abar;      // [n][nw]
@@ -202,6 +203,7 @@ struct ScsArgs {
 struct MbdArgs {
     int n, nw, nq, n_max, ncol, mmax;
     const Counts* counts;
+    const int32_t* order;      // workgroup x takes atom order[x] (largest neighbourhoods first)
     const int64_t* site_off;
     const Site* sites;
     const double* alpha_loc;   // per atom n1 * nw
