@@ -18,6 +18,7 @@
 // then contracted pair by pair with dT_LR/dr and dT_LR/dS~, and pushed
 // through the blend (local part to this atom's SCS, central part scattered to
 // the neighbours' own SCS through a per-site contribution buffer).
+#include <algorithm>
 #include <type_traits>
 
 #include "lmbd_internal.h"
@@ -27,7 +28,8 @@ namespace lmbd {
 
 __host__ __device__ inline size_t al4(size_t x) { return (x + 3) / 4 * 4; }
 
-// LDS layout
+// LDS layout.  The pair sums g of the force stage take the place of sqrt(alpha~),
+// whose last use (the operands of Tbar) precedes them.
 struct MbdLds {
     double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu;
 };
@@ -37,13 +39,13 @@ __device__ inline MbdLds mbd_lds(double* b, int nk, int nw, int nq, int n_max) {
     L.py = L.px + nk;
     L.pz = L.py + nk;
     L.sa = L.pz + nk;
-    L.sqa = L.sa + (size_t)nk * nw;
-    L.Rt = L.sqa + (size_t)nk * nq;
+    L.sqa = L.sa + (size_t)nk * nw;   // [nk][nq]
+    L.g = L.sqa;                      // [4 parts][nk][3], nq >= 12 (force stage only)
+    L.Rt = L.sqa + (size_t)nk * max(nq, 12);
     L.fs = L.Rt + nk;
     L.dfs = L.fs + nk;
     L.ab = L.dfs + nk;
-    L.g = L.ab + (size_t)nk * nw;     // [4 parts][nk][3]
-    L.rb = L.g + 12 * (size_t)nk;     // [4 parts][nk]
+    L.rb = L.ab + (size_t)nk * nw;    // [4 parts][nk]
     L.fg = L.rb + 4 * (size_t)nk;     // [nk][3]
     L.mu = L.fg + 3 * (size_t)nk;
     return L;
@@ -51,7 +53,7 @@ __device__ inline MbdLds mbd_lds(double* b, int nk, int nw, int nq, int n_max) {
 
 size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max) {
     const size_t nk = nkmax;
-    return sizeof(double) * (3 * nk + nk * nw + nk * nq + 3 * nk + nk * nw + 12 * nk + 4 * nk +
+    return sizeof(double) * (3 * nk + nk * nw + nk * (size_t)std::max(nq, 12) + 3 * nk + nk * nw + 4 * nk +
                              3 * nk + (size_t)(n_max + 1) * nq);
 }
 

@@ -64,6 +64,13 @@ struct lmbd_context {
     // fixed order (nothing is allocated while it is set)
     char* arena = nullptr;
     size_t arena_size = 0, arena_used = 0;
+    // pinned host staging of the small host <-> device copies of a call (plan
+    // tables, counts, flags), allocated once with the context; a call whose
+    // copies do not fit uses pageable memory instead
+    char* pin = nullptr;
+    size_t pin_cap = 0, pin_used = 0;
+    bool pin_pending = false;       // copies from the staging area may still be queued
+    int lds_limit = 0;              // LDS bytes per workgroup of the device
     bool profiling = false;
     hipEvent_t ev[2 * LMBD_N_STAGES] = {};
     bool ev_used[LMBD_N_STAGES] = {};
@@ -316,11 +323,42 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     });
 }
 
+// A slice of the pinned staging area (nullptr when it has no room left).
+void* pin_take(lmbd_context* ctx, size_t bytes) {
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (!ctx->pin || ctx->pin_used + need > ctx->pin_cap) return nullptr;
+    void* p = ctx->pin + ctx->pin_used;
+    ctx->pin_used += need;
+    ctx->pin_pending = true;
+    return p;
+}
+
+// Host array -> device, asynchronously from the pinned staging area when it has
+// room (the host array may then be reused at once), else from pageable memory.
+hipError_t copy_h2d(lmbd_context* ctx, void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (void* p = pin_take(ctx, bytes)) {
+        std::memcpy(p, src, bytes);
+        return hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, st);
+    }
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+}
+
 template <typename T>
 lmbd_status upload(lmbd_context* ctx, DBuf& b, const std::vector<T>& v, hipStream_t st) {
     if (sizeof(T) * v.size() > b.cap) return fail(ctx, LMBD_E_DEVICE, "workspace layout mismatch");
-    HIP_TRY(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(copy_h2d(ctx, b.p, v.data(), sizeof(T) * v.size(), st));
     return LMBD_OK;
+}
+
+// Device -> host array through the staging area when it has room; the stream
+// is synchronised before returning either way.
+hipError_t copy_d2h_sync(lmbd_context* ctx, void* dst, const void* src, size_t bytes, hipStream_t st) {
+    void* p = pin_take(ctx, bytes);
+    hipError_t e = hipMemcpyAsync(p ? p : dst, src, bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && p) std::memcpy(dst, p, bytes);
+    return e;
 }
 
 // Sizes that fix the buffers needed before the neighbour counts are known.
@@ -426,6 +464,17 @@ lmbd_status lmbd_create(int32_t device, lmbd_context** out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LMBD_E_INVALID_ARG;
     lmbd_context* ctx = new lmbd_context();
     ctx->device = device;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(device) == hipSuccess) {
+        (void)hipDeviceGetAttribute(&ctx->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+        constexpr size_t kPinBytes = 4u << 20;   // the plan tables of ~30k atoms
+        if (hipHostMalloc(reinterpret_cast<void**>(&ctx->pin), kPinBytes, hipHostMallocDefault) == hipSuccess)
+            ctx->pin_cap = kPinBytes;
+        else
+            ctx->pin = nullptr;
+    }
+    (void)hipSetDevice(prev);
     *out = ctx;
     return LMBD_OK;
 }
@@ -440,6 +489,7 @@ void lmbd_destroy(lmbd_context* ctx) {
         if (e) (void)hipEventDestroy(e);
     DBuf* all[] = {ALL_BUFFERS(ctx)};
     for (DBuf* b : all) release(*b);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
     (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -694,6 +744,11 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     const size_t wsz = mixed ? sizeof(float) : sizeof(double);  // matrix and workspace element size
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (ctx->pin_pending) {   // a call that ended early may have left copies from the staging area queued
+        HIP_TRY(hipDeviceSynchronize());
+        ctx->pin_pending = false;
+    }
+    ctx->pin_used = 0;
     for (int i = 0; i < LMBD_N_STAGES; ++i) {
         ctx->ev_used[i] = false;
         ctx->stage_ms[i] = 0.0;
@@ -785,7 +840,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
 
     // --- per-atom tables and cell list
     int flags_init[4] = {0, INT_MAX, 0, 0};
-    HIP_TRY(hipMemcpyAsync(ctx->flags.p, flags_init, sizeof(flags_init), hipMemcpyHostToDevice, stream));
+    HIP_TRY(copy_h2d(ctx, ctx->flags.p, flags_init, sizeof(flags_init), stream));
     int* err = as<int>(ctx->flags);
     int* err_atom = err + 1;
     HIP_TRY(mark(0, 0));
@@ -812,9 +867,18 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(mark(0, 1));
     std::vector<Counts> cnt(N);
     int flags[4];
-    HIP_TRY(hipMemcpyAsync(cnt.data(), ctx->counts.p, sizeof(Counts) * N, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(flags, ctx->flags.p, sizeof(flags), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    {
+        // counts and flags in one staged copy when the staging area has room
+        Counts* pc = static_cast<Counts*>(pin_take(ctx, sizeof(Counts) * N));
+        int* pf = static_cast<int*>(pin_take(ctx, sizeof(flags)));
+        HIP_TRY(hipMemcpyAsync(pc ? (void*)pc : (void*)cnt.data(), ctx->counts.p, sizeof(Counts) * N,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(pf ? (void*)pf : (void*)flags, ctx->flags.p, sizeof(flags), hipMemcpyDeviceToHost,
+                               stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (pc) std::memcpy(cnt.data(), pc, sizeof(Counts) * N);
+        if (pf) std::memcpy(flags, pf, sizeof(flags));
+    }
     if (flags[0] & 1) return fail(ctx, LMBD_E_INVALID_ARG, "invalid species, volume ratio or position");
 
     // --- memory plan
@@ -824,8 +888,11 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
                         ", sites " + std::to_string(P.nallmax) + ")");
-    int lds_limit = 0;
-    HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    int lds_limit = ctx->lds_limit;
+    if (lds_limit <= 0) {
+        HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+        ctx->lds_limit = lds_limit;
+    }
     if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit ||
         scs_factor_lds_bytes(P.n1max, mixed) > (size_t)lds_limit || scs_assemble_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit ||
         pairlist_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit)
@@ -987,8 +1054,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
             HIP_TRY(hipMemcpyAsync(S.alpha_scs0, as<double>(ctx->a_out) + off, sizeof(double) * n, d2o, stream));
         off += n;
     }
-    HIP_TRY(hipMemcpyAsync(flags, ctx->flags.p, sizeof(flags), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(copy_d2h_sync(ctx, flags, ctx->flags.p, sizeof(flags), stream));
+    ctx->pin_pending = false;
     if (ctx->profiling)
         for (int i = 0; i < LMBD_N_STAGES; ++i)
             if (ctx->ev_used[i]) {
