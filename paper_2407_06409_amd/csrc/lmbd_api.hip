@@ -60,6 +60,7 @@ struct lmbd_context {
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
     DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam;
     DBuf e_out, f_out, a_out, order;
+    DBuf tabs;   // one buffer holding the per-atom plan tables (pl_off .. order are views into it)
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
     char* arena = nullptr;
@@ -84,7 +85,7 @@ struct lmbd_context {
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
         &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
-        &c->order
+        &c->order, &c->tabs
 
 namespace {
 
@@ -389,21 +390,48 @@ hipError_t layout_pre(lmbd_context* c, const PreDims& d, F&& get) {
     return hipSuccess;
 }
 
+// The per-atom plan tables, in this order, as slices of one buffer (one upload):
+// eight int64 tables, then three int32 tables, each on a 256-byte boundary.
+// Returns the bytes of the whole; with `set`, points the table buffers into
+// c->tabs (views: the memory belongs to c->tabs).
+size_t table_views(lmbd_context* c, int64_t n, bool set) {
+    DBuf* t64[] = {&c->pl_off, &c->site_off, &c->hash_off, &c->fac_off, &c->x_off, &c->aloc_off, &c->work_off,
+                   &c->coef_off};
+    DBuf* t32[] = {&c->hash_cap, &c->fac_ld, &c->order};
+    const size_t b64 = ((size_t)n * sizeof(int64_t) + 255) / 256 * 256;
+    const size_t b32 = ((size_t)n * sizeof(int32_t) + 255) / 256 * 256;
+    size_t off = 0;
+    for (DBuf* b : t64) {
+        if (set) {
+            release(*b);
+            b->p = static_cast<char*>(c->tabs.p) + off;
+            b->cap = b64;
+        }
+        off += b64;
+    }
+    for (DBuf* b : t32) {
+        if (set) {
+            release(*b);
+            b->p = static_cast<char*>(c->tabs.p) + off;
+            b->cap = b32;
+        }
+        off += b32;
+    }
+    return off;
+}
+
 template <class F>
 hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size_t wsz, F&& get) {
     const bool mixed = wsz == sizeof(float);
-    const size_t N = (size_t)P.n_atoms, D = sizeof(double), I = sizeof(int32_t), L8 = sizeof(int64_t);
+    const size_t N = (size_t)P.n_atoms, D = sizeof(double), I = sizeof(int32_t);
     const size_t TS = (size_t)P.total_sites;
     const std::pair<DBuf*, size_t> L[] = {
-        {&c->pl_off, N * L8}, {&c->site_off, N * L8}, {&c->hash_off, N * L8}, {&c->hash_cap, N * I},
-        {&c->fac_off, N * L8}, {&c->fac_ld, N * I}, {&c->x_off, N * L8}, {&c->aloc_off, N * L8},
-        {&c->work_off, N * L8}, {&c->sites, TS * sizeof(Site)}, {&c->table, (size_t)P.table_len * I},
+        {&c->tabs, table_views(c, P.n_atoms, false)}, {&c->sites, TS * sizeof(Site)}, {&c->table, (size_t)P.table_len * I},
         {&c->rev, TS * I}, {&c->fac, (size_t)P.fac_len * wsz}, {&c->xsol, (size_t)P.x_len * D},
         {&c->alpha_loc, (size_t)P.aloc_len * D}, {&c->abar_loc, (size_t)P.aloc_len * D},
         {&c->abar_cen, N * nw * D}, {&c->work, (size_t)P.work_len * wsz}, {&c->e_out, N * D},
         {&c->a_out, N * D}, {&c->pl_i, (size_t)P.pl_len * I}, {&c->pl_q, (size_t)P.pl_len * I},
-        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef_off, N * L8}, {&c->coef, (size_t)P.coef_len * sizeof(float)},
-        {&c->order, N * I}};
+        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef, (size_t)P.coef_len * sizeof(float)}};
     for (const auto& e : L) {
         const hipError_t r = get(*e.first, e.second);
         if (r != hipSuccess) return r;
@@ -906,25 +934,27 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if (ctx->arena && ctx->arena_used + post_bytes.total > ctx->arena_size)
         return fail(ctx, LMBD_E_OOM_ADMISSION, "footprint over the workspace size");
     HIP_TRY(layout_post(ctx, P, nw, forces, wsz, [&](DBuf& b, size_t n) { return ensure(ctx, b, n); }));
-    std::vector<int64_t> so(P.site_off.begin(), P.site_off.end() - 1);
-    std::vector<int64_t> ho(P.hash_off.begin(), P.hash_off.end() - 1);
-    std::vector<int64_t> fo(P.fac_off.begin(), P.fac_off.end() - 1);
-    std::vector<int64_t> xo(P.x_off.begin(), P.x_off.end() - 1);
-    std::vector<int64_t> ao(P.aloc_off.begin(), P.aloc_off.end() - 1);
-    std::vector<int64_t> wo(P.work_off.begin(), P.work_off.end() - 1);
-    std::vector<int64_t> plo(P.pl_off.begin(), P.pl_off.end() - 1);
-    std::vector<int64_t> coo(P.coef_off.begin(), P.coef_off.end() - 1);
-    if ((st = upload(ctx, ctx->pl_off, plo, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->coef_off, coo, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->site_off, so, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->hash_off, ho, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->hash_cap, P.hash_cap, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->fac_off, fo, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->fac_ld, P.fac_ld, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->x_off, xo, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->aloc_off, ao, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->work_off, wo, stream)) != LMBD_OK) return st;
-    if ((st = upload(ctx, ctx->order, P.order, stream)) != LMBD_OK) return st;
+    {
+        // all per-atom plan tables in one image, one copy
+        const size_t tb = table_views(ctx, N, true);
+        std::vector<char> img(tb);
+        size_t off = 0;
+        const size_t b64 = ((size_t)N * sizeof(int64_t) + 255) / 256 * 256;
+        const size_t b32 = ((size_t)N * sizeof(int32_t) + 255) / 256 * 256;
+        const std::vector<int64_t>* v64[] = {&P.pl_off, &P.site_off, &P.hash_off, &P.fac_off, &P.x_off, &P.aloc_off,
+                                             &P.work_off, &P.coef_off};
+        for (const std::vector<int64_t>* v : v64) {   // the first N entries (the last is the total)
+            std::memcpy(img.data() + off, v->data(), sizeof(int64_t) * (size_t)N);
+            off += b64;
+        }
+        const std::vector<int32_t>* v32[] = {&P.hash_cap, &P.fac_ld, &P.order};
+        for (const std::vector<int32_t>* v : v32) {
+            std::memcpy(img.data() + off, v->data(), sizeof(int32_t) * (size_t)N);
+            off += b32;
+        }
+        if (tb > ctx->tabs.cap) return fail(ctx, LMBD_E_DEVICE, "workspace layout mismatch");
+        HIP_TRY(copy_h2d(ctx, ctx->tabs.p, img.data(), tb, stream));
+    }
     const int64_t TS = P.total_sites;
 
     // --- neighbour lists and the reverse-slot map
