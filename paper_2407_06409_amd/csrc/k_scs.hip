@@ -798,19 +798,17 @@ __global__ void __launch_bounds__(kChunk) k_scs_dvec(ScsArgs a, int n1max, int n
     }
 }
 
-// Assembly of the lower triangle of B~ (into the factor slot), one workgroup
-// per (atom, frequency), pairs in triangle order in chunks of kChunk: the
+// Assembly of the lower triangle of B~ (into the factor slot) by the workgroup
+// of (atom, frequency) that then factorises it, pairs in triangle order in
+// chunks of kChunk: the
 // coupled pairs of a chunk (from the a-major list) are evaluated compactly,
 // one per thread, into LDS; then each pair of the chunk is written by its own
 // thread (rows of atom i in contiguous 3-element runs), zero blocks for
 // uncoupled pairs.  The mixed path also keeps the FP32 pair coefficients for
 // the refinement residual.
 template <typename R>
-__global__ void __launch_bounds__(kChunk) k_scs_assemble(ScsArgs a, int n1max) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void assemble_matrix(const ScsArgs& a, int k, int w, int n1max, double* lds) {
     constexpr bool mixed = sizeof(R) == 4;
-    const int k = a.order[blockIdx.x];
-    const int w = blockIdx.y;
     const int t = threadIdx.x;
     const Counts cnt = a.counts[k];
     const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1;
@@ -898,10 +896,14 @@ __global__ void __launch_bounds__(kChunk) k_scs_assemble(ScsArgs a, int n1max) {
     }
 }
 
-// Factorisation of B~ in place, one workgroup per (atom, frequency).  The
-// panel buffer is dynamic LDS; Z is a separate static array so that the
-// compiler sees it cannot alias the panel buffer (with one carved buffer it
-// spilled the diagonal step's registers).
+// Assembly and factorisation of B~ in place, one workgroup per (atom,
+// frequency): the matrix written just before it is read back stays in the
+// caches, and the write-bound assembly of one workgroup overlaps the
+// factorisations of the others on the compute unit.  The panel buffer is
+// dynamic LDS (the assembly uses the same space first); Z is a separate static
+// array so that the compiler sees it cannot alias the panel buffer (with one
+// carved buffer it spilled the diagonal step's registers).
+static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
 template <typename R>
 __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
@@ -910,6 +912,7 @@ __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     R* pan = reinterpret_cast<R*>(lds);
     const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
+    assemble_matrix<R>(a, k, w, n1max, lds);   // ends with a barrier
     const int N = 3 * a.counts[k].n1;
     const int ld = a.fac_ld[k];
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
@@ -929,10 +932,16 @@ static size_t factor_panel_bytes(int n1max, bool mixed) {
     return r * (size_t)factor_tiles(n1max) * NB * kSlotLd;
 }
 
-// all LDS of the factorisation: panel buffer and Z = L_pp^{-1}
+// dynamic LDS of the assembly and factorisation kernel
+static size_t factor_dynamic_bytes(int n1max, bool mixed) {
+    return std::max(factor_panel_bytes(n1max, mixed), matrix_lds_bytes(n1max));
+}
+
+// all LDS of the assembly and factorisation: panel buffer (or the assembly's
+// data) and Z = L_pp^{-1}
 size_t scs_factor_lds_bytes(int n1max, bool mixed) {
     const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return factor_panel_bytes(n1max, mixed) + r * NB * kSlotLd;
+    return factor_dynamic_bytes(n1max, mixed) + r * NB * kSlotLd;
 }
 
 // Triangular solves with the stored factor, one workgroup of >= N threads per
@@ -1457,20 +1466,16 @@ hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2ma
 
 hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
-    const size_t ld = dvec_lds_bytes(n1max, n2max), lm = matrix_lds_bytes(n1max);
-    if (mixed) {
-        hipLaunchKernelGGL(k_scs_dvec<float>, grid, dim3(kChunk), ld, st, a, n1max, n2max);
-        hipLaunchKernelGGL(k_scs_assemble<float>, grid, dim3(kChunk), lm, st, a, n1max);
-    } else {
-        hipLaunchKernelGGL(k_scs_dvec<double>, grid, dim3(kChunk), ld, st, a, n1max, n2max);
-        hipLaunchKernelGGL(k_scs_assemble<double>, grid, dim3(kChunk), lm, st, a, n1max);
-    }
+    // d and the rows of d^T; B~ itself is assembled by the factorisation kernel
+    const size_t ld = dvec_lds_bytes(n1max, n2max);
+    if (mixed) hipLaunchKernelGGL(k_scs_dvec<float>, grid, dim3(kChunk), ld, st, a, n1max, n2max);
+    else hipLaunchKernelGGL(k_scs_dvec<double>, grid, dim3(kChunk), ld, st, a, n1max, n2max);
     return hipGetLastError();
 }
 
 hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
     const dim3 grid(a.n, a.nw);
-    const size_t lf = factor_panel_bytes(n1max, mixed);
+    const size_t lf = factor_dynamic_bytes(n1max, mixed);
     if (mixed) hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), lf, st, a, n1max);
     else hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), lf, st, a, n1max);
     return hipGetLastError();
