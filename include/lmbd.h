@@ -170,7 +170,8 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
  * call's stream before and after each stage of the hot path and, once the call
  * has completed, keeps the elapsed milliseconds of the last call per stage.
  * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map+
- * coupling lists, 2 local SCS assembly, 3 local SCS factorisation, 4 local SCS
+ * coupling lists, 2 right-hand sides d of the local SCS, 3 local SCS assembly
+ * and factorisation (one kernel), 4 local SCS
  * solves (with the refinement of the mixed path), 5 local MBD energy
  * (+adjoint), 6 central-polarisability gather, 7 adjoint SCS solves, 8 SCS
  * pair gradients, 9 force gather. */

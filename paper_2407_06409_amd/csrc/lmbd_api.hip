@@ -522,8 +522,8 @@ void lmbd_destroy(lmbd_context* ctx) {
     delete ctx;
 }
 
-static const char* kStageNames[LMBD_N_STAGES] = {"prep_sort_count", "nbr_fill_revmap", "scs_assemble",
-                                                  "scs_factor",      "scs_solve",       "mbd",
+static const char* kStageNames[LMBD_N_STAGES] = {"prep_sort_count", "nbr_fill_revmap", "scs_rhs",
+                                                  "scs_assemble_factor",      "scs_solve",       "mbd",
                                                   "gather_central",  "scs_lambda",      "scs_adjoint",
                                                   "gather_forces"};
 
@@ -1007,7 +1007,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_scs_assemble(stream, sa, P.n1max, P.n2max, mixed));
     HIP_TRY(mark(2, 1));
     HIP_TRY(mark(3, 0));
-    HIP_TRY(launch_scs_factor(stream, sa, P.n1max, mixed));
+    HIP_TRY(launch_scs_factor(stream, sa, P.n1max, mixed));   // assembles B~, then factorises it
     HIP_TRY(mark(3, 1));
     HIP_TRY(mark(4, 0));
     HIP_TRY(launch_scs_solve(stream, sa, P.n1max, mixed));
