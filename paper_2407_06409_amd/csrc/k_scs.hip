@@ -430,10 +430,17 @@ __device__ __forceinline__ void solve_row_update(const R* __restrict__ lrow, int
     Y[i * 3 + 2] -= s2;
 }
 
-template <typename R>
+// Triangular solves with the stored factor: L L^T x = b (fwd) or L^T x = y,
+// three right-hand sides in Y (N x 3, LDS), one row (forward) or column
+// (backward) per thread and slot: thread t takes t, t + blockDim, ..
+// (NS slots, NS * blockDim >= N).  Slot 0 loads a block ahead, further slots
+// (backward only, FWD false) load the block they use at its start.  Each row's
+// sums are formed in the same order whatever NS and blockDim are.
+template <typename R, int NS, bool FWD>
 __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int ld, R* Y, R* zbuf, bool fwd) {
+    static_assert(NS == 1 || !FWD, "the forward pass takes one row per thread");
     typedef typename Vec4T<R>::type V4;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int nt = (N + NB - 1) / NB;
     const int r = tid & 15, c = tid >> 4;
@@ -467,15 +474,15 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
         }
     };
     R zr[kZ];
-    R cur[NB], nxt[NB];
-    if (fwd) {
-        // forward: L y = b, one row per thread (blockDim >= N); the row's segment of
-        // the next block is loaded a block ahead
+    R cur[NS][NB], nxt[NB];
+    if (FWD && fwd) {
+        // forward: L y = b, one row per thread and slot; the row's segment of the
+        // next block is loaded a block ahead
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const V4 t4 = (tid >= NB && tid < N) ? load4(A + (size_t)tid * ld + 4 * v) : zero;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) cur[4 * v + e] = t4[e];
+            for (int e = 0; e < 4; ++e) cur[0][4 * v + e] = t4[e];
         }
         zload(0, true, zr);
         zstore(zbuf, zr);
@@ -487,12 +494,15 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
             R* zb = zbuf + (p & 1) * NB * kSlotLd;
             zstore(zbuf + ((p + 1) & 1) * NB * kSlotLd, zr);   // block p + 1 (loaded during block p - 1)
             zload(p + 2, true, zr);
-            const bool pre = tid >= c0 + 2 * NB && tid < N;      // row tid follows block p + 1
+            {
+                const int row = tid;
+                const bool pre = row >= c0 + 2 * NB && row < N;      // row follows block p + 1
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const V4 t4 = pre ? load4(A + (size_t)tid * ld + c0 + NB + 4 * v) : zero;
+                for (int v = 0; v < 4; ++v) {
+                    const V4 t4 = pre ? load4(A + (size_t)row * ld + c0 + NB + 4 * v) : zero;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
+                    for (int e = 0; e < 4; ++e) nxt[4 * v + e] = t4[e];
+                }
             }
             if (blk && r < jb) {
                 R v = 0;
@@ -502,17 +512,17 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
                 Y[(c0 + r) * 3 + c] = v;  // one wavefront: all reads of the block precede this write
             }
             __syncthreads();
-            if (tid >= c0 + NB && tid < N) solve_row_update(cur, c0, NB, tid, Y);  // jb = 16 when rows follow
+            if (tid >= c0 + NB && tid < N) solve_row_update(cur[0], c0, NB, tid, Y);  // jb = 16 when rows follow
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
+            for (int q = 0; q < NB; ++q) cur[0][q] = nxt[q];
         }
     }
-    // backward: L^T x = y; column tid's segment of the previous block is loaded a block ahead
+    // backward: L^T x = y; each column's segment of the previous block is loaded a block ahead
     {
         const int c0 = (nt - 1) * NB, jb = N - c0;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) cur[q] = (tid < c0 && q < jb) ? A[(size_t)(c0 + q) * ld + tid] : R(0);
+        for (int q = 0; q < NB; ++q) cur[0][q] = (tid < c0 && q < jb) ? A[(size_t)(c0 + q) * ld + tid] : R(0);
     }
     zload(nt - 1, false, zr);
     zstore(zbuf + ((nt - 1) & 1) * NB * kSlotLd, zr);
@@ -526,6 +536,12 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
         zload(p - 2, false, zr);
 #pragma unroll
         for (int q = 0; q < NB; ++q) nxt[q] = (p > 0 && tid < c0 - NB) ? A[(size_t)(c0 - NB + q) * ld + tid] : R(0);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {   // this block's column segment of the further slots
+            const int col = tid + s * nthr;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) cur[s][q] = (col < c0 && q < jb) ? A[(size_t)(c0 + q) * ld + col] : R(0);
+        }
         if (blk && r < jb) {
             R v = 0;
 #pragma unroll
@@ -534,10 +550,14 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
             Y[(c0 + r) * 3 + c] = v;
         }
         __syncthreads();
-        if (tid < c0) solve_row_update(cur, c0, jb, tid, Y);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int col = tid + s * nthr;
+            if (col < c0) solve_row_update(cur[s], c0, jb, col, Y);
+        }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < NB; ++q) cur[q] = nxt[q];
+        for (int q = 0; q < NB; ++q) cur[0][q] = nxt[q];
     }
 }
 
@@ -896,56 +916,8 @@ __device__ __forceinline__ void assemble_matrix(const ScsArgs& a, int k, int w, 
     }
 }
 
-// Assembly and factorisation of B~ in place, one workgroup per (atom,
-// frequency): the matrix written just before it is read back stays in the
-// caches, and the write-bound assembly of one workgroup overlaps the
-// factorisations of the others on the compute unit.  The panel buffer is
-// dynamic LDS (the assembly uses the same space first); Z is a separate static
-// array so that the compiler sees it cannot alias the panel buffer (with one
-// carved buffer it spilled the diagonal step's registers).
-static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
-template <typename R>
-__global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
-    extern __shared__ double lds[];
-    __shared__ R Zs[NB * kSlotLd];
-    __shared__ int counter[2];
-    R* pan = reinterpret_cast<R*>(lds);
-    const int k = a.order[blockIdx.x];
-    const int w = blockIdx.y;
-    assemble_matrix<R>(a, k, w, n1max, lds);   // ends with a barrier
-    const int N = 3 * a.counts[k].n1;
-    const int ld = a.fac_ld[k];
-    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
-    // the wave that factorises the diagonal blocks rotates over the workgroups
-    const int dw = (k + w) % (blockDim.x >> 6);
-    bool ok = true;
-    chol_factor<R>(A, N, ld, pan, Zs, counter, dw, ok);
-    if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
-        atomicOr(a.err, 4);
-        atomicMin(a.err_atom, k);
-    }
-}
-
-// dynamic LDS of the factorisation (the panel buffer)
-static size_t factor_panel_bytes(int n1max, bool mixed) {
-    const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return r * (size_t)factor_tiles(n1max) * NB * kSlotLd;
-}
-
-// dynamic LDS of the assembly and factorisation kernel
-static size_t factor_dynamic_bytes(int n1max, bool mixed) {
-    return std::max(factor_panel_bytes(n1max, mixed), matrix_lds_bytes(n1max));
-}
-
-// all LDS of the assembly and factorisation: panel buffer (or the assembly's
-// data) and Z = L_pp^{-1}
-size_t scs_factor_lds_bytes(int n1max, bool mixed) {
-    const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return factor_dynamic_bytes(n1max, mixed) + r * NB * kSlotLd;
-}
-
-// Triangular solves with the stored factor, one workgroup of >= N threads per
-// (atom, frequency).  Right-hand side and result by mode:
+// Triangular solves with the stored factor, one workgroup per (atom,
+// frequency), NS rows per thread.  Right-hand side and result by mode:
 //   kSolveD      : y = L^{-1} d (left by the factorisation) -> X (solution
 //                  slot) and Tr(X_i)/3                                       [FP64]
 //   kSolveFirst  : y = L^{-1} d -> X                                         [mixed]
@@ -953,11 +925,8 @@ size_t scs_factor_lds_bytes(int n1max, bool mixed) {
 //   kSolveLambda : Xbar_i = xbar_i I / 3 from the polarisability adjoints -> lambda
 enum { kSolveD = 0, kSolveFirst = 1, kSolveCorr = 2, kSolveLambda = 3 };
 
-template <typename R>
-__global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mode) {
-    extern __shared__ double lds[];
-    const int k = a.order[blockIdx.x];
-    const int w = blockIdx.y;
+template <typename R, int NS, bool FWD>
+__device__ __forceinline__ void solve_slot(const ScsArgs& a, int k, int w, int n1max, int mode, double* lds) {
     const int n1 = a.counts[k].n1;
     const int N = 3 * n1;
     const int ld = a.fac_ld[k];
@@ -980,7 +949,7 @@ __global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mod
         for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) Y[e] = A[(size_t)(N + e % 3) * ld + e / 3];
     }
     __syncthreads();
-    chol_solve3<R>(A, N, ld, Y, zbuf, mode == kSolveCorr || mode == kSolveLambda);
+    chol_solve3<R, NS, FWD>(A, N, ld, Y, zbuf, mode == kSolveCorr || mode == kSolveLambda);
     if (mode == kSolveLambda) {
         for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) a.lam[xo + e] = double(Y[e]);
         return;
@@ -994,9 +963,69 @@ __global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mod
         al[(size_t)s * a.nw + w] = (X[(3 * s) * 3 + 0] + X[(3 * s + 1) * 3 + 1] + X[(3 * s + 2) * 3 + 2]) / 3.0;
 }
 
+// one row per thread (blockDim >= N)
+template <typename R>
+__global__ void __launch_bounds__(512) k_scs_solve(ScsArgs a, int n1max, int mode) {
+    extern __shared__ double lds[];
+    solve_slot<R, 1, true>(a, a.order[blockIdx.x], blockIdx.y, n1max, mode, lds);
+}
+
 size_t scs_solve_lds_bytes(int n1max, bool mixed) {
     const size_t r = mixed ? sizeof(float) : sizeof(double);
     return r * (9 * (size_t)n1max + 2 * NB * kSlotLd);
+}
+
+// Assembly, factorisation and first solve of B~ in place, one workgroup per
+// (atom, frequency): the matrix written just before it is read back stays in
+// the caches, as does the factor for the solve, and the write-bound assembly of
+// one workgroup overlaps the factorisations of the others on the compute unit.  The panel buffer is
+// dynamic LDS (the assembly uses the same space first); Z is a separate static
+// array so that the compiler sees it cannot alias the panel buffer (with one
+// carved buffer it spilled the diagonal step's registers).
+static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
+static_assert(2 * 256 >= 3 * kMaxN1, "two rows per thread of the factorisation kernel cover its first solve");
+template <typename R>
+__global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
+    extern __shared__ double lds[];
+    __shared__ R Zs[NB * kSlotLd];
+    __shared__ int counter[2];
+    R* pan = reinterpret_cast<R*>(lds);
+    const int k = a.order[blockIdx.x];
+    const int w = blockIdx.y;
+    assemble_matrix<R>(a, k, w, n1max, lds);   // ends with a barrier
+    const int N = 3 * a.counts[k].n1;
+    const int ld = a.fac_ld[k];
+    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
+    // the wave that factorises the diagonal blocks rotates over the workgroups
+    const int dw = (k + w) % (blockDim.x >> 6);
+    bool ok = true;
+    chol_factor<R>(A, N, ld, pan, Zs, counter, dw, ok);   // ends with a barrier
+    if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
+        atomicOr(a.err, 4);
+        atomicMin(a.err_atom, k);
+    }
+    // the first solve (backward: the forward substitution was carried by the
+    // factorisation) while the factor is still in the caches
+    solve_slot<R, 2, false>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
+}
+
+// dynamic LDS of the factorisation (the panel buffer)
+static size_t factor_panel_bytes(int n1max, bool mixed) {
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return r * (size_t)factor_tiles(n1max) * NB * kSlotLd;
+}
+
+// dynamic LDS of the assembly and factorisation kernel
+static size_t factor_dynamic_bytes(int n1max, bool mixed) {
+    return std::max(std::max(factor_panel_bytes(n1max, mixed), matrix_lds_bytes(n1max)),
+                    scs_solve_lds_bytes(n1max, mixed));
+}
+
+// all LDS of the assembly and factorisation: panel buffer (or the assembly's
+// data) and Z = L_pp^{-1}
+size_t scs_factor_lds_bytes(int n1max, bool mixed) {
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return factor_dynamic_bytes(n1max, mixed) + r * NB * kSlotLd;
 }
 
 // Refinement residual of the mixed path: resid = d - B~ X in FP64, with B~
@@ -1484,14 +1513,12 @@ hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool m
 hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
     const dim3 grid(a.n, a.nw);
     const size_t ls = scs_solve_lds_bytes(n1max, mixed);
+    // the first solve ran in the factorisation kernel; the mixed path refines it here
     if (mixed) {
-        hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveFirst);
         for (int it = 0; it < a.n_refine; ++it) {
             hipLaunchKernelGGL(k_scs_residual, grid, dim3(256), scs_residual_lds_bytes(n1max), st, a, n1max);
             hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(512), ls, st, a, n1max, (int)kSolveCorr);
         }
-    } else {
-        hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(512), ls, st, a, n1max, (int)kSolveD);
     }
     return hipGetLastError();
 }
