@@ -170,9 +170,9 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
  * call's stream before and after each stage of the hot path and, once the call
  * has completed, keeps the elapsed milliseconds of the last call per stage.
  * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map+
- * coupling lists, 2 right-hand sides d of the local SCS, 3 local SCS assembly
- * and factorisation (one kernel), 4 local SCS
- * solves (with the refinement of the mixed path), 5 local MBD energy
+ * coupling lists, 2 right-hand sides d of the local SCS, 3 local SCS assembly,
+ * factorisation and first solve (one kernel), 4 refinement of the local SCS
+ * solution (mixed path; empty in FP64), 5 local MBD energy
  * (+adjoint), 6 central-polarisability gather, 7 adjoint SCS solves, 8 SCS
  * pair gradients, 9 force gather. */
 #define LMBD_N_STAGES 10

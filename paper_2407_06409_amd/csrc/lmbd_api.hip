@@ -523,7 +523,7 @@ void lmbd_destroy(lmbd_context* ctx) {
 }
 
 static const char* kStageNames[LMBD_N_STAGES] = {"prep_sort_count", "nbr_fill_revmap", "scs_rhs",
-                                                  "scs_assemble_factor",      "scs_solve",       "mbd",
+                                                  "scs_assemble_factor_solve", "scs_refine", "mbd",
                                                   "gather_central",  "scs_lambda",      "scs_adjoint",
                                                   "gather_forces"};
 

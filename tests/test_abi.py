@@ -47,7 +47,8 @@ def test_calls_that_need_no_device(lib):
     assert lib.lmbd_status_string(0) == b"ok"
     assert lib.lmbd_status_string(3) == b"request exceeds the memory budget"
     assert lib.lmbd_status_string(7) == b"request cancelled"
-    assert lib.lmbd_stage_name(3) == b"scs_assemble_factor"
+    assert lib.lmbd_stage_name(3) == b"scs_assemble_factor_solve"
+    assert lib.lmbd_stage_name(4) == b"scs_refine"
     assert lib.lmbd_stage_name(2) == b"scs_rhs"
     assert lib.lmbd_stage_name(10) is None
     assert lib.lmbd_last_error(None) == b""
