@@ -582,7 +582,7 @@ __device__ __forceinline__ void chol_solve3(const R* __restrict__ A, int N, int 
 // ---------------------------------------------------------------------------
 // Sums over runs of equal key in a chunk of kChunk values (one per thread,
 // keys ascending through the chunk, -1 for no value): each run's sum is added
-// to acc[NV key ..].  Within a wavefront by segmented prefix sums over the lanes
+// to acc[NV key ..] (global memory).  Within a wavefront by segmented prefix sums over the lanes
 // with DPP moves (row shifts by 1, 2, 4, 8 inside rows of 16 lanes, then the
 // last lane of a row broadcast to the rows after it; a lane adds what it
 // receives when the sending lane has its key), so the run's last lane holds
@@ -617,6 +617,12 @@ __device__ __forceinline__ void seg_step(int key, double (&h)[NV]) {
     }
 }
 
+// acc (global memory) += v.  An address never has two additions in flight
+// (within a chunk each key is added once, and the chunks and carries are
+// separated by barriers), so the order of the additions is fixed; the
+// hardware add at the cache saves the round trip of a read-modify-write.
+__device__ __forceinline__ void acc_add(double* acc, double v) { (void)unsafeAtomicAdd(acc, v); }
+
 template <int NV>
 __device__ __forceinline__ void run_sums(int key, double (&h)[NV], const int32_t* keys, double* acc, double* carry,
                                          int* carry_key) {
@@ -635,7 +641,7 @@ __device__ __forceinline__ void run_sums(int key, double (&h)[NV], const int32_t
         for (int v = 0; v < NV; ++v) carry[NV * wave + v] = h[v];
     } else if (key >= 0 && (lane == 63 || knext != key)) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[NV * key + v] += h[v];
+        for (int v = 0; v < NV; ++v) acc_add(&acc[NV * key + v], h[v]);
     }
 }
 
@@ -645,7 +651,7 @@ __device__ __forceinline__ void add_carries(double* acc, const double* carry, co
     for (int w = 0; w + 1 < kChunkWaves; ++w) {
         const int key = carry_key[w];
         if (key < 0) continue;
-        for (int v = 0; v < NV; ++v) acc[NV * key + v] += carry[NV * w + v];
+        for (int v = 0; v < NV; ++v) acc_add(&acc[NV * key + v], carry[NV * w + v]);
     }
 }
 
@@ -659,39 +665,41 @@ struct ScsLds {
     double *qx, *qy, *qz, *qab, *qsg, *qR;     // shell sites
     double *Y, *X;                             // adjoint: lambda and X, 3N x 3 each
     double* H;                                 // adjoint: pair terms of one chunk, 3 per thread
-    double *gk, *gq;                           // adjoint: per-site sums (K1, shell), 3 each
+    double* gk;                                // d: sums; B~: pair values
     int32_t* key;                              // adjoint: reduction key of each thread's pair
 };
 
 static_assert(kChunk >= kMaxN1, "the adjoint gives every K1 site a thread of its own");
 
+// Adjoint LDS: K1 sites, lambda (Y), the chunk's pair terms (H) and keys, then
+// X for the K1 x K1 pairs, whose space the shell sites take for the K1 x shell
+// pairs.  (The per-site sums are formed in the output slice in global memory.)
 __device__ inline ScsLds scs_lds(double* base, int n1max, int n2max) {
     const int N = 3 * n1max;
-    ScsLds L;
+    ScsLds L = {};
     L.px = base;
     L.py = L.px + n1max;
     L.pz = L.py + n1max;
     L.ab = L.pz + n1max;
     L.sg = L.ab + n1max;
     L.R = L.sg + n1max;
-    L.qx = L.R + n1max;
+    L.Y = L.R + n1max;
+    L.H = L.Y + 3 * N;
+    L.key = reinterpret_cast<int32_t*>(L.H + 3 * kChunk);
+    double* u = reinterpret_cast<double*>(L.key + kChunk);
+    L.X = u;
+    L.qx = u;
     L.qy = L.qx + n2max;
     L.qz = L.qy + n2max;
     L.qab = L.qz + n2max;
     L.qsg = L.qab + n2max;
     L.qR = L.qsg + n2max;
-    L.Y = L.qR + n2max;
-    L.X = L.Y + 3 * N;
-    L.H = L.X + 3 * N;
-    L.gk = L.H + 3 * kChunk;
-    L.gq = L.gk + 3 * n1max;
-    L.key = reinterpret_cast<int32_t*>(L.gq + 3 * n2max);
     return L;
 }
 
 size_t scs_lds_bytes(int n1max, int n2max, bool) {
     const size_t N = 3 * (size_t)n1max;
-    return sizeof(double) * (9 * (size_t)n1max + 6 * N + 9 * (size_t)n2max + 3 * kChunk) +
+    return sizeof(double) * (6 * (size_t)n1max + 3 * N + 3 * kChunk + std::max(3 * N, 6 * (size_t)n2max)) +
            sizeof(int32_t) * kChunk;
 }
 
@@ -733,9 +741,10 @@ __device__ inline ScsLds scs_assemble_lds(double* base, int n1max, int n2max, bo
     return L;
 }
 
-__device__ inline void load_sites(const ScsArgs& a, int k, int w, int n1, int n12, const ScsLds& L) {
+// sites s0 .. n12-1 of atom k (K1 sites below n1, then the shell) to LDS
+__device__ inline void load_sites(const ScsArgs& a, int k, int w, int n1, int n12, const ScsLds& L, int s0 = 0) {
     const Site* S = a.sites + a.site_off[k];
-    for (int s = threadIdx.x; s < n12; s += blockDim.x) {
+    for (int s = s0 + threadIdx.x; s < n12; s += blockDim.x) {
         const Site st = S[s];
         const double ab = a.abar[(size_t)st.base * a.nw + w];
         const double sg = a.sigma[(size_t)st.base * a.nw + w];
@@ -1128,7 +1137,7 @@ size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)
 // contractions and sums are FP64.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
+__global__ void __launch_bounds__(kChunk, 3) k_scs_adjoint(ScsArgs a, int n1max, int n2max) {
     extern __shared__ double lds[];
     const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
@@ -1141,13 +1150,17 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
     ScsLds L = scs_lds(lds, n1max, n2max);
     const double* Xg = a.xsol + a.x_off[k] + (size_t)w * N * 3;
     const double* Lg = a.lam + a.x_off[k] + (size_t)w * N * 3;
-    load_sites(a, k, w, n1, n12, L);
+    load_sites(a, k, w, n1, n1, L);   // the shell sites follow once X is no longer needed
     for (int e = t; e < 3 * N; e += kChunk) {
         L.X[e] = Xg[e];
         L.Y[e] = Lg[e];
     }
-    for (int e = t; e < 3 * n1; e += kChunk) L.gk[e] = 0.0;
-    for (int e = t; e < 3 * n2; e += kChunk) L.gq[e] = 0.0;
+    // this (atom, frequency)'s slice of the contributions: the per-site sums are
+    // formed in it (K1 sites gk, then shell sites gq), then scaled to forces
+    double* out = a.cf + (size_t)w * a.cf_slice + a.site_off[k] * 3;
+    double* gk = out;
+    double* gq = out + 3 * n1;
+    for (int e = t; e < 3 * n12; e += kChunk) out[e] = 0.0;
     const int32_t* seg = pair_segs(a, k);
     const int32_t* seg_i = seg;
     const int32_t* seg_q = seg + (n1 + 1);
@@ -1239,12 +1252,15 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
             L.H[3 * t + 1] = h[1];
             L.H[3 * t + 2] = h[2];
             __syncthreads();
-            run_sums<3>(key, h, L.key, L.gk, carry, carry_key);
+            run_sums<3>(key, h, L.key, gk, carry, carry_key);
             if (walker) consume(lb, p, pe, e0 + kChunk, gb);
             __syncthreads();
-            add_carries<3>(L.gk, carry, carry_key);
+            add_carries<3>(gk, carry, carry_key);
         }
     }
+    __syncthreads();   // X is no longer needed: the shell sites take its space
+    load_sites(a, k, w, n1, n12, L, n1);
+    __syncthreads();
     // K1 x shell pairs, shell-major: h = qab_q * (gradient of the lambda_i : dd_i
     // term with respect to r_i); the shell site gains h, the K1 site loses it
     {
@@ -1280,15 +1296,14 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
             L.H[3 * t + 1] = h[1];
             L.H[3 * t + 2] = h[2];
             __syncthreads();
-            run_sums<3>(key, h, L.key, L.gq, carry, carry_key);
+            run_sums<3>(key, h, L.key, gq, carry, carry_key);
             if (walker) consume(li, p, pe, e0 + kChunk, gi);
             __syncthreads();
-            add_carries<3>(L.gq, carry, carry_key);
+            add_carries<3>(gq, carry, carry_key);
         }
     }
     __syncthreads();
 
-    double* out = a.cf + (size_t)w * a.cf_slice + a.site_off[k] * 3;
     const double fconv = -1.0 / kBohr;  // force = -dE/dx, per Angstrom
     if (ws == 2) {   // the two walkers of a site are adjacent lanes
         for (int c = 0; c < 3; ++c) {
@@ -1297,10 +1312,10 @@ __global__ void __launch_bounds__(kChunk) k_scs_adjoint(ScsArgs a, int n1max, in
         }
     }
     if (walker && part == 0) {
-        for (int c = 0; c < 3; ++c) out[3 * site + c] = fconv * ((L.gk[3 * site + c] + gb[c]) + gi[c]);
+        for (int c = 0; c < 3; ++c) out[3 * site + c] = fconv * ((gk[3 * site + c] + gb[c]) + gi[c]);
     }
     for (int q = t; q < n2; q += kChunk)
-        for (int c = 0; c < 3; ++c) out[3 * (n1 + q) + c] = fconv * L.gq[3 * q + c];
+        for (int c = 0; c < 3; ++c) gq[3 * q + c] = fconv * gq[3 * q + c];
     for (int s = n12 + t; s < nall; s += kChunk)
         for (int c = 0; c < 3; ++c) out[3 * s + c] = 0.0;
 }
