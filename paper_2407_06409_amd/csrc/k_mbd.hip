@@ -222,8 +222,9 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     const int KK = n_max * ncol, KKp = (KK + 3) / 4 * 4;
     const int N3p = (int)al4(N3);                            // row stride of T and of V^T (zero padded)
     W* U = T + al4((size_t)N3 * N3p);                        // u_1 .. u_mmax
-    W* V = U + al4((size_t)a.mmax * N3 * ncol);              // (D u_m)^T, the next product's operand, ncol x N3p
-    W* Pm = V + al4((size_t)ncol * N3p);                     // D u_a side by side, a = 0 .. n_max-1
+    W* V = U + al4((size_t)a.mmax * N3 * ncol);              // (D u_m)^T, the next product's operand, ncol x N3p,
+    W* V2 = V + al4((size_t)ncol * N3p);                     //   in two buffers used in turn
+    W* Pm = V2 + al4((size_t)ncol * N3p);                    // D u_a side by side, a = 0 .. n_max-1
     W* Qm = Pm + (size_t)N3 * KKp;                           // W D Z_a side by side
     auto Uat = [&](int m) { return U + (size_t)(m - 1) * N3 * ncol; };
 
@@ -283,7 +284,10 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
             }
     }
     for (int e = tid; e < N3 * (N3p - N3); e += blockDim.x) T[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
-    for (int e = tid; e < ncol * (N3p - N3); e += blockDim.x) V[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
+    for (int e = tid; e < ncol * (N3p - N3); e += blockDim.x) {
+        V[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
+        V2[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
+    }
     __syncthreads();
 
     // --- u_1 = D T D e_k, V = D u_1
@@ -297,17 +301,18 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
         V[(size_t)col * N3p + row] = W(sq * u);
     }
     __syncthreads();
-    // --- u_{m+1} = D (T V), V = D u_{m+1}  (T symmetric, so it is its own K-major operand)
+    // --- u_{m+1} = D (T V), V' = D u_{m+1}  (T symmetric, so it is its own K-major
+    // operand); the product's stores write both, V' into the other buffer
     for (int m = 1; m < a.mmax; ++m) {
         W* Un = Uat(m + 1);
-        mfma_gemm_nt<3, 3, W>(N3, ncol, N3, T, N3p, V, N3p, false, [&](int r, int col, W v) {
-            Un[(size_t)r * ncol + col] = W(L.sqa[(size_t)(r / 3) * nq + col / 3]) * v;
-        });
-        for (int e = tid; e < N3 * ncol; e += blockDim.x) {
-            const int row = e / ncol, col = e % ncol;
-            V[(size_t)col * N3p + row] = W(L.sqa[(size_t)(row / 3) * nq + col / 3]) * Un[e];
-        }
-        __syncthreads();
+        const W* Vin = (m & 1) ? V : V2;
+        W* Vout = (m & 1) ? V2 : V;
+        mfma_gemm_nt<3, 3, W>(N3, ncol, N3, T, N3p, Vin, N3p, false, [&](int r, int col, W v) {
+            const W sq = W(L.sqa[(size_t)(r / 3) * nq + col / 3]);
+            const W un = sq * v;
+            Un[(size_t)r * ncol + col] = un;
+            Vout[(size_t)col * N3p + r] = sq * un;
+        });   // ends with a barrier
     }
 
     // --- moments mu_n(q) = <u_a, u_b>, a + b = n; four lanes per moment over

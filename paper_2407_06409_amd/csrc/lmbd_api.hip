@@ -298,7 +298,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         xo += (int64_t)nw * N1 * 3;
         ao += (int64_t)c.n1 * nw;
         auto al4 = [](int64_t x) { return (x + 3) / 4 * 4; };  // as the MBD kernel lays out its workspace
-        wo += al4(N3 * al4(N3)) + al4((int64_t)mmax * N3 * ncol) + al4(ncol * al4(N3)) +
+        wo += al4(N3 * al4(N3)) + al4((int64_t)mmax * N3 * ncol) + 2 * al4(ncol * al4(N3)) +
               (forces ? 2 * N3 * al4((int64_t)n_max * ncol) : 0);
         P.n1max = std::max(P.n1max, c.n1);
         P.nkmax = std::max(P.nkmax, c.nK);
