@@ -386,7 +386,8 @@ def main():
         line["mixed"] = {"value": st.n * args.steps / el, "unit": "atoms/s", "ms_per_step": el / args.steps * 1e3,
                          "dtype": "f32 matrices/GEMMs on MFMA, f64 refinement and accumulation",
                          "max_abs_dE_vs_fp64_eV_per_atom": float((om["energies"] - out["energies"]).abs().max()),
-                         "max_abs_dF_vs_fp64_eV_per_A": float((om["forces"] - out["forces"]).abs().max())}
+                         "max_abs_dF_vs_fp64_eV_per_A": float((om["forces"] - out["forces"]).abs().max()),
+                         "stages_ms": dict(ctx.stage_times())}   # of the last mixed step
     if not args.no_serve:
         line["served"] = serve_bench(args.serve_sweep)
     if not args.no_cpu_baseline and args.workload == "plain":
