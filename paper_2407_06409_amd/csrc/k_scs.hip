@@ -1411,21 +1411,44 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
     for (int e = t; e < nwords; e += nt) L.bq[e] = 0u;
     __syncthreads();
     const int sq = scramble_stride(n2), sa = scramble_stride(n1);
-    // every coupling tested once: K1 x shell (i, x = scrambled shell position)
-    for (int e = t; e < n1 * n2; e += nt) {
-        const int i = e / n2, x = e % n2;
-        const int q = (int)(((int64_t)x * sq) % n2);
-        const double dx = L.px[i] - L.qx[q], dy = L.py[i] - L.qy[q], dz = L.pz[i] - L.qz[q];
-        if (dx * dx + dy * dy + dz * dz < rc2) {
-            atomicOr(&L.bq[(size_t)i * wq + (x >> 5)], 1u << (x & 31));
-            atomicOr(&L.cq[(size_t)q * wa + (i >> 5)], 1u << (i & 31));
+    // every coupling tested once: K1 x shell (i, x = scrambled shell position,
+    // q = x sq mod n2); e = i n2 + x advances by nt, and i, x and q follow it
+    // by additions (x sq mod n2 does not change when x wraps by n2)
+    if (n2 > 0) {
+        int i = t / n2, x = t % n2;
+        int q = (int)(((int64_t)x * sq) % n2);
+        const int dq = (int)(((int64_t)(nt % n2) * sq) % n2), di = nt / n2, dx0 = nt % n2;
+        for (int e = t; e < n1 * n2; e += nt) {
+            const double dx = L.px[i] - L.qx[q], dy = L.py[i] - L.qy[q], dz = L.pz[i] - L.qz[q];
+            if (dx * dx + dy * dy + dz * dz < rc2) {
+                atomicOr(&L.bq[(size_t)i * wq + (x >> 5)], 1u << (x & 31));
+                atomicOr(&L.cq[(size_t)q * wa + (i >> 5)], 1u << (i & 31));
+            }
+            i += di;
+            x += dx0;
+            q += dq;
+            if (q >= n2) q -= n2;
+            if (x >= n2) {
+                x -= n2;
+                ++i;
+            }
         }
     }
     // K1 x K1 (i, x = scrambled K1 position of j): j > i in natural order for
     // i's a-major entries, j < i in scrambled order for i's b-side list
+    int ii = t / n1, xx = t % n1;
+    int jj = (int)(((int64_t)xx * sa) % n1);
+    const int dj = (int)(((int64_t)(nt % n1) * sa) % n1), dii = nt / n1, dxx = nt % n1;
     for (int e = t; e < n1 * n1; e += nt) {
-        const int i = e / n1, x = e % n1;
-        const int j = (int)(((int64_t)x * sa) % n1);
+        const int i = ii, x = xx, j = jj;
+        ii += dii;
+        xx += dxx;
+        jj += dj;
+        if (jj >= n1) jj -= n1;
+        if (xx >= n1) {
+            xx -= n1;
+            ++ii;
+        }
         if (j == i) continue;
         const double dx = L.px[i] - L.px[j], dy = L.py[i] - L.py[j], dz = L.pz[i] - L.pz[j];
         if (dx * dx + dy * dy + dz * dz < rc2) {
@@ -1466,12 +1489,13 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
         }
         if (c) {
             int acc = 0;
-            for (int x = 0; x < len; ++x) {
-                const int y = (int)(((int64_t)x * stride) % len);
+            for (int x = 0, y = 0; x < len; ++x) {   // y = x stride mod len
                 const int v = c[y];
                 c[y] = acc;
                 seg[at + y] = acc;
                 acc += v;
+                y += stride;
+                if (y >= len) y -= len;
             }
             c[len] = acc;
             seg[at + len] = acc;
@@ -1504,7 +1528,7 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
         int pos = L.cnt_i[i] + bits_below(row, 32 * w);
         for (uint32_t m = row[w]; m; m &= m - 1) {
             const int x = 32 * w + __ffs(m) - 1;
-            const int q = (int)(((int64_t)x * sq) % n2);
+            const int q = (int)((uint32_t)(x * sq) % (uint32_t)n2);   // x sq < n2^2 < 2^31
             li[pos++] = L.cnt_q[q] + bits_below(L.cq + (size_t)q * wa, i);
         }
     }
@@ -1516,7 +1540,7 @@ __global__ void __launch_bounds__(256) k_pairlist(ScsArgs a, int n1max, int n2ma
         int pos = L.cnt_b[i] + bits_below(row, 32 * w);
         for (uint32_t m = row[w]; m; m &= m - 1) {
             const int x = 32 * w + __ffs(m) - 1;
-            const int j = (int)(((int64_t)x * sa) % n1);
+            const int j = (int)((uint32_t)(x * sa) % (uint32_t)n1);   // x sa < n1^2 < 2^31
             lb[pos++] = L.cnt_a[j] + bits_below(L.na + (size_t)j * wa, i);
         }
     }
