@@ -256,13 +256,12 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
     }
     __syncthreads();
 
-    // --- T_LR (row-major, symmetric, zero diagonal blocks).  Each unordered pair
-    // j <= i once: its 3x3 block is symmetric and the same for (i, j) and (j, i).
-    for (int p = tid; p < nK * (nK + 1) / 2; p += blockDim.x) {
-        int i = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
-        while ((i + 1) * (i + 2) / 2 <= p) ++i;
-        while (i * (i + 1) / 2 > p) --i;
-        const int j = p - i * (i + 1) / 2;
+    // --- T_LR (row-major, symmetric, zero diagonal blocks).  One block (i, j)
+    // per thread, consecutive threads along a block row, so that the rows are
+    // written in contiguous runs (each unordered pair is evaluated from both
+    // ends: the block is the same for (i, j) and (j, i)).
+    for (int p = tid; p < nK * nK; p += blockDim.x) {
+        const int i = p / nK, j = p % nK;
         double blk[9] = {};
         if (i != j) {
             const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
@@ -278,10 +277,7 @@ __global__ void __launch_bounds__(256, 2) k_mbd(MbdArgs a, int nkmax) {
             }
         }
         for (int q = 0; q < 3; ++q)
-            for (int c = 0; c < 3; ++c) {
-                T[(size_t)(3 * i + q) * N3p + 3 * j + c] = W(blk[3 * q + c]);
-                T[(size_t)(3 * j + q) * N3p + 3 * i + c] = W(blk[3 * q + c]);
-            }
+            for (int c = 0; c < 3; ++c) T[(size_t)(3 * i + q) * N3p + 3 * j + c] = W(blk[3 * q + c]);
     }
     for (int e = tid; e < N3 * (N3p - N3); e += blockDim.x) T[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
     for (int e = tid; e < ncol * (N3p - N3); e += blockDim.x) {
