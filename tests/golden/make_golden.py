@@ -3,7 +3,8 @@
 Every number in the files written here comes from the CPU oracle (``oracle/``)
 on the seeded workloads of ``workloads/``; nothing is taken from the GPU path.
 
-    python tests/golden/make_golden.py            # all fixtures
+    python tests/golden/make_golden.py                        # all fixtures
+    python tests/golden/make_golden.py --only C1728_pbc_6p8A    # some, merged into the file
 """
 import json
 import os
@@ -52,21 +53,53 @@ def forces_fixture(name, st, cut, atoms):
             "forces_eV_per_A": [[float(x) for x in f[a]] for a in nz]}
 
 
+def cutoff_6p8A():
+    """The 1,728-atom carbon box with every radius at 6.8 A: 132 K1 sites per atom
+    on average and up to 154 (N = 3 n1 up to 462), the large-neighbourhood end
+    of the solves."""
+    st, cut = C.config_plain_pbc()
+    return st, {k: (6.8 if k.startswith("r_") else v) for k, v in cut.items()}
+
+
+def fixture(name):
+    if name == "C1728_pbc":
+        st, cut = C.config_plain_pbc()
+        return {"cutoffs": cut,
+                "energies": energies_fixture("C1728", st, cut, sample(st.n, 12, 7)),
+                "forces": forces_fixture("C1728", st, cut, sample(st.n, 3, 8))}
+    if name == "HCNO4096_pbc":
+        st, cut = C.config_diff_hcno()
+        return {"cutoffs": cut, "energies": energies_fixture("HCNO4096", st, cut, sample(st.n, 8, 9))}
+    if name == "C13824_pbc":
+        st, cut = C.config_mixed_pbc()
+        return {"cutoffs": cut, "energies": energies_fixture("C13824", st, cut, sample(st.n, 6, 10))}
+    if name == "C1728_pbc_6p8A":
+        st, cut = cutoff_6p8A()
+        return {"cutoffs": cut,
+                "energies": energies_fixture("C1728 6.8A", st, cut, sample(st.n, 4, 11)),
+                "forces": forces_fixture("C1728 6.8A", st, cut, sample(st.n, 1, 12))}
+    raise KeyError(name)
+
+
+NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A"]
+
+
 def main():
+    """All fixtures, or (--only a,b) only the named ones, merged into the stored file."""
+    path = os.path.join(HERE, "oracle_fullsize.json")
+    names = NAMES
     out = {"source": "CPU FP64 oracle (oracle/lmbd.py) on the seeded workloads; written by "
                      "tests/golden/make_golden.py",
            "params": DEFAULT_PARAMS}
-    st, cut = C.config_plain_pbc()
-    out["C1728_pbc"] = {"cutoffs": cut,
-                        "energies": energies_fixture("C1728", st, cut, sample(st.n, 12, 7)),
-                        "forces": forces_fixture("C1728", st, cut, sample(st.n, 3, 8))}
-    st, cut = C.config_diff_hcno()
-    out["HCNO4096_pbc"] = {"cutoffs": cut, "energies": energies_fixture("HCNO4096", st, cut, sample(st.n, 8, 9))}
-    st, cut = C.config_mixed_pbc()
-    out["C13824_pbc"] = {"cutoffs": cut, "energies": energies_fixture("C13824", st, cut, sample(st.n, 6, 10))}
-    with open(os.path.join(HERE, "oracle_fullsize.json"), "w") as fh:
+    if "--only" in sys.argv:
+        names = sys.argv[sys.argv.index("--only") + 1].split(",")
+        with open(path) as fh:
+            out = json.load(fh)
+    for name in names:
+        out[name] = fixture(name)
+    with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print("wrote", os.path.join(HERE, "oracle_fullsize.json"))
+    print("wrote", path)
 
 
 if __name__ == "__main__":

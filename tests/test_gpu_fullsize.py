@@ -44,6 +44,30 @@ def test_c1728_energies_and_partial_forces_match_oracle():
     assert df < 1e-8
 
 
+def test_c1728_cutoff_6p8A_large_neighbourhoods_match_oracle():
+    """Up to 154 K1 sites per atom (N = 3 n1 up to 462): the solves' second row
+    slot (rows 256 and up of the 256-thread workgroups) and the larger LDS
+    layouts, against stored oracle energies and the forces of a one-atom sum."""
+    g = golden()["C1728_pbc_6p8A"]
+    st, _ = C.config_plain_pbc()
+    cut = g["cutoffs"]
+    print(f"case C1728 cutoff 6.8 A n={st.n}", flush=True)
+    full = gpu_run(st, cut, forces=False)
+    atoms = g["energies"]["atoms"]
+    de = np.abs(full["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+    print(f"  max |dE| on {len(atoms)} sampled atoms: {de:.3e} eV", flush=True)
+    assert de < 1e-8
+    w = np.zeros(st.n)
+    w[g["forces"]["weighted_atoms"]] = 1.0
+    part = gpu_run(st, cut, forces=True, weights=w)
+    ref = np.zeros((st.n, 3))
+    ref[g["forces"]["force_atoms"]] = np.array(g["forces"]["forces_eV_per_A"])
+    df = np.abs(part["forces"] - ref).max()
+    print(f"  max |dF| of the weighted one-atom sum over all atoms: {df:.3e} eV/A "
+          f"(max |F| {np.abs(ref).max():.3e})", flush=True)
+    assert df < 1e-8
+
+
 def test_hcno4096_energies_match_oracle():
     g = golden()["HCNO4096_pbc"]
     st, cut = C.config_diff_hcno()
