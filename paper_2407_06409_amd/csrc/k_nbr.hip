@@ -129,18 +129,25 @@ __global__ void k_cell_ranges(int n, const int32_t* __restrict__ sorted_cell,
 }
 
 
-// Visit every candidate site of atom k (one wavefront per atom) in a fixed
-// order; `fn(valid, j, t0, t1, t2, v, d2)` is called once per chunk of 64 lanes.
+// number of cells in the search stencil of a structure
+__device__ inline int stencil_cells(const StructInfo& S) {
+    return (2 * S.reach[0] + 1) * (2 * S.reach[1] + 1) * (2 * S.reach[2] + 1);
+}
+
+// Visit the candidate sites of atom k in the stencil cells [c_begin, c_end)
+// (dx slowest, dz fastest; one wavefront) in a fixed order; `fn(valid, j, t0,
+// t1, t2, v, d2)` is called once per chunk of 64 lanes.  Consecutive blocks of
+// the stencil visited one after the other give the order of the whole stencil.
 template <typename F>
-__device__ inline void visit_candidates(const NbrArgs& a, int k, int lane, F fn) {
+__device__ inline void visit_candidates(const NbrArgs& a, int k, int lane, int c_begin, int c_end, F fn) {
     const StructInfo& S = a.sinfo[a.atom_struct[k]];
     const int local = a.cell_id[k] - S.cell_offset;
     const int ck[3] = {local / (S.ncell[1] * S.ncell[2]), (local / S.ncell[2]) % S.ncell[1],
                        local % S.ncell[2]};
     const int wk0 = a.wrap[3 * k], wk1 = a.wrap[3 * k + 1], wk2 = a.wrap[3 * k + 2];
-    for (int dx = -S.reach[0]; dx <= S.reach[0]; ++dx)
-        for (int dy = -S.reach[1]; dy <= S.reach[1]; ++dy)
-            for (int dz = -S.reach[2]; dz <= S.reach[2]; ++dz) {
+    const int ny = 2 * S.reach[1] + 1, nz = 2 * S.reach[2] + 1;
+    for (int c = c_begin; c < c_end; ++c) {
+                const int dx = c / (ny * nz) - S.reach[0], dy = (c / nz) % ny - S.reach[1], dz = c % nz - S.reach[2];
                 int cc[3] = {ck[0] + dx, ck[1] + dy, ck[2] + dz};
                 int sh[3] = {0, 0, 0};
                 bool inside = true;
@@ -177,14 +184,23 @@ __device__ inline void visit_candidates(const NbrArgs& a, int k, int lane, F fn)
             }
 }
 
-__global__ void __launch_bounds__(256) k_nbr_count(NbrArgs a, Counts* __restrict__ counts) {
-    const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= a.n) return;
+// one atom per workgroup, wavefront w counting the w-th block of the stencil
+__device__ inline void stencil_block(const StructInfo& S, int w, int& c0, int& c1) {
+    const int C = stencil_cells(S);
+    c0 = (int)((int64_t)C * w / kNbrWaves);
+    c1 = (int)((int64_t)C * (w + 1) / kNbrWaves);
+}
+
+__global__ void __launch_bounds__(64 * kNbrWaves) k_nbr_count(NbrArgs a, Counts* __restrict__ counts) {
+    __shared__ int part[kNbrWaves][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = blockIdx.x;
     const StructInfo& S = a.sinfo[a.atom_struct[k]];
     const double r1 = S.r_scs * S.r_scs, rK = S.r_nbr * S.r_nbr, r2 = 4.0 * S.r_scs * S.r_scs;
     int c_all = 0, c1 = 0, cK = 0, c12 = 0;
-    visit_candidates(a, k, lane, [&](bool valid, int, int, int, int, const double*, double d2) {
+    int cb, ce;
+    stencil_block(S, wave, cb, ce);
+    visit_candidates(a, k, lane, cb, ce, [&](bool valid, int, int, int, int, const double*, double d2) {
         if (valid) {
             c_all += 1;
             c1 += d2 < r1;
@@ -198,31 +214,63 @@ __global__ void __launch_bounds__(256) k_nbr_count(NbrArgs a, Counts* __restrict
         cK += __shfl_xor(cK, off);
         c12 += __shfl_xor(c12, off);
     }
-    if (lane == 0) counts[k] = Counts{1 + c_all, 1 + c1, 1 + cK, 1 + c12};
+    if (lane == 0) {
+        int32_t* wc = a.wcounts + ((size_t)k * kNbrWaves + wave) * 4;
+        wc[0] = c_all;
+        wc[1] = c1;
+        wc[2] = cK;
+        wc[3] = c12;
+        part[wave][0] = c_all;
+        part[wave][1] = c1;
+        part[wave][2] = cK;
+        part[wave][3] = c12;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t[4] = {0, 0, 0, 0};
+        for (int w = 0; w < kNbrWaves; ++w)
+            for (int q = 0; q < 4; ++q) t[q] += part[w][q];
+        counts[k] = Counts{1 + t[0], 1 + t[1], 1 + t[2], 1 + t[3]};
+    }
 }
 
-__global__ void __launch_bounds__(256) k_nbr_fill(NbrArgs a, const Counts* __restrict__ counts,
+// one atom per workgroup: wavefront w fills from the w-th block of the
+// stencil, each of its site classes starting after the sites the blocks before
+// it found (their counts come from k_nbr_count), so the order is that of one
+// pass over the whole stencil
+__global__ void __launch_bounds__(64 * kNbrWaves) k_nbr_fill(NbrArgs a, const Counts* __restrict__ counts,
                                                   const int64_t* __restrict__ site_off,
                                                   Site* __restrict__ sites) {
-    const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= a.n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = blockIdx.x;
     const StructInfo& S = a.sinfo[a.atom_struct[k]];
     Site* out = sites + site_off[k];
     const Counts c = counts[k];
-    // sorted thresholds and the counts below each
+    // sorted thresholds and the counts below each (whole stencil, and in the
+    // blocks before this wavefront's); counts index 1, 2, 3 = r_scs, r_nbr, 2 r_scs
     double th[3] = {S.r_scs, S.r_nbr, 2.0 * S.r_scs};
     int below[3] = {c.n1 - 1, c.nK - 1, c.n12 - 1};
+    int idx[3] = {1, 2, 3};
     for (int i = 0; i < 3; ++i)
         for (int j = i + 1; j < 3; ++j)
             if (th[j] < th[i]) {
                 double t = th[i]; th[i] = th[j]; th[j] = t;
                 int b = below[i]; below[i] = below[j]; below[j] = b;
+                int x = idx[i]; idx[i] = idx[j]; idx[j] = x;
             }
+    int before[3] = {0, 0, 0};   // sites of each class found by the earlier blocks
+    for (int w = 0; w < wave; ++w) {
+        const int32_t* wc = a.wcounts + ((size_t)k * kNbrWaves + w) * 4;
+        before[0] += wc[idx[0]];
+        before[1] += wc[idx[1]] - wc[idx[0]];
+        before[2] += wc[0] - wc[idx[1]];
+    }
     const double t0s = th[0] * th[0], t1s = th[1] * th[1];
-    int cursor[3] = {1, 1 + below[0], 1 + below[1]};
-    if (lane == 0) out[0] = Site{0.0, 0.0, 0.0, k, pack_shift(0, 0, 0)};
-    visit_candidates(a, k, lane, [&](bool valid, int j, int t0, int t1, int t2, const double* v,
+    int cursor[3] = {1 + before[0], 1 + below[0] + before[1], 1 + below[1] + before[2]};
+    if (lane == 0 && wave == 0) out[0] = Site{0.0, 0.0, 0.0, k, pack_shift(0, 0, 0)};
+    int cb, ce;
+    stencil_block(S, wave, cb, ce);
+    visit_candidates(a, k, lane, cb, ce, [&](bool valid, int j, int t0, int t1, int t2, const double* v,
                                      double d2) {
         const int cls = d2 < t0s ? 0 : (d2 < t1s ? 1 : 2);
         const uint64_t below_me = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -338,13 +386,13 @@ hipError_t sort_cells(hipStream_t st, int n, int n_cells, const int32_t* cell_id
 }
 
 hipError_t launch_nbr_count(hipStream_t st, const NbrArgs& a, Counts* counts) {
-    hipLaunchKernelGGL(k_nbr_count, dim3((a.n + 3) / 4), dim3(256), 0, st, a, counts);
+    hipLaunchKernelGGL(k_nbr_count, dim3(a.n), dim3(64 * kNbrWaves), 0, st, a, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_nbr_fill(hipStream_t st, const NbrArgs& a, const Counts* counts,
                            const int64_t* site_off, Site* sites) {
-    hipLaunchKernelGGL(k_nbr_fill, dim3((a.n + 3) / 4), dim3(256), 0, st, a, counts, site_off, sites);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(a.n), dim3(64 * kNbrWaves), 0, st, a, counts, site_off, sites);
     return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ struct lmbd_context {
     std::string err;
     DBuf in_pos, in_sp, in_nu, in_w, atom_struct, sinfo, sp_table, omegas;
     DBuf pos_b, abar, sigma, Rv, a0v, r0v, cell_id, wrap, iota, sorted_cell, sorted_atoms;
-    DBuf cell_start, cell_end, sort_temp, counts, flags;
+    DBuf cell_start, cell_end, sort_temp, counts, flags, wcounts;
     DBuf site_off, sites, hash_off, hash_cap, table, rev;
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
@@ -85,7 +85,7 @@ struct lmbd_context {
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
         &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
-        &c->order, &c->tabs
+        &c->order, &c->tabs, &c->wcounts
 
 namespace {
 
@@ -382,6 +382,7 @@ hipError_t layout_pre(lmbd_context* c, const PreDims& d, F&& get) {
         {&c->a0v, N * D}, {&c->r0v, N * D}, {&c->cell_id, N * I}, {&c->wrap, 3 * N * I},
         {&c->sorted_cell, N * I}, {&c->sorted_atoms, N * I}, {&c->cell_start, (size_t)d.n_cells * I},
         {&c->cell_end, (size_t)d.n_cells * I}, {&c->counts, N * sizeof(Counts)}, {&c->flags, 4 * sizeof(int)},
+        {&c->wcounts, N * kNbrWaves * 4 * I},
         {&c->sort_temp, d.sort_temp}};
     for (const auto& e : L) {
         const hipError_t r = get(*e.first, e.second);
@@ -891,6 +892,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     na.cell_start = as<int32_t>(ctx->cell_start);
     na.cell_end = as<int32_t>(ctx->cell_end);
     na.sorted_atoms = as<int32_t>(ctx->sorted_atoms);
+    na.wcounts = as<int32_t>(ctx->wcounts);
     HIP_TRY(launch_nbr_count(stream, na, as<Counts>(ctx->counts)));
     HIP_TRY(mark(0, 1));
     std::vector<Counts> cnt(N);

@@ -149,7 +149,9 @@ struct NbrArgs {
     const int32_t* cell_start;
     const int32_t* cell_end;
     const int32_t* sorted_atoms;
+    int32_t* wcounts;   // per atom and wavefront of the search: counts (all, r_scs, r_nbr, 2 r_scs)
 };
+constexpr int kNbrWaves = 4;   // wavefronts per atom in the neighbour search (each a block of the cell stencil)
 
 struct ScsArgs {
     int n, nw;
