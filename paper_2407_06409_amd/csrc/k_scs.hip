@@ -9,7 +9,10 @@
 // the workloads (measured: diagonally scaled condition numbers below 12), so it
 // is factorised by a left-looking blocked Cholesky in its own slot of device
 // memory; the factor is kept for the adjoint solve.  A non-positive pivot is a
-// breakdown reported to the host.
+// breakdown reported to the host.  Kernels: k_pairlist (pair lists of an atom),
+// k_scs_dvec (d and the rows of d^T), k_scs_factor (assembly of B~,
+// factorisation and first solve), k_scs_residual and k_scs_solve (refinement of
+// the mixed path; the adjoint solve), k_scs_adjoint (pair gradients).
 //
 // Precision: the kernels are templated on the matrix type R.  R = double is the
 // plain FP64 path.  R = float is the mixed path: pair tensors, the matrix and
@@ -1556,7 +1559,7 @@ hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2ma
     return hipGetLastError();
 }
 
-hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
+hipError_t launch_scs_rhs(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed) {
     const dim3 grid(a.n, a.nw);
     // d and the rows of d^T; B~ itself is assembled by the factorisation kernel
     const size_t ld = dvec_lds_bytes(n1max, n2max);

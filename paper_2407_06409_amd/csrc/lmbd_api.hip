@@ -1006,7 +1006,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_pairlist(stream, sa, P.n1max, P.n2max));
     HIP_TRY(mark(1, 1));
     HIP_TRY(mark(2, 0));
-    HIP_TRY(launch_scs_assemble(stream, sa, P.n1max, P.n2max, mixed));
+    HIP_TRY(launch_scs_rhs(stream, sa, P.n1max, P.n2max, mixed));
     HIP_TRY(mark(2, 1));
     HIP_TRY(mark(3, 0));
     HIP_TRY(launch_scs_factor(stream, sa, P.n1max, mixed));   // assembles B~, then factorises it

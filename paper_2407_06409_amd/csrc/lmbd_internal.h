@@ -246,7 +246,7 @@ size_t scs_lds_bytes(int n1max, int n2max, bool mixed);
 size_t scs_assemble_lds_bytes(int n1max, int n2max);
 size_t pairlist_lds_bytes(int n1max, int n2max);
 // d (to its slot) and d^T (the rows appended to B~); B~ itself is assembled by the factorisation kernel
-hipError_t launch_scs_assemble(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
+hipError_t launch_scs_rhs(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
 hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 size_t scs_factor_lds_bytes(int n1max, bool mixed);
 hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
