@@ -460,8 +460,10 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, 
         acen = torch.tensor(central[fr.base[:fr.nK]], dtype=_DT, requires_grad=True)
         ek = _mbd_energy(fr, p, aloc, acen, fa, prm)
         e[k] = float(ek.detach())
-        (w[k] * ek).backward()
-        np.add.at(abar_c, fr.base[:fr.nK], acen.grad.numpy())
+        if ek.requires_grad:
+            (w[k] * ek).backward()
+        if acen.grad is not None:   # an atom with no neighbour in K uses no central polarisability
+            np.add.at(abar_c, fr.base[:fr.nK], acen.grad.numpy())
     t3 = time.perf_counter()
     n_c = 0
     for a in range(N):  # pass C
@@ -476,4 +478,6 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, 
     if timings is not None:
         timings.update(prepare_s=t1 - t0, central_s=t2 - t1, central_atoms=len(needed), pass_b_s=t3 - t2,
                        pass_b_atoms=len(ks), pass_c_s=t4 - t3, pass_c_atoms=n_c)
+    if pos_t.grad is None:   # no energy depends on a position (every atom isolated)
+        return e, np.zeros_like(st["pos"])
     return e, -pos_t.grad.numpy().copy()

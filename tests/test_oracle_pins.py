@@ -419,6 +419,26 @@ def test_forces_finite_difference_open_cluster():
     _fd_check(st, prm, [(0, 0), (3, 1), (7, 2), (11, 0)])
 
 
+def test_forces_with_an_isolated_atom():
+    """An atom with no neighbour inside the cutoffs has zero energy and zero
+    force, and its presence changes nothing for the others (its central
+    polarisability enters no energy, so its adjoint is zero, not missing)."""
+    a = _rand_cluster(6, 71, box=4.0)
+    prm = _params(3.0, 4.0)
+    far = np.array([[25.0, 0.0, 0.0]])
+    st = Structure(np.concatenate([a.pos, far]), np.concatenate([a.species, a.species[:1]]),
+                   np.concatenate([a.nu, a.nu[:1]]), None, np.zeros(3, bool))
+    e, f = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    ea, fa = oracle.lmbd_energy_forces(a, prm, SPECIES_TABLE)
+    assert e[-1] == 0.0 and np.all(f[-1] == 0.0)
+    assert np.allclose(e[:-1], ea, rtol=1e-12, atol=1e-16)
+    assert np.allclose(f[:-1], fa, rtol=1e-10, atol=1e-14)
+    assert np.allclose(f.sum(0), 0.0, atol=1e-12)
+    lone = Structure(far.copy(), a.species[:1], a.nu[:1], None, np.zeros(3, bool))
+    e1, f1 = oracle.lmbd_energy_forces(lone, prm, SPECIES_TABLE)
+    assert e1[0] == 0.0 and np.all(f1 == 0.0)
+
+
 @pytest.mark.slow
 def test_forces_finite_difference_periodic_box():
     st = C.hcno_box(20, 9, g_cm3=1.0)
