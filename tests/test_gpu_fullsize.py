@@ -66,6 +66,12 @@ def test_c1728_cutoff_6p8A_large_neighbourhoods_match_oracle():
     print(f"  max |dF| of the weighted one-atom sum over all atoms: {df:.3e} eV/A "
           f"(max |F| {np.abs(ref).max():.3e})", flush=True)
     assert df < 1e-8
+    # the mixed path (FP32 factors and solves, FP64 refinement) at the same sizes
+    mixed = gpu_run(st, cut, forces=True, weights=w, precision="mixed")
+    de_m = np.abs(mixed["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+    df_m = np.abs(mixed["forces"] - ref).max()
+    print(f"  mixed: max |dE| {de_m:.3e} eV/atom, max |dF| {df_m:.3e} eV/A", flush=True)
+    assert de_m < 1e-5 and df_m < 1e-4
 
 
 def test_hcno4096_energies_match_oracle():
