@@ -12,7 +12,11 @@ design notes of the repository):
     of ln(1 - x); the energy is negative (Sec. II.B MBD energy, Sec. III.A
     series expansion and polynomial-fit form).
   * frequencies are imaginary-axis; the quadrature (omega, weight) is an input;
-    the SCS is solved exactly at omega = 0 and at every quadrature node.
+    by default the SCS is solved exactly at omega = 0 and at every quadrature
+    node.  With scs_freq = "lorentz" it is solved at omega = 0 and omega_ref
+    only, and the blended polarisabilities at the nodes follow the two-point
+    Lorentzian of Sec. III.C (Eqs. alpha_SCS_freq and char-freq), applied to the
+    blended alpha~_i of the frame.
   * one cutoff per role: K1 = B(r_scs), K2 = B(2 r_scs) \\ B(r_scs) for the SCS
     (Sec. III.B), K = B(r_nbr) for the energy, f_LR cut at r_mbd1 for pairs that
     touch the central atom and r_mbd2 otherwise (Sec. III.A cutoff function).
@@ -51,6 +55,17 @@ class OracleParams:
     r_inner: float = 2.0
     n_max: Optional[int] = 6      # None => exact block logarithm (infinite body order)
     c_n: Optional[np.ndarray] = None  # length n_max + 1; None => c_n = -1/n for n >= 2
+    scs_freq: str = "exact"       # "exact": SCS at every node; "lorentz": two-point model (Sec. III.C)
+    omega_ref: Optional[float] = None  # reference frequency of the two-point model, Ha
+
+    def scs_omegas(self):
+        """Frequencies at which the local SCS systems are solved (omega = 0 first)."""
+        if self.scs_freq == "exact":
+            return np.concatenate([[0.0], self.omega])
+        if self.scs_freq == "lorentz":
+            assert self.omega_ref is not None and self.omega_ref > 0.0
+            return np.array([0.0, float(self.omega_ref)])
+        raise ValueError(f"unknown scs_freq {self.scs_freq!r}")
 
     def coefficients(self):
         if self.n_max is None:
@@ -289,6 +304,21 @@ def _scs_solve(frame, p, fa, prm):
 # Local MBD energy (Sec. III.A symmetrised local energy; Sec. III.B blend)
 # ----------------------------------------------------------------------------
 
+def lorentz_polarisabilities(a0, a_ref, omega, omega_ref):
+    """Two-point Lorentzian model of Sec. III.C: (..., len(omega)) polarisabilities.
+
+    Eq. (char-freq): the characteristic frequency omega~ = omega_ref /
+    sqrt(alpha~(0)/alpha~(omega_ref) - 1); Eq. (alpha_SCS_freq): alpha~(omega) =
+    alpha~(0) / (1 + (omega/omega~)^2).  Needs alpha~(0) >= alpha~(omega_ref) > 0
+    (a real characteristic frequency); ValueError otherwise.
+    """
+    if bool(torch.any(a_ref <= 0.0)) or bool(torch.any(a0 < a_ref)):
+        raise ValueError("SCS polarisability not decreasing between 0 and omega_ref")
+    om_t = omega_ref / torch.sqrt(a0 / a_ref - 1.0)
+    w = torch.as_tensor(np.asarray(omega, dtype=np.float64), dtype=_DT)
+    return a0[..., None] / (1.0 + (w / om_t[..., None]) ** 2)
+
+
 def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     """Energy of one central atom in eV.
 
@@ -316,6 +346,9 @@ def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
         else:
             alphas.append(alpha_cen_K[s])
     A = torch.stack(alphas, 0)                                        # (nK, nw)
+    if prm.scs_freq == "lorentz":
+        # columns: omega = 0, then the nodes from the two-point model
+        A = torch.cat([A[:, :1], lorentz_polarisabilities(A[:, 0], A[:, 1], prm.omega, prm.omega_ref)], 1)
 
     # SCS vdW radii and T_LR (Sec. II.B scaled radii; Sec. III.A f_LR)
     Rt = r0 * (A[:, 0] / a0) ** (1.0 / 3.0)
@@ -361,8 +394,7 @@ def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
 def _prepare(structure, prm, species_table):
     st = dict(pos=np.asarray(structure.pos, dtype=np.float64), cell=structure.cell,
               pbc=np.asarray(structure.pbc, dtype=bool))
-    omegas = np.concatenate([[0.0], prm.omega])
-    fa = free_atom_terms(species_table, structure.species, structure.nu, omegas)
+    fa = free_atom_terms(species_table, structure.species, structure.nu, prm.scs_omegas())
     images = _Images(st["pos"], st["cell"], st["pbc"], max(2.0 * prm.r_scs, prm.r_nbr))
     return st, fa, images
 
@@ -372,14 +404,14 @@ def _cell_tensor(st):
 
 
 def scs_central(structure, prm, species_table, atoms=None):
-    """Central SCS polarisabilities alpha~_I,k(w) for w in [0] + omega: (N, nw) array.
+    """Central SCS polarisabilities alpha~_I,k(w) at the SCS frequencies: (N, nw) array.
 
     The central polarisability of atom k is the k-th entry of its own local
     SCS solution (Sec. III.B, the central/local blend).
     """
     st, fa, images = _prepare(structure, prm, species_table)
     N = structure.n
-    nw = 1 + len(prm.omega)
+    nw = len(prm.scs_omegas())
     out = np.zeros((N, nw))
     pos_t = torch.as_tensor(st["pos"], dtype=_DT)
     cell_t = _cell_tensor(st)
@@ -435,7 +467,7 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, 
     t0 = time.perf_counter()
     st, fa, images = _prepare(structure, prm, species_table)
     N = structure.n
-    nw = 1 + len(prm.omega)
+    nw = len(prm.scs_omegas())
     w = np.ones(N) if weights is None else np.asarray(weights, dtype=np.float64)
     ks = list(range(N)) if atoms is None else list(atoms)
     frames = {}

@@ -446,6 +446,78 @@ def test_forces_finite_difference_periodic_box():
     _fd_check(st, prm, [(1, 0), (5, 2), (13, 1)])
 
 
+# ------------------------------------------- two-point Lorentzian SCS model
+
+OMEGA_REF = 0.5
+
+
+def test_lorentz_model_is_exact_for_unscreened_atoms():
+    """Without SCS coupling every polarisability is the TS Lorentzian, whose
+    characteristic frequency the two-point model recovers exactly (Sec. III.C,
+    Eqs. alpha_SCS_freq and char-freq), for any reference frequency."""
+    st = _rand_cluster(10, 81, box=6.0, dmin=1.5)
+    e0, f0 = oracle.lmbd_energy_forces(st, _params(NO_SCS, 4.0), SPECIES_TABLE)
+    for om_ref in (0.3, 1.7):
+        e, f = oracle.lmbd_energy_forces(st, _params(NO_SCS, 4.0, scs_freq="lorentz", omega_ref=om_ref),
+                                         SPECIES_TABLE)
+        assert np.allclose(e, e0, rtol=1e-12, atol=0)
+        assert np.allclose(f, f0, rtol=1e-10, atol=1e-14)
+
+
+def test_lorentz_model_interpolates_the_exact_solves():
+    """A quadrature with the single node omega_ref: the model takes the solved
+    alpha~(0) and alpha~(omega_ref) unchanged, so it equals the exact frequency
+    treatment, energies and forces (screened cluster, blend active)."""
+    st = _rand_cluster(12, 83, box=5.5, dmin=1.4)
+    grid = (np.array([OMEGA_REF]), np.array([0.9]))
+    e0, f0 = oracle.lmbd_energy_forces(st, _params(3.0, 4.0, grid=grid), SPECIES_TABLE)
+    e, f = oracle.lmbd_energy_forces(st, _params(3.0, 4.0, grid=grid, scs_freq="lorentz",
+                                                 omega_ref=OMEGA_REF), SPECIES_TABLE)
+    assert np.all(e0 != 0.0)
+    assert np.allclose(e, e0, rtol=1e-12, atol=0)
+    assert np.allclose(f, f0, rtol=1e-10, atol=1e-14)
+
+
+def test_lorentz_model_second_order_is_casimir_polder_of_screened_lorentzians():
+    """Screened dimer, n_max = 2: each atom's energy is -C6 f^2 / (2 r^6) with C6
+    the Casimir-Polder integral of the two model Lorentzians, whose static values
+    and characteristic frequencies come from independent SCS solves at 0 and
+    omega_ref (Eq. char-freq) and whose damping uses the screened radii."""
+    st = _open([[0, 0, 0], [1.6, 1.1, 0.5]], species=[C_IDX, SPECIES_INDEX["N"]], nu=[0.8, 0.95])
+    prm = _params(5.0, 8.0, grid=GRID200, n_max=2, scs_freq="lorentz", omega_ref=OMEGA_REF)
+    e = oracle.lmbd_energies(st, prm, SPECIES_TABLE)
+    a0, w0, R = _free(st)
+    x = st.pos / cf.BOHR
+    s0 = _solve_scs_fd(x, a0, R)
+    sr = _solve_scs_fd(x, a0 / (1.0 + (OMEGA_REF / w0) ** 2), R)
+    assert np.all(s0 > sr)
+    wt = OMEGA_REF / np.sqrt(s0 / sr - 1.0)
+    Rt = SPECIES_TABLE[st.species, 2] * (s0 / SPECIES_TABLE[st.species, 0]) ** (1.0 / 3.0)
+    r = np.linalg.norm(x[0] - x[1])
+    c6 = cf.c6_casimir_polder(s0[0], wt[0], s0[1], wt[1])
+    ref = -0.5 * c6 * cf.fermi(r, 0.83 * (Rt[0] + Rt[1])) ** 2 / r ** 6 * cf.HARTREE
+    assert np.allclose(e, [ref, ref], rtol=1e-10, atol=0)
+    # the exact frequency treatment differs: the screened dimer is not one Lorentzian
+    ex = oracle.lmbd_energies(st, _params(5.0, 8.0, grid=GRID200, n_max=2), SPECIES_TABLE)
+    assert abs(ex[0] / e[0] - 1.0) > 1e-6
+
+
+def test_lorentz_model_rejects_rising_polarisability():
+    """A real characteristic frequency needs alpha~(0) >= alpha~(omega_ref) > 0."""
+    import torch
+    a0 = torch.tensor([10.0, 5.0], dtype=torch.float64)
+    with pytest.raises(ValueError):
+        L.lorentz_polarisabilities(a0, torch.tensor([9.0, 6.0], dtype=torch.float64), [0.1], 0.5)
+    with pytest.raises(ValueError):
+        L.lorentz_polarisabilities(a0, torch.tensor([9.0, -1.0], dtype=torch.float64), [0.1], 0.5)
+
+
+def test_lorentz_model_forces_finite_difference():
+    st = _rand_cluster(12, 61, box=5.5, dmin=1.4)
+    prm = _params(3.0, 4.0, scs_freq="lorentz", omega_ref=OMEGA_REF)
+    _fd_check(st, prm, [(0, 0), (3, 1), (7, 2), (11, 0)])
+
+
 # ------------------------------------------------------------------ neighbours
 
 def test_neighbourhood_matches_brute_force_images():
