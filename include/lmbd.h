@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LMBD_ABI_VERSION 2
+#define LMBD_ABI_VERSION 3
 
 typedef enum lmbd_status {
     LMBD_OK = 0,
@@ -49,6 +49,8 @@ typedef enum lmbd_status {
 
 /* precision of the hot path */
 enum { LMBD_FP64 = 0, LMBD_MIXED = 1 };
+/* frequency treatment of the SCS polarisabilities */
+enum { LMBD_SCS_EXACT = 0, LMBD_SCS_LORENTZ = 1 };
 /* where the caller's arrays live */
 enum { LMBD_HOST = 0, LMBD_DEVICE = 1 };
 
@@ -71,6 +73,16 @@ typedef struct lmbd_species {
  *  n_freq, omega, weight : host arrays; imaginary-frequency nodes (Ha) and weights of
  *                 int_0^inf d omega; the library applies the 1/(2 pi) itself
  *  precision    : LMBD_FP64 or LMBD_MIXED
+ *  scs_freq     : LMBD_SCS_EXACT solves the local SCS systems at omega = 0 and at
+ *                 every node; LMBD_SCS_LORENTZ solves them at omega = 0 and omega_ref
+ *                 only and gives the blended polarisability of every site the
+ *                 two-point Lorentzian form of Sec. III.C (Eqs. alpha_SCS_freq,
+ *                 char-freq): alpha(w) = alpha(0) / (1 + (w / w~)^2), with w~ fixed
+ *                 by alpha(0) and alpha(omega_ref).  Such a site needs
+ *                 alpha(0) >= alpha(omega_ref) > 0, else the call fails with
+ *                 LMBD_E_SCS_BREAKDOWN.
+ *  omega_ref    : reference frequency of LMBD_SCS_LORENTZ (Ha, > 0; the paper leaves
+ *                 it empirical); ignored by LMBD_SCS_EXACT
  * Cutoffs are per structure (lmbd_structure). */
 typedef struct lmbd_params {
     double beta;
@@ -83,6 +95,8 @@ typedef struct lmbd_params {
     const double* omega;
     const double* weight;
     int32_t precision;
+    int32_t scs_freq;
+    double omega_ref;
 } lmbd_params;
 
 /* One structure of a batch.  Pointers are host or device pointers according to

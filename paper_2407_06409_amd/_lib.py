@@ -5,7 +5,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblmbd.so")
 
+ABI_VERSION = 3   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
 LMBD_FP64, LMBD_MIXED = 0, 1
+LMBD_SCS_EXACT, LMBD_SCS_LORENTZ = 0, 1
 LMBD_HOST, LMBD_DEVICE = 0, 1
 
 STATUS = {
@@ -26,6 +28,7 @@ class Params(ctypes.Structure):
         ("beta", ctypes.c_double), ("damp_d", ctypes.c_double), ("r_buf", ctypes.c_double),
         ("r_inner", ctypes.c_double), ("n_max", ctypes.c_int32), ("c_n", _dp),
         ("n_freq", ctypes.c_int32), ("omega", _dp), ("weight", _dp), ("precision", ctypes.c_int32),
+        ("scs_freq", ctypes.c_int32), ("omega_ref", ctypes.c_double),
     ]
 
 
@@ -76,6 +79,8 @@ def lib():
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_06409_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     L.lmbd_abi_version.restype = ctypes.c_int32
+    if L.lmbd_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI {L.lmbd_abi_version()}, expected {ABI_VERSION}: rebuild it")
     L.lmbd_status_string.restype = ctypes.c_char_p
     L.lmbd_status_string.argtypes = [ctypes.c_int]
     L.lmbd_last_error.restype = ctypes.c_char_p

@@ -25,6 +25,8 @@ class MethodParams:
     n_max: int = 6
     c_n: Optional[Sequence[float]] = None
     precision: str = "fp64"
+    scs_freq: str = "exact"      # "exact" or "lorentz" (two-point model, Sec. III.C)
+    omega_ref: float = 0.0       # reference frequency of the two-point model, Ha
 
     def to_c(self):
         om = np.ascontiguousarray(self.omega, dtype=np.float64)
@@ -37,7 +39,9 @@ class MethodParams:
         p = C.Params(self.beta, self.damp_d, self.r_buf, self.r_inner, int(self.n_max),
                      cn.ctypes.data_as(C._dp) if cn is not None else None, int(om.shape[0]),
                      om.ctypes.data_as(C._dp), wt.ctypes.data_as(C._dp),
-                     C.LMBD_MIXED if self.precision == "mixed" else C.LMBD_FP64)
+                     C.LMBD_MIXED if self.precision == "mixed" else C.LMBD_FP64,
+                     {"exact": C.LMBD_SCS_EXACT, "lorentz": C.LMBD_SCS_LORENTZ}[self.scs_freq],
+                     float(self.omega_ref))
         return p, keep
 
 

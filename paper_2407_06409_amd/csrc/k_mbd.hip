@@ -18,6 +18,13 @@
 // then contracted pair by pair with dT_LR/dr and dT_LR/dS~, and pushed
 // through the blend (local part to this atom's SCS, central part scattered to
 // the neighbours' own SCS through a per-site contribution buffer).
+//
+// Two-point frequency model (Sec. III.C, Eqs. alpha_SCS_freq and char-freq):
+// the SCS is solved at 0 and w_ref only; the blend gives a0 = alpha~_i(0) and
+// ar = alpha~_i(w_ref), and alpha~_i(w) = a0 / (1 + (w / w~_i)^2) with
+// w~_i = w_ref / sqrt(a0 / ar - 1), evaluated as a0 ar / (rho a0 + (1 - rho) ar),
+// rho = (w / w_ref)^2.  Its adjoint: d alpha/d a0 = (1 - rho) (alpha / a0)^2 and
+// d alpha/d ar = rho (alpha / ar)^2.
 #include <algorithm>
 #include <type_traits>
 
@@ -33,7 +40,9 @@ __host__ __device__ inline size_t al4(size_t x) { return (x + 3) / 4 * 4; }
 struct MbdLds {
     double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu;
 };
-__device__ inline MbdLds mbd_lds(double* b, int nk, int nw, int nq, int n_max) {
+// sa and ab hold every frequency of the energy: 0 and the nq nodes.
+__device__ inline MbdLds mbd_lds(double* b, int nk, int nq, int n_max) {
+    const int nw = nq + 1;
     MbdLds L;
     L.px = b;
     L.py = L.px + nk;
@@ -51,8 +60,8 @@ __device__ inline MbdLds mbd_lds(double* b, int nk, int nw, int nq, int n_max) {
     return L;
 }
 
-size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max) {
-    const size_t nk = nkmax;
+size_t mbd_lds_bytes(int nkmax, int nq, int n_max) {
+    const size_t nk = nkmax, nw = (size_t)nq + 1;
     return sizeof(double) * (3 * nk + nk * nw + nk * (size_t)std::max(nq, 12) + 3 * nk + nk * nw + 4 * nk +
                              3 * nk + (size_t)(n_max + 1) * nq);
 }
@@ -217,9 +226,10 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     const int nK = cnt.nK, n1 = cnt.n1, nall = cnt.n_all;
     const int N3 = 3 * nK;
     const int nw = a.nw, nq = a.nq, ncol = a.ncol, n_max = a.n_max;
+    const int nwe = nq + 1;   // row stride of L.sa and L.ab (nw is that of the SCS arrays)
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rs = SI.r_scs;
-    MbdLds L = mbd_lds(lds, nkmax, nw, nq, n_max);
+    MbdLds L = mbd_lds(lds, nkmax, nq, n_max);
     const Site* S = a.sites + a.site_off[k];
     const double* aloc = a.alpha_loc + a.aloc_off[k];
     W* T = static_cast<W*>(a.work) + a.work_off[k];
@@ -251,13 +261,28 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
         }
         L.fs[s] = fsv;
         L.dfs[s] = dfsv;
-        for (int w = 0; w < nw; ++w) {
-            const double al = (s < n1) ? aloc[(size_t)s * nw + w] : 0.0;
-            const double v = (s == 0) ? al : (1.0 - fsv) * al + fsv * cen[w];
-            L.sa[(size_t)s * nw + w] = v;
-            if (w > 0) L.sqa[(size_t)s * nq + (w - 1)] = sqrt(v);
+        if (a.lorentz) {
+            const double a0 = (s == 0) ? aloc[0] : (s < n1) ? (1.0 - fsv) * aloc[(size_t)s * nw] + fsv * cen[0] : cen[0];
+            const double ar = (s == 0) ? aloc[1] : (s < n1) ? (1.0 - fsv) * aloc[(size_t)s * nw + 1] + fsv * cen[1] : cen[1];
+            if (!(ar > 0.0 && a0 >= ar)) {   // no real characteristic frequency
+                atomicOr(a.err, 8);
+                atomicMin(a.err_atom, k);
+            }
+            L.sa[(size_t)s * nwe] = a0;
+            for (int q = 0; q < nq; ++q) {
+                const double v = a0 * ar / (a.rho[q] * a0 + (1.0 - a.rho[q]) * ar);
+                L.sa[(size_t)s * nwe + 1 + q] = v;
+                L.sqa[(size_t)s * nq + q] = sqrt(v);
+            }
+        } else {
+            for (int w = 0; w < nw; ++w) {
+                const double al = (s < n1) ? aloc[(size_t)s * nw + w] : 0.0;
+                const double v = (s == 0) ? al : (1.0 - fsv) * al + fsv * cen[w];
+                L.sa[(size_t)s * nwe + w] = v;
+                if (w > 0) L.sqa[(size_t)s * nq + (w - 1)] = sqrt(v);
+            }
         }
-        L.Rt[s] = a.r0v[st.base] * cbrt(L.sa[(size_t)s * nw] / a.a0v[st.base]);
+        L.Rt[s] = a.r0v[st.base] * cbrt(L.sa[(size_t)s * nwe] / a.a0v[st.base]);
     }
     __syncthreads();
 
@@ -349,8 +374,8 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     if (!a.forces) return;
 
     // --- dE/d alpha~_i(w_q) from the moments (row-local Krylov products)
-    for (int t = tid; t < nK * nw; t += blockDim.x) {
-        const int i = t / nw, w = t % nw;
+    for (int t = tid; t < nK * nwe; t += blockDim.x) {
+        const int i = t / nwe, w = t % nwe;
         double v = 0.0;
         if (w > 0) {
             const int q = w - 1;
@@ -366,7 +391,7 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
                 }
                 s += a.coef[n] * sn;
             }
-            v = wk * a.wq[q] * s / L.sa[(size_t)i * nw + w];
+            v = wk * a.wq[q] * s / L.sa[(size_t)i * nwe + w];
         }
         L.ab[t] = v;
     }
@@ -459,12 +484,26 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
             Rb += L.rb[(size_t)part * nK + i];
         }
         // R~_i = R0 (alpha~_i(0)/alpha0)^(1/3): dR~/d alpha~(0) = R~ / (3 alpha~(0))
-        L.ab[(size_t)i * nw] += Rb * L.Rt[i] / (3.0 * L.sa[(size_t)i * nw]);
+        L.ab[(size_t)i * nwe] += Rb * L.Rt[i] / (3.0 * L.sa[(size_t)i * nwe]);
         const Site st = S[i];
         const double* cen = a.alpha_loc + a.aloc_off[st.base];
+        if (a.lorentz) {
+            // back through the two-point model onto alpha~_i(0) and alpha~_i(w_ref)
+            const double fsv = L.fs[i];
+            const double a0 = L.sa[(size_t)i * nwe];
+            const double ar = (i == 0) ? aloc[1] : (i < n1) ? (1.0 - fsv) * aloc[(size_t)i * nw + 1] + fsv * cen[1] : cen[1];
+            double b0 = L.ab[(size_t)i * nwe], br = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                const double v = L.sa[(size_t)i * nwe + 1 + q], g = L.ab[(size_t)i * nwe + 1 + q];
+                b0 += g * (1.0 - a.rho[q]) * (v / a0) * (v / a0);
+                br += g * a.rho[q] * (v / ar) * (v / ar);
+            }
+            L.ab[(size_t)i * nwe] = b0;
+            L.ab[(size_t)i * nwe + 1] = br;
+        }
         double gf = 0.0;  // sum_w abar_i(w) (alpha~_I,i(w) - alpha~_K,i(w))
         for (int w = 0; w < nw; ++w) {
-            const double ai = L.ab[(size_t)i * nw + w];
+            const double ai = L.ab[(size_t)i * nwe + w];
             if (i == 0) {
                 abl[w] = ai;
                 cap[w] = 0.0;
@@ -519,7 +558,7 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
 }
 
 hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed) {
-    const size_t lds = mbd_lds_bytes(nkmax, a.nw, a.nq, a.n_max);
+    const size_t lds = mbd_lds_bytes(nkmax, a.nq, a.n_max);
     if (mixed)
         hipLaunchKernelGGL(k_mbd<float>, dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
     else

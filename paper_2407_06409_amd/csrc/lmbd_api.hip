@@ -149,6 +149,9 @@ lmbd_status fail(lmbd_context* ctx, lmbd_status s, const std::string& msg) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// number of frequencies at which the local SCS systems are solved
+int scs_freq_count(const lmbd_params* p) { return p->scs_freq == LMBD_SCS_LORENTZ ? 2 : p->n_freq + 1; }
+
 lmbd_status check_params(lmbd_context* ctx, const lmbd_params* p) {
     if (!p) return fail(ctx, LMBD_E_INVALID_ARG, "params is NULL");
     if (!finite_pos(p->beta) || !finite_pos(p->damp_d) || !finite_pos(p->r_buf) || !finite_pos(p->r_inner))
@@ -165,6 +168,10 @@ lmbd_status check_params(lmbd_context* ctx, const lmbd_params* p) {
             if (!std::isfinite(p->c_n[i])) return fail(ctx, LMBD_E_INVALID_ARG, "non-finite c_n");
     if (p->precision != LMBD_FP64 && p->precision != LMBD_MIXED)
         return fail(ctx, LMBD_E_INVALID_ARG, "unknown precision");
+    if (p->scs_freq != LMBD_SCS_EXACT && p->scs_freq != LMBD_SCS_LORENTZ)
+        return fail(ctx, LMBD_E_INVALID_ARG, "unknown SCS frequency treatment");
+    if (p->scs_freq == LMBD_SCS_LORENTZ && !finite_pos(p->omega_ref))
+        return fail(ctx, LMBD_E_INVALID_ARG, "omega_ref must be positive");
     return LMBD_OK;
 }
 
@@ -696,7 +703,7 @@ lmbd_status layout_bytes(const lmbd_params* params, int n_species, const std::ve
         forces = forces || p->forces;
     }
     if (cnt.empty() || cnt.size() > (size_t)(INT32_MAX / 8)) return LMBD_E_UNSUPPORTED;
-    const int nw = params->n_freq + 1;
+    const int nw = scs_freq_count(params);
     PreDims pd;
     pd.N = (int64_t)cnt.size();
     pd.n_structs = (int)parts.size();
@@ -768,7 +775,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     }
     if (N64 > INT32_MAX / 8) return fail(ctx, LMBD_E_UNSUPPORTED, "too many atoms in one call");
     const int N = (int)N64;
-    const int nq = params->n_freq, nw = nq + 1, ncol = 3 * nq, n_max = params->n_max;
+    const int nq = params->n_freq, nw = scs_freq_count(params), ncol = 3 * nq, n_max = params->n_max;
+    const bool lorentz = params->scs_freq == LMBD_SCS_LORENTZ;
     const bool mixed = params->precision == LMBD_MIXED;
     const size_t wsz = mixed ? sizeof(float) : sizeof(double);  // matrix and workspace element size
     HIP_TRY(hipSetDevice(ctx->device));
@@ -850,9 +858,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         for (int i = 0; i < n; ++i) atom_struct[off + i] = s;
         off += n;
     }
-    std::vector<double> omegas(nw);
+    std::vector<double> omegas(nw);   // SCS frequencies: 0, then omega_ref or every node
     omegas[0] = 0.0;
-    for (int q = 0; q < nq; ++q) omegas[q + 1] = params->omega[q];
+    if (lorentz)
+        omegas[1] = params->omega_ref;
+    else
+        for (int q = 0; q < nq; ++q) omegas[q + 1] = params->omega[q];
     std::vector<double> tab(3 * (size_t)n_species);
     for (int i = 0; i < n_species; ++i) {
         tab[3 * i] = species_table[i].alpha0;
@@ -923,7 +934,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
         ctx->lds_limit = lds_limit;
     }
-    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nw, nq, n_max) > (size_t)lds_limit ||
+    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nq, n_max) > (size_t)lds_limit ||
         scs_factor_lds_bytes(P.n1max, mixed) > (size_t)lds_limit || scs_assemble_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit ||
         pairlist_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit)
         return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood needs more LDS than the device offers (" +
@@ -1039,6 +1050,11 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.r_buf = sa.r_buf;
     for (int i = 0; i <= n_max; ++i) ma.coef[i] = (i < 2) ? 0.0 : (params->c_n ? params->c_n[i] : -1.0 / i);
     for (int q = 0; q < nq; ++q) ma.wq[q] = params->weight[q] * kHartree / (2.0 * kPi);
+    ma.lorentz = lorentz ? 1 : 0;
+    if (lorentz)
+        for (int q = 0; q < nq; ++q) ma.rho[q] = (params->omega[q] / params->omega_ref) * (params->omega[q] / params->omega_ref);
+    ma.err = err;
+    ma.err_atom = err_atom;
     ma.e_weight = as<double>(ctx->in_w);
     ma.e_atom = as<double>(ctx->e_out);
     ma.work = ctx->work.p;
@@ -1099,6 +1115,10 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if (flags[0] & 4)
         return fail(ctx, LMBD_E_SCS_BREAKDOWN,
                     "non-positive pivot in the local SCS matrix of atom " + std::to_string(flags[1]));
+    if (flags[0] & 8)
+        return fail(ctx, LMBD_E_SCS_BREAKDOWN,
+                    "SCS polarisability not decreasing between 0 and omega_ref in the frame of atom " +
+                        std::to_string(flags[1]));
     return LMBD_OK;
 }
 

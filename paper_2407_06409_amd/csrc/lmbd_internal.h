@@ -203,7 +203,7 @@ struct ScsArgs {
 };
 
 struct MbdArgs {
-    int n, nw, nq, n_max, ncol, mmax;
+    int n, nw, nq, n_max, ncol, mmax;   // nw: SCS frequencies (stride of the polarisability arrays)
     const Counts* counts;
     const int32_t* order;      // workgroup x takes atom order[x] (largest neighbourhoods first)
     const int64_t* site_off;
@@ -217,6 +217,10 @@ struct MbdArgs {
     double beta, damp_d, r_buf;
     double coef[kMaxNmax + 1];
     double wq[kMaxFreq];       // quadrature weight * Hartree / (2 pi): eV per unit integrand
+    int lorentz;               // SCS solved at 0 and omega_ref only (nw = 2): two-point Lorentzian at the nodes
+    double rho[kMaxFreq];      // two-point model: (omega_q / omega_ref)^2
+    int* err;                  // bit 8: a polarisability rises between 0 and omega_ref
+    int* err_atom;             // lowest atom whose frame raised an error
     const double* e_weight;    // [n] or null
     double* e_atom;            // [n]
     void* work;                // per atom T (N3^2), U (mmax N3 ncol), V (N3 ncol), with forces P^T and
@@ -253,7 +257,7 @@ hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mi
 hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
-size_t mbd_lds_bytes(int nkmax, int nw, int nq, int n_max);
+size_t mbd_lds_bytes(int nkmax, int nq, int n_max);
 hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,

@@ -7,28 +7,30 @@ from workloads import SPECIES_TABLE, frequency_grid, DEFAULT_PARAMS
 GRID = frequency_grid(DEFAULT_PARAMS["n_freq"])
 
 
-def method_params(n_max=6, grid=GRID, precision="fp64"):
+def method_params(n_max=6, grid=GRID, precision="fp64", scs_freq="exact", omega_ref=0.0):
     from paper_2407_06409_amd import MethodParams
     return MethodParams(omega=grid[0], weight=grid[1], beta=DEFAULT_PARAMS["beta"],
                         damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
-                        r_inner=DEFAULT_PARAMS["r_inner"], n_max=n_max, precision=precision)
+                        r_inner=DEFAULT_PARAMS["r_inner"], n_max=n_max, precision=precision,
+                        scs_freq=scs_freq, omega_ref=omega_ref)
 
 
-def oracle_params(cut, n_max=6, grid=GRID):
+def oracle_params(cut, n_max=6, grid=GRID, scs_freq="exact", omega_ref=None):
     import oracle
     return oracle.make_params(cut, grid[0], grid[1], n_max=n_max, beta=DEFAULT_PARAMS["beta"],
                               damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
-                              r_inner=DEFAULT_PARAMS["r_inner"])
+                              r_inner=DEFAULT_PARAMS["r_inner"], scs_freq=scs_freq, omega_ref=omega_ref)
 
 
-def gpu_run(st, cut, n_max=6, forces=True, weights=None, grid=GRID, ctx=None, precision="fp64"):
+def gpu_run(st, cut, n_max=6, forces=True, weights=None, grid=GRID, ctx=None, precision="fp64",
+            scs_freq="exact", omega_ref=0.0):
     from paper_2407_06409_amd import compute
     dev = torch.device("cuda:0")
     pos = torch.as_tensor(st.pos, dtype=torch.float64, device=dev)
     sp = torch.as_tensor(st.species, dtype=torch.int32, device=dev)
     nu = torch.as_tensor(st.nu, dtype=torch.float64, device=dev)
     w = None if weights is None else torch.as_tensor(weights, dtype=torch.float64, device=dev)
-    out = compute(pos, sp, nu, cutoffs=cut, params=method_params(n_max, grid, precision),
+    out = compute(pos, sp, nu, cutoffs=cut, params=method_params(n_max, grid, precision, scs_freq, omega_ref),
                   species_table=SPECIES_TABLE, cell=st.cell, pbc=tuple(int(x) for x in st.pbc),
                   e_weight=w, forces=forces, ctx=ctx, want_alpha=True)
     torch.cuda.synchronize()

@@ -43,7 +43,11 @@ def test_library_exports_every_declared_function(lib):
 
 
 def test_calls_that_need_no_device(lib):
-    assert lib.lmbd_abi_version() == 2
+    from paper_2407_06409_amd import _lib
+    hdr = open(os.path.join(ROOT, "include", "lmbd.h")).read()
+    assert lib.lmbd_abi_version() == _lib.ABI_VERSION == int(re.search(r"LMBD_ABI_VERSION (\d+)", hdr).group(1))
+    # the ctypes mirror of lmbd_params ends with the two-point model's fields
+    assert [f for f, _ in _lib.Params._fields_][-2:] == ["scs_freq", "omega_ref"]
     assert lib.lmbd_status_string(0) == b"ok"
     assert lib.lmbd_status_string(3) == b"request exceeds the memory budget"
     assert lib.lmbd_status_string(7) == b"request cancelled"

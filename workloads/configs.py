@@ -21,6 +21,9 @@ from .grid import frequency_grid
 
 # Method parameters that the workloads fix (values as inputs; each side builds its own struct).
 DEFAULT_PARAMS = dict(beta=0.83, damp_d=6.0, r_buf=0.5, r_inner=2.0, n_max=6, n_freq=12)
+# reference frequency of the two-point SCS frequency model (Ha): the scale of the
+# frequency grid, which has half of its nodes below it
+OMEGA_REF = 0.5
 
 HCNO = {"H": 0.5, "C": 0.3, "N": 0.1, "O": 0.1}
 
