@@ -19,7 +19,9 @@ constexpr double kSqrt2OverPi = 0.79788456080286535588;    // sqrt(2/pi)
 constexpr int kMaxFreq = 33;       // omega = 0 plus up to 32 quadrature nodes
 constexpr int kMaxNmax = 12;       // highest body order
 constexpr int kMaxN1 = 160;        // atoms in K1 (r < r_scs), central atom included
-constexpr int kMaxNK = 160;        // atoms in K (r < r_nbr), central atom included
+constexpr int kMaxNK = 400;        // sites in K (r < r_nbr), central atom included; the MBD kernel's LDS,
+                                   // 8 (3 nq + 15) bytes per site for nq >= 12 nodes, caps it lower for
+                                   // long grids (the host checks that limit too)
 constexpr int kMaxSites = 4096;    // sites in the largest ball, central atom included
 
 // One site of a neighbourhood: an atom or one of its periodic images, stored
