@@ -8,6 +8,7 @@ LIB_PATH = os.path.join(HERE, "liblmbd.so")
 ABI_VERSION = 3   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
 LMBD_FP64, LMBD_MIXED = 0, 1
 LMBD_SCS_EXACT, LMBD_SCS_LORENTZ = 0, 1
+LMBD_MBD_AUTO, LMBD_MBD_DENSE, LMBD_MBD_SPARSE = 0, 1, 2
 LMBD_HOST, LMBD_DEVICE = 0, 1
 
 STATUS = {
@@ -102,6 +103,8 @@ def lib():
     L.lmbd_estimate_footprint.restype = ctypes.c_int
     L.lmbd_estimate_footprint.argtypes = [ctypes.POINTER(Params), ctypes.c_int32,
                                           ctypes.POINTER(StructureDesc), ctypes.POINTER(ctypes.c_size_t)]
+    L.lmbd_set_mbd_product.restype = ctypes.c_int
+    L.lmbd_set_mbd_product.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.lmbd_set_profiling.restype = ctypes.c_int
     L.lmbd_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.lmbd_stage_times.restype = ctypes.c_int
@@ -131,5 +134,5 @@ EXPORTED = ["lmbd_abi_version", "lmbd_create", "lmbd_destroy", "lmbd_set_memory_
             "lmbd_compute_batch", "lmbd_compute", "lmbd_estimate_footprint", "lmbd_status_string",
             "lmbd_last_error", "lmbd_set_profiling", "lmbd_stage_times", "lmbd_stage_name",
             "lmbd_server_create", "lmbd_server_destroy", "lmbd_submit", "lmbd_poll", "lmbd_wait",
-            "lmbd_release", "lmbd_server_get_stats"]
+            "lmbd_release", "lmbd_server_get_stats", "lmbd_set_mbd_product"]
 N_STAGES = 10

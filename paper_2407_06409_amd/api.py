@@ -72,6 +72,13 @@ class Context:
         if st != 0:
             raise C.LmbdError(st)
 
+    def set_mbd_product(self, mode: str = "auto"):
+        """'auto', 'dense' (T_LR stored, matrix-core products) or 'sparse' (coupled pairs only)."""
+        code = {"auto": C.LMBD_MBD_AUTO, "dense": C.LMBD_MBD_DENSE, "sparse": C.LMBD_MBD_SPARSE}[mode]
+        st = self.lib.lmbd_set_mbd_product(self.handle, code)
+        if st != 0:
+            raise C.LmbdError(st, self.last_error())
+
     def set_profiling(self, on: bool = True):
         st = self.lib.lmbd_set_profiling(self.handle, 1 if on else 0)
         if st != 0:

@@ -217,8 +217,57 @@ __device__ inline LrPair<P> lr_pair(P r, P S, P damp_d, P rcut, P rb) {
 // balances them better than four (measured 4.55 -> 4.42 ms FP64, 3.07 -> 2.62
 // ms FP32 on 1,728 C atoms; 384, 768 and 1,024 threads were slower)
 constexpr int kMbdThreads = 512;
-template <typename W>
-__global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
+
+// Value of `x` in lane l (l uniform over the wavefront).
+__device__ inline double read_lane(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sums over the 64 lanes of nine per-lane values, returned to every lane.  A
+// transposed butterfly: at the exchanges over lane bits 5, 4, 3 and 2 a lane keeps
+// half of the (zero-padded to 16) values it carries and sends the other half, so
+// lane l ends with value 8 b5 + 4 b4 + 2 b3 + b2 (b_n: bit n of l) summed over its
+// 16 partners; two plain exchanges finish the sum and one lane per value gives it
+// out: 17 exchanges instead of 54.
+__device__ inline void wave_sum9(const double (&v)[9], double (&out)[9]) {
+    const int lane = threadIdx.x & 63;
+    double a[8], b[4], c[2];
+    bool hi = lane & 32;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const double lo_v = v[t], hi_v = (t == 0) ? v[8] : 0.0;
+        a[t] = (hi ? hi_v : lo_v) + __shfl_xor(hi ? lo_v : hi_v, 32);
+    }
+    hi = lane & 16;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) b[t] = (hi ? a[4 + t] : a[t]) + __shfl_xor(hi ? a[t] : a[4 + t], 16);
+    hi = lane & 8;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) c[t] = (hi ? b[2 + t] : b[t]) + __shfl_xor(hi ? b[t] : b[2 + t], 8);
+    hi = lane & 4;
+    double d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 4);
+    d += __shfl_xor(d, 2);
+    d += __shfl_xor(d, 1);
+#pragma unroll
+    for (int x = 0; x < 9; ++x)
+        out[x] = read_lane(d, ((x >> 3) & 1) << 5 | ((x >> 2) & 1) << 4 | ((x >> 1) & 1) << 3 | (x & 1) << 2);
+}
+
+// SP = false: T_LR is stored dense and every product runs on the matrix cores.
+// SP = true (two-radius regime, Sec. III.A: a site couples to the central atom up
+// to r_MBD,1 but to the others only up to r_MBD,2, so block rows other than the
+// central one are sparse): T_LR is never stored; a wavefront takes one block row,
+// its lanes test 64 candidate sites at a time, the coupled ones are walked by the
+// whole wavefront together (lanes over the Krylov columns), and Tbar is formed
+// only for coupled pairs, each 3x3 block as nine wavefront-wide dot products.
+// The sparse form is bound by the latency of its gathers rather than by arithmetic:
+// it runs 1,024 threads (four wavefronts per SIMD at its register count) to hide it.
+constexpr int kMbdThreadsSparse = 1024;
+template <typename W, bool SP>
+__global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     extern __shared__ double lds[];
     const int k = a.order[blockIdx.x];
     const int tid = threadIdx.x;
@@ -230,6 +279,7 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rs = SI.r_scs;
     MbdLds L = mbd_lds(lds, nkmax, nq, n_max);
+    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const Site* S = a.sites + a.site_off[k];
     const double* aloc = a.alpha_loc + a.aloc_off[k];
     W* T = static_cast<W*>(a.work) + a.work_off[k];
@@ -290,6 +340,7 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     // per thread, consecutive threads along a block row, so that the rows are
     // written in contiguous runs (each unordered pair is evaluated from both
     // ends: the block is the same for (i, j) and (j, i)).
+    if constexpr (!SP) {
     for (int p = tid; p < nK * nK; p += blockDim.x) {
         const int i = p / nK, j = p % nK;
         double blk[9] = {};
@@ -315,9 +366,118 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
         V2[(size_t)(e / (N3p - N3)) * N3p + N3 + e % (N3p - N3)] = W(0);
     }
     __syncthreads();
+    }
+
+    // sparse form: coefficients of the pair (i, j), T_LR,ij = A rhat rhat^T + B I, when it couples
+    auto couple = [&](int i, int j, W& A, W& B, double rh[3]) -> bool {
+        if (j >= nK || j == i) return false;
+        const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+        const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
+        if (!(r < rcut)) return false;
+        const LrPair<W> t = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut), W(a.r_buf));
+        A = t.A;
+        B = t.B;
+        rh[0] = v[0] / r;
+        rh[1] = v[1] / r;
+        rh[2] = v[2] / r;
+        return true;
+    };
+    // sparse form: the coupled sites of every block row and their coefficients, found
+    // once per atom and kept in the space of the dense T (unused here): row i holds
+    // up to nK entries at [i nK, i nK + cnt_i); (4 + 5 sizeof(W)) nK^2 + 4 nK bytes fit
+    // in the 9 nK^2 sizeof(W) of the dense T
+    const size_t NN = (size_t)nK * nK;
+    W* const pA = T;
+    W* const pB = pA + NN;
+    W* const pR0 = pB + NN;
+    W* const pR1 = pR0 + NN;
+    W* const pR2 = pR1 + NN;
+    int* const pj = reinterpret_cast<int*>(pR2 + NN);
+    int* const pcnt = pj + NN;
+    if constexpr (SP) {
+        for (int i = wave; i < nK; i += nwave) {
+            int n = 0;
+            for (int j0 = 0; j0 < nK; j0 += 64) {
+                W A = W(0), B = W(0);
+                double rh[3] = {0.0, 0.0, 0.0};
+                const bool in = couple(i, j0 + lane, A, B, rh);
+                const unsigned long long mask = __ballot(in);
+                if (in) {
+                    const size_t e = (size_t)i * nK + n + __popcll(mask & ((1ull << lane) - 1ull));
+                    pj[e] = j0 + lane;
+                    pA[e] = A;
+                    pB[e] = B;
+                    pR0[e] = W(rh[0]);
+                    pR1[e] = W(rh[1]);
+                    pR2[e] = W(rh[2]);
+                }
+                n += __popcll(mask);
+            }
+            if (lane == 0) pcnt[i] = n;
+        }
+        __syncthreads();
+    }
+    // sparse form: Uout = D T D Uin, one block row (and 64 columns) per wavefront, lanes over
+    // the columns, four coupled sites per step; the loads use in-bounds indices (entry 0 of the
+    // row, column 0) with a zero factor instead of a branch, so that they overlap
+    auto sparse_product = [&](const W* __restrict__ Uin, W* __restrict__ Uout) {
+        for (int it = wave; it < nK * ((ncol + 63) / 64); it += nwave) {
+            const int i = it % nK, col = (it / nK) * 64 + lane, q = col / 3;
+            const int cs = col < ncol ? col : 0, qs = cs / 3;
+            const int n = pcnt[i];
+            const size_t e0 = (size_t)i * nK;
+            W acc0 = W(0), acc1 = W(0), acc2 = W(0);
+            for (int s0 = 0; s0 < n; s0 += 4) {
+                W x[4][3], Aj[4], Bj[4], r0[4], r1[4], r2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = s0 + u < n;
+                    const size_t e = e0 + (ok ? s0 + u : 0);
+                    const int j = pj[e];
+                    Aj[u] = pA[e];
+                    Bj[u] = pB[e];
+                    r0[u] = pR0[e];
+                    r1[u] = pR1[e];
+                    r2[u] = pR2[e];
+                    const W sj = (ok && col < ncol) ? W(L.sqa[(size_t)j * nq + qs]) : W(0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) x[u][c] = sj * Uin[(size_t)(3 * j + c) * ncol + cs];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const W ax = Aj[u] * (r0[u] * x[u][0] + r1[u] * x[u][1] + r2[u] * x[u][2]);
+                    acc0 += ax * r0[u] + Bj[u] * x[u][0];
+                    acc1 += ax * r1[u] + Bj[u] * x[u][1];
+                    acc2 += ax * r2[u] + Bj[u] * x[u][2];
+                }
+            }
+            if (col < ncol) {
+                const W si = W(L.sqa[(size_t)i * nq + q]);
+                Uout[(size_t)(3 * i) * ncol + col] = si * acc0;
+                Uout[(size_t)(3 * i + 1) * ncol + col] = si * acc1;
+                Uout[(size_t)(3 * i + 2) * ncol + col] = si * acc2;
+            }
+        }
+        __syncthreads();
+    };
 
     // --- u_1 = D T D e_k, V = D u_1
     W* U1 = Uat(1);
+    if constexpr (SP) {
+        // u_1 = D T D e_k needs the block column of the central atom only
+        for (int e = tid; e < nK * ncol; e += blockDim.x) {
+            const int i = e / ncol, col = e % ncol, q = col / 3, c = col % 3;
+            W A = W(0), B = W(0);
+            double rh[3] = {0.0, 0.0, 0.0};
+            const bool in = couple(i, 0, A, B, rh);
+            const double s = L.sqa[(size_t)i * nq + q] * L.sqa[q];
+            for (int r = 0; r < 3; ++r)
+                U1[(size_t)(3 * i + r) * ncol + col] =
+                    in ? W(s * (double(A) * rh[r] * rh[c] + (r == c ? double(B) : 0.0))) : W(0);
+        }
+        __syncthreads();
+    } else {
     for (int e = tid; e < N3 * ncol; e += blockDim.x) {
         const int row = e / ncol, col = e % ncol;
         const int q = col / 3, c = col % 3;
@@ -327,10 +487,15 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
         V[(size_t)col * N3p + row] = W(sq * u);
     }
     __syncthreads();
+    }
     // --- u_{m+1} = D (T V), V' = D u_{m+1}  (T symmetric, so it is its own K-major
     // operand); the product's stores write both, V' into the other buffer
     for (int m = 1; m < a.mmax; ++m) {
         W* Un = Uat(m + 1);
+        if constexpr (SP) {
+            sparse_product(Uat(m), Un);
+            continue;
+        }
         const W* Vin = (m & 1) ? V : V2;
         W* Vout = (m & 1) ? V2 : V;
         mfma_gemm_nt<3, 3, W>(N3, ncol, N3, T, N3p, Vin, N3p, false, [&](int r, int col, W v) {
@@ -430,10 +595,66 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     // --- Tbar (overwrites T).  Tbar is symmetric (the terms a, b and b, a of
     // Gbar are transposes of each other), so only blocks on or below the
     // diagonal are formed and read.
-    mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+    if constexpr (!SP)
+        mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
-    const int parts = max(1, min(4, (int)blockDim.x / max(nK, 1)));
+    const int parts = SP ? 1 : max(1, min(4, (int)blockDim.x / max(nK, 1)));
+    if constexpr (SP) {
+        // one block row per wavefront; Tbar_IJ (I > J) of a coupled pair from P and Q
+        for (int i = wave; i < nK; i += nwave) {
+            double g[3] = {0.0, 0.0, 0.0};
+            double Rb = 0.0;
+            const int n = pcnt[i];
+            for (int sidx = 0; sidx < n; ++sidx) {
+                const int j = pj[(size_t)i * nK + sidx];
+                const int I = max(i, j), J = min(i, j);
+                double sb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                // fixed trip count, clamped column and a zero factor: the loads carry no branch
+                for (int kb = 0; kb < KK; kb += 64) {
+                    const int kk = kb + lane;
+                    const int ks = kk < KK ? kk : 0;
+                    const double z = kk < KK ? 1.0 : 0.0;
+                    double pv[3], qv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        pv[c] = z * double(Pm[(size_t)(3 * I + c) * KKp + ks]);
+                        qv[c] = double(Qm[(size_t)(3 * J + c) * KKp + ks]);
+                    }
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sb[3 * x + c] += pv[x] * qv[c];
+                }
+                double C[9], tb[9];
+                wave_sum9(sb, tb);
+                for (int x = 0; x < 3; ++x)
+                    for (int c = 0; c < 3; ++c) C[3 * x + c] = tb[3 * x + c] + tb[3 * c + x];
+                const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+                const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
+                const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+                const LrPair<W> lp = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
+                                                W(a.r_buf));
+                double gp[3];
+                radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
+                g[0] += gp[0];
+                g[1] += gp[1];
+                g[2] += gp[2];
+                double rCr = 0.0;
+                for (int x = 0; x < 3; ++x)
+                    for (int c = 0; c < 3; ++c) rCr += rh[x] * C[3 * x + c] * rh[c];
+                const double ct = (3.0 * rCr - (C[0] + C[4] + C[8])) / (r * r * r);
+                Rb += a.beta * double(lp.fLR) * double(lp.dfS) * ct;
+            }
+            if (lane == 0) {
+                L.g[(size_t)i * 3 + 0] = g[0];
+                L.g[(size_t)i * 3 + 1] = g[1];
+                L.g[(size_t)i * 3 + 2] = g[2];
+                L.rb[i] = Rb;
+            }
+        }
+    } else
     for (int t = tid; t < nK * parts; t += blockDim.x) {
         const int i = t % nK, part = t / nK;
         double g[3] = {0.0, 0.0, 0.0};
@@ -557,12 +778,16 @@ __global__ void __launch_bounds__(kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     for (int e = tid; e < (nall - nK) * nw; e += blockDim.x) cap[(size_t)nK * nw + e] = 0.0;
 }
 
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed) {
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse) {
     const size_t lds = mbd_lds_bytes(nkmax, a.nq, a.n_max);
-    if (mixed)
-        hipLaunchKernelGGL(k_mbd<float>, dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
+    if (mixed && sparse)
+        hipLaunchKernelGGL((k_mbd<float, true>), dim3(a.n), dim3(kMbdThreadsSparse), lds, st, a, nkmax);
+    else if (mixed)
+        hipLaunchKernelGGL((k_mbd<float, false>), dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
+    else if (sparse)
+        hipLaunchKernelGGL((k_mbd<double, true>), dim3(a.n), dim3(kMbdThreadsSparse), lds, st, a, nkmax);
     else
-        hipLaunchKernelGGL(k_mbd<double>, dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
+        hipLaunchKernelGGL((k_mbd<double, false>), dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
     return hipGetLastError();
 }
 

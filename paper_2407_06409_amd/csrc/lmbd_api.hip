@@ -73,6 +73,7 @@ struct lmbd_context {
     bool pin_pending = false;       // copies from the staging area may still be queued
     int lds_limit = 0;              // LDS bytes per workgroup of the device
     bool profiling = false;
+    int mbd_product = LMBD_MBD_AUTO;
     hipEvent_t ev[2 * LMBD_N_STAGES] = {};
     bool ev_used[LMBD_N_STAGES] = {};
     double stage_ms[LMBD_N_STAGES] = {};
@@ -544,6 +545,12 @@ lmbd_status lmbd_set_profiling(lmbd_context* ctx, int32_t enable) {
         for (hipEvent_t& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
     }
     ctx->profiling = enable != 0;
+    return LMBD_OK;
+}
+
+lmbd_status lmbd_set_mbd_product(lmbd_context* ctx, int32_t mode) {
+    if (!ctx || mode < LMBD_MBD_AUTO || mode > LMBD_MBD_SPARSE) return LMBD_E_INVALID_ARG;
+    ctx->mbd_product = mode;
     return LMBD_OK;
 }
 
@@ -1064,7 +1071,13 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
     HIP_TRY(mark(5, 0));
-    HIP_TRY(launch_mbd(stream, ma, P.nkmax, mixed));
+    bool sparse = ctx->mbd_product == LMBD_MBD_SPARSE;
+    if (ctx->mbd_product == LMBD_MBD_AUTO) {
+        // the sparse form pays once block rows couple to a small part of K
+        sparse = true;
+        for (int s = 0; s < n_structs; ++s) sparse = sparse && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr;
+    }
+    HIP_TRY(launch_mbd(stream, ma, P.nkmax, mixed, sparse));
     HIP_TRY(mark(5, 1));
 
     if (forces) {

@@ -19,6 +19,7 @@ constexpr double kSqrt2OverPi = 0.79788456080286535588;    // sqrt(2/pi)
 constexpr int kMaxFreq = 33;       // omega = 0 plus up to 32 quadrature nodes
 constexpr int kMaxNmax = 12;       // highest body order
 constexpr int kMaxN1 = 160;        // atoms in K1 (r < r_scs), central atom included
+constexpr double kSparseMbdRatio = 0.45;  // automatic sparse MBD products when r_mbd2 <= this * r_nbr
 constexpr int kMaxNK = 400;        // sites in K (r < r_nbr), central atom included; the MBD kernel's LDS,
                                    // 8 (3 nq + 15) bytes per site for nq >= 12 nodes, caps it lower for
                                    // long grids (the host checks that limit too)
@@ -260,7 +261,7 @@ hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool m
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
 size_t mbd_lds_bytes(int nkmax, int nq, int n_max);
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed);
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,
                                  const double* ca, double* abar_cen);

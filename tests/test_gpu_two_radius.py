@@ -42,3 +42,56 @@ def test_two_radius_regime_matches_oracle(case, precision):
     print(f"  max |dE| {de:.3e} eV/atom, max |dF| {df:.3e} eV/A (max |F| {np.abs(f_ref).max():.3e})", flush=True)
     e_tol, f_tol = (1e-8, 1e-8) if precision == "fp64" else (1e-5, 1e-4)
     assert de < e_tol and df < f_tol
+
+
+def _ctx(mode):
+    from paper_2407_06409_amd import Context
+    ctx = Context(0)
+    ctx.set_mbd_product(mode)
+    return ctx
+
+
+@pytest.mark.parametrize("mode", ["dense", "sparse"])
+def test_two_radius_regime_both_product_forms(case, mode):
+    """The automatic choice takes the sparse form here; both forms forced."""
+    st, w, e_ref, f_ref, nk = case
+    print(f"case C216 two-radius, MBD products {mode}", flush=True)
+    g = gpu_run(st, CUT, weights=w, ctx=_ctx(mode))
+    de = np.abs(g["energies"][ATOMS] - e_ref).max()
+    df = np.abs(g["forces"] - f_ref).max()
+    print(f"  max |dE| {de:.3e} eV/atom, max |dF| {df:.3e} eV/A", flush=True)
+    assert de < 1e-8 and df < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sparse_form_where_every_pair_couples(precision):
+    """Sparse products forced on a single-radius box (every block coupled): the
+    same results as the oracle, including the pairs cut by the central radius."""
+    st = C.carbon_box(96, 11, g_cm3=2.0)
+    cut = dict(r_scs=4.0, r_nbr=4.5, r_mbd1=4.5, r_mbd2=3.0)
+    print(f"case C96 {cut} sparse MBD products forced, {precision}", flush=True)
+    g = gpu_run(st, cut, precision=precision, ctx=_ctx("sparse"))
+    e, f = oracle.lmbd_energy_forces(st, oracle_params(cut), SPECIES_TABLE)
+    de, df = np.abs(g["energies"] - e).max(), np.abs(g["forces"] - f).max()
+    print(f"  max |dE| {de:.3e} eV/atom, max |dF| {df:.3e} eV/A", flush=True)
+    e_tol, f_tol = (1e-8, 1e-8) if precision == "fp64" else (1e-5, 1e-4)
+    assert de < e_tol and df < f_tol
+
+
+def test_sparse_form_with_two_point_model_and_energy_only():
+    from workloads.configs import OMEGA_REF
+    st, cut = C.config_small_open()
+    print(f"case C64 open sparse forced, two-point model, energies only", flush=True)
+    lor = dict(scs_freq="lorentz", omega_ref=OMEGA_REF)
+    g = gpu_run(st, cut, forces=False, ctx=_ctx("sparse"), **lor)
+    e = oracle.lmbd_energies(st, oracle_params(cut, **lor), SPECIES_TABLE)
+    de = np.abs(g["energies"] - e).max()
+    print(f"  max |dE| {de:.3e} eV/atom", flush=True)
+    assert de < 1e-8
+
+
+def test_unknown_product_form_is_an_argument_error():
+    from paper_2407_06409_amd import Context, load_library
+    ctx = Context(0)
+    assert load_library().lmbd_set_mbd_product(ctx.handle, 7) == 1
+    assert load_library().lmbd_set_mbd_product(None, 0) == 1
