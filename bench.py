@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
                     [--workload plain|mixed] [--no-cpu-baseline] [--no-serve] [--serve-sweep]
-                    [--no-mixed] [--no-two-point]
+                    [--no-mixed] [--no-two-point] [--no-two-radius]
 
 A step is one complete evaluation (neighbour lists, local SCS at every
 frequency, local MBD energies, all adjoints, forces) of the whole workload,
@@ -11,7 +11,8 @@ in a periodic box at 2.0 g/cm^3 with a 6 A cutoff, 12 quadrature nodes and
 n_max = 6, in FP64; the same workload is also timed in mixed precision, and
 with the two-point Lorentzian SCS frequency model (SCS at omega = 0 and
 omega_ref only) in both precisions, beside its deviation from the exact
-frequency treatment.  The
+frequency treatment, and in the two-radius regime (r_MBD,1 = 6 A, r_MBD,2 = 3 A,
+K = B(9 A)) with sparse and with dense MBD products.  The
 serving section replays 256 H/C/N/O requests (50-5,000 atoms) arriving as a
 Poisson stream through the continuous-batching server in mixed precision,
 and through a one-request-at-a-time FP64 server, and reports atoms/s with
@@ -276,6 +277,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving replay")
     ap.add_argument("--serve-sweep", action="store_true", help="also replay at 0.5/1.0/1.2 x the rate")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing of the workload")
+    ap.add_argument("--no-two-radius", action="store_true",
+                    help="skip the timing of the two-radius regime (sparse and dense MBD products)")
     ap.add_argument("--no-two-point", action="store_true",
                     help="skip the timing of the two-point Lorentzian SCS frequency model")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -374,10 +377,10 @@ def main():
         "stages_ms": stage_ms, "roofline": roofline,
         "mean_n1": float(n1.mean()), "energy_eV": float(out["energies"].sum().item()),
     }
-    def time_params(params):
+    def time_params(params, cutoffs=None):
         """Atoms/s, ms per step, the last outputs and stage times of `steps` timed calls."""
         def run():
-            return P.compute(pos, sp, nu, cutoffs=cut, params=params, species_table=SPECIES_TABLE,
+            return P.compute(pos, sp, nu, cutoffs=cutoffs or cut, params=params, species_table=SPECIES_TABLE,
                              cell=st.cell, forces=True, ctx=ctx, stream=stream)
         for _ in range(args.warmup):
             o = run()
@@ -419,6 +422,17 @@ def main():
                 rec["max_abs_dF_vs_fp64_eV_per_A"] = max_diff(o, o64, "forces")
             tp[prec] = rec
         line["two_point_scs"] = tp
+    if not args.no_two_radius and args.precision == "fp64":
+        # the two-radius regime of Sec. III.A on the same box: K = B(r_MBD,1 + r_MBD,2)
+        cut2 = dict(r_scs=cut["r_scs"], r_nbr=9.0, r_mbd1=6.0, r_mbd2=3.0)
+        tr = {"cutoffs_A": cut2, "mean_nK": float(neighbour_counts(st, cut2["r_nbr"]).mean())}
+        for mode in ("auto", "dense"):
+            ctx.set_mbd_product(mode)
+            v, msps, o, stg = time_params(mp, cut2)
+            tr["sparse" if mode == "auto" else "dense"] = {"value": v, "unit": "atoms/s", "ms_per_step": msps,
+                                                           "stages_ms": stg}
+        ctx.set_mbd_product("auto")
+        line["two_radius"] = tr
     if not args.no_serve:
         line["served"] = serve_bench(args.serve_sweep)
     if not args.no_cpu_baseline and args.workload == "plain":

@@ -61,6 +61,15 @@ def cutoff_6p8A():
     return st, {k: (6.8 if k.startswith("r_") else v) for k, v in cut.items()}
 
 
+def two_radius_6_3():
+    """The 1,728-atom carbon box in the two-radius regime of Sec. III.A: r_SCS =
+    r_MBD,1 = 6 A, r_MBD,2 = 3 A and K = B(r_MBD,1 + r_MBD,2) = B(9 A), about 305
+    sites per neighbourhood, of which a block row other than the central atom's
+    couples to about 11."""
+    st, _ = C.config_plain_pbc()
+    return st, dict(r_scs=6.0, r_nbr=9.0, r_mbd1=6.0, r_mbd2=3.0)
+
+
 def fixture(name):
     if name == "C1728_pbc":
         st, cut = C.config_plain_pbc()
@@ -78,10 +87,17 @@ def fixture(name):
         return {"cutoffs": cut,
                 "energies": energies_fixture("C1728 6.8A", st, cut, sample(st.n, 4, 11)),
                 "forces": forces_fixture("C1728 6.8A", st, cut, sample(st.n, 1, 12))}
+    if name == "C1728_pbc_two_radius":
+        st, cut = two_radius_6_3()
+        return {"cutoffs": cut,
+                "energies": energies_fixture("C1728 two-radius", st, cut, sample(st.n, 4, 13)),
+                "forces": forces_fixture("C1728 two-radius", st, cut, sample(st.n, 1, 14))}
     raise KeyError(name)
 
 
-NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A"]
+
+
+NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A", "C1728_pbc_two_radius"]
 
 
 def main():

@@ -74,6 +74,39 @@ def test_c1728_cutoff_6p8A_large_neighbourhoods_match_oracle():
     assert de_m < 1e-5 and df_m < 1e-4
 
 
+@pytest.mark.parametrize("mode", ["sparse", "dense"])
+def test_c1728_two_radius_regime_matches_oracle(mode):
+    """The two-radius regime at full size (r_MBD,1 = r_SCS = 6 A, r_MBD,2 = 3 A, K =
+    B(9 A), about 305 sites per neighbourhood), in the product form the automatic
+    choice takes (sparse) and in the dense one, against stored oracle energies and
+    the forces of a one-atom sum; the mixed path with the sparse form too."""
+    from paper_2407_06409_amd import Context
+    g = golden()["C1728_pbc_two_radius"]
+    st, _ = C.config_plain_pbc()
+    cut = g["cutoffs"]
+    ctx = Context(0)
+    ctx.set_mbd_product(mode)
+    print(f"case C1728 two-radius {cut} n={st.n}, MBD products {mode}", flush=True)
+    atoms = g["energies"]["atoms"]
+    w = np.zeros(st.n)
+    w[g["forces"]["weighted_atoms"]] = 1.0
+    ref = np.zeros((st.n, 3))
+    ref[g["forces"]["force_atoms"]] = np.array(g["forces"]["forces_eV_per_A"])
+    full = gpu_run(st, cut, forces=False, ctx=ctx)
+    de = np.abs(full["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+    part = gpu_run(st, cut, forces=True, weights=w, ctx=ctx)
+    df = np.abs(part["forces"] - ref).max()
+    print(f"  max |dE| on {len(atoms)} sampled atoms {de:.3e} eV, max |dF| of the one-atom sum {df:.3e} eV/A "
+          f"(max |F| {np.abs(ref).max():.3e})", flush=True)
+    assert de < 1e-8 and df < 1e-8
+    if mode == "sparse":
+        mixed = gpu_run(st, cut, forces=True, weights=w, precision="mixed", ctx=ctx)
+        de_m = np.abs(mixed["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
+        df_m = np.abs(mixed["forces"] - ref).max()
+        print(f"  mixed: max |dE| {de_m:.3e} eV/atom, max |dF| {df_m:.3e} eV/A", flush=True)
+        assert de_m < 1e-5 and df_m < 1e-4
+
+
 def test_hcno4096_energies_match_oracle():
     g = golden()["HCNO4096_pbc"]
     st, cut = C.config_diff_hcno()
