@@ -200,9 +200,11 @@ const char* lmbd_stage_name(int32_t i);
  * T_LR and runs every product on the matrix cores; LMBD_MBD_SPARSE never stores
  * it and walks only the coupled pairs (for the two-radius regime of Sec. III.A,
  * where block rows other than the central atom's couple only up to r_mbd2);
- * LMBD_MBD_AUTO (the default) takes the sparse form when every structure of a
- * call has r_mbd2 <= 0.45 r_nbr.  Both forms compute the same quantities (to
- * rounding).  LMBD_E_INVALID_ARG for a NULL context or an unknown mode. */
+ * LMBD_MBD_AUTO (the default) takes the sparse form for each structure of a call
+ * with r_mbd2 <= 0.45 r_nbr and the dense form for the others (a structure's
+ * results do not depend on the batch it is in).  Both forms compute the same
+ * quantities (to rounding).  LMBD_E_INVALID_ARG for a NULL context or an
+ * unknown mode. */
 enum { LMBD_MBD_AUTO = 0, LMBD_MBD_DENSE = 1, LMBD_MBD_SPARSE = 2 };
 lmbd_status lmbd_set_mbd_product(lmbd_context* ctx, int32_t mode);
 

@@ -932,6 +932,16 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     // --- memory plan
     Plan P;
     build_plan(cnt, nw, ncol, n_max, forces, mixed, P);
+    // MBD product form per structure, not per call, so that a structure's results do
+    // not depend on what it shares a call with: dense-form atoms first, then
+    // sparse-form atoms, each part still largest first
+    std::vector<char> sparse_struct(n_structs);
+    for (int s = 0; s < n_structs; ++s)
+        sparse_struct[s] = ctx->mbd_product == LMBD_MBD_SPARSE ||
+                           (ctx->mbd_product == LMBD_MBD_AUTO && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr);
+    std::stable_partition(P.order.begin(), P.order.end(), [&](int32_t k) { return !sparse_struct[atom_struct[k]]; });
+    int n_dense = 0;
+    for (int k = 0; k < N; ++k) n_dense += sparse_struct[atom_struct[k]] ? 0 : 1;
     if (P.n1max > kMaxN1 || P.nkmax > kMaxNK || P.nallmax > kMaxSites)
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
@@ -1071,13 +1081,17 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
     HIP_TRY(mark(5, 0));
-    bool sparse = ctx->mbd_product == LMBD_MBD_SPARSE;
-    if (ctx->mbd_product == LMBD_MBD_AUTO) {
-        // the sparse form pays once block rows couple to a small part of K
-        sparse = true;
-        for (int s = 0; s < n_structs; ++s) sparse = sparse && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr;
+    if (n_dense > 0) {
+        MbdArgs md = ma;
+        md.n = n_dense;
+        HIP_TRY(launch_mbd(stream, md, P.nkmax, mixed, false));
     }
-    HIP_TRY(launch_mbd(stream, ma, P.nkmax, mixed, sparse));
+    if (n_dense < N) {   // the sparse form pays once block rows couple to a small part of K
+        MbdArgs ms = ma;
+        ms.n = N - n_dense;
+        ms.order = ma.order + n_dense;
+        HIP_TRY(launch_mbd(stream, ms, P.nkmax, mixed, true));
+    }
     HIP_TRY(mark(5, 1));
 
     if (forces) {

@@ -127,6 +127,45 @@ def test_served_request_against_oracle():
     assert de < 1e-5 and df < 1e-4
 
 
+def test_two_point_model_served_in_the_mix_equals_alone():
+    """The two-point SCS frequency model through the continuous-batching server.
+    On these H/C/N/O structures some strongly screened atoms have a polarisability
+    that rises between 0 and omega_ref, which the model cannot represent: exactly
+    the requests for which the oracle refuses the model fail with
+    LMBD_E_SCS_BREAKDOWN, alone and in the mix; the others give bitwise the
+    results of the request evaluated alone, and the oracle's model."""
+    from workloads import Structure
+    from workloads.configs import OMEGA_REF
+    lor = dict(scs_freq="lorentz", omega_ref=OMEGA_REF)
+    reqs = _requests(8, seed=900)
+    refused = []
+    for r in reqs:
+        st = Structure(np.asarray(r["pos"]), np.asarray(r["species"]), np.asarray(r["v_ratio"]), r["cell"],
+                       np.array(r["pbc"], bool))
+        try:
+            oracle.lmbd_energies(st, oracle_params(r["cutoffs"], **lor), SPECIES_TABLE)
+            refused.append(False)
+        except ValueError:
+            refused.append(True)
+    mp = method_params(precision="mixed", **lor)
+    alone, _ = _serve(reqs, mp, n_slots=1, max_batch_requests=1, memory_budget=8 << 30)
+    mix, s2 = _serve(reqs, mp, n_slots=3, memory_budget=8 << 30, max_batch_atoms=1500)
+    print(f"two-point model served: {s2}; refused by the oracle: {refused}", flush=True)
+    assert 0 < sum(refused) < len(reqs)
+    for a, m, bad in zip(alone, mix, refused):
+        want = "LMBD_E_SCS_BREAKDOWN" if bad else "LMBD_OK"
+        assert a["status"] == want and m["status"] == want, (a["detail"], m["detail"])
+        if not bad:
+            assert np.array_equal(a["energies"], m["energies"])
+            assert np.array_equal(a["forces"], m["forces"])
+    st, cut = C.hcno_cluster(70, 31), C.cutoffs(4.5)
+    res, _ = _serve([_req(st, cut)], mp, n_slots=2, memory_budget=1 << 30)
+    e, f = oracle.lmbd_energy_forces(st, oracle_params(cut, **lor), SPECIES_TABLE)
+    de, df = np.abs(res[0]["energies"] - e).max(), np.abs(res[0]["forces"] - f).max()
+    print(f"  served two-point model vs oracle: max |dE| {de:.3e}, max |dF| {df:.3e}", flush=True)
+    assert de < 1e-5 and df < 1e-4
+
+
 def test_destroy_cancels_queued_requests():
     from paper_2407_06409_amd import Server
     reqs = _requests(8, seed=900)

@@ -95,3 +95,22 @@ def test_unknown_product_form_is_an_argument_error():
     ctx = Context(0)
     assert load_library().lmbd_set_mbd_product(ctx.handle, 7) == 1
     assert load_library().lmbd_set_mbd_product(None, 0) == 1
+
+
+def test_product_form_is_chosen_per_structure():
+    """A two-radius structure (sparse form) and a single-radius one (dense form) in
+    one call: each result is bitwise that of the structure evaluated alone."""
+    from paper_2407_06409_amd import compute_batch
+    from tests.gpu_common import method_params
+    a = C.carbon_box(216, 21, g_cm3=2.0)
+    b = C.carbon_box(96, 11, g_cm3=2.0)
+    reqs = [dict(pos=a.pos, species=a.species, v_ratio=a.nu, cell=a.cell, pbc=(1, 1, 1), cutoffs=CUT),
+            dict(pos=b.pos, species=b.species, v_ratio=b.nu, cell=b.cell, pbc=(1, 1, 1),
+                 cutoffs=dict(r_scs=4.0, r_nbr=4.0, r_mbd1=4.0, r_mbd2=4.0))]
+    mp = method_params()
+    print("case C216 two-radius + C96 single radius in one call", flush=True)
+    both = compute_batch(reqs, mp, SPECIES_TABLE)
+    for r, got in zip(reqs, both):
+        alone = compute_batch([r], mp, SPECIES_TABLE)[0]
+        assert np.array_equal(alone["energies"], got["energies"])
+        assert np.array_equal(alone["forces"], got["forces"])
