@@ -226,6 +226,12 @@ __device__ inline double read_lane(double x, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+__device__ inline float read_lane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+template <typename W>
+__device__ inline W lane_value(W x, int l) { return read_lane(x, l); }
+
 // Sums over the 64 lanes of nine per-lane values, returned to every lane.  A
 // transposed butterfly: at the exchanges over lane bits 5, 4, 3 and 2 a lane keeps
 // half of the (zero-padded to 16) values it carries and sends the other half, so
@@ -429,17 +435,22 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
             const size_t e0 = (size_t)i * nK;
             W acc0 = W(0), acc1 = W(0), acc2 = W(0);
             for (int s0 = 0; s0 < n; s0 += 4) {
+                // the four entries are loaded cooperatively (lane 4 f + u holds field f of entry
+                // s0 + u: A, B, rhat) and handed to every lane through scalar registers
+                const int fu = lane & 3, ff = min(lane >> 2, 4);
+                const size_t ec = e0 + (s0 + fu < n ? s0 + fu : 0);
+                const W fv = pA[(size_t)ff * NN + ec];
+                const int jv = pj[ec];
                 W x[4][3], Aj[4], Bj[4], r0[4], r1[4], r2[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const bool ok = s0 + u < n;
-                    const size_t e = e0 + (ok ? s0 + u : 0);
-                    const int j = pj[e];
-                    Aj[u] = pA[e];
-                    Bj[u] = pB[e];
-                    r0[u] = pR0[e];
-                    r1[u] = pR1[e];
-                    r2[u] = pR2[e];
+                    const int j = __builtin_amdgcn_readlane(jv, u);
+                    Aj[u] = lane_value(fv, u);
+                    Bj[u] = lane_value(fv, 4 + u);
+                    r0[u] = lane_value(fv, 8 + u);
+                    r1[u] = lane_value(fv, 12 + u);
+                    r2[u] = lane_value(fv, 16 + u);
                     const W sj = (ok && col < ncol) ? W(L.sqa[(size_t)j * nq + qs]) : W(0);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) x[u][c] = sj * Uin[(size_t)(3 * j + c) * ncol + cs];
