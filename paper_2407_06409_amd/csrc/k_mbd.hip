@@ -621,21 +621,30 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                 const int j = pj[(size_t)i * nK + sidx];
                 const int I = max(i, j), J = min(i, j);
                 double sb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                // fixed trip count, clamped column and a zero factor: the loads carry no branch
-                for (int kb = 0; kb < KK; kb += 64) {
-                    const int kk = kb + lane;
-                    const int ks = kk < KK ? kk : 0;
-                    const double z = kk < KK ? 1.0 : 0.0;
-                    double pv[3], qv[3];
+                // 16 bytes of consecutive columns per lane (one vector load per row; the padding
+                // columns of P and Q are zero), a clamped column and a zero factor: the loads
+                // carry no branch
+                constexpr int VW = 16 / sizeof(W);
+                typedef W VV __attribute__((ext_vector_type(VW)));
+                for (int kb = 0; kb < KKp; kb += 64 * VW) {
+                    const int kk = kb + VW * lane;
+                    const int ks = kk < KKp ? kk : 0;
+                    const double z = kk < KKp ? 1.0 : 0.0;
+                    VV pv[3], qv[3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        pv[c] = z * double(Pm[(size_t)(3 * I + c) * KKp + ks]);
-                        qv[c] = double(Qm[(size_t)(3 * J + c) * KKp + ks]);
+                        pv[c] = *reinterpret_cast<const VV*>(Pm + (size_t)(3 * I + c) * KKp + ks);
+                        qv[c] = *reinterpret_cast<const VV*>(Qm + (size_t)(3 * J + c) * KKp + ks);
                     }
 #pragma unroll
                     for (int x = 0; x < 3; ++x)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) sb[3 * x + c] += pv[x] * qv[c];
+                        for (int c = 0; c < 3; ++c) {
+                            double d = 0.0;
+#pragma unroll
+                            for (int v = 0; v < VW; ++v) d += double(pv[x][v]) * double(qv[c][v]);
+                            sb[3 * x + c] += z * d;
+                        }
                 }
                 double C[9], tb[9];
                 wave_sum9(sb, tb);
