@@ -617,9 +617,14 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
             double g[3] = {0.0, 0.0, 0.0};
             double Rb = 0.0;
             const int n = pcnt[i];
-            for (int sidx = 0; sidx < n; ++sidx) {
-                const int j = pj[(size_t)i * nK + sidx];
-                const int I = max(i, j), J = min(i, j);
+            // eight coupled pairs per group: their 3x3 blocks first (lane u keeps pair u's),
+            // then the eight pair tails side by side, one per lane
+            for (int s0 = 0; s0 < n; s0 += 8) {
+                double myC[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int myj = -1;
+                for (int u = 0; u < 8 && s0 + u < n; ++u) {   // uniform over the wavefront
+                    const int j = pj[(size_t)i * nK + s0 + u];
+                    const int I = max(i, j), J = min(i, j);
                 double sb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 // 16 bytes of consecutive columns per lane (one vector load per row; the padding
                 // columns of P and Q are zero), a clamped column and a zero factor: the loads
@@ -646,26 +651,43 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                             sb[3 * x + c] += z * d;
                         }
                 }
-                double C[9], tb[9];
-                wave_sum9(sb, tb);
-                for (int x = 0; x < 3; ++x)
-                    for (int c = 0; c < 3; ++c) C[3 * x + c] = tb[3 * x + c] + tb[3 * c + x];
-                const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-                const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
-                const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
-                const LrPair<W> lp = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
-                                                W(a.r_buf));
-                double gp[3];
-                radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
-                g[0] += gp[0];
-                g[1] += gp[1];
-                g[2] += gp[2];
-                double rCr = 0.0;
-                for (int x = 0; x < 3; ++x)
-                    for (int c = 0; c < 3; ++c) rCr += rh[x] * C[3 * x + c] * rh[c];
-                const double ct = (3.0 * rCr - (C[0] + C[4] + C[8])) / (r * r * r);
-                Rb += a.beta * double(lp.fLR) * double(lp.dfS) * ct;
+                    double tb[9];
+                    wave_sum9(sb, tb);
+                    if (lane == u) {
+                        for (int x = 0; x < 3; ++x)
+                            for (int c = 0; c < 3; ++c) myC[3 * x + c] = tb[3 * x + c] + tb[3 * c + x];
+                        myj = j;
+                    }
+                }
+                if (myj >= 0) {
+                    const int j = myj;
+                    const double* C = myC;
+                    const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+                    const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                    const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
+                    const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+                    const LrPair<W> lp = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
+                                                    W(a.r_buf));
+                    double gp[3];
+                    radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
+                    g[0] += gp[0];
+                    g[1] += gp[1];
+                    g[2] += gp[2];
+                    double rCr = 0.0;
+                    for (int x = 0; x < 3; ++x)
+                        for (int c = 0; c < 3; ++c) rCr += rh[x] * C[3 * x + c] * rh[c];
+                    const double ct = (3.0 * rCr - (C[0] + C[4] + C[8])) / (r * r * r);
+                    Rb += a.beta * double(lp.fLR) * double(lp.dfS) * ct;
+                }
+            }
+            {   // the lanes' partial sums, in a fixed order
+                const double part[9] = {g[0], g[1], g[2], Rb, 0.0, 0.0, 0.0, 0.0, 0.0};
+                double tot[9];
+                wave_sum9(part, tot);
+                g[0] = tot[0];
+                g[1] = tot[1];
+                g[2] = tot[2];
+                Rb = tot[3];
             }
             if (lane == 0) {
                 L.g[(size_t)i * 3 + 0] = g[0];
