@@ -617,22 +617,19 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
             double g[3] = {0.0, 0.0, 0.0};
             double Rb = 0.0;
             const int n = pcnt[i];
-            // eight coupled pairs per group: their 3x3 blocks first (lane u keeps pair u's),
-            // then the eight pair tails side by side, one per lane
+            // eight coupled pairs per step, eight lanes per pair: lane 8u + t sums columns
+            // t, t + 8, ... (16 bytes each) of pair u's nine dot products; the eight lanes of
+            // a pair then combine their sums and the pair's first lane takes its tail
+            constexpr int VW = 16 / sizeof(W);
+            typedef W VV __attribute__((ext_vector_type(VW)));
+            const int pu = lane >> 3, pt = lane & 7;
             for (int s0 = 0; s0 < n; s0 += 8) {
-                double myC[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                int myj = -1;
-                for (int u = 0; u < 8 && s0 + u < n; ++u) {   // uniform over the wavefront
-                    const int j = pj[(size_t)i * nK + s0 + u];
-                    const int I = max(i, j), J = min(i, j);
+                const bool okp = s0 + pu < n;
+                const int j = pj[(size_t)i * nK + (okp ? s0 + pu : s0)];
+                const int I = max(i, j), J = min(i, j);
                 double sb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                // 16 bytes of consecutive columns per lane (one vector load per row; the padding
-                // columns of P and Q are zero), a clamped column and a zero factor: the loads
-                // carry no branch
-                constexpr int VW = 16 / sizeof(W);
-                typedef W VV __attribute__((ext_vector_type(VW)));
-                for (int kb = 0; kb < KKp; kb += 64 * VW) {
-                    const int kk = kb + VW * lane;
+                for (int kb = 0; kb < KKp; kb += 8 * VW) {
+                    const int kk = kb + VW * pt;
                     const int ks = kk < KKp ? kk : 0;
                     const double z = kk < KKp ? 1.0 : 0.0;
                     VV pv[3], qv[3];
@@ -651,14 +648,16 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                             sb[3 * x + c] += z * d;
                         }
                 }
-                    double tb[9];
-                    wave_sum9(sb, tb);
-                    if (lane == u) {
-                        for (int x = 0; x < 3; ++x)
-                            for (int c = 0; c < 3; ++c) myC[3 * x + c] = tb[3 * x + c] + tb[3 * c + x];
-                        myj = j;
-                    }
+#pragma unroll
+                for (int x = 0; x < 9; ++x) {
+                    sb[x] += __shfl_xor(sb[x], 1);
+                    sb[x] += __shfl_xor(sb[x], 2);
+                    sb[x] += __shfl_xor(sb[x], 4);
                 }
+                double myC[9];
+                for (int x = 0; x < 3; ++x)
+                    for (int c = 0; c < 3; ++c) myC[3 * x + c] = sb[3 * x + c] + sb[3 * c + x];
+                const int myj = (okp && pt == 0) ? j : -1;
                 if (myj >= 0) {
                     const int j = myj;
                     const double* C = myC;
