@@ -268,7 +268,7 @@ __device__ inline void wave_sum9(const double (&v)[9], double (&out)[9]) {
 // central one are sparse): T_LR is never stored; a wavefront takes one block row,
 // its lanes test 64 candidate sites at a time, the coupled ones are walked by the
 // whole wavefront together (lanes over the Krylov columns), and Tbar is formed
-// only for coupled pairs, each 3x3 block as nine wavefront-wide dot products.
+// only for coupled pairs, each 3x3 block as nine dot products over eight lanes.
 // The sparse form is bound by the latency of its gathers rather than by arithmetic:
 // it runs 1,024 threads (four wavefronts per SIMD at its register count) to hide it.
 constexpr int kMbdThreadsSparse = 1024;
