@@ -265,10 +265,11 @@ __device__ inline void wave_sum9(const double (&v)[9], double (&out)[9]) {
 // SP = false: T_LR is stored dense and every product runs on the matrix cores.
 // SP = true (two-radius regime, Sec. III.A: a site couples to the central atom up
 // to r_MBD,1 but to the others only up to r_MBD,2, so block rows other than the
-// central one are sparse): T_LR is never stored; a wavefront takes one block row,
-// its lanes test 64 candidate sites at a time, the coupled ones are walked by the
-// whole wavefront together (lanes over the Krylov columns), and Tbar is formed
-// only for coupled pairs, each 3x3 block as nine dot products over eight lanes.
+// central one are sparse): T_LR is never stored.  The coupled sites of every block
+// row and their coefficients are listed once per atom (a wavefront per row, its
+// lanes testing 64 candidates at a time); each Krylov product walks a row's list
+// with the whole wavefront (lanes over the Krylov columns), and Tbar is formed only
+// for coupled pairs, each 3x3 block as nine dot products over eight lanes.
 // The sparse form is bound by the latency of its gathers rather than by arithmetic:
 // it runs 1,024 threads (four wavefronts per SIMD at its register count) to hide it.
 constexpr int kMbdThreadsSparse = 1024;
