@@ -62,6 +62,7 @@ def test_calls_that_need_no_device(lib):
     assert lib.lmbd_create(0, None) == 1
     assert lib.lmbd_compute_batch(None, None, 0, None, 0, None, 0, None) == 1
     assert lib.lmbd_set_memory_budget(None, 0) == 1
+    assert lib.lmbd_set_mbd_product(None, 0) == 1
     assert lib.lmbd_submit(None, None, None) == 1
     assert lib.lmbd_poll(None, 0, None) == 1
     assert lib.lmbd_release(None, 0) == 1
