@@ -117,3 +117,23 @@ def sr_tensor_fd(rv, sigma, S, d=6.0):
     r = np.linalg.norm(rv)
     H = numerical_hessian(erf_coulomb(sigma), rv, h=1e-2 * min(r, sigma))
     return -(1.0 - fermi(r, S, d)) * H
+
+
+def smooth_cutoff(r, rc, rb):
+    """The C1 switch from 1 to 0 over the buffer [rc - rb, rc] (Sec. III.A/III.B cutoff functions).
+
+    Built as the unique cubic with value 1 and zero slope at rc - rb and value 0
+    and zero slope at rc (Hermite conditions, solved numerically here in the
+    basis 1, s, s^2, s^3 of s = r - rc + rb), so it is an independent
+    construction of the buffer polynomial rather than a retyping of it; 1 below
+    the buffer, 0 beyond.
+    """
+    if r < rc - rb:
+        return 1.0
+    if r >= rc:
+        return 0.0
+    M = np.array([[1.0, 0.0, 0.0, 0.0], [0.0, 1.0, 0.0, 0.0],
+                  [1.0, rb, rb * rb, rb ** 3], [0.0, 1.0, 2 * rb, 3 * rb * rb]])
+    c = np.linalg.solve(M, np.array([1.0, 0.0, 0.0, 0.0]))
+    s = r - rc + rb
+    return c[0] + c[1] * s + c[2] * s * s + c[3] * s ** 3

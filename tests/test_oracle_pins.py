@@ -127,24 +127,27 @@ def _sigma(a):
     return (math.sqrt(2.0 / math.pi) * a / 3.0) ** (1.0 / 3.0)
 
 
-def _solve_scs_fd(centers_bohr, abar, R, fixed=None, beta=0.83, finner=None, rc=None):
+def _solve_scs_fd(centers_bohr, abar, R, fixed=None, beta=0.83, finner=None, rc=None, rb=None):
     """Independent small SCS solve with tensors from numerical Hessians.
 
     centers: coupled atoms (n, 3) bohr; abar/R: their TS values; fixed: list of
     (pos, abar_j, R_j) uncoupled atoms entering the right-hand side, with the
     optional inner-buffer weight finner(r).  Pairs at or beyond rc (bohr) do not
-    couple; the constructions keep every coupled pair clear of the cutoff buffer.
+    couple.  Without rb the constructions keep every coupled pair clear of the
+    cutoff buffer; with rb (bohr) every tensor is scaled by the C1 cubic switch
+    over [rc - rb, rc].
     """
     n = len(centers_bohr)
     B = np.zeros((3 * n, 3 * n))
     couples = lambda rv: rc is None or np.linalg.norm(rv) < rc
+    fsr = lambda rv: 1.0 if rb is None else cf.smooth_cutoff(np.linalg.norm(rv), rc, rb)
     for i in range(n):
         B[3 * i:3 * i + 3, 3 * i:3 * i + 3] = np.eye(3) / abar[i]
         for j in range(n):
             if i != j and couples(centers_bohr[i] - centers_bohr[j]):
                 rv = centers_bohr[i] - centers_bohr[j]
                 sig = math.hypot(_sigma(abar[i]), _sigma(abar[j]))
-                B[3 * i:3 * i + 3, 3 * j:3 * j + 3] = cf.sr_tensor_fd(rv, sig, beta * (R[i] + R[j]))
+                B[3 * i:3 * i + 3, 3 * j:3 * j + 3] = fsr(rv) * cf.sr_tensor_fd(rv, sig, beta * (R[i] + R[j]))
     d = np.tile(np.eye(3), (n, 1))
     for (pj, aj, Rj) in (fixed or []):
         for i in range(n):
@@ -153,7 +156,7 @@ def _solve_scs_fd(centers_bohr, abar, R, fixed=None, beta=0.83, finner=None, rc=
             if not couples(rv):
                 continue
             sig = math.hypot(_sigma(abar[i]), _sigma(aj))
-            w = 1.0 if finner is None else finner(r)
+            w = (1.0 if finner is None else finner(r)) * fsr(rv)
             d[3 * i:3 * i + 3] -= w * cf.sr_tensor_fd(rv, sig, beta * (R[i] + Rj)) * aj
     X = np.linalg.solve(B, d)
     return np.array([np.trace(X[3 * i:3 * i + 3]) / 3.0 for i in range(n)])
@@ -276,6 +279,88 @@ def test_series_converges_to_block_logarithm():
     e_2 = oracle.lmbd_energies(st, _params(4.0, 6.0, n_max=2), SPECIES_TABLE)
     assert np.allclose(e_40, e_log, rtol=1e-9, atol=1e-13)
     assert not np.allclose(e_2, e_log, rtol=1e-4)
+
+
+# ---------------------------------------- cutoff buffers and the two MBD radii
+
+def _radii_params(r_scs, r_nbr, r_mbd1, r_mbd2, grid=GRID200, **kw):
+    return oracle.make_params(dict(r_scs=r_scs, r_nbr=r_nbr, r_mbd1=r_mbd1, r_mbd2=r_mbd2),
+                              grid[0], grid[1], **kw)
+
+
+def _at_distance(r_A, direction=(0.3, -0.8, 0.52)):
+    d = np.asarray(direction, dtype=np.float64)
+    return d * (r_A / np.linalg.norm(d))
+
+
+def test_cutoff_polynomial_is_the_c1_hermite_cubic():
+    """The SR buffer function equals the unique cubic that leaves 1 and reaches 0
+    with zero slope at both ends of the buffer (Sec. III.B f_SR)."""
+    import torch
+    rc, rb = 5.0, 0.5
+    r = np.linspace(4.2, 5.2, 201)
+    got = L._cutoff_poly(torch.as_tensor(r), rc, rb).numpy()
+    ref = np.array([cf.smooth_cutoff(x, rc, rb) for x in r])
+    assert np.allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_buffered_dimer_second_order():
+    """SCS off, n_max = 2, the pair inside the f_LR buffer of r_MBD,1: every pair of a
+    dimer touches the central atom, so each atom's energy is -C6 f^2 f_LR(r)^2 / (2 r^6)
+    with f_LR cut at r_MBD,1 (Sec. III.A), whatever r_MBD,2 is."""
+    r1, rb = 4.0, 0.5
+    for r_A, r2 in ((3.55, 2.5), (3.7, 4.0), (3.93, 1.0)):
+        st = _open([[0, 0, 0], _at_distance(r_A)], species=[C_IDX, SPECIES_INDEX["N"]], nu=[0.8, 0.95])
+        e = oracle.lmbd_energies(st, _radii_params(NO_SCS, 4.5, r1, r2, n_max=2), SPECIES_TABLE)
+        a, w, R = _free(st)
+        r = r_A / cf.BOHR
+        f = cf.fermi(r, 0.83 * (R[0] + R[1]))
+        flr = cf.smooth_cutoff(r_A, r1, rb)
+        assert 0.0 < flr < 1.0
+        ref = -0.5 * cf.c6_casimir_polder(a[0], w[0], a[1], w[1]) * (f * flr) ** 2 / r ** 6 * cf.HARTREE
+        assert np.allclose(e, [ref, ref], rtol=1e-11, atol=0)
+
+
+def test_two_radius_trimer_third_order_shares():
+    """SCS off, a triangle with r_MBD,1 above every edge plus the buffer, edge a-b inside
+    the f_LR buffer of r_MBD,2 and the other edges below it.  In the frames of a and b
+    the a-b pair touches the central atom (p = 1, no cut); in the frame of c it does
+    not (p = 2, Sec. III.A).  Each atom's third-order term is one third of the ATM
+    energy, times f_LR(r_ab; r_MBD,2) for c only."""
+    pos = np.array([[0.0, 0.0, 0.0], [3.62, 0.0, 0.0], [1.6, 2.4, 0.5]])
+    r1, r2, rb = 5.0, 4.0, 0.5
+    st = _open(pos, species=[C_IDX, SPECIES_INDEX["O"], SPECIES_INDEX["H"]], nu=[0.85, 0.7, 0.9])
+    e2 = oracle.lmbd_energies(st, _radii_params(NO_SCS, 5.0, r1, r2, n_max=2), SPECIES_TABLE)
+    e3 = oracle.lmbd_energies(st, _radii_params(NO_SCS, 5.0, r1, r2, n_max=3), SPECIES_TABLE)
+    a, w, R = _free(st)
+    x = pos / cf.BOHR
+    f = 1.0
+    for i, j in ((0, 1), (1, 2), (2, 0)):
+        f *= cf.fermi(np.linalg.norm(x[i] - x[j]), 0.83 * (R[i] + R[j]))
+    atm = cf.c9_atm(a[0], w[0], a[1], w[1], a[2], w[2]) * f * cf.atm_geometry_factor(*x) * cf.HARTREE
+    phi = cf.smooth_cutoff(np.linalg.norm(pos[1] - pos[0]), r2, rb)
+    assert 0.05 < phi < 0.95
+    assert np.linalg.norm(pos[2] - pos[0]) < r2 - rb and np.linalg.norm(pos[2] - pos[1]) < r2 - rb
+    assert np.allclose(e3 - e2, np.array([1.0, 1.0, phi]) * atm / 3.0, rtol=1e-10, atol=0)
+
+
+def test_scs_dimer_inside_the_short_range_buffer():
+    """Two atoms inside the f_SR buffer of r_SCS: the independent solve with the tensor
+    scaled by the C1 cubic switch reproduces the oracle's local SCS (Sec. III.B f_SR)."""
+    rs, rb = 3.0, 0.5
+    for r_A in (2.62, 2.86):
+        st = _open([[0, 0, 0], _at_distance(r_A)], species=[C_IDX, SPECIES_INDEX["N"]], nu=[0.8, 0.95])
+        prm = _params(rs, rs)
+        got = oracle.scs_central(st, prm, SPECIES_TABLE)
+        a0, w0, R = _free(st)
+        x = st.pos / cf.BOHR
+        for q, w in enumerate(np.concatenate([[0.0], prm.omega])):
+            ab = a0 / (1.0 + (w / w0) ** 2)
+            ref = _solve_scs_fd(x, ab, R, rc=rs / cf.BOHR, rb=rb / cf.BOHR)
+            assert np.allclose(got[:, q], ref, rtol=1e-8)
+            if q == 0:   # the buffer matters here (at high frequency the screening fades)
+                unbuffered = _solve_scs_fd(x, ab, R, rc=rs / cf.BOHR)
+                assert np.all(np.abs(unbuffered / ref - 1.0) > 1e-4)
 
 
 # ------------------------------------------------------------------ limits (P5)
