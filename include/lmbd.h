@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LMBD_ABI_VERSION 3
+#define LMBD_ABI_VERSION 4
 
 typedef enum lmbd_status {
     LMBD_OK = 0,
@@ -105,16 +105,28 @@ typedef struct lmbd_params {
  *  pos         : [n_atoms][3] Cartesian positions, A
  *  species     : [n_atoms] index into the species table
  *  v_ratio     : [n_atoms] Hirshfeld-volume ratios nu (> 0)
- *  cell        : HOST array [3][3], rows = lattice vectors (A), or NULL for an open
- *                structure; used only along directions with pbc[d] != 0
- *  pbc         : periodicity per lattice direction
+ *  cell        : HOST array [3][3], rows = lattice vectors (A); required when any
+ *                pbc[d] != 0 (non-singular; a non-periodic row only fixes the
+ *                fractional frame of that direction, e.g. the normal of a slab),
+ *                ignored (may be NULL) for an open structure
+ *  pbc         : periodicity per lattice direction (any combination: open,
+ *                slab, wire or bulk); periodic images are taken only along the
+ *                directions with pbc[d] != 0
  *  r_scs       : SCS cutoff: K1 = B(r_scs), K2 = B(2 r_scs) \ B(r_scs) (Sec. III.B)
  *  r_nbr       : radius of the energy neighbourhood K = B(r_nbr) (Sec. III.A)
- *  r_mbd1/2    : f_LR cutoffs for pairs touching / not touching the central atom
+ *  r_mbd1/2    : f_LR cutoffs for pairs touching / not touching the central atom;
+ *                the call fails with LMBD_E_INVALID_ARG unless
+ *                r_nbr >= r_mbd1 >= r_mbd2 (Sec. III.A: the central atom has the
+ *                larger radius, and K must hold every pair that f_LR couples)
  *  e_weight    : [n_atoms] adjoint seeds w_k of the forces, or NULL for w_k = 1
  *  e_atom      : [n_atoms] output per-atom energies E_k (eV), or NULL
  *  forces      : [n_atoms][3] output forces (eV/A), or NULL for energies only
- *  alpha_scs0  : [n_atoms] output central static SCS polarisabilities (bohr^3), or NULL */
+ *  alpha_scs0  : [n_atoms] output central static SCS polarisabilities (bohr^3), or NULL
+ *  dE_dv       : [n_atoms] output d( sum_k w_k E_k ) / d nu_i (eV), the exact
+ *                derivative with respect to the Hirshfeld-volume ratios (through
+ *                the TS polarisabilities, attenuation lengths and radii of
+ *                Sec. II.B), so that a caller can apply the chain rule of the
+ *                volume gradients of Sec. III.D outside the library; or NULL */
 typedef struct lmbd_structure {
     int64_t n_atoms;
     const double* pos;
@@ -130,6 +142,7 @@ typedef struct lmbd_structure {
     double* e_atom;
     double* forces;
     double* alpha_scs0;
+    double* dE_dv;
 } lmbd_structure;
 
 typedef struct lmbd_context lmbd_context;
@@ -188,7 +201,8 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
  * factorisation and first solve (one kernel), 4 refinement of the local SCS
  * solution (mixed path; empty in FP64), 5 local MBD energy
  * (+adjoint), 6 central-polarisability gather, 7 adjoint SCS solves, 8 SCS
- * pair gradients, 9 force gather. */
+ * pair gradients (and, when dE_dv is requested, the volume-ratio adjoint),
+ * 9 force gather. */
 #define LMBD_N_STAGES 10
 lmbd_status lmbd_set_profiling(lmbd_context* ctx, int32_t enable);
 /* ms: caller array of LMBD_N_STAGES doubles; stages not run in the last call read 0. */

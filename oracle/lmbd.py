@@ -166,9 +166,14 @@ def free_atom_terms(species_table, species, nu, omegas):
     r0 = tab[species, 2]
     om = 4.0 * c6 / (3.0 * a0 ** 2)
     w = np.asarray(omegas, dtype=np.float64)
-    abar = (a0 * nu)[:, None] / (1.0 + (w[None, :] / om[:, None]) ** 2)
+    if isinstance(nu, torch.Tensor):   # volume ratios as a differentiable torch tensor
+        lor = torch.as_tensor(1.0 / (1.0 + (w[None, :] / om[:, None]) ** 2), dtype=_DT)
+        abar = (torch.as_tensor(a0, dtype=_DT) * nu)[:, None] * lor
+        R = torch.as_tensor(r0, dtype=_DT) * nu ** (1.0 / 3.0)
+    else:
+        abar = (a0 * nu)[:, None] / (1.0 + (w[None, :] / om[:, None]) ** 2)
+        R = r0 * np.asarray(nu, dtype=np.float64) ** (1.0 / 3.0)
     sigma = (math.sqrt(2.0 / math.pi) * abar / 3.0) ** (1.0 / 3.0)
-    R = r0 * np.asarray(nu, dtype=np.float64) ** (1.0 / 3.0)
     return dict(abar=abar, sigma=sigma, R=R, alpha0=a0, r0=r0, omega_i=om)
 
 
@@ -452,8 +457,13 @@ def lmbd_energies(structure, prm, species_table, atoms=None, central=None):
     return e
 
 
-def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, timings=None):
+def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, timings=None, want_dv=False):
     """Per-atom energies (eV) and exact forces -d(sum_k w_k E_k)/dR (eV/A).
+
+    With ``want_dv`` a third array is returned: d(sum_k w_k E_k)/d nu (eV), the
+    derivative with respect to the Hirshfeld-volume ratios, which enter through
+    the TS polarisabilities, attenuation lengths and radii (Sec. II.B); the same
+    two reverse passes carry it.
 
     Reverse mode in two passes, mirroring the two stages: pass B differentiates
     each atom's MBD stage (its own local SCS included) and collects the
@@ -468,6 +478,12 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, 
     st, fa, images = _prepare(structure, prm, species_table)
     N = structure.n
     nw = len(prm.scs_omegas())
+    nu_t = None
+    if want_dv:
+        nu_t = torch.tensor(np.asarray(structure.nu, dtype=np.float64), dtype=_DT, requires_grad=True)
+
+    def fa_graph():   # free-atom terms; with want_dv a fresh graph from nu for every backward pass
+        return fa if nu_t is None else free_atom_terms(species_table, structure.species, nu_t, prm.scs_omegas())
     w = np.ones(N) if weights is None else np.asarray(weights, dtype=np.float64)
     ks = list(range(N)) if atoms is None else list(atoms)
     frames = {}
@@ -488,9 +504,10 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, 
     for k in ks:  # pass B
         fr = frame(k)
         p = fr.positions(pos_t, cell_t)
-        aloc = _scs_solve(fr, p, fa, prm)
+        fk = fa_graph()
+        aloc = _scs_solve(fr, p, fk, prm)
         acen = torch.tensor(central[fr.base[:fr.nK]], dtype=_DT, requires_grad=True)
-        ek = _mbd_energy(fr, p, aloc, acen, fa, prm)
+        ek = _mbd_energy(fr, p, aloc, acen, fk, prm)
         e[k] = float(ek.detach())
         if ek.requires_grad:
             (w[k] * ek).backward()
@@ -504,12 +521,14 @@ def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, 
         n_c += 1
         fr = frame(a)
         p = fr.positions(pos_t, cell_t)
-        aloc = _scs_solve(fr, p, fa, prm)
+        aloc = _scs_solve(fr, p, fa_graph(), prm)
         (aloc[:, 0] * torch.as_tensor(abar_c[a], dtype=_DT)).sum().backward()
     t4 = time.perf_counter()
     if timings is not None:
         timings.update(prepare_s=t1 - t0, central_s=t2 - t1, central_atoms=len(needed), pass_b_s=t3 - t2,
                        pass_b_atoms=len(ks), pass_c_s=t4 - t3, pass_c_atoms=n_c)
-    if pos_t.grad is None:   # no energy depends on a position (every atom isolated)
-        return e, np.zeros_like(st["pos"])
-    return e, -pos_t.grad.numpy().copy()
+    f = np.zeros_like(st["pos"]) if pos_t.grad is None else -pos_t.grad.numpy().copy()
+    if want_dv:   # (no gradient: no energy depends on a volume ratio)
+        dv = np.zeros(N) if nu_t.grad is None else nu_t.grad.numpy().copy()
+        return e, f, dv
+    return e, f

@@ -125,7 +125,7 @@ def _ptr(x):
 
 
 def compute_batch(structures, params: MethodParams, species_table, *, forces=True, ctx: Context = None,
-                  stream=None, want_alpha=False):
+                  stream=None, want_alpha=False, want_dv=False):
     """Energies and forces of several structures in one set of launches.
 
     ``structures``: list of dicts with keys pos (N,3), species (N,), v_ratio (N,),
@@ -133,7 +133,8 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
     optionally e_weight (N,).  Arrays are either all CUDA tensors (float64/int32,
     results are CUDA tensors, work on the current or given stream) or all host
     numpy arrays (results are numpy arrays).
-    Returns a list of dicts {energies, forces?, alpha_scs0?}.
+    Returns a list of dicts {energies, forces?, alpha_scs0?, dE_dv?} (dE_dv: the exact
+    derivative of sum_k w_k E_k with respect to the Hirshfeld-volume ratios, eV).
     """
     device_mode = isinstance(structures[0]["pos"], torch.Tensor) and structures[0]["pos"].is_cuda
     if ctx is None:
@@ -153,6 +154,7 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
             e = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
             f = torch.empty_like(pos) if forces else None
             a = torch.empty_like(e) if want_alpha else None
+            dv = torch.empty_like(e) if want_dv else None
         else:
             pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
             spc = np.ascontiguousarray(s["species"], dtype=np.int32)
@@ -162,19 +164,20 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
             e = np.empty(pos.shape[0])
             f = np.empty_like(pos) if forces else None
             a = np.empty_like(e) if want_alpha else None
+            dv = np.empty_like(e) if want_dv else None
         cell = s.get("cell")
         cell_np = None if cell is None else np.ascontiguousarray(
             cell.detach().cpu().numpy() if isinstance(cell, torch.Tensor) else cell, dtype=np.float64)
         pbc = s.get("pbc", (0, 0, 0))
         pbc = [int(bool(x)) for x in (pbc.tolist() if hasattr(pbc, "tolist") else pbc)]
         cut = s["cutoffs"]
-        keep.extend([pos, spc, nu, w, e, f, a, cell_np])
+        keep.extend([pos, spc, nu, w, e, f, a, dv, cell_np])
         descs[i] = C.StructureDesc(
             int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
             cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
             (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
-            float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a))
-        outs.append({"energies": e, "forces": f, "alpha_scs0": a})
+            float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a), _ptr(dv))
+        outs.append({"energies": e, "forces": f, "alpha_scs0": a, "dE_dv": dv})
     if device_mode:
         if stream is None:
             stream = torch.cuda.current_stream(structures[0]["pos"].device)
@@ -190,14 +193,15 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
 
 
 def compute(pos, species, v_ratio, *, cutoffs, params: MethodParams, species_table, cell=None,
-            pbc=None, e_weight=None, forces=True, ctx: Context = None, stream=None, want_alpha=False):
+            pbc=None, e_weight=None, forces=True, ctx: Context = None, stream=None, want_alpha=False,
+            want_dv=False):
     """Per-atom energies (eV) and forces (eV/A) of one structure."""
     if pbc is None:
         pbc = (1, 1, 1) if cell is not None else (0, 0, 0)
     s = dict(pos=pos, species=species, v_ratio=v_ratio, cell=cell, pbc=pbc, cutoffs=cutoffs,
              e_weight=e_weight)
     return compute_batch([s], params, species_table, forces=forces, ctx=ctx, stream=stream,
-                         want_alpha=want_alpha)[0]
+                         want_alpha=want_alpha, want_dv=want_dv)[0]
 
 
 def _host_desc(s, forces, keep):
@@ -222,7 +226,7 @@ def _host_desc(s, forces, keep):
         int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
         cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
         (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
-        float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a))
+        float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a), None)
     return d, {"energies": e, "forces": f, "alpha_scs0": a}
 
 
@@ -336,12 +340,13 @@ class LMBDEnergy(torch.autograd.Function):
     """Per-atom lMBD energies as a differentiable function of positions.
 
     backward() runs the library once more with the incoming gradient as the
-    adjoint seeds w_k and returns -forces = d(sum_k w_k E_k)/dR.
+    adjoint seeds w_k and returns -forces = d(sum_k w_k E_k)/dR and, when the
+    volume ratios require a gradient, dE_dv = d(sum_k w_k E_k)/d nu.
     """
 
     @staticmethod
     def forward(ctx, pos, species, v_ratio, cell, cutoffs, params, species_table):
-        out = compute(pos.detach(), species, v_ratio, cutoffs=cutoffs, params=params,
+        out = compute(pos.detach(), species, v_ratio.detach(), cutoffs=cutoffs, params=params,
                       species_table=species_table, cell=cell, forces=False)
         ctx.save_for_backward(pos, species, v_ratio)
         ctx.extra = (cell, cutoffs, params, species_table)
@@ -351,6 +356,8 @@ class LMBDEnergy(torch.autograd.Function):
     def backward(ctx, grad_e):
         pos, species, v_ratio = ctx.saved_tensors
         cell, cutoffs, params, species_table = ctx.extra
-        out = compute(pos.detach(), species, v_ratio, cutoffs=cutoffs, params=params,
-                      species_table=species_table, cell=cell, e_weight=grad_e.contiguous(), forces=True)
-        return -out["forces"], None, None, None, None, None, None
+        want_dv = ctx.needs_input_grad[2]
+        out = compute(pos.detach(), species, v_ratio.detach(), cutoffs=cutoffs, params=params,
+                      species_table=species_table, cell=cell, e_weight=grad_e.contiguous(), forces=True,
+                      want_dv=want_dv)
+        return -out["forces"], None, out["dE_dv"] if want_dv else None, None, None, None, None

@@ -69,6 +69,37 @@ __global__ void __launch_bounds__(256) k_gather_forces(int n, int nslices, int64
     }
 }
 
+// dv[a] = (sum_{s in list(a)} sum_w cnu[slot(base s, rev)][w]) / nu_a; one wavefront per
+// atom, lanes over sites, a fixed xor tree over the lanes
+__global__ void __launch_bounds__(256) k_gather_nu(int n, int nw, const Counts* __restrict__ counts,
+                                                   const int64_t* __restrict__ site_off,
+                                                   const Site* __restrict__ sites,
+                                                   const int32_t* __restrict__ rev,
+                                                   const double* __restrict__ cnu,
+                                                   const double* __restrict__ nu, double* __restrict__ dv) {
+    const int lane = threadIdx.x & 63;
+    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (a >= n) return;
+    const int64_t off = site_off[a];
+    const int nall = counts[a].n_all;
+    double s = 0.0;
+    for (int e = lane; e < nall; e += 64) {
+        const int j = sites[off + e].base;
+        const double* c = cnu + (site_off[j] + rev[off + e]) * nw;
+        for (int w = 0; w < nw; ++w) s += c[w];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) dv[a] = s / nu[a];
+}
+
+hipError_t launch_gather_nu(hipStream_t st, int n, int nw, const Counts* counts, const int64_t* site_off,
+                            const Site* sites, const int32_t* rev, const double* cnu, const double* nu,
+                            double* dv) {
+    hipLaunchKernelGGL(k_gather_nu, dim3((n + 3) / 4), dim3(256), 0, st, n, nw, counts, site_off, sites, rev,
+                       cnu, nu, dv);
+    return hipGetLastError();
+}
+
 // cf[0][x] = sum over slices sl = 0 .. nslices-1 of cf[sl][x] (in slice order), so
 // that the force gather reads one slice
 __global__ void __launch_bounds__(256) k_slice_sum(int64_t len, int nslices, int64_t slice_stride,

@@ -101,9 +101,15 @@ __global__ void k_prep(int n, const double* __restrict__ pos_A, const int32_t* _
     if (S.periodic) {
         for (int d = 0; d < 3; ++d) {
             const double f = p[0] * S.inv[d] + p[1] * S.inv[3 + d] + p[2] * S.inv[6 + d];
-            const double fl = floor(f);
-            wr[d] = (int)fl;
-            int cc = (int)((f - fl) * S.ncell[d]);
+            int cc;
+            if (S.pbc[d]) {
+                const double fl = floor(f);
+                wr[d] = (int)fl;
+                cc = (int)((f - fl) * S.ncell[d]);
+            } else {   // a non-periodic direction of a periodic structure: cells over the atoms' extent
+                wr[d] = 0;
+                cc = (int)((f - S.flo[d]) / S.fext[d] * S.ncell[d]);
+            }
             c[d] = cc < 0 ? 0 : (cc >= S.ncell[d] ? S.ncell[d] - 1 : cc);
         }
     } else {
@@ -152,7 +158,7 @@ __device__ inline void visit_candidates(const NbrArgs& a, int k, int lane, int c
                 int sh[3] = {0, 0, 0};
                 bool inside = true;
                 for (int d = 0; d < 3; ++d) {
-                    if (S.periodic) {
+                    if (S.pbc[d]) {
                         const int m = S.ncell[d];
                         const int q = (cc[d] >= 0) ? cc[d] / m : -((-cc[d] + m - 1) / m);
                         sh[d] = q;

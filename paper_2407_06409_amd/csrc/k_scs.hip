@@ -1324,6 +1324,163 @@ __global__ void __launch_bounds__(kChunk, 3) k_scs_adjoint(ScsArgs a, int n1max,
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the Hirshfeld-volume ratios.  nu_b enters the local SCS system
+// through the TS values of its sites (Sec. II.B): abar = alpha0 nu / (1 +
+// (w/w_i)^2), sigma = (sqrt(2/pi) abar / 3)^(1/3) and R = R0 nu^(1/3), so
+//   nu_b dE/dnu_b = sum over the sites s of b, in every frame and frequency, of
+//   g_s = abar_s Abar_s + sigma_s Sbar_s / 3 + R_s Rbar_s / 3,
+// with Abar, Sbar, Rbar the adjoints of the site's abar, sigma and R.  With
+// lambda and X as in the force adjoint (B~ X = d, B~ lambda = Xbar):
+//   diagonal 1/abar_i of B~:           Abar_i += <lambda_i, X_i> / abar_i^2
+//   K1 pair T_SR(i, j) in B~:          with C the pair's adjoint contraction,
+//       sbar = <C, dT/ds>, Sbar = <C, dT/dS> (s = sqrt(sigma_i^2 + sigma_j^2),
+//       S = beta (R_i + R_j));         Sbar_i += sbar sigma_i / s, Rbar_i += beta Sbar
+//   shell pair T_SR(i, q) abar_q in d: Abar_q -= <lambda_i, T>, and the same
+//       sigma/R terms with C = -abar_q sym(lambda_i).
+// One thread per site of the frame (K1 sites, then shell sites) forms its g_s
+// from its own pair lists in list order, so the sums have a fixed order.
+// Evaluated in FP64 on both paths.
+// ---------------------------------------------------------------------------
+struct SrPairNu {
+    double A, B;     // T = A rhat rhat^T + B I
+    double As, Bs;   // dT/ds
+    double AS, BS;   // dT/dS
+};
+
+__device__ inline SrPairNu sr_pair_nu(double r, double s, double S, double damp_d, double rc, double rb, double wmul) {
+    const double c = kTwoOverSqrtPi;
+    const double u = r / s;
+    const double e = exp(-u * u);
+    const double g = erf(u) - c * u * e;
+    const double ir3 = 1.0 / (r * r * r);
+    const double u3e = u * u * u * e;
+    const double Ac = -(3.0 * g - 2.0 * c * u3e) * ir3, Bc = g * ir3;
+    // d/ds at fixed r (u = r/s): dA/ds = 4 c u^5 e / (s r^3), dB/ds = -2 c u^3 e / (s r^3)
+    const double Acs = 4.0 * c * u3e * u * u * ir3 / s, Bcs = -2.0 * c * u3e * ir3 / s;
+    double dfdr, dfdS, dcut;
+    const double f = fermi<double>(r, S, damp_d, dfdr, dfdS);
+    const double fc = cutoff_poly<double>(r, rc, rb, dcut);
+    const double w = wmul * fc * (1.0 - f), wS = -wmul * fc * dfdS;
+    return SrPairNu{w * Ac, w * Bc, w * Acs, w * Bcs, wS * Ac, wS * Bc};
+}
+
+// <C, a rhat rhat^T + b I> for a symmetric C
+__device__ inline double radial_contract(const double C[9], const double rh[3], double a, double b) {
+    double rCr = 0.0;
+    for (int q = 0; q < 3; ++q)
+        for (int m = 0; m < 3; ++m) rCr += rh[q] * C[3 * q + m] * rh[m];
+    return a * rCr + b * (C[0] + C[4] + C[8]);
+}
+
+__global__ void __launch_bounds__(256) k_scs_nu(ScsArgs a, int n1max, int n2max) {
+    extern __shared__ double lds[];
+    const int k = a.order[blockIdx.x];
+    const int w = blockIdx.y;
+    const Counts cnt = a.counts[k];
+    const int n1 = cnt.n1, n12 = cnt.n12, n2 = n12 - n1, nall = cnt.n_all;
+    const int N = 3 * n1;
+    const double rc = a.sinfo[a.atom_struct[k]].r_scs;
+    ScsLds L = scs_assemble_lds(lds, n1max, n2max, false);
+    const double* X = a.xsol + a.x_off[k] + (size_t)w * N * 3;
+    const double* Y = a.lam + a.x_off[k] + (size_t)w * N * 3;
+    const int32_t* seg = pair_segs(a, k);
+    const int32_t* seg_i = seg;
+    const int32_t* seg_q = seg + (n1 + 1);
+    const int32_t* seg_a = seg + (n12 + 2);
+    const int32_t* seg_b = seg + (n12 + n1 + 3);
+    const int32_t* li = a.pl_i + a.pl_off[k];
+    const int32_t* lq = a.pl_q + a.pl_off[k];
+    const int32_t* la = li + (int64_t)n1 * n2;
+    const int32_t* lb = lq + (int64_t)n1 * n2;
+    double* out = a.cnu + a.site_off[k] * a.nw + w;
+    load_sites(a, k, w, n1, n12, L);
+    __syncthreads();
+    // sbar and Sbar of one pair to the sigma/R part of a site's g
+    auto sr_share = [&](double sig, double Rs, double s, double sbar, double Sbar) {
+        return sbar * sig * sig / (3.0 * s) + a.beta * Sbar * Rs / 3.0;
+    };
+    for (int t = threadIdx.x; t < nall; t += blockDim.x) {
+        double g = 0.0;
+        if (t < n1) {
+            const int i = t;
+            double Xi[9], Yi[9], lam[9];
+            for (int e = 0; e < 9; ++e) {
+                Xi[e] = X[9 * i + e];
+                Yi[e] = Y[9 * i + e];
+            }
+            double yx = 0.0;
+            for (int e = 0; e < 9; ++e) yx += Yi[e] * Xi[e];
+            g += yx / L.ab[i];
+            // K1 x K1 pairs (i, j): first those with i < j (i's run of the a-major list,
+            // whose majors are in scrambled order, so the run ends where the major
+            // changes), then those with j < i (i's segment of the b-side index list)
+            for (int side = 0; side < 2; ++side) {
+                const int pb = side == 0 ? seg_a[i] : seg_b[i], pe = side == 0 ? seg_a[n1] : seg_b[i + 1];
+                for (int p = pb; p < pe; ++p) {
+                    if (side == 0 && (la[p] >> 16) != i) break;
+                    const int32_t ent = side == 0 ? la[p] : la[lb[p]];
+                    const int j = side == 0 ? (ent & 0xFFFF) : (ent >> 16);
+                    const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+                    const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                    const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+                    const double s = sqrt(L.sg[i] * L.sg[i] + L.sg[j] * L.sg[j]);
+                    const SrPairNu tp = sr_pair_nu(r, s, a.beta * (L.R[i] + L.R[j]), a.damp_d, rc, a.r_buf, 1.0);
+                    double C[9];
+                    for (int q = 0; q < 3; ++q)
+                        for (int c = 0; c < 3; ++c) {
+                            double s1 = 0.0;
+                            for (int m = 0; m < 3; ++m)
+                                s1 += Yi[3 * q + m] * X[9 * j + 3 * c + m] + Yi[3 * c + m] * X[9 * j + 3 * q + m] +
+                                      Xi[3 * q + m] * Y[9 * j + 3 * c + m] + Xi[3 * c + m] * Y[9 * j + 3 * q + m];
+                            C[3 * q + c] = -0.5 * s1;
+                        }
+                    g += sr_share(L.sg[i], L.R[i], s, radial_contract(C, rh, tp.As, tp.Bs),
+                                  radial_contract(C, rh, tp.AS, tp.BS));
+                }
+            }
+            // K1 x shell pairs (i, q)
+            for (int e = 0; e < 3; ++e)
+                for (int c = 0; c < 3; ++c) lam[3 * e + c] = 0.5 * (Yi[3 * e + c] + Yi[3 * c + e]);
+            for (int p = seg_i[i]; p < seg_i[i + 1]; ++p) {
+                const int q = lq[li[p]] >> 16;
+                const double v[3] = {L.px[i] - L.qx[q], L.py[i] - L.qy[q], L.pz[i] - L.qz[q]};
+                const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+                const double s = sqrt(L.sg[i] * L.sg[i] + L.qsg[q] * L.qsg[q]);
+                double fin, dfin;
+                inner_buffer(r, a.r_inner, fin, dfin);
+                const SrPairNu tp = sr_pair_nu(r, s, a.beta * (L.R[i] + L.qR[q]), a.damp_d, rc, a.r_buf, fin);
+                const double m = -L.qab[q];
+                g += sr_share(L.sg[i], L.R[i], s, m * radial_contract(lam, rh, tp.As, tp.Bs),
+                              m * radial_contract(lam, rh, tp.AS, tp.BS));
+            }
+        } else if (t < n12) {
+            const int q = t - n1;
+            // q's run of the shell-major list (majors in scrambled order: the run ends
+            // where the major changes)
+            for (int p = seg_q[q]; p < seg_q[n2] && (lq[p] >> 16) == q; ++p) {
+                const int i = lq[p] & 0xFFFF;
+                const double v[3] = {L.px[i] - L.qx[q], L.py[i] - L.qy[q], L.pz[i] - L.qz[q]};
+                const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+                const double s = sqrt(L.sg[i] * L.sg[i] + L.qsg[q] * L.qsg[q]);
+                double fin, dfin;
+                inner_buffer(r, a.r_inner, fin, dfin);
+                const SrPairNu tp = sr_pair_nu(r, s, a.beta * (L.R[i] + L.qR[q]), a.damp_d, rc, a.r_buf, fin);
+                double lam[9];
+                for (int e = 0; e < 3; ++e)
+                    for (int c = 0; c < 3; ++c) lam[3 * e + c] = 0.5 * (Y[9 * i + 3 * e + c] + Y[9 * i + 3 * c + e]);
+                const double m = -L.qab[q];
+                g += -L.qab[q] * radial_contract(lam, rh, tp.A, tp.B);   // abar_q Abar_q
+                g += sr_share(L.qsg[q], L.qR[q], s, m * radial_contract(lam, rh, tp.As, tp.Bs),
+                              m * radial_contract(lam, rh, tp.AS, tp.BS));
+            }
+        }
+        out[(size_t)t * a.nw] = g;   // sites beyond the SCS shell take no share
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Pair lists of one atom (frequency independent).  A shell site q couples to a
 // K1 site i when r_iq < r_scs, two K1 sites a < b when r_ab < r_scs (beyond,
 // f_SR vanishes).  Each coupling appears once; the second list of each kind
@@ -1594,6 +1751,11 @@ hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool m
     const size_t ls = scs_solve_lds_bytes(n1max, mixed);
     if (mixed) hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
     else hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
+    return hipGetLastError();
+}
+
+hipError_t launch_scs_nu(hipStream_t st, const ScsArgs& a, int n1max, int n2max) {
+    hipLaunchKernelGGL(k_scs_nu, dim3(a.n, a.nw), dim3(256), dvec_lds_bytes(n1max, n2max), st, a, n1max, n2max);
     return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ struct lmbd_context {
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
     DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam;
-    DBuf e_out, f_out, a_out, order;
+    DBuf e_out, f_out, a_out, dv_out, order;
     DBuf tabs;   // one buffer holding the per-atom plan tables (pl_off .. order are views into it)
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
@@ -85,7 +85,7 @@ struct lmbd_context {
         &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
-        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->dv_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
         &c->order, &c->tabs, &c->wcounts
 
 namespace {
@@ -183,9 +183,12 @@ lmbd_status check_struct(lmbd_context* ctx, const lmbd_params* p, const lmbd_str
         return fail(ctx, LMBD_E_INVALID_ARG, "cutoffs must be positive");
     if (!(p->r_buf < s.r_scs) || !(p->r_buf < s.r_mbd1) || !(p->r_buf < s.r_mbd2))
         return fail(ctx, LMBD_E_INVALID_ARG, "r_buf must be smaller than every cutoff");
+    // Sec. III.A: the central atom's radius is the larger one, and K = B(r_nbr) must hold
+    // every pair that f_LR couples (else a site leaving K would cut a coupled pair)
+    if (s.r_mbd1 < s.r_mbd2) return fail(ctx, LMBD_E_INVALID_ARG, "r_mbd1 must not be smaller than r_mbd2");
+    if (s.r_nbr < s.r_mbd1) return fail(ctx, LMBD_E_INVALID_ARG, "r_nbr must not be smaller than r_mbd1");
     const int npbc = (s.pbc[0] != 0) + (s.pbc[1] != 0) + (s.pbc[2] != 0);
-    if (npbc != 0 && npbc != 3) return fail(ctx, LMBD_E_UNSUPPORTED, "mixed periodicity is not supported");
-    if (npbc == 3) {
+    if (npbc > 0) {
         if (!s.cell) return fail(ctx, LMBD_E_INVALID_ARG, "periodic structure without a cell");
         for (int i = 0; i < 9; ++i)
             if (!std::isfinite(s.cell[i])) return fail(ctx, LMBD_E_INVALID_ARG, "non-finite cell");
@@ -221,8 +224,9 @@ lmbd_status make_struct_info(lmbd_context* ctx, const lmbd_structure& s, const d
     si.cell_offset = cell_offset;
     si.n_atoms = (int)s.n_atoms;
     const int n = (int)s.n_atoms;
-    if (s.pbc[0] && s.pbc[1] && s.pbc[2]) {
+    if (s.pbc[0] || s.pbc[1] || s.pbc[2]) {
         si.periodic = 1;
+        for (int d = 0; d < 3; ++d) si.pbc[d] = s.pbc[d] != 0;
         for (int i = 0; i < 9; ++i) si.cell[i] = s.cell[i] / kBohr;
         double det;
         inv3(si.cell, si.inv, det);
@@ -233,12 +237,31 @@ lmbd_status make_struct_info(lmbd_context* ctx, const lmbd_structure& s, const d
             const double* b = si.cell + 3 * ((d + 2) % 3);
             const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2],
                          cz = a[0] * b[1] - a[1] * b[0];
-            const double perp = vol / std::sqrt(cx * cx + cy * cy + cz * cz);
-            int nc = (int)std::floor(2.0 * perp / si.r_big);
-            nc = std::max(1, std::min(nc, 64));
-            si.ncell[d] = nc;
-            si.reach[d] = (int)std::ceil(si.r_big * nc / perp * (1.0 + 1e-9));
-            if (si.reach[d] > 60) return fail(ctx, LMBD_E_UNSUPPORTED, "cutoff too large for the cell");
+            const double perp = vol / std::sqrt(cx * cx + cy * cy + cz * cz);   // spacing of the lattice planes
+            if (si.pbc[d]) {
+                int nc = (int)std::floor(2.0 * perp / si.r_big);
+                nc = std::max(1, std::min(nc, 64));
+                si.ncell[d] = nc;
+                si.reach[d] = (int)std::ceil(si.r_big * nc / perp * (1.0 + 1e-9));
+                if (si.reach[d] > 60) return fail(ctx, LMBD_E_UNSUPPORTED, "cutoff too large for the cell");
+            } else {
+                // no images along d: cells of at least r_big over the atoms' extent
+                double lo = 1e300, hi = -1e300;
+                for (int i = 0; i < n; ++i) {
+                    const double x = pos_host[3 * i] / kBohr, y = pos_host[3 * i + 1] / kBohr,
+                                 z = pos_host[3 * i + 2] / kBohr;
+                    if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+                        return fail(ctx, LMBD_E_INVALID_ARG, "non-finite position");
+                    const double f = x * si.inv[d] + y * si.inv[3 + d] + z * si.inv[6 + d];
+                    lo = std::min(lo, f);
+                    hi = std::max(hi, f);
+                }
+                si.flo[d] = lo;
+                si.fext[d] = std::max(hi - lo, 1e-9);
+                int nc = (int)std::floor(si.fext[d] * perp / si.r_big);
+                si.ncell[d] = std::max(1, std::min(nc, 64));
+                si.reach[d] = 1;
+            }
         }
     } else {
         si.periodic = 0;
@@ -455,7 +478,7 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
     if (forces) {
         const std::pair<DBuf*, size_t> F2[] = {
             {&c->ca, TS * nw * D}, {&c->cf, (size_t)(1 + nw) * TS * 3 * D}, {&c->f_out, 3 * N * D},
-            {&c->lam, (size_t)P.x_len * D}};
+            {&c->lam, (size_t)P.x_len * D}, {&c->dv_out, N * D}};
         for (const auto& e : F2) {
             const hipError_t r = get(*e.first, e.second);
             if (r != hipSuccess) return r;
@@ -606,9 +629,16 @@ lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<
         for (int d = 0; d < 3; ++d) {
             if (S.periodic) {
                 const double f = p[3 * g] * S.inv[d] + p[3 * g + 1] * S.inv[3 + d] + p[3 * g + 2] * S.inv[6 + d];
-                const double fl = std::floor(f);
-                wrap[3 * g + d] = (int)fl;
-                c[d] = std::min(std::max((int)((f - fl) * S.ncell[d]), 0), S.ncell[d] - 1);
+                int cc;
+                if (S.pbc[d]) {
+                    const double fl = std::floor(f);
+                    wrap[3 * g + d] = (int)fl;
+                    cc = (int)((f - fl) * S.ncell[d]);
+                } else {
+                    wrap[3 * g + d] = 0;
+                    cc = (int)((f - S.flo[d]) / S.fext[d] * S.ncell[d]);
+                }
+                c[d] = std::min(std::max(cc, 0), S.ncell[d] - 1);
             } else {
                 const double h = S.cell[4 * d] / S.ncell[d];
                 c[d] = std::min(std::max((int)((p[3 * g + d] - S.origin[d]) / h), 0), S.ncell[d] - 1);
@@ -637,7 +667,7 @@ lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<
                     int sh[3] = {0, 0, 0};
                     bool inside = true;
                     for (int d = 0; d < 3; ++d) {
-                        if (S.periodic) {
+                        if (S.pbc[d]) {
                             const int m = S.ncell[d];
                             const int q = (cc[d] >= 0) ? cc[d] / m : -((-cc[d] + m - 1) / m);
                             sh[d] = q;
@@ -695,7 +725,7 @@ lmbd_status analyse_structure(const lmbd_params* params, const lmbd_structure& s
     }
     out.cnt.clear();
     out.cnt.reserve((size_t)s.n_atoms);
-    out.forces = s.forces != nullptr;
+    out.forces = s.forces != nullptr || s.dE_dv != nullptr;   // both need the adjoint passes
     return host_counts(ctx, s, out.cnt, out.n_cells);
 }
 
@@ -772,12 +802,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
             return fail(ctx, LMBD_E_INVALID_ARG, "species data must be positive");
     if (!structs || n_structs < 1) return fail(ctx, LMBD_E_INVALID_ARG, "no structures");
     if (mem != LMBD_HOST && mem != LMBD_DEVICE) return fail(ctx, LMBD_E_INVALID_ARG, "bad mem");
-    bool forces = false;
+    bool forces = false;   // the adjoint passes run (forces or volume-ratio derivatives requested)
+    bool want_dv = false;
     int64_t N64 = 0;
     for (int s = 0; s < n_structs; ++s) {
         st = check_struct(ctx, params, structs[s]);
         if (st != LMBD_OK) return st;
-        forces = forces || structs[s].forces != nullptr;
+        forces = forces || structs[s].forces != nullptr || structs[s].dE_dv != nullptr;
+        want_dv = want_dv || structs[s].dE_dv != nullptr;
         N64 += structs[s].n_atoms;
     }
     if (N64 > INT32_MAX / 8) return fail(ctx, LMBD_E_UNSUPPORTED, "too many atoms in one call");
@@ -813,7 +845,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         const lmbd_structure& S = structs[s];
         const int n = (int)S.n_atoms;
         const double* ph = S.pos;
-        if (mem == LMBD_DEVICE && !(S.pbc[0] && S.pbc[1] && S.pbc[2])) {
+        if (mem == LMBD_DEVICE && !(S.pbc[0] && S.pbc[1] && S.pbc[2])) {   // extents of the non-periodic directions
             pos_host[s].resize(3 * (size_t)n);
             HIP_TRY(hipMemcpyAsync(pos_host[s].data(), S.pos, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
             HIP_TRY(hipStreamSynchronize(stream));
@@ -1108,6 +1140,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         HIP_TRY(mark(7, 1));
         HIP_TRY(mark(8, 0));
         HIP_TRY(launch_scs_adjoint(stream, sa, P.n1max, P.n2max, mixed));
+        if (want_dv) {   // the central adjoints are gathered: their slots take the volume-ratio shares
+            sa.cnu = as<double>(ctx->ca);
+            HIP_TRY(launch_scs_nu(stream, sa, P.n1max, P.n2max));
+            HIP_TRY(launch_gather_nu(stream, N, nw, sa.counts, sa.site_off, sa.sites, as<int32_t>(ctx->rev),
+                                     sa.cnu, as<double>(ctx->in_nu), as<double>(ctx->dv_out)));
+        }
         HIP_TRY(mark(8, 1));
         HIP_TRY(mark(9, 0));
         HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,
@@ -1127,6 +1165,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
                                    stream));
         if (S.alpha_scs0)
             HIP_TRY(hipMemcpyAsync(S.alpha_scs0, as<double>(ctx->a_out) + off, sizeof(double) * n, d2o, stream));
+        if (S.dE_dv)
+            HIP_TRY(hipMemcpyAsync(S.dE_dv, as<double>(ctx->dv_out) + off, sizeof(double) * n, d2o, stream));
         off += n;
     }
     HIP_TRY(copy_d2h_sync(ctx, flags, ctx->flags.p, sizeof(flags), stream));

@@ -47,7 +47,10 @@ struct StructInfo {
     double cell[9];      // rows = lattice vectors, bohr (open: diagonal grid box)
     double inv[9];       // inverse of cell: frac = pos @ inv
     double origin[3];    // open structures: lower corner of the bounding box, bohr
-    int periodic;        // 1 = periodic in all three directions, 0 = open
+    double flo[3];       // periodic structures, non-periodic directions: lowest fractional coordinate
+    double fext[3];      //   and the extent of the fractional coordinates (cells span it)
+    int periodic;        // 1 = periodic along at least one lattice direction, 0 = open
+    int pbc[3];          // periodic along lattice direction d
     int ncell[3];        // cell-list grid
     int reach[3];        // cells to visit on each side
     int cell_offset;     // first batch-global cell index
@@ -203,6 +206,7 @@ struct ScsArgs {
     const double* abar_cen;  // [n][nw]: adjoint of the central polarisabilities
     double* cf;              // force contributions [nw][total_sites][3] (slice base)
     int64_t cf_slice;        // stride between frequency slices
+    double* cnu;             // volume-ratio adjoint numerators [total_sites][nw] (dE_dv)
 };
 
 struct MbdArgs {
@@ -260,6 +264,12 @@ hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mi
 hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
+// per (atom, frequency) and site: the numerator of the site's share of d E / d nu (into a.cnu)
+hipError_t launch_scs_nu(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
+// dE_dv[a] = (sum over the slots that refer to a, over frequencies) / nu_a
+hipError_t launch_gather_nu(hipStream_t st, int n, int nw, const Counts* counts, const int64_t* site_off,
+                            const Site* sites, const int32_t* rev, const double* cnu, const double* nu,
+                            double* dv);
 size_t mbd_lds_bytes(int nkmax, int nq, int n_max);
 hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,

@@ -33,24 +33,69 @@ def sample(n, m, seed):
     return sorted(int(x) for x in np.random.Generator(np.random.PCG64(seed)).choice(n, m, replace=False))
 
 
+# The oracle evaluates one central atom at a time; the fixtures split their atoms
+# over worker processes (one torch thread each).  A force fixture of a partial sum
+# is the sum of the single-atom terms' forces (the forces are linear in the
+# weights), added in atom order.
+_JOB = {}
+
+
+def _init_worker():
+    import torch
+    torch.set_num_threads(1)
+
+
+def _energy_of(k):
+    st, cut = _JOB["st"], _JOB["cut"]
+    return float(oracle.lmbd_energies(st, params(cut), SPECIES_TABLE, atoms=[k])[k])
+
+
+def _forces_of(k):
+    st, cut = _JOB["st"], _JOB["cut"]
+    w = np.zeros(st.n)
+    w[k] = 1.0
+    e, f = oracle.lmbd_energy_forces(st, params(cut), SPECIES_TABLE, weights=w, atoms=[k])
+    return float(e[k]), f
+
+
+def _pool_map(fn, st, cut, items):
+    import multiprocessing as mp
+    _JOB.update(st=st, cut=cut)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(min(len(items), os.cpu_count() or 1), initializer=_init_worker) as pool:
+        return pool.map(fn, items, chunksize=1)
+
+
 def energies_fixture(name, st, cut, atoms):
     t = time.time()
-    e = oracle.lmbd_energies(st, params(cut), SPECIES_TABLE, atoms=atoms)
+    e = _pool_map(_energy_of, st, cut, list(atoms))
     print(f"{name}: energies of {len(atoms)} atoms in {time.time() - t:.1f} s", flush=True)
-    return {"atoms": atoms, "energies_eV": [float(e[a]) for a in atoms]}
+    return {"atoms": list(atoms), "energies_eV": e}
 
 
 def forces_fixture(name, st, cut, atoms):
     """Forces of the partial sum sum_{k in atoms} E_k (weights 1 on the sample, 0 elsewhere)."""
     t = time.time()
-    w = np.zeros(st.n)
-    w[atoms] = 1.0
-    e, f = oracle.lmbd_energy_forces(st, params(cut), SPECIES_TABLE, weights=w, atoms=atoms)
+    parts = _pool_map(_forces_of, st, cut, list(atoms))
+    f = np.zeros((st.n, 3))
+    for _, fk in parts:
+        f += fk
     nz = np.nonzero(np.any(f != 0.0, axis=1))[0]
     print(f"{name}: forces of the {len(atoms)}-atom partial sum in {time.time() - t:.1f} s "
           f"({len(nz)} atoms with nonzero force)", flush=True)
-    return {"weighted_atoms": atoms, "force_atoms": [int(a) for a in nz],
+    return {"weighted_atoms": list(atoms), "force_atoms": [int(a) for a in nz],
             "forces_eV_per_A": [[float(x) for x in f[a]] for a in nz]}
+
+
+def whole_fixture(name, st, cut):
+    """Every atom's energy and the forces of the whole energy (all weights 1)."""
+    t = time.time()
+    parts = _pool_map(_forces_of, st, cut, list(range(st.n)))
+    f = np.zeros((st.n, 3))
+    for _, fk in parts:
+        f += fk
+    print(f"{name}: energies and forces of all {st.n} atoms in {time.time() - t:.1f} s", flush=True)
+    return {"energies_eV": [e for e, _ in parts], "forces_eV_per_A": [[float(x) for x in fa] for fa in f]}
 
 
 def cutoff_6p8A():
@@ -70,18 +115,30 @@ def two_radius_6_3():
     return st, dict(r_scs=6.0, r_nbr=9.0, r_mbd1=6.0, r_mbd2=3.0)
 
 
+def small_hcno_box(n, rc):
+    """Periodic H/C/N/O cube at 1.0 g/cm^3 small enough that every atom's own
+    periodic images lie inside its SCS shell (edge below 2 r_SCS), as the
+    smallest periodic requests of the serving workload are."""
+    return C.hcno_box(n, 7000 + n), dict(r_scs=rc, r_nbr=rc, r_mbd1=rc, r_mbd2=rc)
+
+
 def fixture(name):
     if name == "C1728_pbc":
         st, cut = C.config_plain_pbc()
         return {"cutoffs": cut,
-                "energies": energies_fixture("C1728", st, cut, sample(st.n, 12, 7)),
-                "forces": forces_fixture("C1728", st, cut, sample(st.n, 3, 8))}
+                "energies": energies_fixture("C1728", st, cut, sample(st.n, 64, 7)),
+                "forces": forces_fixture("C1728", st, cut, sample(st.n, 16, 8))}
     if name == "HCNO4096_pbc":
         st, cut = C.config_diff_hcno()
-        return {"cutoffs": cut, "energies": energies_fixture("HCNO4096", st, cut, sample(st.n, 8, 9))}
+        return {"cutoffs": cut, "energies": energies_fixture("HCNO4096", st, cut, sample(st.n, 64, 9)),
+                "forces": forces_fixture("HCNO4096", st, cut, sample(st.n, 16, 15))}
     if name == "C13824_pbc":
         st, cut = C.config_mixed_pbc()
-        return {"cutoffs": cut, "energies": energies_fixture("C13824", st, cut, sample(st.n, 6, 10))}
+        return {"cutoffs": cut, "energies": energies_fixture("C13824", st, cut, sample(st.n, 64, 10))}
+    if name in ("HCNO50_pbc_5A", "HCNO100_pbc_6A"):
+        n, rc = (50, 5.0) if name == "HCNO50_pbc_5A" else (100, 6.0)
+        st, cut = small_hcno_box(n, rc)
+        return {"cutoffs": cut, "box_A": float(st.cell[0, 0]), "whole": whole_fixture(name, st, cut)}
     if name == "C1728_pbc_6p8A":
         st, cut = cutoff_6p8A()
         return {"cutoffs": cut,
@@ -97,7 +154,8 @@ def fixture(name):
 
 
 
-NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A", "C1728_pbc_two_radius"]
+NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A", "C1728_pbc_two_radius", "HCNO50_pbc_5A",
+         "HCNO100_pbc_6A"]
 
 
 def main():

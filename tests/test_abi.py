@@ -73,3 +73,19 @@ def test_bad_device_index_is_an_argument_error(lib):
     h = ctypes.c_void_p()
     assert lib.lmbd_create(-1, ctypes.byref(h)) == 1
     assert lib.lmbd_create(1 << 20, ctypes.byref(h)) == 1
+
+
+def test_radii_out_of_order_are_argument_errors(lib):
+    """r_nbr >= r_mbd1 >= r_mbd2 (Sec. III.A) is checked before anything touches a device."""
+    import numpy as np
+    from paper_2407_06409_amd import api, LmbdError
+    from workloads import frequency_grid
+    g = frequency_grid(12)
+    prm = api.MethodParams(omega=g[0], weight=g[1])
+    base = dict(pos=np.array([[0.0, 0, 0], [2.0, 0, 0]]), species=np.array([1, 1], np.int32),
+                v_ratio=np.array([0.9, 0.8]), cell=None, pbc=(0, 0, 0))
+    for cut in (dict(r_scs=4.0, r_nbr=5.0, r_mbd1=4.0, r_mbd2=4.5),     # r_mbd1 < r_mbd2
+                dict(r_scs=4.0, r_nbr=4.0, r_mbd1=5.0, r_mbd2=3.0)):    # r_nbr < r_mbd1
+        with pytest.raises(LmbdError) as ei:
+            api.estimate_footprint([dict(base, cutoffs=cut)], prm)
+        assert ei.value.code == "LMBD_E_INVALID_ARG"

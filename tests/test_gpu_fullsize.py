@@ -107,15 +107,26 @@ def test_c1728_two_radius_regime_matches_oracle(mode):
         assert de_m < 1e-5 and df_m < 1e-4
 
 
-def test_hcno4096_energies_match_oracle():
+def test_hcno4096_energies_and_partial_forces_match_oracle():
+    """Sampled energies and the forces of a 16-atom weighted partial sum (every atom
+    whose force it moves) against stored oracle values."""
     g = golden()["HCNO4096_pbc"]
     st, cut = C.config_diff_hcno()
     print(f"case HCNO4096 n={st.n}", flush=True)
     out = gpu_run(st, cut, forces=False)
     atoms = g["energies"]["atoms"]
     de = np.abs(out["energies"][atoms] - np.array(g["energies"]["energies_eV"])).max()
-    print(f"  max |dE| {de:.3e} eV", flush=True)
+    print(f"  max |dE| on {len(atoms)} sampled atoms: {de:.3e} eV", flush=True)
     assert de < 1e-8
+    w = np.zeros(st.n)
+    w[g["forces"]["weighted_atoms"]] = 1.0
+    part = gpu_run(st, cut, forces=True, weights=w)
+    ref = np.zeros((st.n, 3))
+    ref[g["forces"]["force_atoms"]] = np.array(g["forces"]["forces_eV_per_A"])
+    df = np.abs(part["forces"] - ref).max()
+    print(f"  max |dF| of the {len(g['forces']['weighted_atoms'])}-atom partial sum over all atoms: {df:.3e} eV/A "
+          f"(max |F| {np.abs(ref).max():.3e})", flush=True)
+    assert df < 1e-8
 
 
 def test_c13824_energies_match_oracle_fp64():

@@ -531,6 +531,51 @@ def test_forces_finite_difference_periodic_box():
     _fd_check(st, prm, [(1, 0), (5, 2), (13, 1)])
 
 
+# ------------------------------------------------ volume-ratio derivatives
+
+def test_volume_ratio_derivative_of_the_pairwise_dimer():
+    """SCS off, n_max = 2: E_a + E_b = -C6 f^2 / r^6 with C6 proportional to nu_a nu_b
+    and S = beta (R0_a nu_a^(1/3) + R0_b nu_b^(1/3)) (the screened radii reduce to the
+    TS ones); its nu-derivative in closed form."""
+    st = _open([[0, 0, 0], _at_distance(2.9)], species=[C_IDX, SPECIES_INDEX["O"]], nu=[0.8, 0.9])
+    prm = _params(NO_SCS, 8.0, grid=GRID200, n_max=2)
+    w = np.array([0.7, 1.3])
+    e, f, dv = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE, weights=w, want_dv=True)
+    a, om, R = _free(st)
+    r = 2.9 / cf.BOHR
+    S = 0.83 * (R[0] + R[1])
+    fe = cf.fermi(r, S)
+    c6 = cf.c6_casimir_polder(a[0], om[0], a[1], om[1])
+    share = -0.5 * c6 * fe * fe / r ** 6 * cf.HARTREE    # each atom's energy
+    assert np.allclose(e, [share, share], rtol=1e-11)
+    dfdS = -6.0 * r * fe * (1 - fe) / S ** 2
+    for b in range(2):
+        dS = 0.83 * R[b] / (3.0 * st.nu[b])
+        d_share = share * (1.0 / st.nu[b] + 2.0 * dfdS * dS / fe)
+        assert abs(dv[b] / (w.sum() * d_share) - 1.0) < 1e-10
+
+
+def test_volume_ratio_derivative_finite_difference():
+    """Screened H/C/N/O cluster (shell, inner buffer and blend active): d(sum_k w_k
+    E_k)/d nu against central differences of the energies."""
+    st = _rand_cluster(12, 91, box=5.5, dmin=1.4)
+    prm = _params(3.0, 4.0)
+    rng = np.random.default_rng(92)
+    w = rng.uniform(0.5, 1.5, st.n)
+    e, f, dv = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE, weights=w, want_dv=True)
+    e2, f2 = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE, weights=w)
+    assert np.allclose(e, e2, rtol=1e-13, atol=0) and np.allclose(f, f2, rtol=1e-11, atol=1e-15)
+    h = 1e-5
+    for b in (0, 4, 9):
+        sp_, sm_ = st.copy(), st.copy()
+        sp_.nu = st.nu.copy()
+        sm_.nu = st.nu.copy()
+        sp_.nu[b] += h
+        sm_.nu[b] -= h
+        fd = (w @ oracle.lmbd_energies(sp_, prm, SPECIES_TABLE) - w @ oracle.lmbd_energies(sm_, prm, SPECIES_TABLE)) / (2 * h)
+        assert abs(fd - dv[b]) < 1e-7 * max(1.0, abs(dv[b])), (b, fd, dv[b])
+
+
 # ------------------------------------------- two-point Lorentzian SCS model
 
 OMEGA_REF = 0.5

@@ -58,6 +58,26 @@ def hcno_box(n, seed, g_cm3=1.0, dmin=0.9, nu_lo=0.6, nu_hi=1.0):
     return Structure(pos, sp, nu, np.eye(3) * length, np.ones(3, dtype=bool), f"HCNO{n}-pbc")
 
 
+def carbon_slab(n, seed, length, thickness, pbc=(1, 1, 0), dmin=1.3, nu_lo=0.6, nu_hi=1.0):
+    """n C atoms periodic along the directions with pbc set (edge ``length``) and
+    confined to [0, thickness) along the others (a slab for pbc (1, 1, 0), a wire
+    for (1, 0, 0)).  The rows of the cell along non-periodic directions carry a
+    tilt: they only fix the fractional frame, never an image."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    span = [length if pbc[d] else thickness for d in range(3)]
+    box = [length if pbc[d] else thickness + 4.0 * length for d in range(3)]   # no clash across the gap
+    from .structures import _rsa
+    pos = _rsa(n, lambda r: r.uniform(0.0, 1.0, size=3) * np.array(span), dmin, (0, 0, 0), box, True, rng)
+    nu = rng.uniform(nu_lo, nu_hi, size=n)
+    cell = np.diag([length if pbc[d] else thickness + 20.0 for d in range(3)])
+    for d in range(3):
+        if not pbc[d]:
+            cell[d, (d + 1) % 3] = 3.0
+            cell[d, (d + 2) % 3] = -2.0
+    return Structure(pos, _carbon(n, rng), nu, cell, np.array([bool(x) for x in pbc]),
+                     f"C{n}-pbc{''.join(str(int(x)) for x in pbc)}")
+
+
 def hcno_cluster(n, seed, g_cm3=1.0, dmin=0.9, nu_lo=0.6, nu_hi=1.0):
     """n H/C/N/O atoms in an open sphere at the given mass density."""
     rng = np.random.Generator(np.random.PCG64(seed))
