@@ -180,6 +180,29 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params,
                                int32_t n_structs, const lmbd_structure* structs,
                                int32_t mem, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the same
+ * evaluation as lmbd_compute_batch, with the same arguments, outputs and status
+ * codes, but every workspace buffer is carved from a static device array of
+ * lmbd_static_scratch_bytes() bytes (64 MiB) that the library holds on each GPU
+ * it runs on until the process ends.  The call allocates and frees no device
+ * memory, and leaves the context's own cached buffers untouched.  A call whose
+ * exact footprint (lmbd_estimate_footprint) exceeds the array fails with
+ * LMBD_E_OOM_ADMISSION before any kernel runs; 64 MiB holds, for example, 64
+ * carbon atoms at a 5 A cutoff with forces in FP64.  Every call on one GPU
+ * shares that GPU's array and its contents are those of the last call: calls
+ * from several host threads on one GPU are serialised by the library, and a
+ * caller must not overlap such a call with another process's use of the same
+ * library copy on that GPU.  Inputs and outputs are the caller's, as in
+ * lmbd_compute_batch; the call returns once the outputs are written. */
+lmbd_status lmbd_compute_batch_static(lmbd_context* ctx, const lmbd_params* params,
+                                      int32_t n_species, const lmbd_species* species_table,
+                                      int32_t n_structs, const lmbd_structure* structs,
+                                      int32_t mem, void* hip_stream);
+
+/* Size in bytes of the static device array behind lmbd_compute_batch_static. */
+size_t lmbd_static_scratch_bytes(void);
+
 /* Single-structure convenience form of lmbd_compute_batch. */
 lmbd_status lmbd_compute(lmbd_context* ctx, const lmbd_params* params,
                          int32_t n_species, const lmbd_species* species_table,

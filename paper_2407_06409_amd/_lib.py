@@ -96,6 +96,10 @@ def lib():
     L.lmbd_compute_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
                                      ctypes.POINTER(Species), ctypes.c_int32,
                                      ctypes.POINTER(StructureDesc), ctypes.c_int32, ctypes.c_void_p]
+    L.lmbd_compute_batch_static.restype = ctypes.c_int
+    L.lmbd_compute_batch_static.argtypes = L.lmbd_compute_batch.argtypes
+    L.lmbd_static_scratch_bytes.restype = ctypes.c_size_t
+    L.lmbd_static_scratch_bytes.argtypes = []
     L.lmbd_compute.restype = ctypes.c_int
     L.lmbd_compute.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_int32,
                                ctypes.POINTER(Species), ctypes.POINTER(StructureDesc), ctypes.c_int32,
@@ -134,5 +138,6 @@ EXPORTED = ["lmbd_abi_version", "lmbd_create", "lmbd_destroy", "lmbd_set_memory_
             "lmbd_compute_batch", "lmbd_compute", "lmbd_estimate_footprint", "lmbd_status_string",
             "lmbd_last_error", "lmbd_set_profiling", "lmbd_stage_times", "lmbd_stage_name",
             "lmbd_server_create", "lmbd_server_destroy", "lmbd_submit", "lmbd_poll", "lmbd_wait",
-            "lmbd_release", "lmbd_server_get_stats", "lmbd_set_mbd_product"]
+            "lmbd_release", "lmbd_server_get_stats", "lmbd_set_mbd_product", "lmbd_compute_batch_static",
+            "lmbd_static_scratch_bytes"]
 N_STAGES = 10

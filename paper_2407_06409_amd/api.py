@@ -125,7 +125,7 @@ def _ptr(x):
 
 
 def compute_batch(structures, params: MethodParams, species_table, *, forces=True, ctx: Context = None,
-                  stream=None, want_alpha=False, want_dv=False):
+                  stream=None, want_alpha=False, want_dv=False, static_scratch=False):
     """Energies and forces of several structures in one set of launches.
 
     ``structures``: list of dicts with keys pos (N,3), species (N,), v_ratio (N,),
@@ -135,6 +135,8 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
     numpy arrays (results are numpy arrays).
     Returns a list of dicts {energies, forces?, alpha_scs0?, dE_dv?} (dE_dv: the exact
     derivative of sum_k w_k E_k with respect to the Hirshfeld-volume ratios, eV).
+    ``static_scratch`` calls the entry point that allocates no device memory (its
+    workspace is the library's static device array; small structures only).
     """
     device_mode = isinstance(structures[0]["pos"], torch.Tensor) and structures[0]["pos"].is_cuda
     if ctx is None:
@@ -186,7 +188,8 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
     else:
         hs = None
         mem = C.LMBD_HOST
-    st = ctx.lib.lmbd_compute_batch(ctx.handle, ctypes.byref(p), n_sp, sp, len(structures), descs, mem, hs)
+    entry = ctx.lib.lmbd_compute_batch_static if static_scratch else ctx.lib.lmbd_compute_batch
+    st = entry(ctx.handle, ctypes.byref(p), n_sp, sp, len(structures), descs, mem, hs)
     if st != 0:
         raise C.LmbdError(st, ctx.last_error())
     return outs

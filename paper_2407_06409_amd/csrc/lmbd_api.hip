@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -77,7 +78,24 @@ struct lmbd_context {
     hipEvent_t ev[2 * LMBD_N_STAGES] = {};
     bool ev_used[LMBD_N_STAGES] = {};
     double stage_ms[LMBD_N_STAGES] = {};
+    char* scratch = nullptr;   // device address of this device's static scratch array (set at creation)
 };
+
+// ---------------------------------------------------------------------------
+// Static scratch for lmbd_compute_batch_static: one file-scope device array per
+// GPU, held until the process ends.  Host code never passes the array's name to
+// a kernel: the device address of each GPU's copy is taken once per device with
+// hipGetSymbolAddress (the device current) and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                   // guards g_scratch_ptr
+char* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_use[kMaxDevices];     // one call at a time per device uses the array
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
 
 #define ALL_BUFFERS(c)                                                                                     \
     &c->in_pos, &c->in_sp, &c->in_nu, &c->in_w, &c->atom_struct, &c->sinfo, &c->sp_table, &c->omegas, &c->pos_b,  \
@@ -533,6 +551,15 @@ lmbd_status lmbd_create(int32_t device, lmbd_context** out) {
             ctx->pin_cap = kPinBytes;
         else
             ctx->pin = nullptr;
+    }
+    if (device < kMaxDevices && hipSetDevice(device) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+                g_scratch_ptr[device] = static_cast<char*>(ptr);
+        }
+        ctx->scratch = g_scratch_ptr[device];
     }
     (void)hipSetDevice(prev);
     *out = ctx;
@@ -1188,6 +1215,45 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
                         std::to_string(flags[1]));
     return LMBD_OK;
 }
+
+lmbd_status lmbd_compute_batch_static(lmbd_context* ctx, const lmbd_params* params, int32_t n_species,
+                                      const lmbd_species* species_table, int32_t n_structs,
+                                      const lmbd_structure* structs, int32_t mem, void* hip_stream) {
+    if (!ctx) return LMBD_E_INVALID_ARG;
+    if (!ctx->scratch || ctx->device >= kMaxDevices)
+        return fail(ctx, LMBD_E_DEVICE, "the static scratch array of the device is not available");
+    std::lock_guard<std::mutex> lk(g_scratch_use[ctx->device]);
+    // A call context that owns nothing: every buffer is carved from the static
+    // array, so neither the call nor its end allocates or frees device memory
+    // (the caller's context keeps its own cached buffers untouched).  It borrows
+    // the context's pinned staging area and stage-timer events.
+    lmbd_context tmp;
+    tmp.device = ctx->device;
+    tmp.budget = ctx->budget;
+    tmp.pin = ctx->pin;
+    tmp.pin_cap = ctx->pin_cap;
+    tmp.pin_pending = ctx->pin_pending;
+    tmp.lds_limit = ctx->lds_limit;
+    tmp.profiling = ctx->profiling;
+    tmp.mbd_product = ctx->mbd_product;
+    for (int i = 0; i < 2 * LMBD_N_STAGES; ++i) tmp.ev[i] = ctx->ev[i];
+    tmp.arena = ctx->scratch;
+    tmp.arena_size = kStaticScratchBytes;
+    const lmbd_status st = lmbd_compute_batch(&tmp, params, n_species, species_table, n_structs, structs, mem,
+                                              hip_stream);
+    ctx->pin_pending = tmp.pin_pending;
+    ctx->err = tmp.err;
+    for (int i = 0; i < LMBD_N_STAGES; ++i) {
+        ctx->ev_used[i] = tmp.ev_used[i];
+        ctx->stage_ms[i] = tmp.stage_ms[i];
+    }
+    if (st == LMBD_E_OOM_ADMISSION)
+        ctx->err = "footprint over the static scratch of " + std::to_string(kStaticScratchBytes) + " bytes (" +
+                   tmp.err + ")";
+    return st;
+}
+
+size_t lmbd_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 lmbd_status lmbd_compute(lmbd_context* ctx, const lmbd_params* params, int32_t n_species,
                          const lmbd_species* species_table, const lmbd_structure* structure, int32_t mem,
