@@ -107,32 +107,71 @@ def mbd_flops(nK, nq, n_max, forces):
     return float(f)
 
 
-def cpu_baseline(st, cut, grid):
+_BASE = {}
+
+
+def _baseline_worker_init():
+    import torch
+    torch.set_num_threads(1)
+
+
+def _baseline_task(k):
+    """One sampled central atom through the oracle as it stands; returns its timings."""
+    import oracle
+    from workloads import SPECIES_TABLE
+    tm = {}
+    w = np.zeros(_BASE["st"].n)
+    w[k] = 1.0
+    oracle.lmbd_energy_forces(_BASE["st"], _BASE["prm"], SPECIES_TABLE, weights=w, atoms=[k], timings=tm)
+    return tm
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(st, cut, grid, n_sample=32):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload.
 
-    Sample: the energy+forces pass of six central atoms; the oracle reports the
-    time and atom count of each of its three passes, from which the cost of one
-    atom of the complete job (one central SCS, one MBD+SCS reverse pass, one SCS
-    reverse pass) is extrapolated.
+    The sample is n_sample seeded central atoms of the box, spread over a pool of
+    worker processes (one torch thread each, as many workers as the process may
+    use, at most 16).  For each sampled atom the oracle runs its energy+forces
+    path as it stands (the central SCS of every atom the frame needs, the MBD
+    and local-SCS reverse pass of the atom, the SCS reverse pass of every atom
+    whose central polarisability it uses) and reports the time of each pass and
+    its atom count.  The complete job needs one of each per atom, so one core
+    spends central/atom + pass B + pass C/atom per atom of the job; the pool
+    of workers runs that many atoms at once.
     """
-    import torch
+    import multiprocessing as mproc
     import oracle
-    from workloads import SPECIES_TABLE, DEFAULT_PARAMS
+    from workloads import DEFAULT_PARAMS
     prm = oracle.make_params(cut, grid[0], grid[1], n_max=DEFAULT_PARAMS["n_max"], beta=DEFAULT_PARAMS["beta"],
                              damp_d=DEFAULT_PARAMS["damp_d"], r_buf=DEFAULT_PARAMS["r_buf"],
                              r_inner=DEFAULT_PARAMS["r_inner"])
-    sample = [0, st.n // 6, st.n // 3, st.n // 2, 2 * st.n // 3, 5 * st.n // 6]
-    tm = {}
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    sample = sorted(int(x) for x in np.random.Generator(np.random.PCG64(77)).choice(st.n, n_sample, replace=False))
+    _BASE.update(st=st, prm=prm)
     t0 = time.perf_counter()
-    oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE, atoms=sample, timings=tm)
+    with mproc.get_context("fork").Pool(workers, initializer=_baseline_worker_init) as pool:
+        tms = pool.map(_baseline_task, sample, chunksize=1)
     wall = time.perf_counter() - t0
-    per_atom = (tm["central_s"] / tm["central_atoms"] + tm["pass_b_s"] / tm["pass_b_atoms"]
-                + tm["pass_c_s"] / max(1, tm["pass_c_atoms"]))
-    return {"value": 1.0 / per_atom, "unit": "atoms/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": (f"energy+forces of {len(sample)} central atoms of the same 1,728-atom box "
-                       f"({tm['central_atoms']} central SCS solves, {tm['pass_c_atoms']} SCS reverse passes, "
-                       f"{wall:.1f} s); per-atom cost of the full job extrapolated from the three pass timings"),
-            "wall_s": wall}
+    per_atom = [t["central_s"] / t["central_atoms"] + t["pass_b_s"] / t["pass_b_atoms"]
+                + t["pass_c_s"] / max(1, t["pass_c_atoms"]) for t in tms]
+    core_s = float(np.mean(per_atom))
+    return {"value": workers / core_s, "unit": "atoms/s", "cores": workers, "kind": "oracle",
+            "cpu_model": host_cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "sample": (f"energy+forces path of {n_sample} seeded central atoms of the same 1,728-atom box, "
+                       f"{workers} worker processes with one thread each ({wall:.1f} s wall); one core spends "
+                       f"{core_s:.3f} s per atom of the complete job (central SCS + MBD/SCS reverse pass + "
+                       "SCS reverse pass per atom, from the oracle's own pass timings)"),
+            "core_s_per_atom": core_s, "wall_s": wall}
 
 
 def _replay(srv, reqs, arrivals):
@@ -213,6 +252,60 @@ def serve_bench(sweep=False):
     if sweep:
         out["rate_sweep_mixed_served"] = sweep_out
     return out
+
+
+def mixed_large(args, P, mp):
+    """The 13,824-atom carbon box (2.0 g/cm^3, 6 A) in mixed precision, energy+forces:
+    atoms/s and ms per step with inputs on the device, and the error of every
+    atom's energy and force against the FP64 path on the same GPU (one FP64 step)
+    and of the sampled energies against the stored oracle values."""
+    import torch
+    from workloads import SPECIES_TABLE
+    from workloads import configs as C
+    st, cut = C.config_mixed_pbc()
+    dev = torch.device("cuda:0")
+    pos = torch.as_tensor(st.pos, dtype=torch.float64, device=dev)
+    sp = torch.as_tensor(st.species, dtype=torch.int32, device=dev)
+    nu = torch.as_tensor(st.nu, dtype=torch.float64, device=dev)
+    ctx = P.Context(0)
+    ctx.set_profiling(True)
+    stream = torch.cuda.current_stream(dev)
+    mixed = dataclasses.replace(mp, precision="mixed")
+
+    def run(params):
+        return P.compute(pos, sp, nu, cutoffs=cut, params=params, species_table=SPECIES_TABLE, cell=st.cell,
+                         forces=True, ctx=ctx, stream=stream)
+
+    steps = max(1, min(args.steps, 5))
+    for _ in range(max(1, min(args.warmup, 2))):
+        run(mixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        om = run(mixed)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stg = dict(ctx.stage_times())
+    ref = run(mp)   # FP64, same inputs
+    torch.cuda.synchronize()
+    de = (om["energies"] - ref["energies"]).abs()
+    df = (om["forces"] - ref["forces"]).abs()
+    rec = {"workload": f"lMBD energy+forces, {st.n} C atoms periodic 2.0 g/cm3, cutoff {cut['r_scs']} A, mixed",
+           "value": st.n * steps / el, "unit": "atoms/s", "ms_per_step": el / steps * 1e3, "steps": steps,
+           "dtype": "f32 matrices/GEMMs on MFMA, f64 refinement and accumulation",
+           "max_abs_dE_vs_fp64_eV_per_atom": float(de.max()), "mean_abs_dE_vs_fp64_eV_per_atom": float(de.mean()),
+           "max_abs_dF_vs_fp64_eV_per_A": float(df.max()), "mean_abs_dF_vs_fp64_eV_per_A": float(df.mean()),
+           "stages_ms": stg}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))["C13824_pbc"]["energies"]
+        e = om["energies"].cpu().numpy()
+        rec["max_abs_dE_vs_oracle_sampled_eV_per_atom"] = float(np.abs(e[g["atoms"]] - np.array(g["energies_eV"])).max())
+        rec["oracle_sampled_atoms"] = len(g["atoms"])
+    ctx.close()
+    del ref, om
+    torch.cuda.empty_cache()
+    return rec
 
 
 SERVE_SLOTS = 3
@@ -433,6 +526,8 @@ def main():
                                                            "stages_ms": stg}
         ctx.set_mbd_product("auto")
         line["two_radius"] = tr
+    if not args.no_mixed and args.precision == "fp64" and args.workload == "plain":
+        line["mixed_c13824"] = mixed_large(args, P, mp)
     if not args.no_serve:
         line["served"] = serve_bench(args.serve_sweep)
     if not args.no_cpu_baseline and args.workload == "plain":

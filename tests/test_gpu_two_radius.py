@@ -65,8 +65,25 @@ def test_two_radius_regime_both_product_forms(case, mode):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_sparse_form_where_every_pair_couples(precision):
-    """Sparse products forced on a single-radius box (every block coupled): the
-    same results as the oracle, including the pairs cut by the central radius."""
+    """Sparse products forced on a single-radius box, r_MBD,1 = r_MBD,2 = r_nbr (every
+    block row couples to every site of K): energies and forces, hence the sparse
+    adjoint (pair contraction, screened radii and blend terms) on full rows, against
+    the oracle."""
+    st = C.carbon_box(96, 11, g_cm3=2.0)
+    cut = dict(r_scs=4.0, r_nbr=4.5, r_mbd1=4.5, r_mbd2=4.5)
+    print(f"case C96 {cut} sparse MBD products forced, {precision}", flush=True)
+    g = gpu_run(st, cut, precision=precision, ctx=_ctx("sparse"))
+    e, f = oracle.lmbd_energy_forces(st, oracle_params(cut), SPECIES_TABLE)
+    de, df = np.abs(g["energies"] - e).max(), np.abs(g["forces"] - f).max()
+    print(f"  max |dE| {de:.3e} eV/atom, max |dF| {df:.3e} eV/A", flush=True)
+    e_tol, f_tol = (1e-8, 1e-8) if precision == "fp64" else (1e-5, 1e-4)
+    assert de < e_tol and df < f_tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sparse_form_on_a_small_two_radius_box(precision):
+    """Sparse products forced with r_MBD,2 = 3 A below r_nbr = r_MBD,1 = 4.5 A: the
+    pairs that do not touch the central atom are cut at the smaller radius."""
     st = C.carbon_box(96, 11, g_cm3=2.0)
     cut = dict(r_scs=4.0, r_nbr=4.5, r_mbd1=4.5, r_mbd2=3.0)
     print(f"case C96 {cut} sparse MBD products forced, {precision}", flush=True)
