@@ -324,8 +324,9 @@ def lorentz_polarisabilities(a0, a_ref, omega, omega_ref):
     return a0[..., None] / (1.0 + (w / om_t[..., None]) ** 2)
 
 
-def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
-    """Energy of one central atom in eV.
+def _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm):
+    """Blended polarisabilities A (nK, 1 + n_nodes: omega = 0, then the nodes) and
+    T_LR (3 nK x 3 nK) of one frame.
 
     alpha_loc: (nw, n1) local polarisabilities of the frame; alpha_cen_K: (nK, nw)
     central polarisabilities of the base atoms of the first nK sites.
@@ -370,7 +371,13 @@ def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     blocks = torch.zeros((nK, nK, 3, 3), dtype=_DT).index_put(
         (torch.as_tensor(I), torch.as_tensor(J)), tlr)
     T = blocks.permute(0, 2, 1, 3).reshape(3 * nK, 3 * nK)
+    return A, T
 
+
+def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
+    """Energy of one central atom in eV (Sec. III.A, the symmetrised local energy)."""
+    nK = frame.nK
+    A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
     coef = prm.coefficients()
     e_freq = []
     for q in range(len(prm.omega)):
@@ -390,6 +397,71 @@ def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
             e_freq.append(acc)
     wq = torch.as_tensor(prm.weight, dtype=_DT)
     return (wq * torch.stack(e_freq)).sum() / (2.0 * math.pi) * HARTREE
+
+
+def _paper_force_functional(frame, p, alpha_loc, alpha_cen_K, fa, prm):
+    """A scalar whose gradient with respect to the central atom is the paper's
+    approximate force on it (Sec. III.D, Eqs. cent-appr-step and cent-appr), eV.
+
+    The force is minus the gradient of the total energy the central atom k sees,
+    E^tot_k = int dw/2pi sum_n c_n Tr(G~^n) over the whole neighbourhood, with
+    two approximations: the central polarisabilities do not move (Eq.
+    full-pol-grad; the caller passes them as constants), and for n >= 3 only the
+    block row and column of k in dG~ are kept, which makes the n-th term's
+    derivative n Tr(G~^(n-1) dG~) = 2 n Tr(g~_k G~^(n-2) dg~_k^T).  The n = 2 term
+    is differentiated in full.  So the functional is
+        int dw/2pi [ c_2 Tr(G~^2) + sum_{n>=3} c_n n Tr(g~_k B_n g~_k^T) ],
+    B_n = G~^(n-2) held fixed, g~_k the block row of k.  Its value is not an
+    energy; only its gradient with respect to r_k is used.
+    """
+    nK = frame.nK
+    A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
+    coef = prm.coefficients()
+    assert coef is not None, "the approximate forces need a finite n_max"
+    vals = []
+    for q in range(len(prm.omega)):
+        s = torch.sqrt(A[:, q + 1]).repeat_interleave(3)
+        G = s[:, None] * T * s[None, :]
+        acc = coef[2] * (G * G).sum()                     # Tr(G^2) of the symmetric G
+        g = G[:3, :]                                      # block row of the central atom
+        Gf = G.detach()
+        for n in range(3, prm.n_max + 1):
+            B = torch.linalg.matrix_power(Gf, n - 2)      # held fixed
+            acc = acc + coef[n] * n * torch.trace(g @ B @ g.T)
+        vals.append(acc)
+    wq = torch.as_tensor(prm.weight, dtype=_DT)
+    return (wq * torch.stack(vals)).sum() / (2.0 * math.pi) * HARTREE
+
+
+def lmbd_paper_forces(structure, prm, species_table, weights=None, atoms=None):
+    """Per-atom energies (eV) and the paper's approximate forces (eV/A): for each
+    atom k, F_k = -w_k d/dr_k of the functional of _paper_force_functional in
+    k's own neighbourhood, with k's own local SCS solve differentiated and the
+    central polarisabilities of the other atoms held fixed (Sec. III.D).  With
+    SCS switched off and cutoffs covering the whole structure this is the exact
+    force of the total energy; in general it is not the gradient of sum_k E_k.
+    ``atoms`` restricts the atoms whose forces are formed (others are zero)."""
+    st, fa, images = _prepare(structure, prm, species_table)
+    N = structure.n
+    w = np.ones(N) if weights is None else np.asarray(weights, dtype=np.float64)
+    ks = list(range(N)) if atoms is None else list(atoms)
+    e = lmbd_energies(structure, prm, species_table, atoms=ks)
+    frames = {k: _Frame(st, k, prm, images) for k in ks}
+    needed = sorted({int(b) for k in ks for b in frames[k].base[:frames[k].nK]})
+    central = scs_central(structure, prm, species_table, needed)
+    cell_t = _cell_tensor(st)
+    f = np.zeros((N, 3))
+    for k in ks:
+        fr = frames[k]
+        pos_t = torch.tensor(st["pos"], dtype=_DT, requires_grad=True)
+        p = fr.positions(pos_t, cell_t)
+        aloc = _scs_solve(fr, p, fa, prm)
+        acen = torch.as_tensor(central[fr.base[:fr.nK]], dtype=_DT)   # d alpha~_I ~ 0
+        val = _paper_force_functional(fr, p, aloc, acen, fa, prm)
+        if val.requires_grad:
+            (grad,) = torch.autograd.grad(val, pos_t)
+            f[k] = -w[k] * grad[k].numpy()
+    return e, f
 
 
 # ----------------------------------------------------------------------------

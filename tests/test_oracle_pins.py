@@ -576,6 +576,44 @@ def test_volume_ratio_derivative_finite_difference():
         assert abs(fd - dv[b]) < 1e-7 * max(1.0, abs(dv[b])), (b, fd, dv[b])
 
 
+# ------------------------------------------- the paper's approximate forces
+
+def test_paper_forces_are_exact_without_screening_and_with_full_cutoffs():
+    """SCS off and every frame covering the whole cluster: no polarisability moves
+    and T_LR,ij with i, j != k does not depend on r_k, so the central-atom
+    approximation is exact and E^tot_k is the total energy: the paper's force on
+    k (Sec. III.D) is minus the gradient of sum_j E_j, checked against central
+    differences of the total energy and against the exact adjoint."""
+    st = _rand_cluster(7, 101, box=5.0, dmin=1.5)
+    prm = _params(NO_SCS, 30.0, n_max=6)
+    e, f = oracle.lmbd_paper_forces(st, prm, SPECIES_TABLE)
+    e_ex, f_ex = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    assert np.allclose(e, e_ex, rtol=1e-13, atol=0)
+    assert np.allclose(f, f_ex, rtol=1e-9, atol=1e-13)
+    h = 1e-4
+    for a, g in ((0, 0), (3, 1), (6, 2)):
+        sp_, sm_ = st.copy(), st.copy()
+        sp_.pos[a, g] += h
+        sm_.pos[a, g] -= h
+        fd = -(oracle.lmbd_energies(sp_, prm, SPECIES_TABLE).sum()
+               - oracle.lmbd_energies(sm_, prm, SPECIES_TABLE).sum()) / (2 * h)
+        assert abs(fd - f[a, g]) < 1e-7 * max(1.0, abs(fd)), (a, g, fd, f[a, g])
+
+
+def test_paper_forces_are_an_approximation_with_screening():
+    """With local SCS the central polarisabilities are held fixed and, for n >= 3, only
+    the central atom's row and column of dG~ are kept: the result is close to, but
+    not, the exact force, and it is not momentum-conserving."""
+    st = _rand_cluster(12, 61, box=5.5, dmin=1.4)
+    prm = _params(3.0, 4.0)
+    e, f = oracle.lmbd_paper_forces(st, prm, SPECIES_TABLE)
+    e_ex, f_ex = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    assert np.array_equal(e, oracle.lmbd_energies(st, prm, SPECIES_TABLE))
+    d = np.abs(f - f_ex).max()
+    assert 1e-7 < d < 0.5 * np.abs(f_ex).max()
+    assert np.abs(f.sum(0)).max() > 1e-9
+
+
 # ------------------------------------------- two-point Lorentzian SCS model
 
 OMEGA_REF = 0.5
