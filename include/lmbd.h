@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LMBD_ABI_VERSION 4
+#define LMBD_ABI_VERSION 5
 
 typedef enum lmbd_status {
     LMBD_OK = 0,
@@ -53,6 +53,8 @@ enum { LMBD_FP64 = 0, LMBD_MIXED = 1 };
 enum { LMBD_SCS_EXACT = 0, LMBD_SCS_LORENTZ = 1 };
 /* where the caller's arrays live */
 enum { LMBD_HOST = 0, LMBD_DEVICE = 1 };
+/* what the forces output holds */
+enum { LMBD_FORCES_EXACT = 0, LMBD_FORCES_PAPER = 1 };
 
 /* Free-atom reference data of one species (Sec. II.B: the TS polarisability,
  * its characteristic frequency omega = 4 C6 / (3 alpha0^2), and vdW radius). */
@@ -83,6 +85,16 @@ typedef struct lmbd_species {
  *                 LMBD_E_SCS_BREAKDOWN.
  *  omega_ref    : reference frequency of LMBD_SCS_LORENTZ (Ha, > 0; the paper leaves
  *                 it empirical); ignored by LMBD_SCS_EXACT
+ *  force_model  : LMBD_FORCES_EXACT: forces = -d( sum_k w_k E_k ) / dR, the exact
+ *                 gradient.  LMBD_FORCES_PAPER: the approximate forces of Sec. III.D
+ *                 (Eqs. full-pol-grad, cent-appr-step, cent-appr): each atom's force
+ *                 comes from its own neighbourhood only, F_k = -w_k d E^tot_k / d r_k of
+ *                 the total energy k sees, with the central polarisabilities of the
+ *                 other atoms held fixed and, for n >= 3, only k's block row and column
+ *                 of dG~ kept (the n = 2 term in full); the frequency integral is the
+ *                 same quadrature as the energy.  Not the gradient of sum_k E_k (exact
+ *                 without screening when every neighbourhood holds the whole
+ *                 structure).  Uses the dense MBD products; dE_dv must be NULL.
  * Cutoffs are per structure (lmbd_structure). */
 typedef struct lmbd_params {
     double beta;
@@ -97,6 +109,7 @@ typedef struct lmbd_params {
     int32_t precision;
     int32_t scs_freq;
     double omega_ref;
+    int32_t force_model;
 } lmbd_params;
 
 /* One structure of a batch.  Pointers are host or device pointers according to

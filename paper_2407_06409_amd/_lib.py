@@ -5,11 +5,12 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblmbd.so")
 
-ABI_VERSION = 4   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
+ABI_VERSION = 5   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
 LMBD_FP64, LMBD_MIXED = 0, 1
 LMBD_SCS_EXACT, LMBD_SCS_LORENTZ = 0, 1
 LMBD_MBD_AUTO, LMBD_MBD_DENSE, LMBD_MBD_SPARSE = 0, 1, 2
 LMBD_HOST, LMBD_DEVICE = 0, 1
+LMBD_FORCES_EXACT, LMBD_FORCES_PAPER = 0, 1
 
 STATUS = {
     0: "LMBD_OK", 1: "LMBD_E_INVALID_ARG", 2: "LMBD_E_OOM", 3: "LMBD_E_OOM_ADMISSION",
@@ -29,7 +30,7 @@ class Params(ctypes.Structure):
         ("beta", ctypes.c_double), ("damp_d", ctypes.c_double), ("r_buf", ctypes.c_double),
         ("r_inner", ctypes.c_double), ("n_max", ctypes.c_int32), ("c_n", _dp),
         ("n_freq", ctypes.c_int32), ("omega", _dp), ("weight", _dp), ("precision", ctypes.c_int32),
-        ("scs_freq", ctypes.c_int32), ("omega_ref", ctypes.c_double),
+        ("scs_freq", ctypes.c_int32), ("omega_ref", ctypes.c_double), ("force_model", ctypes.c_int32),
     ]
 
 

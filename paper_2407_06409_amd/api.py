@@ -27,6 +27,7 @@ class MethodParams:
     precision: str = "fp64"
     scs_freq: str = "exact"      # "exact" or "lorentz" (two-point model, Sec. III.C)
     omega_ref: float = 0.0       # reference frequency of the two-point model, Ha
+    force_model: str = "exact"   # "exact" (gradient of sum_k w_k E_k) or "paper" (Sec. III.D approximation)
 
     def to_c(self):
         om = np.ascontiguousarray(self.omega, dtype=np.float64)
@@ -41,7 +42,8 @@ class MethodParams:
                      om.ctypes.data_as(C._dp), wt.ctypes.data_as(C._dp),
                      C.LMBD_MIXED if self.precision == "mixed" else C.LMBD_FP64,
                      {"exact": C.LMBD_SCS_EXACT, "lorentz": C.LMBD_SCS_LORENTZ}[self.scs_freq],
-                     float(self.omega_ref))
+                     float(self.omega_ref),
+                     {"exact": C.LMBD_FORCES_EXACT, "paper": C.LMBD_FORCES_PAPER}[self.force_model])
         return p, keep
 
 

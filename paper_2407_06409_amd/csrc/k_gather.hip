@@ -69,6 +69,8 @@ __global__ void __launch_bounds__(256) k_gather_forces(int n, int nslices, int64
     }
 }
 
+__global__ void k_slice_sum(int64_t len, int nslices, int64_t slice_stride, double* __restrict__ cf);
+
 // dv[a] = (sum_{s in list(a)} sum_w cnu[slot(base s, rev)][w]) / nu_a; one wavefront per
 // atom, lanes over sites, a fixed xor tree over the lanes
 __global__ void __launch_bounds__(256) k_gather_nu(int n, int nw, const Counts* __restrict__ counts,
@@ -97,6 +99,45 @@ hipError_t launch_gather_nu(hipStream_t st, int n, int nw, const Counts* counts,
                             double* dv) {
     hipLaunchKernelGGL(k_gather_nu, dim3((n + 3) / 4), dim3(256), 0, st, n, nw, counts, site_off, sites, rev,
                        cnu, nu, dv);
+    return hipGetLastError();
+}
+
+// F[a] = sum of the slots of a's own frame whose site is a or one of its images; one
+// wavefront per atom, a fixed xor tree over the lanes
+__global__ void __launch_bounds__(256) k_gather_self(int n, const Counts* __restrict__ counts,
+                                                     const int64_t* __restrict__ site_off,
+                                                     const Site* __restrict__ sites, const double* __restrict__ cf,
+                                                     double* __restrict__ forces) {
+    const int lane = threadIdx.x & 63;
+    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (a >= n) return;
+    const int64_t off = site_off[a];
+    const int nall = counts[a].n_all;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int e = lane; e < nall; e += 64) {
+        if (sites[off + e].base != a) continue;
+        const double* c = cf + (off + e) * 3;
+        f0 += c[0];
+        f1 += c[1];
+        f2 += c[2];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        f0 += __shfl_xor(f0, o);
+        f1 += __shfl_xor(f1, o);
+        f2 += __shfl_xor(f2, o);
+    }
+    if (lane == 0) {
+        forces[3 * a + 0] = f0;
+        forces[3 * a + 1] = f1;
+        forces[3 * a + 2] = f2;
+    }
+}
+
+hipError_t launch_gather_self(hipStream_t st, int n, int nslices, int64_t slice_stride, const Counts* counts,
+                              const int64_t* site_off, const Site* sites, double* cf, double* forces) {
+    hipLaunchKernelGGL(k_slice_sum, dim3((unsigned)((slice_stride + 255) / 256)), dim3(256), 0, st, slice_stride,
+                       nslices, slice_stride, cf);
+    hipLaunchKernelGGL(k_gather_self, dim3((n + 3) / 4), dim3(256), 0, st, n, counts, site_off, sites, cf, forces);
     return hipGetLastError();
 }
 

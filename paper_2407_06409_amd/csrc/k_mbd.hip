@@ -19,6 +19,17 @@
 // through the blend (local part to this atom's SCS, central part scattered to
 // the neighbours' own SCS through a per-site contribution buffer).
 //
+// Approximate forces of Sec. III.D (a.paper): the seed is the functional of the
+// frame whose r_k-gradient is the paper's force, int dw/2pi [c_2 Tr(G~^2) + sum_{n>=3}
+// c_n n Tr(g~_k B_n g~_k^T)] (B_n = G~^(n-2) fixed), so that
+//   Gbar_q = 2 c_2 G~ + sum_{n>=3} c_n n (u_{n-1} e_k^T + e_k u_{n-1}^T):
+// the low-rank part keeps the Tbar product with Z_0 = sum_{n>=3} c_n n u_{n-1} and
+// Z_{n-1} = c_n n e_k, the full n = 2 part is added to Tbar element by element, and
+//   dE/d alpha~_i(w_q) = W_q [2 c_2 sum_j alpha~_j |T_ij|^2 + sum_{n>=3} c_n n
+//                             (<u_{n-1}, u_1>_i + delta_ik mu_n) / alpha~_i];
+// the central polarisabilities are held fixed (nothing is scattered to the
+// neighbours), and the host keeps only the gradient of the frame's own atom.
+//
 // Two-point frequency model (Sec. III.C, Eqs. alpha_SCS_freq and char-freq):
 // the SCS is solved at 0 and w_ref only; the blend gives a0 = alpha~_i(0) and
 // ar = alpha~_i(w_ref), and alpha~_i(w) = a0 / (1 + (w / w~_i)^2) with
@@ -551,6 +562,47 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     if (!a.forces) return;
 
     // --- dE/d alpha~_i(w_q) from the moments (row-local Krylov products)
+    if (a.paper) {
+        // the full n = 2 trace: 2 c_2 sum_j alpha~_j |T_ij|^2, one site per thread over
+        // its block row; the central terms of n >= 3 from u_{n-1} and u_1 (the dense form
+        // only: the host never runs the approximate forces with the sparse products)
+        for (int i = tid; i < nK; i += blockDim.x) {
+            L.ab[(size_t)i * nwe] = 0.0;
+            for (int q0 = 0; q0 < nq; q0 += 4) {   // four nodes at a time, |T_ij|^2 formed again for each group
+                double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < nK; ++j) {
+                    if (j == i) continue;
+                    double nrm = 0.0;
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c) {
+                            const double x = double(T[(size_t)(3 * i + r) * N3p + 3 * j + c]);
+                            nrm += x * x;
+                        }
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+                        if (q0 + x < nq) acc2[x] += L.sa[(size_t)j * nwe + 1 + q0 + x] * nrm;
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int q = q0 + x;
+                    if (q >= nq) continue;
+                    double s = 2.0 * a.coef[2] * acc2[x];
+                    double sn = 0.0;
+                    for (int n = 3; n <= n_max; ++n) {
+                        const W* ua = Uat(n - 1);
+                        const W* u1 = Uat(1);
+                        double d = (i == 0) ? L.mu[n * nq + q] : 0.0;
+                        for (int r = 3 * i; r < 3 * i + 3; ++r)
+                            for (int c = 0; c < 3; ++c)
+                                d += double(ua[(size_t)r * ncol + 3 * q + c]) * double(u1[(size_t)r * ncol + 3 * q + c]);
+                        sn += a.coef[n] * n * d;
+                    }
+                    s += sn / L.sa[(size_t)i * nwe + 1 + q];
+                    L.ab[(size_t)i * nwe + 1 + q] = wk * a.wq[q] * s;
+                }
+            }
+        }
+    } else
     for (int t = tid; t < nK * nwe; t += blockDim.x) {
         const int i = t / nwe, w = t % nwe;
         double v = 0.0;
@@ -591,9 +643,16 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         for (int aa = 0; aa < kMaxNmax; ++aa) {
             if (aa >= n_max) break;
             double z = 0.0;
+            if (a.paper) {   // Z_0 = sum_{n>=3} c_n n u_{n-1}; Z_{n-1} = c_n n e_k
 #pragma unroll
-            for (int b = 0; b < kMaxNmax; ++b)
-                if ((b > 0 || aa >= 1) && b <= n_max - 1 - aa) z += a.coef[min(aa + b + 1, kMaxNmax)] * u[b];
+                for (int b = 2; b < kMaxNmax; ++b)
+                    if (aa == 0 && b <= n_max - 1) z += a.coef[b + 1] * (b + 1) * u[b];
+                if (aa >= 2) z = a.coef[aa + 1] * (aa + 1) * u[0];
+            } else {
+#pragma unroll
+                for (int b = 0; b < kMaxNmax; ++b)
+                    if ((b > 0 || aa >= 1) && b <= n_max - 1 - aa) z += a.coef[min(aa + b + 1, kMaxNmax)] * u[b];
+            }
             pr[(size_t)aa * ncol] = W(sq * u[aa]);
             qr[(size_t)aa * ncol] = W(scale * z);
         }
@@ -607,8 +666,22 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     // --- Tbar (overwrites T).  Tbar is symmetric (the terms a, b and b, a of
     // Gbar are transposes of each other), so only blocks on or below the
     // diagonal are formed and read.
-    if constexpr (!SP)
-        mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+    if constexpr (!SP) {
+        if (a.paper) {   // Tbar += 2 c_2 w_k sum_q W_q D_q^2 T D_q^2, read from T before it is overwritten
+            const double c2 = 2.0 * a.coef[2] * wk;
+            mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) {
+                const size_t e = (size_t)r * N3p + s;
+                const double t = double(T[e]);
+                double f = 0.0;
+                if (t != 0.0)
+                    for (int q = 0; q < nq; ++q)
+                        f += a.wq[q] * L.sa[(size_t)(r / 3) * nwe + 1 + q] * L.sa[(size_t)(s / 3) * nwe + 1 + q];
+                T[e] = W(double(v) + c2 * t * f);
+            });
+        } else {
+            mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) { T[(size_t)r * N3p + s] = v; });
+        }
+    }
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = SP ? 1 : max(1, min(4, (int)blockDim.x / max(nK, 1)));
@@ -767,15 +840,16 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         double gf = 0.0;  // sum_w abar_i(w) (alpha~_I,i(w) - alpha~_K,i(w))
         for (int w = 0; w < nw; ++w) {
             const double ai = L.ab[(size_t)i * nwe + w];
+            // (the approximate forces hold the central polarisabilities fixed: nothing is scattered)
             if (i == 0) {
                 abl[w] = ai;
                 cap[w] = 0.0;
             } else if (i < n1) {
                 abl[(size_t)i * nw + w] = (1.0 - L.fs[i]) * ai;
-                cap[(size_t)i * nw + w] = L.fs[i] * ai;
+                cap[(size_t)i * nw + w] = a.paper ? 0.0 : L.fs[i] * ai;
                 gf += ai * (cen[w] - aloc[(size_t)i * nw + w]);
             } else {
-                cap[(size_t)i * nw + w] = ai;
+                cap[(size_t)i * nw + w] = a.paper ? 0.0 : ai;
             }
         }
         // f_SCS(r_ik), r_ik = |p_i| (the central atom sits at the origin)

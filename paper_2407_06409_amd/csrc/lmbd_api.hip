@@ -191,6 +191,8 @@ lmbd_status check_params(lmbd_context* ctx, const lmbd_params* p) {
         return fail(ctx, LMBD_E_INVALID_ARG, "unknown SCS frequency treatment");
     if (p->scs_freq == LMBD_SCS_LORENTZ && !finite_pos(p->omega_ref))
         return fail(ctx, LMBD_E_INVALID_ARG, "omega_ref must be positive");
+    if (p->force_model != LMBD_FORCES_EXACT && p->force_model != LMBD_FORCES_PAPER)
+        return fail(ctx, LMBD_E_INVALID_ARG, "unknown force model");
     return LMBD_OK;
 }
 
@@ -837,6 +839,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         if (st != LMBD_OK) return st;
         forces = forces || structs[s].forces != nullptr || structs[s].dE_dv != nullptr;
         want_dv = want_dv || structs[s].dE_dv != nullptr;
+        if (structs[s].dE_dv && params->force_model == LMBD_FORCES_PAPER)
+            return fail(ctx, LMBD_E_INVALID_ARG, "dE_dv is the exact derivative: not with the approximate forces");
         N64 += structs[s].n_atoms;
     }
     if (N64 > INT32_MAX / 8) return fail(ctx, LMBD_E_UNSUPPORTED, "too many atoms in one call");
@@ -996,8 +1000,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     // sparse-form atoms, each part still largest first
     std::vector<char> sparse_struct(n_structs);
     for (int s = 0; s < n_structs; ++s)
-        sparse_struct[s] = ctx->mbd_product == LMBD_MBD_SPARSE ||
-                           (ctx->mbd_product == LMBD_MBD_AUTO && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr);
+        sparse_struct[s] = params->force_model == LMBD_FORCES_EXACT &&   // the approximate forces use dense products
+                           (ctx->mbd_product == LMBD_MBD_SPARSE ||
+                            (ctx->mbd_product == LMBD_MBD_AUTO && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr));
     std::stable_partition(P.order.begin(), P.order.end(), [&](int32_t k) { return !sparse_struct[atom_struct[k]]; });
     int n_dense = 0;
     for (int k = 0; k < N; ++k) n_dense += sparse_struct[atom_struct[k]] ? 0 : 1;
@@ -1127,6 +1132,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     for (int i = 0; i <= n_max; ++i) ma.coef[i] = (i < 2) ? 0.0 : (params->c_n ? params->c_n[i] : -1.0 / i);
     for (int q = 0; q < nq; ++q) ma.wq[q] = params->weight[q] * kHartree / (2.0 * kPi);
     ma.lorentz = lorentz ? 1 : 0;
+    ma.paper = params->force_model == LMBD_FORCES_PAPER ? 1 : 0;
     if (lorentz)
         for (int q = 0; q < nq; ++q) ma.rho[q] = (params->omega[q] / params->omega_ref) * (params->omega[q] / params->omega_ref);
     ma.err = err;
@@ -1155,8 +1161,11 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
 
     if (forces) {
         HIP_TRY(mark(6, 0));
-        HIP_TRY(launch_gather_central(stream, N, nw, sa.counts, sa.site_off, sa.sites, as<int32_t>(ctx->rev),
-                                      as<double>(ctx->ca), as<double>(ctx->abar_cen)));
+        if (ma.paper)   // the central polarisabilities are held fixed
+            HIP_TRY(launch_fill(stream, N * nw, 0.0, as<double>(ctx->abar_cen)));
+        else
+            HIP_TRY(launch_gather_central(stream, N, nw, sa.counts, sa.site_off, sa.sites, as<int32_t>(ctx->rev),
+                                          as<double>(ctx->ca), as<double>(ctx->abar_cen)));
         HIP_TRY(mark(6, 1));
         sa.abar_loc = as<double>(ctx->abar_loc);
         sa.abar_cen = as<double>(ctx->abar_cen);
@@ -1175,8 +1184,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         }
         HIP_TRY(mark(8, 1));
         HIP_TRY(mark(9, 0));
-        HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,
-                                     as<int32_t>(ctx->rev), as<double>(ctx->cf), as<double>(ctx->f_out)));
+        if (ma.paper)   // each atom's force from its own frame
+            HIP_TRY(launch_gather_self(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,
+                                       as<double>(ctx->cf), as<double>(ctx->f_out)));
+        else
+            HIP_TRY(launch_gather_forces(stream, N, 1 + nw, TS * 3, sa.counts, sa.site_off, sa.sites,
+                                         as<int32_t>(ctx->rev), as<double>(ctx->cf), as<double>(ctx->f_out)));
         HIP_TRY(mark(9, 1));
     }
     HIP_TRY(launch_central_static(stream, N, nw, sa.alpha_loc, sa.aloc_off, as<double>(ctx->a_out)));

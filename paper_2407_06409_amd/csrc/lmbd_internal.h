@@ -225,6 +225,7 @@ struct MbdArgs {
     double coef[kMaxNmax + 1];
     double wq[kMaxFreq];       // quadrature weight * Hartree / (2 pi): eV per unit integrand
     int lorentz;               // SCS solved at 0 and omega_ref only (nw = 2): two-point Lorentzian at the nodes
+    int paper;                 // adjoint of the approximate forces of Sec. III.D instead of the exact one
     double rho[kMaxFreq];      // two-point model: (omega_q / omega_ref)^2
     int* err;                  // bit 8: a polarisability rises between 0 and omega_ref
     int* err_atom;             // lowest atom whose frame raised an error
@@ -280,6 +281,10 @@ hipError_t launch_fill(hipStream_t st, int n, double v, double* out);
 hipError_t launch_gather_forces(hipStream_t st, int n, int nslices, int64_t slice_stride,
                                 const Counts* counts, const int64_t* site_off, const Site* sites,
                                 const int32_t* rev, double* cf, double* forces);
+// F[a] = sum over the sites s of a's own list with base(s) = a of the slot sums (the
+// gradient of a's own frame with respect to r_a; approximate forces of Sec. III.D)
+hipError_t launch_gather_self(hipStream_t st, int n, int nslices, int64_t slice_stride, const Counts* counts,
+                              const int64_t* site_off, const Site* sites, double* cf, double* forces);
 hipError_t launch_central_static(hipStream_t st, int n, int nw, const double* alpha_loc,
                                  const int64_t* aloc_off, double* out);
 

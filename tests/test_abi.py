@@ -46,8 +46,8 @@ def test_calls_that_need_no_device(lib):
     from paper_2407_06409_amd import _lib
     hdr = open(os.path.join(ROOT, "include", "lmbd.h")).read()
     assert lib.lmbd_abi_version() == _lib.ABI_VERSION == int(re.search(r"LMBD_ABI_VERSION (\d+)", hdr).group(1))
-    # the ctypes mirror of lmbd_params ends with the two-point model's fields
-    assert [f for f, _ in _lib.Params._fields_][-2:] == ["scs_freq", "omega_ref"]
+    # the ctypes mirror of lmbd_params ends with the two-point model's fields and the force model
+    assert [f for f, _ in _lib.Params._fields_][-3:] == ["scs_freq", "omega_ref", "force_model"]
     assert lib.lmbd_status_string(0) == b"ok"
     assert lib.lmbd_status_string(3) == b"request exceeds the memory budget"
     assert lib.lmbd_status_string(7) == b"request cancelled"
