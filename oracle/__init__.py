@@ -9,13 +9,17 @@ package shares no code with it.
 Modules
 -------
 lmbd      per-atom lMBD energies and exact forces (torch, float64, CPU autograd);
-          the paper's approximate forces (Sec. III.D) as a separate function
+          the paper's approximate forces (Sec. III.D) as a separate function;
+          the eigenvalue-bounded polynomial fit of ln(1 - x) (Sec. III.A) with its
+          Lanczos spectrum bounds
 full_mbd  whole-system MBD with whole-system SCS (numpy, float64): the limit
           that lMBD must reach when the cutoffs cover the whole molecule
 """
 from .lmbd import (OracleParams, make_params, neighbourhood, free_atom_terms, lmbd_energies,
-                   lmbd_energy_forces, lmbd_paper_forces, scs_central, BOHR, HARTREE)
+                   lmbd_energy_forces, lmbd_paper_forces, lmbd_spectrum_bounds, scs_central,
+                   PolarisationCatastrophe, BOHR, HARTREE)
 from .full_mbd import full_mbd, full_scs
 
 __all__ = ["OracleParams", "make_params", "neighbourhood", "free_atom_terms", "lmbd_energies",
-           "lmbd_energy_forces", "lmbd_paper_forces", "scs_central", "full_mbd", "full_scs", "BOHR", "HARTREE"]
+           "lmbd_energy_forces", "lmbd_paper_forces", "lmbd_spectrum_bounds",
+           "PolarisationCatastrophe", "scs_central", "full_mbd", "full_scs", "BOHR", "HARTREE"]

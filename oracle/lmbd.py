@@ -56,6 +56,12 @@ class OracleParams:
     n_max: Optional[int] = 6      # None => exact block logarithm (infinite body order)
     c_n: Optional[np.ndarray] = None  # length n_max + 1; None => c_n = -1/n for n >= 2
     scs_freq: str = "exact"       # "exact": SCS at every node; "lorentz": two-point model (Sec. III.C)
+    c_n_mode: str = "series"      # "series": fixed c_n; "fit": per atom and node, a least-squares
+                                  # polynomial of ln(1 - x) over the spectrum of G~ (Sec. III.A)
+    fit_nodes: int = 32           # Gauss-Legendre nodes of the discrete least-squares fit
+    lanczos_steps: Optional[int] = 20  # Lanczos steps for the spectrum bounds; None => exact extremes
+    coef_fixed: Optional[dict] = None  # "fit" mode: {atom: (n_nodes, n_max + 1) array} used instead
+                                       # of refitting (the coefficients held fixed)
     omega_ref: Optional[float] = None  # reference frequency of the two-point model, Ha
 
     def scs_omegas(self):
@@ -306,6 +312,131 @@ def _scs_solve(frame, p, fa, prm):
 
 
 # ----------------------------------------------------------------------------
+# Eigenvalue-bounded polynomial (Sec. III.A, Eqs. diagonal_appr, eigendecomp and
+# polynomial-fit)
+# ----------------------------------------------------------------------------
+
+class PolarisationCatastrophe(ValueError):
+    """The spectrum of G~_K reaches 1: ln(1 - x) has no real value there."""
+
+
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64(z):
+    """The output function of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) on the
+    64-bit counter z: add the golden-ratio increment, then two xor-shift-multiply
+    rounds and a final xor-shift."""
+    z = (z + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def lanczos_start(k, base, shift):
+    """Start vector of the Lanczos iteration of frame k (unnormalised, 3 entries per
+    site): entry (site, c) = U(k, base atom, lattice shift, c), uniform in [-1/2, 1/2),
+    keyed on the site's identity so that it does not depend on the order of the sites
+    (a vector built from the geometry alone would be symmetric in a symmetric frame
+    and could miss the extreme eigenvectors).  With s = the lattice shift packed as
+    three 8-bit fields biased by 128:
+        U = (SM(SM(k * 2^32 + base) + 4 s + c) >> 11) * 2^-53 - 1/2   (SM = SplitMix64)."""
+    out = np.empty(3 * len(base))
+    for i, (j, sh) in enumerate(zip(base, shift)):
+        s = ((int(sh[0]) + 128) << 16) | ((int(sh[1]) + 128) << 8) | (int(sh[2]) + 128)
+        h = _splitmix64((int(k) << 32) + int(j))
+        for c in range(3):
+            z = _splitmix64((h + 4 * s + c) & _M64)
+            out[3 * i + c] = (z >> 11) * 2.0 ** -53 - 0.5
+    return out
+
+
+def lanczos_bounds(G, v1, steps, tol=1e-10):
+    """Estimates of the smallest and largest eigenvalue of the symmetric G (Sec.
+    III.A: Lanczos on the symmetrised matrix): `steps` Lanczos steps from v1 without
+    reorthogonalisation, then the extreme eigenvalues of the tridiagonal matrix.
+    Step j: w = G v_j - beta_j v_{j-1}, alpha_j = <v_j, w>, w -= alpha_j v_j,
+    beta_{j+1} = |w|; the iteration stops early where beta_{j+1} <= tol (|alpha_j| +
+    beta_j) (an invariant subspace: its Ritz values are exact)."""
+    G = np.asarray(G, dtype=np.float64)
+    v = np.asarray(v1, dtype=np.float64) / np.linalg.norm(v1)
+    v_prev = np.zeros_like(v)
+    beta = 0.0
+    al, be = [], []
+    for j in range(steps):
+        w = G @ v - beta * v_prev
+        alpha = float(v @ w)
+        w = w - alpha * v
+        al.append(alpha)
+        if j == steps - 1:
+            break
+        beta_next = float(np.linalg.norm(w))
+        if beta_next <= tol * (abs(alpha) + beta):
+            break
+        be.append(beta_next)
+        v_prev, v, beta = v, w / beta_next, beta_next
+    Tm = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    lam = np.linalg.eigvalsh(Tm)
+    return float(lam[0]), float(lam[-1])
+
+
+def log_fit_coefficients(lam_min, lam_max, n_max, n_nodes=32, f=None):
+    """Coefficients c_0 .. c_{n_max} of the degree-n_max polynomial that fits
+    f(x) = ln(1 - x) (or the given f) in the least-squares sense on the interval
+    [lam_min, lam_max] (Eq. diagonal_appr): the sum over the n_nodes Gauss-Legendre
+    nodes of the interval of the quadrature-weighted squared residual is minimised
+    (the continuous fit with unit weight, discretised).  Solved by numpy's least
+    squares on the weighted Vandermonde matrix in x / s, s = max(|lam_min|,
+    |lam_max|), then scaled back.  An interval narrower than 1e-12 (no coupling)
+    leaves the fit undetermined: the Taylor coefficients -1/n are returned, the limit
+    of the fit as the interval shrinks to the origin."""
+    if f is None:
+        if lam_max >= 1.0:
+            raise PolarisationCatastrophe(f"largest eigenvalue {lam_max} >= 1")
+        f = lambda x: np.log1p(-x)
+    if lam_max - lam_min <= 1e-12:
+        return np.array([0.0] + [-1.0 / n for n in range(1, n_max + 1)])
+    x, w = np.polynomial.legendre.leggauss(n_nodes)
+    h, c = 0.5 * (lam_max - lam_min), 0.5 * (lam_max + lam_min)
+    lam = c + h * x
+    sc = max(abs(lam_min), abs(lam_max))
+    V = (lam / sc)[:, None] ** np.arange(n_max + 1)[None, :]
+    sw = np.sqrt(w)
+    coef, *_ = np.linalg.lstsq(sw[:, None] * V, sw * f(lam), rcond=None)
+    return coef / sc ** np.arange(n_max + 1)
+
+
+def spectrum_bounds(G):
+    """Smallest and largest eigenvalue of the symmetric matrix G (the values the
+    Lanczos iteration converges to)."""
+    lam = np.linalg.eigvalsh(np.asarray(G, dtype=np.float64))
+    return float(lam[0]), float(lam[-1])
+
+
+def frame_bounds(frame, p, alpha_loc, alpha_cen_K, fa, prm):
+    """(n_nodes, 2) bounds [lambda_min, lambda_max] of G~_K at every node: Lanczos
+    with prm.lanczos_steps steps, or the exact extremes if that is None."""
+    with torch.no_grad():
+        A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
+        v1 = lanczos_start(frame.k, frame.base[:frame.nK], frame.shift[:frame.nK])
+        out = []
+        for q in range(len(prm.omega)):
+            s = torch.sqrt(A[:, q + 1]).repeat_interleave(3)
+            G = (s[:, None] * T * s[None, :]).numpy()
+            if prm.lanczos_steps is None:
+                out.append(spectrum_bounds(G))
+            else:
+                out.append(lanczos_bounds(G, v1, prm.lanczos_steps))
+    return np.array(out)
+
+
+def fitted_coefficients(frame, p, alpha_loc, alpha_cen_K, fa, prm):
+    """(n_nodes, n_max + 1) fitted coefficients of one frame, one row per node."""
+    bounds = frame_bounds(frame, p, alpha_loc, alpha_cen_K, fa, prm)
+    return np.array([log_fit_coefficients(a, b, prm.n_max, prm.fit_nodes) for a, b in bounds])
+
+
+# ----------------------------------------------------------------------------
 # Local MBD energy (Sec. III.A symmetrised local energy; Sec. III.B blend)
 # ----------------------------------------------------------------------------
 
@@ -379,10 +510,22 @@ def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     nK = frame.nK
     A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
     coef = prm.coefficients()
+    cfit = None
+    if prm.c_n_mode == "fit":
+        # per node: c_n fitted over [lambda_min, lambda_max] of G~ (held fixed under
+        # differentiation: the forces treat the coefficients as constants, as the
+        # force expression of Sec. III.D does); the n = 0 and n = 1 terms are dropped
+        if prm.coef_fixed is not None and frame.k in prm.coef_fixed:
+            cfit = np.asarray(prm.coef_fixed[frame.k], dtype=np.float64)
+        else:
+            cfit = fitted_coefficients(frame, p, alpha_loc, alpha_cen_K, fa, prm)
     e_freq = []
     for q in range(len(prm.omega)):
         s = torch.sqrt(A[:, q + 1]).repeat_interleave(3)
         G = s[:, None] * T * s[None, :]                               # sqrt(A) T sqrt(A)
+        if cfit is not None:
+            coef = cfit[q].copy()
+            coef[:2] = 0.0
         if coef is None:
             lam, V = torch.linalg.eigh(G)
             e_freq.append((torch.log1p(-lam) * (V[:3, :] ** 2).sum(0)).sum())
@@ -527,6 +670,31 @@ def lmbd_energies(structure, prm, species_table, atoms=None, central=None):
             acen = torch.as_tensor(central[fr.base[:fr.nK]], dtype=_DT)
             e[k] = float(_mbd_energy(fr, p, aloc, acen, fa, prm))
     return e
+
+
+def lmbd_spectrum_bounds(structure, prm, species_table, atoms=None):
+    """(N, n_nodes, 2) bounds [lambda_min, lambda_max] of G~_K of every atom at every
+    quadrature node (Lanczos estimates, or exact with prm.lanczos_steps = None); the
+    rows of atoms not requested are 0.  A largest eigenvalue of 1 or more is the
+    polarisation catastrophe of Sec. III.A (1 - G~_K is then not positive definite)."""
+    st, fa, images = _prepare(structure, prm, species_table)
+    N = structure.n
+    needed = set()
+    for k in (range(N) if atoms is None else atoms):
+        fr = _Frame(st, k, prm, images)
+        needed.update(int(b) for b in fr.base[:fr.nK])
+    central = scs_central(structure, prm, species_table, sorted(needed))
+    pos_t = torch.as_tensor(st["pos"], dtype=_DT)
+    cell_t = _cell_tensor(st)
+    out = np.zeros((N, len(prm.omega), 2))
+    with torch.no_grad():
+        for k in (range(N) if atoms is None else atoms):
+            fr = _Frame(st, k, prm, images)
+            p = fr.positions(pos_t, cell_t)
+            aloc = _scs_solve(fr, p, fa, prm)
+            acen = torch.as_tensor(central[fr.base[:fr.nK]], dtype=_DT)
+            out[k] = frame_bounds(fr, p, aloc, acen, fa, prm)
+    return out
 
 
 def lmbd_energy_forces(structure, prm, species_table, weights=None, atoms=None, timings=None, want_dv=False):

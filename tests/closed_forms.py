@@ -137,3 +137,21 @@ def smooth_cutoff(r, rc, rb):
     c = np.linalg.solve(M, np.array([1.0, 0.0, 0.0, 0.0]))
     s = r - rc + rb
     return c[0] + c[1] * s + c[2] * s * s + c[3] * s ** 3
+
+
+def l2_projection_poly(f, a, b, degree):
+    """The continuous least-squares (unit weight) polynomial of the given degree
+    for f on [a, b], from its Legendre coefficients (2j+1)/2 int_{-1}^{1} f(c + h x)
+    P_j(x) dx computed by adaptive quadrature; returned as a callable."""
+    from scipy import integrate, special
+    h, c = 0.5 * (b - a), 0.5 * (b + a)
+    cl = []
+    for j in range(degree + 1):
+        val, _ = integrate.quad(lambda x: f(c + h * x) * special.eval_legendre(j, x), -1.0, 1.0,
+                                epsabs=1e-14, epsrel=1e-12, limit=200)
+        cl.append((2 * j + 1) / 2.0 * val)
+
+    def p(lam):
+        x = (np.asarray(lam, dtype=np.float64) - c) / h
+        return sum(cj * special.eval_legendre(j, x) for j, cj in enumerate(cl))
+    return p

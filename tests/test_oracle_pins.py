@@ -704,3 +704,193 @@ def test_neighbourhood_matches_brute_force_images():
         got = {(int(j), *map(int, s)) for j, s in zip(base, sh)}
         assert got == ref
         assert base[0] == k and np.all(sh[0] == 0) and np.all(np.diff(d[1:]) >= 0)
+
+
+# ------------------------- eigenvalue-bounded polynomial fit of ln(1 - x)
+
+def test_splitmix64_reproduces_its_published_outputs():
+    """The start vector's generator: the first five outputs of SplitMix64 seeded with
+    1234567 as published with the generator."""
+    g, m = 0x9E3779B97F4A7C15, (1 << 64) - 1
+    out = [L._splitmix64((1234567 + i * g) & m) for i in range(5)]
+    assert out == [6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+                   16408922859458223821]
+    v = L.lanczos_start(3, [3, 5, 5], [[0, 0, 0], [0, 0, 0], [1, -1, 0]])
+    assert np.all(np.abs(v) <= 0.5) and len(set(np.round(v, 15))) == 9   # images keyed apart
+    w = L.lanczos_start(3, [5, 3], [[1, -1, 0], [0, 0, 0]])
+    assert np.array_equal(w[:3], v[6:]) and np.array_equal(w[3:], v[:3])   # keyed on identity
+
+
+def test_log_fit_is_the_discretised_continuous_projection():
+    """The fit reproduces a polynomial of degree <= n_max exactly and equals the
+    continuous least-squares polynomial (Legendre projection by adaptive
+    quadrature) up to the discretisation of the 32-node rule."""
+    cub = lambda x: 0.3 - 1.2 * x + 0.5 * x ** 2 - 2.0 * x ** 3
+    c = L.log_fit_coefficients(-0.7, 0.45, 6, f=cub)
+    assert np.allclose(c, [0.3, -1.2, 0.5, -2.0, 0.0, 0.0, 0.0], atol=1e-12)
+    lam = np.linspace(-0.7, 0.45, 301)
+    for (a, b, n) in ((-0.7, 0.45, 6), (-0.2, 0.05, 4), (-0.9, 0.8, 10)):
+        c = L.log_fit_coefficients(a, b, n)
+        ref = cf.l2_projection_poly(lambda x: np.log1p(-x), a, b, n)
+        lam = np.linspace(a, b, 301)
+        assert np.abs(np.polyval(c[::-1], lam) - ref(lam)).max() < 1e-11, (a, b, n)
+        # a fit, not an interpolant: the residual alternates and is small against the series
+        series = -sum(lam ** k / k for k in range(1, n + 1))
+        assert np.abs(np.polyval(c[::-1], lam) - np.log1p(-lam)).max() < np.abs(series - np.log1p(-lam)).max()
+    # an interval of no width (no coupling): the Taylor coefficients
+    assert np.allclose(L.log_fit_coefficients(0.0, 0.0, 4), [0.0, -1.0, -0.5, -1 / 3, -0.25])
+    with pytest.raises(L.PolarisationCatastrophe):
+        L.log_fit_coefficients(-0.5, 1.0, 6)
+
+
+def test_lanczos_bounds_reach_the_extreme_eigenvalues():
+    """Ritz extremes lie inside the spectrum, move outwards with the step count and
+    reach the exact extremes once the Krylov space is the whole space; an invariant
+    subspace stops the iteration with exact values."""
+    rng = np.random.default_rng(3)
+    lam = np.sort(rng.uniform(-0.8, 0.6, 40))
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    G = Q @ np.diag(lam) @ Q.T
+    v1 = rng.uniform(-0.5, 0.5, 40)
+    prev = (np.inf, -np.inf)
+    for m in (3, 6, 10, 20):
+        lo, hi = L.lanczos_bounds(G, v1, m)
+        assert lam[0] - 1e-12 <= lo <= prev[0] + 1e-12 and prev[1] - 1e-12 <= hi <= lam[-1] + 1e-12
+        prev = (lo, hi)
+    lo, hi = L.lanczos_bounds(G, v1, 40)
+    assert abs(lo - lam[0]) < 1e-10 and abs(hi - lam[-1]) < 1e-10
+    # four distinct eigenvalues (a dimer's spectrum): stops after four steps, exact
+    D = np.diag([0.7, -0.7, 0.3, 0.3, -0.3, -0.3])
+    Q6, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    lo, hi = L.lanczos_bounds(Q6 @ D @ Q6.T, rng.uniform(-0.5, 0.5, 6), 20)
+    assert abs(lo + 0.7) < 1e-13 and abs(hi - 0.7) < 1e-13
+
+
+def _fit_params(r_scs, r_nbr, n_max, grid=GRID12, steps=20, **kw):
+    prm = _params(r_scs, r_nbr, grid=grid, n_max=n_max, **kw)
+    prm.c_n_mode = "fit"
+    prm.lanczos_steps = steps
+    return prm
+
+
+def test_fitted_dimer_energy_closed_form():
+    """Dimer without screening: G~ has the eigenvalues +-t_a per axis (t_z = 2 x,
+    t_x = t_y = -x, x = sqrt(alpha_1 alpha_2) f / r^3), so the bounds are +-2x and
+    sum_{n>=2} c_n Tr[G~^n]_kk = sum_axes [(p(t_a) + p(-t_a)) / 2 - p(0)] with p the
+    least-squares polynomial of ln(1 - x) on [-2x, 2x], here from adaptive quadrature."""
+    st = _open([[0, 0, 0], [1.7, 0.9, -0.4]], species=[C_IDX, SPECIES_INDEX["N"]], nu=[0.8, 0.95])
+    prm = _fit_params(NO_SCS, 30.0, 6, grid=GRID12)
+    e = oracle.lmbd_energies(st, prm, SPECIES_TABLE)
+    b = oracle.lmbd_spectrum_bounds(st, prm, SPECIES_TABLE)
+    a, w, t = _dimer_couplings(st)
+    om, wq = GRID12
+    ref = 0.0
+    for q in range(len(om)):
+        ai = a / (1.0 + (om[q] / w) ** 2)
+        x = math.sqrt(ai[0] * ai[1])
+        ts = [x * ti for ti in t]
+        lo, hi = -2.0 * abs(ts[1]), 2.0 * abs(ts[1])
+        assert abs(b[0, q, 0] - lo) < 1e-13 and abs(b[0, q, 1] - hi) < 1e-13
+        p = cf.l2_projection_poly(lambda y: np.log1p(-y), lo, hi, 6)
+        ref += wq[q] * sum(0.5 * (p(ta) + p(-ta)) - p(0.0) for ta in ts)
+    ref *= cf.HARTREE / (2.0 * math.pi)
+    assert abs(e[0] / ref - 1.0) < 1e-9 and abs(e[1] / ref - 1.0) < 1e-9
+
+
+def test_fitted_energy_is_the_polynomial_of_the_eigendecomposition():
+    """Eq. eigendecomp: sum_{n>=2} c_n Tr[G~^n]_kk equals the central 3x3 block's trace
+    of V p(Lambda) V^T, less c_0 times 3 (the n = 0 term; the n = 1 term is zero)."""
+    import torch
+    st = _rand_cluster(9, 17, box=5.0, dmin=1.5)
+    prm = _fit_params(3.0, 4.5, 5)
+    stp, fa, images = L._prepare(st, prm, SPECIES_TABLE)
+    central = oracle.scs_central(st, prm, SPECIES_TABLE)
+    pos_t = torch.as_tensor(st.pos, dtype=torch.float64)
+    e = oracle.lmbd_energies(st, prm, SPECIES_TABLE)
+    for k in (0, 4, 8):
+        fr = L._Frame(stp, k, prm, images)
+        p = fr.positions(pos_t, None)
+        with torch.no_grad():
+            aloc = L._scs_solve(fr, p, fa, prm)
+            acen = torch.as_tensor(central[fr.base[:fr.nK]], dtype=torch.float64)
+            A, T = L._mbd_operators(fr, p, aloc, acen, fa, prm)
+        coef = L.fitted_coefficients(fr, p, aloc, acen, fa, prm)
+        tot = 0.0
+        for q in range(len(prm.omega)):
+            s = np.sqrt(A[:, q + 1].numpy()).repeat(3)
+            G = s[:, None] * T.numpy() * s[None, :]
+            lam, V = np.linalg.eigh(G)
+            pl = np.polyval(coef[q][::-1], lam)
+            tot += prm.weight[q] * ((V[:3, :] ** 2).sum(0) @ pl - 3.0 * coef[q][0])
+        assert abs(tot * cf.HARTREE / (2.0 * math.pi) / e[k] - 1.0) < 1e-11
+
+
+def test_fit_converges_faster_than_the_series():
+    """Fig. convergence: at the same body order the fitted polynomial is much closer
+    to the block logarithm than the truncated series, and it converges with n_max."""
+    st = _rand_cluster(14, 5, box=6.0, dmin=1.5, hcno=False)
+    e_log = oracle.lmbd_energies(st, _params(3.5, 5.0, n_max=None), SPECIES_TABLE)
+    errs = []
+    for n in (4, 6, 8):
+        e_s = oracle.lmbd_energies(st, _params(3.5, 5.0, n_max=n), SPECIES_TABLE)
+        e_f = oracle.lmbd_energies(st, _fit_params(3.5, 5.0, n, steps=None), SPECIES_TABLE)
+        es, ef = np.abs(e_s - e_log).max(), np.abs(e_f - e_log).max()
+        assert ef < 0.2 * es, (n, ef, es)
+        errs.append(ef)
+    assert errs[2] < errs[1] < errs[0]
+
+
+def test_fit_forces_hold_the_coefficients_fixed():
+    """The forces treat the fitted c_n as constants: they are the central differences
+    of the energy evaluated with the coefficients of the unperturbed geometry."""
+    st = _rand_cluster(8, 23, box=5.0, dmin=1.5)
+    prm = _fit_params(3.0, 4.0, 6, steps=12)
+    e, f = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    import torch
+    stp, fa, images = L._prepare(st, prm, SPECIES_TABLE)
+    central = oracle.scs_central(st, prm, SPECIES_TABLE)
+    pos_t = torch.as_tensor(st.pos, dtype=torch.float64)
+    fixed = {}
+    for k in range(st.n):
+        fr = L._Frame(stp, k, prm, images)
+        p = fr.positions(pos_t, None)
+        with torch.no_grad():
+            aloc = L._scs_solve(fr, p, fa, prm)
+        acen = torch.as_tensor(central[fr.base[:fr.nK]], dtype=torch.float64)
+        fixed[k] = L.fitted_coefficients(fr, p, aloc, acen, fa, prm)
+    pf = _fit_params(3.0, 4.0, 6, steps=12)
+    pf.coef_fixed = fixed
+    assert np.allclose(oracle.lmbd_energies(st, pf, SPECIES_TABLE), e, rtol=0, atol=1e-14)
+    h = 1e-4
+    for (a, g) in ((0, 0), (3, 1), (6, 2)):
+        sp_, sm_ = st.copy(), st.copy()
+        sp_.pos = st.pos.copy()
+        sm_.pos = st.pos.copy()
+        sp_.pos[a, g] += h
+        sm_.pos[a, g] -= h
+        if not (_lists_equal(st, prm, sp_.pos) and _lists_equal(st, prm, sm_.pos)):
+            continue
+        fd = -(oracle.lmbd_energies(sp_, pf, SPECIES_TABLE).sum() - oracle.lmbd_energies(sm_, pf, SPECIES_TABLE).sum()) / (2 * h)
+        assert abs(fd - f[a, g]) < 2e-6 * max(1.0, abs(f[a, g])), (a, g, fd, f[a, g])
+    # refitting at every geometry moves the energy by the coefficients' own change:
+    # not the gradient of the refitted energy (the paper's forces neglect that term)
+    sp_ = st.copy()
+    sp_.pos = st.pos.copy()
+    sp_.pos[0, 0] += 1e-3
+    assert not np.allclose(oracle.lmbd_energies(sp_, pf, SPECIES_TABLE), oracle.lmbd_energies(sp_, prm, SPECIES_TABLE),
+                           rtol=0, atol=1e-15)
+
+
+def test_polarisation_catastrophe_is_detected():
+    """Strongly polarisable atoms at short range: the largest eigenvalue of G~ passes
+    1, ln(1 - x) has no fit there, and the fit mode refuses with an error (the
+    series mode computes a number, the spectrum bounds show the catastrophe)."""
+    tab = np.array(SPECIES_TABLE, copy=True)
+    tab[C_IDX] = [600.0, 2000.0, 4.0]
+    st = _open([[0, 0, 0], [3.0, 0.2, 0.1], [1.2, 2.7, 0.4]])
+    prm = _fit_params(NO_SCS, 10.0, 6, steps=20)
+    b = oracle.lmbd_spectrum_bounds(st, prm, tab)
+    assert b[:, 0, 1].max() >= 1.0
+    with pytest.raises(oracle.PolarisationCatastrophe):
+        oracle.lmbd_energies(st, prm, tab)
+    assert np.all(np.isfinite(oracle.lmbd_energies(st, _params(NO_SCS, 10.0, n_max=6), tab)))
