@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LMBD_ABI_VERSION 5
+#define LMBD_ABI_VERSION 6
 
 typedef enum lmbd_status {
     LMBD_OK = 0,
@@ -44,7 +44,9 @@ typedef enum lmbd_status {
     LMBD_E_DEVICE = 4,         /* a HIP runtime call failed; see lmbd_last_error */
     LMBD_E_SCS_BREAKDOWN = 5,  /* a local SCS matrix B~_K is not positive definite */
     LMBD_E_UNSUPPORTED = 6,    /* a size limit of the kernels is exceeded */
-    LMBD_E_CANCELLED = 7       /* a queued request was dropped when its server was destroyed */
+    LMBD_E_CANCELLED = 7,      /* a queued request was dropped when its server was destroyed */
+    LMBD_E_POLARISATION = 8    /* LMBD_CN_FIT: a spectrum bound of G~_K reaches 1 (polarisation
+                                  catastrophe, Sec. III.A): ln(1 - x) has no fit there */
 } lmbd_status;
 
 /* precision of the hot path */
@@ -55,6 +57,8 @@ enum { LMBD_SCS_EXACT = 0, LMBD_SCS_LORENTZ = 1 };
 enum { LMBD_HOST = 0, LMBD_DEVICE = 1 };
 /* what the forces output holds */
 enum { LMBD_FORCES_EXACT = 0, LMBD_FORCES_PAPER = 1 };
+/* where the body-order coefficients c_n come from */
+enum { LMBD_CN_SERIES = 0, LMBD_CN_FIT = 1 };
 
 /* Free-atom reference data of one species (Sec. II.B: the TS polarisability,
  * its characteristic frequency omega = 4 C6 / (3 alpha0^2), and vdW radius). */
@@ -95,6 +99,28 @@ typedef struct lmbd_species {
  *                 same quadrature as the energy.  Not the gradient of sum_k E_k (exact
  *                 without screening when every neighbourhood holds the whole
  *                 structure).  Uses the dense MBD products; dE_dv must be NULL.
+ *  cn_mode      : LMBD_CN_SERIES: the c_n above for every atom and node.  LMBD_CN_FIT:
+ *                 the eigenvalue-bounded polynomial of Sec. III.A (Eqs. diagonal_appr,
+ *                 eigendecomp, polynomial-fit): for every atom k and node q the bounds
+ *                 [lambda_min, lambda_max] of the spectrum of G~_K(w_q) are estimated by
+ *                 `lanczos_steps` Lanczos steps, and c_0 .. c_n_max are the least-squares
+ *                 polynomial of degree n_max to ln(1 - x) on that interval (sum of the
+ *                 squared residuals at its 32 Gauss-Legendre points, each weighted by
+ *                 its quadrature weight); the energy keeps n = 2 .. n_max.  The Lanczos
+ *                 iteration starts from the vector with entry (site, c) = U(k, base atom,
+ *                 lattice shift, c) of the SplitMix64 hash (Steele, Lea and Flood 2014):
+ *                 with k and the base atom counted within their structure, s the lattice
+ *                 shift packed as ((s0 + 128) << 16) | ((s1 + 128) << 8) | (s2 + 128) and
+ *                 SM the SplitMix64 output function of a 64-bit counter,
+ *                 U = (SM(SM(k 2^32 + base) + 4 s + c) >> 11) 2^-53 - 1/2; it stops early
+ *                 at beta_{j+1} <= 1e-10 (|alpha_j| + beta_j) (an invariant subspace).  An
+ *                 interval narrower than 1e-12 takes c_n = -1/n.  The forces hold the
+ *                 fitted c_n fixed, as the force expression of Sec. III.D does (they are
+ *                 not the derivative of the refitted energy).  A bound lambda_max >= 1
+ *                 fails the call with LMBD_E_POLARISATION (lowest such atom in
+ *                 lmbd_last_error).  c_n must be NULL.
+ *  lanczos_steps: Lanczos steps of LMBD_CN_FIT and of the `spectrum` output, 2 .. 64
+ *                 (0 = 20).
  * Cutoffs are per structure (lmbd_structure). */
 typedef struct lmbd_params {
     double beta;
@@ -110,6 +136,8 @@ typedef struct lmbd_params {
     int32_t scs_freq;
     double omega_ref;
     int32_t force_model;
+    int32_t cn_mode;
+    int32_t lanczos_steps;
 } lmbd_params;
 
 /* One structure of a batch.  Pointers are host or device pointers according to
@@ -139,7 +167,12 @@ typedef struct lmbd_params {
  *                derivative with respect to the Hirshfeld-volume ratios (through
  *                the TS polarisabilities, attenuation lengths and radii of
  *                Sec. II.B), so that a caller can apply the chain rule of the
- *                volume gradients of Sec. III.D outside the library; or NULL */
+ *                volume gradients of Sec. III.D outside the library; or NULL
+ *  spectrum    : [n_atoms][n_freq][2] output: the Lanczos bounds [lambda_min,
+ *                lambda_max] of the spectrum of G~_K(w_q) of every atom and node (the
+ *                estimates LMBD_CN_FIT fits on; lanczos_steps steps), a diagnostic of
+ *                the polarisation catastrophe (lambda_max >= 1) in either cn_mode; or NULL.
+ *                A Lanczos bound lies inside the true spectrum (lambda_max from below). */
 typedef struct lmbd_structure {
     int64_t n_atoms;
     const double* pos;
@@ -156,6 +189,7 @@ typedef struct lmbd_structure {
     double* forces;
     double* alpha_scs0;
     double* dE_dv;
+    double* spectrum;
 } lmbd_structure;
 
 typedef struct lmbd_context lmbd_context;

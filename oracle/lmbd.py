@@ -555,16 +555,21 @@ def _paper_force_functional(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     is differentiated in full.  So the functional is
         int dw/2pi [ c_2 Tr(G~^2) + sum_{n>=3} c_n n Tr(g~_k B_n g~_k^T) ],
     B_n = G~^(n-2) held fixed, g~_k the block row of k.  Its value is not an
-    energy; only its gradient with respect to r_k is used.
+    energy; only its gradient with respect to r_k is used.  With the fitted
+    coefficients (prm.c_n_mode == "fit") each node takes the frame's own c_n,
+    held fixed.
     """
     nK = frame.nK
     A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
     coef = prm.coefficients()
     assert coef is not None, "the approximate forces need a finite n_max"
+    cfit = fitted_coefficients(frame, p, alpha_loc, alpha_cen_K, fa, prm) if prm.c_n_mode == "fit" else None
     vals = []
     for q in range(len(prm.omega)):
         s = torch.sqrt(A[:, q + 1]).repeat_interleave(3)
         G = s[:, None] * T * s[None, :]
+        if cfit is not None:
+            coef = cfit[q]
         acc = coef[2] * (G * G).sum()                     # Tr(G^2) of the symmetric G
         g = G[:3, :]                                      # block row of the central atom
         Gf = G.detach()

@@ -5,16 +5,18 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblmbd.so")
 
-ABI_VERSION = 5   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
+ABI_VERSION = 6   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
 LMBD_FP64, LMBD_MIXED = 0, 1
 LMBD_SCS_EXACT, LMBD_SCS_LORENTZ = 0, 1
 LMBD_MBD_AUTO, LMBD_MBD_DENSE, LMBD_MBD_SPARSE = 0, 1, 2
 LMBD_HOST, LMBD_DEVICE = 0, 1
 LMBD_FORCES_EXACT, LMBD_FORCES_PAPER = 0, 1
+LMBD_CN_SERIES, LMBD_CN_FIT = 0, 1
 
 STATUS = {
     0: "LMBD_OK", 1: "LMBD_E_INVALID_ARG", 2: "LMBD_E_OOM", 3: "LMBD_E_OOM_ADMISSION",
     4: "LMBD_E_DEVICE", 5: "LMBD_E_SCS_BREAKDOWN", 6: "LMBD_E_UNSUPPORTED", 7: "LMBD_E_CANCELLED",
+    8: "LMBD_E_POLARISATION",
 }
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -31,6 +33,7 @@ class Params(ctypes.Structure):
         ("r_inner", ctypes.c_double), ("n_max", ctypes.c_int32), ("c_n", _dp),
         ("n_freq", ctypes.c_int32), ("omega", _dp), ("weight", _dp), ("precision", ctypes.c_int32),
         ("scs_freq", ctypes.c_int32), ("omega_ref", ctypes.c_double), ("force_model", ctypes.c_int32),
+        ("cn_mode", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
     ]
 
 
@@ -41,6 +44,7 @@ class StructureDesc(ctypes.Structure):
         ("r_scs", ctypes.c_double), ("r_nbr", ctypes.c_double), ("r_mbd1", ctypes.c_double),
         ("r_mbd2", ctypes.c_double), ("e_weight", ctypes.c_void_p), ("e_atom", ctypes.c_void_p),
         ("forces", ctypes.c_void_p), ("alpha_scs0", ctypes.c_void_p), ("dE_dv", ctypes.c_void_p),
+        ("spectrum", ctypes.c_void_p),
     ]
 
 

@@ -28,6 +28,8 @@ class MethodParams:
     scs_freq: str = "exact"      # "exact" or "lorentz" (two-point model, Sec. III.C)
     omega_ref: float = 0.0       # reference frequency of the two-point model, Ha
     force_model: str = "exact"   # "exact" (gradient of sum_k w_k E_k) or "paper" (Sec. III.D approximation)
+    cn_mode: str = "series"      # "series" (c_n above) or "fit" (per atom and node, Sec. III.A)
+    lanczos_steps: int = 20      # Lanczos steps of the fit and of the spectrum output
 
     def to_c(self):
         om = np.ascontiguousarray(self.omega, dtype=np.float64)
@@ -43,7 +45,8 @@ class MethodParams:
                      C.LMBD_MIXED if self.precision == "mixed" else C.LMBD_FP64,
                      {"exact": C.LMBD_SCS_EXACT, "lorentz": C.LMBD_SCS_LORENTZ}[self.scs_freq],
                      float(self.omega_ref),
-                     {"exact": C.LMBD_FORCES_EXACT, "paper": C.LMBD_FORCES_PAPER}[self.force_model])
+                     {"exact": C.LMBD_FORCES_EXACT, "paper": C.LMBD_FORCES_PAPER}[self.force_model],
+                     {"series": C.LMBD_CN_SERIES, "fit": C.LMBD_CN_FIT}[self.cn_mode], int(self.lanczos_steps))
         return p, keep
 
 
@@ -127,7 +130,7 @@ def _ptr(x):
 
 
 def compute_batch(structures, params: MethodParams, species_table, *, forces=True, ctx: Context = None,
-                  stream=None, want_alpha=False, want_dv=False, static_scratch=False):
+                  stream=None, want_alpha=False, want_dv=False, want_spectrum=False, static_scratch=False):
     """Energies and forces of several structures in one set of launches.
 
     ``structures``: list of dicts with keys pos (N,3), species (N,), v_ratio (N,),
@@ -135,8 +138,9 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
     optionally e_weight (N,).  Arrays are either all CUDA tensors (float64/int32,
     results are CUDA tensors, work on the current or given stream) or all host
     numpy arrays (results are numpy arrays).
-    Returns a list of dicts {energies, forces?, alpha_scs0?, dE_dv?} (dE_dv: the exact
-    derivative of sum_k w_k E_k with respect to the Hirshfeld-volume ratios, eV).
+    Returns a list of dicts {energies, forces?, alpha_scs0?, dE_dv?, spectrum?} (dE_dv: the
+    exact derivative of sum_k w_k E_k with respect to the Hirshfeld-volume ratios, eV;
+    spectrum: (N, n_freq, 2) Lanczos bounds of the spectrum of G~ per atom and node).
     ``static_scratch`` calls the entry point that allocates no device memory (its
     workspace is the library's static device array; small structures only).
     """
@@ -159,6 +163,8 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
             f = torch.empty_like(pos) if forces else None
             a = torch.empty_like(e) if want_alpha else None
             dv = torch.empty_like(e) if want_dv else None
+            spec = torch.empty((pos.shape[0], p.n_freq, 2), dtype=torch.float64, device=pos.device) \
+                if want_spectrum else None
         else:
             pos = np.ascontiguousarray(s["pos"], dtype=np.float64)
             spc = np.ascontiguousarray(s["species"], dtype=np.int32)
@@ -169,19 +175,21 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
             f = np.empty_like(pos) if forces else None
             a = np.empty_like(e) if want_alpha else None
             dv = np.empty_like(e) if want_dv else None
+            spec = np.empty((pos.shape[0], p.n_freq, 2)) if want_spectrum else None
         cell = s.get("cell")
         cell_np = None if cell is None else np.ascontiguousarray(
             cell.detach().cpu().numpy() if isinstance(cell, torch.Tensor) else cell, dtype=np.float64)
         pbc = s.get("pbc", (0, 0, 0))
         pbc = [int(bool(x)) for x in (pbc.tolist() if hasattr(pbc, "tolist") else pbc)]
         cut = s["cutoffs"]
-        keep.extend([pos, spc, nu, w, e, f, a, dv, cell_np])
+        keep.extend([pos, spc, nu, w, e, f, a, dv, spec, cell_np])
         descs[i] = C.StructureDesc(
             int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
             cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
             (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
-            float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a), _ptr(dv))
-        outs.append({"energies": e, "forces": f, "alpha_scs0": a, "dE_dv": dv})
+            float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a), _ptr(dv),
+            _ptr(spec))
+        outs.append({"energies": e, "forces": f, "alpha_scs0": a, "dE_dv": dv, "spectrum": spec})
     if device_mode:
         if stream is None:
             stream = torch.cuda.current_stream(structures[0]["pos"].device)
@@ -199,14 +207,14 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
 
 def compute(pos, species, v_ratio, *, cutoffs, params: MethodParams, species_table, cell=None,
             pbc=None, e_weight=None, forces=True, ctx: Context = None, stream=None, want_alpha=False,
-            want_dv=False):
+            want_dv=False, want_spectrum=False):
     """Per-atom energies (eV) and forces (eV/A) of one structure."""
     if pbc is None:
         pbc = (1, 1, 1) if cell is not None else (0, 0, 0)
     s = dict(pos=pos, species=species, v_ratio=v_ratio, cell=cell, pbc=pbc, cutoffs=cutoffs,
              e_weight=e_weight)
     return compute_batch([s], params, species_table, forces=forces, ctx=ctx, stream=stream,
-                         want_alpha=want_alpha, want_dv=want_dv)[0]
+                         want_alpha=want_alpha, want_dv=want_dv, want_spectrum=want_spectrum)[0]
 
 
 def _host_desc(s, forces, keep):

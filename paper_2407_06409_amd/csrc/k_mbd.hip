@@ -30,6 +30,15 @@
 // the central polarisabilities are held fixed (nothing is scattered to the
 // neighbours), and the host keeps only the gradient of the frame's own atom.
 //
+// Eigenvalue-bounded coefficients (Sec. III.A, Eqs. diagonal_appr, eigendecomp and
+// polynomial-fit; a.fit): per atom and node, a.lz_steps Lanczos steps on G~ (all nodes
+// side by side as columns: each step one (3n x 3n) x (3n x nq) product) give the
+// tridiagonal matrix whose extreme eigenvalues (bisection on its Sturm counts) bound
+// the spectrum; c_0 .. c_n_max are the least-squares polynomial of ln(1 - x) on that
+// interval over the 32 Gauss-Legendre points, formed as the Legendre projection (the
+// rule makes the discrete inner product exact for the Legendre polynomials up to
+// degree 2 n_max) and converted to powers of x.  The adjoint holds them fixed.
+//
 // Two-point frequency model (Sec. III.C, Eqs. alpha_SCS_freq and char-freq):
 // the SCS is solved at 0 and w_ref only; the blend gives a0 = alpha~_i(0) and
 // ar = alpha~_i(w_ref), and alpha~_i(w) = a0 / (1 + (w / w~_i)^2) with
@@ -49,10 +58,12 @@ __host__ __device__ inline size_t al4(size_t x) { return (x + 3) / 4 * 4; }
 // LDS layout.  The pair sums g of the force stage take the place of sqrt(alpha~),
 // whose last use (the operands of Tbar) precedes them.
 struct MbdLds {
-    double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu;
+    double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu, *cf, *lz;
 };
-// sa and ab hold every frequency of the energy: 0 and the nq nodes.
-__device__ inline MbdLds mbd_lds(double* b, int nk, int nq, int n_max) {
+// sa and ab hold every frequency of the energy: 0 and the nq nodes.  cf (fitted
+// coefficients, [nq][kMaxNmax + 1] and [kMaxNmax + 1][nq]) and lz (Lanczos: alpha and beta [steps][nq], the steps
+// taken and the two bounds per node) exist only when used.
+__device__ inline MbdLds mbd_lds(double* b, int nk, int nq, int n_max, int lz_steps, bool fit) {
     const int nw = nq + 1;
     MbdLds L;
     L.px = b;
@@ -68,13 +79,81 @@ __device__ inline MbdLds mbd_lds(double* b, int nk, int nq, int n_max) {
     L.rb = L.ab + (size_t)nk * nw;    // [4 parts][nk]
     L.fg = L.rb + 4 * (size_t)nk;     // [nk][3]
     L.mu = L.fg + 3 * (size_t)nk;
+    L.cf = L.mu + (size_t)(n_max + 1) * nq;
+    L.lz = L.cf + (fit ? 2 * (size_t)(kMaxNmax + 1) * nq : 0);
     return L;
 }
 
-size_t mbd_lds_bytes(int nkmax, int nq, int n_max) {
+__host__ __device__ inline size_t lz_lds_doubles(int nq, int lz_steps) {
+    return lz_steps > 0 ? (2 * (size_t)lz_steps + 3) * nq : 0;
+}
+
+size_t mbd_lds_bytes(int nkmax, int nq, int n_max, int lz_steps, bool fit) {
     const size_t nk = nkmax, nw = (size_t)nq + 1;
     return sizeof(double) * (3 * nk + nk * nw + nk * (size_t)std::max(nq, 12) + 3 * nk + nk * nw + 4 * nk +
-                             3 * nk + (size_t)(n_max + 1) * nq);
+                             3 * nk + (size_t)(n_max + 1) * nq + (fit ? 2 * (size_t)(kMaxNmax + 1) * nq : 0) +
+                             lz_lds_doubles(nq, lz_steps));
+}
+
+// The output function of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) on a 64-bit counter.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Coefficients c_0 .. c_n_max (c_0 = c_1 = 0 on return) of the least-squares polynomial
+// of ln(1 - x) on [lo, hi] over the Gauss-Legendre points x_i of [-1, 1] mapped to it:
+// the Legendre coefficients a_j = (2 j + 1) / 2 sum_i w_i ln(1 - lambda_i) P_j(x_i),
+// then sum_j a_j P_j(t), t = (x - mid) / half, in powers of x by Clenshaw's recurrence
+// b_j = a_j + (2j+1)/(j+1) t b_{j+1} - (j+1)/(j+2) b_{j+2} carried out on coefficient
+// arrays (b_0 is the polynomial).  No width (hi - lo <= 1e-12): the Taylor
+// coefficients -1/n.
+__host__ __device__ inline void log_fit(double lo, double hi, int n_max, const double* gx, const double* gw,
+                                        double (&c)[kMaxNmax + 1]) {
+#pragma unroll
+    for (int n = 0; n <= kMaxNmax; ++n) c[n] = n >= 2 ? -1.0 / n : 0.0;
+    if (!(hi - lo > 1e-12)) return;
+    const double h = 0.5 * (hi - lo), m = 0.5 * (hi + lo), ih = 1.0 / h;
+    double cl[kMaxNmax + 1];
+#pragma unroll
+    for (int j = 0; j <= kMaxNmax; ++j) cl[j] = 0.0;
+    for (int i = 0; i < kFitNodes; ++i) {
+        const double x = gx[i];
+        const double f = gw[i] * log1p(-(m + h * x));
+        double p0 = 1.0, p1 = x;
+        cl[0] += f;
+        cl[1] += f * x;
+#pragma unroll
+        for (int j = 2; j <= kMaxNmax; ++j) {
+            const double p2 = ((2 * j - 1) * x * p1 - (j - 1) * p0) / j;
+            cl[j] += f * p2;
+            p0 = p1;
+            p1 = p2;
+        }
+    }
+    // b1 = b_{j+1}, b2 = b_{j+2}; b_j overwrites b2, then the two swap roles
+    double b1[kMaxNmax + 1], b2[kMaxNmax + 1];
+#pragma unroll
+    for (int t = 0; t <= kMaxNmax; ++t) b1[t] = b2[t] = 0.0;
+#pragma unroll
+    for (int j = kMaxNmax; j >= 0; --j) {
+        if (j > n_max) continue;
+        const double aj = 0.5 * (2 * j + 1) * cl[j];
+        const double al = (2.0 * j + 1.0) / (j + 1.0) * ih, be = -(j + 1.0) / (j + 2.0);
+#pragma unroll
+        for (int t = kMaxNmax; t >= 0; --t)
+            b2[t] = (t == 0 ? aj : 0.0) + al * ((t > 0 ? b1[t - 1] : 0.0) - m * b1[t]) + be * b2[t];
+#pragma unroll
+        for (int t = 0; t <= kMaxNmax; ++t) {
+            const double x = b1[t];
+            b1[t] = b2[t];
+            b2[t] = x;
+        }
+    }
+#pragma unroll
+    for (int n = 0; n <= kMaxNmax; ++n) c[n] = n >= 2 ? b1[n] : 0.0;
 }
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -296,7 +375,13 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     const int nwe = nq + 1;   // row stride of L.sa and L.ab (nw is that of the SCS arrays)
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rs = SI.r_scs;
-    MbdLds L = mbd_lds(lds, nkmax, nq, n_max);
+    const bool fit = a.fit != 0;
+    MbdLds L = mbd_lds(lds, nkmax, nq, n_max, a.lz_steps, fit);
+    // c_n at node q: fitted per atom and node, or the common series
+    // (fitted: two copies in LDS, [kMaxNmax + 1][nq] here and [nq][kMaxNmax + 1] for the adjoint operands,
+    // whose per-element loop keeps one node's coefficients at fixed offsets)
+    double* const cfn = L.cf + (size_t)(kMaxNmax + 1) * nq;
+    auto cfq = [&](int n, int q) -> double { return fit ? cfn[n * nq + q] : a.coef[n]; };
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const Site* S = a.sites + a.site_off[k];
     const double* aloc = a.alpha_loc + a.aloc_off[k];
@@ -439,6 +524,9 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     // sparse form: Uout = D T D Uin, one block row (and 64 columns) per wavefront, lanes over
     // the columns, four coupled sites per step; the loads use in-bounds indices (entry 0 of the
     // row, column 0) with a zero factor instead of a branch, so that they overlap
+    // sparse form: Uout = D T D Uin, one block row (and 64 columns) per wavefront, lanes over
+    // the columns, four coupled sites per step; the loads use in-bounds indices (entry 0 of the
+    // row, column 0) with a zero factor instead of a branch, so that they overlap
     auto sparse_product = [&](const W* __restrict__ Uin, W* __restrict__ Uout) {
         for (int it = wave; it < nK * ((ncol + 63) / 64); it += nwave) {
             const int i = it % nK, col = (it / nK) * 64 + lane, q = col / 3;
@@ -480,6 +568,38 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                 Uout[(size_t)(3 * i) * ncol + col] = si * acc0;
                 Uout[(size_t)(3 * i + 1) * ncol + col] = si * acc1;
                 Uout[(size_t)(3 * i + 2) * ncol + col] = si * acc2;
+            }
+        }
+        __syncthreads();
+    };
+
+    // sparse form, Lanczos vectors (column-major [nq][N3p], one column per node):
+    // Vout = D T D Vin, one block row per wavefront, lanes over the nodes, the row's
+    // coupled sites in order
+    auto sparse_product_lz = [&](const W* __restrict__ Vin, W* __restrict__ Vout) {
+        const int q = lane < nq ? lane : 0;
+        for (int i = wave; i < nK; i += nwave) {
+            const int n = pcnt[i];
+            const size_t e0 = (size_t)i * nK;
+            W acc0 = W(0), acc1 = W(0), acc2 = W(0);
+            for (int t = 0; t < n; ++t) {
+                const size_t e = e0 + t;
+                const int j = pj[e];
+                const W Aj = pA[e], Bj = pB[e], r0 = pR0[e], r1 = pR1[e], r2 = pR2[e];
+                const W sj = W(L.sqa[(size_t)j * nq + q]);
+                const W* x = Vin + (size_t)q * N3p + 3 * j;
+                const W x0 = sj * x[0], x1 = sj * x[1], x2 = sj * x[2];
+                const W ax = Aj * (r0 * x0 + r1 * x1 + r2 * x2);
+                acc0 += ax * r0 + Bj * x0;
+                acc1 += ax * r1 + Bj * x1;
+                acc2 += ax * r2 + Bj * x2;
+            }
+            if (lane < nq) {
+                const W si = W(L.sqa[(size_t)i * nq + q]);
+                W* y = Vout + (size_t)q * N3p + 3 * i;
+                y[0] = si * acc0;
+                y[1] = si * acc1;
+                y[2] = si * acc2;
             }
         }
         __syncthreads();
@@ -529,6 +649,156 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         });   // ends with a barrier
     }
 
+    // --- spectrum bounds of G~ at every node (Lanczos) and, with a.fit, the fitted c_n
+    if (a.lz_steps > 0) {
+        const int m = a.lz_steps;
+        // three vectors per node, column-major ([nq][N3p]), in the space of V; the dense
+        // products' operand D v (rows 0 .. nq-1, zero padded) in V2
+        W* vb[3] = {V, V + (size_t)nq * N3p, V + 2 * (size_t)nq * N3p};
+        double* la = L.lz;                            // alpha_j of node q at [j nq + q]
+        double* lb = la + (size_t)m * nq;             // beta_{j+1} at [j nq + q]
+        double* lm = lb + (size_t)m * nq;             // steps taken per node
+        double* bnd = lm + nq;                        // [nq][2] bounds
+        auto wave_total = [&](double x) -> double {   // same order, same value in every lane
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+            return x;
+        };
+        // start vector, keyed on (k, base atom, lattice shift, component) in the structure's numbering
+        const uint64_t kl = (uint64_t)(k - SI.atom_offset);
+        auto start = [&](int r) -> double {
+            const Site st = S[r / 3];
+            const uint64_t h = splitmix64((kl << 32) + (uint64_t)(st.base - SI.atom_offset));
+            const uint64_t z = splitmix64(h + 4ull * (uint64_t)(uint32_t)st.shift + (uint64_t)(r % 3));
+            return (double)(z >> 11) * 0x1.0p-53 - 0.5;
+        };
+        for (int q = wave; q < nq; q += nwave) {
+            double s2 = 0.0;
+            for (int r = lane; r < N3; r += 64) {
+                const double x = start(r);
+                s2 += x * x;
+            }
+            const double inv = 1.0 / sqrt(wave_total(s2));
+            W* v1 = vb[1] + (size_t)q * N3p;
+            W* v0 = vb[0] + (size_t)q * N3p;
+            for (int r = lane; r < N3; r += 64) {
+                const W v = W(start(r) * inv);
+                v1[r] = v;
+                v0[r] = W(0);
+                if constexpr (!SP) V2[(size_t)q * N3p + r] = W(L.sqa[(size_t)(r / 3) * nq + q]) * v;
+            }
+            if (lane == 0) lm[q] = m;
+        }
+        __syncthreads();
+        int ip = 0, ic = 1, iw = 2;
+        for (int j = 0; j < m; ++j) {
+            // w = G~ v_j at every node (a node that has stopped has v_j = 0)
+            if constexpr (SP) {
+                sparse_product_lz(vb[ic], vb[iw]);
+            } else {
+                W* wv = vb[iw];
+                mfma_gemm_nt<1, 2, W>(N3, nq, N3, T, N3p, V2, N3p, false, [&](int r, int q, W v) {
+                    wv[(size_t)q * N3p + r] = W(L.sqa[(size_t)(r / 3) * nq + q]) * v;
+                });   // ends with a barrier
+            }
+            // w -= beta_j v_{j-1}; alpha_j = <v_j, w>; w -= alpha_j v_j; beta_{j+1} = |w|;
+            // v_{j+1} = w / beta_{j+1} (zero once the node stops)
+            for (int q = wave; q < nq; q += nwave) {
+                if (lm[q] <= j) continue;
+                const W* vp = vb[ip] + (size_t)q * N3p;
+                const W* vc = vb[ic] + (size_t)q * N3p;
+                W* w = vb[iw] + (size_t)q * N3p;
+                const double bj = j > 0 ? lb[(size_t)(j - 1) * nq + q] : 0.0;
+                double s = 0.0;
+                for (int r = lane; r < N3; r += 64) {
+                    const double t = double(w[r]) - bj * double(vp[r]);
+                    w[r] = W(t);
+                    s += double(vc[r]) * t;
+                }
+                const double al = wave_total(s);
+                double s2 = 0.0;
+                for (int r = lane; r < N3; r += 64) {
+                    const double t = double(w[r]) - al * double(vc[r]);
+                    w[r] = W(t);
+                    s2 += t * t;
+                }
+                const double bn = sqrt(wave_total(s2));
+                const bool stop = j == m - 1 || !(bn > 1e-10 * (fabs(al) + bj));
+                const double inv = stop ? 0.0 : 1.0 / bn;
+                for (int r = lane; r < N3; r += 64) {
+                    const W v = W(double(w[r]) * inv);
+                    w[r] = v;
+                    if constexpr (!SP) V2[(size_t)q * N3p + r] = W(L.sqa[(size_t)(r / 3) * nq + q]) * v;
+                }
+                if (lane == 0) {
+                    la[(size_t)j * nq + q] = al;
+                    lb[(size_t)j * nq + q] = bn;
+                    if (stop) lm[q] = j + 1;
+                }
+            }
+            __syncthreads();
+            const int t = ip;
+            ip = ic;
+            ic = iw;
+            iw = t;
+        }
+        // extreme eigenvalues of each node's tridiagonal matrix: bisection on the number
+        // of eigenvalues below x (the negative pivots of T - x I = L D L^T), one lane per end
+        if (tid < 2 * nq) {
+            const int q = tid >> 1, top = tid & 1;
+            const int me = (int)lm[q];
+            double glo = 0.0, ghi = 0.0;
+            for (int j = 0; j < me; ++j) {
+                const double b0 = j > 0 ? fabs(lb[(size_t)(j - 1) * nq + q]) : 0.0;
+                const double b1 = j + 1 < me ? fabs(lb[(size_t)j * nq + q]) : 0.0;
+                const double aj = la[(size_t)j * nq + q];
+                glo = j == 0 ? aj - b0 - b1 : fmin(glo, aj - b0 - b1);
+                ghi = j == 0 ? aj + b0 + b1 : fmax(ghi, aj + b0 + b1);
+            }
+            const double pad = 1e-14 * (fabs(glo) + fabs(ghi)) + 1e-300;
+            double lo = glo - pad, hi = ghi + pad;
+            const int target = top ? me : 1;   // count(lo) < target <= count(hi)
+            for (int it = 0; it < 256; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (!(mid > lo && mid < hi)) break;
+                int cnt = 0;
+                double d = 1.0;
+                for (int j = 0; j < me; ++j) {
+                    const double bb = j > 0 ? lb[(size_t)(j - 1) * nq + q] : 0.0;
+                    d = la[(size_t)j * nq + q] - mid - (j > 0 ? bb * bb / d : 0.0);
+                    if (fabs(d) < 1e-300) d = -1e-300;
+                    cnt += d < 0.0 ? 1 : 0;
+                }
+                if (cnt >= target)
+                    hi = mid;
+                else
+                    lo = mid;
+            }
+            bnd[tid] = hi;
+            if (a.spectrum) a.spectrum[((size_t)k * nq + q) * 2 + top] = hi;
+        }
+        __syncthreads();
+        if (fit && tid < nq) {
+            const int q = tid;
+            const double lo = bnd[2 * q], hi = bnd[2 * q + 1];
+            double c[kMaxNmax + 1];
+            if (!(hi < 1.0)) {   // polarisation catastrophe: ln(1 - x) has no fit
+                atomicOr(a.err, 16);
+                atomicMin(a.err_atom, k);
+#pragma unroll
+                for (int n = 0; n <= kMaxNmax; ++n) c[n] = 0.0;
+            } else {
+                log_fit(lo, hi, n_max, a.gl_x, a.gl_w, c);
+            }
+#pragma unroll
+            for (int n = 0; n <= kMaxNmax; ++n) {
+                L.cf[q * (kMaxNmax + 1) + n] = c[n];
+                cfn[n * nq + q] = c[n];
+            }
+        }
+        __syncthreads();
+    }
+
     // --- moments mu_n(q) = <u_a, u_b>, a + b = n; four lanes per moment over
     // rows r = part (mod 4), combined by lane exchanges in a fixed order
     const int nmom = (n_max - 1) * nq;
@@ -554,7 +824,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         double e = 0.0;
         for (int q = 0; q < nq; ++q) {
             double eq = 0.0;
-            for (int n = 2; n <= n_max; ++n) eq += a.coef[n] * L.mu[n * nq + q];
+            for (int n = 2; n <= n_max; ++n) eq += cfq(n, q) * L.mu[n * nq + q];
             e += a.wq[q] * eq;
         }
         a.e_atom[k] = e;
@@ -586,7 +856,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                 for (int x = 0; x < 4; ++x) {
                     const int q = q0 + x;
                     if (q >= nq) continue;
-                    double s = 2.0 * a.coef[2] * acc2[x];
+                    double s = 2.0 * cfq(2, q) * acc2[x];
                     double sn = 0.0;
                     for (int n = 3; n <= n_max; ++n) {
                         const W* ua = Uat(n - 1);
@@ -595,7 +865,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                         for (int r = 3 * i; r < 3 * i + 3; ++r)
                             for (int c = 0; c < 3; ++c)
                                 d += double(ua[(size_t)r * ncol + 3 * q + c]) * double(u1[(size_t)r * ncol + 3 * q + c]);
-                        sn += a.coef[n] * n * d;
+                        sn += cfq(n, q) * n * d;
                     }
                     s += sn / L.sa[(size_t)i * nwe + 1 + q];
                     L.ab[(size_t)i * nwe + 1 + q] = wk * a.wq[q] * s;
@@ -618,7 +888,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                         for (int c = 0; c < 3; ++c)
                             sn += double(ua[(size_t)r * ncol + 3 * q + c]) * double(ub[(size_t)r * ncol + 3 * q + c]);
                 }
-                s += a.coef[n] * sn;
+                s += cfq(n, q) * sn;
             }
             v = wk * a.wq[q] * s / L.sa[(size_t)i * nwe + w];
         }
@@ -629,34 +899,42 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     // Q[s][a ncol + col] = w_k W_q sqrt(alpha~_s) Z_a[s][col]
     // one (row, column) of the Krylov blocks per thread: u_0 .. u_{n_max-1} read
     // once, all n_max column blocks of P and Q written
-    for (int e = tid; e < N3 * ncol; e += blockDim.x) {
-        const int r = e / ncol, col = e % ncol, q = col / 3;
-        const double sq = L.sqa[(size_t)(r / 3) * nq + q];
-        const double scale = wk * a.wq[q] * sq;
-        double u[kMaxNmax];
-        u[0] = (r == col % 3) ? 1.0 : 0.0;
+    // (two instantiations: the common series coefficients are kernel arguments at
+    // fixed offsets, the fitted ones LDS entries of the column's node)
+    auto build_pq = [&](auto coef) {
+        for (int e = tid; e < N3 * ncol; e += blockDim.x) {
+            const int r = e / ncol, col = e % ncol, q = col / 3;
+            const double sq = L.sqa[(size_t)(r / 3) * nq + q];
+            const double scale = wk * a.wq[q] * sq;
+            double u[kMaxNmax];
+            u[0] = (r == col % 3) ? 1.0 : 0.0;
 #pragma unroll
-        for (int b = 1; b < kMaxNmax; ++b) u[b] = (b < n_max) ? double(Uat(b)[(size_t)r * ncol + col]) : 0.0;
-        W* pr = Pm + (size_t)r * KKp + col;
-        W* qr = Qm + (size_t)r * KKp + col;
+            for (int b = 1; b < kMaxNmax; ++b) u[b] = (b < n_max) ? double(Uat(b)[(size_t)r * ncol + col]) : 0.0;
+            W* pr = Pm + (size_t)r * KKp + col;
+            W* qr = Qm + (size_t)r * KKp + col;
 #pragma unroll
-        for (int aa = 0; aa < kMaxNmax; ++aa) {
-            if (aa >= n_max) break;
-            double z = 0.0;
-            if (a.paper) {   // Z_0 = sum_{n>=3} c_n n u_{n-1}; Z_{n-1} = c_n n e_k
+            for (int aa = 0; aa < kMaxNmax; ++aa) {
+                if (aa >= n_max) break;
+                double z = 0.0;
+                if (a.paper) {   // Z_0 = sum_{n>=3} c_n n u_{n-1}; Z_{n-1} = c_n n e_k
 #pragma unroll
-                for (int b = 2; b < kMaxNmax; ++b)
-                    if (aa == 0 && b <= n_max - 1) z += a.coef[b + 1] * (b + 1) * u[b];
-                if (aa >= 2) z = a.coef[aa + 1] * (aa + 1) * u[0];
-            } else {
+                    for (int b = 2; b < kMaxNmax; ++b)
+                        if (aa == 0 && b <= n_max - 1) z += coef(b + 1, q) * (b + 1) * u[b];
+                    if (aa >= 2) z = coef(aa + 1, q) * (aa + 1) * u[0];
+                } else {
 #pragma unroll
-                for (int b = 0; b < kMaxNmax; ++b)
-                    if ((b > 0 || aa >= 1) && b <= n_max - 1 - aa) z += a.coef[min(aa + b + 1, kMaxNmax)] * u[b];
+                    for (int b = 0; b < kMaxNmax; ++b)
+                        if ((b > 0 || aa >= 1) && b <= n_max - 1 - aa) z += coef(min(aa + b + 1, kMaxNmax), q) * u[b];
+                }
+                pr[(size_t)aa * ncol] = W(sq * u[aa]);
+                qr[(size_t)aa * ncol] = W(scale * z);
             }
-            pr[(size_t)aa * ncol] = W(sq * u[aa]);
-            qr[(size_t)aa * ncol] = W(scale * z);
         }
-    }
+    };
+    if (fit)
+        build_pq([&](int n, int q) { return L.cf[q * (kMaxNmax + 1) + n]; });
+    else
+        build_pq([&](int n, int) { return a.coef[n]; });
     for (int e = tid; e < N3 * (KKp - KK); e += blockDim.x) {   // padding columns
         const int r = e / (KKp - KK), kk = KK + e % (KKp - KK);
         Pm[(size_t)r * KKp + kk] = W(0);
@@ -667,15 +945,16 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     // Gbar are transposes of each other), so only blocks on or below the
     // diagonal are formed and read.
     if constexpr (!SP) {
-        if (a.paper) {   // Tbar += 2 c_2 w_k sum_q W_q D_q^2 T D_q^2, read from T before it is overwritten
-            const double c2 = 2.0 * a.coef[2] * wk;
+        if (a.paper) {   // Tbar += 2 w_k sum_q c_2(q) W_q D_q^2 T D_q^2, read from T before it is overwritten
+            const double c2 = 2.0 * wk;
             mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) {
                 const size_t e = (size_t)r * N3p + s;
                 const double t = double(T[e]);
                 double f = 0.0;
                 if (t != 0.0)
                     for (int q = 0; q < nq; ++q)
-                        f += a.wq[q] * L.sa[(size_t)(r / 3) * nwe + 1 + q] * L.sa[(size_t)(s / 3) * nwe + 1 + q];
+                        f += a.wq[q] * cfq(2, q) * L.sa[(size_t)(r / 3) * nwe + 1 + q] *
+                             L.sa[(size_t)(s / 3) * nwe + 1 + q];
                 T[e] = W(double(v) + c2 * t * f);
             });
         } else {
@@ -895,7 +1174,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
 }
 
 hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse) {
-    const size_t lds = mbd_lds_bytes(nkmax, a.nq, a.n_max);
+    const size_t lds = mbd_lds_bytes(nkmax, a.nq, a.n_max, a.lz_steps, a.fit != 0);
     if (mixed && sparse)
         hipLaunchKernelGGL((k_mbd<float, true>), dim3(a.n), dim3(kMbdThreadsSparse), lds, st, a, nkmax);
     else if (mixed)

@@ -60,7 +60,7 @@ struct lmbd_context {
     DBuf fac_off, fac_ld, x_off, aloc_off, work_off;
     DBuf fac, xsol, alpha_loc, abar_loc, abar_cen, work, ca, cf;
     DBuf pl_i, pl_q, pl_off, pl_seg, coef, coef_off, dvec, resid, lam;
-    DBuf e_out, f_out, a_out, dv_out, order;
+    DBuf e_out, f_out, a_out, dv_out, sp_out, order;
     DBuf tabs;   // one buffer holding the per-atom plan tables (pl_off .. order are views into it)
     // caller-provided workspace: every buffer of a call is carved from it in a
     // fixed order (nothing is allocated while it is set)
@@ -103,7 +103,7 @@ static __device__ __align__(256) char scratch[kStaticScratchBytes];
         &c->sorted_atoms, &c->cell_start, &c->cell_end, &c->sort_temp, &c->counts, &c->flags, &c->site_off,        \
         &c->sites, &c->hash_off, &c->hash_cap, &c->table, &c->rev, &c->fac_off, &c->fac_ld, &c->x_off,             \
         &c->aloc_off, &c->work_off, &c->fac, &c->xsol, &c->alpha_loc, &c->abar_loc, &c->abar_cen, &c->work,        \
-        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->dv_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
+        &c->ca, &c->cf, &c->e_out, &c->f_out, &c->a_out, &c->dv_out, &c->sp_out, &c->pl_i, &c->pl_q, &c->pl_off, &c->pl_seg, &c->coef, &c->coef_off, &c->dvec, &c->resid, &c->lam, \
         &c->order, &c->tabs, &c->wcounts
 
 namespace {
@@ -193,6 +193,11 @@ lmbd_status check_params(lmbd_context* ctx, const lmbd_params* p) {
         return fail(ctx, LMBD_E_INVALID_ARG, "omega_ref must be positive");
     if (p->force_model != LMBD_FORCES_EXACT && p->force_model != LMBD_FORCES_PAPER)
         return fail(ctx, LMBD_E_INVALID_ARG, "unknown force model");
+    if (p->cn_mode != LMBD_CN_SERIES && p->cn_mode != LMBD_CN_FIT)
+        return fail(ctx, LMBD_E_INVALID_ARG, "unknown c_n mode");
+    if (p->cn_mode == LMBD_CN_FIT && p->c_n) return fail(ctx, LMBD_E_INVALID_ARG, "fitted c_n: c_n must be NULL");
+    if (p->lanczos_steps != 0 && (p->lanczos_steps < 2 || p->lanczos_steps > kMaxLanczos))
+        return fail(ctx, LMBD_E_INVALID_ARG, "lanczos_steps out of range [2, 64] (0 = 20)");
     return LMBD_OK;
 }
 
@@ -473,7 +478,7 @@ size_t table_views(lmbd_context* c, int64_t n, bool set) {
 }
 
 template <class F>
-hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size_t wsz, F&& get) {
+hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, int nq, bool forces, size_t wsz, F&& get) {
     const bool mixed = wsz == sizeof(float);
     const size_t N = (size_t)P.n_atoms, D = sizeof(double), I = sizeof(int32_t);
     const size_t TS = (size_t)P.total_sites;
@@ -483,7 +488,8 @@ hipError_t layout_post(lmbd_context* c, const Plan& P, int nw, bool forces, size
         {&c->alpha_loc, (size_t)P.aloc_len * D}, {&c->abar_loc, (size_t)P.aloc_len * D},
         {&c->abar_cen, N * nw * D}, {&c->work, (size_t)P.work_len * wsz}, {&c->e_out, N * D},
         {&c->a_out, N * D}, {&c->pl_i, (size_t)P.pl_len * I}, {&c->pl_q, (size_t)P.pl_len * I},
-        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef, (size_t)P.coef_len * sizeof(float)}};
+        {&c->pl_seg, 3 * (TS + 2 * N) * I}, {&c->coef, (size_t)P.coef_len * sizeof(float)},
+        {&c->sp_out, N * (size_t)nq * 2 * D}};
     for (const auto& e : L) {
         const hipError_t r = get(*e.first, e.second);
         if (r != hipSuccess) return r;
@@ -531,6 +537,7 @@ const char* lmbd_status_string(lmbd_status s) {
         case LMBD_E_SCS_BREAKDOWN: return "local SCS matrix is not positive definite";
         case LMBD_E_UNSUPPORTED: return "unsupported size or option";
         case LMBD_E_CANCELLED: return "request cancelled";
+        case LMBD_E_POLARISATION: return "a spectrum bound of G~ reaches 1 (polarisation catastrophe)";
     }
     return "unknown status";
 }
@@ -784,9 +791,38 @@ lmbd_status layout_bytes(const lmbd_params* params, int n_species, const std::ve
     (void)layout_pre(&layout, pd, m);
     Plan P;
     build_plan(cnt, nw, 3 * params->n_freq, params->n_max, forces, params->precision == LMBD_MIXED, P);
-    (void)layout_post(&layout, P, nw, forces, params->precision == LMBD_MIXED ? sizeof(float) : sizeof(double), m);
+    (void)layout_post(&layout, P, nw, params->n_freq, forces,
+                      params->precision == LMBD_MIXED ? sizeof(float) : sizeof(double), m);
     *bytes = m.total;
     return LMBD_OK;
+}
+
+// Gauss-Legendre nodes (ascending) and weights of order n on [-1, 1]: Newton's method on
+// P_n from the asymptotic guess cos(pi (i + 3/4) / (n + 1/2)) for the i-th largest root,
+// P_n by its three-term recurrence, P_n' = n (x P_n - P_{n-1}) / (x^2 - 1), and the
+// weights 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, double* x, double* w) {
+    auto eval = [n](double z, double& dp) {
+        double p0 = 1.0, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+            const double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        return p1;
+    };
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            const double dz = eval(z, dp) / dp;
+            z -= dz;
+            if (std::fabs(dz) <= 1e-16) break;
+        }
+        (void)eval(z, dp);
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
 }
 
 void set_workspace(lmbd_context* ctx, void* base, size_t bytes) {
@@ -833,12 +869,14 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if (mem != LMBD_HOST && mem != LMBD_DEVICE) return fail(ctx, LMBD_E_INVALID_ARG, "bad mem");
     bool forces = false;   // the adjoint passes run (forces or volume-ratio derivatives requested)
     bool want_dv = false;
+    bool want_spec = false;
     int64_t N64 = 0;
     for (int s = 0; s < n_structs; ++s) {
         st = check_struct(ctx, params, structs[s]);
         if (st != LMBD_OK) return st;
         forces = forces || structs[s].forces != nullptr || structs[s].dE_dv != nullptr;
         want_dv = want_dv || structs[s].dE_dv != nullptr;
+        want_spec = want_spec || structs[s].spectrum != nullptr;
         if (structs[s].dE_dv && params->force_model == LMBD_FORCES_PAPER)
             return fail(ctx, LMBD_E_INVALID_ARG, "dE_dv is the exact derivative: not with the approximate forces");
         N64 += structs[s].n_atoms;
@@ -849,6 +887,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     const bool lorentz = params->scs_freq == LMBD_SCS_LORENTZ;
     const bool mixed = params->precision == LMBD_MIXED;
     const size_t wsz = mixed ? sizeof(float) : sizeof(double);  // matrix and workspace element size
+    const bool fit = params->cn_mode == LMBD_CN_FIT;
+    const int lz_steps = (fit || want_spec) ? (params->lanczos_steps ? params->lanczos_steps : 20) : 0;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     if (ctx->pin_pending) {   // a call that ended early may have left copies from the staging area queued
@@ -1015,19 +1055,19 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
         ctx->lds_limit = lds_limit;
     }
-    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nq, n_max) > (size_t)lds_limit ||
+    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nq, n_max, lz_steps, fit) > (size_t)lds_limit ||
         scs_factor_lds_bytes(P.n1max, mixed) > (size_t)lds_limit || scs_assemble_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit ||
         pairlist_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit)
         return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood needs more LDS than the device offers (" +
                                                  std::to_string(lds_limit) + " bytes)");
     Measure post_bytes;
-    (void)layout_post(ctx, P, nw, forces, wsz, post_bytes);
+    (void)layout_post(ctx, P, nw, nq, forces, wsz, post_bytes);
     if (ctx->budget && pre_bytes.total + post_bytes.total > ctx->budget)
         return fail(ctx, LMBD_E_OOM_ADMISSION,
                     "footprint " + std::to_string(pre_bytes.total + post_bytes.total) + " bytes over the memory budget");
     if (ctx->arena && ctx->arena_used + post_bytes.total > ctx->arena_size)
         return fail(ctx, LMBD_E_OOM_ADMISSION, "footprint over the workspace size");
-    HIP_TRY(layout_post(ctx, P, nw, forces, wsz, [&](DBuf& b, size_t n) { return ensure(ctx, b, n); }));
+    HIP_TRY(layout_post(ctx, P, nw, nq, forces, wsz, [&](DBuf& b, size_t n) { return ensure(ctx, b, n); }));
     {
         // all per-atom plan tables in one image, one copy
         const size_t tb = table_views(ctx, N, true);
@@ -1135,6 +1175,10 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.paper = params->force_model == LMBD_FORCES_PAPER ? 1 : 0;
     if (lorentz)
         for (int q = 0; q < nq; ++q) ma.rho[q] = (params->omega[q] / params->omega_ref) * (params->omega[q] / params->omega_ref);
+    ma.fit = fit ? 1 : 0;
+    ma.lz_steps = lz_steps;
+    gauss_legendre(kFitNodes, ma.gl_x, ma.gl_w);
+    ma.spectrum = want_spec ? as<double>(ctx->sp_out) : nullptr;
     ma.err = err;
     ma.err_atom = err_atom;
     ma.e_weight = as<double>(ctx->in_w);
@@ -1207,6 +1251,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
             HIP_TRY(hipMemcpyAsync(S.alpha_scs0, as<double>(ctx->a_out) + off, sizeof(double) * n, d2o, stream));
         if (S.dE_dv)
             HIP_TRY(hipMemcpyAsync(S.dE_dv, as<double>(ctx->dv_out) + off, sizeof(double) * n, d2o, stream));
+        if (S.spectrum)
+            HIP_TRY(hipMemcpyAsync(S.spectrum, as<double>(ctx->sp_out) + (size_t)off * nq * 2,
+                                   sizeof(double) * n * nq * 2, d2o, stream));
         off += n;
     }
     HIP_TRY(copy_d2h_sync(ctx, flags, ctx->flags.p, sizeof(flags), stream));
@@ -1226,6 +1273,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         return fail(ctx, LMBD_E_SCS_BREAKDOWN,
                     "SCS polarisability not decreasing between 0 and omega_ref in the frame of atom " +
                         std::to_string(flags[1]));
+    if (flags[0] & 16)
+        return fail(ctx, LMBD_E_POLARISATION,
+                    "largest eigenvalue bound of G~ >= 1 in the frame of atom " + std::to_string(flags[1]));
     return LMBD_OK;
 }
 

@@ -24,6 +24,8 @@ constexpr int kMaxNK = 400;        // sites in K (r < r_nbr), central atom inclu
                                    // 8 (3 nq + 15) bytes per site for nq >= 12 nodes, caps it lower for
                                    // long grids (the host checks that limit too)
 constexpr int kMaxSites = 4096;    // sites in the largest ball, central atom included
+constexpr int kFitNodes = 32;      // Gauss-Legendre points of the least-squares fit of ln(1 - x)
+constexpr int kMaxLanczos = 64;    // Lanczos steps for the spectrum bounds
 
 // One site of a neighbourhood: an atom or one of its periodic images, stored
 // relative to the central atom.  32 bytes.
@@ -227,7 +229,14 @@ struct MbdArgs {
     int lorentz;               // SCS solved at 0 and omega_ref only (nw = 2): two-point Lorentzian at the nodes
     int paper;                 // adjoint of the approximate forces of Sec. III.D instead of the exact one
     double rho[kMaxFreq];      // two-point model: (omega_q / omega_ref)^2
-    int* err;                  // bit 8: a polarisability rises between 0 and omega_ref
+    int fit;                   // c_n per atom and node: least-squares polynomial of ln(1 - x) on the
+                               // Lanczos bounds of the spectrum of G~ (Sec. III.A)
+    int lz_steps;              // Lanczos steps (0: no Lanczos iteration)
+    double gl_x[kFitNodes];    // Gauss-Legendre nodes and weights on [-1, 1] of the fit
+    double gl_w[kFitNodes];
+    double* spectrum;          // [n][nq][2] Lanczos bounds (batch-global atom index), or null
+    int* err;                  // bit 8: a polarisability rises between 0 and omega_ref;
+                               // bit 16: a spectrum bound reaches 1 with the fitted c_n
     int* err_atom;             // lowest atom whose frame raised an error
     const double* e_weight;    // [n] or null
     double* e_atom;            // [n]
@@ -271,7 +280,7 @@ hipError_t launch_scs_nu(hipStream_t st, const ScsArgs& a, int n1max, int n2max)
 hipError_t launch_gather_nu(hipStream_t st, int n, int nw, const Counts* counts, const int64_t* site_off,
                             const Site* sites, const int32_t* rev, const double* cnu, const double* nu,
                             double* dv);
-size_t mbd_lds_bytes(int nkmax, int nq, int n_max);
+size_t mbd_lds_bytes(int nkmax, int nq, int n_max, int lz_steps, bool fit);
 hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,

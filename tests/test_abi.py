@@ -46,9 +46,15 @@ def test_calls_that_need_no_device(lib):
     from paper_2407_06409_amd import _lib
     hdr = open(os.path.join(ROOT, "include", "lmbd.h")).read()
     assert lib.lmbd_abi_version() == _lib.ABI_VERSION == int(re.search(r"LMBD_ABI_VERSION (\d+)", hdr).group(1))
-    # the ctypes mirror of lmbd_params ends with the two-point model's fields and the force model
-    assert [f for f, _ in _lib.Params._fields_][-3:] == ["scs_freq", "omega_ref", "force_model"]
+    # the ctypes mirrors list the members of the header's structures in order
+    for cname, mirror in (("lmbd_params", _lib.Params), ("lmbd_structure", _lib.StructureDesc),
+                          ("lmbd_server_config", _lib.ServerConfig)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), hdr, flags=re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        members = [re.sub(r"\[.*\]", "", d.split()[-1]).lstrip("*") for d in body.split(";") if d.strip()]
+        assert [f for f, _ in mirror._fields_] == members, cname
     assert lib.lmbd_status_string(0) == b"ok"
+    assert lib.lmbd_status_string(8).startswith(b"a spectrum bound")
     assert lib.lmbd_status_string(3) == b"request exceeds the memory budget"
     assert lib.lmbd_status_string(7) == b"request cancelled"
     assert lib.lmbd_stage_name(3) == b"scs_assemble_factor_solve"
