@@ -318,11 +318,14 @@ def summarize(kind, d, workload):
     import csv
     import glob
 
-    def one(pattern):
-        f = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    def one_in(dd, pattern):
+        f = sorted(glob.glob(os.path.join(dd, "**", pattern), recursive=True))
         if not f:
-            sys.exit(f"no {pattern} under {d}")
+            sys.exit(f"no {pattern} under {dd}")
         return list(csv.DictReader(open(f[0])))
+
+    def one(pattern):
+        return one_in(d, pattern)
 
     if kind == "stats":
         rows = one("*kernel_stats.csv")
@@ -330,6 +333,22 @@ def summarize(kind, d, workload):
         for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
             out.append(f"| `{r['Name'][:72]}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                        f"{float(r['Percentage']):.1f}% |")
+        return "\n".join(out)
+    if kind.startswith("mfma:"):
+        # kind = "mfma:<dir>[:<dir> ...]": every counter of the runs, averaged per dispatch, for the
+        # factorisation and MBD kernels; MOPS counters are in units of 512 FLOP
+        rows = []
+        for dd in kind.split(":")[1:]:
+            rows += one_in(dd, "*counter_collection.csv")
+        out = ["| kernel | counter | mean per dispatch | dispatches |", "|---|---|---|---|"]
+        for kn in ("k_scs_factor", "k_mbd"):
+            by = {}
+            for r in rows:
+                if kn in r["Kernel_Name"]:
+                    key = (r["Kernel_Name"].split("(")[0].replace("void ", ""), r["Counter_Name"])
+                    by.setdefault(key, []).append(float(r["Counter_Value"]))
+            for (name, cn), v in sorted(by.items()):
+                out.append(f"| `{name}` | {cn} | {np.mean(v):.6g} | {len(v)} |")
         return "\n".join(out)
     # counters: kind = "pmc:<fetch dir>:<write dir>"
     _, dfetch, dwrite = kind.split(":")
@@ -374,6 +393,10 @@ def main():
                     help="skip the timing of the two-radius regime (sparse and dense MBD products)")
     ap.add_argument("--no-two-point", action="store_true",
                     help="skip the timing of the two-point Lorentzian SCS frequency model")
+    ap.add_argument("--no-fit", action="store_true",
+                    help="skip the timing of the eigenvalue-bounded fitted coefficients")
+    ap.add_argument("--no-paper-forces", action="store_true",
+                    help="skip the timing of the approximate forces of Sec. III.D")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -526,6 +549,40 @@ def main():
                                                            "stages_ms": stg}
         ctx.set_mbd_product("auto")
         line["two_radius"] = tr
+    if not args.no_fit and args.precision == "fp64":
+        # Sec. III.A: per atom and node, c_n fitted to ln(1 - x) on the Lanczos bounds of G~
+        fit = {"lanczos_steps": mp.lanczos_steps,
+               "model": "least-squares polynomial of ln(1 - x) of degree n_max on the Lanczos spectrum "
+                        "bounds of each atom and node (Sec. III.A); forces with the coefficients held fixed"}
+        o64 = None
+        for prec in ("fp64", "mixed"):
+            v, msps, o, stg = time_params(dataclasses.replace(mp, precision=prec, cn_mode="fit"))
+            rec = {"value": v, "unit": "atoms/s", "ms_per_step": msps, "stages_ms": stg,
+                   "max_abs_dE_vs_series_eV_per_atom": max_diff(o, out, "energies"),
+                   "mean_abs_dE_vs_series_eV_per_atom": float((o["energies"] - out["energies"]).abs().mean())}
+            if prec == "fp64":
+                o64 = o
+            else:
+                rec["max_abs_dE_vs_fp64_eV_per_atom"] = max_diff(o, o64, "energies")
+                rec["max_abs_dF_vs_fp64_eV_per_A"] = max_diff(o, o64, "forces")
+            fit[prec] = rec
+        spec = P.compute(pos, sp, nu, cutoffs=cut, params=dataclasses.replace(mp, cn_mode="fit"),
+                         species_table=SPECIES_TABLE, cell=st.cell, forces=False, ctx=ctx, stream=stream,
+                         want_spectrum=True)["spectrum"]
+        fit["spectrum_bounds"] = {"min_lambda_min": float(spec[..., 0].min()),
+                                  "max_lambda_max": float(spec[..., 1].max())}
+        line["fitted_cn"] = fit
+    if not args.no_paper_forces and args.precision == "fp64":
+        # Sec. III.D: each atom's force from its own neighbourhood, central polarisabilities fixed
+        pf = {"model": "approximate forces of Sec. III.D (Eqs. full-pol-grad, cent-appr-step, cent-appr)"}
+        for prec in ("fp64", "mixed"):
+            v, msps, o, stg = time_params(dataclasses.replace(mp, precision=prec, force_model="paper"))
+            d = (o["forces"] - out["forces"]).norm(dim=1)
+            pf[prec] = {"value": v, "unit": "atoms/s", "ms_per_step": msps, "stages_ms": stg,
+                        "max_abs_dF_vs_exact_eV_per_A": max_diff(o, out, "forces"),
+                        "rms_dF_vs_exact_eV_per_A": float(d.pow(2).mean().sqrt()),
+                        "rms_F_exact_eV_per_A": float(out["forces"].norm(dim=1).pow(2).mean().sqrt())}
+        line["paper_forces"] = pf
     if not args.no_mixed and args.precision == "fp64" and args.workload == "plain":
         line["mixed_c13824"] = mixed_large(args, P, mp)
     if not args.no_serve:
