@@ -55,15 +55,17 @@ namespace lmbd {
 
 __host__ __device__ inline size_t al4(size_t x) { return (x + 3) / 4 * 4; }
 
-// LDS layout.  The pair sums g of the force stage take the place of sqrt(alpha~),
-// whose last use (the operands of Tbar) precedes them.
+// Per-site arrays (LDS, or the workspace) and the small per-atom arrays (LDS).  The
+// pair sums g of the force stage take the place of sqrt(alpha~), whose last use (the
+// operands of Tbar) precedes them.
 struct MbdLds {
     double *px, *py, *pz, *sa, *sqa, *Rt, *fs, *dfs, *ab, *g, *rb, *fg, *mu, *cf, *lz;
 };
 // sa and ab hold every frequency of the energy: 0 and the nq nodes.  cf (fitted
 // coefficients, [nq][kMaxNmax + 1] and [kMaxNmax + 1][nq]) and lz (Lanczos: alpha and beta [steps][nq], the steps
-// taken and the two bounds per node) exist only when used.
-__device__ inline MbdLds mbd_lds(double* b, int nk, int nq, int n_max, int lz_steps, bool fit) {
+// taken and the two bounds per node) exist only when used.  The site arrays take
+// mbd_site_doubles(nk, nq) from b, the small ones start at sm.
+__device__ inline MbdLds mbd_lds(double* b, int nk, int nq, double* sm, int n_max, bool fit) {
     const int nw = nq + 1;
     MbdLds L;
     L.px = b;
@@ -78,21 +80,15 @@ __device__ inline MbdLds mbd_lds(double* b, int nk, int nq, int n_max, int lz_st
     L.ab = L.dfs + nk;
     L.rb = L.ab + (size_t)nk * nw;    // [4 parts][nk]
     L.fg = L.rb + 4 * (size_t)nk;     // [nk][3]
-    L.mu = L.fg + 3 * (size_t)nk;
+    L.mu = sm;
     L.cf = L.mu + (size_t)(n_max + 1) * nq;
     L.lz = L.cf + (fit ? 2 * (size_t)(kMaxNmax + 1) * nq : 0);
     return L;
 }
 
-__host__ __device__ inline size_t lz_lds_doubles(int nq, int lz_steps) {
-    return lz_steps > 0 ? (2 * (size_t)lz_steps + 3) * nq : 0;
-}
-
+// (nkmax = 0: the sparse form with the site arrays in the workspace)
 size_t mbd_lds_bytes(int nkmax, int nq, int n_max, int lz_steps, bool fit) {
-    const size_t nk = nkmax, nw = (size_t)nq + 1;
-    return sizeof(double) * (3 * nk + nk * nw + nk * (size_t)std::max(nq, 12) + 3 * nk + nk * nw + 4 * nk +
-                             3 * nk + (size_t)(n_max + 1) * nq + (fit ? 2 * (size_t)(kMaxNmax + 1) * nq : 0) +
-                             lz_lds_doubles(nq, lz_steps));
+    return sizeof(double) * (mbd_site_doubles((size_t)nkmax, nq) + mbd_small_doubles(nq, n_max, lz_steps, fit));
 }
 
 // The output function of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) on a 64-bit counter.
@@ -363,8 +359,9 @@ __device__ inline void wave_sum9(const double (&v)[9], double (&out)[9]) {
 // The sparse form is bound by the latency of its gathers rather than by arithmetic:
 // it runs 1,024 threads (four wavefronts per SIMD at its register count) to hide it.
 constexpr int kMbdThreadsSparse = 1024;
-template <typename W, bool SP>
-__global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
+template <typename W, int FORM>
+__global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
+    constexpr bool SP = FORM != kMbdDense, GS = FORM == kMbdSparseGlobal;
     extern __shared__ double lds[];
     const int k = a.order[blockIdx.x];
     const int tid = threadIdx.x;
@@ -376,7 +373,11 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rs = SI.r_scs;
     const bool fit = a.fit != 0;
-    MbdLds L = mbd_lds(lds, nkmax, nq, n_max, a.lz_steps, fit);
+    W* const wbase = static_cast<W*>(a.work) + a.work_off[k];
+    const int64_t lcap = GS ? mbd_list_cap(nK, SI.m2max) : (int64_t)nK * nK;   // list entries
+    const MbdGlobalLayout G = mbd_global_layout(nK, nq, n_max, a.mmax, lcap, (int64_t)sizeof(W), a.forces != 0);
+    MbdLds L = GS ? mbd_lds(reinterpret_cast<double*>(wbase + G.sites), nK, nq, lds, n_max, fit)
+                  : mbd_lds(lds, nkmax, nq, lds + mbd_site_doubles((size_t)nkmax, nq), n_max, fit);
     // c_n at node q: fitted per atom and node, or the common series
     // (fitted: two copies in LDS, [kMaxNmax + 1][nq] here and [nq][kMaxNmax + 1] for the adjoint operands,
     // whose per-element loop keeps one node's coefficients at fixed offsets)
@@ -385,15 +386,23 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const Site* S = a.sites + a.site_off[k];
     const double* aloc = a.alpha_loc + a.aloc_off[k];
-    W* T = static_cast<W*>(a.work) + a.work_off[k];
     // sub-arrays start on multiples of 4 elements (aligned 4-vector loads)
     const int KK = n_max * ncol, KKp = (KK + 3) / 4 * 4;
     const int N3p = (int)al4(N3);                            // row stride of T and of V^T (zero padded)
+    W* T = wbase;                                            // dense T_LR (the sparse form's lists in its space)
     W* U = T + al4((size_t)N3 * N3p);                        // u_1 .. u_mmax
     W* V = U + al4((size_t)a.mmax * N3 * ncol);              // (D u_m)^T, the next product's operand, ncol x N3p,
     W* V2 = V + al4((size_t)ncol * N3p);                     //   in two buffers used in turn
     W* Pm = V2 + al4((size_t)ncol * N3p);                    // D u_a side by side, a = 0 .. n_max-1
     W* Qm = Pm + (size_t)N3 * KKp;                           // W D Z_a side by side
+    if constexpr (GS) {   // no dense T: the parts of the global-site layout
+        T = wbase + G.lists;
+        U = wbase + G.U;
+        V = wbase + G.V;
+        V2 = wbase + G.V2;
+        Pm = wbase + G.P;
+        Qm = wbase + G.Q;
+    }
     auto Uat = [&](int m) { return U + (size_t)(m - 1) * N3 * ncol; };
 
     // --- blend (Sec. III.B, central/local combination) and SCS radii
@@ -471,13 +480,19 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     __syncthreads();
     }
 
-    // sparse form: coefficients of the pair (i, j), T_LR,ij = A rhat rhat^T + B I, when it couples
-    auto couple = [&](int i, int j, W& A, W& B, double rh[3]) -> bool {
+    // sparse form: whether the pair (i, j) couples, and its coefficients T_LR,ij = A rhat rhat^T + B I
+    auto coupled = [&](int i, int j, double v[3], double& r) -> bool {
         if (j >= nK || j == i) return false;
-        const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-        const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        v[0] = L.px[i] - L.px[j];
+        v[1] = L.py[i] - L.py[j];
+        v[2] = L.pz[i] - L.pz[j];
+        r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        return r < ((i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2);
+    };
+    auto couple = [&](int i, int j, W& A, W& B, double rh[3]) -> bool {
+        double v[3], r;
+        if (!coupled(i, j, v, r)) return false;
         const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
-        if (!(r < rcut)) return false;
         const LrPair<W> t = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut), W(a.r_buf));
         A = t.A;
         B = t.B;
@@ -487,27 +502,58 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         return true;
     };
     // sparse form: the coupled sites of every block row and their coefficients, found
-    // once per atom and kept in the space of the dense T (unused here): row i holds
-    // up to nK entries at [i nK, i nK + cnt_i); (4 + 5 sizeof(W)) nK^2 + 4 nK bytes fit
-    // in the 9 nK^2 sizeof(W) of the dense T
-    const size_t NN = (size_t)nK * nK;
+    // once per atom: row i at [roff[i], roff[i + 1]) of NN entries (site index, A, B, rhat).
+    // With the site arrays in LDS they sit in the space of the dense T (unused here):
+    // (4 + 5 sizeof(W)) nK^2 + 4 (nK + 1) bytes fit in its 9 nK^2 sizeof(W); else in a part of
+    // their own, sized from the structure's largest count of sites within r_mbd2.
+    const size_t NN = (size_t)lcap;
     W* const pA = T;
     W* const pB = pA + NN;
     W* const pR0 = pB + NN;
     W* const pR1 = pR0 + NN;
     W* const pR2 = pR1 + NN;
     int* const pj = reinterpret_cast<int*>(pR2 + NN);
-    int* const pcnt = pj + NN;
+    int* const roff = pj + NN;
     if constexpr (SP) {
+        // counts per row (into roff[i + 1]), then their running sum over the rows
         for (int i = wave; i < nK; i += nwave) {
             int n = 0;
+            for (int j0 = 0; j0 < nK; j0 += 64) {
+                double v[3], r;
+                n += __popcll(__ballot(coupled(i, j0 + lane, v, r)));
+            }
+            if (lane == 0) roff[i + 1] = n;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            int carry = 0;
+            for (int i0 = 0; i0 < nK; i0 += 64) {
+                const bool in = i0 + lane < nK;
+                int x = in ? roff[i0 + lane + 1] : 0;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(x, o);
+                    if (lane >= o) x += t;
+                }
+                if (in) roff[i0 + lane + 1] = carry + x;
+                carry += __shfl(x, 63);
+            }
+            if (lane == 0) roff[0] = 0;
+        }
+        __syncthreads();
+        if (tid == 0 && (size_t)roff[nK] > NN) {   // a row outgrew the bound: refuse the call
+            atomicOr(a.err, 32);
+            atomicMin(a.err_atom, k);
+        }
+        for (int i = wave; i < nK; i += nwave) {
+            int n = roff[i];
             for (int j0 = 0; j0 < nK; j0 += 64) {
                 W A = W(0), B = W(0);
                 double rh[3] = {0.0, 0.0, 0.0};
                 const bool in = couple(i, j0 + lane, A, B, rh);
                 const unsigned long long mask = __ballot(in);
-                if (in) {
-                    const size_t e = (size_t)i * nK + n + __popcll(mask & ((1ull << lane) - 1ull));
+                const size_t e = (size_t)n + __popcll(mask & ((1ull << lane) - 1ull));
+                if (in && e < NN) {
                     pj[e] = j0 + lane;
                     pA[e] = A;
                     pB[e] = B;
@@ -517,13 +563,14 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
                 }
                 n += __popcll(mask);
             }
-            if (lane == 0) pcnt[i] = n;
         }
         __syncthreads();
     }
-    // sparse form: Uout = D T D Uin, one block row (and 64 columns) per wavefront, lanes over
-    // the columns, four coupled sites per step; the loads use in-bounds indices (entry 0 of the
-    // row, column 0) with a zero factor instead of a branch, so that they overlap
+    // entries of row i: [roff[i], roff[i] + row_len(i)), within the capacity
+    auto row_len = [&](int i) -> int {
+        const int e1 = roff[i + 1] < (int)NN ? roff[i + 1] : (int)NN;
+        return e1 > roff[i] ? e1 - roff[i] : 0;
+    };
     // sparse form: Uout = D T D Uin, one block row (and 64 columns) per wavefront, lanes over
     // the columns, four coupled sites per step; the loads use in-bounds indices (entry 0 of the
     // row, column 0) with a zero factor instead of a branch, so that they overlap
@@ -531,8 +578,8 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         for (int it = wave; it < nK * ((ncol + 63) / 64); it += nwave) {
             const int i = it % nK, col = (it / nK) * 64 + lane, q = col / 3;
             const int cs = col < ncol ? col : 0, qs = cs / 3;
-            const int n = pcnt[i];
-            const size_t e0 = (size_t)i * nK;
+            const int n = row_len(i);
+            const size_t e0 = (size_t)roff[i];
             W acc0 = W(0), acc1 = W(0), acc2 = W(0);
             for (int s0 = 0; s0 < n; s0 += 4) {
                 // the four entries are loaded cooperatively (lane 4 f + u holds field f of entry
@@ -579,8 +626,8 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     auto sparse_product_lz = [&](const W* __restrict__ Vin, W* __restrict__ Vout) {
         const int q = lane < nq ? lane : 0;
         for (int i = wave; i < nK; i += nwave) {
-            const int n = pcnt[i];
-            const size_t e0 = (size_t)i * nK;
+            const int n = row_len(i);
+            const size_t e0 = (size_t)roff[i];
             W acc0 = W(0), acc1 = W(0), acc2 = W(0);
             for (int t = 0; t < n; ++t) {
                 const size_t e = e0 + t;
@@ -969,7 +1016,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
         for (int i = wave; i < nK; i += nwave) {
             double g[3] = {0.0, 0.0, 0.0};
             double Rb = 0.0;
-            const int n = pcnt[i];
+            const int n = row_len(i);
             // eight coupled pairs per step, eight lanes per pair: lane 8u + t sums columns
             // t, t + 8, ... (16 bytes each) of pair u's nine dot products; the eight lanes of
             // a pair then combine their sums and the pair's first lane takes its tail
@@ -978,7 +1025,7 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
             const int pu = lane >> 3, pt = lane & 7;
             for (int s0 = 0; s0 < n; s0 += 8) {
                 const bool okp = s0 + pu < n;
-                const int j = pj[(size_t)i * nK + (okp ? s0 + pu : s0)];
+                const int j = pj[(size_t)roff[i] + (okp ? s0 + pu : s0)];
                 const int I = max(i, j), J = min(i, j);
                 double sb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 for (int kb = 0; kb < KKp; kb += 8 * VW) {
@@ -1173,16 +1220,26 @@ __global__ void __launch_bounds__(SP ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd
     for (int e = tid; e < (nall - nK) * nw; e += blockDim.x) cap[(size_t)nK * nw + e] = 0.0;
 }
 
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse) {
-    const size_t lds = mbd_lds_bytes(nkmax, a.nq, a.n_max, a.lz_steps, a.fit != 0);
-    if (mixed && sparse)
-        hipLaunchKernelGGL((k_mbd<float, true>), dim3(a.n), dim3(kMbdThreadsSparse), lds, st, a, nkmax);
-    else if (mixed)
-        hipLaunchKernelGGL((k_mbd<float, false>), dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
-    else if (sparse)
-        hipLaunchKernelGGL((k_mbd<double, true>), dim3(a.n), dim3(kMbdThreadsSparse), lds, st, a, nkmax);
-    else
-        hipLaunchKernelGGL((k_mbd<double, false>), dim3(a.n), dim3(kMbdThreads), lds, st, a, nkmax);
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, int form) {
+    const int nk_lds = form == kMbdSparseGlobal ? 0 : nkmax;   // per-site arrays in LDS or not
+    const size_t lds = mbd_lds_bytes(nk_lds, a.nq, a.n_max, a.lz_steps, a.fit != 0);
+    const dim3 grid(a.n), blk(form == kMbdDense ? kMbdThreads : kMbdThreadsSparse);
+    if (form == kMbdDense) {
+        if (mixed)
+            hipLaunchKernelGGL((k_mbd<float, kMbdDense>), grid, blk, lds, st, a, nk_lds);
+        else
+            hipLaunchKernelGGL((k_mbd<double, kMbdDense>), grid, blk, lds, st, a, nk_lds);
+    } else if (form == kMbdSparse) {
+        if (mixed)
+            hipLaunchKernelGGL((k_mbd<float, kMbdSparse>), grid, blk, lds, st, a, nk_lds);
+        else
+            hipLaunchKernelGGL((k_mbd<double, kMbdSparse>), grid, blk, lds, st, a, nk_lds);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_mbd<float, kMbdSparseGlobal>), grid, blk, lds, st, a, nk_lds);
+        else
+            hipLaunchKernelGGL((k_mbd<double, kMbdSparseGlobal>), grid, blk, lds, st, a, nk_lds);
+    }
     return hipGetLastError();
 }
 

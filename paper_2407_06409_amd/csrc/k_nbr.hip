@@ -198,12 +198,13 @@ __device__ inline void stencil_block(const StructInfo& S, int w, int& c0, int& c
 }
 
 __global__ void __launch_bounds__(64 * kNbrWaves) k_nbr_count(NbrArgs a, Counts* __restrict__ counts) {
-    __shared__ int part[kNbrWaves][4];
+    __shared__ int part[kNbrWaves][5];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int k = blockIdx.x;
     const StructInfo& S = a.sinfo[a.atom_struct[k]];
-    const double r1 = S.r_scs * S.r_scs, rK = S.r_nbr * S.r_nbr, r2 = 4.0 * S.r_scs * S.r_scs;
-    int c_all = 0, c1 = 0, cK = 0, c12 = 0;
+    const double r1 = S.r_scs * S.r_scs, rK = S.r_nbr * S.r_nbr, r2 = 4.0 * S.r_scs * S.r_scs,
+                 rM2 = S.r_mbd2 * S.r_mbd2;
+    int c_all = 0, c1 = 0, cK = 0, c12 = 0, cM2 = 0;
     int cb, ce;
     stencil_block(S, wave, cb, ce);
     visit_candidates(a, k, lane, cb, ce, [&](bool valid, int, int, int, int, const double*, double d2) {
@@ -212,6 +213,7 @@ __global__ void __launch_bounds__(64 * kNbrWaves) k_nbr_count(NbrArgs a, Counts*
             c1 += d2 < r1;
             cK += d2 < rK;
             c12 += d2 < r2;
+            cM2 += d2 < rM2;
         }
     });
     for (int off = 32; off > 0; off >>= 1) {
@@ -219,6 +221,7 @@ __global__ void __launch_bounds__(64 * kNbrWaves) k_nbr_count(NbrArgs a, Counts*
         c1 += __shfl_xor(c1, off);
         cK += __shfl_xor(cK, off);
         c12 += __shfl_xor(c12, off);
+        cM2 += __shfl_xor(cM2, off);
     }
     if (lane == 0) {
         int32_t* wc = a.wcounts + ((size_t)k * kNbrWaves + wave) * 4;
@@ -230,13 +233,14 @@ __global__ void __launch_bounds__(64 * kNbrWaves) k_nbr_count(NbrArgs a, Counts*
         part[wave][1] = c1;
         part[wave][2] = cK;
         part[wave][3] = c12;
+        part[wave][4] = cM2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int t[4] = {0, 0, 0, 0};
+        int t[5] = {0, 0, 0, 0, 0};
         for (int w = 0; w < kNbrWaves; ++w)
-            for (int q = 0; q < 4; ++q) t[q] += part[w][q];
-        counts[k] = Counts{1 + t[0], 1 + t[1], 1 + t[2], 1 + t[3]};
+            for (int q = 0; q < 5; ++q) t[q] += part[w][q];
+        counts[k] = Counts{1 + t[0], 1 + t[1], 1 + t[2], 1 + t[3], 1 + t[4]};
     }
 }
 

@@ -41,6 +41,7 @@ struct Plan {
     int64_t table_len = 0;
     int64_t fac_len = 0, x_len = 0, aloc_len = 0, work_len = 0, coef_len = 0;
     int n1max = 0, nkmax = 0, nallmax = 0, n2max = 0;
+    int nkmax_lds = 0;            // largest nK among the atoms whose MBD site arrays sit in LDS
     std::vector<int64_t> site_off, hash_off, fac_off, x_off, aloc_off, work_off, pl_off, coef_off;
     int64_t pl_len = 0;
     std::vector<int32_t> hash_cap, fac_ld;
@@ -317,7 +318,33 @@ int64_t next_pow2(int64_t x) {
     return p;
 }
 
-void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, bool forces, bool mixed, Plan& P) {
+// Atoms whose MBD stage keeps its per-site arrays in the workspace (the sparse form with
+// global site arrays): those of structures whose largest neighbourhood K exceeds the LDS
+// forms, in sites or in LDS bytes (with room for the Lanczos state, so that the choice does
+// not depend on the outputs requested).  Per atom also the structure's largest count of
+// sites within r_mbd2 (the bound of the sparse rows).  struct_begin: first atom of each
+// structure, then the total.
+void mbd_global_sites(const lmbd_params* p, const std::vector<Counts>& cnt, const std::vector<int64_t>& struct_begin,
+                      std::vector<char>& gs, std::vector<int32_t>& m2max) {
+    const int lz = p->lanczos_steps ? p->lanczos_steps : 20;
+    gs.assign(cnt.size(), 0);
+    m2max.assign(cnt.size(), 0);
+    for (size_t s = 0; s + 1 < struct_begin.size(); ++s) {
+        int nk = 0, m2 = 0;
+        for (int64_t k = struct_begin[s]; k < struct_begin[s + 1]; ++k) {
+            nk = std::max(nk, cnt[k].nK);
+            m2 = std::max(m2, cnt[k].n_m2);
+        }
+        const bool g = nk > kMaxNK || mbd_lds_bytes(nk, p->n_freq, p->n_max, lz, p->cn_mode == LMBD_CN_FIT) > kLdsBytes;
+        for (int64_t k = struct_begin[s]; k < struct_begin[s + 1]; ++k) {
+            gs[k] = g ? 1 : 0;
+            m2max[k] = m2;
+        }
+    }
+}
+
+void build_plan(const std::vector<Counts>& cnt, const std::vector<char>& gs, const std::vector<int32_t>& m2max, int nw,
+                int ncol, int n_max, bool forces, bool mixed, Plan& P) {
     const int64_t n = (int64_t)cnt.size();
     P.n_atoms = n;
     P.site_off.resize(n + 1);
@@ -332,7 +359,7 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
     P.fac_ld.resize(n);
     const int mmax = forces ? std::max(1, n_max - 1) : std::max(1, (n_max + 1) / 2);
     int64_t so = 0, ho = 0, fo = 0, xo = 0, ao = 0, wo = 0, po = 0, co = 0;
-    P.n1max = P.nkmax = P.nallmax = P.n2max = 0;
+    P.n1max = P.nkmax = P.nallmax = P.n2max = P.nkmax_lds = 0;
     for (int64_t k = 0; k < n; ++k) {
         const Counts& c = cnt[k];
         P.site_off[k] = so;
@@ -354,8 +381,13 @@ void build_plan(const std::vector<Counts>& cnt, int nw, int ncol, int n_max, boo
         xo += (int64_t)nw * N1 * 3;
         ao += (int64_t)c.n1 * nw;
         auto al4 = [](int64_t x) { return (x + 3) / 4 * 4; };  // as the MBD kernel lays out its workspace
-        wo += al4(N3 * al4(N3)) + al4((int64_t)mmax * N3 * ncol) + 2 * al4(ncol * al4(N3)) +
-              (forces ? 2 * N3 * al4((int64_t)n_max * ncol) : 0);
+        if (gs[k])
+            wo += mbd_global_layout(c.nK, ncol / 3, n_max, mmax, mbd_list_cap(c.nK, m2max[k]), mixed ? 4 : 8, forces)
+                      .total;
+        else
+            wo += al4(N3 * al4(N3)) + al4((int64_t)mmax * N3 * ncol) + 2 * al4(ncol * al4(N3)) +
+                  (forces ? 2 * N3 * al4((int64_t)n_max * ncol) : 0);
+        if (!gs[k]) P.nkmax_lds = std::max(P.nkmax_lds, c.nK);
         P.n1max = std::max(P.n1max, c.n1);
         P.nkmax = std::max(P.nkmax, c.nK);
         P.nallmax = std::max(P.nallmax, c.n_all);
@@ -691,9 +723,9 @@ lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<
         for (int g = 0; g < n; ++g) order[fill[cell[g]]++] = g;
     }
     const double r1 = S.r_scs * S.r_scs, rK = S.r_nbr * S.r_nbr, r2 = 4.0 * S.r_scs * S.r_scs,
-                 rb = S.r_big * S.r_big;
+                 rb = S.r_big * S.r_big, rM2 = S.r_mbd2 * S.r_mbd2;
     auto count_one = [&](int k) {
-        Counts c{1, 1, 1, 1};
+        Counts c{1, 1, 1, 1, 1};
         const int ck[3] = {cell[k] / (S.ncell[1] * S.ncell[2]), (cell[k] / S.ncell[2]) % S.ncell[1],
                            cell[k] % S.ncell[2]};
         for (int dx = -S.reach[0]; dx <= S.reach[0]; ++dx)
@@ -728,6 +760,7 @@ lmbd_status host_counts(lmbd_context* ctx, const lmbd_structure& s, std::vector<
                         c.n1 += d2 < r1;
                         c.nK += d2 < rK;
                         c.n12 += d2 < r2;
+                        c.n_m2 += d2 < rM2;
                     }
                 }
         return c;
@@ -768,10 +801,12 @@ lmbd_status analyse_structure(const lmbd_params* params, const lmbd_structure& s
 lmbd_status layout_bytes(const lmbd_params* params, int n_species, const std::vector<const StructCounts*>& parts,
                          size_t* bytes) {
     std::vector<Counts> cnt;
+    std::vector<int64_t> begin(1, 0);
     bool forces = false;
     int n_cells = 0;
     for (const StructCounts* p : parts) {
         cnt.insert(cnt.end(), p->cnt.begin(), p->cnt.end());
+        begin.push_back((int64_t)cnt.size());
         n_cells += p->n_cells;
         forces = forces || p->forces;
     }
@@ -790,7 +825,10 @@ lmbd_status layout_bytes(const lmbd_params* params, int n_species, const std::ve
     Measure m;
     (void)layout_pre(&layout, pd, m);
     Plan P;
-    build_plan(cnt, nw, 3 * params->n_freq, params->n_max, forces, params->precision == LMBD_MIXED, P);
+    std::vector<char> gs;
+    std::vector<int32_t> m2max;
+    mbd_global_sites(params, cnt, begin, gs, m2max);
+    build_plan(cnt, gs, m2max, nw, 3 * params->n_freq, params->n_max, forces, params->precision == LMBD_MIXED, P);
     (void)layout_post(&layout, P, nw, params->n_freq, forces,
                       params->precision == LMBD_MIXED ? sizeof(float) : sizeof(double), m);
     *bytes = m.total;
@@ -1033,20 +1071,34 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     if (flags[0] & 1) return fail(ctx, LMBD_E_INVALID_ARG, "invalid species, volume ratio or position");
 
     // --- memory plan
+    std::vector<int64_t> sbegin(n_structs + 1, 0);
+    for (int s = 0; s < n_structs; ++s) sbegin[s + 1] = sbegin[s] + structs[s].n_atoms;
+    std::vector<char> gsites;
+    std::vector<int32_t> m2max;
+    mbd_global_sites(params, cnt, sbegin, gsites, m2max);
+    for (int s = 0; s < n_structs; ++s) sinfo[s].m2max = m2max[sbegin[s]];
+    if ((st = upload(ctx, ctx->sinfo, sinfo, stream)) != LMBD_OK) return st;
     Plan P;
-    build_plan(cnt, nw, ncol, n_max, forces, mixed, P);
-    // MBD product form per structure, not per call, so that a structure's results do
-    // not depend on what it shares a call with: dense-form atoms first, then
-    // sparse-form atoms, each part still largest first
-    std::vector<char> sparse_struct(n_structs);
-    for (int s = 0; s < n_structs; ++s)
-        sparse_struct[s] = params->force_model == LMBD_FORCES_EXACT &&   // the approximate forces use dense products
-                           (ctx->mbd_product == LMBD_MBD_SPARSE ||
-                            (ctx->mbd_product == LMBD_MBD_AUTO && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr));
-    std::stable_partition(P.order.begin(), P.order.end(), [&](int32_t k) { return !sparse_struct[atom_struct[k]]; });
-    int n_dense = 0;
-    for (int k = 0; k < N; ++k) n_dense += sparse_struct[atom_struct[k]] ? 0 : 1;
-    if (P.n1max > kMaxN1 || P.nkmax > kMaxNK || P.nallmax > kMaxSites)
+    build_plan(cnt, gsites, m2max, nw, ncol, n_max, forces, mixed, P);
+    // MBD kernel form per structure, not per call, so that a structure's results do not
+    // depend on what it shares a call with: dense-form atoms first, then sparse-form atoms
+    // with the site arrays in LDS, then those with them in the workspace, each part still
+    // largest first
+    std::vector<int> form(n_structs);
+    for (int s = 0; s < n_structs; ++s) {
+        const bool sparse = params->force_model == LMBD_FORCES_EXACT &&   // the approximate forces use dense products
+                            (ctx->mbd_product == LMBD_MBD_SPARSE ||
+                             (ctx->mbd_product == LMBD_MBD_AUTO && structs[s].r_mbd2 <= kSparseMbdRatio * structs[s].r_nbr));
+        form[s] = gsites[sbegin[s]] ? kMbdSparseGlobal : sparse ? kMbdSparse : kMbdDense;
+        if (form[s] == kMbdSparseGlobal && (params->force_model != LMBD_FORCES_EXACT || ctx->mbd_product == LMBD_MBD_DENSE))
+            return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood too large for the dense MBD products (nK up to " +
+                                                     std::to_string(kMaxNK) + "; larger ones need the sparse form)");
+    }
+    std::stable_sort(P.order.begin(), P.order.end(),
+                     [&](int32_t x, int32_t y) { return form[atom_struct[x]] < form[atom_struct[y]]; });
+    int n_form[3] = {0, 0, 0};
+    for (int k = 0; k < N; ++k) n_form[form[atom_struct[k]]]++;
+    if (P.n1max > kMaxN1 || P.nkmax_lds > kMaxNK || P.nallmax > kMaxSites)
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
                         ", sites " + std::to_string(P.nallmax) + ")");
@@ -1055,7 +1107,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
         ctx->lds_limit = lds_limit;
     }
-    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax, nq, n_max, lz_steps, fit) > (size_t)lds_limit ||
+    if (scs_lds_bytes(P.n1max, P.n2max, mixed) > (size_t)lds_limit || mbd_lds_bytes(P.nkmax_lds, nq, n_max, lz_steps, fit) > (size_t)lds_limit ||
         scs_factor_lds_bytes(P.n1max, mixed) > (size_t)lds_limit || scs_assemble_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit ||
         pairlist_lds_bytes(P.n1max, P.n2max) > (size_t)lds_limit)
         return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood needs more LDS than the device offers (" +
@@ -1190,16 +1242,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
     HIP_TRY(mark(5, 0));
-    if (n_dense > 0) {
-        MbdArgs md = ma;
-        md.n = n_dense;
-        HIP_TRY(launch_mbd(stream, md, P.nkmax, mixed, false));
-    }
-    if (n_dense < N) {   // the sparse form pays once block rows couple to a small part of K
-        MbdArgs ms = ma;
-        ms.n = N - n_dense;
-        ms.order = ma.order + n_dense;
-        HIP_TRY(launch_mbd(stream, ms, P.nkmax, mixed, true));
+    for (int f = 0, first = 0; f < 3; first += n_form[f], ++f) {   // the sparse forms pay once block rows
+        if (n_form[f] == 0) continue;                                   // couple to a small part of K
+        MbdArgs mf = ma;
+        mf.n = n_form[f];
+        mf.order = ma.order + first;
+        HIP_TRY(launch_mbd(stream, mf, P.nkmax_lds, mixed, f));
     }
     HIP_TRY(mark(5, 1));
 
@@ -1273,6 +1321,8 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         return fail(ctx, LMBD_E_SCS_BREAKDOWN,
                     "SCS polarisability not decreasing between 0 and omega_ref in the frame of atom " +
                         std::to_string(flags[1]));
+    if (flags[0] & 32)
+        return fail(ctx, LMBD_E_DEVICE, "coupled-site lists of atom " + std::to_string(flags[1]) + " outgrew their bound");
     if (flags[0] & 16)
         return fail(ctx, LMBD_E_POLARISATION,
                     "largest eigenvalue bound of G~ >= 1 in the frame of atom " + std::to_string(flags[1]));

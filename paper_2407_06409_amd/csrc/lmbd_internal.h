@@ -58,6 +58,7 @@ struct StructInfo {
     int cell_offset;     // first batch-global cell index
     int atom_offset;     // first batch-global atom index
     int n_atoms;
+    int m2max;           // largest Counts::n_m2 of the structure's atoms (bounds the sparse rows)
     double r_scs, r_nbr, r_mbd1, r_mbd2, r_big;  // bohr
 };
 
@@ -67,6 +68,7 @@ struct Counts {
     int32_t n1;      // r < r_scs       (K1 of the SCS)
     int32_t nK;      // r < r_nbr       (K of the energy)
     int32_t n12;     // r < 2 r_scs     (K1 plus the uncoupled shell K2)
+    int32_t n_m2;    // r < r_mbd2      (the sites a block row other than the central one couples to)
 };
 
 // ---------------------------------------------------------------------------
@@ -236,7 +238,8 @@ struct MbdArgs {
     double gl_w[kFitNodes];
     double* spectrum;          // [n][nq][2] Lanczos bounds (batch-global atom index), or null
     int* err;                  // bit 8: a polarisability rises between 0 and omega_ref;
-                               // bit 16: a spectrum bound reaches 1 with the fitted c_n
+                               // bit 16: a spectrum bound reaches 1 with the fitted c_n;
+                               // bit 32: the coupled-site lists outgrew their capacity
     int* err_atom;             // lowest atom whose frame raised an error
     const double* e_weight;    // [n] or null
     double* e_atom;            // [n]
@@ -280,8 +283,61 @@ hipError_t launch_scs_nu(hipStream_t st, const ScsArgs& a, int n1max, int n2max)
 hipError_t launch_gather_nu(hipStream_t st, int n, int nw, const Counts* counts, const int64_t* site_off,
                             const Site* sites, const int32_t* rev, const double* cnu, const double* nu,
                             double* dv);
+// Doubles of the MBD stage's per-site arrays for nk sites and nq nodes: positions (3),
+// blended polarisabilities at 0 and the nodes (nq + 1), their square roots at the nodes
+// (max(nq, 12): the force stage's pair sums take their place), SCS radii, f_SCS and its
+// derivative (3), polarisability adjoints (nq + 1), radius-adjoint parts (4), blend
+// gradients (3).  In LDS, or in the workspace for the sparse form with global site arrays.
+__host__ __device__ inline size_t mbd_site_doubles(size_t nk, int nq) {
+    const size_t nw = (size_t)nq + 1;
+    return 3 * nk + nk * nw + nk * (size_t)(nq > 12 ? nq : 12) + 3 * nk + nk * nw + 4 * nk + 3 * nk;
+}
+// Doubles of the small per-atom LDS arrays: moments, fitted coefficients, Lanczos state.
+__host__ __device__ inline size_t mbd_small_doubles(int nq, int n_max, int lz_steps, bool fit) {
+    return (size_t)(n_max + 1) * nq + (fit ? 2 * (size_t)(kMaxNmax + 1) * nq : 0) +
+           (lz_steps > 0 ? (2 * (size_t)lz_steps + 3) * nq : 0);
+}
+// Capacity (entries) of the coupled-site lists of an atom with nK sites in the sparse form
+// with global site arrays: the central row couples to at most nK - 1 sites, every other row
+// to at most m2max - 1 sites within r_mbd2 plus the central atom (m2max: the structure's
+// largest count of sites within r_mbd2, itself included); two entries of slack per row.
+__host__ __device__ inline int64_t mbd_list_cap(int nK, int m2max) {
+    return (int64_t)(nK - 1) * (m2max + 2) + nK;
+}
+// Per-atom workspace of that form, offsets in elements of the workspace type (size wsz),
+// each part on a 16-byte boundary: site arrays (double), the lists (cap entries of five
+// coefficients A, B, rhat of type W and one int32 site index; nK + 1 int32 row offsets),
+// the Krylov blocks, the two Lanczos/operand buffers and, with forces, P and Q.
+struct MbdGlobalLayout {
+    int64_t sites, lists, U, V, V2, P, Q, total;
+};
+__host__ __device__ inline MbdGlobalLayout mbd_global_layout(int nK, int nq, int n_max, int mmax, int64_t cap,
+                                                             int64_t wsz, bool forces) {
+    const int64_t N3 = 3 * (int64_t)nK, N3p = (N3 + 3) / 4 * 4, ncol = 3 * (int64_t)nq;
+    const int64_t KKp = ((int64_t)n_max * ncol + 3) / 4 * 4;
+    int64_t o = 0;
+    MbdGlobalLayout g;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o += (bytes + 15) / 16 * 16;
+        return at / wsz;
+    };
+    g.sites = take(8 * (int64_t)mbd_site_doubles((size_t)nK, nq));
+    g.lists = take(cap * (5 * wsz + 4) + 4 * ((int64_t)nK + 1));
+    g.U = take(wsz * mmax * N3 * ncol);
+    g.V = take(wsz * ncol * N3p);
+    g.V2 = take(wsz * ncol * N3p);
+    g.P = take(forces ? wsz * N3 * KKp : 0);
+    g.Q = take(forces ? wsz * N3 * KKp : 0);
+    g.total = o / wsz;
+    return g;
+}
+// MBD kernel forms: dense T_LR on the matrix cores; sparse products with the per-site
+// arrays in LDS; sparse products with them in the workspace (neighbourhoods too large for LDS)
+enum { kMbdDense = 0, kMbdSparse = 1, kMbdSparseGlobal = 2 };
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS of a gfx950 workgroup
 size_t mbd_lds_bytes(int nkmax, int nq, int n_max, int lz_steps, bool fit);
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, bool sparse);
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, int form);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,
                                  const double* ca, double* abar_cen);

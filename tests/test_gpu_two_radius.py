@@ -131,3 +131,48 @@ def test_product_form_is_chosen_per_structure():
         alone = compute_batch([r], mp, SPECIES_TABLE)[0]
         assert np.array_equal(alone["energies"], got["energies"])
         assert np.array_equal(alone["forces"], got["forces"])
+
+
+# ---------------------------------------------------------------- neighbourhoods beyond LDS
+# 128 C atoms at 2.0 g/cm^3 (L = 10.9 A), r_SCS = 4, r_MBD,1 = 6, r_MBD,2 = 4, K = B(10 A):
+# about 420 sites per neighbourhood, more than the per-site arrays of the MBD stage can
+# keep in LDS, so the sparse form with its site arrays in the workspace runs.
+BIG_CUT = dict(r_scs=4.0, r_nbr=10.0, r_mbd1=6.0, r_mbd2=4.0)
+BIG_ATOMS = [0, 41, 99]
+
+
+@pytest.fixture(scope="module")
+def big_case():
+    st = C.carbon_box(128, 31, g_cm3=2.0)
+    nk = min(len(oracle.neighbourhood(st.pos, st.cell, st.pbc, k, BIG_CUT["r_nbr"])[0]) for k in BIG_ATOMS)
+    w = np.zeros(st.n)
+    w[BIG_ATOMS] = [1.0, -0.6, 0.8]
+    e, f = oracle.lmbd_energy_forces(st, oracle_params(BIG_CUT), SPECIES_TABLE, weights=w, atoms=BIG_ATOMS)
+    return st, w, e[BIG_ATOMS], f, nk
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_neighbourhoods_beyond_lds_match_oracle(big_case, precision):
+    st, w, e_ref, f_ref, nk = big_case
+    print(f"case C128 {BIG_CUT}, nK at least {nk}, {precision}", flush=True)
+    assert nk > 400
+    g = gpu_run(st, BIG_CUT, weights=w, precision=precision)
+    de = np.abs(g["energies"][BIG_ATOMS] - e_ref).max()
+    df = np.abs(g["forces"] - f_ref).max()
+    print(f"  max |dE| {de:.3e} eV/atom, max |dF| {df:.3e} eV/A (max |F| {np.abs(f_ref).max():.3e})", flush=True)
+    e_tol, f_tol = (1e-8, 1e-8) if precision == "fp64" else (1e-5, 1e-4)
+    assert de < e_tol and df < f_tol
+    assert np.abs(g["forces"].sum(0)).max() < 1e-9
+
+
+def test_neighbourhoods_beyond_lds_need_the_sparse_form(big_case):
+    """Forcing the dense products on such neighbourhoods is refused; energies of every
+    atom are finite and the same with the automatic and the forced sparse choice."""
+    from paper_2407_06409_amd import LmbdError
+    st, w, e_ref, f_ref, nk = big_case
+    with pytest.raises(LmbdError) as ei:
+        gpu_run(st, BIG_CUT, forces=False, ctx=_ctx("dense"))
+    assert ei.value.code == "LMBD_E_UNSUPPORTED"
+    a = gpu_run(st, BIG_CUT, forces=False)
+    b = gpu_run(st, BIG_CUT, forces=False, ctx=_ctx("sparse"))
+    assert np.all(np.isfinite(a["energies"])) and np.array_equal(a["energies"], b["energies"])
