@@ -41,9 +41,13 @@ def neighbour_counts(st, rc):
     """Atoms within rc of every atom, itself included (input analysis only)."""
     from scipy.spatial import cKDTree
     if st.cell is not None:
+        # every periodic image within rc counts (a cube of edge L; rc may exceed L / 2)
         L = float(st.cell[0, 0])
-        tree = cKDTree(np.mod(st.pos, L), boxsize=L)
         pts = np.mod(st.pos, L)
+        m = int(np.ceil(rc / L))
+        rng = np.arange(-m, m + 1)
+        shifts = np.stack(np.meshgrid(rng, rng, rng, indexing="ij"), -1).reshape(-1, 3) * L
+        tree = cKDTree((pts[None, :, :] + shifts[:, None, :]).reshape(-1, 3))
     else:
         tree = cKDTree(st.pos)
         pts = st.pos
@@ -393,6 +397,8 @@ def main():
                     help="skip the timing of the two-radius regime (sparse and dense MBD products)")
     ap.add_argument("--no-two-point", action="store_true",
                     help="skip the timing of the two-point Lorentzian SCS frequency model")
+    ap.add_argument("--no-production-radii", action="store_true",
+                    help="skip the timing of the production two-radius settings (10 + 8 A)")
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the timing of the eigenvalue-bounded fitted coefficients")
     ap.add_argument("--no-paper-forces", action="store_true",
@@ -549,6 +555,40 @@ def main():
                                                            "stages_ms": stg}
         ctx.set_mbd_product("auto")
         line["two_radius"] = tr
+    if not args.no_production_radii and args.precision == "fp64" and args.workload == "plain":
+        # Sec. III.A/IV production radii: r_MBD,1 = 10, r_MBD,2 = 8, K = B(18 A) with periodic images
+        cut3 = dict(r_scs=cut["r_scs"], r_nbr=18.0, r_mbd1=10.0, r_mbd2=8.0)
+        pr = {"cutoffs_A": cut3, "mean_nK": float(neighbour_counts(st, cut3["r_nbr"]).mean()),
+              "mean_sites_within_r_mbd2": float(neighbour_counts(st, cut3["r_mbd2"]).mean()),
+              "form": "sparse MBD products with the per-site arrays in the workspace"}
+        ctx3 = P.Context(0)
+        ctx3.set_profiling(True)
+        steps3 = min(args.steps, 3)
+        for prec in ("fp64", "mixed"):
+            prm3 = dataclasses.replace(mp, precision=prec)
+
+            def run3():
+                return P.compute(pos, sp, nu, cutoffs=cut3, params=prm3, species_table=SPECIES_TABLE,
+                                 cell=st.cell, forces=True, ctx=ctx3, stream=stream)
+            run3()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps3):
+                o3 = run3()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rec = {"value": st.n * steps3 / el, "unit": "atoms/s", "ms_per_step": el / steps3 * 1e3,
+                   "steps": steps3, "stages_ms": dict(ctx3.stage_times())}
+            if prec == "fp64":
+                o3_64 = o3
+            else:
+                rec["max_abs_dE_vs_fp64_eV_per_atom"] = max_diff(o3, o3_64, "energies")
+                rec["max_abs_dF_vs_fp64_eV_per_A"] = max_diff(o3, o3_64, "forces")
+            pr[prec] = rec
+        pr["energy_eV_per_atom_mean"] = float(o3_64["energies"].mean())
+        ctx3.close()
+        del o3, o3_64
+        line["production_radii"] = pr
     if not args.no_fit and args.precision == "fp64":
         # Sec. III.A: per atom and node, c_n fitted to ln(1 - x) on the Lanczos bounds of G~
         fit = {"lanczos_steps": mp.lanczos_steps,

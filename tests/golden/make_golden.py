@@ -115,6 +115,15 @@ def two_radius_6_3():
     return st, dict(r_scs=6.0, r_nbr=9.0, r_mbd1=6.0, r_mbd2=3.0)
 
 
+def two_radius_10_8():
+    """The 1,728-atom carbon box at production two-radius settings of Sec. III.A/IV:
+    r_SCS = 6 A, r_MBD,1 = 10 A, r_MBD,2 = 8 A and K = B(18 A), about 2,450 sites
+    per neighbourhood (periodic images included), each row other than the central
+    atom's coupled to about 220 of them."""
+    st, _ = C.config_plain_pbc()
+    return st, dict(r_scs=6.0, r_nbr=18.0, r_mbd1=10.0, r_mbd2=8.0)
+
+
 def small_hcno_box(n, rc):
     """Periodic H/C/N/O cube at 1.0 g/cm^3 small enough that every atom's own
     periodic images lie inside its SCS shell (edge below 2 r_SCS), as the
@@ -149,13 +158,18 @@ def fixture(name):
         return {"cutoffs": cut,
                 "energies": energies_fixture("C1728 two-radius", st, cut, sample(st.n, 4, 13)),
                 "forces": forces_fixture("C1728 two-radius", st, cut, sample(st.n, 1, 14))}
+    if name == "C1728_pbc_10p8A":
+        st, cut = two_radius_10_8()
+        return {"cutoffs": cut,
+                "energies": energies_fixture("C1728 10+8 A", st, cut, sample(st.n, 8, 16)),
+                "forces": forces_fixture("C1728 10+8 A", st, cut, sample(st.n, 1, 17))}
     raise KeyError(name)
 
 
 
 
 NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A", "C1728_pbc_two_radius", "HCNO50_pbc_5A",
-         "HCNO100_pbc_6A"]
+         "HCNO100_pbc_6A", "C1728_pbc_10p8A"]
 
 
 def main():
