@@ -998,12 +998,15 @@ __device__ __forceinline__ void solve_slot(const ScsArgs& a, int k, int w, int n
 // one row per thread in 512-thread workgroups this keeps three workgroups on a
 // compute unit instead of two (more independent block chains, more loads in
 // flight): 3.45 -> 3.19 ms for the FP64 lambda solve of 1,728 C atoms.
+// Systems of more than 2 x 256 rows (K1 above 170 sites, e.g. r_SCS = 8 A at carbon
+// density) take three rows per thread; the rows' sums are the same either way.
 constexpr int kSolveThreads = 256;
-static_assert(2 * kSolveThreads >= 3 * kMaxN1, "two rows per thread cover the largest system");
-template <typename R>
-__global__ void __launch_bounds__(kSolveThreads, 3) k_scs_solve(ScsArgs a, int n1max, int mode) {
+static_assert(3 * kSolveThreads >= 3 * kMaxN1, "three rows per thread cover the largest system");
+__host__ __device__ inline int solve_slots(int n1max) { return 3 * n1max <= 2 * kSolveThreads ? 2 : 3; }
+template <typename R, int NS>
+__global__ void __launch_bounds__(kSolveThreads, NS == 2 ? 3 : 2) k_scs_solve(ScsArgs a, int n1max, int mode) {
     extern __shared__ double lds[];
-    solve_slot<R, 2, 1>(a, a.order[blockIdx.x], blockIdx.y, n1max, mode, lds);
+    solve_slot<R, NS, 1>(a, a.order[blockIdx.x], blockIdx.y, n1max, mode, lds);
 }
 
 size_t scs_solve_lds_bytes(int n1max, bool mixed) {
@@ -1019,9 +1022,9 @@ size_t scs_solve_lds_bytes(int n1max, bool mixed) {
 // array so that the compiler sees it cannot alias the panel buffer (with one
 // carved buffer it spilled the diagonal step's registers).
 static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
-static_assert(2 * 256 >= 3 * kMaxN1, "two rows per thread of the factorisation kernel cover its first solve");
-template <typename R>
-__global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
+static_assert(3 * 256 >= 3 * kMaxN1, "three rows per thread of the factorisation kernel cover its first solve");
+template <typename R, int NS>
+__global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
     __shared__ R Zs[NB * kSlotLd];
     __shared__ int counter[2];
@@ -1042,7 +1045,7 @@ __global__ void __launch_bounds__(256, 3) k_scs_factor(ScsArgs a, int n1max) {
     }
     // the first solve (backward: the forward substitution was carried by the
     // factorisation) while the factor is still in the caches
-    solve_slot<R, 2, 1>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
+    solve_slot<R, NS, 1>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
 }
 
 // dynamic LDS of the factorisation (the panel buffer)
@@ -1728,8 +1731,14 @@ hipError_t launch_scs_rhs(hipStream_t st, const ScsArgs& a, int n1max, int n2max
 hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
     const dim3 grid(a.n, a.nw);
     const size_t lf = factor_dynamic_bytes(n1max, mixed);
-    if (mixed) hipLaunchKernelGGL(k_scs_factor<float>, grid, dim3(256), lf, st, a, n1max);
-    else hipLaunchKernelGGL(k_scs_factor<double>, grid, dim3(256), lf, st, a, n1max);
+    const bool three = solve_slots(n1max) == 3;
+    if (mixed) {
+        if (three) hipLaunchKernelGGL((k_scs_factor<float, 3>), grid, dim3(256), lf, st, a, n1max);
+        else hipLaunchKernelGGL((k_scs_factor<float, 2>), grid, dim3(256), lf, st, a, n1max);
+    } else {
+        if (three) hipLaunchKernelGGL((k_scs_factor<double, 3>), grid, dim3(256), lf, st, a, n1max);
+        else hipLaunchKernelGGL((k_scs_factor<double, 2>), grid, dim3(256), lf, st, a, n1max);
+    }
     return hipGetLastError();
 }
 
@@ -1740,7 +1749,10 @@ hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mi
     if (mixed) {
         for (int it = 0; it < a.n_refine; ++it) {
             hipLaunchKernelGGL(k_scs_residual, grid, dim3(256), scs_residual_lds_bytes(n1max), st, a, n1max);
-            hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveCorr);
+            if (solve_slots(n1max) == 3)
+                hipLaunchKernelGGL((k_scs_solve<float, 3>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveCorr);
+            else
+                hipLaunchKernelGGL((k_scs_solve<float, 2>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveCorr);
         }
     }
     return hipGetLastError();
@@ -1749,8 +1761,14 @@ hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mi
 hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
     const dim3 grid(a.n, a.nw);
     const size_t ls = scs_solve_lds_bytes(n1max, mixed);
-    if (mixed) hipLaunchKernelGGL(k_scs_solve<float>, grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
-    else hipLaunchKernelGGL(k_scs_solve<double>, grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
+    const bool three = solve_slots(n1max) == 3;
+    if (mixed) {
+        if (three) hipLaunchKernelGGL((k_scs_solve<float, 3>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
+        else hipLaunchKernelGGL((k_scs_solve<float, 2>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
+    } else {
+        if (three) hipLaunchKernelGGL((k_scs_solve<double, 3>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
+        else hipLaunchKernelGGL((k_scs_solve<double, 2>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveLambda);
+    }
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ constexpr double kSqrt2OverPi = 0.79788456080286535588;    // sqrt(2/pi)
 // Kernel size limits (checked on the host before any launch).
 constexpr int kMaxFreq = 33;       // omega = 0 plus up to 32 quadrature nodes
 constexpr int kMaxNmax = 12;       // highest body order
-constexpr int kMaxN1 = 160;        // atoms in K1 (r < r_scs), central atom included
+constexpr int kMaxN1 = 256;        // atoms in K1 (r < r_scs), central atom included
 constexpr double kSparseMbdRatio = 0.45;  // automatic sparse MBD products when r_mbd2 <= this * r_nbr
 constexpr int kMaxNK = 400;        // sites in K (r < r_nbr), central atom included; the MBD kernel's LDS,
                                    // 8 (3 nq + 15) bytes per site for nq >= 12 nodes, caps it lower for

@@ -158,6 +158,13 @@ def fixture(name):
         return {"cutoffs": cut,
                 "energies": energies_fixture("C1728 two-radius", st, cut, sample(st.n, 4, 13)),
                 "forces": forces_fixture("C1728 two-radius", st, cut, sample(st.n, 1, 14))}
+    if name == "HCNO512_pbc_8A":
+        # the paper's SCS cutoff (8 A) on a molecular-liquid-like box: K1 of about 180 sites
+        st = C.hcno_box(512, 8512)
+        cut = dict(r_scs=8.0, r_nbr=8.0, r_mbd1=8.0, r_mbd2=8.0)
+        return {"cutoffs": cut,
+                "energies": energies_fixture("HCNO512 8 A", st, cut, sample(st.n, 4, 18)),
+                "forces": forces_fixture("HCNO512 8 A", st, cut, sample(st.n, 1, 19))}
     if name == "C1728_pbc_10p8A":
         st, cut = two_radius_10_8()
         return {"cutoffs": cut,
@@ -169,7 +176,7 @@ def fixture(name):
 
 
 NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A", "C1728_pbc_two_radius", "HCNO50_pbc_5A",
-         "HCNO100_pbc_6A", "C1728_pbc_10p8A"]
+         "HCNO100_pbc_6A", "C1728_pbc_10p8A", "HCNO512_pbc_8A"]
 
 
 def main():
