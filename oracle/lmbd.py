@@ -19,7 +19,9 @@ design notes of the repository):
     blended alpha~_i of the frame.
   * one cutoff per role: K1 = B(r_scs), K2 = B(2 r_scs) \\ B(r_scs) for the SCS
     (Sec. III.B), K = B(r_nbr) for the energy, f_LR cut at r_mbd1 for pairs that
-    touch the central atom and r_mbd2 otherwise (Sec. III.A cutoff function).
+    touch the central atom and r_mbd2 otherwise (Sec. III.A cutoff function);
+    optionally separate radii r_2b1 / r_2b2 for the n = 2 term (Sec. III.A, the
+    two-body cutoffs): its T_LR is cut at r_2b1 / r_2b2 instead.
   * balls are open: r < r_c is inside.
   * S~ in T_LR uses the blended static polarisability alpha~_i(0) of the frame.
   * periodic images are explicit sites carrying their base atom's data.
@@ -63,6 +65,15 @@ class OracleParams:
     coef_fixed: Optional[dict] = None  # "fit" mode: {atom: (n_nodes, n_max + 1) array} used instead
                                        # of refitting (the coefficients held fixed)
     omega_ref: Optional[float] = None  # reference frequency of the two-point model, Ha
+    r_2b1: Optional[float] = None  # two-body radii (Sec. III.A): the n = 2 term's T_LR is cut at r_2b1
+    r_2b2: Optional[float] = None  #   (pairs touching k) and r_2b2 (others); None: the MBD radii
+
+    def two_body_radii(self):
+        return (self.r_mbd1 if self.r_2b1 is None else self.r_2b1,
+                self.r_mbd2 if self.r_2b2 is None else self.r_2b2)
+
+    def separate_two_body(self):
+        return self.two_body_radii() != (self.r_mbd1, self.r_mbd2)
 
     def scs_omegas(self):
         """Frequencies at which the local SCS systems are solved (omega = 0 first)."""
@@ -90,7 +101,8 @@ class OracleParams:
 def make_params(cutoffs: dict, omega, weight, **kw) -> OracleParams:
     return OracleParams(r_scs=cutoffs["r_scs"], r_nbr=cutoffs["r_nbr"], r_mbd1=cutoffs["r_mbd1"],
                         r_mbd2=cutoffs["r_mbd2"], omega=np.asarray(omega, dtype=np.float64),
-                        weight=np.asarray(weight, dtype=np.float64), **kw)
+                        weight=np.asarray(weight, dtype=np.float64), r_2b1=cutoffs.get("r_2b1"),
+                        r_2b2=cutoffs.get("r_2b2"), **kw)
 
 
 # ----------------------------------------------------------------------------
@@ -455,9 +467,10 @@ def lorentz_polarisabilities(a0, a_ref, omega, omega_ref):
     return a0[..., None] / (1.0 + (w / om_t[..., None]) ** 2)
 
 
-def _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm):
+def _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm, two_body=False):
     """Blended polarisabilities A (nK, 1 + n_nodes: omega = 0, then the nodes) and
-    T_LR (3 nK x 3 nK) of one frame.
+    T_LR (3 nK x 3 nK) of one frame; with two_body also the n = 2 term's T_LR, cut at
+    the two-body radii.
 
     alpha_loc: (nw, n1) local polarisabilities of the frame; alpha_cen_K: (nK, nw)
     central polarisabilities of the base atoms of the first nK sites.
@@ -494,22 +507,31 @@ def _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     r = torch.sqrt((rv * rv).sum(-1))
     St = prm.beta * (Rt[I] + Rt[J])
     central = (I == 0) | (J == 0)
-    rcut = torch.as_tensor(np.where(central, prm.r_mbd1, prm.r_mbd2) / BOHR, dtype=_DT)
-    x = (r - rcut + rb) / rb
-    flr = torch.where(r < rcut - rb, torch.ones_like(r),
-                      torch.where(r < rcut, 1.0 - 3.0 * x * x + 2.0 * x ** 3, torch.zeros_like(r)))
-    tlr = (flr * _fermi(r, St, prm.damp_d))[:, None, None] * _dipole_T(rv)
-    blocks = torch.zeros((nK, nK, 3, 3), dtype=_DT).index_put(
-        (torch.as_tensor(I), torch.as_tensor(J)), tlr)
-    T = blocks.permute(0, 2, 1, 3).reshape(3 * nK, 3 * nK)
-    return A, T
+    damped = _fermi(r, St, prm.damp_d)[:, None, None] * _dipole_T(rv)
+
+    def t_lr(r1, r2):   # f_LR with p = 1 at r1 for pairs touching k, p = 2 at r2 for the others
+        rcut = torch.as_tensor(np.where(central, r1, r2) / BOHR, dtype=_DT)
+        x = (r - rcut + rb) / rb
+        flr = torch.where(r < rcut - rb, torch.ones_like(r),
+                          torch.where(r < rcut, 1.0 - 3.0 * x * x + 2.0 * x ** 3, torch.zeros_like(r)))
+        blocks = torch.zeros((nK, nK, 3, 3), dtype=_DT).index_put(
+            (torch.as_tensor(I), torch.as_tensor(J)), flr[:, None, None] * damped)
+        return blocks.permute(0, 2, 1, 3).reshape(3 * nK, 3 * nK)
+
+    T = t_lr(prm.r_mbd1, prm.r_mbd2)
+    if not two_body:
+        return A, T
+    return A, T, (t_lr(*prm.two_body_radii()) if prm.separate_two_body() else T)
 
 
 def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     """Energy of one central atom in eV (Sec. III.A, the symmetrised local energy)."""
     nK = frame.nK
-    A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
+    A, T, T2 = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm, two_body=True)
+    sep = prm.separate_two_body()
     coef = prm.coefficients()
+    if sep and coef is None:
+        raise ValueError("separate two-body radii need a finite body order")
     cfit = None
     if prm.c_n_mode == "fit":
         # per node: c_n fitted over [lambda_min, lambda_max] of G~ (held fixed under
@@ -535,8 +557,11 @@ def _mbd_energy(frame, p, alpha_loc, alpha_cen_K, fa, prm):
             acc = torch.zeros((), dtype=_DT)
             for n in range(1, prm.n_max + 1):
                 u = G @ u
-                if coef[n] != 0.0:
+                if coef[n] != 0.0 and not (sep and n == 2):
                     acc = acc + coef[n] * torch.trace(u[:3, :])
+            if sep:   # the n = 2 term with the two-body T_LR: Tr[G2 G2]_kk over the central block row
+                g2 = s[:3, None] * T2[:3, :] * s[None, :]
+                acc = acc + coef[2] * (g2 * g2).sum()
             e_freq.append(acc)
     wq = torch.as_tensor(prm.weight, dtype=_DT)
     return (wq * torch.stack(e_freq)).sum() / (2.0 * math.pi) * HARTREE
@@ -557,10 +582,11 @@ def _paper_force_functional(frame, p, alpha_loc, alpha_cen_K, fa, prm):
     B_n = G~^(n-2) held fixed, g~_k the block row of k.  Its value is not an
     energy; only its gradient with respect to r_k is used.  With the fitted
     coefficients (prm.c_n_mode == "fit") each node takes the frame's own c_n,
-    held fixed.
+    held fixed.  With separate two-body radii the n = 2 trace uses their T_LR
+    (r_2b1 on the pairs touching k, r_2b2 on the others).
     """
     nK = frame.nK
-    A, T = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm)
+    A, T, T2 = _mbd_operators(frame, p, alpha_loc, alpha_cen_K, fa, prm, two_body=True)
     coef = prm.coefficients()
     assert coef is not None, "the approximate forces need a finite n_max"
     cfit = fitted_coefficients(frame, p, alpha_loc, alpha_cen_K, fa, prm) if prm.c_n_mode == "fit" else None
@@ -570,7 +596,8 @@ def _paper_force_functional(frame, p, alpha_loc, alpha_cen_K, fa, prm):
         G = s[:, None] * T * s[None, :]
         if cfit is not None:
             coef = cfit[q]
-        acc = coef[2] * (G * G).sum()                     # Tr(G^2) of the symmetric G
+        G2 = s[:, None] * T2 * s[None, :]                 # the n = 2 term's G (two-body radii)
+        acc = coef[2] * (G2 * G2).sum()                   # Tr(G^2) of the symmetric G
         g = G[:3, :]                                      # block row of the central atom
         Gf = G.detach()
         for n in range(3, prm.n_max + 1):

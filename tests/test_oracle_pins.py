@@ -894,3 +894,85 @@ def test_polarisation_catastrophe_is_detected():
     with pytest.raises(oracle.PolarisationCatastrophe):
         oracle.lmbd_energies(st, prm, tab)
     assert np.all(np.isfinite(oracle.lmbd_energies(st, _params(NO_SCS, 10.0, n_max=6), tab)))
+
+
+# ------------------------------------------------------------- separate two-body radii
+
+def test_two_body_radii_dimer():
+    """SCS off, a dimer beyond r_MBD,1 but inside the f_LR buffer of the two-body radius
+    r_2b,1 (Sec. III.A): the MBD T_LR has no coupling, so every term n >= 3 is zero,
+    while the n = 2 term is the pairwise -C6 f^2 f_LR(r; r_2b,1)^2 / (2 r^6) for any
+    n_max; with r_2b,1 = r_MBD,1 the dimer has no energy at all."""
+    rb = 0.5
+    for r_A in (4.62, 4.8):
+        st = _open([[0, 0, 0], _at_distance(r_A)], species=[C_IDX, SPECIES_INDEX["N"]], nu=[0.8, 0.95])
+        cut = dict(r_scs=NO_SCS, r_nbr=5.5, r_mbd1=3.0, r_mbd2=3.0, r_2b1=5.0, r_2b2=2.0)
+        a, w, R = _free(st)
+        r = r_A / cf.BOHR
+        f = cf.fermi(r, 0.83 * (R[0] + R[1]))
+        flr = cf.smooth_cutoff(r_A, 5.0, rb)
+        assert 0.0 < flr < 1.0
+        ref = -0.5 * cf.c6_casimir_polder(a[0], w[0], a[1], w[1]) * (f * flr) ** 2 / r ** 6 * cf.HARTREE
+        for n_max in (2, 6):
+            e = oracle.lmbd_energies(st, oracle.make_params(cut, GRID200[0], GRID200[1], n_max=n_max),
+                                     SPECIES_TABLE)
+            assert np.allclose(e, [ref, ref], rtol=1e-11, atol=0), (r_A, n_max)
+        same = dict(cut, r_2b1=3.0, r_2b2=3.0)
+        e0 = oracle.lmbd_energies(st, oracle.make_params(same, GRID200[0], GRID200[1], n_max=6), SPECIES_TABLE)
+        assert np.all(e0 == 0.0)
+
+
+def test_two_body_radii_trimer_splits_the_orders():
+    """SCS off, a triangle: with separate two-body radii the second-order energy is the
+    pairwise sum with f_LR at r_2b,1 on the pairs touching each central atom, and the
+    third-order share is still one third of the ATM energy with the MBD radii's
+    factors (edge a-b in the buffer of r_MBD,2, so c's share carries it)."""
+    pos = np.array([[0.0, 0.0, 0.0], [3.62, 0.0, 0.0], [1.6, 2.4, 0.5]])
+    r1, r2, rb = 5.0, 4.0, 0.5
+    st = _open(pos, species=[C_IDX, SPECIES_INDEX["O"], SPECIES_INDEX["H"]], nu=[0.85, 0.7, 0.9])
+    # r_2b,1 = 4 A: the a-b edge (3.62 A) inside its buffer, the other edges below it
+    cut = dict(r_scs=NO_SCS, r_nbr=5.0, r_mbd1=r1, r_mbd2=r2, r_2b1=4.0, r_2b2=1.0)
+    p2 = oracle.make_params(cut, GRID200[0], GRID200[1], n_max=2)
+    p3 = oracle.make_params(cut, GRID200[0], GRID200[1], n_max=3)
+    e2 = oracle.lmbd_energies(st, p2, SPECIES_TABLE)
+    e3 = oracle.lmbd_energies(st, p3, SPECIES_TABLE)
+    a, w, R = _free(st)
+    x = pos / cf.BOHR
+    pair = {}
+    for i, j in ((0, 1), (1, 2), (2, 0)):
+        r = np.linalg.norm(x[i] - x[j])
+        c6 = cf.c6_casimir_polder(a[i], w[i], a[j], w[j])
+        fl = cf.smooth_cutoff(np.linalg.norm(pos[i] - pos[j]), 4.0, rb)
+        pair[(i, j)] = pair[(j, i)] = -0.5 * c6 * (cf.fermi(r, 0.83 * (R[i] + R[j])) * fl) ** 2 / r ** 6 * cf.HARTREE
+    assert 0.05 < cf.smooth_cutoff(np.linalg.norm(pos[1] - pos[0]), 4.0, rb) < 0.95
+    ref2 = [pair[(0, 1)] + pair[(0, 2)], pair[(1, 0)] + pair[(1, 2)], pair[(2, 0)] + pair[(2, 1)]]
+    assert np.allclose(e2, ref2, rtol=1e-11, atol=0)
+    f = 1.0
+    for i, j in ((0, 1), (1, 2), (2, 0)):
+        f *= cf.fermi(np.linalg.norm(x[i] - x[j]), 0.83 * (R[i] + R[j]))
+    atm = cf.c9_atm(a[0], w[0], a[1], w[1], a[2], w[2]) * f * cf.atm_geometry_factor(*x) * cf.HARTREE
+    phi = cf.smooth_cutoff(np.linalg.norm(pos[1] - pos[0]), r2, rb)
+    assert np.allclose(e3 - e2, np.array([1.0, 1.0, phi]) * atm / 3.0, rtol=1e-10, atol=0)
+
+
+def test_two_body_radii_forces_finite_difference():
+    """Exact forces with separate two-body radii (a larger r_2b,1 than r_MBD,1) against
+    central differences of the energy."""
+    st = _rand_cluster(10, 71, box=5.5, dmin=1.4)
+    cut = dict(r_scs=3.0, r_nbr=5.0, r_mbd1=3.5, r_mbd2=3.0, r_2b1=5.0, r_2b2=4.0)
+    prm = oracle.make_params(cut, GRID12[0], GRID12[1], n_max=5)
+    _fd_check(st, prm, [(0, 0), (4, 1), (9, 2)])
+
+
+def test_two_body_radii_paper_forces_exact_limit():
+    """The approximate forces with separate two-body radii: without screening and with
+    every frame holding the whole structure they are the exact forces (the n = 2 term
+    of the frame's total trace moves with r_k only through its central pairs, whatever
+    r_2b,2 is)."""
+    st = _rand_cluster(8, 19, box=4.5, dmin=1.3)
+    cut = dict(r_scs=NO_SCS, r_nbr=12.0, r_mbd1=9.0, r_mbd2=8.5, r_2b1=12.0, r_2b2=2.5)
+    prm = oracle.make_params(cut, GRID12[0], GRID12[1], n_max=5)
+    e, f = oracle.lmbd_energy_forces(st, prm, SPECIES_TABLE)
+    ep, fp = oracle.lmbd_paper_forces(st, prm, SPECIES_TABLE)
+    assert np.allclose(ep, e, rtol=0, atol=1e-14)
+    assert np.allclose(fp, f, rtol=0, atol=1e-12 * max(1.0, np.abs(f).max()))
