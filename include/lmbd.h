@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define LMBD_ABI_VERSION 6
+#define LMBD_ABI_VERSION 7
 
 typedef enum lmbd_status {
     LMBD_OK = 0,
@@ -159,6 +159,13 @@ typedef struct lmbd_params {
  *                the call fails with LMBD_E_INVALID_ARG unless
  *                r_nbr >= r_mbd1 >= r_mbd2 (Sec. III.A: the central atom has the
  *                larger radius, and K must hold every pair that f_LR couples)
+ *  r_2b1/2     : the two-body radii of Sec. III.A: the n = 2 term of the energy uses a
+ *                T_LR with f_LR cut at r_2b1 for pairs touching the central atom and at
+ *                r_2b2 for the others (the terms n >= 3 keep r_mbd1/2).  The energy and
+ *                the exact forces depend on r_2b1 only; r_2b2 enters the approximate
+ *                forces (LMBD_FORCES_PAPER, whose n = 2 term is the frame's whole trace).
+ *                0 = the MBD radius; required r_nbr >= r_2b1 >= r_2b2 > r_buf.  With
+ *                radii that differ from the MBD ones n_max must be finite (always so here)
  *  e_weight    : [n_atoms] adjoint seeds w_k of the forces, or NULL for w_k = 1
  *  e_atom      : [n_atoms] output per-atom energies E_k (eV), or NULL
  *  forces      : [n_atoms][3] output forces (eV/A), or NULL for energies only
@@ -184,6 +191,8 @@ typedef struct lmbd_structure {
     double r_nbr;
     double r_mbd1;
     double r_mbd2;
+    double r_2b1;
+    double r_2b2;
     const double* e_weight;
     double* e_atom;
     double* forces;

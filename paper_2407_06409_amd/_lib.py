@@ -5,7 +5,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblmbd.so")
 
-ABI_VERSION = 6   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
+ABI_VERSION = 7   # LMBD_ABI_VERSION of include/lmbd.h that these structures mirror
 LMBD_FP64, LMBD_MIXED = 0, 1
 LMBD_SCS_EXACT, LMBD_SCS_LORENTZ = 0, 1
 LMBD_MBD_AUTO, LMBD_MBD_DENSE, LMBD_MBD_SPARSE = 0, 1, 2
@@ -42,7 +42,8 @@ class StructureDesc(ctypes.Structure):
         ("n_atoms", ctypes.c_int64), ("pos", ctypes.c_void_p), ("species", ctypes.c_void_p),
         ("v_ratio", ctypes.c_void_p), ("cell", _dp), ("pbc", ctypes.c_int32 * 3),
         ("r_scs", ctypes.c_double), ("r_nbr", ctypes.c_double), ("r_mbd1", ctypes.c_double),
-        ("r_mbd2", ctypes.c_double), ("e_weight", ctypes.c_void_p), ("e_atom", ctypes.c_void_p),
+        ("r_mbd2", ctypes.c_double), ("r_2b1", ctypes.c_double), ("r_2b2", ctypes.c_double),
+        ("e_weight", ctypes.c_void_p), ("e_atom", ctypes.c_void_p),
         ("forces", ctypes.c_void_p), ("alpha_scs0", ctypes.c_void_p), ("dE_dv", ctypes.c_void_p),
         ("spectrum", ctypes.c_void_p),
     ]

@@ -134,7 +134,7 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
     """Energies and forces of several structures in one set of launches.
 
     ``structures``: list of dicts with keys pos (N,3), species (N,), v_ratio (N,),
-    cell (3,3) or None, pbc (3,), cutoffs {r_scs, r_nbr, r_mbd1, r_mbd2} and
+    cell (3,3) or None, pbc (3,), cutoffs {r_scs, r_nbr, r_mbd1, r_mbd2[, r_2b1, r_2b2]} and
     optionally e_weight (N,).  Arrays are either all CUDA tensors (float64/int32,
     results are CUDA tensors, work on the current or given stream) or all host
     numpy arrays (results are numpy arrays).
@@ -187,7 +187,8 @@ def compute_batch(structures, params: MethodParams, species_table, *, forces=Tru
             int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
             cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
             (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
-            float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a), _ptr(dv),
+            float(cut["r_mbd1"]), float(cut["r_mbd2"]), float(cut.get("r_2b1") or 0.0),
+            float(cut.get("r_2b2") or 0.0), _ptr(w), _ptr(e), _ptr(f), _ptr(a), _ptr(dv),
             _ptr(spec))
         outs.append({"energies": e, "forces": f, "alpha_scs0": a, "dE_dv": dv, "spectrum": spec})
     if device_mode:
@@ -239,7 +240,8 @@ def _host_desc(s, forces, keep):
         int(pos.shape[0]), _ptr(pos), _ptr(spc), _ptr(nu),
         cell_np.ctypes.data_as(C._dp) if cell_np is not None else None,
         (ctypes.c_int32 * 3)(*pbc), float(cut["r_scs"]), float(cut["r_nbr"]),
-        float(cut["r_mbd1"]), float(cut["r_mbd2"]), _ptr(w), _ptr(e), _ptr(f), _ptr(a), None)
+        float(cut["r_mbd1"]), float(cut["r_mbd2"]), float(cut.get("r_2b1") or 0.0),
+            float(cut.get("r_2b2") or 0.0), _ptr(w), _ptr(e), _ptr(f), _ptr(a), None)
     return d, {"energies": e, "forces": f, "alpha_scs0": a}
 
 

@@ -30,6 +30,16 @@
 // the central polarisabilities are held fixed (nothing is scattered to the
 // neighbours), and the host keeps only the gradient of the frame's own atom.
 //
+// Two-body radii (Sec. III.A; SI.two_body): the n = 2 term takes a T_LR of its own, cut
+// at r_2b1 on the pairs touching k and r_2b2 on the others.  Its moment is formed
+// directly, mu_2 = sum_j alpha~_k alpha~_j |T2_kj|^2 (the central block row), its
+// polarisability adjoint likewise, it leaves the Krylov coefficients of Tbar, and its
+// pair derivative C2_kj = 2 w_k sum_q W_q c_2 alpha~_k alpha~_j T2_kj is contracted with
+// dT2/dr where the pair visits of the contraction meet it (the sparse lists hold the
+// central pairs out to max(r_mbd1, r_2b1)).  The approximate forces take the n = 2
+// trace of the whole frame with T2: |T2_ij|^2 in the polarisability adjoint and
+// C2_ij = 4 w_k sum_q W_q c_2 alpha~_i alpha~_j T2_ij on every pair within the two-body radii.
+//
 // Eigenvalue-bounded coefficients (Sec. III.A, Eqs. diagonal_appr, eigendecomp and
 // polynomial-fit; a.fit): per atom and node, a.lz_steps Lanczos steps on G~ (all nodes
 // side by side as columns: each step one (3n x 3n) x (3n x nq) product) give the
@@ -359,7 +369,9 @@ __device__ inline void wave_sum9(const double (&v)[9], double (&out)[9]) {
 // The sparse form is bound by the latency of its gathers rather than by arithmetic:
 // it runs 1,024 threads (four wavefronts per SIMD at its register count) to hide it.
 constexpr int kMbdThreadsSparse = 1024;
-template <typename W, int FORM>
+// TB: the atoms' structures have two-body radii of their own (a separate instantiation,
+// so that the other kernels carry none of its registers)
+template <typename W, int FORM, bool TB>
 __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdThreads, 1) k_mbd(MbdArgs a, int nkmax) {
     constexpr bool SP = FORM != kMbdDense, GS = FORM == kMbdSparseGlobal;
     extern __shared__ double lds[];
@@ -373,6 +385,7 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
     const StructInfo& SI = a.sinfo[a.atom_struct[k]];
     const double rs = SI.r_scs;
     const bool fit = a.fit != 0;
+    constexpr bool has2b = TB;
     W* const wbase = static_cast<W*>(a.work) + a.work_off[k];
     const int64_t lcap = GS ? mbd_list_cap(nK, SI.m2max) : (int64_t)nK * nK;   // list entries
     const MbdGlobalLayout G = mbd_global_layout(nK, nq, n_max, a.mmax, lcap, (int64_t)sizeof(W), a.forces != 0);
@@ -487,7 +500,8 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
         v[1] = L.py[i] - L.py[j];
         v[2] = L.pz[i] - L.pz[j];
         r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        return r < ((i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2);
+        // (central pairs out to the two-body radius too: their MBD coefficients are 0 there)
+        return r < ((i == 0 || j == 0) ? (has2b ? fmax(SI.r_mbd1, SI.r_2b1) : SI.r_mbd1) : SI.r_mbd2);
     };
     auto couple = [&](int i, int j, W& A, W& B, double rh[3]) -> bool {
         double v[3], r;
@@ -866,6 +880,36 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
         if (t < nmom && part == 0) L.mu[(2 + t / nq) * nq + t % nq] = s;
     }
     __syncthreads();
+    // two-body radii: t2_j = |T2_kj|^2 (into the space of the blend gradients, unused until
+    // the force stage), then mu_2 = alpha~_k sum_j alpha~_j t2_j per node, in site order
+    // over the lanes of one wavefront per node
+    auto t2pair = [&](int i, int j, double& r, double rh[3], LrPair<double>& t) -> bool {
+        const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+        r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const double rc = (i == 0 || j == 0) ? SI.r_2b1 : SI.r_2b2;
+        if (i == j || !(r < rc)) return false;
+        t = lr_pair<double>(r, a.beta * (L.Rt[i] + L.Rt[j]), a.damp_d, rc, a.r_buf);
+        rh[0] = v[0] / r;
+        rh[1] = v[1] / r;
+        rh[2] = v[2] / r;
+        return true;
+    };
+    if (has2b) {
+        for (int j = tid; j < nK; j += blockDim.x) {
+            double r, rh[3];
+            LrPair<double> t;
+            L.fg[j] = t2pair(0, j, r, rh, t) ? (t.A + t.B) * (t.A + t.B) + 2.0 * t.B * t.B : 0.0;
+        }
+        __syncthreads();
+        for (int q = wave; q < nq; q += nwave) {
+            double x = 0.0;
+            for (int j = lane; j < nK; j += 64) x += L.sa[(size_t)j * nwe + 1 + q] * L.fg[j];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) L.mu[2 * nq + q] = L.sa[1 + q] * x;
+        }
+        __syncthreads();
+    }
     const double wk = a.e_weight ? a.e_weight[k] : 1.0;
     if (tid == 0) {
         double e = 0.0;
@@ -890,11 +934,17 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
                 for (int j = 0; j < nK; ++j) {
                     if (j == i) continue;
                     double nrm = 0.0;
-                    for (int r = 0; r < 3; ++r)
-                        for (int c = 0; c < 3; ++c) {
-                            const double x = double(T[(size_t)(3 * i + r) * N3p + 3 * j + c]);
-                            nrm += x * x;
-                        }
+                    if (has2b) {   // |T2_ij|^2 = (A + B)^2 + 2 B^2 of the two-body tensor
+                        double r, rh[3];
+                        LrPair<double> t;
+                        if (t2pair(i, j, r, rh, t)) nrm = (t.A + t.B) * (t.A + t.B) + 2.0 * t.B * t.B;
+                    } else {
+                        for (int r = 0; r < 3; ++r)
+                            for (int c = 0; c < 3; ++c) {
+                                const double x = double(T[(size_t)(3 * i + r) * N3p + 3 * j + c]);
+                                nrm += x * x;
+                            }
+                    }
 #pragma unroll
                     for (int x = 0; x < 4; ++x)
                         if (q0 + x < nq) acc2[x] += L.sa[(size_t)j * nwe + 1 + q0 + x] * nrm;
@@ -928,6 +978,11 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
             double s = 0.0;
             for (int n = 2; n <= n_max; ++n) {
                 double sn = (i == 0) ? L.mu[n * nq + q] : 0.0;
+                if (n == 2 && has2b) {   // alpha~_k alpha~_i t2_i (the central term is mu_2 itself)
+                    if (i > 0) sn = L.sa[1 + q] * L.sa[(size_t)i * nwe + 1 + q] * L.fg[i];
+                    s += cfq(n, q) * sn;
+                    continue;
+                }
                 for (int aa = 1; aa < n; ++aa) {
                     const W* ua = Uat(aa);
                     const W* ub = Uat(n - aa);
@@ -979,9 +1034,9 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
         }
     };
     if (fit)
-        build_pq([&](int n, int q) { return L.cf[q * (kMaxNmax + 1) + n]; });
+        build_pq([&](int n, int q) { return (has2b && n == 2) ? 0.0 : L.cf[q * (kMaxNmax + 1) + n]; });
     else
-        build_pq([&](int n, int) { return a.coef[n]; });
+        build_pq([&](int n, int) { return (has2b && n == 2) ? 0.0 : a.coef[n]; });
     for (int e = tid; e < N3 * (KKp - KK); e += blockDim.x) {   // padding columns
         const int r = e / (KKp - KK), kk = KK + e % (KKp - KK);
         Pm[(size_t)r * KKp + kk] = W(0);
@@ -992,7 +1047,7 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
     // Gbar are transposes of each other), so only blocks on or below the
     // diagonal are formed and read.
     if constexpr (!SP) {
-        if (a.paper) {   // Tbar += 2 w_k sum_q c_2(q) W_q D_q^2 T D_q^2, read from T before it is overwritten
+        if (a.paper && !has2b) {   // Tbar += 2 w_k sum_q c_2(q) W_q D_q^2 T D_q^2, read from T before it is overwritten
             const double c2 = 2.0 * wk;
             mfma_gemm_nt<3, 3, W>(N3, N3, KKp, Pm, KKp, Qm, KKp, true, [&](int r, int s, W v) {
                 const size_t e = (size_t)r * N3p + s;
@@ -1011,6 +1066,28 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
 
     // --- pair contraction: dE/dp_i and dE/dR~_i (each unordered pair from both ends)
     const int parts = SP ? 1 : max(1, min(4, (int)blockDim.x / max(nK, 1)));
+    // the two-body term's pair derivative C2 = kappa T2_ij, kappa = 2 w_k sum_q W_q c_2
+    // alpha~_i alpha~_j (central pairs; 4 and every pair for the approximate forces),
+    // contracted with dT2/dp_i and, through S~, with dT2/dR~
+    auto add2b = [&](int i, int j, double g[3], double& Rb) {
+        if (!has2b || (!a.paper && i != 0 && j != 0)) return;
+        double r, rh[3];
+        LrPair<double> t;
+        if (!t2pair(i, j, r, rh, t)) return;
+        double kap = 0.0;
+        for (int q = 0; q < nq; ++q)
+            kap += a.wq[q] * cfq(2, q) * L.sa[(size_t)i * nwe + 1 + q] * L.sa[(size_t)j * nwe + 1 + q];
+        kap *= (a.paper ? 4.0 : 2.0) * wk;
+        double C[9];
+        for (int x = 0; x < 3; ++x)
+            for (int c = 0; c < 3; ++c) C[3 * x + c] = kap * (t.A * rh[x] * rh[c] + (x == c ? t.B : 0.0));
+        double gp[3];
+        radial_tensor_grad(rh, r, t.A, t.dA, t.dB, C, gp);
+        g[0] += gp[0];
+        g[1] += gp[1];
+        g[2] += gp[2];
+        Rb += a.beta * t.fLR * t.dfS * 2.0 * kap * t.A / (r * r * r);   // <C2, T_dip> = 2 kappa A / r^3
+    };
     if constexpr (SP) {
         // one block row per wavefront; Tbar_IJ (I > J) of a coupled pair from P and Q
         for (int i = wave; i < nK; i += nwave) {
@@ -1134,6 +1211,20 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
         L.rb[(size_t)part * nK + i] = Rb;
     }
     __syncthreads();
+    if (has2b) {   // the two-body term's pairs, each from both ends, one site per thread
+        for (int i = tid; i < nK; i += blockDim.x) {
+            double g[3] = {0.0, 0.0, 0.0}, Rb = 0.0;
+            if (a.paper || i == 0)
+                for (int j = 0; j < nK; ++j) add2b(i, j, g, Rb);
+            else
+                add2b(i, 0, g, Rb);
+            L.g[(size_t)i * 3 + 0] += g[0];
+            L.g[(size_t)i * 3 + 1] += g[1];
+            L.g[(size_t)i * 3 + 2] += g[2];
+            L.rb[i] += Rb;
+        }
+        __syncthreads();
+    }
     // reduce the parts in a fixed order; R~ adjoint into alpha~(0); blend adjoint
     double* abl = a.abar_loc + a.aloc_off[k];
     double* cap = a.ca + a.site_off[k] * nw;
@@ -1220,25 +1311,26 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
     for (int e = tid; e < (nall - nK) * nw; e += blockDim.x) cap[(size_t)nK * nw + e] = 0.0;
 }
 
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, int form) {
+template <typename W, bool TB>
+static void launch_mbd_t(hipStream_t st, const MbdArgs& a, int nk_lds, size_t lds, int form) {
+    const dim3 grid(a.n), blk(form == kMbdDense ? kMbdThreads : kMbdThreadsSparse);
+    if (form == kMbdDense)
+        hipLaunchKernelGGL((k_mbd<W, kMbdDense, TB>), grid, blk, lds, st, a, nk_lds);
+    else if (form == kMbdSparse)
+        hipLaunchKernelGGL((k_mbd<W, kMbdSparse, TB>), grid, blk, lds, st, a, nk_lds);
+    else
+        hipLaunchKernelGGL((k_mbd<W, kMbdSparseGlobal, TB>), grid, blk, lds, st, a, nk_lds);
+}
+
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, int form, bool two_body) {
     const int nk_lds = form == kMbdSparseGlobal ? 0 : nkmax;   // per-site arrays in LDS or not
     const size_t lds = mbd_lds_bytes(nk_lds, a.nq, a.n_max, a.lz_steps, a.fit != 0);
-    const dim3 grid(a.n), blk(form == kMbdDense ? kMbdThreads : kMbdThreadsSparse);
-    if (form == kMbdDense) {
-        if (mixed)
-            hipLaunchKernelGGL((k_mbd<float, kMbdDense>), grid, blk, lds, st, a, nk_lds);
-        else
-            hipLaunchKernelGGL((k_mbd<double, kMbdDense>), grid, blk, lds, st, a, nk_lds);
-    } else if (form == kMbdSparse) {
-        if (mixed)
-            hipLaunchKernelGGL((k_mbd<float, kMbdSparse>), grid, blk, lds, st, a, nk_lds);
-        else
-            hipLaunchKernelGGL((k_mbd<double, kMbdSparse>), grid, blk, lds, st, a, nk_lds);
+    if (mixed) {
+        if (two_body) launch_mbd_t<float, true>(st, a, nk_lds, lds, form);
+        else launch_mbd_t<float, false>(st, a, nk_lds, lds, form);
     } else {
-        if (mixed)
-            hipLaunchKernelGGL((k_mbd<float, kMbdSparseGlobal>), grid, blk, lds, st, a, nk_lds);
-        else
-            hipLaunchKernelGGL((k_mbd<double, kMbdSparseGlobal>), grid, blk, lds, st, a, nk_lds);
+        if (two_body) launch_mbd_t<double, true>(st, a, nk_lds, lds, form);
+        else launch_mbd_t<double, false>(st, a, nk_lds, lds, form);
     }
     return hipGetLastError();
 }

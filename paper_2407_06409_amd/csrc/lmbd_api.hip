@@ -213,6 +213,11 @@ lmbd_status check_struct(lmbd_context* ctx, const lmbd_params* p, const lmbd_str
     // every pair that f_LR couples (else a site leaving K would cut a coupled pair)
     if (s.r_mbd1 < s.r_mbd2) return fail(ctx, LMBD_E_INVALID_ARG, "r_mbd1 must not be smaller than r_mbd2");
     if (s.r_nbr < s.r_mbd1) return fail(ctx, LMBD_E_INVALID_ARG, "r_nbr must not be smaller than r_mbd1");
+    {
+        const double b1 = s.r_2b1 != 0.0 ? s.r_2b1 : s.r_mbd1, b2 = s.r_2b2 != 0.0 ? s.r_2b2 : s.r_mbd2;
+        if (!finite_pos(b1) || !finite_pos(b2) || !(p->r_buf < b2) || b1 < b2 || s.r_nbr < b1)
+            return fail(ctx, LMBD_E_INVALID_ARG, "two-body radii need r_nbr >= r_2b1 >= r_2b2 > r_buf");
+    }
     const int npbc = (s.pbc[0] != 0) + (s.pbc[1] != 0) + (s.pbc[2] != 0);
     if (npbc > 0) {
         if (!s.cell) return fail(ctx, LMBD_E_INVALID_ARG, "periodic structure without a cell");
@@ -245,6 +250,9 @@ lmbd_status make_struct_info(lmbd_context* ctx, const lmbd_structure& s, const d
     si.r_nbr = s.r_nbr / kBohr;
     si.r_mbd1 = s.r_mbd1 / kBohr;
     si.r_mbd2 = s.r_mbd2 / kBohr;
+    si.r_2b1 = (s.r_2b1 != 0.0 ? s.r_2b1 : s.r_mbd1) / kBohr;
+    si.r_2b2 = (s.r_2b2 != 0.0 ? s.r_2b2 : s.r_mbd2) / kBohr;
+    si.two_body = (si.r_2b1 != si.r_mbd1 || si.r_2b2 != si.r_mbd2) ? 1 : 0;
     si.r_big = std::max(2.0 * si.r_scs, si.r_nbr);
     si.atom_offset = atom_offset;
     si.cell_offset = cell_offset;
@@ -1094,10 +1102,11 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
             return fail(ctx, LMBD_E_UNSUPPORTED, "neighbourhood too large for the dense MBD products (nK up to " +
                                                      std::to_string(kMaxNK) + "; larger ones need the sparse form)");
     }
-    std::stable_sort(P.order.begin(), P.order.end(),
-                     [&](int32_t x, int32_t y) { return form[atom_struct[x]] < form[atom_struct[y]]; });
-    int n_form[3] = {0, 0, 0};
-    for (int k = 0; k < N; ++k) n_form[form[atom_struct[k]]]++;
+    // launch groups: MBD form, then whether the structure has two-body radii of its own
+    auto group = [&](int32_t k) { return 2 * form[atom_struct[k]] + sinfo[atom_struct[k]].two_body; };
+    std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t x, int32_t y) { return group(x) < group(y); });
+    int n_group[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < N; ++k) n_group[group(k)]++;
     if (P.n1max > kMaxN1 || P.nkmax_lds > kMaxNK || P.nallmax > kMaxSites)
         return fail(ctx, LMBD_E_UNSUPPORTED,
                     "neighbourhood too large (n1 " + std::to_string(P.n1max) + ", nK " + std::to_string(P.nkmax) +
@@ -1242,12 +1251,12 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     ma.ca = forces ? as<double>(ctx->ca) : nullptr;
     ma.cf0 = forces ? as<double>(ctx->cf) : nullptr;
     HIP_TRY(mark(5, 0));
-    for (int f = 0, first = 0; f < 3; first += n_form[f], ++f) {   // the sparse forms pay once block rows
-        if (n_form[f] == 0) continue;                                   // couple to a small part of K
+    for (int gi = 0, first = 0; gi < 6; first += n_group[gi], ++gi) {   // the sparse forms pay once block
+        if (n_group[gi] == 0) continue;                                      // rows couple to a small part of K
         MbdArgs mf = ma;
-        mf.n = n_form[f];
+        mf.n = n_group[gi];
         mf.order = ma.order + first;
-        HIP_TRY(launch_mbd(stream, mf, P.nkmax_lds, mixed, f));
+        HIP_TRY(launch_mbd(stream, mf, P.nkmax_lds, mixed, gi / 2, (gi & 1) != 0));
     }
     HIP_TRY(mark(5, 1));
 

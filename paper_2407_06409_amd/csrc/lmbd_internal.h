@@ -59,7 +59,9 @@ struct StructInfo {
     int atom_offset;     // first batch-global atom index
     int n_atoms;
     int m2max;           // largest Counts::n_m2 of the structure's atoms (bounds the sparse rows)
+    int two_body;        // the n = 2 term has radii of its own (r_2b1, r_2b2 differ from r_mbd1, r_mbd2)
     double r_scs, r_nbr, r_mbd1, r_mbd2, r_big;  // bohr
+    double r_2b1, r_2b2;                          // bohr (equal to r_mbd1, r_mbd2 unless set)
 };
 
 // Per-atom neighbourhood counts (central atom included in every count).
@@ -337,7 +339,8 @@ __host__ __device__ inline MbdGlobalLayout mbd_global_layout(int nK, int nq, int
 enum { kMbdDense = 0, kMbdSparse = 1, kMbdSparseGlobal = 2 };
 constexpr size_t kLdsBytes = 160 * 1024;   // LDS of a gfx950 workgroup
 size_t mbd_lds_bytes(int nkmax, int nq, int n_max, int lz_steps, bool fit);
-hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, int form);
+// two_body: every atom of the launch belongs to a structure with two-body radii of its own
+hipError_t launch_mbd(hipStream_t st, const MbdArgs& a, int nkmax, bool mixed, int form, bool two_body);
 hipError_t launch_gather_central(hipStream_t st, int n, int nw, const Counts* counts,
                                  const int64_t* site_off, const Site* sites, const int32_t* rev,
                                  const double* ca, double* abar_cen);
