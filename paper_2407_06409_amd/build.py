@@ -32,5 +32,24 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """A copy of the library whose host code carries AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code as in the release build), for checking
+    the host side of the C ABI without a GPU.  Returns the path of the library."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liblmbd_hostsan.so")
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"]
+    for opt in ("-fsanitize=address", "-fsanitize=undefined", "-fno-omit-frame-pointer",
+                "-fno-sanitize-recover=undefined"):
+        flags += ["-Xarch_host", opt]
+    cmd = [hipcc, *flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose="-q" not in sys.argv)
