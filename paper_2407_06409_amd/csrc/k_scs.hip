@@ -94,29 +94,29 @@ __device__ inline void inner_buffer(double r, double rin, double& fin, double& d
 // Z = L_bb^{-1}, transposed (Z[r][q], r > q, at (q, r)); the diagonal of Z is
 // 1 / L[r][r].
 //
-// Left-looking blocked Cholesky by one workgroup, 16-column panels p:
-//  (1) update  A[c0:N, c0:c0+16] -= L[c0:N, 0:c0] L[c0:c0+16, 0:c0]^T  on MFMA
-//      16x16x4, one (row tile, k-split) unit per wavefront, 16 k at a time
-//      from two aligned 4-vector loads per lane.  The updated tiles go to a
-//      panel buffer in LDS (never back to the matrix); when the panel has
-//      fewer row tiles than there are wavefronts the k range is split and the
-//      partial tiles sit side by side in that buffer.  An even panel whose
-//      update is not split also applies the same loaded chunks to the next
-//      panel's columns (in place in the matrix), so the odd panel after it
-//      only needs the one chunk just finished;
-//  (2) diagonal block: one wavefront factorises it from the panel buffer
-//      (lane l holds row l, values of other rows are broadcast with lane
-//      reads) and inverts it, Z = L_pp^{-1}, into the block's strict upper
-//      part and into LDS.  When the update is not split, this wavefront
-//      updates only the diagonal tile and starts at once, while the others
-//      update the tiles below; which wavefront it is rotates over the
-//      workgroups, so that the diagonal steps of the workgroups sharing a
-//      compute unit spread over its SIMDs;
-//  (3) rows below: X = A Z^T on MFMA, one 16-row tile per wavefront, read
-//      from the panel buffer and written to the matrix.
-// LDS use is one 16-row tile per 16 rows of the neighbourhood (about 2 KB per
-// tile in FP64), so several factorisations share a compute unit and hide
-// each other's memory latency.
+// Left-looking blocked Cholesky by one workgroup, 32-column panels P (two 16-column
+// tiles, h = 0, 1), in units of two 16-row tiles from the panel's diagonal down:
+//  (1) update  A[c0:N+3, c0:c0+32] -= L[c0:N+3, 0:c0] L[c0:c0+32, 0:c0]^T  on MFMA
+//      16x16x4, 16 k at a time from aligned 4-vector loads, a ring of chunks in
+//      flight per wavefront.  The tiles of a unit stay in registers, held
+//      transposed (M = A^T: the accumulator layout in which a tile's four
+//      registers are directly the right-hand operands of the four k-steps of
+//      the next 16 x 16 x 16 product).  Units are handed out from a counter in
+//      LDS; with fewer units than wavefronts their k range is split and the
+//      parts meet in LDS; in long panels the k range of unit 0 is split over
+//      all wavefronts first;
+//  (2) unit 0 (the diagonal tiles), by one wavefront at raised priority:
+//      factorise the first diagonal tile and invert it (Z1 = L11^{-1}), L21 =
+//      A21 Z1^T, A22 -= L21 L21^T, factorise and invert the second (Z2), all
+//      into the matrix and Z1, L21, Z2 into LDS, then raise a flag in LDS;
+//  (3) any other unit, once the flag is up: X1 = A1 Z1^T, A2 -= X1 L21^T,
+//      X2 = A2 Z2^T on its own registers, written to the matrix.
+// One barrier per panel (two with split units).  The three extra rows (d^T) are
+// ordinary rows of the last row tiles, so the factorisation leaves y = L^{-1} d
+// in them.  Which wavefront takes the diagonal rotates over the workgroups, so
+// that the chains of the workgroups sharing a compute unit spread over its SIMDs.
+// LDS: a few tiles and the split parts, so several factorisations share a
+// compute unit and hide each other's memory latency.
 // ---------------------------------------------------------------------------
 constexpr int kSlotLd = 17;   // row stride of a 16x16 tile in LDS (padding against bank conflicts)
 #ifndef LMBD_FACTOR_RING
@@ -154,267 +154,351 @@ __device__ inline typename Vec4T<R>::type load4(const R* p) {
     return *reinterpret_cast<const typename Vec4T<R>::type*>(p);
 }
 
+constexpr int kMaxParts = 3;          // stored k-split parts of a panel: at most wavefronts - 1
+constexpr int kSpinMax = 1 << 22;     // polls of the diagonal flag before a wavefront gives up
 
+// Diagonal block by one wavefront: the 16 x 16 tile in Lt (row-major, rows < jb) is
+// factorised with lane l holding row l of the tile and column l of Z = L^{-1}.  Step c
+// scales column c by 1 / L_cc and reads L[s][c] (s > c) from lane s; the same values
+// update the later rows of the tile (right-looking) and the later entries of every
+// column of Z (z[s] -= L[s][c] z[c], by forward substitution in the order of c).  L goes
+// to the matrix at (c0, c0), Z to Zs (row-major) and its strict lower part, transposed,
+// to the block's strict upper part in the matrix.  Rows from jb on are those of the
+// identity.  good turns false on a pivot that is not positive.
 template <typename R>
-__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ pan, R* __restrict__ Zs,
-                                            int* counter, int dw, bool& ok) {
+__device__ __forceinline__ void diag_block(R* __restrict__ Lt, int jb, R* __restrict__ A, int ld, int c0,
+                                           R* __restrict__ Zs, bool& good) {
+    // (l is made opaque so that the per-lane constants are not hoisted out of the
+    // panel loop, where they would only take registers)
+    int l = threadIdx.x & 63;
+    asm volatile("" : "+v"(l));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    R row[NB], z[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        row[c] = (l < jb && c <= l) ? Lt[l * kSlotLd + c] : (l == c ? R(1) : R(0));
+        z[c] = (l == c) ? R(1) : R(0);
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const R dcc = bcast(row[c], c);
+        if (c < jb && !(dcc > R(0))) good = false;
+        const R inv = rsqrt_refined(dcc);
+        if (l == c) row[c] = dcc * inv;
+        else if (l > c) row[c] *= inv;
+        z[c] *= inv;
+#pragma unroll
+        for (int s = c + 1; s < NB; ++s) {
+            const R lsc = bcast(row[c], s);  // L[s][c]
+            if (l >= s) row[s] -= row[c] * lsc;
+            z[s] -= lsc * z[c];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (l < jb) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c <= l) A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
+    }
+    if (l < NB) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Zs[q * kSlotLd + l] = z[q];
+    }
+    if (l < jb) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (q > l && q < jb) A[(size_t)(c0 + l) * ld + c0 + q] = z[q];
+    }
+}
+
+// The factorisation (see the storage and algorithm notes above).  Lt: one tile and
+// its padding column; part: kMaxParts x 4 tiles of k-split partial sums; Z1, Z2, L21:
+// one tile each; ctl: two unit counters, the diagonal flag and the give-up flag.
+template <typename R>
+__device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ Lt,
+                                            R* __restrict__ part, R* __restrict__ Z1, R* __restrict__ Z2,
+                                            R* __restrict__ L21, int* ctl, int dw, bool& ok, bool& stalled) {
     typedef Mfma<R> M;
+    typedef typename M::acc Acc;
     typedef typename Vec4T<R>::type V4;
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
+    const int lane = tid & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform, so are the unit indices below
     const int li = lane & 15, lk = lane >> 4;
-    const int nt = (N + NB - 1) / NB;           // panels (columns of B~)
-    const int Nr = N + 3;                        // rows: B~, then d^T
-    const int ntr = (Nr + NB - 1) / NB;          // row tiles
+    const int Nr = N + 3;                           // rows: B~, then d^T
+    const int ntr = (Nr + NB - 1) / NB;             // row tiles
+    const int npan = (N + 2 * NB - 1) / (2 * NB);   // 32-column panels
     const V4 zero = {R(0), R(0), R(0), R(0)};
+    Acc zacc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zacc[q] = R(0);
     bool good = true;
-    bool paired_prev = false;   // the previous (even) panel already applied chunks < p-1 to this panel
-    if (tid == 0) counter[0] = 0;
+    if (tid < 4) ctl[tid] = 0;
     __syncthreads();
-    for (int p = 0; p < nt; ++p) {
-        const int c0 = p * NB;
-        const int jb = min(NB, N - c0);
-        const int m = ntr - p;                       // row tiles from this panel down
-        const bool only_last = paired_prev;          // then only chunk p-1 is left
-        const int k_lo = only_last ? p - 1 : 0;
-        const int nk = p - k_lo;                     // chunks of this panel's update
-        const int S = (!only_last && p > 0 && m < nwave) ? min(nwave / m, nk) : 1;
-        // an even panel with an unsplit update also applies its chunks to the
-        // next panel's columns (in place), so that panel only needs the last chunk
-        const bool pair = (p % 2 == 0) && p > 0 && S == 1 && !only_last && p + 1 < nt;
-        const int U = m * S;
-        // with an unsplit update the diagonal wave updates tile 0 alone and
-        // factorises it at once, while the other waves update the tiles below
-        const bool early = (S == 1) && nwave > 1;
-        // (1) update: one (row tile, k-split) unit at a time per wavefront, units
-        // taken from a counter in LDS; the unit with s = 0 starts from the
-        // matrix, the others from zero; results (partial tiles for s > 0) go to
-        // the panel buffer, tile u = t + s m.  A unit's result does not depend
-        // on which wavefront computes it.
-        // NT row tiles t0, t0 + 1, .. (k-split part s) as one unit: the panel
-        // rows (b) loaded once per chunk serve all its tiles
-        auto unit_tiles = [&](int t0, int s, auto ntc) {
-            constexpr int NT = decltype(ntc)::value;
-            typename M::acc acc0[NT], acc1[NT];   // start from the matrix values
-            bool tv[NT], two[NT];
+    for (int P = 0; P < npan; ++P) {
+        const int c0 = 2 * NB * P;
+        const int jb = min(2 * NB, N - c0), jb1 = min(NB, jb), jb2 = jb - jb1;
+        const bool two = jb2 > 0;                   // the panel has a second column tile
+        const int mt = ntr - 2 * P;                 // row tiles from the panel's diagonal down
+        const int nu = (mt + 1) / 2;                // units: pairs of row tiles
+        const int nch = 2 * P;                      // finished 16-column chunks
+        const int S = (nu < nwave && nch > 1) ? min(nwave / nu, nch) : 1;   // k-split parts
+        // (1) the update of unit u (row tiles 2u, 2u + 1; both column tiles) with the
+        // chunks s, s + S, ..: m[x][h] = A(2u + x, h)^T - (L_h L_t^T)^T, starting from
+        // the matrix (part 0) or from zero
+        auto update = [&](int u, int s, int S, Acc(&m)[2][2]) {
+            bool v[2][2];
 #pragma unroll
-            for (int x = 0; x < NT; ++x) {
-                const int t = t0 + x;
-                tv[x] = t < m;
-                two[x] = pair && t > 0 && tv[x];
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + li, col1 = c0 + NB + li;
-                    acc0[x][q] = (tv[x] && s == 0 && row < Nr && col < N && (t > 0 || row >= col)) ? A[(size_t)row * ld + col] : R(0);
-                    acc1[x][q] = (two[x] && row < Nr && col1 < N && (t > 1 || row >= col1)) ? A[(size_t)row * ld + col1] : R(0);
+                for (int h = 0; h < 2; ++h) {
+                    const int t = 2 * u + x;
+                    v[x][h] = t < mt && (h == 0 || two) && !(t == 0 && h == 1);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = c0 + NB * t + li, col = c0 + NB * h + M::acc_row(lk, q);
+                        m[x][h][q] = (s == 0 && v[x][h] && row < Nr && col < N && (t != h || row >= col))
+                                         ? A[(size_t)row * ld + col] : R(0);
+                    }
                 }
-            }
-            const bool anytwo = pair && t0 + NT - 1 > 0;   // uniform
-            if (nk > 0) {
-                const int brow0 = c0 + li, brow1 = c0 + NB + li;
-                const bool bok0 = brow0 < N, bok1 = anytwo && brow1 < N;
-                const R* pa[NT];
-                bool aok[NT];
+            if (s < nch) {   // uniform
+                const R* pt[2];
+                const R* ph[2];
+                bool okt[2], okh[2];
 #pragma unroll
-                for (int x = 0; x < NT; ++x) {
-                    const int arow = c0 + NB * (t0 + x) + li;
-                    aok[x] = tv[x] && arow < Nr;
-                    pa[x] = A + (size_t)(aok[x] ? arow : 0) * ld + 4 * lk;
+                for (int x = 0; x < 2; ++x) {
+                    const int r = c0 + NB * (2 * u + x) + li;
+                    okt[x] = 2 * u + x < mt && r < Nr;
+                    pt[x] = A + (size_t)(okt[x] ? r : 0) * ld + 4 * lk;
                 }
-                const R* pb0 = A + (size_t)(bok0 ? brow0 : 0) * ld + 4 * lk;
-                const R* pb1 = A + (size_t)(bok1 ? brow1 : 0) * ld + 4 * lk;
-                auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < p) ? load4(base + NB * c) : zero; };
-                // ring of kRing chunks: each chunk's registers are refilled with the
-                // chunk kRing ahead right after use
-                const int c1 = k_lo + s;
-                V4 ra[kRing][NT], rb[kRing], rc[kRing];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = c0 + NB * h + li;
+                    okh[h] = (h == 0 || two) && r < N;
+                    ph[h] = A + (size_t)(okh[h] ? r : 0) * ld + 4 * lk;
+                }
+                auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < nch) ? load4(base + NB * c) : zero; };
+                // ring of kRing chunks: each chunk's registers are refilled with the chunk
+                // kRing ahead right after use
+                V4 rt[kRing][2], rh[kRing][2];
 #pragma unroll
                 for (int j = 0; j < kRing; ++j) {
 #pragma unroll
-                    for (int x = 0; x < NT; ++x) ra[j][x] = ld4(pa[x], aok[x], c1 + j * S);
-                    rb[j] = ld4(pb0, bok0, c1 + j * S);
-                    rc[j] = ld4(pb1, bok1, c1 + j * S);
+                    for (int x = 0; x < 2; ++x) rt[j][x] = ld4(pt[x], okt[x], s + j * S);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) rh[j][h] = ld4(ph[h], okh[h], s + j * S);
                 }
-                for (int ch = c1; ch < p; ch += kRing * S) {
+                for (int ch = s; ch < nch; ch += kRing * S) {
 #pragma unroll
                     for (int j = 0; j < kRing; ++j) {
-                        if (ch + j * S < p) {   // uniform
+                        if (ch + j * S < nch) {   // uniform
 #pragma unroll
-                            for (int x = 0; x < NT; ++x) {
+                            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                                for (int e = 0; e < 4; ++e) acc0[x] = M::mma(-ra[j][x][e], rb[j][e], acc0[x]);
-                            }
-                            if (anytwo) {
+                                for (int h = 0; h < 2; ++h)
+                                    if (v[x][h]) {   // uniform
 #pragma unroll
-                                for (int x = 0; x < NT; ++x) {
-#pragma unroll
-                                    for (int e = 0; e < 4; ++e) acc1[x] = M::mma(-ra[j][x][e], rc[j][e], acc1[x]);
-                                }
-                            }
+                                        for (int e = 0; e < 4; ++e) m[x][h] = M::mma(-rh[j][h][e], rt[j][x][e], m[x][h]);
+                                    }
                         }
                         const int cn = ch + (j + kRing) * S;
 #pragma unroll
-                        for (int x = 0; x < NT; ++x) ra[j][x] = ld4(pa[x], aok[x], cn);
-                        rb[j] = ld4(pb0, bok0, cn);
-                        rc[j] = ld4(pb1, bok1, cn);
-                    }
-                }
-            }
+                        for (int x = 0; x < 2; ++x) rt[j][x] = ld4(pt[x], okt[x], cn);
 #pragma unroll
-            for (int x = 0; x < NT; ++x) {
-                if (!tv[x]) continue;
-                const int t = t0 + x;
-                R* tl = pan + (size_t)(t + s * m) * NB * kSlotLd;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) tl[M::acc_row(lk, q) * kSlotLd + li] = acc0[x][q];
-                if (two[x]) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = c0 + NB * t + M::acc_row(lk, q), col = c0 + NB + li;
-                        if (row < Nr && col < N && (t > 1 || row >= col)) A[(size_t)row * ld + col] = acc1[x][q];
+                        for (int h = 0; h < 2; ++h) rh[j][h] = ld4(ph[h], okh[h], cn);
                     }
                 }
             }
         };
-        auto unit = [&](int u) { unit_tiles(u % m, u / m, std::integral_constant<int, 1>()); };
-        // (2) diagonal block: the diagonal wave, lane l holds row l (in the early
-        // case it reads back the tile it has just written itself)
-        auto diag = [&]() {
-          {
-            const int l = lane;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            R row[NB];
+        // X^T = Z M for a tile held transposed (M = X^T before the step): the Z operand
+        // row-major from LDS, the tile's registers as the right-hand operands
+        auto zmul = [&](const R* Zs, const Acc& mm) {
+            Acc xo = zacc;
 #pragma unroll
-            for (int c = 0; c < NB; ++c) row[c] = (l < jb && c <= l) ? R(0) : (l == c ? R(1) : R(0));
-            if (l < jb) {
-                for (int s = 0; s < S; ++s) {
-                    const R* tl = pan + (size_t)(s * m) * NB * kSlotLd + l * kSlotLd;
-#pragma unroll
-                    for (int c = 0; c < NB; ++c)
-                        if (c <= l) row[c] += tl[c];
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            R invv[NB];   // 1 / L[c][c], the same in every lane
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const R dcc = bcast(row[c], c);
-                if (c < jb && !(dcc > R(0))) good = false;
-                const R inv = rsqrt_refined(dcc);
-                invv[c] = inv;
-                if (l == c) row[c] = dcc * inv;
-                else if (l > c) row[c] *= inv;
-#pragma unroll
-                for (int s = c + 1; s < NB; ++s) {
-                    const R lsc = bcast(row[c], s);  // L[s][c]
-                    if (l >= s) row[s] -= row[c] * lsc;
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            // L to the matrix, and to the diagonal tile of the panel buffer (its rows
-            // < jb are not needed any more) with 1/L_ii in the padding column
-            R* Lt = pan;
-            if (l < jb) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (c <= l) {
-                        A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
-                        Lt[l * kSlotLd + c] = row[c];
-                    }
-            }
-            if (l == 0) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) Lt[c * kSlotLd + NB] = invv[c];
-            }
-          }
-          {
-            // Z = L_pp^{-1}, lane j < 16 holds column j (forward substitution with
-            // the rows of L read back as LDS broadcasts); Z[q][j] (q > j) is stored
-            // at (c0 + j, c0 + q), and all of Z row-major in LDS.  (l is made
-            // opaque so that the per-lane constants are not hoisted out of the
-            // panel loop, where they would only take registers.)
-            int l = lane;
-            asm volatile("" : "+v"(l));
-            const R* Lt = pan;
-            R z[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                R v = (q == l) ? R(1) : R(0);
-                if (q < jb) {
-#pragma unroll
-                    for (int r = 0; r < q; ++r) v -= Lt[q * kSlotLd + r] * z[r];
-                    v *= Lt[q * kSlotLd + NB];
-                }
-                z[q] = v;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (l < NB) {
-#pragma unroll
-                for (int q = 0; q < NB; ++q) Zs[q * kSlotLd + l] = z[q];
-            }
-            if (l < jb) {
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    if (q > l && q < jb) A[(size_t)(c0 + l) * ld + c0 + q] = z[q];
-            }
-          }
+            for (int e = 0; e < 4; ++e) xo = M::mma(Zs[li * kSlotLd + M::acc_row(lk, e)], mm[e], xo);
+            return xo;
         };
-        int* ctr = counter + (p & 1);
-        if (early && wave == dw) {
-            unit(0);
-            diag();
-        }
-        for (;;) {
-            int g = 0;
-            if (lane == 0) g = atomicAdd(ctr, 1);
-            g = __shfl(g, 0);
-            if (early) {   // tiles 1 + 2g and 2 + 2g
-                if (1 + 2 * g >= m) break;
-                unit_tiles(1 + 2 * g, 0, std::integral_constant<int, 2>());
-            } else {
-                if (g >= U) break;
-                unit(g);
-            }
-        }
-        paired_prev = pair;
-        if (!early) {
-            __syncthreads();
-            if (wave == dw) diag();
-        }
-        if (tid == 0) counter[(p + 1) & 1] = 0;   // for the next panel (its last use was two barriers ago)
-        __syncthreads();
-        // (3) rows below the block (the rows of d^T among them): X = A Z^T on
-        // MFMA, one 16-row tile per wavefront, A summed over the k-split parts in
-        // the panel buffer; in a last, partial panel the rows of d^T share the
-        // diagonal tile
-        const int t0 = jb < NB ? 0 : 1;
-        for (int t = t0 + (wave - dw + nwave) % nwave; t < m; t += nwave) {
-            typename M::acc x;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = R(0);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kk = 4 * lk + e;
-                R av = pan[(size_t)t * NB * kSlotLd + li * kSlotLd + kk];
-                for (int s = 1; s < S; ++s) av += pan[(size_t)(t + s * m) * NB * kSlotLd + li * kSlotLd + kk];
-                x = M::mma(av, Zs[li * kSlotLd + kk], x);
-            }
+        // rows rmin.. of the result X (held transposed) of row tile t, column tile h
+        auto store_x = [&](const Acc& xt, int t, int h, int rmin) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = c0 + NB * t + M::acc_row(lk, q);
-                if (row >= c0 + jb && row < Nr && c0 + li < N) A[(size_t)row * ld + c0 + li] = x[q];
+                const int row = c0 + NB * t + li, col = c0 + NB * h + M::acc_row(lk, q);
+                if (li >= rmin && row < Nr && col < N) A[(size_t)row * ld + col] = xt[q];
+            }
+        };
+        // (2) unit 0, by one wavefront: the diagonal tiles and L21, published to the others
+        // (the tiles of row tile 1 wait in LDS, in the first part slot, while the first
+        // diagonal block is factorised; its rows of d^T, if any, stay in Lt)
+        auto diag_unit = [&](Acc(&m)[2][2]) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Lt[li * kSlotLd + M::acc_row(lk, q)] = m[0][0][q];
+                part[(0 * 4 + q) * 64 + lane] = m[1][0][q];
+                part[(1 * 4 + q) * 64 + lane] = m[1][1][q];
+            }
+            asm volatile("" ::: "memory");   // really reload them: no registers held over the chain
+            diag_block<R>(Lt, jb1, A, ld, c0, Z1, good);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (jb1 < NB) {   // rows of d^T in the diagonal tile
+                Acc m00;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) m00[q] = Lt[li * kSlotLd + M::acc_row(lk, q)];
+                store_x(zmul(Z1, m00), 0, 0, jb1);
+            }
+            if (mt > 1) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    m[1][0][q] = part[(0 * 4 + q) * 64 + lane];
+                    m[1][1][q] = part[(1 * 4 + q) * 64 + lane];
+                }
+                const Acc l21 = zmul(Z1, m[1][0]);
+                store_x(l21, 1, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) L21[li * kSlotLd + M::acc_row(lk, q)] = l21[q];
+                if (two) {
+                    // A22 -= L21 L21^T: the registers of L21^T are both operands
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) m[1][1] = M::mma(-l21[e], l21[e], m[1][1]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) Lt[li * kSlotLd + M::acc_row(lk, q)] = m[1][1][q];
+                    asm volatile("" ::: "memory");
+                    diag_block<R>(Lt, jb2, A, ld, c0 + NB, Z2, good);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    if (jb2 < NB) {   // rows of d^T in the second diagonal tile (still in Lt)
+                        Acc m11;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) m11[q] = Lt[li * kSlotLd + M::acc_row(lk, q)];
+                        store_x(zmul(Z2, m11), 1, 1, jb2);
+                    }
+                }
+            }
+            // the flag orders only the LDS tiles: the wavefront does not wait for its
+            // stores to the matrix, which the other wavefronts read after the panel's barrier
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            if (lane == 0) __hip_atomic_store(ctl + 2, P + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        // (3) any other unit, once the diagonal flag says panel P: X1 = A1 Z1^T,
+        // A2 -= X1 L21^T, X2 = A2 Z2^T, all on the unit's registers
+        auto below_unit = [&](int u, Acc(&m)[2][2]) {
+            for (int it = 0;; ++it) {   // bounded wait: a wavefront that gives up flags the call
+                if (__hip_atomic_load(ctl + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > P) break;
+                if (__hip_atomic_load(ctl + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0) break;
+                if (it >= kSpinMax) {
+                    __hip_atomic_store(ctl + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    stalled = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            R z1[4], z2[4], lr[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = li * kSlotLd + M::acc_row(lk, e);
+                z1[e] = Z1[o];
+                z2[e] = Z2[o];
+                lr[e] = L21[o];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int t = 2 * u + x;
+                if (t >= mt) continue;   // uniform
+                Acc x1 = zacc;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x1 = M::mma(z1[e], m[x][0][e], x1);
+                store_x(x1, t, 0, 0);
+                if (two) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) m[x][1] = M::mma(-lr[e], x1[e], m[x][1]);
+                    Acc x2 = zacc;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) x2 = M::mma(z2[e], m[x][1][e], x2);
+                    store_x(x2, t, 1, 0);
+                }
+            }
+        };
+        if (S == 1) {
+            // the diagonal wavefront takes unit 0 and starts its chain at once; units 1..
+            // go to whichever wavefront asks next
+            // the chain of the diagonal tiles is the panel's critical path: its
+            // wavefront issues ahead of the other workgroups' updates on its SIMD, and
+            // with many chunks unit 0's update is split over all wavefronts first
+            if (nch >= 2 * nwave) {
+                const int g = (wave - dw + nwave) % nwave;
+                Acc m[2][2] = {{zacc, zacc}, {zacc, zacc}};
+                update(0, g, nwave, m);
+                if (g > 0) {
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) part[(((g - 1) * 4 + y) * 4 + q) * 64 + lane] = m[y >> 1][y & 1][q];
+                }
+                __syncthreads();
+                if (g == 0) {
+                    __builtin_amdgcn_s_setprio(2);
+                    for (int g2 = 1; g2 < nwave; ++g2) {
+#pragma unroll
+                        for (int y = 0; y < 4; ++y)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) m[y >> 1][y & 1][q] += part[(((g2 - 1) * 4 + y) * 4 + q) * 64 + lane];
+                    }
+                    diag_unit(m);
+                    __builtin_amdgcn_s_setprio(0);
+                }
+            } else if (wave == dw) {
+                __builtin_amdgcn_s_setprio(2);
+                Acc m[2][2];
+                update(0, 0, 1, m);
+                diag_unit(m);
+                __builtin_amdgcn_s_setprio(0);
+            }
+            if (tid == 0) ctl[(P + 1) & 1] = 0;   // the next panel's counter (last used before the previous barrier)
+            int* ctr = ctl + (P & 1);
+            for (;;) {
+                int g = 0;
+                if (lane == 0) g = atomicAdd(ctr, 1);
+                g = __builtin_amdgcn_readfirstlane(g);
+                if (1 + g >= nu) break;
+                Acc m[2][2];
+                update(1 + g, 0, 1, m);
+                below_unit(1 + g, m);
+            }
+        } else {
+            // few units: item g = (unit g % nu, part g / nu) on wavefront dw + g; the parts
+            // s > 0 go through LDS to the wavefront of part 0, which adds them in order
+            const int g = (wave - dw + nwave) % nwave;
+            const bool have = g < nu * S;
+            const int u = g % nu, s = g / nu;
+            Acc m[2][2] = {{zacc, zacc}, {zacc, zacc}};   // defined on every path: nothing carried between panels
+            if (have) update(u, s, S, m);
+            if (have && s > 0) {
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) part[(((g - nu) * 4 + y) * 4 + q) * 64 + lane] = m[y >> 1][y & 1][q];
+            }
+            if (tid == 0) ctl[(P + 1) & 1] = 0;
+            __syncthreads();
+            if (have && s == 0) {
+                for (int s2 = 1; s2 < S; ++s2) {
+                    const int g2 = u + s2 * nu;
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) m[y >> 1][y & 1][q] += part[(((g2 - nu) * 4 + y) * 4 + q) * 64 + lane];
+                }
+                if (u == 0) {
+                    __builtin_amdgcn_s_setprio(2);
+                    diag_unit(m);
+                    __builtin_amdgcn_s_setprio(0);
+                } else {
+                    below_unit(u, m);
+                }
             }
         }
-        __syncthreads();
+        __syncthreads();   // the panel's columns are in the matrix before the next panel reads them
     }
     ok = good;
-}
-
-// panel buffer tiles of the factorisation for neighbourhoods of up to n1max atoms
-__host__ __device__ inline int factor_tiles(int n1max) {
-    const int nt = (3 * n1max + 3 + NB - 1) / NB;
-    return nt > 4 ? nt : 4;
 }
 
 template <typename R>
@@ -1017,18 +1101,19 @@ size_t scs_solve_lds_bytes(int n1max, bool mixed) {
 // Assembly, factorisation and first solve of B~ in place, one workgroup per
 // (atom, frequency): the matrix written just before it is read back stays in
 // the caches, as does the factor for the solve, and the write-bound assembly of
-// one workgroup overlaps the factorisations of the others on the compute unit.  The panel buffer is
-// dynamic LDS (the assembly uses the same space first); Z is a separate static
-// array so that the compiler sees it cannot alias the panel buffer (with one
-// carved buffer it spilled the diagonal step's registers).
+// one workgroup overlaps the factorisations of the others on the compute unit.
+// The diagonal tile and the k-split parts are dynamic LDS (the assembly and the
+// solve use the same space before and after); Z1, Z2 and L21 are a separate
+// static array so that the compiler sees they cannot alias it.
 static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
 static_assert(3 * 256 >= 3 * kMaxN1, "three rows per thread of the factorisation kernel cover its first solve");
+static_assert(256 / 64 - 1 <= kMaxParts, "k-split parts of four wavefronts");
 template <typename R, int NS>
 __global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, int n1max) {
     extern __shared__ double lds[];
-    __shared__ R Zs[NB * kSlotLd];
-    __shared__ int counter[2];
-    R* pan = reinterpret_cast<R*>(lds);
+    __shared__ R Zsh[3 * NB * kSlotLd];
+    __shared__ int ctl[4];
+    R* Lt = reinterpret_cast<R*>(lds);
     const int k = a.order[blockIdx.x];
     const int w = blockIdx.y;
     assemble_matrix<R>(a, k, w, n1max, lds);   // ends with a barrier
@@ -1037,10 +1122,15 @@ __global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, 
     R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
     // the wave that factorises the diagonal blocks rotates over the workgroups
     const int dw = (k + w) % (blockDim.x >> 6);
-    bool ok = true;
-    chol_factor<R>(A, N, ld, pan, Zs, counter, dw, ok);   // ends with a barrier
+    bool ok = true, stalled = false;
+    chol_factor<R>(A, N, ld, Lt, Lt + NB * kSlotLd, Zsh, Zsh + NB * kSlotLd, Zsh + 2 * NB * kSlotLd, ctl, dw, ok,
+                   stalled);   // ends with a barrier
     if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
         atomicOr(a.err, 4);
+        atomicMin(a.err_atom, k);
+    }
+    if (stalled && (threadIdx.x & 63) == 0) {
+        atomicOr(a.err, 64);
         atomicMin(a.err_atom, k);
     }
     // the first solve (backward: the forward substitution was carried by the
@@ -1048,23 +1138,21 @@ __global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, 
     solve_slot<R, NS, 1>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
 }
 
-// dynamic LDS of the factorisation (the panel buffer)
-static size_t factor_panel_bytes(int n1max, bool mixed) {
+// dynamic LDS of the factorisation: the diagonal tile and the k-split parts
+static size_t factor_panel_bytes(bool mixed) {
     const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return r * (size_t)factor_tiles(n1max) * NB * kSlotLd;
+    return r * ((size_t)NB * kSlotLd + (size_t)kMaxParts * 16 * 64);
 }
 
 // dynamic LDS of the assembly and factorisation kernel
 static size_t factor_dynamic_bytes(int n1max, bool mixed) {
-    return std::max(std::max(factor_panel_bytes(n1max, mixed), matrix_lds_bytes(n1max)),
-                    scs_solve_lds_bytes(n1max, mixed));
+    return std::max(std::max(factor_panel_bytes(mixed), matrix_lds_bytes(n1max)), scs_solve_lds_bytes(n1max, mixed));
 }
 
-// all LDS of the assembly and factorisation: panel buffer (or the assembly's
-// data) and Z = L_pp^{-1}
+// all LDS of the assembly and factorisation: the dynamic part and Z1, Z2, L21
 size_t scs_factor_lds_bytes(int n1max, bool mixed) {
     const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return factor_dynamic_bytes(n1max, mixed) + r * NB * kSlotLd;
+    return factor_dynamic_bytes(n1max, mixed) + r * 3 * NB * kSlotLd;
 }
 
 // Refinement residual of the mixed path: resid = d - B~ X in FP64, with B~

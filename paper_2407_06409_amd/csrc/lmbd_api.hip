@@ -1330,6 +1330,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
         return fail(ctx, LMBD_E_SCS_BREAKDOWN,
                     "SCS polarisability not decreasing between 0 and omega_ref in the frame of atom " +
                         std::to_string(flags[1]));
+    if (flags[0] & 64)
+        return fail(ctx, LMBD_E_DEVICE, "a wavefront of the SCS factorisation of atom " + std::to_string(flags[1]) +
+                                            " gave up waiting for its diagonal block");
     if (flags[0] & 32)
         return fail(ctx, LMBD_E_DEVICE, "coupled-site lists of atom " + std::to_string(flags[1]) + " outgrew their bound");
     if (flags[0] & 16)
