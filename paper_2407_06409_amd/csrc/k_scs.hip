@@ -184,13 +184,14 @@ __device__ __forceinline__ void diag_block(R* __restrict__ Lt, int jb, R* __rest
         const R dcc = bcast(row[c], c);
         if (c < jb && !(dcc > R(0))) good = false;
         const R inv = rsqrt_refined(dcc);
-        if (l == c) row[c] = dcc * inv;
-        else if (l > c) row[c] *= inv;
+        // every lane updates: entries above the diagonal (l < s) are never stored
+        // or read from another lane again
+        row[c] = (l == c ? dcc : row[c]) * inv;
         z[c] *= inv;
 #pragma unroll
         for (int s = c + 1; s < NB; ++s) {
             const R lsc = bcast(row[c], s);  // L[s][c]
-            if (l >= s) row[s] -= row[c] * lsc;
+            row[s] -= row[c] * lsc;
             z[s] -= lsc * z[c];
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -212,12 +213,14 @@ __device__ __forceinline__ void diag_block(R* __restrict__ Lt, int jb, R* __rest
 }
 
 // The factorisation (see the storage and algorithm notes above).  Lt: one tile and
-// its padding column; part: kMaxParts x 4 tiles of k-split partial sums; Z1, Z2, L21:
-// one tile each; ctl: two unit counters, the diagonal flag and the give-up flag.
+// its padding column; part: kMaxParts x 4 tiles of k-split partial sums; pre: 2 x 4
+// tiles (the prepared unit 0, double-buffered over panels); Z1, Z2, L21: one tile
+// each; ctl: two unit counters, the diagonal flag and the give-up flag.
 template <typename R>
 __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R* __restrict__ Lt,
-                                            R* __restrict__ part, R* __restrict__ Z1, R* __restrict__ Z2,
-                                            R* __restrict__ L21, int* ctl, int dw, bool& ok, bool& stalled) {
+                                            R* __restrict__ part, R* __restrict__ pre, R* __restrict__ Z1,
+                                            R* __restrict__ Z2, R* __restrict__ L21, int* ctl, int dw, bool& ok,
+                                            bool& stalled) {
     typedef Mfma<R> M;
     typedef typename M::acc Acc;
     typedef typename Vec4T<R>::type V4;
@@ -232,6 +235,85 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     Acc zacc;
 #pragma unroll
     for (int q = 0; q < 4; ++q) zacc[q] = R(0);
+    // (1) the update of unit u (row tiles 2u, 2u + 1; both column tiles) of the panel
+    // at column c0p (mtp row tiles from its diagonal down, a second column tile if twop)
+    // with the chunks cb, cb + st, .. below ce: m[x][h] = A(2u + x, h)^T - (L_h L_t^T)^T,
+    // starting from the matrix (init 0), from zero (1) or from m as given (2)
+    auto update = [&](int c0p, int mtp, bool twop, int u, int cb, int st, int ce, int init, Acc(&m)[2][2]) {
+        bool v[2][2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = 2 * u + x;
+                v[x][h] = t < mtp && (h == 0 || twop) && !(t == 0 && h == 1);
+                if (init != 2) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = c0p + NB * t + li, col = c0p + NB * h + M::acc_row(lk, q);
+                        m[x][h][q] = (init == 0 && v[x][h] && row < Nr && col < N && (t != h || row >= col))
+                                         ? A[(size_t)row * ld + col] : R(0);
+                    }
+                }
+            }
+        if (cb < ce) {   // uniform
+            const R* pt[2];
+            const R* ph[2];
+            bool okt[2], okh[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int r = c0p + NB * (2 * u + x) + li;
+                okt[x] = 2 * u + x < mtp && r < Nr;
+                pt[x] = A + (size_t)(okt[x] ? r : 0) * ld + 4 * lk;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = c0p + NB * h + li;
+                okh[h] = (h == 0 || twop) && r < N;
+                ph[h] = A + (size_t)(okh[h] ? r : 0) * ld + 4 * lk;
+            }
+            auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < ce) ? load4(base + NB * c) : zero; };
+            // ring of kRing chunks: each chunk's registers are refilled with the chunk
+            // kRing ahead right after use
+            V4 rt[kRing][2], rh[kRing][2];
+#pragma unroll
+            for (int j = 0; j < kRing; ++j) {
+#pragma unroll
+                for (int x = 0; x < 2; ++x) rt[j][x] = ld4(pt[x], okt[x], cb + j * st);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) rh[j][h] = ld4(ph[h], okh[h], cb + j * st);
+            }
+            for (int ch = cb; ch < ce; ch += kRing * st) {
+#pragma unroll
+                for (int j = 0; j < kRing; ++j) {
+                    if (ch + j * st < ce) {   // uniform
+#pragma unroll
+                        for (int x = 0; x < 2; ++x)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+                                if (v[x][h]) {   // uniform
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e) m[x][h] = M::mma(-rh[j][h][e], rt[j][x][e], m[x][h]);
+                                }
+                    }
+                    const int cn = ch + (j + kRing) * st;
+#pragma unroll
+                    for (int x = 0; x < 2; ++x) rt[j][x] = ld4(pt[x], okt[x], cn);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) rh[j][h] = ld4(ph[h], okh[h], cn);
+                }
+            }
+        }
+    };
+    // k-split parts of panel Pq's units; and whether unit 0 of panel Pq is prepared
+    // during panel Pq - 1 (all chunks but the last two) by the wavefront after the
+    // diagonal one, so that the chain of Pq starts after two chunks
+    auto kparts = [&](int Pq) {
+        const int nuq = (ntr - 2 * Pq + 1) / 2, nchq = 2 * Pq;
+        return (nuq < nwave && nchq > 1) ? min(nwave / nuq, nchq) : 1;
+    };
+    auto has_pre = [&](int Pq) { return Pq >= 2 && Pq < npan && kparts(Pq) == 1; };
+    const int pw = (dw + 1) % nwave;
     bool good = true;
     if (tid < 4) ctl[tid] = 0;
     __syncthreads();
@@ -242,74 +324,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
         const int mt = ntr - 2 * P;                 // row tiles from the panel's diagonal down
         const int nu = (mt + 1) / 2;                // units: pairs of row tiles
         const int nch = 2 * P;                      // finished 16-column chunks
-        const int S = (nu < nwave && nch > 1) ? min(nwave / nu, nch) : 1;   // k-split parts
-        // (1) the update of unit u (row tiles 2u, 2u + 1; both column tiles) with the
-        // chunks s, s + S, ..: m[x][h] = A(2u + x, h)^T - (L_h L_t^T)^T, starting from
-        // the matrix (part 0) or from zero
-        auto update = [&](int u, int s, int S, Acc(&m)[2][2]) {
-            bool v[2][2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int t = 2 * u + x;
-                    v[x][h] = t < mt && (h == 0 || two) && !(t == 0 && h == 1);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = c0 + NB * t + li, col = c0 + NB * h + M::acc_row(lk, q);
-                        m[x][h][q] = (s == 0 && v[x][h] && row < Nr && col < N && (t != h || row >= col))
-                                         ? A[(size_t)row * ld + col] : R(0);
-                    }
-                }
-            if (s < nch) {   // uniform
-                const R* pt[2];
-                const R* ph[2];
-                bool okt[2], okh[2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    const int r = c0 + NB * (2 * u + x) + li;
-                    okt[x] = 2 * u + x < mt && r < Nr;
-                    pt[x] = A + (size_t)(okt[x] ? r : 0) * ld + 4 * lk;
-                }
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = c0 + NB * h + li;
-                    okh[h] = (h == 0 || two) && r < N;
-                    ph[h] = A + (size_t)(okh[h] ? r : 0) * ld + 4 * lk;
-                }
-                auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < nch) ? load4(base + NB * c) : zero; };
-                // ring of kRing chunks: each chunk's registers are refilled with the chunk
-                // kRing ahead right after use
-                V4 rt[kRing][2], rh[kRing][2];
-#pragma unroll
-                for (int j = 0; j < kRing; ++j) {
-#pragma unroll
-                    for (int x = 0; x < 2; ++x) rt[j][x] = ld4(pt[x], okt[x], s + j * S);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) rh[j][h] = ld4(ph[h], okh[h], s + j * S);
-                }
-                for (int ch = s; ch < nch; ch += kRing * S) {
-#pragma unroll
-                    for (int j = 0; j < kRing; ++j) {
-                        if (ch + j * S < nch) {   // uniform
-#pragma unroll
-                            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                                for (int h = 0; h < 2; ++h)
-                                    if (v[x][h]) {   // uniform
-#pragma unroll
-                                        for (int e = 0; e < 4; ++e) m[x][h] = M::mma(-rh[j][h][e], rt[j][x][e], m[x][h]);
-                                    }
-                        }
-                        const int cn = ch + (j + kRing) * S;
-#pragma unroll
-                        for (int x = 0; x < 2; ++x) rt[j][x] = ld4(pt[x], okt[x], cn);
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) rh[j][h] = ld4(ph[h], okh[h], cn);
-                    }
-                }
-            }
-        };
+        const int S = kparts(P);                    // k-split parts
         // X^T = Z M for a tile held transposed (M = X^T before the step): the Z operand
         // row-major from LDS, the tile's registers as the right-hand operands
         auto zmul = [&](const R* Zs, const Acc& mm) {
@@ -421,36 +436,33 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             // the diagonal wavefront takes unit 0 and starts its chain at once; units 1..
             // go to whichever wavefront asks next
             // the chain of the diagonal tiles is the panel's critical path: its
-            // wavefront issues ahead of the other workgroups' updates on its SIMD, and
-            // with many chunks unit 0's update is split over all wavefronts first
-            if (nch >= 2 * nwave) {
-                const int g = (wave - dw + nwave) % nwave;
-                Acc m[2][2] = {{zacc, zacc}, {zacc, zacc}};
-                update(0, g, nwave, m);
-                if (g > 0) {
+            // wavefront issues ahead of the other workgroups' updates on its SIMD and
+            // finds unit 0 prepared but for the last two chunks
+            if (wave == dw) {
+                __builtin_amdgcn_s_setprio(2);
+                Acc m[2][2];
+                if (has_pre(P)) {
+                    const R* pr = pre + (P & 1) * 16 * 64;
 #pragma unroll
                     for (int y = 0; y < 4; ++y)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) part[(((g - 1) * 4 + y) * 4 + q) * 64 + lane] = m[y >> 1][y & 1][q];
+                        for (int q = 0; q < 4; ++q) m[y >> 1][y & 1][q] = pr[(y * 4 + q) * 64 + lane];
+                    update(c0, mt, two, 0, nch - 2, 1, nch, 2, m);
+                } else {
+                    update(c0, mt, two, 0, 0, 1, nch, 0, m);
                 }
-                __syncthreads();
-                if (g == 0) {
-                    __builtin_amdgcn_s_setprio(2);
-                    for (int g2 = 1; g2 < nwave; ++g2) {
-#pragma unroll
-                        for (int y = 0; y < 4; ++y)
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) m[y >> 1][y & 1][q] += part[(((g2 - 1) * 4 + y) * 4 + q) * 64 + lane];
-                    }
-                    diag_unit(m);
-                    __builtin_amdgcn_s_setprio(0);
-                }
-            } else if (wave == dw) {
-                __builtin_amdgcn_s_setprio(2);
-                Acc m[2][2];
-                update(0, 0, 1, m);
                 diag_unit(m);
                 __builtin_amdgcn_s_setprio(0);
+            }
+            if (wave == pw && has_pre(P + 1)) {   // unit 0 of the next panel with this panel's chunks
+                const int c0n = c0 + 2 * NB;
+                Acc m[2][2];
+                update(c0n, mt - 2, N - c0n > NB, 0, 0, 1, nch, 0, m);
+                R* pr = pre + ((P + 1) & 1) * 16 * 64;
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pr[(y * 4 + q) * 64 + lane] = m[y >> 1][y & 1][q];
             }
             if (tid == 0) ctl[(P + 1) & 1] = 0;   // the next panel's counter (last used before the previous barrier)
             int* ctr = ctl + (P & 1);
@@ -460,7 +472,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 g = __builtin_amdgcn_readfirstlane(g);
                 if (1 + g >= nu) break;
                 Acc m[2][2];
-                update(1 + g, 0, 1, m);
+                update(c0, mt, two, 1 + g, 0, 1, nch, 0, m);
                 below_unit(1 + g, m);
             }
         } else {
@@ -470,7 +482,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             const bool have = g < nu * S;
             const int u = g % nu, s = g / nu;
             Acc m[2][2] = {{zacc, zacc}, {zacc, zacc}};   // defined on every path: nothing carried between panels
-            if (have) update(u, s, S, m);
+            if (have) update(c0, mt, two, u, s, S, nch, s == 0 ? 0 : 1, m);
             if (have && s > 0) {
 #pragma unroll
                 for (int y = 0; y < 4; ++y)
@@ -1123,8 +1135,9 @@ __global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, 
     // the wave that factorises the diagonal blocks rotates over the workgroups
     const int dw = (k + w) % (blockDim.x >> 6);
     bool ok = true, stalled = false;
-    chol_factor<R>(A, N, ld, Lt, Lt + NB * kSlotLd, Zsh, Zsh + NB * kSlotLd, Zsh + 2 * NB * kSlotLd, ctl, dw, ok,
-                   stalled);   // ends with a barrier
+    R* part = Lt + NB * kSlotLd;
+    chol_factor<R>(A, N, ld, Lt, part, part + kMaxParts * 16 * 64, Zsh, Zsh + NB * kSlotLd, Zsh + 2 * NB * kSlotLd,
+                   ctl, dw, ok, stalled);   // ends with a barrier
     if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
         atomicOr(a.err, 4);
         atomicMin(a.err_atom, k);
@@ -1138,10 +1151,11 @@ __global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, 
     solve_slot<R, NS, 1>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
 }
 
-// dynamic LDS of the factorisation: the diagonal tile and the k-split parts
+// dynamic LDS of the factorisation: the diagonal tile, the k-split parts and the two
+// buffers of the prepared unit 0
 static size_t factor_panel_bytes(bool mixed) {
     const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return r * ((size_t)NB * kSlotLd + (size_t)kMaxParts * 16 * 64);
+    return r * ((size_t)NB * kSlotLd + (size_t)(kMaxParts + 2) * 16 * 64);
 }
 
 // dynamic LDS of the assembly and factorisation kernel
