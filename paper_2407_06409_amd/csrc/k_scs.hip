@@ -69,7 +69,8 @@ __device__ inline SrPair<P> sr_pair(P r, P ir, P s_ij, P S, P damp_d, P rc, P rb
 }
 
 __device__ inline void tri_decode(int t, int& i, int& j) {
-    int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    // a single-precision estimate of the row, corrected in integers
+    int a = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
     while ((a + 1) * (a + 2) / 2 <= t) ++a;
     while (a * (a + 1) / 2 > t) --a;
     i = a;
@@ -809,13 +810,12 @@ __device__ inline int32_t* pair_segs(const ScsArgs& a, int k) {
 
 // sites only (assembly): K1 sites then shell sites
 // assembly of d: K1 sites and shell sites; assembly of B~: K1 sites, one
-// chunk of pair values and slots, word counts and a bit per K1 pair (coupled)
+// chunk of slots, word counts and a bit per K1 pair (coupled)
 __host__ __device__ inline int assemble_mask_words(int n1max) { return (n1max * (n1max + 1) / 2 + 31) / 32; }
 
 static size_t dvec_lds_bytes(int n1max, int n2max) { return sizeof(double) * 6 * ((size_t)n1max + n2max); }
 static size_t matrix_lds_bytes(int n1max) {
-    return sizeof(double) * (6 * (size_t)n1max + 2 * kChunk) +
-           sizeof(int32_t) * (2 * kChunk + (size_t)assemble_mask_words(n1max));
+    return sizeof(double) * 6 * (size_t)n1max + sizeof(int32_t) * (2 * kChunk + (size_t)assemble_mask_words(n1max));
 }
 size_t scs_assemble_lds_bytes(int n1max, int n2max) {
     return std::max(dvec_lds_bytes(n1max, n2max), matrix_lds_bytes(n1max));
@@ -835,8 +835,8 @@ __device__ inline ScsLds scs_assemble_lds(double* base, int n1max, int n2max, bo
     L.qab = L.qz + n2max;
     L.qsg = L.qab + n2max;
     L.qR = L.qsg + n2max;
-    L.gk = L.qR + n2max;          // d: sums; B~: pair values
-    L.key = reinterpret_cast<int32_t*>(L.gk + (matrix ? 2 * kChunk : 6 * n1max));
+    L.gk = L.qR + n2max;          // d: sums
+    L.key = reinterpret_cast<int32_t*>(L.gk + (matrix ? 0 : 6 * n1max));
     return L;
 }
 
@@ -962,8 +962,6 @@ __device__ __forceinline__ void assemble_matrix(const ScsArgs& a, int k, int w, 
     const int ld = a.fac_ld[k];
     const double rc = a.sinfo[a.atom_struct[k]].r_scs;
     ScsLds L = scs_assemble_lds(lds, n1max, 0, true);
-    double* vA = L.gk;                                      // kChunk
-    double* vB = L.gk + kChunk;                             // kChunk
     int32_t* slot = L.key;                                  // kChunk
     int32_t* wcnt = L.key + kChunk;                         // kChunk / 32
     uint32_t* mask = reinterpret_cast<uint32_t*>(L.key + 2 * kChunk);
@@ -1002,21 +1000,24 @@ __device__ __forceinline__ void assemble_matrix(const ScsArgs& a, int k, int w, 
             }
         }
         __syncthreads();
+        // coupled pairs, compacted: T_SR and its block of B~
         if (t < total) {
             const int pp = slot[t];
             int i, j;
             tri_decode(pp, i, j);
             double rh[3], rr;
             const SrPair<R> tp = k1_pair<R>(a, L, i, j, rc, rh, rr);
-            vA[t] = double(tp.A);
-            vB[t] = double(tp.B);
             if (mixed) {
                 coef[2 * pp] = (float)tp.A;
                 coef[2 * pp + 1] = (float)tp.B;
             }
+            const double Av = double(tp.A), Bv = double(tp.B);
+            R* blk = A + (size_t)(3 * i) * ld + 3 * j;
+            for (int q = 0; q < 3; ++q)
+                for (int c = 0; c < 3; ++c) blk[(size_t)q * ld + c] = R(Av * rh[q] * rh[c] + (q == c ? Bv : 0.0));
         }
-        __syncthreads();
-        if (p < npairs) {
+        // every other pair of the chunk: diagonal blocks and uncoupled zeros
+        if (p < npairs && rank < 0) {
             int i, j;
             tri_decode(p, i, j);
             R* blk = A + (size_t)(3 * i) * ld + 3 * j;
@@ -1024,22 +1025,16 @@ __device__ __forceinline__ void assemble_matrix(const ScsArgs& a, int k, int w, 
                 const R inv = R(1.0 / L.ab[i]);
                 for (int q = 0; q < 3; ++q)
                     for (int c = 0; c <= q; ++c) blk[(size_t)q * ld + c] = (q == c) ? inv : R(0);
-                if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
-            } else if (rank < 0) {
+            } else {
                 for (int q = 0; q < 3; ++q)
                     for (int c = 0; c < 3; ++c) blk[(size_t)q * ld + c] = R(0);
-                if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
-            } else {
-                const double Av = vA[rank], Bv = vB[rank];
-                const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
-                const double ir = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
-                for (int q = 0; q < 3; ++q)
-                    for (int c = 0; c < 3; ++c) blk[(size_t)q * ld + c] = R(Av * rh[q] * rh[c] + (q == c ? Bv : 0.0));
             }
+            if (mixed) { coef[2 * p] = 0.f; coef[2 * p + 1] = 0.f; }
         }
-        __syncthreads();
+        // (no barrier here: the next chunk's first barrier separates these reads of
+        // slot from its writes, and wcnt was last read before the barrier above)
     }
+    __syncthreads();
 }
 
 // Triangular solves with the stored factor, one workgroup per (atom,
