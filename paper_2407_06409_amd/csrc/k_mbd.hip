@@ -1088,7 +1088,141 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
         g[2] += gp[2];
         Rb += a.beta * t.fLR * t.dfS * 2.0 * kap * t.A / (r * r * r);   // <C2, T_dip> = 2 kappa A / r^3
     };
-    if constexpr (SP) {
+    if constexpr (GS) {
+        // Each unordered coupled pair once (the neighbourhoods of this form are large and
+        // the contraction is bound by the gathers of P and Q rows): pass 1, one block row
+        // i per wavefront over its partners j < i (a prefix of the sorted row), forms
+        // Tbar_ij = P_i Q_j^T, C = Tbar_ij + Tbar_ij^T and the pair's terms (its gradient
+        // with respect to r_i and its R~ term) into the entry's slot of a pair buffer.
+        // Pass 2 sums every row over its partners in list order, reading the partner's
+        // slot (found by binary search in the partner's sorted row) with the gradient's
+        // sign turned for j > i: the gradient of a pair term is odd in rhat, the R~ term
+        // even.  The sums have a fixed order, as in the other forms.  The buffer (four
+        // values of the arithmetic type per entry) takes the place of the entries' T_LR
+        // coefficients, which the products before have used for the last time.
+        W* const pbuf = pA;
+        constexpr int VW = 16 / sizeof(W);
+        typedef W VV __attribute__((ext_vector_type(VW)));
+        const int pu = lane >> 3, pt = lane & 7;
+        for (int i = wave; i < nK; i += nwave) {
+            const int n = row_len(i);
+            const size_t e0 = (size_t)roff[i];
+            int nlo = 0;   // partners below i
+            for (int s0 = 0; s0 < n; s0 += 64) nlo += __popcll(__ballot(s0 + lane < n && pj[e0 + s0 + lane] < i));
+            // eight pairs per step, eight lanes per pair (as in the LDS form)
+            for (int s0 = 0; s0 < nlo; s0 += 8) {
+                const bool okp = s0 + pu < nlo;
+                const int j = pj[e0 + (okp ? s0 + pu : s0)];
+                double sb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                for (int kb = 0; kb < KKp; kb += 8 * VW) {
+                    const int kk = kb + VW * pt;
+                    const int ks = kk < KKp ? kk : 0;
+                    const double z = kk < KKp ? 1.0 : 0.0;
+                    VV pv[3], qv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        pv[c] = *reinterpret_cast<const VV*>(Pm + (size_t)(3 * i + c) * KKp + ks);
+                        qv[c] = *reinterpret_cast<const VV*>(Qm + (size_t)(3 * j + c) * KKp + ks);
+                    }
+#pragma unroll
+                    for (int x = 0; x < 3; ++x)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double d = 0.0;
+#pragma unroll
+                            for (int v = 0; v < VW; ++v) d += double(pv[x][v]) * double(qv[c][v]);
+                            sb[3 * x + c] += z * d;
+                        }
+                }
+#pragma unroll
+                for (int x = 0; x < 9; ++x) {
+                    sb[x] += __shfl_xor(sb[x], 1);
+                    sb[x] += __shfl_xor(sb[x], 2);
+                    sb[x] += __shfl_xor(sb[x], 4);
+                }
+                if (okp && pt == 0) {
+                    double C[9];
+                    for (int x = 0; x < 3; ++x)
+                        for (int c = 0; c < 3; ++c) C[3 * x + c] = sb[3 * x + c] + sb[3 * c + x];
+                    const double v[3] = {L.px[i] - L.px[j], L.py[i] - L.py[j], L.pz[i] - L.pz[j]};
+                    const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                    const double rcut = (i == 0 || j == 0) ? SI.r_mbd1 : SI.r_mbd2;
+                    const double rh[3] = {v[0] / r, v[1] / r, v[2] / r};
+                    const LrPair<W> lp = lr_pair<W>(W(r), W(a.beta * (L.Rt[i] + L.Rt[j])), W(a.damp_d), W(rcut),
+                                                    W(a.r_buf));
+                    double gp[3];
+                    radial_tensor_grad(rh, r, double(lp.A), double(lp.dA), double(lp.dB), C, gp);
+                    double rCr = 0.0;
+                    for (int x = 0; x < 3; ++x)
+                        for (int c = 0; c < 3; ++c) rCr += rh[x] * C[3 * x + c] * rh[c];
+                    const double ct = (3.0 * rCr - (C[0] + C[4] + C[8])) / (r * r * r);
+                    W* slot = pbuf + (e0 + s0 + pu) * 4;
+                    slot[0] = W(gp[0]);
+                    slot[1] = W(gp[1]);
+                    slot[2] = W(gp[2]);
+                    slot[3] = W(a.beta * double(lp.fLR) * double(lp.dfS) * ct);
+                }
+            }
+        }
+        __syncthreads();   // the pair buffer is complete
+        for (int i = wave; i < nK; i += nwave) {
+            double g[3] = {0.0, 0.0, 0.0};
+            double Rb = 0.0;
+            const int n = row_len(i);
+            const size_t e0 = (size_t)roff[i];
+            for (int s0 = 0; s0 < n; s0 += 64) {
+                // the slot of entry s0 + lane (every lane), then the sums in the order of
+                // eight pairs per step, pair u of a step on lane 8u
+                long long src = -1;
+                bool neg = false;
+                if (s0 + lane < n) {
+                    const int j = pj[e0 + s0 + lane];
+                    if (j < i) {
+                        src = (long long)(e0 + s0 + lane);
+                    } else {
+                        int lo = roff[j], hi = roff[j] + row_len(j);
+                        const int end = hi;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pj[mid] < i) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        if (lo < end && pj[lo] == i) {
+                            src = lo;
+                            neg = true;
+                        } else {   // the coupling relation is symmetric: never taken
+                            atomicOr(a.err, 32);
+                            atomicMin(a.err_atom, k);
+                        }
+                    }
+                }
+                for (int t = 0; t < 8; ++t) {
+                    const int from = 8 * t + pu;
+                    const long long sr = __shfl(src, from);
+                    const bool ng = __shfl((int)neg, from) != 0;
+                    if (pt == 0 && s0 + from < n && sr >= 0) {
+                        const W* slot = pbuf + (size_t)sr * 4;
+                        const double sg = ng ? -1.0 : 1.0;
+                        g[0] += sg * double(slot[0]);
+                        g[1] += sg * double(slot[1]);
+                        g[2] += sg * double(slot[2]);
+                        Rb += double(slot[3]);
+                    }
+                }
+            }
+            {   // the lanes' partial sums, in a fixed order
+                const double part[9] = {g[0], g[1], g[2], Rb, 0.0, 0.0, 0.0, 0.0, 0.0};
+                double tot[9];
+                wave_sum9(part, tot);
+                if (lane == 0) {
+                    L.g[(size_t)i * 3 + 0] = tot[0];
+                    L.g[(size_t)i * 3 + 1] = tot[1];
+                    L.g[(size_t)i * 3 + 2] = tot[2];
+                    L.rb[i] = tot[3];
+                }
+            }
+        }
+    } else if constexpr (SP) {
         // one block row per wavefront; Tbar_IJ (I > J) of a coupled pair from P and Q
         for (int i = wave; i < nK; i += nwave) {
             double g[3] = {0.0, 0.0, 0.0};
