@@ -23,7 +23,7 @@ constexpr double kSparseMbdRatio = 0.45;  // automatic sparse MBD products when 
 constexpr int kMaxNK = 400;        // sites in K (r < r_nbr), central atom included; the MBD kernel's LDS,
                                    // 8 (3 nq + 15) bytes per site for nq >= 12 nodes, caps it lower for
                                    // long grids (the host checks that limit too)
-constexpr int kMaxSites = 4096;    // sites in the largest ball, central atom included
+constexpr int kMaxSites = 32768;   // sites in the largest ball, central atom included (20 + 14 A at carbon density)
 constexpr int kFitNodes = 32;      // Gauss-Legendre points of the least-squares fit of ln(1 - x)
 constexpr int kMaxLanczos = 64;    // Lanczos steps for the spectrum bounds
 

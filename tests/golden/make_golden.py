@@ -165,6 +165,11 @@ def fixture(name):
         return {"cutoffs": cut,
                 "energies": energies_fixture("HCNO512 8 A", st, cut, sample(st.n, 4, 18)),
                 "forces": forces_fixture("HCNO512 8 A", st, cut, sample(st.n, 1, 19))}
+    if name == "C216_pbc_15p10A":
+        # the paper's 15 + 10 A production radii (Sec. IV): K = B(25 A), about 6,600 sites with images
+        st = C.carbon_box(216, 41, g_cm3=2.0)
+        cut = dict(r_scs=6.0, r_nbr=25.0, r_mbd1=15.0, r_mbd2=10.0)
+        return {"cutoffs": cut, "energies": energies_fixture("C216 15+10 A", st, cut, sample(st.n, 4, 20))}
     if name == "C1728_pbc_10p8A":
         st, cut = two_radius_10_8()
         return {"cutoffs": cut,
@@ -176,7 +181,7 @@ def fixture(name):
 
 
 NAMES = ["C1728_pbc", "HCNO4096_pbc", "C13824_pbc", "C1728_pbc_6p8A", "C1728_pbc_two_radius", "HCNO50_pbc_5A",
-         "HCNO100_pbc_6A", "C1728_pbc_10p8A", "HCNO512_pbc_8A"]
+         "HCNO100_pbc_6A", "C1728_pbc_10p8A", "HCNO512_pbc_8A", "C216_pbc_15p10A"]
 
 
 def main():
