@@ -586,8 +586,39 @@ def main():
                 rec["max_abs_dF_vs_fp64_eV_per_A"] = max_diff(o3, o3_64, "forces")
             pr[prec] = rec
         pr["energy_eV_per_atom_mean"] = float(o3_64["energies"].mean())
-        ctx3.close()
         del o3, o3_64
+        # the paper's larger production radii on smaller boxes of the same carbon (K of
+        # about 6,600 and 16,500 sites with periodic images)
+        larger = {}
+        for label, nb, seed, cutL in (("C216_15p10A", 216, 41, dict(r_scs=cut["r_scs"], r_nbr=25.0, r_mbd1=15.0, r_mbd2=10.0)),
+                                      ("C64_20p14A", 64, 43, dict(r_scs=cut["r_scs"], r_nbr=34.0, r_mbd1=20.0, r_mbd2=14.0))):
+            stL = C.carbon_box(nb, seed, g_cm3=2.0)
+            posL = torch.as_tensor(stL.pos, dtype=torch.float64, device=dev)
+            spL = torch.as_tensor(stL.species, dtype=torch.int32, device=dev)
+            nuL = torch.as_tensor(stL.nu, dtype=torch.float64, device=dev)
+            recL = {"cutoffs_A": cutL, "mean_nK": float(neighbour_counts(stL, cutL["r_nbr"]).mean())}
+            for prec in ("fp64", "mixed"):
+                prmL = dataclasses.replace(mp, precision=prec)
+
+                def runL():
+                    return P.compute(posL, spL, nuL, cutoffs=cutL, params=prmL, species_table=SPECIES_TABLE,
+                                     cell=stL.cell, forces=True, ctx=ctx3, stream=stream)
+                runL()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                oL = runL()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                recL[prec] = {"value": stL.n / el, "unit": "atoms/s", "ms_per_step": el * 1e3, "steps": 1}
+                if prec == "fp64":
+                    oL64 = oL
+                else:
+                    recL[prec]["max_abs_dE_vs_fp64_eV_per_atom"] = max_diff(oL, oL64, "energies")
+                    recL[prec]["max_abs_dF_vs_fp64_eV_per_A"] = max_diff(oL, oL64, "forces")
+            larger[label] = recL
+            del oL, oL64
+        pr["larger_radii"] = larger
+        ctx3.close()
         line["production_radii"] = pr
     if not args.no_fit and args.precision == "fp64":
         # Sec. III.A: per atom and node, c_n fitted to ln(1 - x) on the Lanczos bounds of G~
