@@ -43,7 +43,10 @@ typedef enum lmbd_status {
     LMBD_E_OOM_ADMISSION = 3,  /* request larger than the memory budget of the context */
     LMBD_E_DEVICE = 4,         /* a HIP runtime call failed; see lmbd_last_error */
     LMBD_E_SCS_BREAKDOWN = 5,  /* a local SCS matrix B~_K is not positive definite */
-    LMBD_E_UNSUPPORTED = 6,    /* a size limit of the kernels is exceeded */
+    LMBD_E_UNSUPPORTED = 6,    /* a size limit of the kernels is exceeded: K1 (r < r_scs) above 256
+                                  sites, an SCS shell whose coupling rows outgrow the pair-list
+                                  kernel's LDS, or the largest ball of an atom above 32,768 sites
+                                  (K above 400 sites is served by the global-site MBD form) */
     LMBD_E_CANCELLED = 7,      /* a queued request was dropped when its server was destroyed */
     LMBD_E_POLARISATION = 8    /* LMBD_CN_FIT: a spectrum bound of G~_K reaches 1 (polarisation
                                   catastrophe, Sec. III.A): ln(1 - x) has no fit there */
