@@ -860,23 +860,25 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
         __syncthreads();
     }
 
-    // --- moments mu_n(q) = <u_a, u_b>, a + b = n; four lanes per moment over
-    // rows r = part (mod 4), combined by lane exchanges in a fixed order
+    // --- moments mu_n(q) = <u_a, u_b>, a + b = n: eight moments (consecutive in the
+    // node, so that a row's reads are contiguous) per wavefront, eight lanes per moment
+    // over rows r = part (mod 8), combined by lane exchanges in a fixed order
     const int nmom = (n_max - 1) * nq;
-    for (int base = 0; base < 4 * nmom; base += blockDim.x) {
-        const int t = (base + tid) >> 2, part = (base + tid) & 3;
+    for (int g0 = 8 * wave; g0 < nmom; g0 += 8 * nwave) {
+        const int t = g0 + (lane & 7), part = lane >> 3;
         double s = 0.0;
         if (t < nmom) {
             const int n = 2 + t / nq, q = t % nq;
             const int ia = n / 2, ib = n - ia;
             const W* ua = Uat(ia);
             const W* ub = Uat(ib);
-            for (int row = part; row < N3; row += 4)
+            for (int row = part; row < N3; row += 8)
                 for (int c = 0; c < 3; ++c)
                     s += double(ua[(size_t)row * ncol + 3 * q + c]) * double(ub[(size_t)row * ncol + 3 * q + c]);
         }
-        s += __shfl_xor(s, 1);
-        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
         if (t < nmom && part == 0) L.mu[(2 + t / nq) * nq + t % nq] = s;
     }
     __syncthreads();
@@ -983,14 +985,19 @@ __global__ void __launch_bounds__(FORM != kMbdDense ? kMbdThreadsSparse : kMbdTh
                     s += cfq(n, q) * sn;
                     continue;
                 }
-                for (int aa = 1; aa < n; ++aa) {
+                // sum over a = 1 .. n-1 of the row block of u_a u_{n-a}^T: the terms a and
+                // n - a are equal, so each unordered pair is formed once
+                double pr = 0.0;
+                for (int aa = 1; 2 * aa <= n; ++aa) {
                     const W* ua = Uat(aa);
                     const W* ub = Uat(n - aa);
+                    double d = 0.0;
                     for (int r = 3 * i; r < 3 * i + 3; ++r)
                         for (int c = 0; c < 3; ++c)
-                            sn += double(ua[(size_t)r * ncol + 3 * q + c]) * double(ub[(size_t)r * ncol + 3 * q + c]);
+                            d += double(ua[(size_t)r * ncol + 3 * q + c]) * double(ub[(size_t)r * ncol + 3 * q + c]);
+                    pr += (2 * aa == n) ? d : 2.0 * d;
                 }
-                s += cfq(n, q) * sn;
+                s += cfq(n, q) * (sn + pr);
             }
             v = wk * a.wq[q] * s / L.sa[(size_t)i * nwe + w];
         }
