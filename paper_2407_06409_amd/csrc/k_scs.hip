@@ -159,13 +159,14 @@ constexpr int kMaxParts = 3;          // stored k-split parts of a panel: at mos
 constexpr int kSpinMax = 1 << 22;     // polls of the diagonal flag before a wavefront gives up
 
 // Diagonal block by one wavefront: the 16 x 16 tile in Lt (row-major, rows < jb) is
-// factorised with lane l holding row l of the tile and column l of Z = L^{-1}.  Step c
-// scales column c by 1 / L_cc and reads L[s][c] (s > c) from lane s; the same values
-// update the later rows of the tile (right-looking) and the later entries of every
-// column of Z (z[s] -= L[s][c] z[c], by forward substitution in the order of c).  L goes
-// to the matrix at (c0, c0), Z to Zs (row-major) and its strict lower part, transposed,
-// to the block's strict upper part in the matrix.  Rows from jb on are those of the
-// identity.  good turns false on a pivot that is not positive.
+// factorised with lane l < 16 holding row l of the tile and lane 16 + l column l of
+// Z = L^{-1}.  Step c scales entry c of every lane by 1 / L_cc and reads L[s][c] (s > c)
+// from lane s; the same update x[s] -= L[s][c] x[c], one instruction for both halves,
+// is the right-looking update of the later rows of the tile and the forward
+// substitution of every column of Z in the order of c.  L goes to the matrix at
+// (c0, c0), Z to Zs (row-major) and its strict lower part, transposed, to the block's
+// strict upper part in the matrix.  Rows from jb on are those of the identity.  good
+// turns false on a pivot that is not positive.
 template <typename R>
 __device__ __forceinline__ void diag_block(R* __restrict__ Lt, int jb, R* __restrict__ A, int ld, int c0,
                                            R* __restrict__ Zs, bool& good) {
@@ -173,43 +174,38 @@ __device__ __forceinline__ void diag_block(R* __restrict__ Lt, int jb, R* __rest
     // panel loop, where they would only take registers)
     int l = threadIdx.x & 63;
     asm volatile("" : "+v"(l));
+    const int r = l & 15;
+    const bool lrow = l < NB;   // lanes of L; lanes 16 .. 31 carry Z (and 32 .. 63 a copy)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    R row[NB], z[NB];
+    R x[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        x[c] = (lrow && r < jb && c <= r) ? Lt[r * kSlotLd + c] : (r == c ? R(1) : R(0));
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-        row[c] = (l < jb && c <= l) ? Lt[l * kSlotLd + c] : (l == c ? R(1) : R(0));
-        z[c] = (l == c) ? R(1) : R(0);
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        const R dcc = bcast(row[c], c);
+        const R dcc = bcast(x[c], c);
         if (c < jb && !(dcc > R(0))) good = false;
         const R inv = rsqrt_refined(dcc);
-        // every lane updates: entries above the diagonal (l < s) are never stored
-        // or read from another lane again
-        row[c] = (l == c ? dcc : row[c]) * inv;
-        z[c] *= inv;
+        // entries above the diagonal of the tile (l < s) are never stored or read
+        // from another lane again
+        x[c] = (l == c ? dcc : x[c]) * inv;
 #pragma unroll
-        for (int s = c + 1; s < NB; ++s) {
-            const R lsc = bcast(row[c], s);  // L[s][c]
-            row[s] -= row[c] * lsc;
-            z[s] -= lsc * z[c];
-        }
+        for (int s = c + 1; s < NB; ++s) x[s] -= x[c] * bcast(x[c], s);   // L[s][c]
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (l < jb) {
+    if (lrow && r < jb) {
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-            if (c <= l) A[(size_t)(c0 + l) * ld + c0 + c] = row[c];
+            if (c <= r) A[(size_t)(c0 + r) * ld + c0 + c] = x[c];
     }
-    if (l < NB) {
+    if (l >= NB && l < 2 * NB) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) Zs[q * kSlotLd + l] = z[q];
-    }
-    if (l < jb) {
+        for (int q = 0; q < NB; ++q) Zs[q * kSlotLd + r] = x[q];
+        if (r < jb) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-            if (q > l && q < jb) A[(size_t)(c0 + l) * ld + c0 + q] = z[q];
+            for (int q = 0; q < NB; ++q)
+                if (q > r && q < jb) A[(size_t)(c0 + r) * ld + c0 + q] = x[q];
+        }
     }
 }
 
