@@ -121,6 +121,14 @@ def default_context(device: int = 0) -> Context:
     return _default_ctx[device]
 
 
+def release_default_context(device: int = 0) -> None:
+    """Destroy the default context of a device and with it the workspaces it keeps
+    between calls (the next call without a context starts a new one)."""
+    ctx = _default_ctx.pop(device, None)
+    if ctx is not None:
+        ctx.close()
+
+
 def _ptr(x):
     if x is None:
         return None

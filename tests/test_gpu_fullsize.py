@@ -192,7 +192,11 @@ def test_c1728_production_two_radius_matches_oracle():
     2,450 sites per neighbourhood with periodic images; r_SCS = 6 A) on the 1,728-atom
     box: the sparse MBD form with its site arrays in the workspace, against stored oracle
     energies of sampled atoms and the forces of a one-atom sum, FP64 and mixed."""
-    from paper_2407_06409_amd import Context
+    import torch
+    from paper_2407_06409_amd import Context, release_default_context
+    # a call of about 126 GiB (FP64 with forces): nothing held from the earlier tests
+    release_default_context()
+    torch.cuda.empty_cache()
     g = golden()["C1728_pbc_10p8A"]
     st, _ = C.config_plain_pbc()
     cut = g["cutoffs"]
