@@ -280,8 +280,8 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
  * has completed, keeps the elapsed milliseconds of the last call per stage.
  * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map+
  * coupling lists, 2 right-hand sides d of the local SCS, 3 local SCS assembly,
- * factorisation and first solve (one kernel), 4 refinement of the local SCS
- * solution (mixed path; empty in FP64), 5 local MBD energy
+ * factorisation, first solve and, in the mixed path, its refinement (one
+ * kernel), 4 kept for the refinement's former kernels (empty), 5 local MBD energy
  * (+adjoint), 6 central-polarisability gather, 7 adjoint SCS solves, 8 SCS
  * pair gradients (and, when dE_dv is requested, the volume-ratio adjoint),
  * 9 force gather. */

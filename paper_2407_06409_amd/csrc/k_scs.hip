@@ -11,8 +11,8 @@
 // memory; the factor is kept for the adjoint solve.  A non-positive pivot is a
 // breakdown reported to the host.  Kernels: k_pairlist (pair lists of an atom),
 // k_scs_dvec (d and the rows of d^T), k_scs_factor (assembly of B~,
-// factorisation and first solve), k_scs_residual and k_scs_solve (refinement of
-// the mixed path; the adjoint solve), k_scs_adjoint (pair gradients).
+// factorisation, first solve and the mixed path's refinement), k_scs_solve (the
+// adjoint solve), k_scs_adjoint (pair gradients).
 //
 // Precision: the kernels are templated on the matrix type R.  R = double is the
 // plain FP64 path.  R = float is the mixed path: pair tensors, the matrix and
@@ -1101,73 +1101,11 @@ size_t scs_solve_lds_bytes(int n1max, bool mixed) {
     return r * (9 * (size_t)n1max + 2 * NB * kSlotLd);
 }
 
-// Assembly, factorisation and first solve of B~ in place, one workgroup per
-// (atom, frequency): the matrix written just before it is read back stays in
-// the caches, as does the factor for the solve, and the write-bound assembly of
-// one workgroup overlaps the factorisations of the others on the compute unit.
-// The diagonal tile and the k-split parts are dynamic LDS (the assembly and the
-// solve use the same space before and after); Z1, Z2 and L21 are a separate
-// static array so that the compiler sees they cannot alias it.
-static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
-static_assert(3 * 256 >= 3 * kMaxN1, "three rows per thread of the factorisation kernel cover its first solve");
-static_assert(256 / 64 - 1 <= kMaxParts, "k-split parts of four wavefronts");
-template <typename R, int NS>
-__global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, int n1max) {
-    extern __shared__ double lds[];
-    __shared__ R Zsh[3 * NB * kSlotLd];
-    __shared__ int ctl[4];
-    R* Lt = reinterpret_cast<R*>(lds);
-    const int k = a.order[blockIdx.x];
-    const int w = blockIdx.y;
-    assemble_matrix<R>(a, k, w, n1max, lds);   // ends with a barrier
-    const int N = 3 * a.counts[k].n1;
-    const int ld = a.fac_ld[k];
-    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
-    // the wave that factorises the diagonal blocks rotates over the workgroups
-    const int dw = (k + w) % (blockDim.x >> 6);
-    bool ok = true, stalled = false;
-    R* part = Lt + NB * kSlotLd;
-    chol_factor<R>(A, N, ld, Lt, part, part + kMaxParts * 16 * 64, Zsh, Zsh + NB * kSlotLd, Zsh + 2 * NB * kSlotLd,
-                   ctl, dw, ok, stalled);   // ends with a barrier
-    if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
-        atomicOr(a.err, 4);
-        atomicMin(a.err_atom, k);
-    }
-    if (stalled && (threadIdx.x & 63) == 0) {
-        atomicOr(a.err, 64);
-        atomicMin(a.err_atom, k);
-    }
-    // the first solve (backward: the forward substitution was carried by the
-    // factorisation) while the factor is still in the caches
-    solve_slot<R, NS, 1>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
-}
-
-// dynamic LDS of the factorisation: the diagonal tile, the k-split parts and the two
-// buffers of the prepared unit 0
-static size_t factor_panel_bytes(bool mixed) {
-    const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return r * ((size_t)NB * kSlotLd + (size_t)(kMaxParts + 2) * 16 * 64);
-}
-
-// dynamic LDS of the assembly and factorisation kernel
-static size_t factor_dynamic_bytes(int n1max, bool mixed) {
-    return std::max(std::max(factor_panel_bytes(mixed), matrix_lds_bytes(n1max)), scs_solve_lds_bytes(n1max, mixed));
-}
-
-// all LDS of the assembly and factorisation: the dynamic part and Z1, Z2, L21
-size_t scs_factor_lds_bytes(int n1max, bool mixed) {
-    const size_t r = mixed ? sizeof(float) : sizeof(double);
-    return factor_dynamic_bytes(n1max, mixed) + r * 3 * NB * kSlotLd;
-}
-
 // Refinement residual of the mixed path: resid = d - B~ X in FP64, with B~
 // rebuilt from its FP32 pair coefficients; partner ranges split over kRes
 // threads and recombined in a fixed order.
-__global__ void __launch_bounds__(256) k_scs_residual(ScsArgs a, int n1max) {
-    extern __shared__ double lds[];
+__device__ __forceinline__ void residual_slot(const ScsArgs& a, int k, int w, int n1max, double* lds) {
     constexpr int kRes = 2;
-    const int k = a.order[blockIdx.x];
-    const int w = blockIdx.y;
     const int n1 = a.counts[k].n1;
     const int N = 3 * n1;
     const size_t xo = a.x_off[k] + (size_t)w * N * 3;
@@ -1220,7 +1158,80 @@ __global__ void __launch_bounds__(256) k_scs_residual(ScsArgs a, int n1max) {
     }
 }
 
-size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)n1max + 4 * (size_t)n1max + 2 * 9 * (size_t)n1max); }
+static size_t scs_residual_lds_bytes(int n1max) { return sizeof(double) * (9 * (size_t)n1max + 4 * (size_t)n1max + 2 * 9 * (size_t)n1max); }
+
+// Assembly, factorisation and first solve of B~ in place, one workgroup per
+// (atom, frequency): the matrix written just before it is read back stays in
+// the caches, as does the factor for the solve (and, in the mixed path, for the
+// correction solve of the refinement), and the write-bound assembly of one
+// workgroup overlaps the factorisations of the others on the compute unit.
+// The diagonal tile and the k-split parts are dynamic LDS (the assembly, the
+// solves and the residual use the same space before and after); Z1, Z2 and L21 are a separate
+// static array so that the compiler sees they cannot alias it.
+static_assert(kChunk == 256, "the 256 threads of the factorisation kernel run the assembly's chunks");
+static_assert(3 * 256 >= 3 * kMaxN1, "three rows per thread of the factorisation kernel cover its first solve");
+static_assert(256 / 64 - 1 <= kMaxParts, "k-split parts of four wavefronts");
+template <typename R, int NS>
+__global__ void __launch_bounds__(256, NS == 2 ? 3 : 2) k_scs_factor(ScsArgs a, int n1max) {
+    extern __shared__ double lds[];
+    __shared__ R Zsh[3 * NB * kSlotLd];
+    __shared__ int ctl[4];
+    R* Lt = reinterpret_cast<R*>(lds);
+    const int k = a.order[blockIdx.x];
+    const int w = blockIdx.y;
+    assemble_matrix<R>(a, k, w, n1max, lds);   // ends with a barrier
+    const int N = 3 * a.counts[k].n1;
+    const int ld = a.fac_ld[k];
+    R* A = static_cast<R*>(a.fac) + a.fac_off[k] + (size_t)w * ld * (N + 3);
+    // the wave that factorises the diagonal blocks rotates over the workgroups
+    const int dw = (k + w) % (blockDim.x >> 6);
+    bool ok = true, stalled = false;
+    R* part = Lt + NB * kSlotLd;
+    chol_factor<R>(A, N, ld, Lt, part, part + kMaxParts * 16 * 64, Zsh, Zsh + NB * kSlotLd, Zsh + 2 * NB * kSlotLd,
+                   ctl, dw, ok, stalled);   // ends with a barrier
+    if (!ok && (threadIdx.x & 63) == 0) {   // only lanes of the diagonal wave can fail
+        atomicOr(a.err, 4);
+        atomicMin(a.err_atom, k);
+    }
+    if (stalled && (threadIdx.x & 63) == 0) {
+        atomicOr(a.err, 64);
+        atomicMin(a.err_atom, k);
+    }
+    // the first solve (backward: the forward substitution was carried by the
+    // factorisation) while the factor is still in the caches
+    solve_slot<R, NS, 1>(a, k, w, n1max, sizeof(R) == 4 ? kSolveFirst : kSolveD, lds);
+    if constexpr (sizeof(R) == 4) {
+        // the mixed path's refinement in the same launch, the FP32 factor still in
+        // the caches for the correction solve
+        for (int it = 0; it < a.n_refine; ++it) {
+            __syncthreads();   // X written; the LDS of the solve free
+            residual_slot(a, k, w, n1max, lds);
+            __syncthreads();   // the residual written
+            solve_slot<R, NS, 1>(a, k, w, n1max, kSolveCorr, lds);
+        }
+    }
+}
+
+// dynamic LDS of the factorisation: the diagonal tile, the k-split parts and the two
+// buffers of the prepared unit 0
+static size_t factor_panel_bytes(bool mixed) {
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return r * ((size_t)NB * kSlotLd + (size_t)(kMaxParts + 2) * 16 * 64);
+}
+
+// dynamic LDS of the assembly and factorisation kernel
+static size_t factor_dynamic_bytes(int n1max, bool mixed) {
+    const size_t solve = scs_solve_lds_bytes(n1max, mixed);
+    return std::max(std::max(factor_panel_bytes(mixed), matrix_lds_bytes(n1max)),
+                    mixed ? std::max(solve, scs_residual_lds_bytes(n1max)) : solve);
+}
+
+// all LDS of the assembly and factorisation: the dynamic part and Z1, Z2, L21
+size_t scs_factor_lds_bytes(int n1max, bool mixed) {
+    const size_t r = mixed ? sizeof(float) : sizeof(double);
+    return factor_dynamic_bytes(n1max, mixed) + r * 3 * NB * kSlotLd;
+}
+
 
 // ---------------------------------------------------------------------------
 // Adjoint.  With X = B~^{-1} d and seeds xbar_i (adjoint of alpha~_iso_i =
@@ -1831,22 +1842,6 @@ hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool m
     } else {
         if (three) hipLaunchKernelGGL((k_scs_factor<double, 3>), grid, dim3(256), lf, st, a, n1max);
         else hipLaunchKernelGGL((k_scs_factor<double, 2>), grid, dim3(256), lf, st, a, n1max);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mixed) {
-    const dim3 grid(a.n, a.nw);
-    const size_t ls = scs_solve_lds_bytes(n1max, mixed);
-    // the first solve ran in the factorisation kernel; the mixed path refines it here
-    if (mixed) {
-        for (int it = 0; it < a.n_refine; ++it) {
-            hipLaunchKernelGGL(k_scs_residual, grid, dim3(256), scs_residual_lds_bytes(n1max), st, a, n1max);
-            if (solve_slots(n1max) == 3)
-                hipLaunchKernelGGL((k_scs_solve<float, 3>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveCorr);
-            else
-                hipLaunchKernelGGL((k_scs_solve<float, 2>), grid, dim3(kSolveThreads), ls, st, a, n1max, (int)kSolveCorr);
-        }
     }
     return hipGetLastError();
 }

@@ -1202,10 +1202,9 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(launch_scs_rhs(stream, sa, P.n1max, P.n2max, mixed));
     HIP_TRY(mark(2, 1));
     HIP_TRY(mark(3, 0));
-    HIP_TRY(launch_scs_factor(stream, sa, P.n1max, mixed));   // assembles B~, then factorises it
+    HIP_TRY(launch_scs_factor(stream, sa, P.n1max, mixed));   // assembles B~, factorises it, solves (and refines)
     HIP_TRY(mark(3, 1));
-    HIP_TRY(mark(4, 0));
-    HIP_TRY(launch_scs_solve(stream, sa, P.n1max, mixed));
+    HIP_TRY(mark(4, 0));   // (stage 4: no kernel of its own any more)
     HIP_TRY(mark(4, 1));
 
     // --- local MBD energy (+ adjoint)

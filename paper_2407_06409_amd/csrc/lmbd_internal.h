@@ -275,7 +275,6 @@ size_t pairlist_lds_bytes(int n1max, int n2max);
 hipError_t launch_scs_rhs(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
 hipError_t launch_scs_factor(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 size_t scs_factor_lds_bytes(int n1max, bool mixed);
-hipError_t launch_scs_solve(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 hipError_t launch_scs_lambda(hipStream_t st, const ScsArgs& a, int n1max, bool mixed);
 hipError_t launch_pairlist(hipStream_t st, const ScsArgs& a, int n1max, int n2max);
 hipError_t launch_scs_adjoint(hipStream_t st, const ScsArgs& a, int n1max, int n2max, bool mixed);
