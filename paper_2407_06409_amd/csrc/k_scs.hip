@@ -237,6 +237,10 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
     // with the chunks cb, cb + st, .. below ce: m[x][h] = A(2u + x, h)^T - (L_h L_t^T)^T,
     // starting from the matrix (init 0), from zero (1) or from m as given (2)
     auto update = [&](int c0p, int mtp, bool twop, int u, int cb, int st, int ce, int init, Acc(&m)[2][2]) {
+        // (the lane's indices are made opaque here so that the offsets derived from
+        // them are formed per call rather than held, or spilled, over the panel loop)
+        int lio = li, lko = lk;
+        asm volatile("" : "+v"(lio), "+v"(lko));
         bool v[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -247,7 +251,7 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 if (init != 2) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int row = c0p + NB * t + li, col = c0p + NB * h + M::acc_row(lk, q);
+                        const int row = c0p + NB * t + lio, col = c0p + NB * h + M::acc_row(lko, q);
                         m[x][h][q] = (init == 0 && v[x][h] && row < Nr && col < N && (t != h || row >= col))
                                          ? A[(size_t)row * ld + col] : R(0);
                     }
@@ -259,15 +263,15 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
             bool okt[2], okh[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                const int r = c0p + NB * (2 * u + x) + li;
+                const int r = c0p + NB * (2 * u + x) + lio;
                 okt[x] = 2 * u + x < mtp && r < Nr;
-                pt[x] = A + (size_t)(okt[x] ? r : 0) * ld + 4 * lk;
+                pt[x] = A + (size_t)(okt[x] ? r : 0) * ld + 4 * lko;
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int r = c0p + NB * h + li;
+                const int r = c0p + NB * h + lio;
                 okh[h] = (h == 0 || twop) && r < N;
-                ph[h] = A + (size_t)(okh[h] ? r : 0) * ld + 4 * lk;
+                ph[h] = A + (size_t)(okh[h] ? r : 0) * ld + 4 * lko;
             }
             auto ld4 = [&](const R* base, bool okr, int c) { return (okr && c < ce) ? load4(base + NB * c) : zero; };
             // ring of kRing chunks: each chunk's registers are refilled with the chunk
@@ -349,38 +353,39 @@ __device__ __forceinline__ void chol_factor(R* __restrict__ A, int N, int ld, R*
                 part[(1 * 4 + q) * 64 + lane] = m[1][1][q];
             }
             asm volatile("" ::: "memory");   // really reload them: no registers held over the chain
-            diag_block<R>(Lt, jb1, A, ld, c0, Z1, good);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            if (jb1 < NB) {   // rows of d^T in the diagonal tile
-                Acc m00;
+            // the two diagonal blocks in one loop that is not unrolled: the block's code
+            // (the longest straight line of the kernel) is there once per call
+            const int nblk = (mt > 1 && two) ? 2 : 1;
+#pragma clang loop unroll(disable)
+            for (int b = 0; b < nblk; ++b) {
+                R* Zb = b == 0 ? Z1 : Z2;
+                const int jbb = b == 0 ? jb1 : jb2;
+                diag_block<R>(Lt, jbb, A, ld, c0 + NB * b, Zb, good);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (jbb < NB) {   // rows of d^T in the diagonal tile (still in Lt)
+                    Acc mbb;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) m00[q] = Lt[li * kSlotLd + M::acc_row(lk, q)];
-                store_x(zmul(Z1, m00), 0, 0, jb1);
-            }
-            if (mt > 1) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    m[1][0][q] = part[(0 * 4 + q) * 64 + lane];
-                    m[1][1][q] = part[(1 * 4 + q) * 64 + lane];
+                    for (int q = 0; q < 4; ++q) mbb[q] = Lt[li * kSlotLd + M::acc_row(lk, q)];
+                    store_x(zmul(Zb, mbb), b, b, jbb);
                 }
-                const Acc l21 = zmul(Z1, m[1][0]);
-                store_x(l21, 1, 0, 0);
+                if (b == 0 && mt > 1) {
+                    Acc m10, m11;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) L21[li * kSlotLd + M::acc_row(lk, q)] = l21[q];
-                if (two) {
-                    // A22 -= L21 L21^T: the registers of L21^T are both operands
+                    for (int q = 0; q < 4; ++q) {
+                        m10[q] = part[(0 * 4 + q) * 64 + lane];
+                        m11[q] = part[(1 * 4 + q) * 64 + lane];
+                    }
+                    const Acc l21 = zmul(Z1, m10);
+                    store_x(l21, 1, 0, 0);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) m[1][1] = M::mma(-l21[e], l21[e], m[1][1]);
+                    for (int q = 0; q < 4; ++q) L21[li * kSlotLd + M::acc_row(lk, q)] = l21[q];
+                    if (two) {
+                        // A22 -= L21 L21^T: the registers of L21^T are both operands
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) Lt[li * kSlotLd + M::acc_row(lk, q)] = m[1][1][q];
-                    asm volatile("" ::: "memory");
-                    diag_block<R>(Lt, jb2, A, ld, c0 + NB, Z2, good);
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    if (jb2 < NB) {   // rows of d^T in the second diagonal tile (still in Lt)
-                        Acc m11;
+                        for (int e = 0; e < 4; ++e) m11 = M::mma(-l21[e], l21[e], m11);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) m11[q] = Lt[li * kSlotLd + M::acc_row(lk, q)];
-                        store_x(zmul(Z2, m11), 1, 1, jb2);
+                        for (int q = 0; q < 4; ++q) Lt[li * kSlotLd + M::acc_row(lk, q)] = m11[q];
+                        asm volatile("" ::: "memory");
                     }
                 }
             }
