@@ -462,15 +462,13 @@ def main():
     n1 = neighbour_counts(st, cut["r_scs"])
     nK = neighbour_counts(st, cut["r_nbr"])
     # the forward substitution of X = B~^-1 d is carried by the factorisation and
-    # the backward one runs in the same kernel; mixed refines with a forward +
-    # backward correction solve
+    # the backward one runs in the same kernel, as does the mixed path's refinement
+    # (residual and forward + backward correction solve), none of them counted
     flops = {
         "scs_assemble_factor_solve": scs_factor_flops(n1, nw),   # the factorisation's FLOPs only
         "mbd": mbd_flops(nK, nq, n_max, True),
         "scs_lambda": scs_solve_flops(n1, nw, 2),
     }
-    if args.precision != "fp64":
-        flops["scs_refine"] = scs_solve_flops(n1, nw, 2)
     peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
     stage_tflops = {k: flops[k] / (stage_ms[k] * 1e-3) / 1e12 for k in flops if stage_ms.get(k, 0) > 0}
     dom = max(flops, key=lambda k: stage_ms.get(k, 0.0))   # the longest kernel with a dense-algebra count

@@ -281,7 +281,8 @@ lmbd_status lmbd_estimate_footprint(const lmbd_params* params, int32_t n_structs
  * Stages: 0 prep+cell sort+neighbour counts, 1 neighbour lists+reverse map+
  * coupling lists, 2 right-hand sides d of the local SCS, 3 local SCS assembly,
  * factorisation, first solve and, in the mixed path, its refinement (one
- * kernel), 4 kept for the refinement's former kernels (empty), 5 local MBD energy
+ * kernel), 4 unused (the refinement had kernels of its own here; not recorded),
+ * 5 local MBD energy
  * (+adjoint), 6 central-polarisability gather, 7 adjoint SCS solves, 8 SCS
  * pair gradients (and, when dE_dv is requested, the volume-ratio adjoint),
  * 9 force gather. */

@@ -1203,9 +1203,7 @@ lmbd_status lmbd_compute_batch(lmbd_context* ctx, const lmbd_params* params, int
     HIP_TRY(mark(2, 1));
     HIP_TRY(mark(3, 0));
     HIP_TRY(launch_scs_factor(stream, sa, P.n1max, mixed));   // assembles B~, factorises it, solves (and refines)
-    HIP_TRY(mark(3, 1));
-    HIP_TRY(mark(4, 0));   // (stage 4: no kernel of its own any more)
-    HIP_TRY(mark(4, 1));
+    HIP_TRY(mark(3, 1));   // (stage 4, the refinement's former kernels, is not recorded)
 
     // --- local MBD energy (+ adjoint)
     MbdArgs ma;
