@@ -1140,7 +1140,7 @@ __device__ __forceinline__ void residual_slot(const ScsArgs& a, int k, int w, in
             const double cA = coef[2 * pj], cB = coef[2 * pj + 1];
             if (cA == 0.0 && cB == 0.0) continue;
             const double v[3] = {px[i] - px[j], py[i] - py[j], pz[i] - pz[j]};
-            const double ir = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double ir = rsqrt_refined(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);   // (a few ulp: far below the FP32 coefficients' error)
             const double rh[3] = {v[0] * ir, v[1] * ir, v[2] * ir};
             for (int c = 0; c < 3; ++c) {
                 const double x0 = X[(3 * j + 0) * 3 + c], x1 = X[(3 * j + 1) * 3 + c], x2 = X[(3 * j + 2) * 3 + c];
